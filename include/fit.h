@@ -1,0 +1,210 @@
+/*
+ * fit.h -- C ABI of the MI355X FIT leapfrog library (libfit.so).
+ *
+ * The library advances the semi-discrete Maxwell system obtained by the
+ * Finite Integration Technique on a staggered hexahedral grid pair with the
+ * leapfrog scheme, and evaluates the discrete energy inner products
+ * (Merkel, Niyonzima, Schoeps, "ParaExp using Leapfrog as Integrator for
+ * High-Frequency Electromagnetic Simulations", Sec. II and II-A).
+ *
+ * Conventions common to every call
+ * --------------------------------
+ * Grid.   nx, ny, nz count primal CELLS (the paper counts grid points; points
+ *         = cells + 1 per axis).  Node (i, j, k) has 0 <= i <= nx, etc.
+ *         Spacings dx, dy, dz are uniform per axis.
+ * Units.  eps0 and mu0 scale the per-cell relative values (0 selects 1, i.e.
+ *         normalised units with c = 1).
+ * Field layout ("slot layout").  A field is 3 component arrays, each of
+ *         nx*ny*nz elements, stored back to back: element [a][k][j][i]
+ *         (i fastest) holds the voltage of the direction-a primal edge (for e)
+ *         or of the dual edge crossing the direction-a primal facet (for h)
+ *         anchored at node (i, j, k).  Every edge and facet that is not in a
+ *         PEC wall has a slot; all other slots are zero and stay zero.
+ *         e lives on edges with (for a = x) 1 <= j <= ny-1, 1 <= k <= nz-1
+ *         (cyclically for y, z); h on facets with 1 <= i <= nx-1 (for a = x).
+ * Boundary. Perfect electric conductor on all six faces (tangential e = 0,
+ *         normal b = 0), the only boundary used in the paper.
+ * Dtype.  Fields and stencils run in FIT_F32 or FIT_F64; every reduction
+ *         (energies, probe objective, Gram entries, adjoint gradients)
+ *         accumulates in FP64 with compensated summation.
+ * Memory. The library allocates (hipMalloc) and owns every device buffer it
+ *         needs (fields, materials, partial sums, trace, adjoint state).
+ *         Pointers passed in are borrowed for the duration of the call only.
+ *         "device" pointers must be device memory of the current HIP device;
+ *         "host" pointers ordinary host memory.
+ * Streams. All work is enqueued on the stream given at creation (NULL =
+ *         the default stream).  Calls that return host data synchronise that
+ *         stream; the others return once the work is enqueued.
+ * Errors. Every call returns a fit_status; nothing throws across the ABI.
+ *         fit_last_error() returns a thread-local message for the last
+ *         non-OK status.  A HIP failure (launch error, sticky device error)
+ *         surfaces as FIT_E_HIP on the call that observes it.
+ * Threads. A handle must not be used from two threads at once.
+ */
+#ifndef FIT_H
+#define FIT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FIT_OK = 0,
+  FIT_E_INVALID = -1,   /* bad argument (sizes, pointers, non-SPD material, ...) */
+  FIT_E_OOM = -2,       /* device allocation failed */
+  FIT_E_HIP = -3,       /* HIP runtime / kernel error */
+  FIT_E_UNSTABLE = -4,  /* dt above the CFL bound without FIT_ALLOW_UNSTABLE */
+  FIT_E_DIVERGED = -5,  /* energy watchdog: non-finite energy */
+  FIT_E_STATE = -6      /* call not valid in the handle's current state */
+} fit_status;
+
+typedef enum { FIT_F32 = 0, FIT_F64 = 1 } fit_dtype;
+
+enum { FIT_ALLOW_UNSTABLE = 1u };
+
+typedef struct fit_grid fit_grid;   /* opaque handle */
+
+typedef struct {
+  int32_t nx, ny, nz;     /* cells per axis, each >= 1 */
+  double dx, dy, dz;      /* uniform spacings, > 0 (0 selects 1) */
+  double eps0, mu0;       /* vacuum constants, >= 0 (0 selects 1) */
+  int32_t dtype;          /* fit_dtype */
+  uint32_t flags;         /* FIT_ALLOW_UNSTABLE */
+} fit_grid_desc;
+
+/* Number of doubles per energy-trace row; see fit_trace_read. */
+#define FIT_TRACE_COLS 10
+
+/* Library version string (static storage). */
+const char* fit_version(void);
+
+/* Thread-local message describing the last non-OK status. */
+const char* fit_last_error(void);
+
+/* Create a grid: staggered primal/dual grid of nx*ny*nz cells (Sec. II).
+ * Fields start at zero, materials at vacuum (eps_r = mu_r = 1, sigma = 0),
+ * no source, step counter 0.  `stream` is a hipStream_t or NULL.
+ * Errors: FIT_E_INVALID (sizes/spacings), FIT_E_OOM. */
+int fit_grid_create(const fit_grid_desc* desc, void* stream, fit_grid** out);
+
+/* Destroy a grid and free its device memory (synchronises its stream).
+ * NULL is accepted. */
+int fit_grid_destroy(fit_grid* g);
+
+/* Per-cell materials -> the diagonal material matrices M_eps, M_sigma, M_mu
+ * (eq. maxwell_grid3).  Host FP64 arrays of nx*ny*nz values, layout
+ * [k][j][i].  mu_r may be NULL (all 1), sigma may be NULL (all 0).
+ * The edge/facet averages are formed inside the kernels: M_eps of an edge is
+ * eps0 times the mean eps_r of the (up to 4) cells around it times
+ * d_b d_c / d_a; M_sigma likewise; M_mu^{-1} of a facet is the mean of
+ * 1/(mu0 mu_r) over the 2 cells on its dual edge times d_a / (d_b d_c).
+ * Errors: FIT_E_INVALID if eps_r <= 0, mu_r <= 0, sigma < 0 or non-finite. */
+int fit_set_materials(fit_grid* g, const double* eps_r, const double* mu_r,
+                      const double* sigma);
+
+/* Gaussian line-current source (Sec. IV-A, eq. line_current):
+ * i(t) = i_max exp(-4 ((t - sigma_t) / sigma_t)^2) on the single primal edge
+ * of direction `axis` (0, 1, 2) leaving node (i, j, k), flowing in +axis,
+ * sampled at t_{m+1/2} = (m + 1/2) dt.  It enters the e-update with a minus
+ * sign (M_eps de/dt = C~ h - j).  axis = -1 removes the source.
+ * Errors: FIT_E_INVALID if the edge lies in a PEC wall or sigma_t <= 0. */
+int fit_set_source(fit_grid* g, int axis, int i, int j, int k, double i_max,
+                   double sigma_t);
+
+/* CFL step bound (eq. cfl): min over cells of
+ * sqrt(eps mu / (dx^-2 + dy^-2 + dz^-2)).  Writes *dt_cfl. */
+int fit_cfl_dt(const fit_grid* g, double* dt_cfl);
+
+/* Set the state e^(m), h^(m+1/2) and the step counter m.  e, h: 3*nx*ny*nz
+ * values each in the slot layout and the grid's dtype; on_device != 0 means
+ * device pointers, else host pointers.  Either pointer may be NULL (that
+ * field is zeroed).  Slots of PEC-wall edges/facets are forced to zero. */
+int fit_set_fields(fit_grid* g, const void* e, const void* h, int64_t step, int on_device);
+
+/* Copy the current state out (layouts as fit_set_fields).  Either pointer
+ * may be NULL.  Host destinations synchronise. */
+int fit_get_fields(fit_grid* g, void* e, void* h, int on_device);
+
+/* Current step counter m (the state holds e^(m), h^(m+1/2)). */
+int fit_get_step(const fit_grid* g, int64_t* step);
+
+/* Apply one PEC-restricted discrete curl: which = 0 applies the primal curl
+ * C (edge voltages -> facet fluxes, eq. maxwell_grid1: C e = -d_t b); which =
+ * 1 applies the dual curl C~ (dual-edge voltages -> dual-facet quantities,
+ * C~ h = d_t d + j).  in/out: device pointers, slot layout, grid dtype;
+ * in != out.  Output slots in PEC walls are zero. */
+int fit_apply_curl(fit_grid* g, int which, const void* in, void* out);
+
+/* Advance nsteps leapfrog steps (Sec. II-A):
+ *   (M_eps + dt/2 M_sigma) e^(m+1) = (M_eps - dt/2 M_sigma) e^m + dt (C~ h^(m+1/2) - j_s(t_{m+1/2}))
+ *   h^(m+3/2) = h^(m+1/2) - dt M_mu^{-1} C e^(m+1)
+ * (the loss current is taken at the interpolated e^(m+1/2) = (e^m + e^(m+1))/2;
+ * for sigma = 0 this is the paper's update).  Cost: 2 curl applications per
+ * step (eq. cost_LF).  dt must be > 0 and <= fit_cfl_dt unless the grid was
+ * created with FIT_ALLOW_UNSTABLE (else FIT_E_UNSTABLE).  Energies are
+ * traced as configured by fit_trace_config; the probe objective is
+ * accumulated when a probe is set.  Asynchronous. */
+int fit_step(fit_grid* g, int64_t nsteps, double dt);
+
+/* Energies of the current state (eq. energy, m = n): out[0] = <e^m, e^m>_eps,
+ * out[1] = <h^(m+1/2), h^(m+1/2)>_mu, FP64.  Synchronises.
+ * Returns FIT_E_DIVERGED (with out filled) if either is not finite. */
+int fit_energy(fit_grid* g, double out[2]);
+
+/* Energy trace.  every > 0 records one row for each step m with
+ * m % every == 0 (every = 0 disables); up to `capacity` rows are kept
+ * (later rows are dropped and counted).  The row of step m holds the inner
+ * products available around that step (FP64):
+ *   [0] m
+ *   [1] <e^m, e^m>_eps        [2] <e^m, e^(m+1)>_eps     [3] <e^(m+1), e^(m+1)>_eps
+ *   [4] <h^(m-1/2), h^(m+1/2)>_mu (NaN if step m-1 was not run in this handle)
+ *   [5] <h^(m+1/2), h^(m+1/2)>_mu   [6] <h^(m+1/2), h^(m+3/2)>_mu   [7] <h^(m+3/2), h^(m+3/2)>_mu
+ *   [8] ebar^T M_sigma ebar   [9] ebar . j_s,   ebar = (e^m + e^(m+1))/2.
+ * From these, the paper's conserved energy is W^m = ([1]+[2]+[4]+[5])/2, and
+ * Q^(m+1) - Q^m = -2 dt ([8] + [9]) with Q^m = [1] + [4], Q^(m+1) = [3] + [6].
+ * Reconfiguring clears recorded rows. */
+int fit_trace_config(fit_grid* g, int64_t every, int64_t capacity);
+
+/* Copy up to max_rows recorded rows (FIT_TRACE_COLS doubles each) to host
+ * `out`, write the number copied to *nrows and the number dropped for lack of
+ * capacity to *dropped (may be NULL), then clear the record.  Synchronises. */
+int fit_trace_read(fit_grid* g, double* out, int64_t max_rows, int64_t* nrows,
+                   int64_t* dropped);
+
+/* Probe objective J = dt * sum over steps m >= 1 of sum_{edges i in probe}
+ * M_eps,i (e_i^m)^2, accumulated by fit_step (FP64, compensated).  The probe
+ * holds the edges whose midpoints lie in the closed node-coordinate box
+ * [lo[a], hi[a]] for a = x, y, z.  Setting the probe resets J to 0;
+ * lo = hi = NULL removes it. */
+int fit_set_probe(fit_grid* g, const int32_t lo[3], const int32_t hi[3]);
+
+/* Read the probe objective accumulated so far (synchronises). */
+int fit_probe_value(fit_grid* g, double* J);
+
+/* Reset the probe objective to 0. */
+int fit_probe_reset(fit_grid* g);
+
+/* Kernel timing.  Between fit_profile_begin and fit_profile_end every
+ * kernel launch made by this handle is bracketed by a pair of hipEvents on
+ * the handle's stream (at most max_launches launches are timed; later ones
+ * run untimed).  fit_profile_end synchronises and writes, per kernel class
+ * (FIT_PROF_* index), the summed launch duration in milliseconds to
+ * ms[FIT_PROF_N] and the number of timed launches to count[FIT_PROF_N]
+ * (either may be NULL).  This is instrumentation for the paper's cost
+ * measure (curl applications, eq. cost_LF) in wall-clock form. */
+enum { FIT_PROF_EPASS = 0, FIT_PROF_HPASS = 1, FIT_PROF_REDUCE = 2, FIT_PROF_STEP = 3,
+       FIT_PROF_ADJOINT = 4, FIT_PROF_OTHER = 5, FIT_PROF_N = 6 };
+int fit_profile_begin(fit_grid* g, int64_t max_launches);
+int fit_profile_end(fit_grid* g, double ms[FIT_PROF_N], int64_t count[FIT_PROF_N]);
+
+/* Number of curl applications (sparse matrix-vector products of the paper's
+ * cost model, eq. cost_LF: 2 per leapfrog step) performed by this handle. */
+int fit_smvp_count(const fit_grid* g, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FIT_H */

@@ -90,8 +90,10 @@ class Operators:
         return pos
 
 
-def run(ops: Operators, e0, h0, dt: float, nsteps: int, source=None, record=False):
-    """Advance (e^0, h^(1/2)) by ``nsteps`` leapfrog steps.
+def run(ops: Operators, e0, h0, dt: float, nsteps: int, source=None, record=False,
+        step0: int = 0):
+    """Advance (e^m0, h^(m0+1/2)) by ``nsteps`` leapfrog steps, m0 = ``step0``
+    (the global index of the first step; it only sets the source time).
 
     ``source``: None or dict(axis, i, j, k, i_max, sigma_t) with sigma_t in
     time units; the current i(t_{m+1/2}) flows on that one edge.
@@ -113,7 +115,8 @@ def run(ops: Operators, e0, h0, dt: float, nsteps: int, source=None, record=Fals
     for m in range(nsteps):
         js = np.zeros_like(e)
         if src_pos is not None:
-            js[src_pos] = gaussian_current((m + 0.5) * dt, source["i_max"], source["sigma_t"])
+            js[src_pos] = gaussian_current((step0 + m + 0.5) * dt, source["i_max"],
+                                           source["sigma_t"])
         e1 = (rhs * e + dt * (ops.Ct @ h - js)) / lhs
         h1 = h - dt * Mmi * (ops.C @ e1)
         ebar = 0.5 * (e + e1)

@@ -1,0 +1,103 @@
+"""ctypes declarations for libfit.so (argument marshalling only).
+
+The library is built in-tree (``python -m paper_1705_08019_amd.build``) and
+loaded from this package directory.  There is no fallback: if the library is
+missing or fails to load, every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libfit.so")
+
+FIT_OK = 0
+FIT_F32, FIT_F64 = 0, 1
+FIT_ALLOW_UNSTABLE = 1
+FIT_TRACE_COLS = 10
+STATUS = {0: "FIT_OK", -1: "FIT_E_INVALID", -2: "FIT_E_OOM", -3: "FIT_E_HIP",
+          -4: "FIT_E_UNSTABLE", -5: "FIT_E_DIVERGED", -6: "FIT_E_STATE"}
+
+
+class FitError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class GridDesc(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+                ("dx", C.c_double), ("dy", C.c_double), ("dz", C.c_double),
+                ("eps0", C.c_double), ("mu0", C.c_double),
+                ("dtype", C.c_int32), ("flags", C.c_uint32)]
+
+
+_vp, _i, _i64, _d = C.c_void_p, C.c_int, C.c_int64, C.c_double
+_dp = C.POINTER(C.c_double)
+_i32p = C.POINTER(C.c_int32)
+_i64p = C.POINTER(C.c_int64)
+
+# name -> argtypes (all return int status unless listed in _CHAR)
+SIGNATURES = {
+    "fit_grid_create": [C.POINTER(GridDesc), _vp, C.POINTER(_vp)],
+    "fit_grid_destroy": [_vp],
+    "fit_set_materials": [_vp, _dp, _dp, _dp],
+    "fit_set_source": [_vp, _i, _i, _i, _i, _d, _d],
+    "fit_cfl_dt": [_vp, _dp],
+    "fit_set_fields": [_vp, _vp, _vp, _i64, _i],
+    "fit_get_fields": [_vp, _vp, _vp, _i],
+    "fit_get_step": [_vp, _i64p],
+    "fit_apply_curl": [_vp, _i, _vp, _vp],
+    "fit_step": [_vp, _i64, _d],
+    "fit_energy": [_vp, _dp],
+    "fit_trace_config": [_vp, _i64, _i64],
+    "fit_trace_read": [_vp, _dp, _i64, _i64p, _i64p],
+    "fit_set_probe": [_vp, _i32p, _i32p],
+    "fit_probe_value": [_vp, _dp],
+    "fit_probe_reset": [_vp],
+    "fit_profile_begin": [_vp, _i64],
+    "fit_profile_end": [_vp, _dp, _i64p],
+    "fit_smvp_count": [_vp, _i64p],
+}
+PROF_KINDS = ("epass", "hpass", "reduce", "step", "adjoint", "other")
+_CHAR = {"fit_version": [], "fit_last_error": []}
+
+_lib = None
+
+
+def lib():
+    """Load libfit.so once; raise if it is missing (no fallback path)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                               "`python -m paper_1705_08019_amd.build`")
+        L = C.CDLL(LIB_PATH)
+        for name, args in SIGNATURES.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        for name, args in _CHAR.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+def check(rc: int):
+    if rc != FIT_OK:
+        raise FitError(rc, lib().fit_last_error().decode())
+    return rc
+
+
+def call(name: str, *args):
+    return check(getattr(lib(), name)(*args))
+
+
+def dptr(arr):
+    """Pointer to a contiguous float64 numpy array (or None)."""
+    if arr is None:
+        return None
+    return arr.ctypes.data_as(_dp)

@@ -1,0 +1,631 @@
+// C-ABI host code of libfit: handle management, material upload, the
+// leapfrog time loop (two kernel launches per step, eq. cost_LF), energy
+// trace bookkeeping and the probe objective.  All arithmetic of the method
+// runs in the HIP kernels; this file only validates, allocates, launches.
+#include "fit.h"
+#include "fit_host.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace fit {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(FIT_E_HIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int dev_alloc(void** p, size_t bytes, const char* what) {
+  *p = nullptr;
+  if (bytes == 0) return FIT_OK;
+  const hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *p = nullptr;
+    return fail(FIT_E_OOM, std::string("hipMalloc failed for ") + what + " (" +
+                               std::to_string(bytes) + " bytes): " + hipGetErrorString(e));
+  }
+  return FIT_OK;
+}
+
+void dev_free(void*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+int ensure_part(fit_grid* g, int64_t rows) {
+  if (rows <= g->part_rows) return FIT_OK;
+  if (g->part) {
+    (void)hipStreamSynchronize(g->s);
+    dev_free(reinterpret_cast<void*&>(g->part));
+  }
+  int rc = dev_alloc(reinterpret_cast<void**>(&g->part), (size_t)rows * kPartTerms * sizeof(double),
+                     "partial sums");
+  if (rc) {
+    g->part_rows = 0;
+    return rc;
+  }
+  g->part_rows = rows;
+  return FIT_OK;
+}
+
+void default_tiling(const Dims& d, int* ty, int* kc) {
+  const int ntx = (d.nx + 63) / 64;
+  const int t = 4;
+  const int nty = (d.ny + t - 1) / t;
+  const int64_t target = 2048;
+  int64_t nkc = (target + (int64_t)ntx * nty - 1) / ((int64_t)ntx * nty);
+  int k = (int)((d.nz + nkc - 1) / nkc);
+  k = std::max(k, 8);
+  *ty = t;
+  *kc = std::min(k, d.nz);
+}
+
+// Host-side mirror of the probe membership of a direction-a edge (used only
+// for argument validation).
+static bool valid_box(const int32_t lo[3], const int32_t hi[3]) {
+  for (int a = 0; a < 3; ++a)
+    if (lo[a] > hi[a]) return false;
+  return true;
+}
+
+template <typename T>
+static void fill_eargs(fit_grid* g, EArgs<T>& a, const T* ein, T* eout, const T* h, double dt,
+                       int64_t m) {
+  const Dims& d = g->d;
+  for (int c = 0; c < 3; ++c) {
+    a.ein[c] = ein + c * d.n;
+    a.eout[c] = eout + c * d.n;
+    a.h[c] = h + c * d.n;
+    a.kb[c] = (T)(4.0 * dt / g->gedge[c]);
+    a.ge[c] = g->gedge[c] / 4.0;
+  }
+  a.eps = static_cast<const T*>(g->eps);
+  a.sig = static_cast<const T*>(g->sig);
+  a.d = d;
+  a.t = make_tiling(d, g->ty, g->kc);
+  a.hs = (T)(0.5 * dt);
+  a.src_comp = g->src_axis;
+  a.src_idx = g->src_axis >= 0 ? g->src_idx : -1;
+  const double val = g->src_axis >= 0 ? source_value(g, dt, m) : 0.0;
+  a.src_val = (T)val;
+  a.src_val_d = (double)(T)val;
+  a.probe = g->probe;
+  a.part = g->part;
+}
+
+template <typename T>
+static void fill_hargs(fit_grid* g, HArgs<T>& a, const T* e, const T* hin, T* hout, double dt) {
+  const Dims& d = g->d;
+  for (int c = 0; c < 3; ++c) {
+    a.e[c] = e + c * d.n;
+    a.hin[c] = hin + c * d.n;
+    a.hout[c] = hout + c * d.n;
+    a.kd[c] = (T)(dt * g->gf2[c]);
+    a.gf2[c] = g->gf2[c];
+  }
+  a.imu = g->mu_uniform ? nullptr : static_cast<const T*>(g->imu);
+  a.imu_u = (T)g->imu_u;
+  a.d = d;
+  a.t = make_tiling(d, g->ty, g->kc);
+  a.part = g->part;
+}
+
+ProfScope::ProfScope(fit_grid* g_, int kind) : g(g_), slot(-1) {
+  if (!g->prof_on || g->prof_used >= (int64_t)g->prof_kind.size()) return;
+  slot = g->prof_used++;
+  g->prof_kind[slot] = kind;
+  (void)hipEventRecord(g->prof_ev[2 * slot], g->s);
+}
+
+ProfScope::~ProfScope() {
+  if (slot >= 0) (void)hipEventRecord(g->prof_ev[2 * slot + 1], g->s);
+}
+
+double source_value(const fit_grid* g, double dt, int64_t m) {
+  const double t = ((double)m + 0.5) * dt;
+  const double x = (t - g->sigma_t) / g->sigma_t;
+  return g->i_max * std::exp(-4.0 * x * x);
+}
+
+// One leapfrog step m -> m+1 with separate e and h passes.  ein/eout and
+// hin/hout may alias (in-place) or not (recording).  Energy partials and the
+// trace rows are produced as configured on the handle.
+template <typename T>
+int step_once(fit_grid* g, double dt, const T* ein, T* eout, const T* hin, T* hout) {
+  const int64_t m = g->m;
+  const bool tr_this = g->trace_every > 0 && m % g->trace_every == 0;
+  const bool tr_next = g->trace_every > 0 && (m + 1) % g->trace_every == 0;
+  const bool have_row = tr_this && g->trace_rows < g->trace_cap;
+  if (tr_this && !have_row) g->trace_dropped++;
+  const bool probe = g->probe.on != 0;
+  const Tiling t = make_tiling(g->d, g->ty, g->kc);
+  const int64_t nb = t.blocks();
+  if ((have_row || tr_next || probe) && ensure_part(g, nb)) return FIT_E_OOM;
+  double* row = have_row ? g->trace + g->trace_rows * FIT_TRACE_COLS : nullptr;
+  hipError_t e;
+
+  EArgs<T> ea;
+  fill_eargs<T>(g, ea, ein, eout, hin, dt, m);
+  {
+    ProfScope ps(g, FIT_PROF_EPASS);
+    e = launch_epass<T>(ea, g->lossy, have_row, probe, g->s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "e-update launch");
+  if (have_row || probe) {
+    const int cols[kPartTerms] = {1, 2, 3, 8, 9, -1, -1, -1};
+    const bool prev_ok = g->pend_m == m;
+    ProfScope ps(g, FIT_PROF_REDUCE);
+    e = launch_reduce(g->part, nb, row, cols, probe ? PE_PROBE : -1, dt,
+                      probe ? g->jacc : nullptr, have_row && !prev_ok ? 4 : -1,
+                      have_row ? m : -1, have_row && prev_ok ? g->pend : nullptr, 4, g->s);
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  }
+
+  HArgs<T> ha;
+  fill_hargs<T>(g, ha, eout, hin, hout, dt);
+  const bool henergy = have_row || tr_next;
+  {
+    ProfScope ps(g, FIT_PROF_HPASS);
+    e = launch_hpass<T>(ha, g->mu_uniform, henergy, g->s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "h-update launch");
+  if (have_row) {
+    const int cols[kPartTerms] = {5, 6, 7, -1, -1, -1, -1, -1};
+    ProfScope ps(g, FIT_PROF_REDUCE);
+    e = launch_reduce(g->part, nb, row, cols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  }
+  if (tr_next) {
+    // <h^(m+1/2), h^(m+3/2)> is the h cross term of row m+1.
+    const int cols[kPartTerms] = {-1, 0, -1, -1, -1, -1, -1, -1};
+    ProfScope ps(g, FIT_PROF_REDUCE);
+    e = launch_reduce(g->part, nb, g->pend, cols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    g->pend_m = m + 1;
+  }
+  if (have_row) g->trace_rows++;
+  g->m = m + 1;
+  g->smvp += 2;
+  return FIT_OK;
+}
+
+template int step_once<float>(fit_grid*, double, const float*, float*, const float*, float*);
+template int step_once<double>(fit_grid*, double, const double*, double*, const double*, double*);
+
+int check_dt(const fit_grid* g, double dt) {
+  if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FIT_E_INVALID, "dt must be positive and finite");
+  if (!(g->desc.flags & FIT_ALLOW_UNSTABLE) && dt > g->cfl * (1.0 + 1e-12))
+    return fail(FIT_E_UNSTABLE, "dt = " + std::to_string(dt) + " exceeds the CFL bound " +
+                                    std::to_string(g->cfl));
+  return FIT_OK;
+}
+
+template <typename T>
+int upload_cells(fit_grid* g, void** dst, const std::vector<double>& v, const char* what) {
+  if (!*dst) {
+    int rc = dev_alloc(dst, v.size() * sizeof(T), what);
+    if (rc) return rc;
+  }
+  std::vector<T> tmp(v.begin(), v.end());
+  hipError_t e = hipMemcpyAsync(*dst, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, g->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->s);
+  if (e != hipSuccess) return hip_fail(e, "material upload");
+  return FIT_OK;
+}
+
+}  // namespace fit
+
+using namespace fit;
+
+extern "C" {
+
+const char* fit_version(void) { return "fitmi 0.1 (gfx950)"; }
+
+const char* fit_last_error(void) { return g_err.c_str(); }
+
+int fit_grid_create(const fit_grid_desc* desc, void* stream, fit_grid** out) {
+  if (!desc || !out) return fail(FIT_E_INVALID, "null argument");
+  *out = nullptr;
+  if (desc->nx < 1 || desc->ny < 1 || desc->nz < 1)
+    return fail(FIT_E_INVALID, "need at least one cell per axis");
+  if (desc->dtype != FIT_F32 && desc->dtype != FIT_F64) return fail(FIT_E_INVALID, "bad dtype");
+  const double sp[3] = {desc->dx, desc->dy, desc->dz};
+  for (double v : sp)
+    if (!(v >= 0.0) || !std::isfinite(v)) return fail(FIT_E_INVALID, "spacings must be >= 0");
+  if (!(desc->eps0 >= 0.0) || !(desc->mu0 >= 0.0) || !std::isfinite(desc->eps0) ||
+      !std::isfinite(desc->mu0))
+    return fail(FIT_E_INVALID, "eps0, mu0 must be >= 0");
+  const int64_t n = (int64_t)desc->nx * desc->ny * desc->nz;
+  if (n > (int64_t)1 << 40) return fail(FIT_E_INVALID, "grid too large");
+  fit_grid* g = new (std::nothrow) fit_grid();
+  if (!g) return fail(FIT_E_OOM, "host allocation failed");
+  g->desc = *desc;
+  double* dd[3] = {&g->desc.dx, &g->desc.dy, &g->desc.dz};
+  for (double* v : dd)
+    if (*v == 0.0) *v = 1.0;
+  if (g->desc.eps0 == 0.0) g->desc.eps0 = 1.0;
+  if (g->desc.mu0 == 0.0) g->desc.mu0 = 1.0;
+  g->s = static_cast<hipStream_t>(stream);
+  g->f64 = desc->dtype == FIT_F64;
+  g->esz = g->f64 ? 8 : 4;
+  g->d.nx = desc->nx;
+  g->d.ny = desc->ny;
+  g->d.nz = desc->nz;
+  g->d.sx = desc->nx;
+  g->d.sxy = (int64_t)desc->nx * desc->ny;
+  g->d.n = n;
+  const double s3[3] = {g->desc.dx, g->desc.dy, g->desc.dz};
+  for (int a = 0; a < 3; ++a) {
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    g->gedge[a] = s3[b] * s3[c] / s3[a];          // M_eps = eps * g_a
+    g->gf2[a] = s3[a] / (s3[b] * s3[c]) / 2.0;    // M_mu^{-1} = gf2 (imu_1 + imu_2)
+  }
+  default_tiling(g->d, &g->ty, &g->kc);
+  int rc = dev_alloc(&g->e, 3 * n * g->esz, "e");
+  if (!rc) rc = dev_alloc(&g->h, 3 * n * g->esz, "h");
+  if (!rc) rc = dev_alloc(&g->eps, n * g->esz, "eps");
+  if (!rc) rc = dev_alloc(reinterpret_cast<void**>(&g->jacc), 4 * sizeof(double), "probe sum");
+  if (!rc) rc = dev_alloc(reinterpret_cast<void**>(&g->pend), sizeof(double), "pending term");
+  if (rc) {
+    fit_grid_destroy(g);
+    return rc;
+  }
+  hipError_t e = hipMemsetAsync(g->e, 0, 3 * n * g->esz, g->s);
+  if (e == hipSuccess) e = hipMemsetAsync(g->h, 0, 3 * n * g->esz, g->s);
+  if (e == hipSuccess) e = hipMemsetAsync(g->jacc, 0, 4 * sizeof(double), g->s);
+  if (e != hipSuccess) {
+    fit_grid_destroy(g);
+    return hip_fail(e, "initial clear");
+  }
+  // vacuum materials
+  std::vector<double> ones((size_t)n, 1.0);
+  rc = fit_set_materials(g, ones.data(), nullptr, nullptr);
+  if (rc) {
+    fit_grid_destroy(g);
+    return rc;
+  }
+  *out = g;
+  return FIT_OK;
+}
+
+int fit_grid_destroy(fit_grid* g) {
+  if (!g) return FIT_OK;
+  (void)hipStreamSynchronize(g->s);
+  for (hipEvent_t ev : g->prof_ev) (void)hipEventDestroy(ev);
+  g->prof_ev.clear();
+  grid_release_extras(g);
+  dev_free(g->e);
+  dev_free(g->h);
+  dev_free(g->eps);
+  dev_free(g->sig);
+  dev_free(g->imu);
+  dev_free(reinterpret_cast<void*&>(g->part));
+  dev_free(reinterpret_cast<void*&>(g->trace));
+  dev_free(reinterpret_cast<void*&>(g->jacc));
+  dev_free(reinterpret_cast<void*&>(g->pend));
+  delete g;
+  return FIT_OK;
+}
+
+int fit_set_materials(fit_grid* g, const double* eps_r, const double* mu_r, const double* sigma) {
+  if (!g || !eps_r) return fail(FIT_E_INVALID, "null argument");
+  const int64_t n = g->d.n;
+  std::vector<double> eps((size_t)n), imu((size_t)n), sig;
+  bool lossy = false;
+  double cfl = INFINITY;
+  const double inv = 1.0 / (g->desc.dx * g->desc.dx) + 1.0 / (g->desc.dy * g->desc.dy) +
+                     1.0 / (g->desc.dz * g->desc.dz);
+  bool mu_uni = true;
+  for (int64_t c = 0; c < n; ++c) {
+    const double er = eps_r[c];
+    const double mr = mu_r ? mu_r[c] : 1.0;
+    if (!(er > 0.0) || !std::isfinite(er)) return fail(FIT_E_INVALID, "eps_r must be > 0 and finite");
+    if (!(mr > 0.0) || !std::isfinite(mr)) return fail(FIT_E_INVALID, "mu_r must be > 0 and finite");
+    eps[c] = g->desc.eps0 * er;
+    imu[c] = 1.0 / (g->desc.mu0 * mr);
+    if (imu[c] != imu[0]) mu_uni = false;
+    cfl = std::min(cfl, std::sqrt(eps[c] * (g->desc.mu0 * mr) / inv));
+  }
+  if (sigma) {
+    sig.resize((size_t)n);
+    for (int64_t c = 0; c < n; ++c) {
+      if (!(sigma[c] >= 0.0) || !std::isfinite(sigma[c]))
+        return fail(FIT_E_INVALID, "sigma must be >= 0 and finite");
+      sig[c] = sigma[c];
+      if (sigma[c] != 0.0) lossy = true;
+    }
+  }
+  int rc = g->f64 ? upload_cells<double>(g, &g->eps, eps, "eps") : upload_cells<float>(g, &g->eps, eps, "eps");
+  if (rc) return rc;
+  if (lossy) {
+    rc = g->f64 ? upload_cells<double>(g, &g->sig, sig, "sigma")
+                : upload_cells<float>(g, &g->sig, sig, "sigma");
+    if (rc) return rc;
+  }
+  if (!mu_uni) {
+    rc = g->f64 ? upload_cells<double>(g, &g->imu, imu, "1/mu")
+                : upload_cells<float>(g, &g->imu, imu, "1/mu");
+    if (rc) return rc;
+  }
+  g->lossy = lossy;
+  g->mu_uniform = mu_uni;
+  g->imu_u = imu[0];
+  g->cfl = cfl;
+  g->eps_host = eps;
+  g->sig_host = lossy ? sig : std::vector<double>();
+  g->materials_version++;
+  return FIT_OK;
+}
+
+int fit_set_source(fit_grid* g, int axis, int i, int j, int k, double i_max, double sigma_t) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  if (axis == -1) {
+    g->src_axis = -1;
+    g->src_idx = -1;
+    return FIT_OK;
+  }
+  if (axis < 0 || axis > 2) return fail(FIT_E_INVALID, "axis must be 0, 1, 2 or -1");
+  if (!(sigma_t > 0.0) || !std::isfinite(sigma_t) || !std::isfinite(i_max))
+    return fail(FIT_E_INVALID, "sigma_t must be > 0");
+  const int p[3] = {i, j, k};
+  const int nn[3] = {g->d.nx, g->d.ny, g->d.nz};
+  for (int a = 0; a < 3; ++a) {
+    const int lo = (a == axis) ? 0 : 1;
+    const int hi = (a == axis) ? nn[a] - 1 : nn[a] - 1;
+    if (p[a] < lo || p[a] > hi)
+      return fail(FIT_E_INVALID, "source edge lies outside the grid or in a PEC wall");
+  }
+  g->src_axis = axis;
+  g->src_idx = (int64_t)i + g->d.sx * j + g->d.sxy * (int64_t)k;
+  g->i_max = i_max;
+  g->sigma_t = sigma_t;
+  return FIT_OK;
+}
+
+int fit_cfl_dt(const fit_grid* g, double* dt_cfl) {
+  if (!g || !dt_cfl) return fail(FIT_E_INVALID, "null argument");
+  *dt_cfl = g->cfl;
+  return FIT_OK;
+}
+
+static int copy_field(fit_grid* g, void* dst, const void* src, int dir_in, int on_device) {
+  const size_t bytes = 3 * (size_t)g->d.n * g->esz;
+  hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice
+                                 : (dir_in ? hipMemcpyHostToDevice : hipMemcpyDeviceToHost);
+  hipError_t e = hipMemcpyAsync(dst, src, bytes, kind, g->s);
+  if (e == hipSuccess && !on_device) e = hipStreamSynchronize(g->s);
+  if (e != hipSuccess) return hip_fail(e, "field copy");
+  return FIT_OK;
+}
+
+int fit_set_fields(fit_grid* g, const void* e, const void* h, int64_t step, int on_device) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  if (step < 0) return fail(FIT_E_INVALID, "step must be >= 0");
+  const size_t bytes = 3 * (size_t)g->d.n * g->esz;
+  hipError_t er;
+  int rc;
+  if (e) {
+    if ((rc = copy_field(g, g->e, e, 1, on_device))) return rc;
+  } else if ((er = hipMemsetAsync(g->e, 0, bytes, g->s)) != hipSuccess) {
+    return hip_fail(er, "clear e");
+  }
+  if (h) {
+    if ((rc = copy_field(g, g->h, h, 1, on_device))) return rc;
+  } else if ((er = hipMemsetAsync(g->h, 0, bytes, g->s)) != hipSuccess) {
+    return hip_fail(er, "clear h");
+  }
+  if (g->f64) {
+    er = launch_mask<double>(static_cast<double*>(g->e), g->d, 0, g->s);
+    if (er == hipSuccess) er = launch_mask<double>(static_cast<double*>(g->h), g->d, 1, g->s);
+  } else {
+    er = launch_mask<float>(static_cast<float*>(g->e), g->d, 0, g->s);
+    if (er == hipSuccess) er = launch_mask<float>(static_cast<float*>(g->h), g->d, 1, g->s);
+  }
+  if (er != hipSuccess) return hip_fail(er, "PEC mask");
+  g->m = step;
+  g->pend_m = -1;
+  return FIT_OK;
+}
+
+int fit_get_fields(fit_grid* g, void* e, void* h, int on_device) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  int rc;
+  if (e && (rc = copy_field(g, e, g->e, 0, on_device))) return rc;
+  if (h && (rc = copy_field(g, h, g->h, 0, on_device))) return rc;
+  return FIT_OK;
+}
+
+int fit_get_step(const fit_grid* g, int64_t* step) {
+  if (!g || !step) return fail(FIT_E_INVALID, "null argument");
+  *step = g->m;
+  return FIT_OK;
+}
+
+int fit_apply_curl(fit_grid* g, int which, const void* in, void* out) {
+  if (!g || !in || !out) return fail(FIT_E_INVALID, "null argument");
+  if (which != 0 && which != 1) return fail(FIT_E_INVALID, "which must be 0 (C) or 1 (C~)");
+  if (in == out) return fail(FIT_E_INVALID, "in and out must differ");
+  hipError_t e = g->f64 ? launch_curl<double>(static_cast<const double*>(in), static_cast<double*>(out), g->d, which, g->s)
+                        : launch_curl<float>(static_cast<const float*>(in), static_cast<float*>(out), g->d, which, g->s);
+  if (e != hipSuccess) return hip_fail(e, "curl launch");
+  return FIT_OK;
+}
+
+int fit_step(fit_grid* g, int64_t nsteps, double dt) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  if (nsteps < 0) return fail(FIT_E_INVALID, "nsteps must be >= 0");
+  int rc = check_dt(g, dt);
+  if (rc) return rc;
+  for (int64_t s = 0; s < nsteps; ++s) {
+    rc = g->f64 ? step_once<double>(g, dt, static_cast<const double*>(g->e), static_cast<double*>(g->e),
+                                    static_cast<const double*>(g->h), static_cast<double*>(g->h))
+                : step_once<float>(g, dt, static_cast<const float*>(g->e), static_cast<float*>(g->e),
+                                   static_cast<const float*>(g->h), static_cast<float*>(g->h));
+    if (rc) return rc;
+  }
+  return FIT_OK;
+}
+
+int fit_energy(fit_grid* g, double out[2]) {
+  if (!g || !out) return fail(FIT_E_INVALID, "null argument");
+  const int64_t nb = (g->d.n + 255) / 256;
+  int rc = ensure_part(g, nb);
+  if (rc) return rc;
+  double ge[3], gf2[3];
+  for (int a = 0; a < 3; ++a) {
+    ge[a] = g->gedge[a] / 4.0;
+    gf2[a] = g->gf2[a];
+  }
+  int64_t nblk = 0;
+  hipError_t e;
+  if (g->f64)
+    e = launch_energy<double>(static_cast<const double*>(g->e), static_cast<const double*>(g->h),
+                              static_cast<const double*>(g->eps),
+                              g->mu_uniform ? nullptr : static_cast<const double*>(g->imu),
+                              g->imu_u, g->d, ge, gf2, g->part, &nblk, g->s);
+  else
+    e = launch_energy<float>(static_cast<const float*>(g->e), static_cast<const float*>(g->h),
+                             static_cast<const float*>(g->eps),
+                             g->mu_uniform ? nullptr : static_cast<const float*>(g->imu),
+                             (float)g->imu_u, g->d, ge, gf2, g->part, &nblk, g->s);
+  if (e != hipSuccess) return hip_fail(e, "energy launch");
+  // reduce into the tail of the partial buffer's first row is unsafe; use the pending slot pair
+  const int cols[kPartTerms] = {0, 1, -1, -1, -1, -1, -1, -1};
+  e = launch_reduce(g->part, nblk, g->jacc + 2, cols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
+  if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  e = hipMemcpyAsync(out, g->jacc + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, g->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->s);
+  if (e != hipSuccess) return hip_fail(e, "energy readback");
+  if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
+    return fail(FIT_E_DIVERGED, "energy is not finite");
+  return FIT_OK;
+}
+
+int fit_trace_config(fit_grid* g, int64_t every, int64_t capacity) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  if (every < 0 || capacity < 0) return fail(FIT_E_INVALID, "every, capacity must be >= 0");
+  (void)hipStreamSynchronize(g->s);
+  dev_free(reinterpret_cast<void*&>(g->trace));
+  g->trace_every = 0;
+  g->trace_cap = 0;
+  g->trace_rows = 0;
+  g->trace_dropped = 0;
+  g->pend_m = -1;
+  if (every > 0 && capacity > 0) {
+    int rc = dev_alloc(reinterpret_cast<void**>(&g->trace),
+                       (size_t)capacity * FIT_TRACE_COLS * sizeof(double), "trace");
+    if (rc) return rc;
+    g->trace_every = every;
+    g->trace_cap = capacity;
+  }
+  return FIT_OK;
+}
+
+int fit_trace_read(fit_grid* g, double* out, int64_t max_rows, int64_t* nrows, int64_t* dropped) {
+  if (!g || !nrows || (max_rows > 0 && !out)) return fail(FIT_E_INVALID, "null argument");
+  const int64_t n = std::min<int64_t>(std::max<int64_t>(max_rows, 0), g->trace_rows);
+  if (n > 0) {
+    hipError_t e = hipMemcpyAsync(out, g->trace, (size_t)n * FIT_TRACE_COLS * sizeof(double),
+                                  hipMemcpyDeviceToHost, g->s);
+    if (e != hipSuccess) return hip_fail(e, "trace readback");
+  }
+  hipError_t e = hipStreamSynchronize(g->s);
+  if (e != hipSuccess) return hip_fail(e, "trace readback");
+  *nrows = n;
+  if (dropped) *dropped = g->trace_dropped + (g->trace_rows - n);
+  g->trace_rows = 0;
+  g->trace_dropped = 0;
+  for (int64_t r = 0; r < n; ++r)
+    if (!std::isfinite(out[r * FIT_TRACE_COLS + 1]) || !std::isfinite(out[r * FIT_TRACE_COLS + 5]))
+      return fail(FIT_E_DIVERGED, "traced energy is not finite");
+  return FIT_OK;
+}
+
+int fit_set_probe(fit_grid* g, const int32_t lo[3], const int32_t hi[3]) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  if (!lo && !hi) {
+    g->probe.on = 0;
+  } else {
+    if (!lo || !hi || !valid_box(lo, hi)) return fail(FIT_E_INVALID, "bad probe box");
+    for (int a = 0; a < 3; ++a) {
+      g->probe.lo[a] = lo[a];
+      g->probe.hi[a] = hi[a];
+    }
+    g->probe.on = 1;
+  }
+  return fit_probe_reset(g);
+}
+
+int fit_probe_value(fit_grid* g, double* J) {
+  if (!g || !J) return fail(FIT_E_INVALID, "null argument");
+  double v[2];
+  hipError_t e = hipMemcpyAsync(v, g->jacc, 2 * sizeof(double), hipMemcpyDeviceToHost, g->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->s);
+  if (e != hipSuccess) return hip_fail(e, "probe readback");
+  *J = v[0] + v[1];
+  return FIT_OK;
+}
+
+int fit_probe_reset(fit_grid* g) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  hipError_t e = hipMemsetAsync(g->jacc, 0, 2 * sizeof(double), g->s);
+  if (e != hipSuccess) return hip_fail(e, "probe reset");
+  return FIT_OK;
+}
+
+int fit_profile_begin(fit_grid* g, int64_t max_launches) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  if (max_launches < 0 || max_launches > (1 << 22)) return fail(FIT_E_INVALID, "bad max_launches");
+  const size_t need = 2 * (size_t)max_launches;
+  while (g->prof_ev.size() < need) {
+    hipEvent_t ev;
+    hipError_t e = hipEventCreate(&ev);
+    if (e != hipSuccess) return hip_fail(e, "hipEventCreate");
+    g->prof_ev.push_back(ev);
+  }
+  g->prof_kind.assign((size_t)max_launches, FIT_PROF_OTHER);
+  g->prof_used = 0;
+  g->prof_on = true;
+  return FIT_OK;
+}
+
+int fit_profile_end(fit_grid* g, double ms[FIT_PROF_N], int64_t count[FIT_PROF_N]) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  if (!g->prof_on) return fail(FIT_E_STATE, "profiling was not started");
+  g->prof_on = false;
+  hipError_t e = hipStreamSynchronize(g->s);
+  if (e != hipSuccess) return hip_fail(e, "profile sync");
+  double acc[FIT_PROF_N] = {0};
+  int64_t cnt[FIT_PROF_N] = {0};
+  for (int64_t i = 0; i < g->prof_used; ++i) {
+    float t = 0.f;
+    e = hipEventElapsedTime(&t, g->prof_ev[2 * i], g->prof_ev[2 * i + 1]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    acc[g->prof_kind[i]] += t;
+    cnt[g->prof_kind[i]]++;
+  }
+  for (int k = 0; k < FIT_PROF_N; ++k) {
+    if (ms) ms[k] = acc[k];
+    if (count) count[k] = cnt[k];
+  }
+  return FIT_OK;
+}
+
+int fit_smvp_count(const fit_grid* g, int64_t* count) {
+  if (!g || !count) return fail(FIT_E_INVALID, "null argument");
+  *count = g->smvp;
+  return FIT_OK;
+}
+
+}  // extern "C"

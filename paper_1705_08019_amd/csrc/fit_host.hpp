@@ -1,0 +1,76 @@
+// Host-side handle definition and helpers shared by the C-ABI source files.
+#pragma once
+
+#include <string>
+#include <vector>
+
+#include "fit.h"
+#include "fit_internal.hpp"
+
+struct fit_adjoint_ws;
+
+struct fit_grid {
+  fit_grid_desc desc{};
+  fit::Dims d{};
+  hipStream_t s = nullptr;
+  bool f64 = false;
+  size_t esz = 4;
+  void* e = nullptr;     // 3 * n field values, slot layout
+  void* h = nullptr;
+  void* eps = nullptr;   // eps0 * eps_r per cell (field dtype)
+  void* sig = nullptr;   // sigma per cell, allocated when some sigma != 0
+  void* imu = nullptr;   // 1/(mu0 mu_r) per cell, allocated when mu is not uniform
+  bool lossy = false;
+  bool mu_uniform = true;
+  double imu_u = 1.0;
+  double cfl = 0.0;
+  std::vector<double> eps_host, sig_host;   // FP64 copies (adjoint chain rule, checks)
+  int64_t materials_version = 0;
+  double gedge[3] = {1, 1, 1};   // d_b d_c / d_a
+  double gf2[3] = {0.5, 0.5, 0.5};
+  int src_axis = -1;
+  int64_t src_idx = -1;
+  double i_max = 0.0, sigma_t = 1.0;
+  int64_t m = 0;
+  int64_t smvp = 0;              // curl applications performed (2 per step)
+  double* part = nullptr;
+  int64_t part_rows = 0;
+  double* trace = nullptr;
+  int64_t trace_every = 0, trace_cap = 0, trace_rows = 0, trace_dropped = 0;
+  double* pend = nullptr;        // h cross term waiting for the next trace row
+  int64_t pend_m = -1;
+  double* jacc = nullptr;        // [0..1] probe (sum, comp), [2..3] energy scratch
+  fit::Probe probe{};
+  int ty = 4, kc = 64;
+  fit_adjoint_ws* adj = nullptr;
+  // kernel timing (fit_profile_begin/end)
+  std::vector<hipEvent_t> prof_ev;   // 2 per timed launch
+  std::vector<int> prof_kind;
+  int64_t prof_used = 0;
+  bool prof_on = false;
+};
+
+namespace fit {
+
+extern thread_local std::string g_err;
+int fail(int code, const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+int dev_alloc(void** p, size_t bytes, const char* what);
+void dev_free(void*& p);
+int ensure_part(fit_grid* g, int64_t rows);
+double source_value(const fit_grid* g, double dt, int64_t m);
+int check_dt(const fit_grid* g, double dt);
+template <typename T>
+int step_once(fit_grid* g, double dt, const T* ein, T* eout, const T* hin, T* hout);
+// Frees adjoint/other optional workspaces (defined with those features).
+void grid_release_extras(fit_grid* g);
+
+// Bracket one kernel launch with timing events when profiling is on.
+struct ProfScope {
+  fit_grid* g;
+  int64_t slot;
+  ProfScope(fit_grid* g_, int kind);
+  ~ProfScope();
+};
+
+}  // namespace fit

@@ -1,0 +1,104 @@
+// Internal declarations shared by the HIP kernel files and the C-ABI host code.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace fit {
+
+// Grid geometry in the slot layout: component arrays of n = nx*ny*nz
+// elements, x fastest.  sx = nx, sxy = nx*ny.
+struct Dims {
+  int nx, ny, nz;
+  int64_t sx, sxy, n;
+};
+
+// Tiling of a z-marching launch: blockDim = (64, ty); each thread owns one
+// (i, j) column of a 64 x ty tile and marches over a chunk of kc planes.
+struct Tiling {
+  int ty, kc;
+  int ntx, nty, nkc;
+  int64_t blocks() const { return (int64_t)ntx * nty * nkc; }
+};
+
+Tiling make_tiling(const Dims& d, int ty, int kc);
+
+// Closed probe box in node coordinates; a direction-a edge at node p is in
+// the probe when lo[a] <= p_a and p_a + 1 <= hi[a] and lo[b] <= p_b <= hi[b]
+// for the two other axes.
+struct Probe {
+  int lo[3], hi[3];
+  int on;
+};
+
+// Number of FP64 partial terms written per block by the energy variants.
+constexpr int kPartTerms = 8;
+// E-pass partial term slots
+enum { PE_EE_MM = 0, PE_EE_MM1 = 1, PE_EE_M1M1 = 2, PE_LOSS = 3, PE_SRC = 4, PE_PROBE = 5 };
+// H-pass partial term slots
+enum { PH_HH_CC = 0, PH_HH_CN = 1, PH_HH_NN = 2 };
+
+template <typename T>
+struct EArgs {
+  const T* ein[3];
+  T* eout[3];
+  const T* h[3];
+  const T* eps;      // eps0 * eps_r per cell
+  const T* sig;      // sigma per cell (lossy variant only)
+  Dims d;
+  Tiling t;
+  T kb[3];           // 4 dt / g_a with g_a = d_b d_c / d_a  (cb = kb / (S4eps + hs S4sig))
+  T hs;              // dt / 2
+  double ge[3];      // g_a / 4: M_eps = ge * S4eps,  M_sigma = ge * S4sig
+  int src_comp;      // -1: no source
+  int64_t src_idx;
+  T src_val;         // i(t_{m+1/2})
+  double src_val_d;
+  Probe probe;
+  double* part;      // [blocks][kPartTerms] or null
+};
+
+template <typename T>
+struct HArgs {
+  const T* e[3];
+  const T* hin[3];
+  T* hout[3];
+  const T* imu;      // 1 / (mu0 mu_r) per cell, or null when uniform
+  T imu_u;           // uniform 1 / (mu0 mu_r)
+  Dims d;
+  Tiling t;
+  T kd[3];           // dt * d_a / (d_b d_c) / 2  (cd = kd * (imu_1 + imu_2))
+  double gf2[3];     // d_a / (d_b d_c) / 2: M_mu^{-1} = gf2 * (imu_1 + imu_2)
+  double* part;
+};
+
+// Launch wrappers (fit_kernels.hip).  Return hipError_t of the launch.
+template <typename T>
+hipError_t launch_epass(const EArgs<T>& a, bool lossy, bool energy, bool probe, hipStream_t s);
+template <typename T>
+hipError_t launch_hpass(const HArgs<T>& a, bool mu_uniform, bool energy, hipStream_t s);
+
+// Reduce `nblk` rows of kPartTerms partial sums (FP64, Neumaier) and scatter
+// term t to dst[cols[t]] (cols[t] < 0: skip).  If jacc != null, term
+// probe_term times jscale is added to the compensated pair jacc[0..1].
+// If nan_col >= 0, dst[nan_col] is set to NaN; if row_m >= 0, dst[0] = row_m.
+// If pend != null, dst[pend_col] = *pend (a term reduced by an earlier launch).
+hipError_t launch_reduce(const double* part, int64_t nblk, double* dst, const int* cols,
+                         int probe_term, double jscale, double* jacc, int nan_col,
+                         int64_t row_m, const double* pend, int pend_col, hipStream_t s);
+
+// Zero the slots of PEC-wall edges (which = 0) or facets (which = 1).
+template <typename T>
+hipError_t launch_mask(T* f, const Dims& d, int which, hipStream_t s);
+
+// out = C in (which = 0, edges -> facets) or C~ in (which = 1, facets -> edges).
+template <typename T>
+hipError_t launch_curl(const T* in, T* out, const Dims& d, int which, hipStream_t s);
+
+// Standalone energies <e,e>_eps and <h,h>_mu of a state -> part rows 0, 1.
+template <typename T>
+hipError_t launch_energy(const T* e, const T* h, const T* eps, const T* imu, T imu_u,
+                         const Dims& d, const double ge[3], const double gf2[3],
+                         double* part, int64_t* nblk, hipStream_t s);
+
+}  // namespace fit

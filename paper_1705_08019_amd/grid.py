@@ -1,0 +1,205 @@
+"""Python handle for one FIT grid (thin wrapper over the C ABI in include/fit.h).
+
+PyTorch supplies device memory for the tensors handed in and out and the
+stream the library enqueues on; every step of the method runs in libfit's
+HIP kernels.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import call, dptr
+
+_TORCH_DTYPE = {"f32": torch.float32, "f64": torch.float64}
+_NP_DTYPE = {"f32": np.float32, "f64": np.float64}
+
+
+def current_stream_handle(device=None) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+class FitGrid:
+    """nx x ny x nz cell grid with PEC walls, fields in the slot layout
+    (3, nz, ny, nx): slot [a, k, j, i] = edge/facet of direction a at node (i, j, k)."""
+
+    def __init__(self, nx: int, ny: int, nz: int, dtype: str = "f32",
+                 spacing=(1.0, 1.0, 1.0), eps0: float = 1.0, mu0: float = 1.0,
+                 allow_unstable: bool = False, stream=None):
+        if dtype not in _TORCH_DTYPE:
+            raise ValueError("dtype must be 'f32' or 'f64'")
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.dtype = dtype
+        self.tdtype = _TORCH_DTYPE[dtype]
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self._stream = current_stream_handle() if stream is None else int(stream)
+        desc = _lib.GridDesc(self.nx, self.ny, self.nz, *map(float, spacing),
+                             float(eps0), float(mu0),
+                             _lib.FIT_F64 if dtype == "f64" else _lib.FIT_F32,
+                             _lib.FIT_ALLOW_UNSTABLE if allow_unstable else 0)
+        h = C.c_void_p()
+        call("fit_grid_create", C.byref(desc), C.c_void_p(self._stream), C.byref(h))
+        self._h = h
+
+    # ------------------------------------------------------------------ lifecycle
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().fit_grid_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (3, self.nz, self.ny, self.nx)
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    # ------------------------------------------------------------------ setup
+    def set_materials(self, eps_r, mu_r=None, sigma=None):
+        def prep(a):
+            if a is None:
+                return None
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            if a.size != self.cells:
+                raise ValueError("per-cell arrays need nx*ny*nz values")
+            return a
+        e, m, s = prep(eps_r), prep(mu_r), prep(sigma)
+        call("fit_set_materials", self._h, dptr(e), dptr(m), dptr(s))
+
+    def set_source(self, axis: int, i: int, j: int, k: int, i_max: float, sigma_t: float):
+        call("fit_set_source", self._h, axis, i, j, k, float(i_max), float(sigma_t))
+
+    def clear_source(self):
+        call("fit_set_source", self._h, -1, 0, 0, 0, 0.0, 1.0)
+
+    def cfl_dt(self) -> float:
+        v = C.c_double()
+        call("fit_cfl_dt", self._h, C.byref(v))
+        return v.value
+
+    # ------------------------------------------------------------------ state
+    def _as_arg(self, x):
+        """(pointer, on_device, keepalive) for a field given as tensor/ndarray/None."""
+        if x is None:
+            return None, 1, None
+        if isinstance(x, torch.Tensor):
+            if tuple(x.shape) != self.shape and x.numel() != 3 * self.cells:
+                raise ValueError(f"field must have {3 * self.cells} values")
+            if x.is_cuda:
+                x = x.to(self.tdtype).contiguous()
+                return C.c_void_p(x.data_ptr()), 1, x
+            x = x.detach().numpy()
+        a = np.ascontiguousarray(x, dtype=_NP_DTYPE[self.dtype])
+        if a.size != 3 * self.cells:
+            raise ValueError(f"field must have {3 * self.cells} values")
+        return C.c_void_p(a.ctypes.data), 0, a
+
+    def set_fields(self, e=None, h=None, step: int = 0):
+        pe, de, ke = self._as_arg(e)
+        ph, dh, kh = self._as_arg(h)
+        if pe is not None and ph is not None and de != dh:
+            # mixed host/device: go through the device for both
+            e = torch.as_tensor(np.asarray(e)).to(self.device) if de == 0 else e
+            h = torch.as_tensor(np.asarray(h)).to(self.device) if dh == 0 else h
+            return self.set_fields(e, h, step)
+        on_dev = de if pe is not None else dh
+        call("fit_set_fields", self._h, pe, ph, int(step), on_dev)
+        torch.cuda.current_stream().synchronize() if on_dev else None
+        del ke, kh
+
+    def get_fields(self):
+        """(e, h) as new device tensors of shape (3, nz, ny, nx)."""
+        e = torch.empty(self.shape, dtype=self.tdtype, device=self.device)
+        h = torch.empty(self.shape, dtype=self.tdtype, device=self.device)
+        call("fit_get_fields", self._h, C.c_void_p(e.data_ptr()), C.c_void_p(h.data_ptr()), 1)
+        return e, h
+
+    def get_fields_host(self):
+        e = np.empty(self.shape, dtype=_NP_DTYPE[self.dtype])
+        h = np.empty(self.shape, dtype=_NP_DTYPE[self.dtype])
+        call("fit_get_fields", self._h, C.c_void_p(e.ctypes.data), C.c_void_p(h.ctypes.data), 0)
+        return e, h
+
+    @property
+    def step_index(self) -> int:
+        v = C.c_int64()
+        call("fit_get_step", self._h, C.byref(v))
+        return v.value
+
+    # ------------------------------------------------------------------ operators
+    def apply_curl(self, x: torch.Tensor, which: int) -> torch.Tensor:
+        """which = 0: C (edges -> facets); which = 1: C~ (facets -> edges)."""
+        if x.numel() != 3 * self.cells:
+            raise ValueError(f"input must have {3 * self.cells} values")
+        x = x.to(device=self.device, dtype=self.tdtype).contiguous()
+        out = torch.empty(self.shape, dtype=self.tdtype, device=self.device)
+        call("fit_apply_curl", self._h, int(which), C.c_void_p(x.data_ptr()),
+             C.c_void_p(out.data_ptr()))
+        return out
+
+    def step(self, nsteps: int, dt: float):
+        call("fit_step", self._h, int(nsteps), float(dt))
+
+    def energy(self):
+        out = (C.c_double * 2)()
+        call("fit_energy", self._h, out)
+        return out[0], out[1]
+
+    # ------------------------------------------------------------------ diagnostics
+    def trace_config(self, every: int, capacity: int):
+        call("fit_trace_config", self._h, int(every), int(capacity))
+        self._trace_cap = int(capacity)
+
+    def trace_read(self, max_rows: int = None):
+        cap = int(getattr(self, "_trace_cap", 0) if max_rows is None else max_rows)
+        out = np.empty((max(cap, 1), _lib.FIT_TRACE_COLS), dtype=np.float64)
+        n, dropped = C.c_int64(), C.c_int64()
+        call("fit_trace_read", self._h, dptr(out), cap, C.byref(n), C.byref(dropped))
+        return out[: n.value].copy(), dropped.value
+
+    def set_probe(self, lo, hi):
+        lo_a = (C.c_int32 * 3)(*map(int, lo))
+        hi_a = (C.c_int32 * 3)(*map(int, hi))
+        call("fit_set_probe", self._h, lo_a, hi_a)
+
+    def clear_probe(self):
+        call("fit_set_probe", self._h, None, None)
+
+    def probe_value(self) -> float:
+        v = C.c_double()
+        call("fit_probe_value", self._h, C.byref(v))
+        return v.value
+
+    def probe_reset(self):
+        call("fit_probe_reset", self._h)
+
+    # ------------------------------------------------------------------ timing
+    def profile_begin(self, max_launches: int):
+        call("fit_profile_begin", self._h, int(max_launches))
+
+    def profile_end(self) -> dict:
+        """{kind: (total_ms, launches)} over the launches since profile_begin."""
+        n = len(_lib.PROF_KINDS)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int64 * n)()
+        call("fit_profile_end", self._h, ms, cnt)
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(_lib.PROF_KINDS)}
+
+    def smvp_count(self) -> int:
+        v = C.c_int64()
+        call("fit_smvp_count", self._h, C.byref(v))
+        return v.value

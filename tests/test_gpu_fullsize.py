@@ -1,0 +1,92 @@
+"""Full-size parity on the 256 x 256 x 512 bandwidth workload, in the launch
+configuration the benchmark times.
+
+The oracle cannot hold the whole grid, so one GPU step is checked on sampled
+6 x 6 x 6-cell windows: the oracle, built for the window alone, advances the
+window's state by one step; every e on a window-interior edge, and every h on
+a facet whose boundary edges are all window-interior, depends only on data
+inside the window and must match.  Along the run, the discrete energy balance
+Q^(m+1) - Q^m = -2 dt (ebar M_sigma ebar + ebar j_s) is checked on the GPU's
+own FP64 trace (a property that holds at any size).
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from fit_workloads import c3
+from oracle.topology import Topology
+from oracle.materials import Materials
+from oracle.leapfrog import Operators, run
+from oracle import layout
+
+pytestmark = pytest.mark.gpu
+
+
+def _window_check(spec, e0, h0, e1, h1, dt, src, origin, step0, w=6):
+    i0, j0, k0 = origin
+    sl = (slice(None), slice(k0, k0 + w), slice(j0, j0 + w), slice(i0, i0 + w))
+    t = Topology(w, w, w)
+    eps = spec.eps_r[sl[1:]]
+    sig = None if spec.sigma is None else spec.sigma[sl[1:]]
+    ops = Operators(t, Materials(t, eps, sigma=sig))
+    ew0 = layout.edges_from_slots(ops, e0[sl].astype(np.float64))
+    hw0 = layout.facets_from_slots(ops, h0[sl].astype(np.float64))
+    lsrc = None
+    si, sj, sk = src["i"] - i0, src["j"] - j0, src["k"] - k0
+    if 0 < si < w and 0 < sj < w and 0 <= sk < w:
+        lsrc = dict(src, i=si, j=sj, k=sk)
+    ew1, hw1, _ = run(ops, ew0, hw0, dt, 1, source=lsrc, step0=step0)
+    eg = layout.edges_from_slots(ops, e1[sl].astype(np.float64))
+    hg = layout.facets_from_slots(ops, h1[sl].astype(np.float64))
+    # facets whose four boundary edges are all window-interior
+    Cfull = t.curl()[ops.if_]
+    kept = t.interior_edges()
+    ok = np.array([kept[Cfull.indices[Cfull.indptr[r]:Cfull.indptr[r + 1]]].all()
+                   for r in range(Cfull.shape[0])])
+    se = max(np.max(np.abs(ew1)), 1e-30)
+    sh = max(np.max(np.abs(hw1[ok])), 1e-30)
+    de = np.max(np.abs(eg - ew1)) / se
+    dh = np.max(np.abs(hg[ok] - hw1[ok])) / sh
+    return de, dh, lsrc is not None
+
+
+def test_c3_fullsize_sampled_windows_and_balance():
+    from paper_1705_08019_amd import FitGrid
+    spec = c3()
+    g = FitGrid(spec.nx, spec.ny, spec.nz, "f32")
+    g.set_materials(spec.eps_r, spec.mu_r, spec.sigma)
+    dt = spec.cfl_frac * g.cfl_dt()
+    s = spec.source
+    src = dict(axis=2, i=s["i"], j=s["j"], k=s["k"], i_max=s["i_max"],
+               sigma_t=s["sigma_t_steps"] * dt)
+    g.set_source(2, s["i"], s["j"], s["k"], s["i_max"], src["sigma_t"])
+    g.trace_config(spec.energy_every, 64)
+    g.step(15, dt)
+    e_a, h_a = (x.cpu().numpy() for x in g.get_fields())     # source still active here
+    g.step(1, dt)
+    e_b, h_b = (x.cpu().numpy() for x in g.get_fields())
+    g.step(134, dt)
+    tr, _ = g.trace_read()
+    assert tr.shape[0] == 3
+    for row in tr[1:]:
+        Qm, Qm1 = row[1] + row[4], row[3] + row[6]
+        assert abs((Qm1 - Qm) + 2 * dt * (row[8] + row[9])) <= 1e-5 * abs(Qm1)
+    e0, h0 = (x.cpu().numpy() for x in g.get_fields())
+    g.step(1, dt)
+    e1, h1 = (x.cpu().numpy() for x in g.get_fields())
+    rng = np.random.default_rng(2024)
+    origins = [(s["i"] - 3, s["j"] - 3, s["k"] - 3)]          # the source window
+    # inside the region the pulse has reached after 150 steps (|x - src| < ~50 cells)
+    origins += [(int(rng.integers(s["i"] - 50, s["i"] + 45)),
+                 int(rng.integers(s["j"] - 50, s["j"] + 45)),
+                 int(rng.integers(s["k"] - 50, s["k"] + 45))) for _ in range(24)]
+    # windows touching the walls and the tile / chunk seams
+    origins += [(0, 0, 0), (spec.nx - 6, spec.ny - 6, spec.nz - 6), (61, 2, 61), (125, 61, 317)]
+    for o in origins:
+        de, dh, _ = _window_check(spec, e0, h0, e1, h1, dt, src, o, 150)
+        assert de <= 1e-5 and dh <= 1e-5, (o, de, dh)
+    # the source window while the current is near its peak (global step 15)
+    de, dh, has_src = _window_check(spec, e_a, h_a, e_b, h_b, dt, src, origins[0], 15)
+    assert has_src and de <= 1e-5 and dh <= 1e-5, (de, dh)
+    g.close()

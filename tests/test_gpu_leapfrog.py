@@ -1,0 +1,219 @@
+"""GPU parity of the plain leapfrog path (through the C ABI) against the oracle.
+
+Tolerances: FP64 relative L2 <= 1e-12 on fields and energies; FP32 relative
+L2 <= 1e-4 on fields and <= 1e-6 on energies (relative to the energy scale).
+"""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from fit_workloads import c1, c2_small, facet_potential, dielectric_blocks, lossy_slab
+from oracle.leapfrog import run
+from oracle import adjoint as oadj
+from _glue import (oracle_ops, spec_dt, oracle_source, rel_l2, to_np, edges_from_slots,
+                   facets_from_slots, edges_to_slots, facets_to_slots)
+
+pytestmark = pytest.mark.gpu
+
+# (fields, conserved/balanced energies, individual inner products).  An
+# individual inner product <x, x> moves by at most 2 |x| |dx|, so it inherits
+# twice the field tolerance; the conserved energies W, Q, R do not depend on
+# the phase error of the fields and keep the energy tolerance.
+TOL = {"f64": (1e-12, 1e-12, 1e-12), "f32": (1e-4, 1e-6, 2e-4)}
+
+
+def _grid(spec, dtype=None, **kw):
+    from paper_1705_08019_amd import FitGrid
+    g = FitGrid(spec.nx, spec.ny, spec.nz, dtype or spec.dtype, spacing=spec.spacing, **kw)
+    g.set_materials(spec.eps_r, spec.mu_r, spec.sigma)
+    return g
+
+
+def _derived(row):
+    """W^m, Q^m, R^m, Q^(m+1) from one trace row (NaN where undefined)."""
+    Q_m = row[1] + row[4]
+    R_m = row[2] + row[5]
+    return np.array([0.5 * (Q_m + R_m), Q_m, R_m, row[3] + row[6]])
+
+
+def _compare_trace(tr_gpu, tr_ref, steps, tol):
+    _, etol, ctol = tol
+    scale = np.nanmax(np.abs(tr_ref[:, 1:8]))
+    for row in tr_gpu:
+        m = int(row[0])
+        assert m in steps
+        ref = tr_ref[m]
+        for c in range(1, 10):
+            if math.isnan(ref[c]):
+                assert math.isnan(row[c]), (m, c)
+            else:
+                assert abs(row[c] - ref[c]) <= ctol * scale, (m, c, row[c], ref[c])
+        dg, dr = _derived(row), _derived(ref)
+        for q in range(4):
+            if not math.isnan(dr[q]):
+                assert abs(dg[q] - dr[q]) <= etol * scale, (m, q, dg[q], dr[q])
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_c1_cavity_parity(dtype):
+    spec = c1()
+    ops = oracle_ops(spec)
+    g = _grid(spec, dtype)
+    psi = facet_potential(spec.nx, spec.ny, spec.nz, spec.init_potential_seed)
+    e0_gpu = g.apply_curl(torch.tensor(psi, device="cuda"), 1)
+    e0_ref = ops.Ct @ facets_from_slots(ops, psi)
+    ftol, etol, _ = TOL[dtype]
+    assert rel_l2(edges_from_slots(ops, to_np(e0_gpu)), e0_ref) <= (1e-15 if dtype == "f64" else 1e-7)
+    dt = spec_dt(spec)
+    assert abs(g.cfl_dt() - 1 / math.sqrt(3)) < 1e-15
+    g.set_fields(e0_gpu, None, 0)
+    g.trace_config(1, spec.nsteps)
+    g.step(spec.nsteps, dt)
+    e, h = g.get_fields()
+    tr, dropped = g.trace_read()
+    assert dropped == 0 and tr.shape[0] == spec.nsteps
+    eN, hN, tr_ref = run(ops, e0_ref, np.zeros(ops.n_h), dt, spec.nsteps)
+    assert rel_l2(edges_from_slots(ops, to_np(e)), eN) <= ftol
+    assert rel_l2(facets_from_slots(ops, to_np(h)), hN) <= ftol
+    # dead (PEC-wall) slots stay exactly zero
+    en, hn = to_np(e), to_np(h)
+    assert np.array_equal(edges_to_slots(ops, edges_from_slots(ops, en)), en)
+    assert np.array_equal(facets_to_slots(ops, facets_from_slots(ops, hn)), hn)
+    _compare_trace(tr, tr_ref, range(spec.nsteps), TOL[dtype])
+    # the paper's conserved energy, from the GPU's own trace
+    W = 0.5 * (tr[1:, 1] + tr[1:, 2] + tr[1:, 4] + tr[1:, 5])
+    assert np.max(np.abs(W - W[0])) / W[0] <= (1e-13 if dtype == "f64" else 1e-5)
+    ee, hh = g.energy()
+    assert abs(ee - tr_ref[-1, 3]) <= TOL[dtype][2] * tr_ref[-1, 3]
+
+
+@pytest.mark.parametrize("which", [0, 1])
+@pytest.mark.parametrize("dims", [(70, 37, 19), (1, 1, 1), (2, 3, 1), (65, 2, 9)])
+def test_curl_parity_ragged(which, dims):
+    from paper_1705_08019_amd import FitGrid
+    nx, ny, nz = dims
+    ops = oracle_ops(dims)
+    g = FitGrid(nx, ny, nz, "f64")
+    rng = np.random.default_rng(sum(dims) + which)
+    x = rng.standard_normal((3, nz, ny, nx))          # garbage in PEC-wall slots too
+    out = to_np(g.apply_curl(torch.tensor(x, device="cuda"), which))
+    if which == 0:
+        ref = ops.C @ edges_from_slots(ops, x)
+        got = facets_from_slots(ops, out)
+        assert np.count_nonzero(out) <= ops.n_h
+    else:
+        ref = ops.Ct @ facets_from_slots(ops, x)
+        got = edges_from_slots(ops, out)
+        assert np.count_nonzero(out) <= ops.n_e
+    np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("dtype,dims,nsteps", [("f32", (32, 32, 32), 1000),
+                                               ("f64", (67, 35, 21), 300)])
+def test_lossy_blocks_source_parity(dtype, dims, nsteps):
+    """Dielectric blocks, lossy z-slabs and the Gaussian source; ragged tiles
+    (x spans two 64-lane tiles, z spans several chunks with a short tail)."""
+    from paper_1705_08019_amd import FitGrid
+    nx, ny, nz = dims
+    spec = c2_small(32, nsteps, dtype)
+    if dims != (32, 32, 32):
+        spec.nx, spec.ny, spec.nz = nx, ny, nz
+        spec.eps_r = dielectric_blocks(nx, ny, nz, 12, 77)
+        spec.sigma = lossy_slab(nx, ny, nz, 2)
+        spec.source = dict(axis=2, i=nx // 2, j=ny // 2, k=nz // 2, i_max=1.0, sigma_t_steps=20.0)
+    ops = oracle_ops(spec)
+    dt = spec_dt(spec)
+    src = oracle_source(spec, dt)
+    g = _grid(spec, dtype)
+    g.set_source(2, src["i"], src["j"], src["k"], src["i_max"], src["sigma_t"])
+    g.trace_config(10, nsteps)
+    g.step(nsteps, dt)
+    e, h = g.get_fields()
+    tr, _ = g.trace_read()
+    eN, hN, tr_ref = run(ops, np.zeros(ops.n_e), np.zeros(ops.n_h), dt, nsteps, source=src)
+    ftol, etol, _ = TOL[dtype]
+    assert rel_l2(edges_from_slots(ops, to_np(e)), eN) <= ftol
+    assert rel_l2(facets_from_slots(ops, to_np(h)), hN) <= ftol
+    assert tr.shape[0] == nsteps // 10
+    _compare_trace(tr, tr_ref, range(0, nsteps, 10), TOL[dtype])
+    # discrete Poynting balance on the GPU's own trace: Q^(m+1) - Q^m = -2 dt (loss + src)
+    for row in tr[1:]:
+        Qm, Qm1 = row[1] + row[4], row[3] + row[6]
+        assert abs((Qm1 - Qm) + 2 * dt * (row[8] + row[9])) <= 50 * etol * max(abs(Qm1), 1e-30)
+
+
+def test_nonuniform_mu_spacing_and_probe_parity():
+    from paper_1705_08019_amd import FitGrid
+    nx, ny, nz = 20, 9, 13
+    sp = (0.8, 1.3, 1.1)
+    rng = np.random.default_rng(8)
+    eps = dielectric_blocks(nx, ny, nz, 6, 3)
+    mu = rng.uniform(1.0, 3.0, (nz, ny, nx))
+    sig = lossy_slab(nx, ny, nz, 2, 0.2)
+    ops = oracle_ops((nx, ny, nz), eps=eps, sigma=sig, mu=mu, spacing=sp)
+    g = FitGrid(nx, ny, nz, "f64", spacing=sp)
+    g.set_materials(eps, mu, sig)
+    from oracle.stability import cfl_dt
+    dt = 0.9 * cfl_dt(eps, mu, sp)
+    assert abs(g.cfl_dt() - cfl_dt(eps, mu, sp)) <= 1e-15 * cfl_dt(eps, mu, sp)
+    e0 = rng.standard_normal((3, nz, ny, nx))
+    h0 = rng.standard_normal((3, nz, ny, nx))
+    g.set_fields(e0, h0, 0)
+    box = ((4, 12), (2, 6), (3, 9))
+    g.set_probe([b[0] for b in box], [b[1] for b in box])
+    g.trace_config(7, 100)
+    n = 150
+    g.step(n, dt)
+    e, h = g.get_fields()
+    tr, _ = g.trace_read()
+    e0o, h0o = edges_from_slots(ops, e0), facets_from_slots(ops, h0)
+    eN, hN, tr_ref = run(ops, e0o, h0o, dt, n)
+    assert rel_l2(edges_from_slots(ops, to_np(e)), eN) <= 1e-12
+    assert rel_l2(facets_from_slots(ops, to_np(h)), hN) <= 1e-12
+    _compare_trace(tr, tr_ref, range(0, n, 7), TOL["f64"])
+    w = oadj.probe_weights(ops, box)
+    J_ref = oadj.objective(ops, e0o, h0o, dt, n, None, w)
+    assert abs(g.probe_value() - J_ref) <= 1e-12 * J_ref
+    ee, hh = g.energy()
+    assert abs(hh - hN @ (ops.M_mu * hN)) <= 1e-12 * hh
+
+
+def test_state_roundtrip_is_bitwise():
+    spec = c2_small(24, 0, "f32")
+    from paper_1705_08019_amd import FitGrid
+    dt = spec_dt(spec)
+    src = oracle_source(spec, dt)
+    g1, g2 = _grid(spec), _grid(spec)
+    for g in (g1, g2):
+        g.set_source(2, src["i"], src["j"], src["k"], src["i_max"], src["sigma_t"])
+    g1.step(80, dt)
+    g2.step(40, dt)
+    e, h = g2.get_fields()
+    g3 = _grid(spec)
+    g3.set_source(2, src["i"], src["j"], src["k"], src["i_max"], src["sigma_t"])
+    g3.set_fields(e, h, g2.step_index)
+    g3.step(40, dt)
+    a, b = g1.get_fields(), g3.get_fields()
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert g3.step_index == 80
+
+
+def test_error_paths():
+    from paper_1705_08019_amd import FitGrid, FitError
+    g = FitGrid(8, 8, 8, "f32")
+    with pytest.raises(FitError, match="UNSTABLE"):
+        g.step(1, 1.01 * g.cfl_dt())
+    with pytest.raises(FitError, match="INVALID"):
+        g.set_materials(-np.ones(512))
+    with pytest.raises(FitError, match="INVALID"):
+        g.set_materials(np.ones(512), sigma=-np.ones(512))
+    with pytest.raises(FitError, match="INVALID"):
+        g.set_source(2, 0, 4, 4, 1.0, 1.0)        # z-edge in the x = 0 wall
+    with pytest.raises(FitError, match="INVALID"):
+        g.step(1, -1.0)
+    ga = FitGrid(8, 8, 8, "f32", allow_unstable=True)
+    ga.step(2, 1.01 * ga.cfl_dt())               # allowed when forced
+    assert ga.step_index == 2
