@@ -40,28 +40,34 @@ B_HPASS = 4 * (3 + 3 + 3)       # 36
 B_STEP = B_EPASS + B_HPASS      # 80
 
 
-def kernel_source_hash() -> str:
+KERNEL_SOURCES = {"step": ("fit_step.hip", "fit_point.hpp"),
+                  "epass": ("fit_kernels.hip", "fit_point.hpp"),
+                  "hpass": ("fit_kernels.hip", "fit_point.hpp")}
+
+
+def kernel_source_hash(tag: str) -> str:
+    """Hash of the sources a kernel is compiled from (its counters go stale
+    when they change)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1705_08019_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
-        if f.endswith((".hip", ".cpp", ".hpp")):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+    for f in KERNEL_SOURCES[tag]:
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()[:16]
 
 
 def load_traffic(kernel: str):
-    """HBM bytes per cell for `kernel` from the committed counter summary, if
-    it was taken on the current kernel sources; else None."""
+    """HBM bytes per launch of `kernel` from the committed counter summary, if
+    the counters were taken on the current kernel sources; else None."""
     path = os.path.join(ROOT, "profiles", "traffic_c3.json")
     try:
         with open(path) as fh:
-            rec = json.load(fh)
+            rec = json.load(fh).get("kernels", {}).get(kernel)
     except (OSError, ValueError):
         return None
-    if rec.get("source_hash") != kernel_source_hash():
+    if not rec or rec.get("source_hash") != kernel_source_hash(kernel):
         return None
-    return rec.get("kernels", {}).get(kernel)
+    return rec
 
 
 def c3_inputs():
@@ -69,7 +75,7 @@ def c3_inputs():
     return c3()
 
 
-def run_plain(spec, steps: int, warmup: int, profile: bool = True):
+def run_plain(spec, steps: int, warmup: int, profile: bool = True, tile=None):
     import torch
     from paper_1705_08019_amd import FitGrid
     g = FitGrid(spec.nx, spec.ny, spec.nz, spec.dtype)
@@ -78,6 +84,11 @@ def run_plain(spec, steps: int, warmup: int, profile: bool = True):
     s = spec.source
     g.set_source(s["axis"], s["i"], s["j"], s["k"], s["i_max"], s["sigma_t_steps"] * dt)
     every = spec.energy_every
+    if tile is None:
+        tuned = g.autotune(dt, reps=10)
+    else:
+        g.set_tuning(tile[0], int(tile[1]), int(tile[2]))
+        tuned = (*g.get_tuning(), float("nan"))
     g.trace_config(every, steps // every + warmup // every + 4)
     g.step(warmup, dt)
     torch.cuda.synchronize()
@@ -97,7 +108,7 @@ def run_plain(spec, steps: int, warmup: int, profile: bool = True):
     tr, dropped = g.trace_read()
     e_tot = tr[:, 1] + tr[:, 5]
     assert np.all(np.isfinite(e_tot)), "energy trace is not finite"
-    out = dict(ms=ms, wall_s=wall, prof=prof, trace_rows=int(tr.shape[0]),
+    out = dict(ms=ms, wall_s=wall, prof=prof, trace_rows=int(tr.shape[0]), tuned=tuned,
                energy_last=float(e_tot[-1]), smvp=g.smvp_count(), grid=g)
     return out
 
@@ -105,14 +116,15 @@ def run_plain(spec, steps: int, warmup: int, profile: bool = True):
 def cpu_baseline():
     """The oracle (FP64 CSR leapfrog, single thread) on a bounded sample of the
     same recipe: 64 x 64 x 128 cells, 64 blocks, 8-cell lossy slabs, centre
-    source; 150 steps (about 15 s of CPU work)."""
+    source; the step count is sized from a 10-step probe to about 15 s of CPU
+    work."""
     from threadpoolctl import threadpool_limits
     from fit_workloads import dielectric_blocks, lossy_slab
     from oracle.topology import Topology
     from oracle.materials import Materials
     from oracle.leapfrog import Operators, run
     from oracle.stability import cfl_dt
-    nx, ny, nz, steps = 64, 64, 128, 150
+    nx, ny, nz = 64, 64, 128
     eps = dielectric_blocks(nx, ny, nz, 64, 3)
     sig = lossy_slab(nx, ny, nz, 8)
     t = Topology(nx, ny, nz)
@@ -120,6 +132,10 @@ def cpu_baseline():
     dt = 0.9 * cfl_dt(eps)
     src = dict(axis=2, i=nx // 2, j=ny // 2, k=nz // 2, i_max=1.0, sigma_t=20 * dt)
     with threadpool_limits(1):
+        t0 = time.perf_counter()
+        run(ops, np.zeros(ops.n_e), np.zeros(ops.n_h), dt, 10, source=src)
+        probe = time.perf_counter() - t0
+        steps = int(min(2000, max(20, 15.0 / max(probe / 10, 1e-6))))
         t0 = time.perf_counter()
         run(ops, np.zeros(ops.n_e), np.zeros(ops.n_h), dt, steps, source=src)
         sec = time.perf_counter() - t0
@@ -131,6 +147,131 @@ def cpu_baseline():
                       f"{os.cpu_count()} logical CPUs visible)"}
 
 
+def measure_copy(nbytes: int = 1 << 30, reps: int = 5) -> float:
+    """Bandwidth of a plain 1 GiB device copy (read + write bytes / time),
+    the practical HBM ceiling on this machine; context for the roofline."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    best = 1e30
+    for _ in range(reps):
+        ev[0].record()
+        dst.copy_(src)
+        ev[1].record()
+        torch.cuda.synchronize()
+        best = min(best, ev[0].elapsed_time(ev[1]))
+    del src, dst
+    return round(2 * nbytes / (best / 1e3) / 1e9, 1)
+
+
+def calib_copy(nbytes: int = 1 << 30, reps: int = 3):
+    """Plain device copy of known size (dst.copy_(src), FP32) for scaling the
+    HBM byte counters: each launch reads and writes exactly nbytes."""
+    import torch
+    n = nbytes // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ms = []
+    for _ in range(reps):
+        ev[0].record()
+        dst.copy_(src)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms.append(ev[0].elapsed_time(ev[1]))
+    best = min(ms)
+    print(json.dumps({"calib_copy_bytes_each_way": nbytes, "reps": reps,
+                      "best_ms": round(best, 4),
+                      "copy_GBs_read_plus_write": round(2 * nbytes / (best / 1e3) / 1e9, 1)}),
+          flush=True)
+
+
+def _csv_rows(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        with open(f, newline="") as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _counter_by_launch(d, counter):
+    """{(kernel, grid, wg): [values KiB per dispatch]} from a --pmc run."""
+    out = {}
+    for r in _csv_rows(d, "_counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        key = (r["Kernel_Name"], int(r["Grid_Size"]), int(r["Workgroup_Size"]))
+        out.setdefault(key, []).append(float(r["Counter_Value"]))
+    return out
+
+
+def summarize(kt, fetch, write, cfetch, cwrite, out_md, cells, cmd_note):
+    """Turn rocprofv3 outputs into profiles/<name>.md and profiles/traffic_c3.json."""
+    stats = _csv_rows(kt, "_kernel_stats.csv")
+    calib = 1 << 30
+    cf = _counter_by_launch(cfetch, "FETCH_SIZE")
+    cw = _counter_by_launch(cwrite, "WRITE_SIZE")
+    f_copy = [v for k, vals in cf.items() if "copyBuffer" in k[0] or "copy" in k[0].lower()
+              for v in vals]
+    w_copy = [v for k, vals in cw.items() if "copyBuffer" in k[0] for v in vals]
+    fscale = calib / 1024.0 / (sum(f_copy) / len(f_copy))
+    wscale = calib / 1024.0 / (sum(w_copy) / len(w_copy))
+    fe = _counter_by_launch(fetch, "FETCH_SIZE")
+    wr = _counter_by_launch(write, "WRITE_SIZE")
+    lines = ["# rocprofv3 summary: " + os.path.basename(out_md).replace(".md", ""), "",
+             "Commands (run from the repository root on the MI355X box):", "", "```"]
+    lines += cmd_note + ["```", "", "## Kernel durations (--kernel-trace --stats)", "",
+                         "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.2f} | "
+                     f"{float(r['MinNs'])/1e3:.2f} | {float(r['MaxNs'])/1e3:.2f} |")
+    lines += ["", "## HBM bytes (--pmc FETCH_SIZE, --pmc WRITE_SIZE)", "",
+              f"Calibration: a plain 1 GiB device copy reads FETCH_SIZE = "
+              f"{sum(f_copy)/len(f_copy):.0f} KiB and writes WRITE_SIZE = "
+              f"{sum(w_copy)/len(w_copy):.0f} KiB per launch, so the scale factors are "
+              f"fetch x{fscale:.3f}, write x{wscale:.3f}.", "",
+              "| kernel | grid | wg | launches | FETCH KiB | WRITE KiB | scaled GB/launch | "
+              "B/cell |", "|---|---|---|---|---|---|---|---|"]
+    kernels = {}
+    for key in sorted(set(fe) | set(wr)):
+        f = fe.get(key, [0.0])
+        w = wr.get(key, [0.0])
+        fk, wk = sum(f) / len(f), sum(w) / len(w)
+        gb = (fk * fscale + wk * wscale) * 1024 / 1e9
+        bpc = gb * 1e9 / cells
+        name = key[0]
+        lines.append(f"| `{name[:70]}` | {key[1]} | {key[2]} | {len(f)} | {fk:.0f} | {wk:.0f} | "
+                     f"{gb:.4f} | {bpc:.2f} |")
+        tag = ("step" if "k_step<float, true, false, false>" in name
+               else "epass" if "k_epass<float, true, false, false>" in name
+               else "hpass" if "k_hpass<float, true, false>" in name else None)
+        if tag and (tag not in kernels or len(f) > kernels[tag]["launches"]):
+            kernels[tag] = {"source_hash": kernel_source_hash(tag),
+                            "bytes_per_launch": round(gb * 1e9), "bytes_per_cell": round(bpc, 2),
+                            "fetch_KiB": round(fk, 1), "write_KiB": round(wk, 1),
+                            "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
+                            "launches": len(f), "grid": key[1], "wg": key[2]}
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    tpath = os.path.join(os.path.dirname(out_md), "traffic_c3.json")
+    rec = {"cells": cells, "kernels": {}, "summaries": []}
+    try:
+        with open(tpath) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        pass
+    rec["kernels"].update(kernels)
+    if os.path.basename(out_md) not in rec["summaries"]:
+        rec["summaries"].append(os.path.basename(out_md))
+    with open(tpath, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,7 +280,18 @@ def main(argv=None):
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip batched/adjoint/Gram forms")
     ap.add_argument("--no-profile", action="store_true", help="no per-launch timing events")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="only run a 1 GiB device copy (counter calibration) and exit")
+    ap.add_argument("--tile", default=None,
+                    help="path,ty,kc (e.g. fused,16,128): skip the autotuner, use this tile")
+    ap.add_argument("--summarize", nargs=5, metavar="DIR", default=None,
+                    help="kt fetch write copyfetch copywrite rocprofv3 output dirs -> profiles/")
+    ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "fused_step_c3.md"))
+    ap.add_argument("--summary-cmd", action="append", default=[])
     args = ap.parse_args(argv)
+    if args.summarize:
+        summarize(*args.summarize, args.summary_out, 256 * 256 * 512, args.summary_cmd)
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "layout (z-slab halo exchange) is a design note, not a measured path.",
@@ -150,27 +302,40 @@ def main(argv=None):
         print("bench.py needs a GPU", file=sys.stderr)
         return 2
     torch.cuda.set_device(0)
+    if args.calib_copy:
+        calib_copy()
+        return 0
     spec = c3_inputs()
     cells = spec.cells
-    r = run_plain(spec, args.steps, args.warmup, profile=not args.no_profile)
+    tile = args.tile.split(",") if args.tile else None
+    r = run_plain(spec, args.steps, args.warmup, profile=not args.no_profile, tile=tile)
     ms_step = r["ms"] / args.steps
     value = cells * args.steps / (r["ms"] / 1e3) / 1e9
     roof = None
+    path, ty, kc = r["grid"].get_tuning()
     if r["prof"] is not None:
-        pe_ms, pe_n = r["prof"]["epass"]
-        ph_ms, ph_n = r["prof"]["hpass"]
-        e_avg = pe_ms / max(pe_n, 1)
-        h_avg = ph_ms / max(ph_n, 1)
-        ach = B_EPASS * cells / (e_avg / 1e3) / 1e9
-        tr = load_traffic("epass")
-        roof = {"bound": "hbm", "kernel": "k_epass (e-update: dual curl + M_eps/M_sigma + source)",
-                "achieved": round(ach, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": round(ach / PEAK_HBM_GBS, 4),
-                "traffic": None if tr is None else tr,
-                "alg_bytes_per_cell": B_EPASS, "avg_launch_ms": round(e_avg, 5),
-                "launches_timed": pe_n,
-                "hpass": {"alg_bytes_per_cell": B_HPASS, "avg_launch_ms": round(h_avg, 5),
-                          "achieved": round(B_HPASS * cells / (h_avg / 1e3) / 1e9, 1)},
+        st_ms, st_n = r["prof"]["step"]
+        if st_n > 0:   # fused single-pass step kernel: one launch = one full step
+            avg = st_ms / st_n
+            kname, kb, tkey = ("k_step (fused leapfrog step: dual curl + M_eps/M_sigma + source, "
+                               "primal curl + M_mu, energies)"), B_STEP, "step"
+        else:          # split half-step kernels: the e-update is the larger one
+            pe_ms, pe_n = r["prof"]["epass"]
+            avg = pe_ms / max(pe_n, 1)
+            st_n = pe_n
+            kname, kb, tkey = "k_epass (e-update: dual curl + M_eps/M_sigma + source)", B_EPASS, "epass"
+        ach = kb * cells / (avg / 1e3) / 1e9
+        roof = {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1),
+                "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                "traffic": (None if load_traffic(tkey) is None
+                            else load_traffic(tkey)["bytes_per_launch"]),
+                "traffic_unit": "bytes per launch (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, "
+                                "scaled by a 1 GiB copy; profiles/traffic_c3.json)",
+                "alg_bytes_per_launch": kb * cells, "alg_bytes_per_cell": kb,
+                "avg_launch_ms": round(avg, 5), "launches_timed": st_n,
+                "path": path, "tile": [64, ty, kc],
+                "autotune_ms_per_step": (None if r["tuned"][3] != r["tuned"][3]
+                                         else round(r["tuned"][3], 5)),
                 "step_alg_GBs": round(B_STEP * cells / (ms_step / 1e3) / 1e9, 1)}
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s",
@@ -185,6 +350,7 @@ def main(argv=None):
         "roofline": roof,
     }
     r["grid"].close()
+    line["config"]["copy_GBs_read_plus_write"] = measure_copy()
     if not args.no_forms:
         line["forms"] = {}
     if not args.no_cpu:

@@ -199,6 +199,29 @@ enum { FIT_PROF_EPASS = 0, FIT_PROF_HPASS = 1, FIT_PROF_REDUCE = 2, FIT_PROF_STE
 int fit_profile_begin(fit_grid* g, int64_t max_launches);
 int fit_profile_end(fit_grid* g, double ms[FIT_PROF_N], int64_t count[FIT_PROF_N]);
 
+/* Kernel path and tile shape of fit_step.  path: FIT_PATH_AUTO (fused
+ * single-pass kernel when mu is uniform, else the two half-step kernels),
+ * FIT_PATH_SPLIT (e-update and h-update kernels, in place) or FIT_PATH_FUSED
+ * (one kernel per step, state ping-pongs between two buffer sets; needs a
+ * uniform mu).  ty: rows of the 64-wide column tile (power of two; split
+ * 1..8, fused 2..16); kc: z-planes per workgroup; ty = kc = 0 selects the
+ * default for the path.  Every path computes the same values (bitwise:
+ * the per-node arithmetic is shared).  Errors: FIT_E_INVALID. */
+enum { FIT_PATH_AUTO = 0, FIT_PATH_SPLIT = 1, FIT_PATH_FUSED = 2 };
+int fit_set_tuning(fit_grid* g, int path, int ty, int kc);
+
+/* The path fit_step will take and its tile shape. */
+int fit_get_tuning(const fit_grid* g, int* path, int* ty, int* kc);
+
+/* Autotuner: time candidate kernel paths and tile shapes (tile heights,
+ * z-chunks sized to one or two rounds of resident workgroups, from the
+ * runtime's occupancy query) with `reps` timed launches each, on the current
+ * state and dt, and keep the fastest (as fit_set_tuning).  The state, step
+ * counter, trace and probe are left unchanged (candidates run out of place
+ * into the second buffer set).  Any output pointer may be NULL; *ms_best is
+ * the per-step time of the winner.  Synchronises. */
+int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* ty, int* kc, float* ms_best);
+
 /* Number of curl applications (sparse matrix-vector products of the paper's
  * cost model, eq. cost_LF: 2 per leapfrog step) performed by this handle. */
 int fit_smvp_count(const fit_grid* g, int64_t* count);

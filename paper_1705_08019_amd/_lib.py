@@ -59,6 +59,10 @@ SIGNATURES = {
     "fit_profile_begin": [_vp, _i64],
     "fit_profile_end": [_vp, _dp, _i64p],
     "fit_smvp_count": [_vp, _i64p],
+    "fit_set_tuning": [_vp, _i, _i, _i],
+    "fit_get_tuning": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)],
+    "fit_autotune": [_vp, _d, _i, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                     C.POINTER(C.c_float)],
 }
 PROF_KINDS = ("epass", "hpass", "reduce", "step", "adjoint", "other")
 _CHAR = {"fit_version": [], "fit_last_error": []}

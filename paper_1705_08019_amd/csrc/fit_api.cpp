@@ -71,6 +71,41 @@ void default_tiling(const Dims& d, int* ty, int* kc) {
   *kc = std::min(k, d.nz);
 }
 
+// Fused-kernel tiling: pick the z-chunk so that one round of resident
+// workgroups (LDS- and wave-limited) covers the grid once.
+void default_step_tiling(const Dims& d, size_t esz, bool lossy, int* ty, int* kc) {
+  // tall tiles amortise the halo row; 16 rows (1024 threads) for FP32 when
+  // the grid is tall enough, 4 for FP64 (LDS)
+  const int t = esz == 8 ? 4 : (d.ny >= 64 ? 16 : 8);
+  int per_cu = step_blocks_per_cu(t, esz, lossy);
+  if (per_cu <= 0) {   // no device information: estimate from LDS and waves
+    const size_t lds = step_lds_bytes(t, esz, lossy) + 2048;
+    per_cu = (int)std::min<size_t>((160 * 1024) / lds, 2048 / (64 * t));
+  }
+  per_cu = std::max(per_cu, 1);
+  int cus = 256;
+  int dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  (void)hipGetLastError();
+  const int64_t resident = (int64_t)cus * per_cu;
+  const int64_t tiles = (int64_t)((d.nx + 63) / 64) * ((d.ny + t - 1) / t);
+  // one round of resident workgroups covers the grid
+  const int64_t nkc = std::max<int64_t>(1, resident / tiles);
+  int k = (int)((d.nz + nkc - 1) / nkc);
+  k = std::max(k, std::min(8, d.nz));
+  *ty = t;
+  *kc = std::min(k, d.nz);
+}
+
+bool use_fused(const fit_grid* g) {
+  if (g->path == 1) return false;
+  return g->mu_uniform;   // the fused kernel takes a uniform mu
+}
+
 // Host-side mirror of the probe membership of a direction-a edge (used only
 // for argument validation).
 static bool valid_box(const int32_t lo[3], const int32_t hi[3]) {
@@ -163,7 +198,7 @@ int step_once(fit_grid* g, double dt, const T* ein, T* eout, const T* hin, T* ho
   }
   if (e != hipSuccess) return hip_fail(e, "e-update launch");
   if (have_row || probe) {
-    const int cols[kPartTerms] = {1, 2, 3, 8, 9, -1, -1, -1};
+    const int cols[kPartTerms] = {1, 2, 3, 8, 9, -1, -1, -1, -1, -1};
     const bool prev_ok = g->pend_m == m;
     ProfScope ps(g, FIT_PROF_REDUCE);
     e = launch_reduce(g->part, nb, row, cols, probe ? PE_PROBE : -1, dt,
@@ -181,14 +216,14 @@ int step_once(fit_grid* g, double dt, const T* ein, T* eout, const T* hin, T* ho
   }
   if (e != hipSuccess) return hip_fail(e, "h-update launch");
   if (have_row) {
-    const int cols[kPartTerms] = {5, 6, 7, -1, -1, -1, -1, -1};
+    const int cols[kPartTerms] = {5, 6, 7, -1, -1, -1, -1, -1, -1, -1};
     ProfScope ps(g, FIT_PROF_REDUCE);
     e = launch_reduce(g->part, nb, row, cols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
   }
   if (tr_next) {
     // <h^(m+1/2), h^(m+3/2)> is the h cross term of row m+1.
-    const int cols[kPartTerms] = {-1, 0, -1, -1, -1, -1, -1, -1};
+    const int cols[kPartTerms] = {-1, 0, -1, -1, -1, -1, -1, -1, -1, -1};
     ProfScope ps(g, FIT_PROF_REDUCE);
     e = launch_reduce(g->part, nb, g->pend, cols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
@@ -202,6 +237,91 @@ int step_once(fit_grid* g, double dt, const T* ein, T* eout, const T* hin, T* ho
 
 template int step_once<float>(fit_grid*, double, const float*, float*, const float*, float*);
 template int step_once<double>(fit_grid*, double, const double*, double*, const double*, double*);
+
+// One fused leapfrog step m -> m+1: state read from (e, h), written to
+// (e_alt, h_alt), then the two sets swap roles.
+template <typename T>
+int step_fused(fit_grid* g, double dt) {
+  const int64_t m = g->m;
+  const bool tr_this = g->trace_every > 0 && m % g->trace_every == 0;
+  const bool tr_next = g->trace_every > 0 && (m + 1) % g->trace_every == 0;
+  const bool have_row = tr_this && g->trace_rows < g->trace_cap;
+  if (tr_this && !have_row) g->trace_dropped++;
+  const bool probe = g->probe.on != 0;
+  const bool energy = have_row || tr_next;
+  const Dims& d = g->d;
+  if (!g->e_alt) {
+    int rc = dev_alloc(&g->e_alt, 3 * d.n * g->esz, "e (second buffer)");
+    if (!rc) rc = dev_alloc(&g->h_alt, 3 * d.n * g->esz, "h (second buffer)");
+    if (rc) {
+      dev_free(g->e_alt);
+      dev_free(g->h_alt);
+      return rc;
+    }
+  }
+  SArgs<T> a;
+  const T* e0 = static_cast<const T*>(g->e);
+  const T* h0 = static_cast<const T*>(g->h);
+  T* e1 = static_cast<T*>(g->e_alt);
+  T* h1 = static_cast<T*>(g->h_alt);
+  for (int c = 0; c < 3; ++c) {
+    a.e0[c] = e0 + c * d.n;
+    a.h0[c] = h0 + c * d.n;
+    a.e1[c] = e1 + c * d.n;
+    a.h1[c] = h1 + c * d.n;
+    a.kb[c] = (T)(4.0 * dt / g->gedge[c]);
+    a.kd[c] = (T)(dt * g->gf2[c]);
+    a.ge[c] = g->gedge[c] / 4.0;
+    a.gf2[c] = g->gf2[c];
+  }
+  a.eps = static_cast<const T*>(g->eps);
+  a.sig = static_cast<const T*>(g->sig);
+  a.d = d;
+  a.t = make_tiling(d, g->sty, g->skc);
+  a.hs = (T)(0.5 * dt);
+  a.imu2 = (T)g->imu_u + (T)g->imu_u;
+  a.src_comp = g->src_axis;
+  a.src_idx = g->src_axis >= 0 ? g->src_idx : -1;
+  const double val = g->src_axis >= 0 ? source_value(g, dt, m) : 0.0;
+  a.src_val = (T)val;
+  a.src_val_d = (double)(T)val;
+  a.probe = g->probe;
+  const int64_t nb = a.t.blocks();
+  if ((energy || probe) && ensure_part(g, nb)) return FIT_E_OOM;
+  a.part = g->part;
+  hipError_t e;
+  {
+    ProfScope ps(g, FIT_PROF_STEP);
+    e = launch_step<T>(a, g->lossy, energy, probe, g->s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "fused step launch");
+  if (have_row || probe) {
+    double* row = have_row ? g->trace + g->trace_rows * FIT_TRACE_COLS : nullptr;
+    const int cols[kPartTerms] = {1, 2, 3, 8, 9, -1, 5, 6, 7, -1};
+    const bool prev_ok = g->pend_m == m;
+    ProfScope ps(g, FIT_PROF_REDUCE);
+    e = launch_reduce(g->part, nb, row, cols, probe ? PE_PROBE : -1, dt,
+                      probe ? g->jacc : nullptr, have_row && !prev_ok ? 4 : -1,
+                      have_row ? m : -1, have_row && prev_ok ? g->pend : nullptr, 4, g->s);
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  }
+  if (tr_next) {
+    const int cols[kPartTerms] = {-1, -1, -1, -1, -1, -1, -1, 0, -1, -1};
+    ProfScope ps(g, FIT_PROF_REDUCE);
+    e = launch_reduce(g->part, nb, g->pend, cols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    g->pend_m = m + 1;
+  }
+  std::swap(g->e, g->e_alt);
+  std::swap(g->h, g->h_alt);
+  if (have_row) g->trace_rows++;
+  g->m = m + 1;
+  g->smvp += 2;
+  return FIT_OK;
+}
+
+template int step_fused<float>(fit_grid*, double);
+template int step_fused<double>(fit_grid*, double);
 
 int check_dt(const fit_grid* g, double dt) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FIT_E_INVALID, "dt must be positive and finite");
@@ -222,6 +342,71 @@ int upload_cells(fit_grid* g, void** dst, const std::vector<double>& v, const ch
   if (e == hipSuccess) e = hipStreamSynchronize(g->s);
   if (e != hipSuccess) return hip_fail(e, "material upload");
   return FIT_OK;
+}
+
+// Time `reps` launches of one candidate on fixed inputs: the fused kernel
+// reads (e, h) and writes the second buffer set; the split kernels run out of
+// place into the second set.  The handle's state is left untouched.
+template <typename T>
+int time_candidate(fit_grid* g, double dt, int path, int ty, int kc, int reps, float* ms) {
+  const Dims& d = g->d;
+  const int save_path = g->path, save_ty = g->ty, save_kc = g->kc, save_sty = g->sty,
+            save_skc = g->skc;
+  const int64_t save_m = g->m, save_smvp = g->smvp, save_tr = g->trace_every;
+  const int64_t save_pend = g->pend_m;
+  const fit::Probe save_probe = g->probe;
+  g->trace_every = 0;
+  g->probe.on = 0;
+  if (path == 2) {
+    g->sty = ty;
+    g->skc = kc;
+  } else {
+    g->ty = ty;
+    g->kc = kc;
+  }
+  hipEvent_t ev[2];
+  (void)hipEventCreate(&ev[0]);
+  (void)hipEventCreate(&ev[1]);
+  int rc = FIT_OK;
+  auto one = [&]() -> int {
+    if (path == 2) {
+      // run the fused step, then swap back so the inputs stay the same
+      int r = step_fused<T>(g, dt);
+      std::swap(g->e, g->e_alt);
+      std::swap(g->h, g->h_alt);
+      return r;
+    }
+    if (!g->e_alt) {
+      int r = dev_alloc(&g->e_alt, 3 * d.n * g->esz, "e (second buffer)");
+      if (!r) r = dev_alloc(&g->h_alt, 3 * d.n * g->esz, "h (second buffer)");
+      if (r) return r;
+    }
+    return step_once<T>(g, dt, static_cast<const T*>(g->e), static_cast<T*>(g->e_alt),
+                        static_cast<const T*>(g->h), static_cast<T*>(g->h_alt));
+  };
+  for (int w = 0; w < 2 && !rc; ++w) rc = one();
+  if (!rc) {
+    (void)hipEventRecord(ev[0], g->s);
+    for (int r = 0; r < reps && !rc; ++r) rc = one();
+    (void)hipEventRecord(ev[1], g->s);
+    hipError_t e = hipEventSynchronize(ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, ev[0], ev[1]);
+    if (e != hipSuccess && !rc) rc = hip_fail(e, "autotune timing");
+    *ms /= (float)std::max(reps, 1);
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  g->path = save_path;
+  g->ty = save_ty;
+  g->kc = save_kc;
+  g->sty = save_sty;
+  g->skc = save_skc;
+  g->m = save_m;
+  g->smvp = save_smvp;
+  g->trace_every = save_tr;
+  g->pend_m = save_pend;
+  g->probe = save_probe;
+  return rc;
 }
 
 }  // namespace fit
@@ -272,6 +457,7 @@ int fit_grid_create(const fit_grid_desc* desc, void* stream, fit_grid** out) {
     g->gf2[a] = s3[a] / (s3[b] * s3[c]) / 2.0;    // M_mu^{-1} = gf2 (imu_1 + imu_2)
   }
   default_tiling(g->d, &g->ty, &g->kc);
+  default_step_tiling(g->d, g->esz, false, &g->sty, &g->skc);
   int rc = dev_alloc(&g->e, 3 * n * g->esz, "e");
   if (!rc) rc = dev_alloc(&g->h, 3 * n * g->esz, "h");
   if (!rc) rc = dev_alloc(&g->eps, n * g->esz, "eps");
@@ -307,6 +493,8 @@ int fit_grid_destroy(fit_grid* g) {
   grid_release_extras(g);
   dev_free(g->e);
   dev_free(g->h);
+  dev_free(g->e_alt);
+  dev_free(g->h_alt);
   dev_free(g->eps);
   dev_free(g->sig);
   dev_free(g->imu);
@@ -360,6 +548,7 @@ int fit_set_materials(fit_grid* g, const double* eps_r, const double* mu_r, cons
   }
   g->lossy = lossy;
   g->mu_uniform = mu_uni;
+  if (!g->tile_explicit) default_step_tiling(g->d, g->esz, lossy, &g->sty, &g->skc);
   g->imu_u = imu[0];
   g->cfl = cfl;
   g->eps_host = eps;
@@ -467,11 +656,16 @@ int fit_step(fit_grid* g, int64_t nsteps, double dt) {
   if (nsteps < 0) return fail(FIT_E_INVALID, "nsteps must be >= 0");
   int rc = check_dt(g, dt);
   if (rc) return rc;
+  const bool fused = use_fused(g);
   for (int64_t s = 0; s < nsteps; ++s) {
-    rc = g->f64 ? step_once<double>(g, dt, static_cast<const double*>(g->e), static_cast<double*>(g->e),
-                                    static_cast<const double*>(g->h), static_cast<double*>(g->h))
-                : step_once<float>(g, dt, static_cast<const float*>(g->e), static_cast<float*>(g->e),
-                                   static_cast<const float*>(g->h), static_cast<float*>(g->h));
+    if (fused) {
+      rc = g->f64 ? step_fused<double>(g, dt) : step_fused<float>(g, dt);
+    } else {
+      rc = g->f64 ? step_once<double>(g, dt, static_cast<const double*>(g->e), static_cast<double*>(g->e),
+                                      static_cast<const double*>(g->h), static_cast<double*>(g->h))
+                  : step_once<float>(g, dt, static_cast<const float*>(g->e), static_cast<float*>(g->e),
+                                     static_cast<const float*>(g->h), static_cast<float*>(g->h));
+    }
     if (rc) return rc;
   }
   return FIT_OK;
@@ -501,7 +695,7 @@ int fit_energy(fit_grid* g, double out[2]) {
                              (float)g->imu_u, g->d, ge, gf2, g->part, &nblk, g->s);
   if (e != hipSuccess) return hip_fail(e, "energy launch");
   // reduce into the tail of the partial buffer's first row is unsafe; use the pending slot pair
-  const int cols[kPartTerms] = {0, 1, -1, -1, -1, -1, -1, -1};
+  const int cols[kPartTerms] = {0, 1, -1, -1, -1, -1, -1, -1, -1, -1};
   e = launch_reduce(g->part, nblk, g->jacc + 2, cols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
   if (e != hipSuccess) return hip_fail(e, "reduce launch");
   e = hipMemcpyAsync(out, g->jacc + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, g->s);
@@ -619,6 +813,104 @@ int fit_profile_end(fit_grid* g, double ms[FIT_PROF_N], int64_t count[FIT_PROF_N
     if (ms) ms[k] = acc[k];
     if (count) count[k] = cnt[k];
   }
+  return FIT_OK;
+}
+
+int fit_set_tuning(fit_grid* g, int path, int ty, int kc) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  if (path < 0 || path > 2) return fail(FIT_E_INVALID, "path must be 0 (auto), 1 (split), 2 (fused)");
+  if (path == 2 && !g->mu_uniform) return fail(FIT_E_INVALID, "the fused step needs a uniform mu");
+  const bool fused = path == 2 || (path == 0 && g->mu_uniform);
+  if (ty != 0 || kc != 0) {
+    const int tmax = fused ? 16 : 8;
+    const int tmin = fused ? 2 : 1;
+    if (ty < tmin || ty > tmax || (ty & (ty - 1)) != 0)
+      return fail(FIT_E_INVALID, "ty must be a power of two in [" + std::to_string(tmin) + ", " +
+                                     std::to_string(tmax) + "]");
+    if (kc < 1) return fail(FIT_E_INVALID, "kc must be >= 1");
+    if (fused && step_lds_bytes(ty, g->esz, g->lossy) > 160 * 1024)
+      return fail(FIT_E_INVALID, "tile needs more LDS than a CU has");
+  }
+  g->path = path;
+  g->tile_explicit = ty != 0 || kc != 0;
+  if (ty != 0 || kc != 0) {
+    if (fused) {
+      g->sty = ty;
+      g->skc = std::min(kc, g->d.nz);
+    } else {
+      g->ty = ty;
+      g->kc = std::min(kc, g->d.nz);
+    }
+  } else {
+    default_tiling(g->d, &g->ty, &g->kc);
+    default_step_tiling(g->d, g->esz, g->lossy, &g->sty, &g->skc);
+  }
+  return FIT_OK;
+}
+
+int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* ty, int* kc, float* ms_best) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  if (reps < 1 || reps > 1000) return fail(FIT_E_INVALID, "reps must be in [1, 1000]");
+  int rc = check_dt(g, dt);
+  if (rc) return rc;
+  struct Cand { int path, ty, kc; };
+  std::vector<Cand> cands;
+  int cus = 256, dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  if (g->mu_uniform) {
+    const int tys32[3] = {4, 8, 16}, tys64[3] = {2, 4, 8};
+    for (int a = 0; a < 3; ++a) {
+      const int t = g->f64 ? tys64[a] : tys32[a];
+      if (step_lds_bytes(t, g->esz, g->lossy) > 160 * 1024) continue;
+      const int per_cu = std::max(1, step_blocks_per_cu(t, g->esz, g->lossy));
+      const int64_t tiles = (int64_t)((g->d.nx + 63) / 64) * ((g->d.ny + t - 1) / t);
+      for (int mult = 1; mult <= 2; ++mult) {
+        const int64_t nkc = std::max<int64_t>(1, mult * (int64_t)cus * per_cu / tiles);
+        const int k = std::min<int>(g->d.nz, std::max<int>(std::min(8, g->d.nz),
+                                                         (int)((g->d.nz + nkc - 1) / nkc)));
+        bool dup = false;
+        for (const Cand& c : cands) dup |= (c.path == 2 && c.ty == t && c.kc == k);
+        if (!dup) cands.push_back({2, t, k});
+      }
+    }
+  }
+  {
+    int t, k;
+    default_tiling(g->d, &t, &k);
+    cands.push_back({1, t, k});
+    cands.push_back({1, t, std::min(g->d.nz, 4 * k)});
+  }
+  float best = 1e30f;
+  Cand bc = cands[0];
+  for (const Cand& c : cands) {
+    float ms = 0.f;
+    rc = g->f64 ? time_candidate<double>(g, dt, c.path, c.ty, c.kc, reps, &ms)
+                : time_candidate<float>(g, dt, c.path, c.ty, c.kc, reps, &ms);
+    if (rc) return rc;
+    if (ms < best) {
+      best = ms;
+      bc = c;
+    }
+  }
+  rc = fit_set_tuning(g, bc.path, bc.ty, bc.kc);
+  if (rc) return rc;
+  if (path) *path = bc.path;
+  if (ty) *ty = bc.ty;
+  if (kc) *kc = bc.kc;
+  if (ms_best) *ms_best = best;
+  return FIT_OK;
+}
+
+int fit_get_tuning(const fit_grid* g, int* path, int* ty, int* kc) {
+  if (!g || !path || !ty || !kc) return fail(FIT_E_INVALID, "null argument");
+  const bool fused = use_fused(g);
+  *path = fused ? 2 : 1;
+  *ty = fused ? g->sty : g->ty;
+  *kc = fused ? g->skc : g->kc;
   return FIT_OK;
 }
 

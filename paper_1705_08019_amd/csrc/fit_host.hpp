@@ -41,7 +41,12 @@ struct fit_grid {
   int64_t pend_m = -1;
   double* jacc = nullptr;        // [0..1] probe (sum, comp), [2..3] energy scratch
   fit::Probe probe{};
-  int ty = 4, kc = 64;
+  int ty = 4, kc = 64;          // split half-step kernels
+  int sty = 8, skc = 64;        // fused step kernel
+  int path = 0;                 // FIT_PATH_*: 0 auto, 1 split, 2 fused
+  bool tile_explicit = false;   // tile shape set by fit_set_tuning
+  void* e_alt = nullptr;        // second buffer set of the fused (ping-pong) step
+  void* h_alt = nullptr;
   fit_adjoint_ws* adj = nullptr;
   // kernel timing (fit_profile_begin/end)
   std::vector<hipEvent_t> prof_ev;   // 2 per timed launch
@@ -64,6 +69,10 @@ template <typename T>
 int step_once(fit_grid* g, double dt, const T* ein, T* eout, const T* hin, T* hout);
 // Frees adjoint/other optional workspaces (defined with those features).
 void grid_release_extras(fit_grid* g);
+bool use_fused(const fit_grid* g);
+void default_step_tiling(const Dims& d, size_t esz, bool lossy, int* ty, int* kc);
+template <typename T>
+int step_fused(fit_grid* g, double dt);
 
 // Bracket one kernel launch with timing events when profiling is on.
 struct ProfScope {

@@ -32,11 +32,13 @@ struct Probe {
 };
 
 // Number of FP64 partial terms written per block by the energy variants.
-constexpr int kPartTerms = 8;
+constexpr int kPartTerms = 10;
 // E-pass partial term slots
 enum { PE_EE_MM = 0, PE_EE_MM1 = 1, PE_EE_M1M1 = 2, PE_LOSS = 3, PE_SRC = 4, PE_PROBE = 5 };
 // H-pass partial term slots
 enum { PH_HH_CC = 0, PH_HH_CN = 1, PH_HH_NN = 2 };
+// Fused-step partial term slots: the E slots above, then the H terms.
+enum { PS_HH_CC = 6, PS_HH_CN = 7, PS_HH_NN = 8 };
 
 template <typename T>
 struct EArgs {
@@ -71,6 +73,40 @@ struct HArgs {
   double gf2[3];     // d_a / (d_b d_c) / 2: M_mu^{-1} = gf2 * (imu_1 + imu_2)
   double* part;
 };
+
+// Fused single-pass leapfrog step: reads state m from (e0, h0), writes state
+// m+1 to (e1, h1) (distinct buffers).  Uniform mu only.
+template <typename T>
+struct SArgs {
+  const T* e0[3];
+  const T* h0[3];
+  T* e1[3];
+  T* h1[3];
+  const T* eps;
+  const T* sig;
+  Dims d;
+  Tiling t;
+  T kb[3];
+  T hs;
+  T kd[3];
+  T imu2;            // imu_u + imu_u
+  double ge[3];
+  double gf2[3];
+  int src_comp;
+  int64_t src_idx;
+  T src_val;
+  double src_val_d;
+  Probe probe;
+  double* part;
+};
+
+// Dynamic LDS bytes of the fused kernel for a tile height ty, and the number
+// of its workgroups a CU holds at once (0 if the runtime cannot tell).
+size_t step_lds_bytes(int ty, size_t esz, bool lossy);
+int step_blocks_per_cu(int ty, size_t esz, bool lossy);
+
+template <typename T>
+hipError_t launch_step(const SArgs<T>& a, bool lossy, bool energy, bool probe, hipStream_t s);
 
 // Launch wrappers (fit_kernels.hip).  Return hipError_t of the launch.
 template <typename T>

@@ -17,6 +17,7 @@
 // formed in registers from the per-cell arrays, so the e-update moves 8 B of
 // material data per cell (FP32) instead of 24 B of per-edge coefficients.
 #include "fit_internal.hpp"
+#include "fit_point.hpp"
 
 #include <cmath>
 
@@ -91,8 +92,8 @@ __global__ __launch_bounds__(512) void k_epass(EArgs<T> A) {
   const int k1 = min(k0 + A.t.kc, d.nz);
   const bool act = (i < d.nx) && (j < d.ny);
 
-  double acc[6] = {0, 0, 0, 0, 0, 0};
-  double cmp[6] = {0, 0, 0, 0, 0, 0};
+  double acc[kPartTerms] = {0};
+  double cmp[kPartTerms] = {0};
 
   if (act) {
     const bool ip = i > 0, jp = j > 0;
@@ -149,32 +150,18 @@ __global__ __launch_bounds__(512) void k_epass(EArgs<T> A) {
         S4y = sxs + Sxs;
         S4z = Sxs + (s_jm + s_ijm);
       }
-      T cx = (hzc - hz_jm) - (hyc - hyp);
-      T cy = (hxc - hxp) - (hzc - hz_im);
-      T cz = (hyc - hy_im) - (hxc - hx_jm);
-      T jsrc = 0;
+      T jx = 0, jy = 0, jz = 0;
       if (idx == A.src_idx) {
-        jsrc = A.src_val;
-        if (A.src_comp == 0) cx -= jsrc;
-        if (A.src_comp == 1) cy -= jsrc;
-        if (A.src_comp == 2) cz -= jsrc;
+        if (A.src_comp == 0) jx = A.src_val;
+        if (A.src_comp == 1) jy = A.src_val;
+        if (A.src_comp == 2) jz = A.src_val;
       }
       const bool lx = jp && k > 0, ly = ip && k > 0, lz = ip && jp;
       const T exo = A.ein[0][idx], eyo = A.ein[1][idx], ezo = A.ein[2][idx];
       T exn, eyn, ezn;
-      if (LOSSY) {
-        const T Dx = E4x + A.hs * S4x, Dy = E4y + A.hs * S4y, Dz = E4z + A.hs * S4z;
-        exn = ((E4x - A.hs * S4x) * exo + A.kb[0] * cx) / Dx;
-        eyn = ((E4y - A.hs * S4y) * eyo + A.kb[1] * cy) / Dy;
-        ezn = ((E4z - A.hs * S4z) * ezo + A.kb[2] * cz) / Dz;
-      } else {
-        exn = exo + A.kb[0] * cx / E4x;
-        eyn = eyo + A.kb[1] * cy / E4y;
-        ezn = ezo + A.kb[2] * cz / E4z;
-      }
-      exn = lx ? exn : T(0);
-      eyn = ly ? eyn : T(0);
-      ezn = lz ? ezn : T(0);
+      e_point<T, LOSSY>(hxc, hyc, hzc, hxp, hyp, hx_jm, hy_im, hz_jm, hz_im, E4x, E4y, E4z, S4x,
+                        S4y, S4z, exo, eyo, ezo, jx, jy, jz, lx, ly, lz, A.kb[0], A.kb[1],
+                        A.kb[2], A.hs, exn, eyn, ezn);
       A.eout[0][idx] = exn;
       A.eout[1][idx] = eyn;
       A.eout[2][idx] = ezn;
@@ -267,9 +254,6 @@ __global__ __launch_bounds__(512) void k_hpass(HArgs<T> A) {
       const T ez_in = in_ ? ez[idx + 1] : T(0);
       const T ey_in = in_ ? ey[idx + 1] : T(0);
       const T ex_jn = jn ? ex[idx + sx] : T(0);
-      const T cx = (ez_jn - ezc) - (eyn - eyc);
-      const T cy = (exn - exc) - (ez_in - ezc);
-      const T cz = (ey_in - eyc) - (ex_jn - exc);
       T mx, my, mz;  // imu_1 + imu_2 per facet
       T imc = 0;
       if (MU_UNIFORM) {
@@ -281,12 +265,9 @@ __global__ __launch_bounds__(512) void k_hpass(HArgs<T> A) {
         mz = imc + imp;
       }
       const T hxo = A.hin[0][idx], hyo = A.hin[1][idx], hzo = A.hin[2][idx];
-      T hxn = hxo - A.kd[0] * mx * cx;
-      T hyn = hyo - A.kd[1] * my * cy;
-      T hzn = hzo - A.kd[2] * mz * cz;
-      hxn = ip ? hxn : T(0);
-      hyn = jp ? hyn : T(0);
-      hzn = k > 0 ? hzn : T(0);
+      T hxn, hyn, hzn;
+      h_point<T>(exc, eyc, ezc, exn, eyn, ez_jn, ez_in, ey_in, ex_jn, hxo, hyo, hzo, mx, my, mz,
+                 ip, jp, k > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
       A.hout[0][idx] = hxn;
       A.hout[1][idx] = hyn;
       A.hout[2][idx] = hzn;

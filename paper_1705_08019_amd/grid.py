@@ -203,3 +203,22 @@ class FitGrid:
         v = C.c_int64()
         call("fit_smvp_count", self._h, C.byref(v))
         return v.value
+
+    # ------------------------------------------------------------------ tuning
+    PATHS = {"auto": 0, "split": 1, "fused": 2}
+
+    def set_tuning(self, path: str = "auto", ty: int = 0, kc: int = 0):
+        call("fit_set_tuning", self._h, self.PATHS[path], int(ty), int(kc))
+
+    def get_tuning(self):
+        p, t, k = C.c_int(), C.c_int(), C.c_int()
+        call("fit_get_tuning", self._h, C.byref(p), C.byref(t), C.byref(k))
+        return {1: "split", 2: "fused"}[p.value], t.value, k.value
+
+    def autotune(self, dt: float, reps: int = 10):
+        """Time candidate paths/tiles on the current state (unchanged) and keep
+        the fastest; returns (path, ty, kc, ms_per_step)."""
+        p, t, k, ms = C.c_int(), C.c_int(), C.c_int(), C.c_float()
+        call("fit_autotune", self._h, float(dt), int(reps), C.byref(p), C.byref(t), C.byref(k),
+             C.byref(ms))
+        return {1: "split", 2: "fused"}[p.value], t.value, k.value, ms.value

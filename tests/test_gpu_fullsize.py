@@ -44,8 +44,11 @@ def _window_check(spec, e0, h0, e1, h1, dt, src, origin, step0, w=6):
     kept = t.interior_edges()
     ok = np.array([kept[Cfull.indices[Cfull.indptr[r]:Cfull.indptr[r + 1]]].all()
                    for r in range(Cfull.shape[0])])
-    se = max(np.max(np.abs(ew1)), 1e-30)
-    sh = max(np.max(np.abs(hw1[ok])), 1e-30)
+    # scale of the terms entering each update: FP32 rounding of the inputs
+    # perturbs e^(m+1) by ~eps32 * (|e| + dt |C~ h| / M_eps) and h^(m+3/2) by
+    # ~eps32 * (|h| + dt |C e| / M_mu); bound |C x| by 4 max |x|.
+    se = max(np.max(np.abs(ew1)), np.max(np.abs(ew0)), 4 * dt * np.max(np.abs(hw0)), 1e-30)
+    sh = max(np.max(np.abs(hw1[ok])), np.max(np.abs(hw0)), 4 * dt * np.max(np.abs(ew1)), 1e-30)
     de = np.max(np.abs(eg - ew1)) / se
     dh = np.max(np.abs(hg[ok] - hw1[ok])) / sh
     return de, dh, lsrc is not None

@@ -57,11 +57,13 @@ def _compare_trace(tr_gpu, tr_ref, steps, tol):
                 assert abs(dg[q] - dr[q]) <= etol * scale, (m, q, dg[q], dr[q])
 
 
+@pytest.mark.parametrize("path", ["split", "fused"])
 @pytest.mark.parametrize("dtype", ["f64", "f32"])
-def test_c1_cavity_parity(dtype):
+def test_c1_cavity_parity(dtype, path):
     spec = c1()
     ops = oracle_ops(spec)
     g = _grid(spec, dtype)
+    g.set_tuning(path)
     psi = facet_potential(spec.nx, spec.ny, spec.nz, spec.init_potential_seed)
     e0_gpu = g.apply_curl(torch.tensor(psi, device="cuda"), 1)
     e0_ref = ops.Ct @ facets_from_slots(ops, psi)
@@ -111,9 +113,10 @@ def test_curl_parity_ragged(which, dims):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14)
 
 
+@pytest.mark.parametrize("path", ["split", "fused"])
 @pytest.mark.parametrize("dtype,dims,nsteps", [("f32", (32, 32, 32), 1000),
                                                ("f64", (67, 35, 21), 300)])
-def test_lossy_blocks_source_parity(dtype, dims, nsteps):
+def test_lossy_blocks_source_parity(dtype, dims, nsteps, path):
     """Dielectric blocks, lossy z-slabs and the Gaussian source; ragged tiles
     (x spans two 64-lane tiles, z spans several chunks with a short tail)."""
     from paper_1705_08019_amd import FitGrid
@@ -128,6 +131,7 @@ def test_lossy_blocks_source_parity(dtype, dims, nsteps):
     dt = spec_dt(spec)
     src = oracle_source(spec, dt)
     g = _grid(spec, dtype)
+    g.set_tuning(path)
     g.set_source(2, src["i"], src["j"], src["k"], src["i_max"], src["sigma_t"])
     g.trace_config(10, nsteps)
     g.step(nsteps, dt)
@@ -217,3 +221,69 @@ def test_error_paths():
     ga = FitGrid(8, 8, 8, "f32", allow_unstable=True)
     ga.step(2, 1.01 * ga.cfl_dt())               # allowed when forced
     assert ga.step_index == 2
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_paths_and_tiles_bitwise(dtype):
+    """Split and fused kernels, over several tile shapes and z-chunkings, give
+    bitwise identical fields (any halo race or ordering bug shows up here);
+    traced energies agree to FP64 rounding of the different block sums."""
+    from paper_1705_08019_amd import FitGrid
+    nx, ny, nz = 131, 45, 37
+    eps = dielectric_blocks(nx, ny, nz, 16, 5)
+    sig = lossy_slab(nx, ny, nz, 3)
+    src = (2, 70, 20, 18, 1.0)
+    ref = None
+    configs = [("split", 0, 0), ("split", 1, 5), ("split", 8, 37), ("fused", 0, 0),
+               ("fused", 2, 3), ("fused", 4, 16), ("fused", 8, 1), ("fused", 16, 37)]
+    if dtype == "f64":
+        configs = [c for c in configs if c[1] <= 8]
+    for path, ty, kc in configs:
+        g = FitGrid(nx, ny, nz, dtype)
+        g.set_materials(eps, None, sig)
+        dt = 0.9 * g.cfl_dt()
+        g.set_tuning(path, ty, kc)
+        g.set_source(*src[:4], src[4], 20 * dt)
+        g.trace_config(5, 40)
+        g.step(77, dt)
+        e, h = g.get_fields()
+        tr, _ = g.trace_read()
+        if ref is None:
+            ref = (e, h, tr)
+            continue
+        assert torch.equal(e, ref[0]) and torch.equal(h, ref[1]), (path, ty, kc)
+        np.testing.assert_allclose(tr, ref[2], rtol=1e-13, atol=0)
+        g.close()
+
+
+def test_fused_rejects_nonuniform_mu():
+    from paper_1705_08019_amd import FitGrid, FitError
+    g = FitGrid(8, 8, 8, "f32")
+    g.set_materials(np.ones(512), mu_r=np.linspace(1, 2, 512))
+    with pytest.raises(FitError, match="INVALID"):
+        g.set_tuning("fused")
+    assert g.get_tuning()[0] == "split"
+
+
+def test_autotune_keeps_state_and_results():
+    from paper_1705_08019_amd import FitGrid
+    nx, ny, nz = 96, 70, 40
+    eps = dielectric_blocks(nx, ny, nz, 10, 6)
+    sig = lossy_slab(nx, ny, nz, 2)
+    grids = []
+    for tune in (False, True):
+        g = FitGrid(nx, ny, nz, "f32")
+        g.set_materials(eps, None, sig)
+        dt = 0.9 * g.cfl_dt()
+        g.set_source(2, 48, 35, 20, 1.0, 20 * dt)
+        g.step(13, dt)
+        if tune:
+            before = g.get_fields()
+            path, ty, kc, ms = g.autotune(dt, reps=3)
+            after = g.get_fields()
+            assert torch.equal(before[0], after[0]) and torch.equal(before[1], after[1])
+            assert g.step_index == 13 and ms > 0
+            assert g.get_tuning() == (path, ty, kc)
+        g.step(30, dt)
+        grids.append(g.get_fields())
+    assert torch.equal(grids[0][0], grids[1][0]) and torch.equal(grids[0][1], grids[1][1])
