@@ -186,6 +186,17 @@ int fit_probe_value(fit_grid* g, double* J);
 /* Reset the probe objective to 0. */
 int fit_probe_reset(fit_grid* g);
 
+/* Mode-Gram energy matrix (the bilinear form of eq. energy over snapshots):
+ * G[a][b] = sum_r M_rr x_a[r] x_b[r] for K snapshots x_0 .. x_{K-1}, with
+ * M = M_eps (which = 0, x are e-fields) or M = M_mu (which = 1, h-fields)
+ * of this grid's materials.  X: device pointer, snapshot a at X + a * ld
+ * elements, each in the slot layout and the grid's dtype (ld >= 3 nx ny nz);
+ * PEC-wall slots carry weight 0.  Computed on the FP64 matrix cores with
+ * FP64 accumulation inside a workgroup and compensated summation across
+ * workgroups.  G: host, K * K doubles row-major, exactly symmetric.
+ * 1 <= K <= 4096.  Synchronises. */
+int fit_gram(fit_grid* g, const void* X, int64_t ld, int K, int which, double* G);
+
 /* Kernel timing.  Between fit_profile_begin and fit_profile_end every
  * kernel launch made by this handle is bracketed by a pair of hipEvents on
  * the handle's stream (at most max_launches launches are timed; later ones

@@ -61,6 +61,7 @@ SIGNATURES = {
     "fit_smvp_count": [_vp, _i64p],
     "fit_set_tuning": [_vp, _i, _i, _i],
     "fit_get_tuning": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)],
+    "fit_gram": [_vp, _vp, _i64, _i, _i, _dp],
     "fit_autotune": [_vp, _d, _i, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                      C.POINTER(C.c_float)],
 }

@@ -502,6 +502,8 @@ int fit_grid_destroy(fit_grid* g) {
   dev_free(reinterpret_cast<void*&>(g->trace));
   dev_free(reinterpret_cast<void*&>(g->jacc));
   dev_free(reinterpret_cast<void*&>(g->pend));
+  dev_free(reinterpret_cast<void*&>(g->gram_part));
+  dev_free(reinterpret_cast<void*&>(g->gram_G));
   delete g;
   return FIT_OK;
 }
@@ -813,6 +815,49 @@ int fit_profile_end(fit_grid* g, double ms[FIT_PROF_N], int64_t count[FIT_PROF_N
     if (ms) ms[k] = acc[k];
     if (count) count[k] = cnt[k];
   }
+  return FIT_OK;
+}
+
+int fit_gram(fit_grid* g, const void* X, int64_t ld, int K, int which, double* G) {
+  if (!g || !X || !G) return fail(FIT_E_INVALID, "null argument");
+  if (K < 1 || K > 4096) return fail(FIT_E_INVALID, "K must be in [1, 4096]");
+  if (which != 0 && which != 1) return fail(FIT_E_INVALID, "which must be 0 (e, M_eps) or 1 (h, M_mu)");
+  if (ld < 3 * g->d.n) return fail(FIT_E_INVALID, "ld must be >= 3 nx ny nz");
+  const int64_t cap_blocks = 1024;
+  int rc = FIT_OK;
+  if (!g->gram_part)
+    rc = dev_alloc(reinterpret_cast<void**>(&g->gram_part),
+                   (size_t)cap_blocks * 64 * 64 * sizeof(double), "Gram partials");
+  if (rc) return rc;
+  if (g->gram_G_cap < (int64_t)K * K) {
+    dev_free(reinterpret_cast<void*&>(g->gram_G));
+    g->gram_G_cap = 0;
+    rc = dev_alloc(reinterpret_cast<void**>(&g->gram_G), (size_t)K * K * sizeof(double), "Gram");
+    if (rc) return rc;
+    g->gram_G_cap = (int64_t)K * K;
+  }
+  double gw[3];
+  for (int a = 0; a < 3; ++a) gw[a] = which == 0 ? g->gedge[a] / 4.0 : g->gf2[a];
+  int64_t nwg = 0;
+  hipError_t e;
+  {
+    ProfScope ps(g, FIT_PROF_OTHER);
+    if (g->f64)
+      e = launch_gram<double>(static_cast<const double*>(X), ld, K, which,
+                              static_cast<const double*>(g->eps),
+                              g->mu_uniform ? nullptr : static_cast<const double*>(g->imu),
+                              g->imu_u, g->d, gw, g->gram_part, cap_blocks, g->gram_G, g->s, &nwg);
+    else
+      e = launch_gram<float>(static_cast<const float*>(X), ld, K, which,
+                             static_cast<const float*>(g->eps),
+                             g->mu_uniform ? nullptr : static_cast<const float*>(g->imu),
+                             (float)g->imu_u, g->d, gw, g->gram_part, cap_blocks, g->gram_G, g->s,
+                             &nwg);
+  }
+  if (e != hipSuccess) return hip_fail(e, "Gram launch");
+  e = hipMemcpyAsync(G, g->gram_G, (size_t)K * K * sizeof(double), hipMemcpyDeviceToHost, g->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->s);
+  if (e != hipSuccess) return hip_fail(e, "Gram readback");
   return FIT_OK;
 }
 

@@ -48,6 +48,9 @@ struct fit_grid {
   void* e_alt = nullptr;        // second buffer set of the fused (ping-pong) step
   void* h_alt = nullptr;
   fit_adjoint_ws* adj = nullptr;
+  double* gram_part = nullptr;  // per-workgroup Gram blocks
+  double* gram_G = nullptr;     // device K x K result
+  int64_t gram_G_cap = 0;
   // kernel timing (fit_profile_begin/end)
   std::vector<hipEvent_t> prof_ev;   // 2 per timed launch
   std::vector<int> prof_kind;

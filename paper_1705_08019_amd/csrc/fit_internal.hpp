@@ -108,6 +108,13 @@ int step_blocks_per_cu(int ty, size_t esz, bool lossy);
 template <typename T>
 hipError_t launch_step(const SArgs<T>& a, bool lossy, bool energy, bool probe, hipStream_t s);
 
+// Gram matrix G = X^T diag(M) X over K snapshots (fit_gram.hip); part must
+// hold part_cap_blocks * 64 * 64 doubles, G (device) K * K doubles.
+template <typename T>
+hipError_t launch_gram(const T* X, int64_t ld, int K, int which, const T* eps, const T* imu,
+                       T imu_u, const Dims& d, const double gw[3], double* part,
+                       int64_t part_cap_blocks, double* G, hipStream_t s, int64_t* nwg_used);
+
 // Launch wrappers (fit_kernels.hip).  Return hipError_t of the launch.
 template <typename T>
 hipError_t launch_epass(const EArgs<T>& a, bool lossy, bool energy, bool probe, hipStream_t s);

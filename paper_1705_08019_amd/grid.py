@@ -222,3 +222,18 @@ class FitGrid:
         call("fit_autotune", self._h, float(dt), int(reps), C.byref(p), C.byref(t), C.byref(k),
              C.byref(ms))
         return {1: "split", 2: "fused"}[p.value], t.value, k.value, ms.value
+
+    # ------------------------------------------------------------------ Gram
+    def gram(self, X: torch.Tensor, which: int = 0) -> np.ndarray:
+        """G = X^T diag(M) X for K snapshots X of shape (K, 3, nz, ny, nx) (or
+        (K, 3 nx ny nz)) on the device; which 0: e with M_eps, 1: h with M_mu."""
+        if not (isinstance(X, torch.Tensor) and X.is_cuda):
+            raise ValueError("X must be a device tensor")
+        K = X.shape[0]
+        Xc = X.to(self.tdtype).reshape(K, -1).contiguous()
+        if Xc.shape[1] != 3 * self.cells:
+            raise ValueError("each snapshot must have 3 * nx * ny * nz values")
+        G = np.empty((K, K), dtype=np.float64)
+        call("fit_gram", self._h, C.c_void_p(Xc.data_ptr()), Xc.stride(0), int(K), int(which),
+             dptr(G))
+        return G
