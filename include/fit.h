@@ -197,6 +197,45 @@ int fit_probe_reset(fit_grid* g);
  * 1 <= K <= 4096.  Synchronises. */
 int fit_gram(fit_grid* g, const void* X, int64_t ld, int K, int which, double* G);
 
+/* ---- Differentiation: discrete reverse-time adjoint of fit_step ----------
+ * The objective is the probe energy J of fit_set_probe accumulated over a
+ * forward run of N steps from step 0.  The adjoint recursion (lambda = dJ/de,
+ * mu = dJ/dh, zero beyond the horizon), for m = N-1 down to 0:
+ *   lambda^(m+1) = a lambda^(m+2) - C~ (dt M_mu^{-1} mu^(m+3/2)) + 2 dt w M_eps e^(m+1)
+ *   mu^(m+1/2)   = mu^(m+3/2) + C (b lambda^(m+1))
+ * with a, b the e-update coefficients of fit_step; it differentiates the
+ * leapfrog updates of Sec. II-A exactly (dt held fixed).  Sensitivities to the
+ * per-cell eps_r and sigma are accumulated per edge in FP64 and gathered onto
+ * the cells by fit_adjoint_grad.  Needs a uniform mu and a probe. */
+
+/* Advance nsteps leapfrog steps like fit_step, recording every state:
+ * e_rec + s * 3n holds e^(m0+s) and h_rec + s * 3n holds h^(m0+s+1/2) for
+ * s = 0 .. nsteps (device pointers, (nsteps+1) * 3 * nx*ny*nz elements each,
+ * grid dtype, slot layout); m0 is the step counter on entry.  The handle ends
+ * in state m0 + nsteps.  No energy trace and no probe accumulation. */
+int fit_step_record(fit_grid* g, int64_t nsteps, double dt, void* e_rec, void* h_rec);
+
+/* Start a reverse sweep over a forward horizon of nsteps steps taken with dt:
+ * clears lambda, mu and the accumulated sensitivities.  Errors: FIT_E_STATE
+ * without a probe, FIT_E_INVALID for a non-uniform mu. */
+int fit_adjoint_begin(fit_grid* g, int64_t nsteps, double dt);
+
+/* One reverse step m (must be called for m = N-1, N-2, ..., 0 in order, else
+ * FIT_E_STATE) given the forward states e^m, e^(m+1) and h^(m+1/2) (device
+ * pointers, slot layout, grid dtype), e.g. recomputed from a checkpoint with
+ * fit_step_record.  Asynchronous. */
+int fit_adjoint_step(fit_grid* g, int64_t m, const void* e_m, const void* e_m1, const void* h_mh);
+
+/* Reverse steps m0 + nsteps - 1 down to m0 over a recorded segment
+ * (e_rec, h_rec as written by fit_step_record starting at m0). */
+int fit_adjoint_segment(fit_grid* g, int64_t m0, int64_t nsteps, const void* e_rec,
+                        const void* h_rec);
+
+/* Per-cell gradients dJ/deps_r and dJ/dsigma (FP64, nx*ny*nz values each,
+ * layout [k][j][i]) of the sensitivities accumulated so far; device or host
+ * destinations.  Host destinations synchronise. */
+int fit_adjoint_grad(fit_grid* g, double* deps, double* dsigma, int on_device);
+
 /* Kernel timing.  Between fit_profile_begin and fit_profile_end every
  * kernel launch made by this handle is bracketed by a pair of hipEvents on
  * the handle's stream (at most max_launches launches are timed; later ones

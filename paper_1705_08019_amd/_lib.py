@@ -62,6 +62,11 @@ SIGNATURES = {
     "fit_set_tuning": [_vp, _i, _i, _i],
     "fit_get_tuning": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "fit_gram": [_vp, _vp, _i64, _i, _i, _dp],
+    "fit_step_record": [_vp, _i64, _d, _vp, _vp],
+    "fit_adjoint_begin": [_vp, _i64, _d],
+    "fit_adjoint_step": [_vp, _i64, _vp, _vp, _vp],
+    "fit_adjoint_segment": [_vp, _i64, _i64, _vp, _vp],
+    "fit_adjoint_grad": [_vp, _vp, _vp, _i],
     "fit_autotune": [_vp, _d, _i, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                      C.POINTER(C.c_float)],
 }

@@ -241,7 +241,7 @@ template int step_once<double>(fit_grid*, double, const double*, double*, const 
 // One fused leapfrog step m -> m+1: state read from (e, h), written to
 // (e_alt, h_alt), then the two sets swap roles.
 template <typename T>
-int step_fused(fit_grid* g, double dt) {
+int step_fused_io(fit_grid* g, double dt, const T* e0, const T* h0, T* e1, T* h1) {
   const int64_t m = g->m;
   const bool tr_this = g->trace_every > 0 && m % g->trace_every == 0;
   const bool tr_next = g->trace_every > 0 && (m + 1) % g->trace_every == 0;
@@ -250,20 +250,7 @@ int step_fused(fit_grid* g, double dt) {
   const bool probe = g->probe.on != 0;
   const bool energy = have_row || tr_next;
   const Dims& d = g->d;
-  if (!g->e_alt) {
-    int rc = dev_alloc(&g->e_alt, 3 * d.n * g->esz, "e (second buffer)");
-    if (!rc) rc = dev_alloc(&g->h_alt, 3 * d.n * g->esz, "h (second buffer)");
-    if (rc) {
-      dev_free(g->e_alt);
-      dev_free(g->h_alt);
-      return rc;
-    }
-  }
   SArgs<T> a;
-  const T* e0 = static_cast<const T*>(g->e);
-  const T* h0 = static_cast<const T*>(g->h);
-  T* e1 = static_cast<T*>(g->e_alt);
-  T* h1 = static_cast<T*>(g->h_alt);
   for (int c = 0; c < 3; ++c) {
     a.e0[c] = e0 + c * d.n;
     a.h0[c] = h0 + c * d.n;
@@ -312,16 +299,40 @@ int step_fused(fit_grid* g, double dt) {
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
     g->pend_m = m + 1;
   }
-  std::swap(g->e, g->e_alt);
-  std::swap(g->h, g->h_alt);
   if (have_row) g->trace_rows++;
   g->m = m + 1;
   g->smvp += 2;
   return FIT_OK;
 }
 
+int ensure_alt(fit_grid* g) {
+  if (g->e_alt) return FIT_OK;
+  int rc = dev_alloc(&g->e_alt, 3 * g->d.n * g->esz, "e (second buffer)");
+  if (!rc) rc = dev_alloc(&g->h_alt, 3 * g->d.n * g->esz, "h (second buffer)");
+  if (rc) {
+    dev_free(g->e_alt);
+    dev_free(g->h_alt);
+  }
+  return rc;
+}
+
+template <typename T>
+int step_fused(fit_grid* g, double dt) {
+  int rc = ensure_alt(g);
+  if (rc) return rc;
+  rc = step_fused_io<T>(g, dt, static_cast<const T*>(g->e), static_cast<const T*>(g->h),
+                        static_cast<T*>(g->e_alt), static_cast<T*>(g->h_alt));
+  if (rc) return rc;
+  std::swap(g->e, g->e_alt);
+  std::swap(g->h, g->h_alt);
+  return FIT_OK;
+}
+
 template int step_fused<float>(fit_grid*, double);
 template int step_fused<double>(fit_grid*, double);
+template int step_fused_io<float>(fit_grid*, double, const float*, const float*, float*, float*);
+template int step_fused_io<double>(fit_grid*, double, const double*, const double*, double*,
+                                   double*);
 
 int check_dt(const fit_grid* g, double dt) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FIT_E_INVALID, "dt must be positive and finite");
@@ -376,11 +387,7 @@ int time_candidate(fit_grid* g, double dt, int path, int ty, int kc, int reps, f
       std::swap(g->h, g->h_alt);
       return r;
     }
-    if (!g->e_alt) {
-      int r = dev_alloc(&g->e_alt, 3 * d.n * g->esz, "e (second buffer)");
-      if (!r) r = dev_alloc(&g->h_alt, 3 * d.n * g->esz, "h (second buffer)");
-      if (r) return r;
-    }
+    if (int r = ensure_alt(g)) return r;
     return step_once<T>(g, dt, static_cast<const T*>(g->e), static_cast<T*>(g->e_alt),
                         static_cast<const T*>(g->h), static_cast<T*>(g->h_alt));
   };

@@ -7,7 +7,18 @@
 #include "fit.h"
 #include "fit_internal.hpp"
 
-struct fit_adjoint_ws;
+// Adjoint workspace: reverse state and per-edge FP64 sensitivities.
+struct fit_adjoint_ws {
+  int64_t N = 0;          // forward horizon (steps)
+  double dt = 0.0;
+  int64_t next_m = -1;    // reverse step expected next (N-1 down to 0)
+  void* lam = nullptr;    // 3n, grid dtype
+  void* mu = nullptr;
+  void* tau = nullptr;
+  double* gMe = nullptr;  // 3n
+  double* gMs = nullptr;
+  double* gcell = nullptr;  // 2n: per-cell gradients
+};
 
 struct fit_grid {
   fit_grid_desc desc{};
@@ -76,6 +87,10 @@ bool use_fused(const fit_grid* g);
 void default_step_tiling(const Dims& d, size_t esz, bool lossy, int* ty, int* kc);
 template <typename T>
 int step_fused(fit_grid* g, double dt);
+template <typename T>
+int step_fused_io(fit_grid* g, double dt, const T* e0, const T* h0, T* e1, T* h1);
+int ensure_alt(fit_grid* g);
+void default_tiling(const Dims& d, int* ty, int* kc);
 
 // Bracket one kernel launch with timing events when profiling is on.
 struct ProfScope {

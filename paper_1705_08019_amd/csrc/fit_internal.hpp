@@ -115,6 +115,40 @@ hipError_t launch_gram(const T* X, int64_t ld, int K, int which, const T* eps, c
                        T imu_u, const Dims& d, const double gw[3], double* part,
                        int64_t part_cap_blocks, double* G, hipStream_t s, int64_t* nwg_used);
 
+// Reverse-time adjoint step (fit_adjoint.hip).  lam, tau, em, em1 are
+// 3-component slot-layout arrays (component a at a * n); gMe, gMs per-edge
+// FP64 sensitivities dJ/dM_eps, dJ/dM_sigma.
+template <typename T>
+struct AdjArgs {
+  const T* h[3];      // h^(m+1/2)
+  T* mu[3];           // mu^(m+3/2) -> mu^(m+1/2)
+  T* lam;             // lambda^(m+2) -> lambda^(m+1)
+  T* tau;             // b lambda^(m+1)
+  const T* em;        // e^m
+  const T* em1;       // e^(m+1)
+  const T* eps;
+  const T* sig;
+  double* gMe;
+  double* gMs;
+  Dims d;
+  Tiling t;
+  T kb[3];
+  T hs;
+  T dmu[3];           // dt M_mu^{-1} per facet direction (uniform mu)
+  double ge[3];
+  double dt, hdt;
+  int src_comp;
+  int64_t src_idx;
+  T src_val;
+  Probe probe;
+};
+
+template <typename T>
+hipError_t launch_adjoint_step(const AdjArgs<T>& a, bool lossy, hipStream_t s);
+hipError_t launch_adjoint_gather(const double* gMe, const double* gMs, const Dims& d,
+                                 const double gq[3], double eps0, double* deps, double* dsig,
+                                 hipStream_t s);
+
 // Launch wrappers (fit_kernels.hip).  Return hipError_t of the launch.
 template <typename T>
 hipError_t launch_epass(const EArgs<T>& a, bool lossy, bool energy, bool probe, hipStream_t s);

@@ -237,3 +237,41 @@ class FitGrid:
         call("fit_gram", self._h, C.c_void_p(Xc.data_ptr()), Xc.stride(0), int(K), int(which),
              dptr(G))
         return G
+
+    # ------------------------------------------------------------------ adjoint
+    def step_record(self, nsteps: int, dt: float, e_rec: torch.Tensor, h_rec: torch.Tensor):
+        """Advance nsteps, writing e^(m0+s) to e_rec[s] and h^(m0+s+1/2) to
+        h_rec[s] (device tensors with >= nsteps+1 leading entries)."""
+        for r in (e_rec, h_rec):
+            if not (r.is_cuda and r.dtype == self.tdtype and r.is_contiguous()
+                    and r.numel() >= (nsteps + 1) * 3 * self.cells):
+                raise ValueError("record buffers: contiguous device tensors of the grid dtype "
+                                 "with (nsteps+1) * 3 * cells values")
+        call("fit_step_record", self._h, int(nsteps), float(dt), C.c_void_p(e_rec.data_ptr()),
+             C.c_void_p(h_rec.data_ptr()))
+
+    def adjoint_begin(self, nsteps: int, dt: float):
+        call("fit_adjoint_begin", self._h, int(nsteps), float(dt))
+
+    def adjoint_step(self, m: int, e_m: torch.Tensor, e_m1: torch.Tensor, h_mh: torch.Tensor):
+        for x in (e_m, e_m1, h_mh):
+            if not (x.is_cuda and x.dtype == self.tdtype and x.is_contiguous()
+                    and x.numel() == 3 * self.cells):
+                raise ValueError("states must be contiguous device tensors of the grid dtype")
+        call("fit_adjoint_step", self._h, int(m), C.c_void_p(e_m.data_ptr()),
+             C.c_void_p(e_m1.data_ptr()), C.c_void_p(h_mh.data_ptr()))
+
+    def adjoint_segment(self, m0: int, nsteps: int, e_rec: torch.Tensor, h_rec: torch.Tensor):
+        for r in (e_rec, h_rec):
+            if not (r.is_cuda and r.dtype == self.tdtype and r.is_contiguous()
+                    and r.numel() >= (nsteps + 1) * 3 * self.cells):
+                raise ValueError("record buffers too small")
+        call("fit_adjoint_segment", self._h, int(m0), int(nsteps), C.c_void_p(e_rec.data_ptr()),
+             C.c_void_p(h_rec.data_ptr()))
+
+    def adjoint_grad(self):
+        """(dJ/deps_r, dJ/dsigma) as FP64 device tensors of shape (nz, ny, nx)."""
+        de = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float64, device=self.device)
+        ds = torch.empty_like(de)
+        call("fit_adjoint_grad", self._h, C.c_void_p(de.data_ptr()), C.c_void_p(ds.data_ptr()), 1)
+        return de, ds

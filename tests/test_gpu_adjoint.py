@@ -1,0 +1,148 @@
+"""GPU parity of the reverse-time adjoint (through torch.autograd and the C
+ABI) against the oracle's discrete adjoint and central finite differences."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from fit_workloads import dielectric_blocks, lossy_slab, c5, c5_small
+from oracle import adjoint as oadj
+from _glue import oracle_ops, spec_dt, oracle_source
+
+pytestmark = pytest.mark.gpu
+
+
+def _problem(spec, dtype, dt, nsteps, K):
+    from paper_1705_08019_amd import ProbeProblem
+    box = spec.probe
+    return ProbeProblem(nx=spec.nx, ny=spec.ny, nz=spec.nz, nsteps=nsteps,
+                        probe_lo=tuple(b[0] for b in box), probe_hi=tuple(b[1] for b in box),
+                        dtype=dtype, dt=dt, checkpoint_every=K, source=spec.source)
+
+
+def _grads(spec, dtype, dt, nsteps, K, sigma=True):
+    from paper_1705_08019_amd import probe_energy
+    eps = torch.tensor(spec.eps_r, requires_grad=True)
+    sig = torch.tensor(spec.sigma, requires_grad=True) if sigma else None
+    J = probe_energy(eps, sig, _problem(spec, dtype, dt, nsteps, K))
+    J.backward()
+    return float(J), eps.grad.numpy(), (sig.grad.numpy() if sigma else None)
+
+
+def _small_spec(n=(10, 9, 8)):
+    nx, ny, nz = n
+    spec = c5_small(8, 0, "f64")
+    spec.nx, spec.ny, spec.nz = nx, ny, nz
+    spec.eps_r = dielectric_blocks(nx, ny, nz, 5, 31)
+    spec.sigma = lossy_slab(nx, ny, nz, 2) + 0.01
+    spec.source = dict(axis=2, i=4, j=4, k=3, i_max=1.0, sigma_t_steps=8.0)
+    spec.probe = ((5, 8), (4, 7), (4, 6))
+    return spec
+
+
+@pytest.mark.parametrize("nsteps,K", [(80, 16), (70, 16), (37, 64)])
+def test_adjoint_fp64_matches_oracle(nsteps, K):
+    spec = _small_spec()
+    dt = spec_dt(spec)
+    J, ge, gs = _grads(spec, "f64", dt, nsteps, K)
+    ops = oracle_ops(spec)
+    w = oadj.probe_weights(ops, spec.probe)
+    Jr, ge_r, gs_r, _, _ = oadj.gradient(ops, np.zeros(ops.n_e), np.zeros(ops.n_h), dt, nsteps,
+                                         oracle_source(spec, dt), w)
+    assert abs(J - Jr) <= 1e-12 * Jr
+    np.testing.assert_allclose(ge.ravel(), ge_r, rtol=0, atol=1e-10 * np.max(np.abs(ge_r)))
+    np.testing.assert_allclose(gs.ravel(), gs_r, rtol=0, atol=1e-10 * np.max(np.abs(gs_r)))
+
+
+def test_adjoint_fp64_matches_gpu_central_differences():
+    from paper_1705_08019_amd import FitGrid
+    spec = _small_spec((12, 8, 9))
+    dt = spec_dt(spec)
+    nsteps = 60
+    J, ge, gs = _grads(spec, "f64", dt, nsteps, 16)
+
+    def J_fwd(eps, sig):
+        g = FitGrid(spec.nx, spec.ny, spec.nz, "f64")
+        g.set_materials(eps, None, sig)
+        s = spec.source
+        g.set_source(2, s["i"], s["j"], s["k"], 1.0, s["sigma_t_steps"] * dt)
+        g.set_probe([b[0] for b in spec.probe], [b[1] for b in spec.probe])
+        g.step(nsteps, dt)
+        return g.probe_value()
+
+    rng = np.random.default_rng(55)
+    h = 1e-3
+    for c in rng.choice(spec.eps_r.size, 12, replace=False):
+        k, j, i = np.unravel_index(c, spec.eps_r.shape)
+        ep, em = spec.eps_r.copy(), spec.eps_r.copy()
+        ep[k, j, i] += h
+        em[k, j, i] -= h
+        fd = (J_fwd(ep, spec.sigma) - J_fwd(em, spec.sigma)) / (2 * h)
+        assert abs(fd - ge[k, j, i]) <= 1e-5 * np.max(np.abs(ge)), (c, fd, ge[k, j, i])
+        sp_, sm_ = spec.sigma.copy(), spec.sigma.copy()
+        sp_[k, j, i] += h
+        sm_[k, j, i] -= h
+        fd = (J_fwd(spec.eps_r, sp_) - J_fwd(spec.eps_r, sm_)) / (2 * h)
+        assert abs(fd - gs[k, j, i]) <= 1e-5 * np.max(np.abs(gs)), (c, fd, gs[k, j, i])
+
+
+def test_adjoint_fp32_24cube_matches_fp64_oracle():
+    """The 24^3 copy of the 96^3 adjoint workload at the full horizon
+    (4096 steps, checkpoints every 64): FP32 fields against the FP64 oracle."""
+    spec = c5_small(24, 4096, "f32")
+    dt = spec_dt(spec)
+    J, ge, gs = _grads(spec, "f32", dt, spec.nsteps, spec.checkpoint_every)
+    ops = oracle_ops(spec)
+    w = oadj.probe_weights(ops, spec.probe)
+    Jr, ge_r, gs_r, _, _ = oadj.gradient(ops, np.zeros(ops.n_e), np.zeros(ops.n_h), dt,
+                                         spec.nsteps, oracle_source(spec, dt), w)
+    assert abs(J - Jr) <= 1e-4 * Jr
+    err_e = np.max(np.abs(ge.ravel() - ge_r)) / np.max(np.abs(ge_r))
+    err_s = np.max(np.abs(gs.ravel() - gs_r)) / np.max(np.abs(gs_r))
+    print(f"24^3 x 4096 FP32 adjoint vs FP64 oracle: max rel err eps {err_e:.2e} sigma {err_s:.2e}")
+    assert err_e <= 2e-5 and err_s <= 2e-5
+
+
+def test_adjoint_fp32_96cube_vs_fp64_central_differences():
+    """Full adjoint workload (96^3, 4096 steps, checkpoints every 64) in FP32;
+    central differences (h = 1e-3) of FP64 forward runs on 32 seeded cells
+    between the source and the probe (eps) and 16 seeded lossy-slab cells
+    near the source column (sigma)."""
+    from paper_1705_08019_amd import FitGrid
+    spec = c5()
+    dt = spec_dt(spec)
+    J, ge, gs = _grads(spec, "f32", dt, spec.nsteps, spec.checkpoint_every)
+    s = spec.source
+
+    def J_fwd(eps, sig):
+        g = FitGrid(spec.nx, spec.ny, spec.nz, "f64")
+        g.set_materials(eps, None, sig)
+        g.set_source(2, s["i"], s["j"], s["k"], 1.0, s["sigma_t_steps"] * dt)
+        g.set_probe([b[0] for b in spec.probe], [b[1] for b in spec.probe])
+        g.step(spec.nsteps, dt)
+        v = g.probe_value()
+        g.close()
+        return v
+
+    rng = np.random.default_rng(55)
+    h = 1e-3
+    scale_e = np.max(np.abs(ge))
+    errs = []
+    for _ in range(32):
+        i, j, k = (int(v) for v in rng.integers(44, 80, size=3))
+        ep, em = spec.eps_r.copy(), spec.eps_r.copy()
+        ep[k, j, i] += h
+        em[k, j, i] -= h
+        fd = (J_fwd(ep, spec.sigma) - J_fwd(em, spec.sigma)) / (2 * h)
+        errs.append(abs(fd - ge[k, j, i]) / scale_e)
+    scale_s = np.max(np.abs(gs))
+    for _ in range(16):
+        i, j = (int(v) for v in rng.integers(40, 56, size=2))
+        k = int(rng.integers(0, 8))
+        sp_, sm_ = spec.sigma.copy(), spec.sigma.copy()
+        sp_[k, j, i] += h
+        sm_[k, j, i] -= h
+        fd = (J_fwd(spec.eps_r, sp_) - J_fwd(spec.eps_r, sm_)) / (2 * h)
+        errs.append(abs(fd - gs[k, j, i]) / scale_s)
+    print(f"96^3 FP32 adjoint vs FP64 central differences: max rel err {max(errs):.2e}")
+    assert max(errs) <= 1e-4
