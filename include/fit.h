@@ -236,6 +236,42 @@ int fit_adjoint_segment(fit_grid* g, int64_t m0, int64_t nsteps, const void* e_r
  * destinations.  Host destinations synchronise. */
 int fit_adjoint_grad(fit_grid* g, double* deps, double* dsigma, int on_device);
 
+/* ---- Batched grids: many independent grids advanced together ------------
+ * A batch advances nb grids (same dtype, uniform mu each; sizes, materials,
+ * sources and dt may all differ) together.  Each launch covers one step of
+ * every grid: one workgroup per fused-step tile of every grid (no workgroup
+ * waits on another; the kernel boundary orders the steps).  Chunks of S
+ * steps are captured once in a hipGraph and replayed.  Each grid's result is
+ * bitwise identical to fit_step on that grid alone.  The grids stay usable on
+ * their own between batch calls; a batch references them and must be
+ * destroyed before them.  Batched steps record no energy trace; a grid with a
+ * probe is rejected. */
+typedef struct fit_batch fit_batch;
+
+/* Build a batch over nb >= 1 distinct grids; `stream` is the caller's
+ * hipStream_t (NULL = default stream); work is ordered after and before it. */
+int fit_batch_create(fit_grid* const* grids, int nb, void* stream, fit_batch** out);
+
+/* Destroy a batch (not its grids).  NULL is accepted. */
+int fit_batch_destroy(fit_batch* b);
+
+/* Tile rows ty (power of two, 2..16; 0 keeps), z-planes per item kc (0 =
+ * whole columns) and steps per captured launch (0 keeps; default 16). */
+int fit_batch_set_tuning(fit_batch* b, int ty, int kc, int steps_per_graph);
+int fit_batch_get_tuning(const fit_batch* b, int* ty, int* kc, int* steps_per_graph, int* nwg);
+
+/* Autotuner: time candidate (ty, kc) with `reps` single-step launches each
+ * (state unchanged) and keep the fastest. dt: host array of nb step sizes. */
+int fit_batch_autotune(fit_batch* b, const double* dt, int reps, int* ty, int* kc, float* ms_best);
+
+/* Advance every grid of the batch by nsteps steps; dt: host array of nb step
+ * sizes (each <= its grid's CFL bound unless that grid allows instability).
+ * use_graph != 0 replays the captured S-step graph for whole chunks (the
+ * remainder runs as direct launches); 0 launches directly.  Asynchronous with
+ * respect to the host; ordered after and before the caller's stream.
+ * get_tuning's last output is the number of workgroups per step launch. */
+int fit_batch_step(fit_batch* b, int64_t nsteps, const double* dt, int use_graph);
+
 /* Kernel timing.  Between fit_profile_begin and fit_profile_end every
  * kernel launch made by this handle is bracketed by a pair of hipEvents on
  * the handle's stream (at most max_launches launches are timed; later ones

@@ -7,5 +7,6 @@ package only marshals arguments.  Build the library in-tree first:
 from ._lib import FitError, lib  # noqa: F401
 from .grid import FitGrid  # noqa: F401
 from .adjoint import ProbeProblem, probe_energy  # noqa: F401
+from .batch import FitBatch  # noqa: F401
 
-__all__ = ["FitGrid", "FitError", "lib", "ProbeProblem", "probe_energy"]
+__all__ = ["FitGrid", "FitBatch", "FitError", "lib", "ProbeProblem", "probe_energy"]

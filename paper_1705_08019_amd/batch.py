@@ -1,0 +1,58 @@
+"""Python handle for a batch of grids advanced by one persistent launch
+(thin wrapper over fit_batch_* in include/fit.h)."""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+
+from . import _lib
+from ._lib import call, dptr
+from .grid import FitGrid, current_stream_handle
+
+
+class FitBatch:
+    def __init__(self, grids, stream=None):
+        self.grids = list(grids)
+        if not all(isinstance(g, FitGrid) for g in self.grids):
+            raise TypeError("FitBatch takes FitGrid objects")
+        arr = (C.c_void_p * len(self.grids))(*[g.handle.value for g in self.grids])
+        h = C.c_void_p()
+        st = current_stream_handle() if stream is None else int(stream)
+        call("fit_batch_create", arr, len(self.grids), C.c_void_p(st), C.byref(h))
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            _lib.lib().fit_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _dt(self, dt):
+        a = np.ascontiguousarray(np.broadcast_to(np.asarray(dt, dtype=np.float64),
+                                                 (len(self.grids),)))
+        return a
+
+    def set_tuning(self, ty: int = 0, kc: int = 0, steps_per_graph: int = 0):
+        call("fit_batch_set_tuning", self._h, int(ty), int(kc), int(steps_per_graph))
+
+    def get_tuning(self):
+        v = [C.c_int() for _ in range(4)]
+        call("fit_batch_get_tuning", self._h, *[C.byref(x) for x in v])
+        return tuple(x.value for x in v)   # ty, kc, steps_per_graph, workgroups
+
+    def autotune(self, dt, reps: int = 5):
+        a = self._dt(dt)
+        t, k, ms = C.c_int(), C.c_int(), C.c_float()
+        call("fit_batch_autotune", self._h, dptr(a), int(reps), C.byref(t), C.byref(k),
+             C.byref(ms))
+        return t.value, k.value, ms.value
+
+    def step(self, nsteps: int, dt, use_graph: bool = True):
+        a = self._dt(dt)
+        call("fit_batch_step", self._h, int(nsteps), dptr(a), 1 if use_graph else 0)

@@ -1,0 +1,389 @@
+// C-ABI of the batched leapfrog: descriptor tables, source tables, graph
+// capture/replay of S-step chunks (one launch per step of all grids) and the
+// batch autotuner.
+#include <algorithm>
+#include <cmath>
+#include <string>
+#include <vector>
+
+#include "fit_host.hpp"
+
+struct fit_batch {
+  std::vector<fit_grid*> grids;
+  int nb = 0;
+  bool f64 = false;
+  bool lossy_any = false;
+  hipStream_t user = nullptr;    // caller's stream
+  hipStream_t s = nullptr;       // private stream (graph capture needs a non-default stream)
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  void* desc = nullptr;          // device BatchGrid<T>[nb]
+  int* item_grid = nullptr;      // device, P entries
+  fit::BatchCtl* ctl = nullptr;  // device
+  void* src_tab = nullptr;       // device [nb][src_cap]
+  int64_t src_cap = 0;
+  int P = 0;
+  int ty = 8, kc = 0;            // kc = 0: whole columns
+  int steps_per_graph = 16;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int graph_S = 0;
+};
+
+namespace fit {
+
+static void batch_drop_graph(fit_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+  b->graph_S = 0;
+}
+
+// Build the item table and persistent grid size for the current tiling.
+static int batch_layout(fit_batch* b) {
+  std::vector<int> items;
+  for (int g = 0; g < b->nb; ++g) {
+    const Dims& d = b->grids[g]->d;
+    const int kc = b->kc > 0 ? std::min(b->kc, d.nz) : d.nz;
+    const Tiling t = make_tiling(d, b->ty, kc);
+    for (int64_t q = 0; q < t.blocks(); ++q) items.push_back(g);
+  }
+  b->P = (int)items.size();
+  dev_free(reinterpret_cast<void*&>(b->item_grid));
+  int rc = dev_alloc(reinterpret_cast<void**>(&b->item_grid), items.size() * sizeof(int), "item table");
+  if (rc) return rc;
+  hipError_t e = hipMemcpy(b->item_grid, items.data(), items.size() * sizeof(int),
+                           hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "item table upload");
+  // sets the dynamic-LDS attribute of the batch kernel for this tile height
+  (void)batch_blocks_per_cu(b->ty, b->f64 ? 8 : 4, b->lossy_any);
+  batch_drop_graph(b);
+  return FIT_OK;
+}
+
+// Fill and upload the per-grid descriptors for a call starting now.
+template <typename T>
+static int batch_desc(fit_batch* b, const double* dt, int64_t nsteps, bool with_src) {
+  std::vector<BatchGrid<T>> desc((size_t)b->nb);
+  if (with_src && nsteps > b->src_cap) {
+    dev_free(b->src_tab);
+    b->src_cap = 0;
+    int rc = dev_alloc(&b->src_tab, (size_t)b->nb * (size_t)nsteps * sizeof(T), "source table");
+    if (rc) return rc;
+    b->src_cap = nsteps;
+  }
+  std::vector<T> tab;
+  if (with_src) tab.assign((size_t)b->nb * (size_t)b->src_cap, T(0));
+  int off = 0;
+  for (int g = 0; g < b->nb; ++g) {
+    fit_grid* gr = b->grids[g];
+    BatchGrid<T>& D = desc[g];
+    D.e[0] = static_cast<T*>(gr->e);
+    D.e[1] = static_cast<T*>(gr->e_alt);
+    D.h[0] = static_cast<T*>(gr->h);
+    D.h[1] = static_cast<T*>(gr->h_alt);
+    D.eps = static_cast<const T*>(gr->eps);
+    D.sig = static_cast<const T*>(gr->sig);
+    D.d = gr->d;
+    const int kc = b->kc > 0 ? std::min(b->kc, gr->d.nz) : gr->d.nz;
+    D.t = make_tiling(gr->d, b->ty, kc);
+    for (int c = 0; c < 3; ++c) {
+      D.kb[c] = (T)(4.0 * dt[g] / gr->gedge[c]);
+      D.kd[c] = (T)(dt[g] * gr->gf2[c]);
+    }
+    D.hs = (T)(0.5 * dt[g]);
+    D.imu2 = (T)gr->imu_u + (T)gr->imu_u;
+    D.lossy = gr->lossy ? 1 : 0;
+    D.src_comp = gr->src_axis;
+    D.src_idx = gr->src_axis >= 0 ? gr->src_idx : -1;
+    D.src_tab = nullptr;
+    if (with_src && gr->src_axis >= 0) {
+      T* row = tab.data() + (size_t)g * b->src_cap;
+      for (int64_t s = 0; s < nsteps; ++s) row[s] = (T)source_value(gr, dt[g], gr->m + s);
+      D.src_tab = static_cast<const T*>(b->src_tab) + (size_t)g * b->src_cap;
+    }
+    D.par0 = 0;
+    D.ntiles = (int)D.t.blocks();
+    D.tile_off = off;
+    off += D.ntiles;
+  }
+  hipError_t e = hipSuccess;
+  if (with_src)
+    e = hipMemcpyAsync(b->src_tab, tab.data(), tab.size() * sizeof(T), hipMemcpyHostToDevice, b->s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b->desc, desc.data(), desc.size() * sizeof(BatchGrid<T>),
+                       hipMemcpyHostToDevice, b->s);
+  // the host vectors die at return: wait for the copies
+  if (e == hipSuccess) e = hipStreamSynchronize(b->s);
+  if (e != hipSuccess) return hip_fail(e, "batch descriptor upload");
+  return FIT_OK;
+}
+
+template <typename T>
+static BatchArgs<T> batch_args_host(fit_batch* b, int fixed) {
+  BatchArgs<T> a;
+  a.grids = static_cast<const BatchGrid<T>*>(b->desc);
+  a.item_grid = b->item_grid;
+  a.ctl = b->ctl;
+  a.nb = b->nb;
+  a.P = b->P;
+  a.ty = b->ty;
+  a.lossy_any = b->lossy_any ? 1 : 0;
+  a.fixed_parity = fixed;
+  return a;
+}
+
+template <typename T>
+static int batch_run(fit_batch* b, int64_t nsteps, const double* dt, int use_graph) {
+  int rc = batch_desc<T>(b, dt, nsteps, true);
+  if (rc) return rc;
+  const int S = std::max(1, b->steps_per_graph);
+  const int64_t chunks = use_graph ? nsteps / S : 0;
+  const int64_t rem = nsteps - chunks * S;
+  const BatchArgs<T> a = batch_args_host<T>(b, 0);
+  hipError_t e = launch_batch_set_base(b->ctl, 0, b->s);
+  if (e != hipSuccess) return hip_fail(e, "batch step counter");
+  if (chunks > 0) {
+    if (!b->exec || b->graph_S != S) {
+      batch_drop_graph(b);
+      e = hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+      hipError_t el = hipSuccess;
+      for (int q = 0; q < S && el == hipSuccess; ++q) el = launch_batch<T>(a, b->s);
+      e = hipStreamEndCapture(b->s, &b->graph);
+      if (el != hipSuccess) {
+        batch_drop_graph(b);
+        return hip_fail(el, "batch launch in capture");
+      }
+      if (e != hipSuccess) {
+        batch_drop_graph(b);
+        return hip_fail(e, "graph capture end");
+      }
+      e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+      if (e != hipSuccess) {
+        batch_drop_graph(b);
+        return hip_fail(e, "graph instantiate");
+      }
+      b->graph_S = S;
+    }
+    for (int64_t c = 0; c < chunks; ++c) {
+      e = hipGraphLaunch(b->exec, b->s);
+      if (e != hipSuccess) return hip_fail(e, "graph launch");
+    }
+  }
+  for (int64_t q = 0; q < rem; ++q) {
+    e = launch_batch<T>(a, b->s);
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+  }
+  for (int g = 0; g < b->nb; ++g) {
+    fit_grid* gr = b->grids[g];
+    if (nsteps & 1) {
+      std::swap(gr->e, gr->e_alt);
+      std::swap(gr->h, gr->h_alt);
+    }
+    gr->m += nsteps;
+    gr->smvp += 2 * nsteps;
+  }
+  return FIT_OK;
+}
+
+// Time `reps` single steps (every step reads the same state) for the current tiling.
+template <typename T>
+static int batch_time(fit_batch* b, const double* dt, int reps, float* ms) {
+  int rc = batch_desc<T>(b, dt, 1, true);
+  if (rc) return rc;
+  const BatchArgs<T> a = batch_args_host<T>(b, 1);
+  hipEvent_t ev[2];
+  (void)hipEventCreate(&ev[0]);
+  (void)hipEventCreate(&ev[1]);
+  hipError_t e = launch_batch<T>(a, b->s);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], b->s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_batch<T>(a, b->s);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], b->s);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, ev[0], ev[1]);
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (e != hipSuccess) return hip_fail(e, "batch autotune timing");
+  *ms /= (float)reps;
+  return FIT_OK;
+}
+
+}  // namespace fit
+
+using namespace fit;
+
+extern "C" {
+
+int fit_batch_destroy(fit_batch* b);
+
+int fit_batch_create(fit_grid* const* grids, int nb, void* stream, fit_batch** out) {
+  if (!grids || !out || nb < 1) return fail(FIT_E_INVALID, "need at least one grid");
+  *out = nullptr;
+  fit_batch* b = new (std::nothrow) fit_batch();
+  if (!b) return fail(FIT_E_OOM, "host allocation failed");
+  b->nb = nb;
+  b->user = static_cast<hipStream_t>(stream);
+  for (int g = 0; g < nb; ++g) {
+    fit_grid* gr = grids[g];
+    if (!gr) {
+      delete b;
+      return fail(FIT_E_INVALID, "null grid in batch");
+    }
+    for (int q = 0; q < g; ++q)
+      if (grids[q] == gr) {
+        delete b;
+        return fail(FIT_E_INVALID, "a grid appears twice in the batch");
+      }
+    if (g > 0 && gr->f64 != grids[0]->f64) {
+      delete b;
+      return fail(FIT_E_INVALID, "all grids of a batch need the same dtype");
+    }
+    if (!gr->mu_uniform) {
+      delete b;
+      return fail(FIT_E_INVALID, "batched grids need a uniform mu");
+    }
+    b->grids.push_back(gr);
+    b->lossy_any |= gr->lossy;
+  }
+  b->f64 = grids[0]->f64;
+  b->ty = b->f64 ? 4 : 8;
+
+  int rc = FIT_OK;
+  for (fit_grid* gr : b->grids)
+    if (!rc) rc = ensure_alt(gr);
+  hipError_t e = hipStreamCreateWithFlags(&b->s, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming);
+  if (e != hipSuccess && !rc) rc = hip_fail(e, "batch stream");
+  const size_t dsz = b->f64 ? sizeof(BatchGrid<double>) : sizeof(BatchGrid<float>);
+  if (!rc) rc = dev_alloc(&b->desc, dsz * nb, "batch descriptors");
+  if (!rc) rc = dev_alloc(reinterpret_cast<void**>(&b->ctl), sizeof(BatchCtl), "batch control");
+  if (!rc) {
+    e = hipMemset(b->ctl, 0, sizeof(BatchCtl));
+    if (e != hipSuccess) rc = hip_fail(e, "batch control clear");
+  }
+  if (!rc) rc = batch_layout(b);
+  if (rc) {
+    fit_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return FIT_OK;
+}
+
+int fit_batch_destroy(fit_batch* b) {
+  if (!b) return FIT_OK;
+  if (b->s) (void)hipStreamSynchronize(b->s);
+  batch_drop_graph(b);
+  dev_free(b->desc);
+  dev_free(reinterpret_cast<void*&>(b->item_grid));
+  dev_free(reinterpret_cast<void*&>(b->ctl));
+  dev_free(b->src_tab);
+  if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+  if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+  if (b->s) (void)hipStreamDestroy(b->s);
+  delete b;
+  return FIT_OK;
+}
+
+int fit_batch_set_tuning(fit_batch* b, int ty, int kc, int steps_per_graph) {
+  if (!b) return fail(FIT_E_INVALID, "null batch");
+  if (ty != 0) {
+    if (ty < 2 || ty > 16 || (ty & (ty - 1)) != 0)
+      return fail(FIT_E_INVALID, "ty must be a power of two in [2, 16]");
+    if (step_lds_bytes(ty, b->f64 ? 8 : 4, b->lossy_any) > 160 * 1024)
+      return fail(FIT_E_INVALID, "tile needs more LDS than a CU has");
+    b->ty = ty;
+  }
+  if (kc < 0) return fail(FIT_E_INVALID, "kc must be >= 0 (0: whole columns)");
+  b->kc = kc;
+  if (steps_per_graph < 0 || steps_per_graph > 1 << 20)
+    return fail(FIT_E_INVALID, "bad steps_per_graph");
+  if (steps_per_graph > 0) b->steps_per_graph = steps_per_graph;
+  return batch_layout(b);
+}
+
+int fit_batch_get_tuning(const fit_batch* b, int* ty, int* kc, int* steps_per_graph, int* nwg) {
+  if (!b) return fail(FIT_E_INVALID, "null batch");
+  if (ty) *ty = b->ty;
+  if (kc) *kc = b->kc;
+  if (steps_per_graph) *steps_per_graph = b->steps_per_graph;
+  if (nwg) *nwg = b->P;
+  return FIT_OK;
+}
+
+static int batch_check_dt(fit_batch* b, const double* dt) {
+  if (!dt) return fail(FIT_E_INVALID, "dt array is null");
+  for (int g = 0; g < b->nb; ++g) {
+    if (int rc = check_dt(b->grids[g], dt[g])) return rc;
+    if (b->grids[g]->probe.on)
+      return fail(FIT_E_STATE, "batched steps do not accumulate a probe objective; clear the probe");
+  }
+  return FIT_OK;
+}
+
+// join: the private stream waits for the caller's stream, and vice versa at the end
+static int batch_enter(fit_batch* b) {
+  hipError_t e = hipEventRecord(b->ev_in, b->user);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->s, b->ev_in, 0);
+  if (e != hipSuccess) return hip_fail(e, "batch stream join");
+  return FIT_OK;
+}
+static int batch_leave(fit_batch* b) {
+  hipError_t e = hipEventRecord(b->ev_out, b->s);
+  if (e == hipSuccess) e = hipStreamWaitEvent(b->user, b->ev_out, 0);
+  if (e != hipSuccess) return hip_fail(e, "batch stream join");
+  return FIT_OK;
+}
+
+int fit_batch_step(fit_batch* b, int64_t nsteps, const double* dt, int use_graph) {
+  if (!b) return fail(FIT_E_INVALID, "null batch");
+  if (nsteps < 0) return fail(FIT_E_INVALID, "nsteps must be >= 0");
+  if (int rc = batch_check_dt(b, dt)) return rc;
+  if (nsteps == 0) return FIT_OK;
+  if (int rc = batch_enter(b)) return rc;
+  int rc = b->f64 ? batch_run<double>(b, nsteps, dt, use_graph) : batch_run<float>(b, nsteps, dt, use_graph);
+  int rc2 = batch_leave(b);
+  return rc ? rc : rc2;
+}
+
+int fit_batch_autotune(fit_batch* b, const double* dt, int reps, int* ty, int* kc, float* ms_best) {
+  if (!b) return fail(FIT_E_INVALID, "null batch");
+  if (reps < 1 || reps > 1000) return fail(FIT_E_INVALID, "reps must be in [1, 1000]");
+  if (int rc = batch_check_dt(b, dt)) return rc;
+  if (int rc = batch_enter(b)) return rc;
+  const int tys32[3] = {4, 8, 16}, tys64[3] = {2, 4, 8};
+  const int kcs[3] = {0, 48, 24};
+  float best = 1e30f;
+  int bty = b->ty, bkc = b->kc;
+  int rc = FIT_OK;
+  for (int a = 0; a < 3 && !rc; ++a) {
+    const int t = b->f64 ? tys64[a] : tys32[a];
+    if (step_lds_bytes(t, b->f64 ? 8 : 4, b->lossy_any) > 160 * 1024) continue;
+    for (int q = 0; q < 3 && !rc; ++q) {
+      b->ty = t;
+      b->kc = kcs[q];
+      rc = batch_layout(b);
+      float ms = 0.f;
+      if (!rc) rc = b->f64 ? batch_time<double>(b, dt, reps, &ms) : batch_time<float>(b, dt, reps, &ms);
+      if (!rc && ms < best) {
+        best = ms;
+        bty = t;
+        bkc = kcs[q];
+      }
+    }
+  }
+  b->ty = bty;
+  b->kc = bkc;
+  int rc2 = batch_layout(b);
+  int rc3 = batch_leave(b);
+  if (rc) return rc;
+  if (rc2) return rc2;
+  if (ty) *ty = bty;
+  if (kc) *kc = bkc;
+  if (ms_best) *ms_best = best;
+  return rc3;
+}
+
+}  // extern "C"

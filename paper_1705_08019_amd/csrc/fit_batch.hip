@@ -1,0 +1,115 @@
+// Batched leapfrog: many independent grids of uneven size, each with its own
+// materials, source and dt, advanced together (the paper's independent
+// leapfrog runs of Sec. III / Alg. 1 form such a batch).
+//
+// One launch covers one step of EVERY grid: workgroup r of the launch runs
+// item r of the step's item table, i.e. one fused-step tile (the tile body of
+// fit_step_tile.hpp) of one grid.  Consecutive steps are ordered by the
+// kernel boundary alone: no workgroup ever waits on another, and no atomics
+// are used.  The index of the step within a call lives in device memory and
+// is advanced by a one-thread kernel after every step, so a captured chain of
+// S (step, advance) launches can be replayed as a hipGraph.
+#include "fit_step_tile.hpp"
+
+namespace fit {
+
+__global__ void k_batch_set_base(BatchCtl* ctl, int64_t base) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->step_base = base;
+    ctl->error = 0;
+  }
+}
+
+__global__ void k_batch_advance(BatchCtl* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->step_base += 1;
+}
+
+template <typename T>
+__device__ __forceinline__ void batch_args(const BatchGrid<T>& G, int p, T src, SArgs<T>& a) {
+  const int64_t n = G.d.n;
+  for (int c = 0; c < 3; ++c) {
+    a.e0[c] = G.e[p] + c * n;
+    a.h0[c] = G.h[p] + c * n;
+    a.e1[c] = G.e[1 - p] + c * n;
+    a.h1[c] = G.h[1 - p] + c * n;
+    a.kb[c] = G.kb[c];
+    a.kd[c] = G.kd[c];
+    a.ge[c] = 0.0;
+    a.gf2[c] = 0.0;
+  }
+  a.eps = G.eps;
+  a.sig = G.sig;
+  a.d = G.d;
+  a.t = G.t;
+  a.hs = G.hs;
+  a.imu2 = G.imu2;
+  a.src_comp = G.src_comp;
+  a.src_idx = G.src_idx;
+  a.src_val = src;
+  a.src_val_d = 0.0;
+  a.probe.on = 0;
+  a.part = nullptr;
+}
+
+// One step of every grid: blockIdx.x = item within the step.
+template <typename T>
+__global__ __launch_bounds__(1024) void k_batch(BatchArgs<T> B) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const int r = (int)blockIdx.x;
+  const int g = B.item_grid[r];
+  const BatchGrid<T>& G = B.grids[g];
+  const int t = r - G.tile_off;
+  const int64_t sg = B.fixed_parity ? 0 : B.ctl->step_base;   // step index within the call
+  const int p = (int)((G.par0 + sg) & 1);
+  SArgs<T> a;
+  batch_args<T>(G, p, G.src_tab ? G.src_tab[sg] : T(0), a);
+  const int tx = t % G.t.ntx;
+  const int rr = t / G.t.ntx;
+  const int tyi = rr % G.t.nty;
+  const int kz = rr / G.t.nty;
+  if (G.lossy)
+    step_tile<T, true, false, false>(a, tx, tyi, kz, sm, nullptr);
+  else
+    step_tile<T, false, false, false>(a, tx, tyi, kz, sm, nullptr);
+}
+
+template <typename T>
+static int batch_occupancy(int ty, size_t lds) {
+  int nb = 0;
+  if (lds > 64 * 1024)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<T>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_batch<T>),
+                                                   64 * ty, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
+int batch_blocks_per_cu(int ty, size_t esz, bool lossy) {
+  const size_t lds = step_lds_bytes(ty, esz, lossy);
+  return esz == 8 ? batch_occupancy<double>(ty, lds) : batch_occupancy<float>(ty, lds);
+}
+
+// One step of every grid, then the step counter (fixed_parity: no counter).
+template <typename T>
+hipError_t launch_batch(const BatchArgs<T>& b, hipStream_t s) {
+  const size_t lds = step_lds_bytes(b.ty, sizeof(T), b.lossy_any != 0);
+  hipLaunchKernelGGL(k_batch<T>, dim3((unsigned)b.P), dim3(64, b.ty), lds, s, b);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || b.fixed_parity) return e;
+  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, b.ctl);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_set_base(BatchCtl* ctl, int64_t base, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_set_base, dim3(1), dim3(64), 0, s, ctl, base);
+  return hipGetLastError();
+}
+
+template hipError_t launch_batch<float>(const BatchArgs<float>&, hipStream_t);
+template hipError_t launch_batch<double>(const BatchArgs<double>&, hipStream_t);
+
+}  // namespace fit

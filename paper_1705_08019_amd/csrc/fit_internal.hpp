@@ -149,6 +149,51 @@ hipError_t launch_adjoint_gather(const double* gMe, const double* gMs, const Dim
                                  const double gq[3], double eps0, double* deps, double* dsig,
                                  hipStream_t s);
 
+// Batched leapfrog, one launch per step of all grids (fit_batch.hip).
+struct BatchCtl {
+  int64_t step_base;   // index of the next step within the current call
+  int error;
+  int pad;
+};
+
+template <typename T>
+struct BatchGrid {
+  T* e[2];             // the two state buffer sets
+  T* h[2];
+  const T* eps;
+  const T* sig;
+  Dims d;
+  Tiling t;
+  T kb[3];
+  T hs;
+  T kd[3];
+  T imu2;
+  int lossy;
+  int src_comp;
+  int64_t src_idx;
+  const T* src_tab;    // source current of each step of the call, or null
+  int par0;            // buffer set holding the state at the start of the call
+  int ntiles;          // tiles per step
+  int tile_off;        // offset of this grid's tiles within one step's items
+};
+
+template <typename T>
+struct BatchArgs {
+  const BatchGrid<T>* grids;
+  const int* item_grid;   // grid of each item of a step (P entries)
+  BatchCtl* ctl;
+  int nb;
+  int P;                  // items (workgroups) per step
+  int ty;
+  int lossy_any;          // LDS sized for the lossy tile
+  int fixed_parity;       // autotuning: read par0, step index 0, no counter
+};
+
+int batch_blocks_per_cu(int ty, size_t esz, bool lossy);
+template <typename T>
+hipError_t launch_batch(const BatchArgs<T>& b, hipStream_t s);
+hipError_t launch_batch_set_base(BatchCtl* ctl, int64_t base, hipStream_t s);
+
 // Launch wrappers (fit_kernels.hip).  Return hipError_t of the launch.
 template <typename T>
 hipError_t launch_epass(const EArgs<T>& a, bool lossy, bool energy, bool probe, hipStream_t s);

@@ -1,0 +1,284 @@
+// Tile body of the fused single-pass leapfrog step, shared by the per-grid
+// kernel (fit_step.hip) and the persistent batched kernel (fit_batch.hip).
+// See fit_step.hip for the algorithm.
+#pragma once
+
+#include "fit_internal.hpp"
+#include "fit_point.hpp"
+
+namespace fit {
+
+__device__ __forceinline__ void nadd_s(double& s, double& c, double x) {
+  const double t = s + x;
+  c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
+  s = t;
+}
+
+// Ring entries of one plane staged per thread (RP <= 3 * 64 * ty for ty >= 2).
+constexpr int kRingPerThread = 3;
+
+// One 64 x ty column tile of one z-chunk: tile coordinates (tx, tyi, kz);
+// sm = dynamic LDS of step_lds_bytes(); part = this tile's partial-sum row
+// (ENERGY or PROBE only).
+template <typename T, bool LOSSY, bool ENERGY, bool PROBE>
+__device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, int kz, T* sm,
+                                          double* part) {
+  const Dims d = A.d;
+  const int TY = A.t.ty;
+  const int RW = 66, RP = RW * (TY + 2);
+  const int EW = 65, EP = EW * (TY + 1);
+  T* hL = sm;                          // [3][3][RP]  h^(m+1/2), planes k, k-1, k-2 rotating
+  T* cL = hL + 9 * RP;                 // [3][RP]     eps0 eps_r
+  T* sL = cL + 3 * RP;                 // [3][RP]     sigma (lossy only)
+  T* nL = sL + (LOSSY ? 3 * RP : 0);   // [2][3][EP]  e^(m+1), planes k, k-1
+
+  const int i0 = tx * 64, j0 = tyi * TY;
+  const int k0 = kz * A.t.kc;
+  const int k1 = min(k0 + A.t.kc, d.nz);
+  const int lx = (int)threadIdx.x, ly = (int)threadIdx.y;
+  const int tid = ly * 64 + lx, nthr = 64 * TY;
+  const int i = i0 + lx, j = j0 + ly;
+  const bool own = (i < d.nx) && (j < d.ny);
+  const int64_t sx = d.sx, sxy = d.sxy;
+
+  // one extra e^(m+1) point per thread for the +y halo row / +x halo column
+  const int nhalo = 64 + TY + 1;
+  const bool has_h = tid < nhalo;
+  const int hx_ = tid < 64 ? tid : 64;
+  const int hy_ = tid < 64 ? TY : tid - 64;
+  const int hi = i0 + hx_, hj = j0 + hy_;
+  const bool hvalid = has_h && hi < d.nx && hj < d.ny;
+
+  auto ring = [&](int x, int y) { return (y + 1) * RW + (x + 1); };
+  auto ext = [&](int x, int y) { return y * EW + x; };
+
+  // ---- register staging of one plane: ring entries q = tid + r * nthr
+  T pre[kRingPerThread][5];
+  T eo[3], ho[3];
+  auto fetch = [&](int k) {
+#pragma unroll
+    for (int r = 0; r < kRingPerThread; ++r) {
+      const int q = tid + r * nthr;
+      const int gx = i0 + (q % RW) - 1, gy = j0 + (q / RW) - 1;
+      const bool in = q < RP && k >= 0 && k < d.nz && gx >= 0 && gx < d.nx && gy >= 0 &&
+                      gy < d.ny;
+      const int64_t g = gx + sx * gy + sxy * (int64_t)k;
+      pre[r][0] = in ? A.h0[0][g] : T(0);
+      pre[r][1] = in ? A.h0[1][g] : T(0);
+      pre[r][2] = in ? A.h0[2][g] : T(0);
+      pre[r][3] = in ? A.eps[g] : T(0);
+      pre[r][4] = (LOSSY && in) ? A.sig[g] : T(0);
+    }
+    const bool plane = k >= 0 && k < d.nz;
+    const int64_t g = i + sx * j + sxy * (int64_t)k;
+    const int64_t gh = hi + sx * hj + sxy * (int64_t)k;
+    const bool lo = plane && own, lh = plane && hvalid;
+    eo[0] = lo ? A.e0[0][g] : T(0);
+    eo[1] = lo ? A.e0[1][g] : T(0);
+    eo[2] = lo ? A.e0[2][g] : T(0);
+    ho[0] = lh ? A.e0[0][gh] : T(0);
+    ho[1] = lh ? A.e0[1][gh] : T(0);
+    ho[2] = lh ? A.e0[2][gh] : T(0);
+  };
+  auto stage = [&](int buf) {
+#pragma unroll
+    for (int r = 0; r < kRingPerThread; ++r) {
+      const int q = tid + r * nthr;
+      if (q < RP) {
+        hL[(buf * 3 + 0) * RP + q] = pre[r][0];
+        hL[(buf * 3 + 1) * RP + q] = pre[r][1];
+        hL[(buf * 3 + 2) * RP + q] = pre[r][2];
+        cL[buf * RP + q] = pre[r][3];
+        if (LOSSY) sL[buf * RP + q] = pre[r][4];
+      }
+    }
+  };
+
+  // e^(m+1) at ext point (x, y) of plane k; p = ring buffer of plane k, q of k-1.
+  auto enew = [&](int x, int y, int k, int p, int q, T exo, T eyo, T ezo, bool valid, T& exn,
+                  T& eyn, T& ezn, T& E4x, T& E4y, T& E4z, T& S4x, T& S4y, T& S4z) {
+    const int r = ring(x, y), rim = ring(x - 1, y), rjm = ring(x, y - 1), rijm = ring(x - 1, y - 1);
+    const T* hp = hL + p * 3 * RP;
+    const T* hq = hL + q * 3 * RP;
+    const T* cp = cL + p * RP;
+    const T* cq = cL + q * RP;
+    const T c = cp[r], c_im = cp[rim], c_jm = cp[rjm], c_ijm = cp[rijm];
+    const T Sx = c + c_im, Sy = c + c_jm, Sxj = c_jm + c_ijm;
+    const T pc = cq[r];
+    const T sye = pc + cq[rjm], sxe = pc + cq[rim];
+    E4x = sye + Sy;
+    E4y = sxe + Sx;
+    E4z = Sx + Sxj;
+    S4x = S4y = S4z = T(0);
+    if (LOSSY) {
+      const T* sp = sL + p * RP;
+      const T* sq = sL + q * RP;
+      const T s = sp[r], s_im = sp[rim], s_jm = sp[rjm], s_ijm = sp[rijm];
+      const T Sxs = s + s_im, Sys = s + s_jm;
+      const T ps = sq[r];
+      const T sys = ps + sq[rjm], sxs = ps + sq[rim];
+      S4x = sys + Sys;
+      S4y = sxs + Sxs;
+      S4z = Sxs + (s_jm + s_ijm);
+    }
+    const int gi = i0 + x, gj = j0 + y;
+    const int64_t g = gi + sx * gj + sxy * (int64_t)k;
+    T jx = 0, jy = 0, jz = 0;
+    if (valid && g == A.src_idx) {
+      if (A.src_comp == 0) jx = A.src_val;
+      if (A.src_comp == 1) jy = A.src_val;
+      if (A.src_comp == 2) jz = A.src_val;
+    }
+    // keep denominators of out-of-grid points finite (their result is discarded)
+    if (!valid) {
+      E4x = E4y = E4z = T(1);
+    }
+    e_point<T, LOSSY>(hp[r], hp[RP + r], hp[2 * RP + r], hq[r], hq[RP + r], hp[rjm],
+                      hp[RP + rim], hp[2 * RP + rjm], hp[2 * RP + rim], E4x, E4y, E4z, S4x, S4y,
+                      S4z, exo, eyo, ezo, jx, jy, jz, valid && gj > 0 && k > 0,
+                      valid && gi > 0 && k > 0, valid && gi > 0 && gj > 0, A.kb[0], A.kb[1],
+                      A.kb[2], A.hs, exn, eyn, ezn);
+  };
+
+  double acc[kPartTerms] = {0};
+  double cmp[kPartTerms] = {0};
+  bool pi_x = false, pi_yz = false, pj_y = false, pj_xz = false;
+  if (PROBE) {
+    pi_x = i >= A.probe.lo[0] && i + 1 <= A.probe.hi[0];
+    pi_yz = i >= A.probe.lo[0] && i <= A.probe.hi[0];
+    pj_y = j >= A.probe.lo[1] && j + 1 <= A.probe.hi[1];
+    pj_xz = j >= A.probe.lo[1] && j <= A.probe.hi[1];
+  }
+
+  // prologue: plane k0 - 1 (zeros below the grid) into ring buffer 2, prefetch plane k0
+  int bp = 2;          // ring buffer of plane k - 1
+  int bc = 0;          // ring buffer of plane k
+  fetch(k0 - 1);
+  stage(bp);
+  fetch(k0);
+
+  for (int k = k0; k <= k1; ++k) {
+    const bool plane = k < d.nz;
+    const int ep = k & 1;          // ext buffer of plane k (k-1 in ep ^ 1)
+    // plane k: registers -> LDS; keep e^m of the own / halo point
+    stage(bc);
+    const T eo0 = eo[0], eo1 = eo[1], eo2 = eo[2];
+    const T ho0 = ho[0], ho1 = ho[1], ho2 = ho[2];
+    // prefetch plane k+1 (in flight during the compute below)
+    if (k + 1 <= k1) fetch(k + 1);
+    __syncthreads();
+    T* np_ = nL + ep * 3 * EP;
+    const int64_t g = i + sx * j + sxy * (int64_t)k;
+    {
+      T exn = 0, eyn = 0, ezn = 0, E4x, E4y, E4z, S4x, S4y, S4z;
+      if (plane) enew(lx, ly, k, bc, bp, eo0, eo1, eo2, own, exn, eyn, ezn, E4x, E4y, E4z, S4x,
+                      S4y, S4z);
+      const int e = ext(lx, ly);
+      np_[e] = exn;
+      np_[EP + e] = eyn;
+      np_[2 * EP + e] = ezn;
+      if (plane && own && k < k1) {
+        A.e1[0][g] = exn;
+        A.e1[1][g] = eyn;
+        A.e1[2][g] = ezn;
+        if (ENERGY) {
+          const double mx = A.ge[0] * (double)E4x, my = A.ge[1] * (double)E4y,
+                       mz = A.ge[2] * (double)E4z;
+          const double ox = eo0, oy = eo1, oz = eo2, nx_ = exn, ny_ = eyn, nz_ = ezn;
+          nadd_s(acc[PE_EE_MM], cmp[PE_EE_MM], mx * ox * ox + my * oy * oy + mz * oz * oz);
+          nadd_s(acc[PE_EE_MM1], cmp[PE_EE_MM1], mx * ox * nx_ + my * oy * ny_ + mz * oz * nz_);
+          nadd_s(acc[PE_EE_M1M1], cmp[PE_EE_M1M1],
+                 mx * nx_ * nx_ + my * ny_ * ny_ + mz * nz_ * nz_);
+          if (LOSSY) {
+            const double bx = 0.5 * (ox + nx_), by = 0.5 * (oy + ny_), bz = 0.5 * (oz + nz_);
+            nadd_s(acc[PE_LOSS], cmp[PE_LOSS],
+                   A.ge[0] * (double)S4x * bx * bx + A.ge[1] * (double)S4y * by * by +
+                       A.ge[2] * (double)S4z * bz * bz);
+          }
+          if (g == A.src_idx) {
+            const double bs = A.src_comp == 0 ? 0.5 * (ox + nx_)
+                            : A.src_comp == 1 ? 0.5 * (oy + ny_) : 0.5 * (oz + nz_);
+            nadd_s(acc[PE_SRC], cmp[PE_SRC], bs * A.src_val_d);
+          }
+        }
+        if (PROBE) {
+          const bool kx = k >= A.probe.lo[2] && k <= A.probe.hi[2];
+          const bool kz_ = k >= A.probe.lo[2] && k + 1 <= A.probe.hi[2];
+          const double nx_ = exn, ny_ = eyn, nz_ = ezn;
+          double pv = 0.0;
+          if (pi_x && pj_xz && kx) pv += A.ge[0] * (double)E4x * nx_ * nx_;
+          if (pi_yz && pj_y && kx) pv += A.ge[1] * (double)E4y * ny_ * ny_;
+          if (pi_yz && pj_xz && kz_) pv += A.ge[2] * (double)E4z * nz_ * nz_;
+          nadd_s(acc[PE_PROBE], cmp[PE_PROBE], pv);
+        }
+      }
+    }
+    if (has_h) {
+      T exn = 0, eyn = 0, ezn = 0, E4x, E4y, E4z, S4x, S4y, S4z;
+      if (plane) enew(hx_, hy_, k, bc, bp, ho0, ho1, ho2, hvalid, exn, eyn, ezn, E4x, E4y, E4z,
+                      S4x, S4y, S4z);
+      const int e = ext(hx_, hy_);
+      np_[e] = exn;
+      np_[EP + e] = eyn;
+      np_[2 * EP + e] = ezn;
+    }
+    __syncthreads();
+    // h^(m+3/2) of plane k-1 from e^(m+1) of planes k-1 (nq) and k (np_)
+    const int km = k - 1;
+    if (k > k0 && own) {
+      const T* nq = nL + (ep ^ 1) * 3 * EP;
+      const int e = ext(lx, ly), e_in = ext(lx + 1, ly), e_jn = ext(lx, ly + 1);
+      const int r = ring(lx, ly);
+      const T* hq = hL + bp * 3 * RP;
+      const T hxo = hq[r], hyo = hq[RP + r], hzo = hq[2 * RP + r];
+      T hxn, hyn, hzn;
+      h_point<T>(nq[e], nq[EP + e], nq[2 * EP + e], np_[e], np_[EP + e], nq[2 * EP + e_jn],
+                 nq[2 * EP + e_in], nq[EP + e_in], nq[e_jn], hxo, hyo, hzo, A.imu2, A.imu2,
+                 A.imu2, i > 0, j > 0, km > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
+      const int64_t gm = i + sx * j + sxy * (int64_t)km;
+      A.h1[0][gm] = hxn;
+      A.h1[1][gm] = hyn;
+      A.h1[2][gm] = hzn;
+      if (ENERGY) {
+        const double wx = i > 0 ? 1.0 / (A.gf2[0] * (double)A.imu2) : 0.0;
+        const double wy = j > 0 ? 1.0 / (A.gf2[1] * (double)A.imu2) : 0.0;
+        const double wz = km > 0 ? 1.0 / (A.gf2[2] * (double)A.imu2) : 0.0;
+        const double ox = hxo, oy = hyo, oz = hzo, nx_ = hxn, ny_ = hyn, nz_ = hzn;
+        nadd_s(acc[PS_HH_CC], cmp[PS_HH_CC], wx * ox * ox + wy * oy * oy + wz * oz * oz);
+        nadd_s(acc[PS_HH_CN], cmp[PS_HH_CN], wx * ox * nx_ + wy * oy * ny_ + wz * oz * nz_);
+        nadd_s(acc[PS_HH_NN], cmp[PS_HH_NN], wx * nx_ * nx_ + wy * ny_ * ny_ + wz * nz_ * nz_);
+      }
+    }
+    // rotate ring buffers: plane k becomes k-1; the oldest buffer takes k+1
+    const int nb_ = 3 - bc - bp;
+    bp = bc;
+    bc = nb_;
+  }
+
+  if (ENERGY || PROBE) {
+    // block sum of the 9 terms, fixed order
+    __shared__ double red[16][9];
+    double v[9];
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+      double x = acc[t] + cmp[t];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+      v[t] = x;
+    }
+    __syncthreads();
+    if (lx == 0) {
+#pragma unroll
+      for (int t = 0; t < 9; ++t) red[ly][t] = v[t];
+    }
+    __syncthreads();
+    if (ly == 0 && lx < 9) {
+      double s = 0.0;
+      for (int w = 0; w < TY; ++w) s += red[w][lx];
+      part[lx] = s;
+    }
+  }
+}
+
+
+}  // namespace fit

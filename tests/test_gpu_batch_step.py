@@ -1,0 +1,125 @@
+"""Batched leapfrog (one launch per step of all grids, graph-captured chunks):
+every grid of a batch must equal (bitwise) the plain single-grid run of that
+grid, through direct launches and graph replays alike."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from fit_workloads import c4, c4_small, lossy_slab
+
+pytestmark = pytest.mark.gpu
+
+
+def _make(specs, dtype, lossy_every=0):
+    from paper_1705_08019_amd import FitGrid
+    grids, dts = [], []
+    rng = np.random.default_rng(7)
+    for n, s in enumerate(specs):
+        g = FitGrid(s.nx, s.ny, s.nz, dtype)
+        sig = lossy_slab(s.nx, s.ny, s.nz, 2, 0.05) if (lossy_every and n % lossy_every == 0) else None
+        g.set_materials(s.eps_r, None, sig)
+        dt = 0.9 * g.cfl_dt() * float(rng.uniform(0.8, 1.0))
+        src = s.source
+        g.set_source(src["axis"], src["i"], src["j"], src["k"], src["i_max"],
+                     src["sigma_t_steps"] * dt)
+        grids.append(g)
+        dts.append(dt)
+    return grids, np.array(dts)
+
+
+def _fields(grids):
+    return [g.get_fields() for g in grids]
+
+
+def _assert_equal(fa, fb):
+    for n, (a, b) in enumerate(zip(fa, fb)):
+        assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1]), f"grid {n} differs"
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_direct_equals_plain(dtype):
+    from paper_1705_08019_amd import FitBatch
+    specs = c4_small(count=7, nsteps=0)
+    gb, dts = _make(specs, dtype, lossy_every=3)
+    gp, _ = _make(specs, dtype, lossy_every=3)
+    b = FitBatch(gb)
+    b.step(50, dts, use_graph=False)
+    for g, dt in zip(gp, dts):
+        g.step(50, dt)
+    _assert_equal(_fields(gb), _fields(gp))
+    assert all(g.step_index == 50 for g in gb)
+    b.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_graph_equals_plain(dtype):
+    from paper_1705_08019_amd import FitBatch
+    specs = c4_small(count=7, nsteps=0)
+    gb, dts = _make(specs, dtype, lossy_every=3)
+    gp, _ = _make(specs, dtype, lossy_every=3)
+    b = FitBatch(gb)
+    b.set_tuning(0, 0, 16)
+    b.step(200, dts)                        # 12 graph replays + 8 direct launches
+    for g, dt in zip(gp, dts):
+        g.step(200, dt)
+    _assert_equal(_fields(gb), _fields(gp))
+    assert all(g.step_index == 200 for g in gb)
+    # direct launches give the same, and tiles split in z too
+    b.set_tuning(4 if dtype == "f32" else 2, 5, 0)
+    b.step(37, dts, use_graph=False)
+    for g, dt in zip(gp, dts):
+        g.step(37, dt)
+    _assert_equal(_fields(gb), _fields(gp))
+    b.close()
+
+
+def test_graph_replays_interleaved_with_eager_work():
+    from paper_1705_08019_amd import FitBatch
+    specs = c4_small(count=5, nsteps=0)
+    gb, dts = _make(specs, "f32")
+    gp, _ = _make(specs, "f32")
+    b = FitBatch(gb)
+    b.set_tuning(0, 0, 8)
+    for rep in range(4):
+        b.step(8, dts)                      # exactly one replay of the captured graph
+        for g, dt in zip(gp, dts):
+            g.step(8, dt)
+        junk = torch.randn(1 << 20, device="cuda").sum()   # unrelated eager work
+        torch.cuda.synchronize()
+        _assert_equal(_fields(gb), _fields(gp))
+        assert float(junk) == float(junk)
+    b.close()
+
+
+def test_batch_autotune_keeps_state():
+    from paper_1705_08019_amd import FitBatch
+    specs = c4_small(count=4, nsteps=0)
+    gb, dts = _make(specs, "f32")
+    b = FitBatch(gb)
+    b.step(10, dts)
+    before = _fields(gb)
+    ty, kc, ms = b.autotune(dts, reps=2)
+    assert ms > 0 and b.get_tuning()[:2] == (ty, kc)
+    _assert_equal(_fields(gb), before)
+    assert all(g.step_index == 10 for g in gb)
+    b.close()
+
+
+def test_batch_full_workload_equals_plain():
+    """64 grids of 32..96 cells per axis, 4000 steps (the batched workload),
+    graph replays of 16 steps: every grid equals its plain single-grid run."""
+    from paper_1705_08019_amd import FitBatch
+    specs = c4()
+    gb, dts = _make(specs, "f32")
+    b = FitBatch(gb)
+    b.autotune(dts, reps=2)
+    b.step(specs[0].nsteps, dts)
+    fb = _fields(gb)
+    b.close()
+    for g in gb:
+        g.close()
+    gp, _ = _make(specs, "f32")
+    for g, dt in zip(gp, dts):
+        g.step(specs[0].nsteps, dt)
+    _assert_equal(fb, _fields(gp))
