@@ -40,7 +40,7 @@ B_HPASS = 4 * (3 + 3 + 3)       # 36
 B_STEP = B_EPASS + B_HPASS      # 80
 
 
-KERNEL_SOURCES = {"step": ("fit_step.hip", "fit_point.hpp"),
+KERNEL_SOURCES = {"step": ("fit_step.hip", "fit_step_tile.hpp", "fit_point.hpp"),
                   "epass": ("fit_kernels.hip", "fit_point.hpp"),
                   "hpass": ("fit_kernels.hip", "fit_point.hpp")}
 
@@ -163,6 +163,125 @@ def measure_copy(nbytes: int = 1 << 30, reps: int = 5) -> float:
         best = min(best, ev[0].elapsed_time(ev[1]))
     del src, dst
     return round(2 * nbytes / (best / 1e3) / 1e9, 1)
+
+
+def form_batched(plain_steps: int = 400):
+    """64 FP32 grids, per-axis sizes ~ U{32..96}, 8 dielectric blocks each,
+    lossless, random interior source each, 4000 steps: batched launches
+    (graph-captured, autotuned) against plain per-grid launches of the same
+    grids (plain timed over `plain_steps` steps)."""
+    import torch
+    from fit_workloads import c4
+    from paper_1705_08019_amd import FitGrid, FitBatch
+    specs = c4()
+    nsteps = specs[0].nsteps
+
+    def make():
+        grids, dts = [], []
+        for sp in specs:
+            g = FitGrid(sp.nx, sp.ny, sp.nz, "f32")
+            g.set_materials(sp.eps_r, None, None)
+            dt = 0.9 * g.cfl_dt()
+            s = sp.source
+            g.set_source(s["axis"], s["i"], s["j"], s["k"], s["i_max"], s["sigma_t_steps"] * dt)
+            grids.append(g)
+            dts.append(dt)
+        return grids, np.array(dts)
+
+    cells = sum(sp.cells for sp in specs)
+    grids, dts = make()
+    b = FitBatch(grids)
+    ty, kc, _ = b.autotune(dts, reps=5)
+    b.step(32, dts)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    b.step(nsteps, dts)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms_b = ev[0].elapsed_time(ev[1])
+    b.close()
+    for g in grids:
+        g.close()
+    grids, dts = make()
+    for g, dt in zip(grids, dts):
+        g.autotune(dt, reps=3)
+        g.step(4, dt)
+    torch.cuda.synchronize()
+    ev[0].record()
+    for g, dt in zip(grids, dts):
+        g.step(plain_steps, dt)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms_p = ev[0].elapsed_time(ev[1])
+    for g in grids:
+        g.close()
+    gb = cells * nsteps / (ms_b / 1e3) / 1e9
+    gp = cells * plain_steps / (ms_p / 1e3) / 1e9
+    return {"workload": "c4: 64 FP32 grids, sizes ~U{32..96}^3, 8 blocks each, 4000 steps",
+            "cells_total": cells, "steps": nsteps, "Gcell_updates_per_s": round(gb, 3),
+            "alg_GBs": round(B_STEP * gb, 1), "frac": round(B_STEP * gb / PEAK_HBM_GBS, 4),
+            "plain_per_grid_Gcell_updates_per_s": round(gp, 3),
+            "plain_steps_timed": plain_steps, "batched_over_plain": round(gb / gp, 3),
+            "tile": [64, ty, kc], "launch": "one launch per step of all grids, hipGraph chunks of 16"}
+
+
+def form_adjoint():
+    """96^3 FP32, materials as the 128^3 workload, 4096 steps, checkpoints
+    every 64, probe [64, 80]^3: forward (with checkpoints) and backward
+    (segment recompute + reverse sweep) throughput."""
+    import torch
+    from fit_workloads import c5
+    from paper_1705_08019_amd import ProbeProblem, probe_energy
+    sp = c5()
+    box = sp.probe
+    prob = ProbeProblem(nx=sp.nx, ny=sp.ny, nz=sp.nz, nsteps=sp.nsteps,
+                        probe_lo=tuple(x[0] for x in box), probe_hi=tuple(x[1] for x in box),
+                        dtype="f32", checkpoint_every=sp.checkpoint_every, source=sp.source)
+    eps = torch.tensor(sp.eps_r, requires_grad=True)
+    sig = torch.tensor(sp.sigma, requires_grad=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    J = probe_energy(eps, sig, prob)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    cs = sp.cells * sp.nsteps
+    fwd = cs / (t1 - t0) / 1e9
+    bwd = cs / (t2 - t1) / 1e9
+    return {"workload": "c5: 96^3 FP32, 4096 steps, checkpoints every 64, probe 16^3",
+            "forward_Gcell_steps_per_s": round(fwd, 3), "adjoint_Gcell_steps_per_s": round(bwd, 3),
+            "adjoint_over_forward": round(bwd / fwd, 3), "forward_s": round(t1 - t0, 4),
+            "backward_s": round(t2 - t1, 4), "J": float(J),
+            "note": "wall time incl. Python checkpoint bookkeeping; backward = recompute + reverse"}
+
+
+def form_gram(K: int = 64, reps: int = 5):
+    """Gram matrix of K FP32 snapshots of the 128^3 e-field (6.29 M rows):
+    FP64 MFMA TFLOP/s against the FP64 matrix peak."""
+    import torch
+    from fit_workloads import c2
+    from paper_1705_08019_amd import FitGrid
+    sp = c2()
+    g = FitGrid(sp.nx, sp.ny, sp.nz, "f32")
+    g.set_materials(sp.eps_r, None, sp.sigma)
+    X = torch.randn((K, 3 * sp.cells), dtype=torch.float32, device="cuda")
+    g.gram(X, 0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        g.gram(X, 0)
+    sec = (time.perf_counter() - t0) / reps
+    flops = 2.0 * 3 * sp.cells * K * K
+    g.close()
+    del X
+    return {"workload": f"K={K} FP32 snapshots of the 128^3 e-field", "K": K,
+            "ms": round(sec * 1e3, 3), "TFLOPs": round(flops / sec / 1e12, 2),
+            "peak_fp64_mfma_TFLOPs": 78.6, "frac": round(flops / sec / 1e12 / 78.6, 4),
+            "bytes_read_GB": round(K * 3 * sp.cells * 4 / 1e9, 3),
+            "note": "includes the 64x64 partial reduction and the host copy of G"}
 
 
 def calib_copy(nbytes: int = 1 << 30, reps: int = 3):
@@ -352,7 +471,8 @@ def main(argv=None):
     r["grid"].close()
     line["config"]["copy_GBs_read_plus_write"] = measure_copy()
     if not args.no_forms:
-        line["forms"] = {}
+        line["forms"] = {"batched": form_batched(), "adjoint": form_adjoint(),
+                         "gram": form_gram()}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
