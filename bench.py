@@ -87,8 +87,10 @@ def run_plain(spec, steps: int, warmup: int, profile: bool = True, tile=None):
     if tile is None:
         tuned = g.autotune(dt, reps=10)
     else:
-        g.set_tuning(tile[0], int(tile[1]), int(tile[2]))
-        tuned = (*g.get_tuning(), float("nan"))
+        tw = int(tile[3]) if len(tile) > 3 else 64
+        g.set_tuning(tile[0], int(tile[1]), int(tile[2]), tw)
+        p_, ty_, kc_, tw_ = g.get_tuning()
+        tuned = (p_, ty_, kc_, float("nan"), tw_)
     g.trace_config(every, steps // every + warmup // every + 4)
     g.step(warmup, dt)
     torch.cuda.synchronize()
@@ -191,7 +193,7 @@ def form_batched(plain_steps: int = 400):
     cells = sum(sp.cells for sp in specs)
     grids, dts = make()
     b = FitBatch(grids)
-    ty, kc, _ = b.autotune(dts, reps=5)
+    ty, kc, _, tw = b.autotune(dts, reps=5)
     b.step(32, dts)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -223,7 +225,7 @@ def form_batched(plain_steps: int = 400):
             "alg_GBs": round(B_STEP * gb, 1), "frac": round(B_STEP * gb / PEAK_HBM_GBS, 4),
             "plain_per_grid_Gcell_updates_per_s": round(gp, 3),
             "plain_steps_timed": plain_steps, "batched_over_plain": round(gb / gp, 3),
-            "tile": [64, ty, kc], "launch": "one launch per step of all grids, hipGraph chunks of 16"}
+            "tile": [tw, ty, kc], "launch": "one launch per step of all grids, hipGraph chunks of 16"}
 
 
 def form_adjoint():
@@ -402,7 +404,7 @@ def main(argv=None):
     ap.add_argument("--calib-copy", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration) and exit")
     ap.add_argument("--tile", default=None,
-                    help="path,ty,kc (e.g. fused,16,128): skip the autotuner, use this tile")
+                    help="path,ty,kc[,tw] (e.g. fused,16,128,64): skip the autotuner, use this tile")
     ap.add_argument("--summarize", nargs=5, metavar="DIR", default=None,
                     help="kt fetch write copyfetch copywrite rocprofv3 output dirs -> profiles/")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "fused_step_c3.md"))
@@ -431,7 +433,7 @@ def main(argv=None):
     ms_step = r["ms"] / args.steps
     value = cells * args.steps / (r["ms"] / 1e3) / 1e9
     roof = None
-    path, ty, kc = r["grid"].get_tuning()
+    path, ty, kc, tw = r["grid"].get_tuning()
     if r["prof"] is not None:
         st_ms, st_n = r["prof"]["step"]
         if st_n > 0:   # fused single-pass step kernel: one launch = one full step
@@ -452,7 +454,7 @@ def main(argv=None):
                                 "scaled by a 1 GiB copy; profiles/traffic_c3.json)",
                 "alg_bytes_per_launch": kb * cells, "alg_bytes_per_cell": kb,
                 "avg_launch_ms": round(avg, 5), "launches_timed": st_n,
-                "path": path, "tile": [64, ty, kc],
+                "path": path, "tile": [tw, ty, kc],
                 "autotune_ms_per_step": (None if r["tuned"][3] != r["tuned"][3]
                                          else round(r["tuned"][3], 5)),
                 "step_alg_GBs": round(B_STEP * cells / (ms_step / 1e3) / 1e9, 1)}

@@ -255,14 +255,17 @@ int fit_batch_create(fit_grid* const* grids, int nb, void* stream, fit_batch** o
 /* Destroy a batch (not its grids).  NULL is accepted. */
 int fit_batch_destroy(fit_batch* b);
 
-/* Tile rows ty (power of two, 2..16; 0 keeps), z-planes per item kc (0 =
- * whole columns) and steps per captured launch (0 keeps; default 16). */
-int fit_batch_set_tuning(fit_batch* b, int ty, int kc, int steps_per_graph);
-int fit_batch_get_tuning(const fit_batch* b, int* ty, int* kc, int* steps_per_graph, int* nwg);
+/* Tile width tw (32, 64, 128 or 256; 0 keeps), rows ty (power of two,
+ * 2..16; 0 keeps; tw ty <= 1024), z-planes per item kc (0 = whole columns)
+ * and steps per captured launch (0 keeps; default 16). */
+int fit_batch_set_tuning(fit_batch* b, int tw, int ty, int kc, int steps_per_graph);
+int fit_batch_get_tuning(const fit_batch* b, int* tw, int* ty, int* kc, int* steps_per_graph,
+                         int* nwg);
 
-/* Autotuner: time candidate (ty, kc) with `reps` single-step launches each
+/* Autotuner: time candidate (tw, ty, kc) with `reps` single-step launches each
  * (state unchanged) and keep the fastest. dt: host array of nb step sizes. */
-int fit_batch_autotune(fit_batch* b, const double* dt, int reps, int* ty, int* kc, float* ms_best);
+int fit_batch_autotune(fit_batch* b, const double* dt, int reps, int* tw, int* ty, int* kc,
+                       float* ms_best);
 
 /* Advance every grid of the batch by nsteps steps; dt: host array of nb step
  * sizes (each <= its grid's CFL bound unless that grid allows instability).
@@ -289,15 +292,16 @@ int fit_profile_end(fit_grid* g, double ms[FIT_PROF_N], int64_t count[FIT_PROF_N
  * single-pass kernel when mu is uniform, else the two half-step kernels),
  * FIT_PATH_SPLIT (e-update and h-update kernels, in place) or FIT_PATH_FUSED
  * (one kernel per step, state ping-pongs between two buffer sets; needs a
- * uniform mu).  ty: rows of the 64-wide column tile (power of two; split
- * 1..8, fused 2..16); kc: z-planes per workgroup; ty = kc = 0 selects the
- * default for the path.  Every path computes the same values (bitwise:
- * the per-node arithmetic is shared).  Errors: FIT_E_INVALID. */
+ * uniform mu).  tw x ty: column tile (fused: tw in {32, 64, 128, 256}, ty a
+ * power of two in [2, 16], tw ty <= 1024; split: tw = 64, ty in {1..8});
+ * kc: z-planes per workgroup; tw = ty = kc = 0 selects the path's default.
+ * Every path and tile computes the same values (bitwise: the per-node
+ * arithmetic is shared).  Errors: FIT_E_INVALID. */
 enum { FIT_PATH_AUTO = 0, FIT_PATH_SPLIT = 1, FIT_PATH_FUSED = 2 };
-int fit_set_tuning(fit_grid* g, int path, int ty, int kc);
+int fit_set_tuning(fit_grid* g, int path, int tw, int ty, int kc);
 
 /* The path fit_step will take and its tile shape. */
-int fit_get_tuning(const fit_grid* g, int* path, int* ty, int* kc);
+int fit_get_tuning(const fit_grid* g, int* path, int* tw, int* ty, int* kc);
 
 /* Autotuner: time candidate kernel paths and tile shapes (tile heights,
  * z-chunks sized to one or two rounds of resident workgroups, from the
@@ -306,7 +310,8 @@ int fit_get_tuning(const fit_grid* g, int* path, int* ty, int* kc);
  * counter, trace and probe are left unchanged (candidates run out of place
  * into the second buffer set).  Any output pointer may be NULL; *ms_best is
  * the per-step time of the winner.  Synchronises. */
-int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* ty, int* kc, float* ms_best);
+int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* tw, int* ty, int* kc,
+                 float* ms_best);
 
 /* Number of curl applications (sparse matrix-vector products of the paper's
  * cost model, eq. cost_LF: 2 per leapfrog step) performed by this handle. */

@@ -59,16 +59,17 @@ SIGNATURES = {
     "fit_profile_begin": [_vp, _i64],
     "fit_profile_end": [_vp, _dp, _i64p],
     "fit_smvp_count": [_vp, _i64p],
-    "fit_set_tuning": [_vp, _i, _i, _i],
-    "fit_get_tuning": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)],
+    "fit_set_tuning": [_vp, _i, _i, _i, _i],
+    "fit_get_tuning": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                       C.POINTER(C.c_int)],
     "fit_gram": [_vp, _vp, _i64, _i, _i, _dp],
     "fit_batch_create": [C.POINTER(_vp), _i, _vp, C.POINTER(_vp)],
     "fit_batch_destroy": [_vp],
-    "fit_batch_set_tuning": [_vp, _i, _i, _i],
+    "fit_batch_set_tuning": [_vp, _i, _i, _i, _i],
     "fit_batch_get_tuning": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
-                             C.POINTER(C.c_int)],
+                             C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "fit_batch_autotune": [_vp, _dp, _i, C.POINTER(C.c_int), C.POINTER(C.c_int),
-                           C.POINTER(C.c_float)],
+                           C.POINTER(C.c_int), C.POINTER(C.c_float)],
     "fit_batch_step": [_vp, _i64, _dp, _i],
     "fit_step_record": [_vp, _i64, _d, _vp, _vp],
     "fit_adjoint_begin": [_vp, _i64, _d],
@@ -76,7 +77,7 @@ SIGNATURES = {
     "fit_adjoint_segment": [_vp, _i64, _i64, _vp, _vp],
     "fit_adjoint_grad": [_vp, _vp, _vp, _i],
     "fit_autotune": [_vp, _d, _i, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
-                     C.POINTER(C.c_float)],
+                     C.POINTER(C.c_int), C.POINTER(C.c_float)],
 }
 PROF_KINDS = ("epass", "hpass", "reduce", "step", "adjoint", "other")
 _CHAR = {"fit_version": [], "fit_last_error": []}

@@ -38,20 +38,23 @@ class FitBatch:
                                                  (len(self.grids),)))
         return a
 
-    def set_tuning(self, ty: int = 0, kc: int = 0, steps_per_graph: int = 0):
-        call("fit_batch_set_tuning", self._h, int(ty), int(kc), int(steps_per_graph))
+    def set_tuning(self, ty: int = 0, kc: int = 0, steps_per_graph: int = 0, tw: int = 0):
+        call("fit_batch_set_tuning", self._h, int(tw), int(ty), int(kc), int(steps_per_graph))
 
     def get_tuning(self):
-        v = [C.c_int() for _ in range(4)]
+        """(ty, kc, steps_per_graph, workgroups per step, tw)."""
+        v = [C.c_int() for _ in range(5)]
         call("fit_batch_get_tuning", self._h, *[C.byref(x) for x in v])
-        return tuple(x.value for x in v)   # ty, kc, steps_per_graph, workgroups
+        tw, ty, kc, spg, nwg = (x.value for x in v)
+        return ty, kc, spg, nwg, tw
 
     def autotune(self, dt, reps: int = 5):
+        """Returns (ty, kc, ms_per_step, tw)."""
         a = self._dt(dt)
-        t, k, ms = C.c_int(), C.c_int(), C.c_float()
-        call("fit_batch_autotune", self._h, dptr(a), int(reps), C.byref(t), C.byref(k),
-             C.byref(ms))
-        return t.value, k.value, ms.value
+        w, t, k, ms = C.c_int(), C.c_int(), C.c_int(), C.c_float()
+        call("fit_batch_autotune", self._h, dptr(a), int(reps), C.byref(w), C.byref(t),
+             C.byref(k), C.byref(ms))
+        return t.value, k.value, ms.value, w.value
 
     def step(self, nsteps: int, dt, use_graph: bool = True):
         a = self._dt(dt)

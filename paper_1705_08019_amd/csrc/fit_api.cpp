@@ -73,14 +73,15 @@ void default_tiling(const Dims& d, int* ty, int* kc) {
 
 // Fused-kernel tiling: pick the z-chunk so that one round of resident
 // workgroups (LDS- and wave-limited) covers the grid once.
-void default_step_tiling(const Dims& d, size_t esz, bool lossy, int* ty, int* kc) {
+void default_step_tiling(const Dims& d, size_t esz, bool lossy, int* ty, int* kc, int* tw) {
   // tall tiles amortise the halo row; 16 rows (1024 threads) for FP32 when
-  // the grid is tall enough, 4 for FP64 (LDS)
+  // the grid is tall enough, 4 for FP64 (LDS); 64-wide rows
+  const int w = 64;
   const int t = esz == 8 ? 4 : (d.ny >= 64 ? 16 : 8);
-  int per_cu = step_blocks_per_cu(t, esz, lossy);
+  int per_cu = step_blocks_per_cu(t, esz, lossy, w);
   if (per_cu <= 0) {   // no device information: estimate from LDS and waves
-    const size_t lds = step_lds_bytes(t, esz, lossy) + 2048;
-    per_cu = (int)std::min<size_t>((160 * 1024) / lds, 2048 / (64 * t));
+    const size_t lds = step_lds_bytes(t, esz, lossy, w) + 2048;
+    per_cu = (int)std::min<size_t>((160 * 1024) / lds, 2048 / (w * t));
   }
   per_cu = std::max(per_cu, 1);
   int cus = 256;
@@ -92,14 +93,18 @@ void default_step_tiling(const Dims& d, size_t esz, bool lossy, int* ty, int* kc
   }
   (void)hipGetLastError();
   const int64_t resident = (int64_t)cus * per_cu;
-  const int64_t tiles = (int64_t)((d.nx + 63) / 64) * ((d.ny + t - 1) / t);
+  const int64_t tiles = (int64_t)((d.nx + w - 1) / w) * ((d.ny + t - 1) / t);
   // one round of resident workgroups covers the grid
   const int64_t nkc = std::max<int64_t>(1, resident / tiles);
   int k = (int)((d.nz + nkc - 1) / nkc);
   k = std::max(k, std::min(8, d.nz));
   *ty = t;
   *kc = std::min(k, d.nz);
+  *tw = w;
 }
+
+// Tile widths of the fused step: 32, 64, 128 or 256 lanes.
+static bool valid_tw(int tw) { return tw == 32 || tw == 64 || tw == 128 || tw == 256; }
 
 bool use_fused(const fit_grid* g) {
   if (g->path == 1) return false;
@@ -264,7 +269,7 @@ int step_fused_io(fit_grid* g, double dt, const T* e0, const T* h0, T* e1, T* h1
   a.eps = static_cast<const T*>(g->eps);
   a.sig = static_cast<const T*>(g->sig);
   a.d = d;
-  a.t = make_tiling(d, g->sty, g->skc);
+  a.t = make_tiling(d, g->sty, g->skc, g->stw);
   a.hs = (T)(0.5 * dt);
   a.imu2 = (T)g->imu_u + (T)g->imu_u;
   a.src_comp = g->src_axis;
@@ -359,10 +364,10 @@ int upload_cells(fit_grid* g, void** dst, const std::vector<double>& v, const ch
 // reads (e, h) and writes the second buffer set; the split kernels run out of
 // place into the second set.  The handle's state is left untouched.
 template <typename T>
-int time_candidate(fit_grid* g, double dt, int path, int ty, int kc, int reps, float* ms) {
+int time_candidate(fit_grid* g, double dt, int path, int tw, int ty, int kc, int reps, float* ms) {
   const Dims& d = g->d;
   const int save_path = g->path, save_ty = g->ty, save_kc = g->kc, save_sty = g->sty,
-            save_skc = g->skc;
+            save_skc = g->skc, save_stw = g->stw;
   const int64_t save_m = g->m, save_smvp = g->smvp, save_tr = g->trace_every;
   const int64_t save_pend = g->pend_m;
   const fit::Probe save_probe = g->probe;
@@ -371,6 +376,7 @@ int time_candidate(fit_grid* g, double dt, int path, int ty, int kc, int reps, f
   if (path == 2) {
     g->sty = ty;
     g->skc = kc;
+    g->stw = tw;
   } else {
     g->ty = ty;
     g->kc = kc;
@@ -408,6 +414,7 @@ int time_candidate(fit_grid* g, double dt, int path, int ty, int kc, int reps, f
   g->kc = save_kc;
   g->sty = save_sty;
   g->skc = save_skc;
+  g->stw = save_stw;
   g->m = save_m;
   g->smvp = save_smvp;
   g->trace_every = save_tr;
@@ -464,7 +471,7 @@ int fit_grid_create(const fit_grid_desc* desc, void* stream, fit_grid** out) {
     g->gf2[a] = s3[a] / (s3[b] * s3[c]) / 2.0;    // M_mu^{-1} = gf2 (imu_1 + imu_2)
   }
   default_tiling(g->d, &g->ty, &g->kc);
-  default_step_tiling(g->d, g->esz, false, &g->sty, &g->skc);
+  default_step_tiling(g->d, g->esz, false, &g->sty, &g->skc, &g->stw);
   int rc = dev_alloc(&g->e, 3 * n * g->esz, "e");
   if (!rc) rc = dev_alloc(&g->h, 3 * n * g->esz, "h");
   if (!rc) rc = dev_alloc(&g->eps, n * g->esz, "eps");
@@ -557,7 +564,7 @@ int fit_set_materials(fit_grid* g, const double* eps_r, const double* mu_r, cons
   }
   g->lossy = lossy;
   g->mu_uniform = mu_uni;
-  if (!g->tile_explicit) default_step_tiling(g->d, g->esz, lossy, &g->sty, &g->skc);
+  if (!g->tile_explicit) default_step_tiling(g->d, g->esz, lossy, &g->sty, &g->skc, &g->stw);
   g->imu_u = imu[0];
   g->cfl = cfl;
   g->eps_host = eps;
@@ -868,25 +875,32 @@ int fit_gram(fit_grid* g, const void* X, int64_t ld, int K, int which, double* G
   return FIT_OK;
 }
 
-int fit_set_tuning(fit_grid* g, int path, int ty, int kc) {
+int fit_set_tuning(fit_grid* g, int path, int tw, int ty, int kc) {
   if (!g) return fail(FIT_E_INVALID, "null handle");
   if (path < 0 || path > 2) return fail(FIT_E_INVALID, "path must be 0 (auto), 1 (split), 2 (fused)");
   if (path == 2 && !g->mu_uniform) return fail(FIT_E_INVALID, "the fused step needs a uniform mu");
   const bool fused = path == 2 || (path == 0 && g->mu_uniform);
-  if (ty != 0 || kc != 0) {
-    const int tmax = fused ? 16 : 8;
-    const int tmin = fused ? 2 : 1;
-    if (ty < tmin || ty > tmax || (ty & (ty - 1)) != 0)
-      return fail(FIT_E_INVALID, "ty must be a power of two in [" + std::to_string(tmin) + ", " +
-                                     std::to_string(tmax) + "]");
+  const bool expl = tw != 0 || ty != 0 || kc != 0;
+  if (expl && tw == 0) tw = 64;
+  if (expl) {
+    if (fused) {
+      if (!valid_tw(tw)) return fail(FIT_E_INVALID, "tw must be 32, 64, 128 or 256 for the fused step");
+      if (ty < 2 || ty > 16 || (ty & (ty - 1)) != 0 || tw * ty > 1024)
+        return fail(FIT_E_INVALID, "ty must be a power of two in [2, 16] with tw * ty <= 1024");
+      if (step_lds_bytes(ty, g->esz, g->lossy, tw) > 160 * 1024)
+        return fail(FIT_E_INVALID, "tile needs more LDS than a CU has");
+    } else {
+      if (tw != 64) return fail(FIT_E_INVALID, "the split kernels use tw = 64");
+      if (ty < 1 || ty > 8 || (ty & (ty - 1)) != 0)
+        return fail(FIT_E_INVALID, "ty must be a power of two in [1, 8] for the split path");
+    }
     if (kc < 1) return fail(FIT_E_INVALID, "kc must be >= 1");
-    if (fused && step_lds_bytes(ty, g->esz, g->lossy) > 160 * 1024)
-      return fail(FIT_E_INVALID, "tile needs more LDS than a CU has");
   }
   g->path = path;
-  g->tile_explicit = ty != 0 || kc != 0;
-  if (ty != 0 || kc != 0) {
+  g->tile_explicit = expl;
+  if (expl) {
     if (fused) {
+      g->stw = tw;
       g->sty = ty;
       g->skc = std::min(kc, g->d.nz);
     } else {
@@ -895,17 +909,18 @@ int fit_set_tuning(fit_grid* g, int path, int ty, int kc) {
     }
   } else {
     default_tiling(g->d, &g->ty, &g->kc);
-    default_step_tiling(g->d, g->esz, g->lossy, &g->sty, &g->skc);
+    default_step_tiling(g->d, g->esz, g->lossy, &g->sty, &g->skc, &g->stw);
   }
   return FIT_OK;
 }
 
-int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* ty, int* kc, float* ms_best) {
+int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* tw, int* ty, int* kc,
+                 float* ms_best) {
   if (!g) return fail(FIT_E_INVALID, "null handle");
   if (reps < 1 || reps > 1000) return fail(FIT_E_INVALID, "reps must be in [1, 1000]");
   int rc = check_dt(g, dt);
   if (rc) return rc;
-  struct Cand { int path, ty, kc; };
+  struct Cand { int path, tw, ty, kc; };
   std::vector<Cand> cands;
   int cus = 256, dev = 0;
   if (hipGetDevice(&dev) == hipSuccess) {
@@ -914,53 +929,60 @@ int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* ty, int* kc, 
       cus = v;
   }
   if (g->mu_uniform) {
-    const int tys32[3] = {4, 8, 16}, tys64[3] = {2, 4, 8};
-    for (int a = 0; a < 3; ++a) {
-      const int t = g->f64 ? tys64[a] : tys32[a];
-      if (step_lds_bytes(t, g->esz, g->lossy) > 160 * 1024) continue;
-      const int per_cu = std::max(1, step_blocks_per_cu(t, g->esz, g->lossy));
-      const int64_t tiles = (int64_t)((g->d.nx + 63) / 64) * ((g->d.ny + t - 1) / t);
-      for (int mult = 1; mult <= 2; ++mult) {
-        const int64_t nkc = std::max<int64_t>(1, mult * (int64_t)cus * per_cu / tiles);
-        const int k = std::min<int>(g->d.nz, std::max<int>(std::min(8, g->d.nz),
-                                                         (int)((g->d.nz + nkc - 1) / nkc)));
-        bool dup = false;
-        for (const Cand& c : cands) dup |= (c.path == 2 && c.ty == t && c.kc == k);
-        if (!dup) cands.push_back({2, t, k});
+    const int widths[4] = {32, 64, 128, 256};
+    const int heights[4] = {2, 4, 8, 16};
+    for (int w : widths) {
+      if (w > 2 * g->d.nx && w > 32) continue;        // mostly empty lanes
+      for (int t : heights) {
+        if (w * t > 1024 || w * t < 128) continue;
+        if (step_lds_bytes(t, g->esz, g->lossy, w) > 160 * 1024) continue;
+        const int per_cu = step_blocks_per_cu(t, g->esz, g->lossy, w);
+        if (per_cu <= 0) continue;
+        const int64_t tiles = (int64_t)((g->d.nx + w - 1) / w) * ((g->d.ny + t - 1) / t);
+        for (int mult = 1; mult <= 2; ++mult) {
+          const int64_t nkc = std::max<int64_t>(1, mult * (int64_t)cus * per_cu / tiles);
+          const int k = std::min<int>(g->d.nz, std::max<int>(std::min(8, g->d.nz),
+                                                           (int)((g->d.nz + nkc - 1) / nkc)));
+          bool dup = false;
+          for (const Cand& c : cands) dup |= (c.path == 2 && c.tw == w && c.ty == t && c.kc == k);
+          if (!dup) cands.push_back({2, w, t, k});
+        }
       }
     }
   }
   {
     int t, k;
     default_tiling(g->d, &t, &k);
-    cands.push_back({1, t, k});
-    cands.push_back({1, t, std::min(g->d.nz, 4 * k)});
+    cands.push_back({1, 64, t, k});
+    cands.push_back({1, 64, t, std::min(g->d.nz, 4 * k)});
   }
   float best = 1e30f;
   Cand bc = cands[0];
   for (const Cand& c : cands) {
     float ms = 0.f;
-    rc = g->f64 ? time_candidate<double>(g, dt, c.path, c.ty, c.kc, reps, &ms)
-                : time_candidate<float>(g, dt, c.path, c.ty, c.kc, reps, &ms);
+    rc = g->f64 ? time_candidate<double>(g, dt, c.path, c.tw, c.ty, c.kc, reps, &ms)
+                : time_candidate<float>(g, dt, c.path, c.tw, c.ty, c.kc, reps, &ms);
     if (rc) return rc;
     if (ms < best) {
       best = ms;
       bc = c;
     }
   }
-  rc = fit_set_tuning(g, bc.path, bc.ty, bc.kc);
+  rc = fit_set_tuning(g, bc.path, bc.tw, bc.ty, bc.kc);
   if (rc) return rc;
   if (path) *path = bc.path;
+  if (tw) *tw = bc.tw;
   if (ty) *ty = bc.ty;
   if (kc) *kc = bc.kc;
   if (ms_best) *ms_best = best;
   return FIT_OK;
 }
 
-int fit_get_tuning(const fit_grid* g, int* path, int* ty, int* kc) {
-  if (!g || !path || !ty || !kc) return fail(FIT_E_INVALID, "null argument");
+int fit_get_tuning(const fit_grid* g, int* path, int* tw, int* ty, int* kc) {
+  if (!g || !path || !tw || !ty || !kc) return fail(FIT_E_INVALID, "null argument");
   const bool fused = use_fused(g);
   *path = fused ? 2 : 1;
+  *tw = fused ? g->stw : 64;
   *ty = fused ? g->sty : g->ty;
   *kc = fused ? g->skc : g->kc;
   return FIT_OK;

@@ -23,6 +23,7 @@ struct fit_batch {
   int64_t src_cap = 0;
   int P = 0;
   int ty = 8, kc = 0;            // kc = 0: whole columns
+  int tw = 64;
   int steps_per_graph = 16;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -45,7 +46,7 @@ static int batch_layout(fit_batch* b) {
   for (int g = 0; g < b->nb; ++g) {
     const Dims& d = b->grids[g]->d;
     const int kc = b->kc > 0 ? std::min(b->kc, d.nz) : d.nz;
-    const Tiling t = make_tiling(d, b->ty, kc);
+    const Tiling t = make_tiling(d, b->ty, kc, b->tw);
     for (int64_t q = 0; q < t.blocks(); ++q) items.push_back(g);
   }
   b->P = (int)items.size();
@@ -56,7 +57,7 @@ static int batch_layout(fit_batch* b) {
                            hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "item table upload");
   // sets the dynamic-LDS attribute of the batch kernel for this tile height
-  (void)batch_blocks_per_cu(b->ty, b->f64 ? 8 : 4, b->lossy_any);
+  (void)batch_blocks_per_cu(b->ty, b->f64 ? 8 : 4, b->lossy_any, b->tw);
   batch_drop_graph(b);
   return FIT_OK;
 }
@@ -86,7 +87,7 @@ static int batch_desc(fit_batch* b, const double* dt, int64_t nsteps, bool with_
     D.sig = static_cast<const T*>(gr->sig);
     D.d = gr->d;
     const int kc = b->kc > 0 ? std::min(b->kc, gr->d.nz) : gr->d.nz;
-    D.t = make_tiling(gr->d, b->ty, kc);
+    D.t = make_tiling(gr->d, b->ty, kc, b->tw);
     for (int c = 0; c < 3; ++c) {
       D.kb[c] = (T)(4.0 * dt[g] / gr->gedge[c]);
       D.kd[c] = (T)(dt[g] * gr->gf2[c]);
@@ -128,6 +129,7 @@ static BatchArgs<T> batch_args_host(fit_batch* b, int fixed) {
   a.nb = b->nb;
   a.P = b->P;
   a.ty = b->ty;
+  a.tw = b->tw;
   a.lossy_any = b->lossy_any ? 1 : 0;
   a.fixed_parity = fixed;
   return a;
@@ -287,25 +289,30 @@ int fit_batch_destroy(fit_batch* b) {
   return FIT_OK;
 }
 
-int fit_batch_set_tuning(fit_batch* b, int ty, int kc, int steps_per_graph) {
+int fit_batch_set_tuning(fit_batch* b, int tw, int ty, int kc, int steps_per_graph) {
   if (!b) return fail(FIT_E_INVALID, "null batch");
-  if (ty != 0) {
-    if (ty < 2 || ty > 16 || (ty & (ty - 1)) != 0)
-      return fail(FIT_E_INVALID, "ty must be a power of two in [2, 16]");
-    if (step_lds_bytes(ty, b->f64 ? 8 : 4, b->lossy_any) > 160 * 1024)
-      return fail(FIT_E_INVALID, "tile needs more LDS than a CU has");
-    b->ty = ty;
-  }
+  const int ntw = tw != 0 ? tw : b->tw;
+  const int nty = ty != 0 ? ty : b->ty;
+  if (!(ntw == 32 || ntw == 64 || ntw == 128 || ntw == 256))
+    return fail(FIT_E_INVALID, "tw must be 32, 64, 128 or 256");
+  if (nty < 2 || nty > 16 || (nty & (nty - 1)) != 0 || ntw * nty > 1024)
+    return fail(FIT_E_INVALID, "ty must be a power of two in [2, 16] with tw * ty <= 1024");
+  if (step_lds_bytes(nty, b->f64 ? 8 : 4, b->lossy_any, ntw) > 160 * 1024)
+    return fail(FIT_E_INVALID, "tile needs more LDS than a CU has");
   if (kc < 0) return fail(FIT_E_INVALID, "kc must be >= 0 (0: whole columns)");
-  b->kc = kc;
   if (steps_per_graph < 0 || steps_per_graph > 1 << 20)
     return fail(FIT_E_INVALID, "bad steps_per_graph");
+  b->tw = ntw;
+  b->ty = nty;
+  b->kc = kc;
   if (steps_per_graph > 0) b->steps_per_graph = steps_per_graph;
   return batch_layout(b);
 }
 
-int fit_batch_get_tuning(const fit_batch* b, int* ty, int* kc, int* steps_per_graph, int* nwg) {
+int fit_batch_get_tuning(const fit_batch* b, int* tw, int* ty, int* kc, int* steps_per_graph,
+                         int* nwg) {
   if (!b) return fail(FIT_E_INVALID, "null batch");
+  if (tw) *tw = b->tw;
   if (ty) *ty = b->ty;
   if (kc) *kc = b->kc;
   if (steps_per_graph) *steps_per_graph = b->steps_per_graph;
@@ -348,38 +355,46 @@ int fit_batch_step(fit_batch* b, int64_t nsteps, const double* dt, int use_graph
   return rc ? rc : rc2;
 }
 
-int fit_batch_autotune(fit_batch* b, const double* dt, int reps, int* ty, int* kc, float* ms_best) {
+int fit_batch_autotune(fit_batch* b, const double* dt, int reps, int* tw, int* ty, int* kc,
+                       float* ms_best) {
   if (!b) return fail(FIT_E_INVALID, "null batch");
   if (reps < 1 || reps > 1000) return fail(FIT_E_INVALID, "reps must be in [1, 1000]");
   if (int rc = batch_check_dt(b, dt)) return rc;
   if (int rc = batch_enter(b)) return rc;
-  const int tys32[3] = {4, 8, 16}, tys64[3] = {2, 4, 8};
+  const int widths[3] = {32, 64, 128};
+  const int heights[4] = {2, 4, 8, 16};
   const int kcs[3] = {0, 48, 24};
   float best = 1e30f;
-  int bty = b->ty, bkc = b->kc;
+  int btw = b->tw, bty = b->ty, bkc = b->kc;
   int rc = FIT_OK;
-  for (int a = 0; a < 3 && !rc; ++a) {
-    const int t = b->f64 ? tys64[a] : tys32[a];
-    if (step_lds_bytes(t, b->f64 ? 8 : 4, b->lossy_any) > 160 * 1024) continue;
-    for (int q = 0; q < 3 && !rc; ++q) {
-      b->ty = t;
-      b->kc = kcs[q];
-      rc = batch_layout(b);
-      float ms = 0.f;
-      if (!rc) rc = b->f64 ? batch_time<double>(b, dt, reps, &ms) : batch_time<float>(b, dt, reps, &ms);
-      if (!rc && ms < best) {
-        best = ms;
-        bty = t;
-        bkc = kcs[q];
+  for (int w : widths) {
+    for (int t : heights) {
+      if (w * t > 1024 || w * t < 128 || rc) continue;
+      if (step_lds_bytes(t, b->f64 ? 8 : 4, b->lossy_any, w) > 160 * 1024) continue;
+      for (int q = 0; q < 3 && !rc; ++q) {
+        b->tw = w;
+        b->ty = t;
+        b->kc = kcs[q];
+        rc = batch_layout(b);
+        float ms = 0.f;
+        if (!rc) rc = b->f64 ? batch_time<double>(b, dt, reps, &ms) : batch_time<float>(b, dt, reps, &ms);
+        if (!rc && ms < best) {
+          best = ms;
+          btw = w;
+          bty = t;
+          bkc = kcs[q];
+        }
       }
     }
   }
+  b->tw = btw;
   b->ty = bty;
   b->kc = bkc;
   int rc2 = batch_layout(b);
   int rc3 = batch_leave(b);
   if (rc) return rc;
   if (rc2) return rc2;
+  if (tw) *tw = btw;
   if (ty) *ty = bty;
   if (kc) *kc = bkc;
   if (ms_best) *ms_best = best;

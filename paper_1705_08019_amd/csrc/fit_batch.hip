@@ -75,29 +75,29 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs<T> B) {
 }
 
 template <typename T>
-static int batch_occupancy(int ty, size_t lds) {
+static int batch_occupancy(int ty, int tw, size_t lds) {
   int nb = 0;
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<T>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_batch<T>),
-                                                   64 * ty, lds) != hipSuccess) {
+                                                   tw * ty, lds) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
   return nb;
 }
 
-int batch_blocks_per_cu(int ty, size_t esz, bool lossy) {
-  const size_t lds = step_lds_bytes(ty, esz, lossy);
-  return esz == 8 ? batch_occupancy<double>(ty, lds) : batch_occupancy<float>(ty, lds);
+int batch_blocks_per_cu(int ty, size_t esz, bool lossy, int tw) {
+  const size_t lds = step_lds_bytes(ty, esz, lossy, tw);
+  return esz == 8 ? batch_occupancy<double>(ty, tw, lds) : batch_occupancy<float>(ty, tw, lds);
 }
 
 // One step of every grid, then the step counter (fixed_parity: no counter).
 template <typename T>
 hipError_t launch_batch(const BatchArgs<T>& b, hipStream_t s) {
-  const size_t lds = step_lds_bytes(b.ty, sizeof(T), b.lossy_any != 0);
-  hipLaunchKernelGGL(k_batch<T>, dim3((unsigned)b.P), dim3(64, b.ty), lds, s, b);
+  const size_t lds = step_lds_bytes(b.ty, sizeof(T), b.lossy_any != 0, b.tw);
+  hipLaunchKernelGGL(k_batch<T>, dim3((unsigned)b.P), dim3(b.tw, b.ty), lds, s, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || b.fixed_parity) return e;
   hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, b.ctl);

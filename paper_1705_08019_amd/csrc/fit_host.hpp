@@ -54,6 +54,7 @@ struct fit_grid {
   fit::Probe probe{};
   int ty = 4, kc = 64;          // split half-step kernels
   int sty = 8, skc = 64;        // fused step kernel
+  int stw = 64;                 // fused step tile width
   int path = 0;                 // FIT_PATH_*: 0 auto, 1 split, 2 fused
   bool tile_explicit = false;   // tile shape set by fit_set_tuning
   void* e_alt = nullptr;        // second buffer set of the fused (ping-pong) step
@@ -84,7 +85,7 @@ int step_once(fit_grid* g, double dt, const T* ein, T* eout, const T* hin, T* ho
 // Frees adjoint/other optional workspaces (defined with those features).
 void grid_release_extras(fit_grid* g);
 bool use_fused(const fit_grid* g);
-void default_step_tiling(const Dims& d, size_t esz, bool lossy, int* ty, int* kc);
+void default_step_tiling(const Dims& d, size_t esz, bool lossy, int* ty, int* kc, int* tw);
 template <typename T>
 int step_fused(fit_grid* g, double dt);
 template <typename T>

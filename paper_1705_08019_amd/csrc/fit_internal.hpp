@@ -13,15 +13,18 @@ struct Dims {
   int64_t sx, sxy, n;
 };
 
-// Tiling of a z-marching launch: blockDim = (64, ty); each thread owns one
-// (i, j) column of a 64 x ty tile and marches over a chunk of kc planes.
+// Tiling of a z-marching launch: blockDim = (tw, ty); each thread owns one
+// (i, j) column of a tw x ty tile and marches over a chunk of kc planes.
+// The half-step kernels use tw = 64; the fused step takes tw in {32, 64,
+// 128, 256} (a row of tw lanes spans tw / 64 waves, or two rows share one).
 struct Tiling {
   int ty, kc;
   int ntx, nty, nkc;
+  int tw;
   int64_t blocks() const { return (int64_t)ntx * nty * nkc; }
 };
 
-Tiling make_tiling(const Dims& d, int ty, int kc);
+Tiling make_tiling(const Dims& d, int ty, int kc, int tw = 64);
 
 // Closed probe box in node coordinates; a direction-a edge at node p is in
 // the probe when lo[a] <= p_a and p_a + 1 <= hi[a] and lo[b] <= p_b <= hi[b]
@@ -100,10 +103,10 @@ struct SArgs {
   double* part;
 };
 
-// Dynamic LDS bytes of the fused kernel for a tile height ty, and the number
+// Dynamic LDS bytes of the fused kernel for a tw x ty tile, and the number
 // of its workgroups a CU holds at once (0 if the runtime cannot tell).
-size_t step_lds_bytes(int ty, size_t esz, bool lossy);
-int step_blocks_per_cu(int ty, size_t esz, bool lossy);
+size_t step_lds_bytes(int ty, size_t esz, bool lossy, int tw = 64);
+int step_blocks_per_cu(int ty, size_t esz, bool lossy, int tw = 64);
 
 template <typename T>
 hipError_t launch_step(const SArgs<T>& a, bool lossy, bool energy, bool probe, hipStream_t s);
@@ -185,11 +188,12 @@ struct BatchArgs {
   int nb;
   int P;                  // items (workgroups) per step
   int ty;
+  int tw;
   int lossy_any;          // LDS sized for the lossy tile
   int fixed_parity;       // autotuning: read par0, step index 0, no counter
 };
 
-int batch_blocks_per_cu(int ty, size_t esz, bool lossy);
+int batch_blocks_per_cu(int ty, size_t esz, bool lossy, int tw);
 template <typename T>
 hipError_t launch_batch(const BatchArgs<T>& b, hipStream_t s);
 hipError_t launch_batch_set_base(BatchCtl* ctl, int64_t base, hipStream_t s);

@@ -23,11 +23,12 @@
 
 namespace fit {
 
-Tiling make_tiling(const Dims& d, int ty, int kc) {
+Tiling make_tiling(const Dims& d, int ty, int kc, int tw) {
   Tiling t;
   t.ty = ty;
+  t.tw = tw;
   t.kc = kc < 1 ? 1 : (kc > d.nz ? d.nz : kc);
-  t.ntx = (d.nx + 63) / 64;
+  t.ntx = (d.nx + tw - 1) / tw;
   t.nty = (d.ny + ty - 1) / ty;
   t.nkc = (d.nz + t.kc - 1) / t.kc;
   return t;

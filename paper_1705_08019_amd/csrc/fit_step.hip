@@ -3,7 +3,7 @@
 // buffer set, so a step moves 6 field values + the per-cell materials per
 // cell instead of the 9 + materials of two separate half-step passes.
 //
-// Tiling.  A workgroup owns a 64 (x) x ty (y) column tile and marches a chunk
+// Tiling.  A workgroup owns a tw (x) x ty (y) column tile and marches a chunk
 // of z-planes.  For each plane k it stages h^(m+1/2), eps and sigma of the
 // tile plus a one-cell ring in LDS (double-buffered: planes k and k-1), forms
 // e^(m+1) on the tile plus its +x column and +y row (the halo values the
@@ -23,9 +23,9 @@ __device__ __forceinline__ int64_t xcd_remap_s(int64_t bid, int64_t nb) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
 }
 
-size_t step_lds_bytes(int ty, size_t esz, bool lossy) {
-  const size_t RP = 66 * (size_t)(ty + 2);   // ring plane: x in [-1, 64], y in [-1, ty]
-  const size_t EP = 65 * (size_t)(ty + 1);   // ext plane: x in [0, 64], y in [0, ty]
+size_t step_lds_bytes(int ty, size_t esz, bool lossy, int tw) {
+  const size_t RP = (size_t)(tw + 2) * (size_t)(ty + 2);   // ring plane: x in [-1, tw], y in [-1, ty]
+  const size_t EP = (size_t)(tw + 1) * (size_t)(ty + 1);   // ext plane: x in [0, tw], y in [0, ty]
   return esz * (3 * 3 * RP + 3 * RP + (lossy ? 3 * RP : 0) + 2 * 3 * EP);
 }
 
@@ -43,14 +43,14 @@ __global__ __launch_bounds__(1024) void k_step(SArgs<T> A) {
 }
 
 template <typename T, bool LOSSY>
-static int occupancy_of(int ty) {
+static int occupancy_of(int ty, int tw) {
   int nb = 0;
-  const size_t lds = step_lds_bytes(ty, sizeof(T), LOSSY);
+  const size_t lds = step_lds_bytes(ty, sizeof(T), LOSSY, tw);
   if (lds > 64 * 1024)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step<T, LOSSY, false, false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void*>(&k_step<T, LOSSY, false, false>), 64 * ty, lds) !=
+          &nb, reinterpret_cast<const void*>(&k_step<T, LOSSY, false, false>), tw * ty, lds) !=
       hipSuccess) {
     (void)hipGetLastError();
     return 0;
@@ -58,15 +58,16 @@ static int occupancy_of(int ty) {
   return nb;
 }
 
-int step_blocks_per_cu(int ty, size_t esz, bool lossy) {
-  if (esz == 8) return lossy ? occupancy_of<double, true>(ty) : occupancy_of<double, false>(ty);
-  return lossy ? occupancy_of<float, true>(ty) : occupancy_of<float, false>(ty);
+int step_blocks_per_cu(int ty, size_t esz, bool lossy, int tw) {
+  if (esz == 8)
+    return lossy ? occupancy_of<double, true>(ty, tw) : occupancy_of<double, false>(ty, tw);
+  return lossy ? occupancy_of<float, true>(ty, tw) : occupancy_of<float, false>(ty, tw);
 }
 
 template <typename T>
 hipError_t launch_step(const SArgs<T>& a, bool lossy, bool energy, bool probe, hipStream_t s) {
-  const dim3 blk(64, a.t.ty), grd((unsigned)a.t.blocks());
-  const size_t lds = step_lds_bytes(a.t.ty, sizeof(T), lossy);
+  const dim3 blk(a.t.tw, a.t.ty), grd((unsigned)a.t.blocks());
+  const size_t lds = step_lds_bytes(a.t.ty, sizeof(T), lossy, a.t.tw);
 #define FIT_S(L, E, P)                                                                    \
   do {                                                                                   \
     if (lds > 64 * 1024) {                                                               \

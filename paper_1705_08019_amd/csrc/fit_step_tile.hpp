@@ -14,10 +14,11 @@ __device__ __forceinline__ void nadd_s(double& s, double& c, double x) {
   s = t;
 }
 
-// Ring entries of one plane staged per thread (RP <= 3 * 64 * ty for ty >= 2).
+// Ring entries of one plane staged per thread (RP = (tw+2)(ty+2) <= 3 tw ty for
+// tw >= 32, ty >= 2).
 constexpr int kRingPerThread = 3;
 
-// One 64 x ty column tile of one z-chunk: tile coordinates (tx, tyi, kz);
+// One tw x ty column tile of one z-chunk: tile coordinates (tx, tyi, kz);
 // sm = dynamic LDS of step_lds_bytes(); part = this tile's partial-sum row
 // (ENERGY or PROBE only).
 template <typename T, bool LOSSY, bool ENERGY, bool PROBE>
@@ -25,27 +26,28 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
                                           double* part) {
   const Dims d = A.d;
   const int TY = A.t.ty;
-  const int RW = 66, RP = RW * (TY + 2);
-  const int EW = 65, EP = EW * (TY + 1);
+  const int TW = A.t.tw;                 // tile width (x) = blockDim.x
+  const int RW = TW + 2, RP = RW * (TY + 2);
+  const int EW = TW + 1, EP = EW * (TY + 1);
   T* hL = sm;                          // [3][3][RP]  h^(m+1/2), planes k, k-1, k-2 rotating
   T* cL = hL + 9 * RP;                 // [3][RP]     eps0 eps_r
   T* sL = cL + 3 * RP;                 // [3][RP]     sigma (lossy only)
   T* nL = sL + (LOSSY ? 3 * RP : 0);   // [2][3][EP]  e^(m+1), planes k, k-1
 
-  const int i0 = tx * 64, j0 = tyi * TY;
+  const int i0 = tx * TW, j0 = tyi * TY;
   const int k0 = kz * A.t.kc;
   const int k1 = min(k0 + A.t.kc, d.nz);
   const int lx = (int)threadIdx.x, ly = (int)threadIdx.y;
-  const int tid = ly * 64 + lx, nthr = 64 * TY;
+  const int tid = ly * TW + lx, nthr = TW * TY;
   const int i = i0 + lx, j = j0 + ly;
   const bool own = (i < d.nx) && (j < d.ny);
   const int64_t sx = d.sx, sxy = d.sxy;
 
   // one extra e^(m+1) point per thread for the +y halo row / +x halo column
-  const int nhalo = 64 + TY + 1;
+  const int nhalo = TW + TY + 1;
   const bool has_h = tid < nhalo;
-  const int hx_ = tid < 64 ? tid : 64;
-  const int hy_ = tid < 64 ? TY : tid - 64;
+  const int hx_ = tid < TW ? tid : TW;
+  const int hy_ = tid < TW ? TY : tid - TW;
   const int hi = i0 + hx_, hj = j0 + hy_;
   const bool hvalid = has_h && hi < d.nx && hj < d.ny;
 
@@ -256,8 +258,9 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
   }
 
   if (ENERGY || PROBE) {
-    // block sum of the 9 terms, fixed order
+    // block sum of the 9 terms, fixed order: per wave, then over waves
     __shared__ double red[16][9];
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
     double v[9];
 #pragma unroll
     for (int t = 0; t < 9; ++t) {
@@ -267,15 +270,15 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
       v[t] = x;
     }
     __syncthreads();
-    if (lx == 0) {
+    if (lane == 0) {
 #pragma unroll
-      for (int t = 0; t < 9; ++t) red[ly][t] = v[t];
+      for (int t = 0; t < 9; ++t) red[wave][t] = v[t];
     }
     __syncthreads();
-    if (ly == 0 && lx < 9) {
+    if (tid < 9) {
       double s = 0.0;
-      for (int w = 0; w < TY; ++w) s += red[w][lx];
-      part[lx] = s;
+      for (int w = 0; w < nw; ++w) s += red[w][tid];
+      part[tid] = s;
     }
   }
 }

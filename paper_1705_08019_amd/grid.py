@@ -207,21 +207,26 @@ class FitGrid:
     # ------------------------------------------------------------------ tuning
     PATHS = {"auto": 0, "split": 1, "fused": 2}
 
-    def set_tuning(self, path: str = "auto", ty: int = 0, kc: int = 0):
-        call("fit_set_tuning", self._h, self.PATHS[path], int(ty), int(kc))
+    def set_tuning(self, path: str = "auto", ty: int = 0, kc: int = 0, tw: int = None):
+        """Kernel path and tile (tw x ty columns, kc planes); zeros = defaults.
+        tw defaults to 64 when ty/kc are given."""
+        if tw is None:
+            tw = 64 if (ty or kc) else 0
+        call("fit_set_tuning", self._h, self.PATHS[path], int(tw), int(ty), int(kc))
 
     def get_tuning(self):
-        p, t, k = C.c_int(), C.c_int(), C.c_int()
-        call("fit_get_tuning", self._h, C.byref(p), C.byref(t), C.byref(k))
-        return {1: "split", 2: "fused"}[p.value], t.value, k.value
+        """(path, ty, kc, tw)."""
+        p, w, t, k = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        call("fit_get_tuning", self._h, C.byref(p), C.byref(w), C.byref(t), C.byref(k))
+        return {1: "split", 2: "fused"}[p.value], t.value, k.value, w.value
 
     def autotune(self, dt: float, reps: int = 10):
         """Time candidate paths/tiles on the current state (unchanged) and keep
-        the fastest; returns (path, ty, kc, ms_per_step)."""
-        p, t, k, ms = C.c_int(), C.c_int(), C.c_int(), C.c_float()
-        call("fit_autotune", self._h, float(dt), int(reps), C.byref(p), C.byref(t), C.byref(k),
-             C.byref(ms))
-        return {1: "split", 2: "fused"}[p.value], t.value, k.value, ms.value
+        the fastest; returns (path, ty, kc, ms_per_step, tw)."""
+        p, w, t, k, ms = C.c_int(), C.c_int(), C.c_int(), C.c_int(), C.c_float()
+        call("fit_autotune", self._h, float(dt), int(reps), C.byref(p), C.byref(w), C.byref(t),
+             C.byref(k), C.byref(ms))
+        return {1: "split", 2: "fused"}[p.value], t.value, k.value, ms.value, w.value
 
     # ------------------------------------------------------------------ Gram
     def gram(self, X: torch.Tensor, which: int = 0) -> np.ndarray:

@@ -93,8 +93,8 @@ def test_batch_autotune_keeps_state():
     b = FitBatch(gb)
     b.step(10, dts)
     before = _fields(gb)
-    ty, kc, ms = b.autotune(dts, reps=2)
-    assert ms > 0 and b.get_tuning()[:2] == (ty, kc)
+    ty, kc, ms, tw = b.autotune(dts, reps=2)
+    assert ms > 0 and b.get_tuning()[:2] == (ty, kc) and b.get_tuning()[4] == tw
     _assert_equal(_fields(gb), before)
     assert all(g.step_index == 10 for g in gb)
     b.close()

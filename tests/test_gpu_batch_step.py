@@ -71,6 +71,14 @@ def test_batch_graph_equals_plain(dtype):
     for g, dt in zip(gp, dts):
         g.step(37, dt)
     _assert_equal(_fields(gb), _fields(gp))
+    # narrow and wide tiles (the grids are 6..20 cells across)
+    for tw, ty, kc in ((32, 4, 0), (32, 2, 7), (128, 2, 3)):
+        b.set_tuning(ty, kc, 4, tw=tw)
+        assert b.get_tuning()[4] == tw
+        b.step(19, dts)
+        for g, dt in zip(gp, dts):
+            g.step(19, dt)
+        _assert_equal(_fields(gb), _fields(gp))
     b.close()
 
 
@@ -99,8 +107,8 @@ def test_batch_autotune_keeps_state():
     b = FitBatch(gb)
     b.step(10, dts)
     before = _fields(gb)
-    ty, kc, ms = b.autotune(dts, reps=2)
-    assert ms > 0 and b.get_tuning()[:2] == (ty, kc)
+    ty, kc, ms, tw = b.autotune(dts, reps=2)
+    assert ms > 0 and b.get_tuning()[:2] == (ty, kc) and b.get_tuning()[4] == tw
     _assert_equal(_fields(gb), before)
     assert all(g.step_index == 10 for g in gb)
     b.close()

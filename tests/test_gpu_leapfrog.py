@@ -234,15 +234,22 @@ def test_paths_and_tiles_bitwise(dtype):
     sig = lossy_slab(nx, ny, nz, 3)
     src = (2, 70, 20, 18, 1.0)
     ref = None
-    configs = [("split", 0, 0), ("split", 1, 5), ("split", 8, 37), ("fused", 0, 0),
-               ("fused", 2, 3), ("fused", 4, 16), ("fused", 8, 1), ("fused", 16, 37)]
+    # (path, ty, kc, tw): tile widths 32..256 against a 131-cell x extent
+    # (ragged last tile for every width, a single tile at 256)
+    configs = [("split", 0, 0, 0), ("split", 1, 5, 64), ("split", 8, 37, 64),
+               ("fused", 0, 0, 0), ("fused", 2, 3, 64), ("fused", 4, 16, 64),
+               ("fused", 8, 1, 64), ("fused", 16, 37, 64), ("fused", 2, 5, 32),
+               ("fused", 16, 9, 32), ("fused", 8, 4, 128), ("fused", 4, 6, 128),
+               ("fused", 4, 37, 256), ("fused", 2, 2, 256)]
     if dtype == "f64":
-        configs = [c for c in configs if c[1] <= 8]
-    for path, ty, kc in configs:
+        configs = [c for c in configs if c[1] * max(c[3], 64) <= 512]
+    for path, ty, kc, tw in configs:
         g = FitGrid(nx, ny, nz, dtype)
         g.set_materials(eps, None, sig)
         dt = 0.9 * g.cfl_dt()
-        g.set_tuning(path, ty, kc)
+        g.set_tuning(path, ty, kc, tw)
+        if ty:
+            assert g.get_tuning() == (path, ty, kc, tw)
         g.set_source(*src[:4], src[4], 20 * dt)
         g.trace_config(5, 40)
         g.step(77, dt)
@@ -251,7 +258,7 @@ def test_paths_and_tiles_bitwise(dtype):
         if ref is None:
             ref = (e, h, tr)
             continue
-        assert torch.equal(e, ref[0]) and torch.equal(h, ref[1]), (path, ty, kc)
+        assert torch.equal(e, ref[0]) and torch.equal(h, ref[1]), (path, ty, kc, tw)
         np.testing.assert_allclose(tr, ref[2], rtol=1e-13, atol=0)
         g.close()
 
@@ -279,11 +286,11 @@ def test_autotune_keeps_state_and_results():
         g.step(13, dt)
         if tune:
             before = g.get_fields()
-            path, ty, kc, ms = g.autotune(dt, reps=3)
+            path, ty, kc, ms, tw = g.autotune(dt, reps=3)
             after = g.get_fields()
             assert torch.equal(before[0], after[0]) and torch.equal(before[1], after[1])
             assert g.step_index == 13 and ms > 0
-            assert g.get_tuning() == (path, ty, kc)
+            assert g.get_tuning() == (path, ty, kc, tw)
         g.step(30, dt)
         grids.append(g.get_fields())
     assert torch.equal(grids[0][0], grids[1][0]) and torch.equal(grids[0][1], grids[1][1])
