@@ -255,15 +255,22 @@ int fit_batch_create(fit_grid* const* grids, int nb, void* stream, fit_batch** o
 /* Destroy a batch (not its grids).  NULL is accepted. */
 int fit_batch_destroy(fit_batch* b);
 
-/* Tile width tw (32, 64, 128 or 256; 0 keeps), rows ty (power of two,
- * 2..16; 0 keeps; tw ty <= 1024), z-planes per item kc (0 = whole columns)
- * and steps per captured launch (0 keeps; default 16). */
+/* Tile of every grid: tw x ty columns with tw in {32, 64, 128, 256} and ty a
+ * power of two in [2, 16] (64 <= tw ty <= 1024); or tw = FIT_TW_ROWS:
+ * row-packed tiles, ty = threads per workgroup (a multiple of 64 in
+ * [128, 1024]) and each grid's tile as wide as its x extent when that fits
+ * (else 32..256 wide) with its rows splitting the y extent evenly.  0 keeps
+ * tw / ty.  kc: z-planes per item (0 = whole columns); steps per captured
+ * launch (0 keeps; default 16).  FIT_E_INVALID (tuning unchanged) if a tile
+ * needs more LDS than a workgroup can have. */
+enum { FIT_TW_ROWS = -1 };
 int fit_batch_set_tuning(fit_batch* b, int tw, int ty, int kc, int steps_per_graph);
 int fit_batch_get_tuning(const fit_batch* b, int* tw, int* ty, int* kc, int* steps_per_graph,
                          int* nwg);
 
-/* Autotuner: time candidate (tw, ty, kc) with `reps` single-step launches each
- * (state unchanged) and keep the fastest. dt: host array of nb step sizes. */
+/* Autotuner: time candidate (tw, ty, kc), row-packed ones included, with
+ * `reps` single-step launches each (state unchanged) and keep the fastest.
+ * dt: host array of nb step sizes. */
 int fit_batch_autotune(fit_batch* b, const double* dt, int reps, int* tw, int* ty, int* kc,
                        float* ms_best);
 

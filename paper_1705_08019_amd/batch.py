@@ -1,5 +1,5 @@
-"""Python handle for a batch of grids advanced by one persistent launch
-(thin wrapper over fit_batch_* in include/fit.h)."""
+"""Python handle for a batch of grids advanced together, one launch per step
+of all grids (thin wrapper over fit_batch_* in include/fit.h)."""
 from __future__ import annotations
 
 import ctypes as C
@@ -12,6 +12,8 @@ from .grid import FitGrid, current_stream_handle
 
 
 class FitBatch:
+    TW_ROWS = -1     # row-packed tiles (ty = threads per workgroup)
+
     def __init__(self, grids, stream=None):
         self.grids = list(grids)
         if not all(isinstance(g, FitGrid) for g in self.grids):
@@ -39,6 +41,8 @@ class FitBatch:
         return a
 
     def set_tuning(self, ty: int = 0, kc: int = 0, steps_per_graph: int = 0, tw: int = 0):
+        """tw x ty tiles (tw = TW_ROWS: row-packed, ty threads per workgroup),
+        kc planes per item (0: whole columns); zeros keep."""
         call("fit_batch_set_tuning", self._h, int(tw), int(ty), int(kc), int(steps_per_graph))
 
     def get_tuning(self):

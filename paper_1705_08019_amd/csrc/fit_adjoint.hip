@@ -19,16 +19,10 @@
 
 namespace fit {
 
-__device__ __forceinline__ int64_t xcd_remap_a(int64_t bid, int64_t nb) {
-  const int64_t q = nb / 8, r = nb % 8;
-  const int64_t x = bid % 8, l = bid / 8;
-  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
-}
-
 template <typename T, bool LOSSY>
 __global__ __launch_bounds__(512) void k_adj_e(AdjArgs<T> A) {
   const Dims d = A.d;
-  const int64_t lt = xcd_remap_a(blockIdx.x, gridDim.x);
+  const int64_t lt = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = (int)(lt % A.t.ntx);
   const int64_t rr = lt / A.t.ntx;
   const int tyi = (int)(rr % A.t.nty);
@@ -159,7 +153,7 @@ __global__ __launch_bounds__(512) void k_adj_e(AdjArgs<T> A) {
 template <typename T>
 __global__ __launch_bounds__(512) void k_adj_h(AdjArgs<T> A) {
   const Dims d = A.d;
-  const int64_t lt = xcd_remap_a(blockIdx.x, gridDim.x);
+  const int64_t lt = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = (int)(lt % A.t.ntx);
   const int64_t rr = lt / A.t.ntx;
   const int tyi = (int)(rr % A.t.nty);

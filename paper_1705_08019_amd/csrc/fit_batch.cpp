@@ -22,8 +22,12 @@ struct fit_batch {
   void* src_tab = nullptr;       // device [nb][src_cap]
   int64_t src_cap = 0;
   int P = 0;
-  int ty = 8, kc = 0;            // kc = 0: whole columns
-  int tw = 64;
+  // tile: tw x ty for every grid (tw > 0), or row-packed (tw = FIT_TW_ROWS):
+  // ty threads per workgroup, each grid's tile shaped to its own extent
+  int tw = 64, ty = 8;
+  int kc = 0;                    // z-planes per item; 0: whole columns
+  int nthreads = 512;            // threads per workgroup of the current layout
+  size_t lds = 0;                // dynamic LDS of the current layout
   int steps_per_graph = 16;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -40,25 +44,88 @@ static void batch_drop_graph(fit_batch* b) {
   b->graph_S = 0;
 }
 
-// Build the item table and persistent grid size for the current tiling.
+// Row-packed tile of one grid for `nt` threads: the tile width is the grid's
+// whole x extent when it fits (no x halo at all), else a 32..256-wide power of
+// two; the rows split the y extent evenly.  Picks the shape that leaves the
+// fewest idle threads (ties: the wider tile).
+static void rows_shape(const Dims& d, int nt, int* tw_out, int* ty_out) {
+  const int cand[5] = {d.nx, 256, 128, 64, 32};
+  double best = -1.0;
+  *tw_out = 32;
+  *ty_out = std::max(1, std::min(d.ny, nt / 32));
+  for (int w : cand) {
+    if (w < 1 || w > 256 || 2 * w > nt) continue;
+    const int rows = nt / w;
+    const int nty = (d.ny + rows - 1) / rows;
+    const int t = (d.ny + nty - 1) / nty;
+    if (w + t + 2 > nt) continue;
+    const int ntx = (d.nx + w - 1) / w;
+    const double util = (double)d.nx * d.ny / ((double)ntx * nty * nt);
+    if (util > best * (1.0 + 1e-9)) {
+      best = util;
+      *tw_out = w;
+      *ty_out = t;
+    }
+  }
+}
+
+// Tile of grid d under the batch's current tuning.
+static Tiling batch_tiling(const fit_batch* b, const Dims& d) {
+  const int kc = b->kc > 0 ? std::min(b->kc, d.nz) : d.nz;
+  if (b->tw > 0) return make_tiling(d, b->ty, kc, b->tw);
+  int tw = 0, ty = 0;
+  rows_shape(d, b->ty, &tw, &ty);
+  return make_tiling(d, ty, kc, tw);
+}
+
+// Build the item table, the workgroup shape and the LDS size for the current
+// tiling.  FIT_E_INVALID (nothing changed) if a grid's tile needs more LDS
+// than a workgroup can have.
 static int batch_layout(fit_batch* b) {
+  const int nt = b->tw > 0 ? b->tw * b->ty : b->ty;
+  const size_t esz = b->f64 ? 8 : 4;
+  size_t lds = 0;
   std::vector<int> items;
   for (int g = 0; g < b->nb; ++g) {
-    const Dims& d = b->grids[g]->d;
-    const int kc = b->kc > 0 ? std::min(b->kc, d.nz) : d.nz;
-    const Tiling t = make_tiling(d, b->ty, kc, b->tw);
+    const Tiling t = batch_tiling(b, b->grids[g]->d);
+    if (t.tw * t.ty > nt || t.tw + t.ty + 2 > nt)
+      return fail(FIT_E_INVALID, "tile does not fit the workgroup");
+    lds = std::max(lds, step_lds_bytes(t.ty, esz, b->lossy_any, t.tw));
     for (int64_t q = 0; q < t.blocks(); ++q) items.push_back(g);
   }
-  b->P = (int)items.size();
+  if (lds > 160 * 1024) return fail(FIT_E_INVALID, "tile needs more LDS than a workgroup can have");
+  if (items.size() > (size_t)0x7fffffff) return fail(FIT_E_INVALID, "too many work items");
   dev_free(reinterpret_cast<void*&>(b->item_grid));
+  b->P = 0;
   int rc = dev_alloc(reinterpret_cast<void**>(&b->item_grid), items.size() * sizeof(int), "item table");
   if (rc) return rc;
   hipError_t e = hipMemcpy(b->item_grid, items.data(), items.size() * sizeof(int),
                            hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "item table upload");
-  // sets the dynamic-LDS attribute of the batch kernel for this tile height
-  (void)batch_blocks_per_cu(b->ty, b->f64 ? 8 : 4, b->lossy_any, b->tw);
+  b->P = (int)items.size();
+  b->nthreads = nt;
+  b->lds = lds;
+  (void)batch_prepare(esz, nt, lds);
   batch_drop_graph(b);
+  return FIT_OK;
+}
+
+// Set a tuning and lay the batch out for it; on failure the previous tuning
+// (and layout) is restored.
+static int batch_retune(fit_batch* b, int tw, int ty, int kc) {
+  const int otw = b->tw, oty = b->ty, okc = b->kc;
+  b->tw = tw;
+  b->ty = ty;
+  b->kc = kc;
+  int rc = batch_layout(b);
+  if (rc) {
+    const std::string msg = fit_last_error();
+    b->tw = otw;
+    b->ty = oty;
+    b->kc = okc;
+    (void)batch_layout(b);
+    return fail(rc, msg);
+  }
   return FIT_OK;
 }
 
@@ -86,8 +153,7 @@ static int batch_desc(fit_batch* b, const double* dt, int64_t nsteps, bool with_
     D.eps = static_cast<const T*>(gr->eps);
     D.sig = static_cast<const T*>(gr->sig);
     D.d = gr->d;
-    const int kc = b->kc > 0 ? std::min(b->kc, gr->d.nz) : gr->d.nz;
-    D.t = make_tiling(gr->d, b->ty, kc, b->tw);
+    D.t = batch_tiling(b, gr->d);
     for (int c = 0; c < 3; ++c) {
       D.kb[c] = (T)(4.0 * dt[g] / gr->gedge[c]);
       D.kd[c] = (T)(dt[g] * gr->gf2[c]);
@@ -128,9 +194,8 @@ static BatchArgs<T> batch_args_host(fit_batch* b, int fixed) {
   a.ctl = b->ctl;
   a.nb = b->nb;
   a.P = b->P;
-  a.ty = b->ty;
-  a.tw = b->tw;
-  a.lossy_any = b->lossy_any ? 1 : 0;
+  a.nthreads = b->nthreads;
+  a.lds = (int)b->lds;
   a.fixed_parity = fixed;
   return a;
 }
@@ -249,6 +314,7 @@ int fit_batch_create(fit_grid* const* grids, int nb, void* stream, fit_batch** o
     b->lossy_any |= gr->lossy;
   }
   b->f64 = grids[0]->f64;
+  b->tw = 64;
   b->ty = b->f64 ? 4 : 8;
 
   int rc = FIT_OK;
@@ -292,21 +358,25 @@ int fit_batch_destroy(fit_batch* b) {
 int fit_batch_set_tuning(fit_batch* b, int tw, int ty, int kc, int steps_per_graph) {
   if (!b) return fail(FIT_E_INVALID, "null batch");
   const int ntw = tw != 0 ? tw : b->tw;
-  const int nty = ty != 0 ? ty : b->ty;
-  if (!(ntw == 32 || ntw == 64 || ntw == 128 || ntw == 256))
-    return fail(FIT_E_INVALID, "tw must be 32, 64, 128 or 256");
-  if (nty < 2 || nty > 16 || (nty & (nty - 1)) != 0 || ntw * nty > 1024)
-    return fail(FIT_E_INVALID, "ty must be a power of two in [2, 16] with tw * ty <= 1024");
-  if (step_lds_bytes(nty, b->f64 ? 8 : 4, b->lossy_any, ntw) > 160 * 1024)
-    return fail(FIT_E_INVALID, "tile needs more LDS than a CU has");
+  int nty = ty != 0 ? ty : b->ty;
+  if (ntw == FIT_TW_ROWS) {
+    if (ty == 0 && b->tw != FIT_TW_ROWS) nty = 512;
+    if (nty < 128 || nty > 1024 || nty % 64 != 0)
+      return fail(FIT_E_INVALID, "row-packed tiles: ty = threads per workgroup, a multiple of 64 in [128, 1024]");
+  } else {
+    if (!(ntw == 32 || ntw == 64 || ntw == 128 || ntw == 256))
+      return fail(FIT_E_INVALID, "tw must be 32, 64, 128, 256 or FIT_TW_ROWS");
+    if (ty == 0 && b->tw == FIT_TW_ROWS) nty = std::max(2, 512 / ntw);
+    if (nty < 2 || nty > 16 || (nty & (nty - 1)) != 0 || ntw * nty > 1024 || ntw * nty < 64)
+      return fail(FIT_E_INVALID, "ty must be a power of two in [2, 16] with 64 <= tw * ty <= 1024");
+  }
   if (kc < 0) return fail(FIT_E_INVALID, "kc must be >= 0 (0: whole columns)");
   if (steps_per_graph < 0 || steps_per_graph > 1 << 20)
     return fail(FIT_E_INVALID, "bad steps_per_graph");
-  b->tw = ntw;
-  b->ty = nty;
-  b->kc = kc;
+  int rc = batch_retune(b, ntw, nty, kc);
+  if (rc) return rc;
   if (steps_per_graph > 0) b->steps_per_graph = steps_per_graph;
-  return batch_layout(b);
+  return FIT_OK;
 }
 
 int fit_batch_get_tuning(const fit_batch* b, int* tw, int* ty, int* kc, int* steps_per_graph,
@@ -361,29 +431,29 @@ int fit_batch_autotune(fit_batch* b, const double* dt, int reps, int* tw, int* t
   if (reps < 1 || reps > 1000) return fail(FIT_E_INVALID, "reps must be in [1, 1000]");
   if (int rc = batch_check_dt(b, dt)) return rc;
   if (int rc = batch_enter(b)) return rc;
-  const int widths[3] = {32, 64, 128};
-  const int heights[4] = {2, 4, 8, 16};
-  const int kcs[3] = {0, 48, 24};
+  struct Cand { int tw, ty; };
+  std::vector<Cand> shapes;
+  for (int nt : {256, 512, 1024}) shapes.push_back({FIT_TW_ROWS, nt});
+  for (int w : {32, 64, 128})
+    for (int t : {2, 4, 8, 16})
+      if (w * t >= 128 && w * t <= 1024) shapes.push_back({w, t});
+  const int kcs[5] = {0, 48, 32, 24, 16};
   float best = 1e30f;
   int btw = b->tw, bty = b->ty, bkc = b->kc;
   int rc = FIT_OK;
-  for (int w : widths) {
-    for (int t : heights) {
-      if (w * t > 1024 || w * t < 128 || rc) continue;
-      if (step_lds_bytes(t, b->f64 ? 8 : 4, b->lossy_any, w) > 160 * 1024) continue;
-      for (int q = 0; q < 3 && !rc; ++q) {
-        b->tw = w;
-        b->ty = t;
-        b->kc = kcs[q];
-        rc = batch_layout(b);
-        float ms = 0.f;
-        if (!rc) rc = b->f64 ? batch_time<double>(b, dt, reps, &ms) : batch_time<float>(b, dt, reps, &ms);
-        if (!rc && ms < best) {
-          best = ms;
-          btw = w;
-          bty = t;
-          bkc = kcs[q];
-        }
+  for (const Cand& c : shapes) {
+    for (int q = 0; q < 5 && !rc; ++q) {
+      b->tw = c.tw;
+      b->ty = c.ty;
+      b->kc = kcs[q];
+      if (batch_layout(b) != FIT_OK) continue;   // e.g. tile over the LDS limit
+      float ms = 0.f;
+      rc = b->f64 ? batch_time<double>(b, dt, reps, &ms) : batch_time<float>(b, dt, reps, &ms);
+      if (!rc && ms < best) {
+        best = ms;
+        btw = c.tw;
+        bty = c.ty;
+        bkc = kcs[q];
       }
     }
   }

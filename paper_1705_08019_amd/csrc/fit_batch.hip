@@ -51,12 +51,12 @@ __device__ __forceinline__ void batch_args(const BatchGrid<T>& G, int p, T src, 
   a.part = nullptr;
 }
 
-// One step of every grid: blockIdx.x = item within the step.
+// One step of every grid: one workgroup per item of the step's item table.
 template <typename T>
 __global__ __launch_bounds__(1024) void k_batch(BatchArgs<T> B) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
-  const int r = (int)blockIdx.x;
+  const int r = (int)xcd_remap(blockIdx.x, gridDim.x);
   const int g = B.item_grid[r];
   const BatchGrid<T>& G = B.grids[g];
   const int t = r - G.tile_off;
@@ -75,29 +75,26 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs<T> B) {
 }
 
 template <typename T>
-static int batch_occupancy(int ty, int tw, size_t lds) {
+static int batch_occupancy(int nthreads, size_t lds) {
   int nb = 0;
-  if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<T>),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch<T>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, reinterpret_cast<const void*>(&k_batch<T>),
-                                                   tw * ty, lds) != hipSuccess) {
+                                                   nthreads, lds) != hipSuccess) {
     (void)hipGetLastError();
     return 0;
   }
   return nb;
 }
 
-int batch_blocks_per_cu(int ty, size_t esz, bool lossy, int tw) {
-  const size_t lds = step_lds_bytes(ty, esz, lossy, tw);
-  return esz == 8 ? batch_occupancy<double>(ty, tw, lds) : batch_occupancy<float>(ty, tw, lds);
+int batch_prepare(size_t esz, int nthreads, size_t lds) {
+  return esz == 8 ? batch_occupancy<double>(nthreads, lds) : batch_occupancy<float>(nthreads, lds);
 }
 
 // One step of every grid, then the step counter (fixed_parity: no counter).
 template <typename T>
 hipError_t launch_batch(const BatchArgs<T>& b, hipStream_t s) {
-  const size_t lds = step_lds_bytes(b.ty, sizeof(T), b.lossy_any != 0, b.tw);
-  hipLaunchKernelGGL(k_batch<T>, dim3((unsigned)b.P), dim3(b.tw, b.ty), lds, s, b);
+  hipLaunchKernelGGL(k_batch<T>, dim3((unsigned)b.P), dim3(b.nthreads), (size_t)b.lds, s, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || b.fixed_parity) return e;
   hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, b.ctl);

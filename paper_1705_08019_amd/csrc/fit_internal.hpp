@@ -35,6 +35,16 @@ struct Probe {
 };
 
 // Number of FP64 partial terms written per block by the energy variants.
+// Workgroups are dispatched round-robin over the 8 XCDs of the chip: give
+// each XCD a contiguous range of logical work items (tiles in x-fastest, then
+// y, then z-chunk order) so that halo rows shared by neighbouring tiles stay
+// in one XCD's L2.  bid = hardware workgroup index, nb = grid size.
+__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
+  const int64_t q = nb / 8, r = nb % 8;
+  const int64_t x = bid % 8, l = bid / 8;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
+}
+
 constexpr int kPartTerms = 10;
 // E-pass partial term slots
 enum { PE_EE_MM = 0, PE_EE_MM1 = 1, PE_EE_M1M1 = 2, PE_LOSS = 3, PE_SRC = 4, PE_PROBE = 5 };
@@ -187,13 +197,14 @@ struct BatchArgs {
   BatchCtl* ctl;
   int nb;
   int P;                  // items (workgroups) per step
-  int ty;
-  int tw;
-  int lossy_any;          // LDS sized for the lossy tile
+  int nthreads;           // threads per workgroup (1-D; >= tw ty of every grid's tile)
+  int lds;                // dynamic LDS bytes (the largest grid tile's)
   int fixed_parity;       // autotuning: read par0, step index 0, no counter
 };
 
-int batch_blocks_per_cu(int ty, size_t esz, bool lossy, int tw);
+// Allow the batched kernel the largest dynamic LDS a workgroup can have and
+// return its resident workgroups per CU for this shape (0 if unknown).
+int batch_prepare(size_t esz, int nthreads, size_t lds);
 template <typename T>
 hipError_t launch_batch(const BatchArgs<T>& b, hipStream_t s);
 hipError_t launch_batch_set_base(BatchCtl* ctl, int64_t base, hipStream_t s);

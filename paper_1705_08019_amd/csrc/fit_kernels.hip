@@ -34,15 +34,6 @@ Tiling make_tiling(const Dims& d, int ty, int kc, int tw) {
   return t;
 }
 
-// Workgroups are dispatched round-robin over the 8 XCDs of the chip.  Give
-// each XCD a contiguous range of logical tiles (x fastest, then y, then the z
-// chunk) so the halo rows shared by y-neighbour tiles stay in one XCD's L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
-  const int64_t q = nb / 8, r = nb % 8;
-  const int64_t x = bid % 8, l = bid / 8;
-  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
-}
-
 // Neumaier compensated accumulation.
 __device__ __forceinline__ void nadd(double& s, double& c, double x) {
   const double t = s + x;

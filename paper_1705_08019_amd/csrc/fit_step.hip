@@ -17,12 +17,6 @@
 
 namespace fit {
 
-__device__ __forceinline__ int64_t xcd_remap_s(int64_t bid, int64_t nb) {
-  const int64_t q = nb / 8, r = nb % 8;
-  const int64_t x = bid % 8, l = bid / 8;
-  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
-}
-
 size_t step_lds_bytes(int ty, size_t esz, bool lossy, int tw) {
   const size_t RP = (size_t)(tw + 2) * (size_t)(ty + 2);   // ring plane: x in [-1, tw], y in [-1, ty]
   const size_t EP = (size_t)(tw + 1) * (size_t)(ty + 1);   // ext plane: x in [0, tw], y in [0, ty]
@@ -32,7 +26,7 @@ size_t step_lds_bytes(int ty, size_t esz, bool lossy, int tw) {
 template <typename T, bool LOSSY, bool ENERGY, bool PROBE>
 __global__ __launch_bounds__(1024) void k_step(SArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  const int64_t lt = xcd_remap_s(blockIdx.x, gridDim.x);
+  const int64_t lt = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = (int)(lt % A.t.ntx);
   const int64_t rr = lt / A.t.ntx;
   const int tyi = (int)(rr % A.t.nty);

@@ -1,5 +1,5 @@
 // Tile body of the fused single-pass leapfrog step, shared by the per-grid
-// kernel (fit_step.hip) and the persistent batched kernel (fit_batch.hip).
+// kernel (fit_step.hip) and the batched multi-grid kernel (fit_batch.hip).
 // See fit_step.hip for the algorithm.
 #pragma once
 
@@ -14,13 +14,30 @@ __device__ __forceinline__ void nadd_s(double& s, double& c, double x) {
   s = t;
 }
 
-// Ring entries of one plane staged per thread (RP = (tw+2)(ty+2) <= 3 tw ty for
-// tw >= 32, ty >= 2).
+// Global-memory access through address-space-1 pointers: the batched kernel
+// reads its field pointers from a device table, where the compiler cannot
+// prove them global and would emit flat accesses (which share the LDS wait
+// counter and so stall every LDS wait on the plane prefetch).
+template <typename T>
+__device__ __forceinline__ T gld(const T* p, int64_t i) {
+  return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+template <typename T>
+__device__ __forceinline__ void gst(T* p, int64_t i, T v) {
+  ((__attribute__((address_space(1))) T*)p)[i] = v;
+}
+
+// Ring entries of one plane staged per thread: RP = (tw+2)(ty+2) <= 3 nthr
+// whenever tw ty <= nthr and tw + ty + 2 <= nthr (the launchers check both).
 constexpr int kRingPerThread = 3;
 
 // One tw x ty column tile of one z-chunk: tile coordinates (tx, tyi, kz);
 // sm = dynamic LDS of step_lds_bytes(); part = this tile's partial-sum row
-// (ENERGY or PROBE only).
+// (ENERGY or PROBE only).  The workgroup's threads (any 2-D shape, a multiple
+// of 64 and at least tw ty of them, also at least tw + ty + 1) are numbered
+// linearly; thread t < tw ty owns column (t mod tw, t div tw) of the tile, the
+// rest only help to stage planes (row-packed tiles of the batched kernel,
+// whose tile width is a grid's whole x extent, leave such threads over).
 template <typename T, bool LOSSY, bool ENERGY, bool PROBE>
 __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, int kz, T* sm,
                                           double* part) {
@@ -37,10 +54,12 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
   const int i0 = tx * TW, j0 = tyi * TY;
   const int k0 = kz * A.t.kc;
   const int k1 = min(k0 + A.t.kc, d.nz);
-  const int lx = (int)threadIdx.x, ly = (int)threadIdx.y;
-  const int tid = ly * TW + lx, nthr = TW * TY;
+  const int tid = (int)(threadIdx.x + threadIdx.y * blockDim.x);
+  const int nthr = (int)(blockDim.x * blockDim.y);
+  const bool act = tid < TW * TY;      // owns a column of the tile
+  const int lx = tid % TW, ly = tid / TW;
   const int i = i0 + lx, j = j0 + ly;
-  const bool own = (i < d.nx) && (j < d.ny);
+  const bool own = act && (i < d.nx) && (j < d.ny);
   const int64_t sx = d.sx, sxy = d.sxy;
 
   // one extra e^(m+1) point per thread for the +y halo row / +x halo column
@@ -65,22 +84,22 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
       const bool in = q < RP && k >= 0 && k < d.nz && gx >= 0 && gx < d.nx && gy >= 0 &&
                       gy < d.ny;
       const int64_t g = gx + sx * gy + sxy * (int64_t)k;
-      pre[r][0] = in ? A.h0[0][g] : T(0);
-      pre[r][1] = in ? A.h0[1][g] : T(0);
-      pre[r][2] = in ? A.h0[2][g] : T(0);
-      pre[r][3] = in ? A.eps[g] : T(0);
-      pre[r][4] = (LOSSY && in) ? A.sig[g] : T(0);
+      pre[r][0] = in ? gld(A.h0[0], g) : T(0);
+      pre[r][1] = in ? gld(A.h0[1], g) : T(0);
+      pre[r][2] = in ? gld(A.h0[2], g) : T(0);
+      pre[r][3] = in ? gld(A.eps, g) : T(0);
+      pre[r][4] = (LOSSY && in) ? gld(A.sig, g) : T(0);
     }
     const bool plane = k >= 0 && k < d.nz;
     const int64_t g = i + sx * j + sxy * (int64_t)k;
     const int64_t gh = hi + sx * hj + sxy * (int64_t)k;
     const bool lo = plane && own, lh = plane && hvalid;
-    eo[0] = lo ? A.e0[0][g] : T(0);
-    eo[1] = lo ? A.e0[1][g] : T(0);
-    eo[2] = lo ? A.e0[2][g] : T(0);
-    ho[0] = lh ? A.e0[0][gh] : T(0);
-    ho[1] = lh ? A.e0[1][gh] : T(0);
-    ho[2] = lh ? A.e0[2][gh] : T(0);
+    eo[0] = lo ? gld(A.e0[0], g) : T(0);
+    eo[1] = lo ? gld(A.e0[1], g) : T(0);
+    eo[2] = lo ? gld(A.e0[2], g) : T(0);
+    ho[0] = lh ? gld(A.e0[0], gh) : T(0);
+    ho[1] = lh ? gld(A.e0[1], gh) : T(0);
+    ho[2] = lh ? gld(A.e0[2], gh) : T(0);
   };
   auto stage = [&](int buf) {
 #pragma unroll
@@ -171,7 +190,7 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
     __syncthreads();
     T* np_ = nL + ep * 3 * EP;
     const int64_t g = i + sx * j + sxy * (int64_t)k;
-    {
+    if (act) {
       T exn = 0, eyn = 0, ezn = 0, E4x, E4y, E4z, S4x, S4y, S4z;
       if (plane) enew(lx, ly, k, bc, bp, eo0, eo1, eo2, own, exn, eyn, ezn, E4x, E4y, E4z, S4x,
                       S4y, S4z);
@@ -180,9 +199,9 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
       np_[EP + e] = eyn;
       np_[2 * EP + e] = ezn;
       if (plane && own && k < k1) {
-        A.e1[0][g] = exn;
-        A.e1[1][g] = eyn;
-        A.e1[2][g] = ezn;
+        gst(A.e1[0], g, exn);
+        gst(A.e1[1], g, eyn);
+        gst(A.e1[2], g, ezn);
         if (ENERGY) {
           const double mx = A.ge[0] * (double)E4x, my = A.ge[1] * (double)E4y,
                        mz = A.ge[2] * (double)E4z;
@@ -238,9 +257,9 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
                  nq[2 * EP + e_in], nq[EP + e_in], nq[e_jn], hxo, hyo, hzo, A.imu2, A.imu2,
                  A.imu2, i > 0, j > 0, km > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
       const int64_t gm = i + sx * j + sxy * (int64_t)km;
-      A.h1[0][gm] = hxn;
-      A.h1[1][gm] = hyn;
-      A.h1[2][gm] = hzn;
+      gst(A.h1[0], gm, hxn);
+      gst(A.h1[1], gm, hyn);
+      gst(A.h1[2], gm, hzn);
       if (ENERGY) {
         const double wx = i > 0 ? 1.0 / (A.gf2[0] * (double)A.imu2) : 0.0;
         const double wy = j > 0 ? 1.0 / (A.gf2[1] * (double)A.imu2) : 0.0;

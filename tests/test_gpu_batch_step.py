@@ -71,8 +71,9 @@ def test_batch_graph_equals_plain(dtype):
     for g, dt in zip(gp, dts):
         g.step(37, dt)
     _assert_equal(_fields(gb), _fields(gp))
-    # narrow and wide tiles (the grids are 6..20 cells across)
-    for tw, ty, kc in ((32, 4, 0), (32, 2, 7), (128, 2, 3)):
+    # narrow, wide and row-packed tiles (the grids are 6..20 cells across)
+    for tw, ty, kc in ((32, 4, 0), (32, 2, 7), (128, 2, 3), (FitBatch.TW_ROWS, 128, 0),
+                       (FitBatch.TW_ROWS, 512, 5), (FitBatch.TW_ROWS, 1024, 2)):
         b.set_tuning(ty, kc, 4, tw=tw)
         assert b.get_tuning()[4] == tw
         b.step(19, dts)
@@ -131,3 +132,24 @@ def test_batch_full_workload_equals_plain():
     for g, dt in zip(gp, dts):
         g.step(specs[0].nsteps, dt)
     _assert_equal(fb, _fields(gp))
+
+
+def test_batch_tuning_errors_keep_layout():
+    """Bad tunings are refused and leave the previous tuning in force."""
+    from paper_1705_08019_amd import FitBatch, FitError
+    specs = c4_small(count=3, nsteps=0)
+    gb, dts = _make(specs, "f32")
+    gp, _ = _make(specs, "f32")
+    b = FitBatch(gb)
+    b.set_tuning(4, 3, 0, tw=64)
+    before = b.get_tuning()
+    for ty, kc, tw in ((3, 0, 64), (4, -1, 64), (4, 0, 48), (100, 0, FitBatch.TW_ROWS),
+                       (2048, 0, FitBatch.TW_ROWS), (32, 0, 64)):
+        with pytest.raises(FitError, match="INVALID"):
+            b.set_tuning(ty, kc, 0, tw=tw)
+        assert b.get_tuning() == before
+    b.step(21, dts)
+    for g, dt in zip(gp, dts):
+        g.step(21, dt)
+    _assert_equal(_fields(gb), _fields(gp))
+    b.close()
