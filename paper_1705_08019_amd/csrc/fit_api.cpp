@@ -518,12 +518,15 @@ int fit_grid_destroy(fit_grid* g) {
   dev_free(reinterpret_cast<void*&>(g->pend));
   dev_free(reinterpret_cast<void*&>(g->gram_part));
   dev_free(reinterpret_cast<void*&>(g->gram_G));
+  dev_free(reinterpret_cast<void*&>(g->gram_w[0]));
+  dev_free(reinterpret_cast<void*&>(g->gram_w[1]));
   delete g;
   return FIT_OK;
 }
 
 int fit_set_materials(fit_grid* g, const double* eps_r, const double* mu_r, const double* sigma) {
   if (!g || !eps_r) return fail(FIT_E_INVALID, "null argument");
+  g->gram_w_ok[0] = g->gram_w_ok[1] = false;
   const int64_t n = g->d.n;
   std::vector<double> eps((size_t)n), imu((size_t)n), sig;
   bool lossy = false;
@@ -850,23 +853,35 @@ int fit_gram(fit_grid* g, const void* X, int64_t ld, int K, int which, double* G
     if (rc) return rc;
     g->gram_G_cap = (int64_t)K * K;
   }
-  double gw[3];
-  for (int a = 0; a < 3; ++a) gw[a] = which == 0 ? g->gedge[a] / 4.0 : g->gf2[a];
-  int64_t nwg = 0;
   hipError_t e;
+  if (!g->gram_w_ok[which]) {
+    if (!g->gram_w[which]) {
+      rc = dev_alloc(reinterpret_cast<void**>(&g->gram_w[which]), (size_t)(3 * g->d.n) * sizeof(double),
+                     "Gram weights");
+      if (rc) return rc;
+    }
+    double gw[3];
+    for (int a = 0; a < 3; ++a) gw[a] = which == 0 ? g->gedge[a] / 4.0 : g->gf2[a];
+    if (g->f64)
+      e = launch_gram_weights<double>(g->gram_w[which], which, static_cast<const double*>(g->eps),
+                                      g->mu_uniform ? nullptr : static_cast<const double*>(g->imu),
+                                      g->imu_u, g->d, gw, g->s);
+    else
+      e = launch_gram_weights<float>(g->gram_w[which], which, static_cast<const float*>(g->eps),
+                                     g->mu_uniform ? nullptr : static_cast<const float*>(g->imu),
+                                     (float)g->imu_u, g->d, gw, g->s);
+    if (e != hipSuccess) return hip_fail(e, "Gram weights");
+    g->gram_w_ok[which] = true;
+  }
+  int64_t nwg = 0;
   {
     ProfScope ps(g, FIT_PROF_OTHER);
     if (g->f64)
-      e = launch_gram<double>(static_cast<const double*>(X), ld, K, which,
-                              static_cast<const double*>(g->eps),
-                              g->mu_uniform ? nullptr : static_cast<const double*>(g->imu),
-                              g->imu_u, g->d, gw, g->gram_part, cap_blocks, g->gram_G, g->s, &nwg);
+      e = launch_gram<double>(static_cast<const double*>(X), ld, K, g->gram_w[which], g->d,
+                              g->gram_part, cap_blocks, g->gram_G, g->s, &nwg);
     else
-      e = launch_gram<float>(static_cast<const float*>(X), ld, K, which,
-                             static_cast<const float*>(g->eps),
-                             g->mu_uniform ? nullptr : static_cast<const float*>(g->imu),
-                             (float)g->imu_u, g->d, gw, g->gram_part, cap_blocks, g->gram_G, g->s,
-                             &nwg);
+      e = launch_gram<float>(static_cast<const float*>(X), ld, K, g->gram_w[which], g->d,
+                             g->gram_part, cap_blocks, g->gram_G, g->s, &nwg);
   }
   if (e != hipSuccess) return hip_fail(e, "Gram launch");
   e = hipMemcpyAsync(G, g->gram_G, (size_t)K * K * sizeof(double), hipMemcpyDeviceToHost, g->s);

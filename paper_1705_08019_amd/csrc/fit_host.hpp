@@ -63,6 +63,8 @@ struct fit_grid {
   double* gram_part = nullptr;  // per-workgroup Gram blocks
   double* gram_G = nullptr;     // device K x K result
   int64_t gram_G_cap = 0;
+  double* gram_w[2] = {nullptr, nullptr};   // Gram row weights (M_eps, M_mu), 3 n each
+  bool gram_w_ok[2] = {false, false};       // weights match the current materials
   // kernel timing (fit_profile_begin/end)
   std::vector<hipEvent_t> prof_ev;   // 2 per timed launch
   std::vector<int> prof_kind;

@@ -121,11 +121,16 @@ int step_blocks_per_cu(int ty, size_t esz, bool lossy, int tw = 64);
 template <typename T>
 hipError_t launch_step(const SArgs<T>& a, bool lossy, bool energy, bool probe, hipStream_t s);
 
-// Gram matrix G = X^T diag(M) X over K snapshots (fit_gram.hip); part must
+// Row weights W (3 n doubles) of the Gram form: M_eps of the edges (which 0,
+// gw = g_a / 4) or M_mu of the facets (which 1, gw = gf2_a) (fit_gram.hip).
+template <typename T>
+hipError_t launch_gram_weights(double* W, int which, const T* eps, const T* imu, T imu_u,
+                               const Dims& d, const double gw[3], hipStream_t s);
+
+// Gram matrix G = X^T diag(W) X over K snapshots (fit_gram.hip); part must
 // hold part_cap_blocks * 64 * 64 doubles, G (device) K * K doubles.
 template <typename T>
-hipError_t launch_gram(const T* X, int64_t ld, int K, int which, const T* eps, const T* imu,
-                       T imu_u, const Dims& d, const double gw[3], double* part,
+hipError_t launch_gram(const T* X, int64_t ld, int K, const double* W, const Dims& d, double* part,
                        int64_t part_cap_blocks, double* G, hipStream_t s, int64_t* nwg_used);
 
 // Reverse-time adjoint step (fit_adjoint.hip).  lam, tau, em, em1 are

@@ -14,7 +14,8 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("dtype,K,which", [("f64", 24, 0), ("f64", 5, 1), ("f32", 70, 0),
-                                           ("f64", 64, 0), ("f32", 1, 0)])
+                                           ("f64", 64, 0), ("f32", 1, 0), ("f32", 40, 1),
+                                           ("f32", 16, 0)])
 def test_gram_random_snapshots(dtype, K, which):
     from paper_1705_08019_amd import FitGrid
     nx, ny, nz = 37, 21, 13
