@@ -39,6 +39,11 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E spec
 B_EPASS = 4 * (3 + 3 + 3 + 2)   # 44
 B_HPASS = 4 * (3 + 3 + 3)       # 36
 B_STEP = B_EPASS + B_HPASS      # 80
+# reverse (adjoint) step, FP32 fields: lambda and mu read + write, e^m, e^(m+1)
+# and h^(m+1/2) read, eps and sigma read, and the two FP64 per-edge
+# sensitivity accumulators read + written (the per-edge form of the
+# recursion; the kernel folds them onto the cells and moves 124 B)
+B_ADJ = 4 * (6 + 6 + 9 + 2) + 8 * 2 * 3 * 2    # 188
 
 
 KERNEL_SOURCES = {"step": ("fit_step.hip", "fit_step_tile.hpp", "fit_point.hpp"),
@@ -232,20 +237,28 @@ def form_batched(plain_steps: int = 400):
 def form_adjoint():
     """96^3 FP32, materials as the 128^3 workload, 4096 steps, checkpoints
     every 64, probe [64, 80]^3: forward (with checkpoints) and backward
-    (segment recompute + reverse sweep) throughput."""
+    (segment recompute + reverse sweep) throughput through the autograd
+    Function (after one short warm-up run), and the per-step device times of
+    the forward step, the recording recompute and the reverse-step kernel."""
     import torch
     from fit_workloads import c5
-    from paper_1705_08019_amd import ProbeProblem, probe_energy
+    from paper_1705_08019_amd import FitGrid, ProbeProblem, probe_energy
     sp = c5()
     box = sp.probe
-    prob = ProbeProblem(nx=sp.nx, ny=sp.ny, nz=sp.nz, nsteps=sp.nsteps,
-                        probe_lo=tuple(x[0] for x in box), probe_hi=tuple(x[1] for x in box),
-                        dtype="f32", checkpoint_every=sp.checkpoint_every, source=sp.source)
+
+    def problem(nsteps):
+        return ProbeProblem(nx=sp.nx, ny=sp.ny, nz=sp.nz, nsteps=nsteps,
+                            probe_lo=tuple(x[0] for x in box), probe_hi=tuple(x[1] for x in box),
+                            dtype="f32", checkpoint_every=sp.checkpoint_every, source=sp.source)
+
     eps = torch.tensor(sp.eps_r, requires_grad=True)
     sig = torch.tensor(sp.sigma, requires_grad=True)
+    probe_energy(eps, sig, problem(128)).backward()          # warm-up
+    eps.grad = None
+    sig.grad = None
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    J = probe_energy(eps, sig, prob)
+    J = probe_energy(eps, sig, problem(sp.nsteps))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     J.backward()
@@ -254,11 +267,58 @@ def form_adjoint():
     cs = sp.cells * sp.nsteps
     fwd = cs / (t1 - t0) / 1e9
     bwd = cs / (t2 - t1) / 1e9
+
+    # per-step device times on the same grid
+    g = FitGrid(sp.nx, sp.ny, sp.nz, "f32")
+    g.set_materials(sp.eps_r, None, sp.sigma)
+    dt = 0.9 * g.cfl_dt()
+    s = sp.source
+    g.set_source(s["axis"], s["i"], s["j"], s["k"], s["i_max"], s["sigma_t_steps"] * dt)
+    g.set_probe([x[0] for x in box], [x[1] for x in box])
+    g.autotune(dt, reps=3)
+    K = sp.checkpoint_every
+    shape = (K + 1, 3, sp.nz, sp.ny, sp.nx)
+    er = torch.empty(shape, dtype=torch.float32, device="cuda")
+    hr = torch.empty(shape, dtype=torch.float32, device="cuda")
+    g.step(64, dt)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    g.step(4 * K, dt)
+    ev[1].record()
+    torch.cuda.synchronize()
+    us_fwd = ev[0].elapsed_time(ev[1]) / (4 * K) * 1e3
+    ev[0].record()
+    g.step_record(K, dt, er, hr)
+    ev[1].record()
+    torch.cuda.synchronize()
+    us_rec = ev[0].elapsed_time(ev[1]) / K * 1e3
+    m0 = g.step_index - K
+    best = None
+    for _ in range(3):
+        g.adjoint_begin(g.step_index, dt)
+        torch.cuda.synchronize()
+        ev[0].record()
+        g.adjoint_segment(m0, K, er, hr)
+        ev[1].record()
+        torch.cuda.synchronize()
+        us = ev[0].elapsed_time(ev[1]) / K * 1e3
+        best = us if best is None else min(best, us)
+    g.close()
+    del er, hr
+    ach = B_ADJ * sp.cells / (best * 1e-6) / 1e9
     return {"workload": "c5: 96^3 FP32, 4096 steps, checkpoints every 64, probe 16^3",
             "forward_Gcell_steps_per_s": round(fwd, 3), "adjoint_Gcell_steps_per_s": round(bwd, 3),
             "adjoint_over_forward": round(bwd / fwd, 3), "forward_s": round(t1 - t0, 4),
             "backward_s": round(t2 - t1, 4), "J": float(J),
-            "note": "wall time incl. Python checkpoint bookkeeping; backward = recompute + reverse"}
+            "note": "wall time incl. Python checkpoint bookkeeping; backward = recompute + reverse",
+            "step_us": {"forward_with_probe": round(us_fwd, 2), "recompute_recording": round(us_rec, 2),
+                        "reverse_k_adj": round(best, 2)},
+            "reverse_roofline": {"kernel": "k_adj (fused reverse step + per-cell FP64 gradients)",
+                                 "alg_bytes_per_cell": B_ADJ, "achieved": round(ach, 1),
+                                 "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                 "frac": round(ach / PEAK_HBM_GBS, 4),
+                                 "note": "96^3 state (21 MB per field set) is largely resident in the 256 MB Infinity Cache"}}
 
 
 def gram_mfma_tiles(K: int) -> int:

@@ -204,9 +204,10 @@ int fit_gram(fit_grid* g, const void* X, int64_t ld, int K, int which, double* G
  *   lambda^(m+1) = a lambda^(m+2) - C~ (dt M_mu^{-1} mu^(m+3/2)) + 2 dt w M_eps e^(m+1)
  *   mu^(m+1/2)   = mu^(m+3/2) + C (b lambda^(m+1))
  * with a, b the e-update coefficients of fit_step; it differentiates the
- * leapfrog updates of Sec. II-A exactly (dt held fixed).  Sensitivities to the
- * per-cell eps_r and sigma are accumulated per edge in FP64 and gathered onto
- * the cells by fit_adjoint_grad.  Needs a uniform mu and a probe. */
+ * leapfrog updates of Sec. II-A exactly (dt held fixed).  Each reverse step
+ * is one fused pass; its edge sensitivities to M_eps and M_sigma go straight
+ * onto the per-cell eps_r and sigma gradients (FP64 accumulators), read by
+ * fit_adjoint_grad.  Needs a uniform mu and a probe. */
 
 /* Advance nsteps leapfrog steps like fit_step, recording every state:
  * e_rec + s * 3n holds e^(m0+s) and h_rec + s * 3n holds h^(m0+s+1/2) for
@@ -214,6 +215,13 @@ int fit_gram(fit_grid* g, const void* X, int64_t ld, int K, int which, double* G
  * grid dtype, slot layout); m0 is the step counter on entry.  The handle ends
  * in state m0 + nsteps.  No energy trace and no probe accumulation. */
 int fit_step_record(fit_grid* g, int64_t nsteps, double dt, void* e_rec, void* h_rec);
+
+/* Tile of the reverse-step kernel, used from the next fit_adjoint_begin:
+ * tw x ty columns (tw ty + tw + ty + 1 <= 512 threads: the tile and its halo
+ * points), kc z-planes per workgroup; tw = ty = 0 and kc = 0 select the
+ * defaults (a width that wastes the fewest lanes, chunks for one round of
+ * resident workgroups).  Errors: FIT_E_INVALID. */
+int fit_adjoint_set_tuning(fit_grid* g, int tw, int ty, int kc);
 
 /* Start a reverse sweep over a forward horizon of nsteps steps taken with dt:
  * clears lambda, mu and the accumulated sensitivities.  Errors: FIT_E_STATE

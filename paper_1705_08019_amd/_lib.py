@@ -72,6 +72,7 @@ SIGNATURES = {
                            C.POINTER(C.c_int), C.POINTER(C.c_float)],
     "fit_batch_step": [_vp, _i64, _dp, _i],
     "fit_step_record": [_vp, _i64, _d, _vp, _vp],
+    "fit_adjoint_set_tuning": [_vp, _i, _i, _i],
     "fit_adjoint_begin": [_vp, _i64, _d],
     "fit_adjoint_step": [_vp, _i64, _vp, _vp, _vp],
     "fit_adjoint_segment": [_vp, _i64, _i64, _vp, _vp],

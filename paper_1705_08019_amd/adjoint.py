@@ -38,6 +38,8 @@ class ProbeProblem:
     spacing: tuple = (1.0, 1.0, 1.0)
     e0: Optional[torch.Tensor] = None   # initial e^0 (slot layout), default 0
     h0: Optional[torch.Tensor] = None   # initial h^(1/2), default 0
+    autotune: bool = True               # time the forward step's tiles once before the run
+    adjoint_tile: Optional[tuple] = None   # (tw, ty, kc) of the reverse step, None: default
 
 
 def _setup(problem: ProbeProblem, eps_r, sigma) -> tuple:
@@ -51,6 +53,10 @@ def _setup(problem: ProbeProblem, eps_r, sigma) -> tuple:
         st = s["sigma_t"] if "sigma_t" in s else s["sigma_t_steps"] * dt
         g.set_source(s["axis"], s["i"], s["j"], s["k"], s.get("i_max", 1.0), st)
     g.set_probe(problem.probe_lo, problem.probe_hi)
+    if problem.autotune:
+        g.autotune(dt, reps=3)
+    if problem.adjoint_tile is not None:
+        g.adjoint_set_tuning(*problem.adjoint_tile)
     return g, dt
 
 

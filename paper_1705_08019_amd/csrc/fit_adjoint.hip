@@ -7,242 +7,370 @@
 // Reverse step m (lambda = dJ/de, mu = dJ/dh, both zero beyond the horizon):
 //   lambda^(m+1) = a lambda^(m+2) - C~ (d mu^(m+3/2)) + 2 dt w M_eps e^(m+1)
 //   mu^(m+1/2)   = mu^(m+3/2) + C (b lambda^(m+1))
-//   dJ/dM_eps += lambda^(m+1) (da/dM_eps e^m + db/dM_eps s^m) + dt w (e^(m+1))^2
-//   dJ/dM_sig += lambda^(m+1) (da/dM_sig e^m + db/dM_sig s^m)
-// Because C~ = C^T, the two reverse passes are the forward stencils with the
-// roles swapped: k_adj_e applies the dual curl (backward differences) to
-// d mu, k_adj_h the primal curl (forward differences) to tau = b lambda.
-// The last kernel gathers the per-edge sensitivities onto the cells
-// (M_eps of an edge is eps0 g_a / 4 times the sum of its 4 cells' eps_r).
+//   dJ/dM_eps(edge) += lambda^(m+1) (da/dM_eps e^m + db/dM_eps s^m) + dt w (e^(m+1))^2
+//   dJ/dM_sig(edge) += lambda^(m+1) (da/dM_sig e^m + db/dM_sig s^m)
+// and, since M_eps of an edge is (g_a / 4) times the sum of its 4 cells'
+// eps0 eps_r (M_sigma likewise without eps0), each step's edge sensitivities
+// go straight onto the cells: dJ/deps_r(c) += eps0 (g_a / 4) dJ/dM_eps summed
+// over the 12 edges of cell c (FP64 accumulators, one per cell and quantity).
+//
+// Because C~ = C^T the reverse step has the shape of the forward one (the
+// dual curl with backward differences feeds lambda, the primal curl with
+// forward differences feeds mu), so it runs as one fused z-march per step
+// like k_step: a tw x ty column tile walks its z-chunk; per plane k it stages
+// h^(m+1/2), mu^(m+3/2), eps and sigma of plane k in LDS (double-buffered;
+// the z neighbours below are carried in registers), forms lambda^(m+1),
+// tau = b lambda^(m+1) and the FP64 edge sensitivities of plane k on the tile
+// and on a +x / +y halo (recomputed, so tiles need no ordering; the halo points
+// have threads of their own, so no wave does two points), then mu^(m+1/2) of
+// plane k-1 from tau of planes k-1 (LDS) and k (registers), and adds the
+// sensitivities of the 12 edges of each cell of plane k-1 to the per-cell
+// accumulators.  lambda and mu ping-pong between two buffer sets.
 // mu (permeability) must be uniform here.
 #include "fit_internal.hpp"
 
 namespace fit {
 
+template <typename T>
+__device__ __forceinline__ T ald(const T* p, int64_t i) {
+  return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+template <typename T>
+__device__ __forceinline__ void ast(T* p, int64_t i, T v) {
+  ((__attribute__((address_space(1))) T*)p)[i] = v;
+}
+
+// 1 / x for x > 0 in FP64: the hardware estimate refined by two Newton steps
+// (error a few ulp; the FP64 divide sequence costs several times more).
+__device__ __forceinline__ double rcp_d(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(r, fma(-x, r, 1.0), r);
+  r = fma(r, fma(-x, r, 1.0), r);
+  return r;
+}
+
+// Ring entries per thread: (tw + 2)(ty + 2) <= 3 nthr (host-checked).
+constexpr int kAdjRing = 3;
+
+// z-neighbour (plane k-1) values of one point, carried between iterations.
+template <typename T>
+struct AdjPrev {
+  T hx, hy, ux, uy, uz, Sx, Sy, Sxs, Sys;
+};
+
+// Threads: t < tw ty own tile column (t mod tw, t div tw); the next
+// tw + ty + 1 threads own one halo point each (the +y row, then the +x
+// column with the corner); the rest only stage planes.
 template <typename T, bool LOSSY>
-__global__ __launch_bounds__(512) void k_adj_e(AdjArgs<T> A) {
+__global__ __launch_bounds__(512) void k_adj(AdjArgs<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   const Dims d = A.d;
+  const int TW = A.t.tw, TY = A.t.ty;
+  const int RW = TW + 2, RP = RW * (TY + 2);
+  const int EW = TW + 1, EP = EW * (TY + 1);
+  double* qL = reinterpret_cast<double*>(smem_raw);   // [6][EP] scaled sensitivities of plane k
+  T* rL0 = reinterpret_cast<T*>(qL + 6 * EP);         // [2][8][RP] h xyz, mu xyz, eps, sigma
+  T* tL = rL0 + 16 * RP;                              // [2][3][EP] tau of planes k, k-1
+
   const int64_t lt = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = (int)(lt % A.t.ntx);
-  const int64_t rr = lt / A.t.ntx;
-  const int tyi = (int)(rr % A.t.nty);
-  const int kz = (int)(rr / A.t.nty);
-  const int i = tx * 64 + (int)threadIdx.x;
-  const int j = tyi * A.t.ty + (int)threadIdx.y;
+  const int64_t rr_ = lt / A.t.ntx;
+  const int tyi = (int)(rr_ % A.t.nty);
+  const int kz = (int)(rr_ / A.t.nty);
+  const int i0 = tx * TW, j0 = tyi * TY;
   const int k0 = kz * A.t.kc;
   const int k1 = min(k0 + A.t.kc, d.nz);
-  if (i >= d.nx || j >= d.ny) return;
-  const bool ip = i > 0, jp = j > 0;
-  const int64_t sx = d.sx, sxy = d.sxy;
-  const T* __restrict__ hx = A.h[0];
-  const T* __restrict__ hy = A.h[1];
-  const T* __restrict__ hz = A.h[2];
-  const T* __restrict__ ux = A.mu[0];
-  const T* __restrict__ uy = A.mu[1];
-  const T* __restrict__ uz = A.mu[2];
-  const T* __restrict__ eps = A.eps;
-  const T* __restrict__ sig = A.sig;
-  int64_t idx = i + sx * j + sxy * (int64_t)k0;
-  T hyp = 0, hxp = 0, uyp = 0, uxp = 0, sxe = 0, sye = 0, sxs = 0, sys = 0;
-  if (k0 > 0) {
-    const int64_t q = idx - sxy;
-    hyp = hy[q];
-    hxp = hx[q];
-    uyp = uy[q];
-    uxp = ux[q];
-    const T c = eps[q];
-    sxe = c + (ip ? eps[q - 1] : T(0));
-    sye = c + (jp ? eps[q - sx] : T(0));
-    if (LOSSY) {
-      const T s = sig[q];
-      sxs = s + (ip ? sig[q - 1] : T(0));
-      sys = s + (jp ? sig[q - sx] : T(0));
+  const int tid = (int)(threadIdx.x + threadIdx.y * blockDim.x);
+  const int nthr = (int)(blockDim.x * blockDim.y);
+  const int NO = TW * TY;
+  const bool act = tid < NO;                                // owns a tile column
+  const bool hal = tid >= NO && tid < NO + TW + TY + 1;     // owns a halo point
+  const int hq = tid - NO;
+  // this thread's point (tile coordinates)
+  const int px = act ? tid % TW : (hq < TW ? hq : TW);
+  const int py = act ? tid / TW : (hq < TW ? TY : hq - TW);
+  const int pi = i0 + px, pj = j0 + py;
+  const bool pvalid = (act || hal) && pi < d.nx && pj < d.ny;
+  const bool own = act && pvalid;
+  const int64_t sx = d.sx, sxy = d.sxy, n = d.n;
+
+  auto ring = [&](int x, int y) { return (y + 1) * RW + (x + 1); };
+  auto ext = [&](int x, int y) { return y * EW + x; };
+
+  // ---- register prefetch: the ring entries of a plane, and this thread's
+  // point values lambda^(m+2) xyz, e^m xyz, e^(m+1) xyz
+  T pre[kAdjRing][8];
+  T pv[9];
+  auto fetch_ring = [&](int k) {
+#pragma unroll
+    for (int r = 0; r < kAdjRing; ++r) {
+      const int q = tid + r * nthr;
+      const int gx = i0 + (q % RW) - 1, gy = j0 + (q / RW) - 1;
+      const bool in = q < RP && k >= 0 && k < d.nz && gx >= 0 && gx < d.nx && gy >= 0 &&
+                      gy < d.ny;
+      const int64_t g = gx + sx * gy + sxy * (int64_t)k;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        pre[r][c] = in ? ald(A.h, g + c * n) : T(0);
+        pre[r][3 + c] = in ? ald(A.mu0, g + c * n) : T(0);
+      }
+      pre[r][6] = in ? ald(A.eps, g) : T(0);
+      pre[r][7] = (LOSSY && in) ? ald(A.sig, g) : T(0);
     }
-  }
-  const bool pi_x = i >= A.probe.lo[0] && i + 1 <= A.probe.hi[0];
-  const bool pi_yz = i >= A.probe.lo[0] && i <= A.probe.hi[0];
-  const bool pj_y = j >= A.probe.lo[1] && j + 1 <= A.probe.hi[1];
-  const bool pj_xz = j >= A.probe.lo[1] && j <= A.probe.hi[1];
-  for (int k = k0; k < k1; ++k, idx += sxy) {
-    // dual curl of h (for s^m) and of d mu
-    const T hxc = hx[idx], hyc = hy[idx], hzc = hz[idx];
-    const T hz_jm = jp ? hz[idx - sx] : T(0), hx_jm = jp ? hx[idx - sx] : T(0);
-    const T hy_im = ip ? hy[idx - 1] : T(0), hz_im = ip ? hz[idx - 1] : T(0);
-    const T uxc = ux[idx], uyc = uy[idx], uzc = uz[idx];
-    const T uz_jm = jp ? uz[idx - sx] : T(0), ux_jm = jp ? ux[idx - sx] : T(0);
-    const T uy_im = ip ? uy[idx - 1] : T(0), uz_im = ip ? uz[idx - 1] : T(0);
-    T sx_ = (hzc - hz_jm) - (hyc - hyp);
-    T sy_ = (hxc - hxp) - (hzc - hz_im);
-    T sz_ = (hyc - hy_im) - (hxc - hx_jm);
-    if (idx == A.src_idx) {
-      if (A.src_comp == 0) sx_ -= A.src_val;
-      if (A.src_comp == 1) sy_ -= A.src_val;
-      if (A.src_comp == 2) sz_ -= A.src_val;
+  };
+  auto fetch_pt = [&](int k) {
+    const bool lo = k >= 0 && k < d.nz && pvalid;
+    const int64_t g = pi + sx * pj + sxy * (int64_t)k;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      pv[c] = lo ? ald(A.lam0, g + c * n) : T(0);
+      pv[3 + c] = lo ? ald(A.em, g + c * n) : T(0);
+      pv[6 + c] = lo ? ald(A.em1, g + c * n) : T(0);
     }
-    const T gx = A.dmu[2] * (uzc - uz_jm) - A.dmu[1] * (uyc - uyp);
-    const T gy = A.dmu[0] * (uxc - uxp) - A.dmu[2] * (uzc - uz_im);
-    const T gz = A.dmu[1] * (uyc - uy_im) - A.dmu[0] * (uxc - ux_jm);
-    // materials
-    const T c = eps[idx];
-    const T c_im = ip ? eps[idx - 1] : T(0);
-    const T c_jm = jp ? eps[idx - sx] : T(0);
-    const T c_ijm = (ip && jp) ? eps[idx - sx - 1] : T(0);
-    const T Sx = c + c_im, Sy = c + c_jm, Sxj = c_jm + c_ijm;
-    const T E4[3] = {sye + Sy, sxe + Sx, Sx + Sxj};
-    T S4[3] = {0, 0, 0};
-    T Sxs = 0, Sys = 0;
+  };
+  auto stage = [&](T* rL) {
+#pragma unroll
+    for (int r = 0; r < kAdjRing; ++r) {
+      const int q = tid + r * nthr;
+      if (q < RP) {
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          if (LOSSY || c < 7) rL[c * RP + q] = pre[r][c];
+      }
+    }
+  };
+  // plane-(k-1) values of point (x, y), read from a staged ring
+  auto take_prev = [&](const T* rL, int x, int y, AdjPrev<T>& p) {
+    const int r = ring(x, y), rim = ring(x - 1, y), rjm = ring(x, y - 1);
+    p.hx = rL[0 * RP + r];
+    p.hy = rL[1 * RP + r];
+    p.ux = rL[3 * RP + r];
+    p.uy = rL[4 * RP + r];
+    p.uz = rL[5 * RP + r];
+    const T c = rL[6 * RP + r];
+    p.Sx = c + rL[6 * RP + rim];
+    p.Sy = c + rL[6 * RP + rjm];
+    p.Sxs = p.Sys = T(0);
     if (LOSSY) {
-      const T s = sig[idx];
-      const T s_im = ip ? sig[idx - 1] : T(0);
-      const T s_jm = jp ? sig[idx - sx] : T(0);
-      const T s_ijm = (ip && jp) ? sig[idx - sx - 1] : T(0);
+      const T s = rL[7 * RP + r];
+      p.Sxs = s + rL[7 * RP + rim];
+      p.Sys = s + rL[7 * RP + rjm];
+    }
+  };
+
+  // lambda^(m+1), tau and the scaled edge sensitivities at point (x, y) of
+  // plane k (ring rL); v = lambda^(m+2), e^m, e^(m+1) there; p = its
+  // plane-(k-1) values (replaced by those of plane k on return).
+  auto lam_point = [&](const T* rL, int x, int y, int k, bool valid, const T* v, AdjPrev<T>& p,
+                       T* lam, T* tau, double* qe, double* qs) {
+    const int r = ring(x, y), rim = ring(x - 1, y), rjm = ring(x, y - 1), rijm = ring(x - 1, y - 1);
+    const T hxc = rL[0 * RP + r], hyc = rL[1 * RP + r], hzc = rL[2 * RP + r];
+    const T hz_jm = rL[2 * RP + rjm], hx_jm = rL[0 * RP + rjm];
+    const T hy_im = rL[1 * RP + rim], hz_im = rL[2 * RP + rim];
+    const T uxc = rL[3 * RP + r], uyc = rL[4 * RP + r], uzc = rL[5 * RP + r];
+    const T uz_jm = rL[5 * RP + rjm], ux_jm = rL[3 * RP + rjm];
+    const T uy_im = rL[4 * RP + rim], uz_im = rL[5 * RP + rim];
+    const int gi = i0 + x, gj = j0 + y;
+    const int64_t g = gi + sx * gj + sxy * (int64_t)k;
+    // s^m = C~ h^(m+1/2) - j_s
+    T s0 = (hzc - hz_jm) - (hyc - p.hy);
+    T s1 = (hxc - p.hx) - (hzc - hz_im);
+    T s2 = (hyc - hy_im) - (hxc - hx_jm);
+    if (valid && g == A.src_idx) {
+      if (A.src_comp == 0) s0 -= A.src_val;
+      if (A.src_comp == 1) s1 -= A.src_val;
+      if (A.src_comp == 2) s2 -= A.src_val;
+    }
+    const T sv[3] = {s0, s1, s2};
+    // C~ (d mu^(m+3/2))
+    const T gv[3] = {A.dmu[2] * (uzc - uz_jm) - A.dmu[1] * (uyc - p.uy),
+                     A.dmu[0] * (uxc - p.ux) - A.dmu[2] * (uzc - uz_im),
+                     A.dmu[1] * (uyc - uy_im) - A.dmu[0] * (uxc - ux_jm)};
+    // materials: sums of the 4 cells around each edge
+    const T c = rL[6 * RP + r], c_im = rL[6 * RP + rim], c_jm = rL[6 * RP + rjm],
+            c_ijm = rL[6 * RP + rijm];
+    const T Sx = c + c_im, Sy = c + c_jm;
+    const T E4[3] = {p.Sy + Sy, p.Sx + Sx, Sx + (c_jm + c_ijm)};
+    T S4[3] = {T(0), T(0), T(0)};
+    T Sxs = T(0), Sys = T(0);
+    if (LOSSY) {
+      const T s = rL[7 * RP + r], s_im = rL[7 * RP + rim], s_jm = rL[7 * RP + rjm],
+              s_ijm = rL[7 * RP + rijm];
       Sxs = s + s_im;
       Sys = s + s_jm;
-      S4[0] = sys + Sys;
-      S4[1] = sxs + Sxs;
+      S4[0] = p.Sys + Sys;
+      S4[1] = p.Sxs + Sxs;
       S4[2] = Sxs + (s_jm + s_ijm);
     }
-    const bool live[3] = {jp && k > 0, ip && k > 0, ip && jp};
+    const bool live[3] = {valid && gj > 0 && k > 0, valid && gi > 0 && k > 0,
+                          valid && gi > 0 && gj > 0};
+    const bool pi_x = gi >= A.probe.lo[0] && gi + 1 <= A.probe.hi[0];
+    const bool pi_yz = gi >= A.probe.lo[0] && gi <= A.probe.hi[0];
+    const bool pj_y = gj >= A.probe.lo[1] && gj + 1 <= A.probe.hi[1];
+    const bool pj_xz = gj >= A.probe.lo[1] && gj <= A.probe.hi[1];
     const bool kx = k >= A.probe.lo[2] && k <= A.probe.hi[2];
     const bool kz_ = k >= A.probe.lo[2] && k + 1 <= A.probe.hi[2];
     const bool inp[3] = {pi_x && pj_xz && kx, pi_yz && pj_y && kx, pi_yz && pj_xz && kz_};
-    const T sv[3] = {sx_, sy_, sz_};
-    const T gv[3] = {gx, gy, gz};
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const int64_t o = a * d.n + idx;
-      const double Me = A.ge[a] * (double)E4[a];
+      const T E = live[a] ? E4[a] : T(1);   // finite denominators on dead / outside points
+      const double Me = A.ge[a] * (double)E;
       const double Ms = A.ge[a] * (double)S4[a];
-      const double Dd = Me + A.hdt * Ms;
-      const T em = A.em[o], em1 = A.em1[o], lo = A.lam[o];
-      const T Dt = E4[a] + A.hs * S4[a];
-      const T ca = LOSSY ? (E4[a] - A.hs * S4[a]) / Dt : T(1);
+      const T Dt = E + A.hs * S4[a];
+      const T ca = LOSSY ? (E - A.hs * S4[a]) / Dt : T(1);
       const T cb = A.kb[a] / Dt;
-      T ln = ca * lo - gv[a];
+      const T em = v[3 + a], em1 = v[6 + a];
+      T ln = ca * v[a] - gv[a];
       double probe_e2 = 0.0;
       if (inp[a]) {
         probe_e2 = (double)em1 * (double)em1;
         ln += (T)(2.0 * A.dt * Me * (double)em1);
       }
       ln = live[a] ? ln : T(0);
-      A.lam[o] = ln;
-      A.tau[o] = live[a] ? cb * ln : T(0);
-      if (live[a]) {
-        const double l = ln;
-        const double inv2 = 1.0 / (Dd * Dd);
-        const double da_dMe = A.dt * Ms * inv2, db_dMe = -A.dt * inv2;
-        const double da_dMs = -A.dt * Me * inv2, db_dMs = -0.5 * A.dt * A.dt * inv2;
-        A.gMe[o] += l * (da_dMe * (double)em + db_dMe * (double)sv[a]) + A.dt * probe_e2;
-        A.gMs[o] += l * (da_dMs * (double)em + db_dMs * (double)sv[a]);
+      lam[a] = ln;
+      tau[a] = cb * ln;
+      // da/dM_eps = dt M_sig / D^2, db/dM_eps = -dt / D^2,
+      // da/dM_sig = -dt M_eps / D^2, db/dM_sig = -dt^2 / (2 D^2)
+      const double Dd = Me + A.hdt * Ms;
+      const double f = (double)ln * A.dt * rcp_d(Dd * Dd);
+      qe[a] = A.eps0 * A.ge[a] * (f * (Ms * (double)em - (double)sv[a]) + A.dt * probe_e2);
+      qs[a] = A.ge[a] * (-f * (Me * (double)em + A.hdt * (double)sv[a]));
+      if (!live[a]) qe[a] = qs[a] = 0.0;
+    }
+    p.hx = hxc;
+    p.hy = hyc;
+    p.ux = uxc;
+    p.uy = uyc;
+    p.uz = uzc;
+    p.Sx = Sx;
+    p.Sy = Sy;
+    p.Sxs = Sxs;
+    p.Sys = Sys;
+  };
+
+  // prologue: plane k0 - 1 (zeros below the grid) gives the carried values
+  AdjPrev<T> pvp{};
+  fetch_ring(k0 - 1);
+  stage(rL0 + 8 * RP);
+  __syncthreads();
+  if (act || hal) take_prev(rL0 + 8 * RP, px, py, pvp);
+  fetch_ring(k0);
+  fetch_pt(k0);
+  double Ae = 0.0, Ze = 0.0, As = 0.0, Zs = 0.0;   // own cell: partial sums of plane k-1
+
+  for (int k = k0; k <= k1; ++k) {
+    const bool plane = k < d.nz;
+    // the accumulators of cell (i, j, k-1), updated at the end of this iteration
+    const bool cell = own && k > k0;
+    const int64_t cidx = pi + sx * pj + sxy * (int64_t)(k - 1);
+    const double ge0 = cell ? ald(A.geps, cidx) : 0.0;
+    const double gs0 = cell ? ald(A.gsig, cidx) : 0.0;
+    // ring of plane k: buffer k & 1 (the other one may still be read for k-1)
+    T* rL = rL0 + (k & 1) * 8 * RP;
+    stage(rL);
+    if (k + 1 <= k1) fetch_ring(k + 1);   // in flight during the compute below
+    __syncthreads();   // ring k staged; every read of qL from iteration k-1 is done
+    T* tk = tL + (k & 1) * 3 * EP;               // tau of plane k
+    const T* tq = tL + ((k & 1) ^ 1) * 3 * EP;   // tau of plane k-1
+    const T mux = pvp.ux, muy = pvp.uy, muz = pvp.uz;   // mu^(m+3/2) of plane k-1
+    T tau_o[3] = {T(0), T(0), T(0)};
+    if (act || hal) {
+      T lam[3];
+      double qe[3], qs[3];
+      lam_point(rL, px, py, k, plane && pvalid, pv, pvp, lam, tau_o, qe, qs);
+      const int e = ext(px, py);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        tau_o[a] = plane ? tau_o[a] : T(0);
+        tk[a * EP + e] = tau_o[a];
+        qL[a * EP + e] = plane ? qe[a] : 0.0;
+        qL[(3 + a) * EP + e] = plane ? qs[a] : 0.0;
+      }
+      if (plane && own && k < k1) {
+        const int64_t g = pi + sx * pj + sxy * (int64_t)k;
+#pragma unroll
+        for (int a = 0; a < 3; ++a) ast(A.lam1, g + a * n, lam[a]);
       }
     }
-    hyp = hyc;
-    hxp = hxc;
-    uyp = uyc;
-    uxp = uxc;
-    sxe = Sx;
-    sye = Sy;
-    if (LOSSY) {
-      sxs = Sxs;
-      sys = Sys;
+    if (k + 1 <= k1) fetch_pt(k + 1);   // in flight during the mu update and the cell sums
+    // mu^(m+1/2) of plane k-1 = mu^(m+3/2) + C tau (forward differences)
+    if (k > k0 && own) {
+      const int km = k - 1;
+      const int e = ext(px, py), e_in = ext(px + 1, py), e_jn = ext(px, py + 1);
+      const T txc = tq[e], tyc = tq[EP + e], tzc = tq[2 * EP + e];
+      const T cx = (tq[2 * EP + e_jn] - tzc) - (tau_o[1] - tyc);
+      const T cy = (tau_o[0] - txc) - (tq[2 * EP + e_in] - tzc);
+      const T cz = (tq[EP + e_in] - tyc) - (tq[e_jn] - txc);
+      const int64_t gm = pi + sx * pj + sxy * (int64_t)km;
+      ast(A.mu1, gm, pi > 0 ? mux + cx : T(0));
+      ast(A.mu1, gm + n, pj > 0 ? muy + cy : T(0));
+      ast(A.mu1, gm + 2 * n, km > 0 ? muz + cz : T(0));
+    }
+    __syncthreads();
+    // the 12 edges of cell (i, j, k-1): x-edges (i, j..j+1) and y-edges
+    // (i..i+1, j) of planes k-1 and k, z-edges (i..i+1, j..j+1) of plane k-1
+    if (own) {
+      const int e = ext(px, py), e_in = ext(px + 1, py), e_jn = ext(px, py + 1),
+                e_ijn = ext(px + 1, py + 1);
+      const double Ae_k = (qL[e] + qL[e_jn]) + (qL[EP + e] + qL[EP + e_in]);
+      const double Ze_k =
+          (qL[2 * EP + e] + qL[2 * EP + e_in]) + (qL[2 * EP + e_jn] + qL[2 * EP + e_ijn]);
+      const double As_k = (qL[3 * EP + e] + qL[3 * EP + e_jn]) + (qL[4 * EP + e] + qL[4 * EP + e_in]);
+      const double Zs_k =
+          (qL[5 * EP + e] + qL[5 * EP + e_in]) + (qL[5 * EP + e_jn] + qL[5 * EP + e_ijn]);
+      if (cell) {
+        ast(A.geps, cidx, ge0 + ((Ae + Ze) + Ae_k));
+        ast(A.gsig, cidx, gs0 + ((As + Zs) + As_k));
+      }
+      Ae = Ae_k;
+      Ze = Ze_k;
+      As = As_k;
+      Zs = Zs_k;
     }
   }
 }
 
-// mu^(m+1/2) = mu^(m+3/2) + C tau   (in place; C by forward differences)
-template <typename T>
-__global__ __launch_bounds__(512) void k_adj_h(AdjArgs<T> A) {
-  const Dims d = A.d;
-  const int64_t lt = xcd_remap(blockIdx.x, gridDim.x);
-  const int tx = (int)(lt % A.t.ntx);
-  const int64_t rr = lt / A.t.ntx;
-  const int tyi = (int)(rr % A.t.nty);
-  const int kz = (int)(rr / A.t.nty);
-  const int i = tx * 64 + (int)threadIdx.x;
-  const int j = tyi * A.t.ty + (int)threadIdx.y;
-  const int k0 = kz * A.t.kc;
-  const int k1 = min(k0 + A.t.kc, d.nz);
-  if (i >= d.nx || j >= d.ny) return;
-  const int64_t sx = d.sx, sxy = d.sxy;
-  const T* __restrict__ tx_ = A.tau;
-  const T* __restrict__ ty_ = A.tau + d.n;
-  const T* __restrict__ tz_ = A.tau + 2 * d.n;
-  const bool in_ = i + 1 < d.nx, jn = j + 1 < d.ny;
-  int64_t idx = i + sx * j + sxy * (int64_t)k0;
-  T txc = tx_[idx], tyc = ty_[idx];
-  for (int k = k0; k < k1; ++k, idx += sxy) {
-    const bool kn = k + 1 < d.nz;
-    const T txn = kn ? tx_[idx + sxy] : T(0);
-    const T tyn = kn ? ty_[idx + sxy] : T(0);
-    const T tzc = tz_[idx];
-    const T tz_jn = jn ? tz_[idx + sx] : T(0);
-    const T tz_in = in_ ? tz_[idx + 1] : T(0);
-    const T ty_in = in_ ? ty_[idx + 1] : T(0);
-    const T tx_jn = jn ? tx_[idx + sx] : T(0);
-    const T cx = (tz_jn - tzc) - (tyn - tyc);
-    const T cy = (txn - txc) - (tz_in - tzc);
-    const T cz = (ty_in - tyc) - (tx_jn - txc);
-    T* ux = A.mu[0];
-    T* uy = A.mu[1];
-    T* uz = A.mu[2];
-    ux[idx] = i > 0 ? ux[idx] + cx : T(0);
-    uy[idx] = j > 0 ? uy[idx] + cy : T(0);
-    uz[idx] = k > 0 ? uz[idx] + cz : T(0);
-    txc = txn;
-    tyc = tyn;
-  }
+size_t adjoint_lds_bytes(int tw, int ty, size_t esz) {
+  const size_t RP = (size_t)(tw + 2) * (ty + 2), EP = (size_t)(tw + 1) * (ty + 1);
+  return 6 * EP * sizeof(double) + (16 * RP + 6 * EP) * esz;
 }
 
-// dJ/deps_r[c] = eps0 sum over the 12 edges of cell c of (g_a / 4) dJ/dM_eps;
-// dJ/dsigma[c] likewise with dJ/dM_sigma (no eps0).
-__global__ __launch_bounds__(256) void k_adj_gather(const double* gMe, const double* gMs, Dims d,
-                                                    double gq0, double gq1, double gq2,
-                                                    double eps0, double* deps, double* dsig) {
-  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= d.n) return;
-  const int i = (int)(c % d.nx);
-  const int64_t r = c / d.nx;
-  const int j = (int)(r % d.ny);
-  const int k = (int)(r / d.ny);
-  const double gq[3] = {gq0, gq1, gq2};
-  double se = 0.0, ss = 0.0;
-  // edges of direction a around the cell: its two transverse node indices are
-  // (p_b, p_b + 1) x (p_c, p_c + 1); slots beyond the grid are PEC walls (0)
-  const int p[3] = {i, j, k};
-  const int nn[3] = {d.nx, d.ny, d.nz};
-  const int64_t st[3] = {1, d.sx, d.sxy};
-  for (int a = 0; a < 3; ++a) {
-    const int b = (a + 1) % 3, cc = (a + 2) % 3;
-    for (int db = 0; db < 2; ++db) {
-      for (int dc = 0; dc < 2; ++dc) {
-        const int qb = p[b] + db, qc = p[cc] + dc;
-        if (qb >= nn[b] || qc >= nn[cc]) continue;
-        const int64_t o = a * d.n + c + db * st[b] + dc * st[cc];
-        se += gq[a] * gMe[o];
-        ss += gq[a] * gMs[o];
-      }
-    }
+int adjoint_threads(int tw, int ty) { return ((tw * ty + tw + ty + 1 + 63) / 64) * 64; }
+
+template <typename T, bool LOSSY>
+static int adj_occupancy(int nthreads, size_t lds) {
+  const void* fn = reinterpret_cast<const void*>(&k_adj<T, LOSSY>);
+  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  int nb = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nthreads, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
   }
-  deps[c] = eps0 * se;
-  dsig[c] = ss;
+  return nb;
+}
+
+int adjoint_blocks_per_cu(int tw, int ty, size_t esz, bool lossy) {
+  const int nt = adjoint_threads(tw, ty);
+  const size_t lds = adjoint_lds_bytes(tw, ty, esz);
+  if (esz == 8)
+    return lossy ? adj_occupancy<double, true>(nt, lds) : adj_occupancy<double, false>(nt, lds);
+  return lossy ? adj_occupancy<float, true>(nt, lds) : adj_occupancy<float, false>(nt, lds);
 }
 
 template <typename T>
 hipError_t launch_adjoint_step(const AdjArgs<T>& a, bool lossy, hipStream_t s) {
-  const dim3 blk(64, a.t.ty), grd((unsigned)a.t.blocks());
-  if (lossy) hipLaunchKernelGGL((k_adj_e<T, true>), grd, blk, 0, s, a);
-  else hipLaunchKernelGGL((k_adj_e<T, false>), grd, blk, 0, s, a);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_adj_h<T>, grd, blk, 0, s, a);
-  return hipGetLastError();
-}
-
-hipError_t launch_adjoint_gather(const double* gMe, const double* gMs, const Dims& d,
-                                 const double gq[3], double eps0, double* deps, double* dsig,
-                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_adj_gather, dim3((unsigned)((d.n + 255) / 256)), dim3(256), 0, s, gMe, gMs,
-                     d, gq[0], gq[1], gq[2], eps0, deps, dsig);
+  const int nt = adjoint_threads(a.t.tw, a.t.ty);
+  const size_t lds = adjoint_lds_bytes(a.t.tw, a.t.ty, sizeof(T));
+  const void* fn = lossy ? reinterpret_cast<const void*>(&k_adj<T, true>)
+                         : reinterpret_cast<const void*>(&k_adj<T, false>);
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  if (lossy)
+    hipLaunchKernelGGL((k_adj<T, true>), dim3((unsigned)a.t.blocks()), dim3(nt), lds, s, a);
+  else
+    hipLaunchKernelGGL((k_adj<T, false>), dim3((unsigned)a.t.blocks()), dim3(nt), lds, s, a);
   return hipGetLastError();
 }
 

@@ -43,6 +43,26 @@ void dev_free(void*& p) {
   p = nullptr;
 }
 
+// Probe accumulator rows for `rows` workgroups; on growth the rows so far
+// are first folded into the probe total.
+int ensure_pacc(fit_grid* g, int64_t rows) {
+  if (rows <= g->pacc_rows) return FIT_OK;
+  if (g->pacc) {
+    hipError_t e = launch_pacc_flush(g->pacc, g->pacc_rows, g->jacc, g->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(g->s);
+    if (e != hipSuccess) return hip_fail(e, "probe rows flush");
+    dev_free(reinterpret_cast<void*&>(g->pacc));
+  }
+  g->pacc_rows = 0;
+  int rc = dev_alloc(reinterpret_cast<void**>(&g->pacc), (size_t)rows * 2 * sizeof(double),
+                     "probe rows");
+  if (rc) return rc;
+  hipError_t e = hipMemsetAsync(g->pacc, 0, (size_t)rows * 2 * sizeof(double), g->s);
+  if (e != hipSuccess) return hip_fail(e, "probe rows clear");
+  g->pacc_rows = rows;
+  return FIT_OK;
+}
+
 int ensure_part(fit_grid* g, int64_t rows) {
   if (rows <= g->part_rows) return FIT_OK;
   if (g->part) {
@@ -74,10 +94,20 @@ void default_tiling(const Dims& d, int* ty, int* kc) {
 // Fused-kernel tiling: pick the z-chunk so that one round of resident
 // workgroups (LDS- and wave-limited) covers the grid once.
 void default_step_tiling(const Dims& d, size_t esz, bool lossy, int* ty, int* kc, int* tw) {
-  // tall tiles amortise the halo row; 16 rows (1024 threads) for FP32 when
-  // the grid is tall enough, 4 for FP64 (LDS); 64-wide rows
-  const int w = 64;
-  const int t = esz == 8 ? 4 : (d.ny >= 64 ? 16 : 8);
+  // 1024 threads (FP32) or 256 (FP64, LDS) in a tile whose width (128, 64
+  // or 32) wastes the fewest lanes on the x extent (ties: the wider); the
+  // autotuner refines this
+  const int nthr = esz == 8 ? 256 : 1024;
+  int w = 64, best = 1 << 30;
+  for (int c : {128, 64, 32}) {
+    if (nthr / c < 2) continue;
+    const int waste = ((d.nx + c - 1) / c) * c - d.nx;
+    if (waste < best) {
+      best = waste;
+      w = c;
+    }
+  }
+  const int t = std::min(16, nthr / w);
   int per_cu = step_blocks_per_cu(t, esz, lossy, w);
   if (per_cu <= 0) {   // no device information: estimate from LDS and waves
     const size_t lds = step_lds_bytes(t, esz, lossy, w) + 2048;
@@ -142,6 +172,8 @@ static void fill_eargs(fit_grid* g, EArgs<T>& a, const T* ein, T* eout, const T*
   a.src_val_d = (double)(T)val;
   a.probe = g->probe;
   a.part = g->part;
+  a.pacc = g->pacc;
+  a.pscale = dt;
 }
 
 template <typename T>
@@ -192,6 +224,9 @@ int step_once(fit_grid* g, double dt, const T* ein, T* eout, const T* hin, T* ho
   const Tiling t = make_tiling(g->d, g->ty, g->kc);
   const int64_t nb = t.blocks();
   if ((have_row || tr_next || probe) && ensure_part(g, nb)) return FIT_E_OOM;
+  if (probe) {
+    if (int rc = ensure_pacc(g, nb)) return rc;
+  }
   double* row = have_row ? g->trace + g->trace_rows * FIT_TRACE_COLS : nullptr;
   hipError_t e;
 
@@ -202,13 +237,12 @@ int step_once(fit_grid* g, double dt, const T* ein, T* eout, const T* hin, T* ho
     e = launch_epass<T>(ea, g->lossy, have_row, probe, g->s);
   }
   if (e != hipSuccess) return hip_fail(e, "e-update launch");
-  if (have_row || probe) {
+  if (have_row) {
     const int cols[kPartTerms] = {1, 2, 3, 8, 9, -1, -1, -1, -1, -1};
     const bool prev_ok = g->pend_m == m;
     ProfScope ps(g, FIT_PROF_REDUCE);
-    e = launch_reduce(g->part, nb, row, cols, probe ? PE_PROBE : -1, dt,
-                      probe ? g->jacc : nullptr, have_row && !prev_ok ? 4 : -1,
-                      have_row ? m : -1, have_row && prev_ok ? g->pend : nullptr, 4, g->s);
+    e = launch_reduce(g->part, nb, row, cols, -1, 0.0, nullptr, !prev_ok ? 4 : -1, m,
+                      prev_ok ? g->pend : nullptr, 4, g->s);
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
   }
 
@@ -279,22 +313,26 @@ int step_fused_io(fit_grid* g, double dt, const T* e0, const T* h0, T* e1, T* h1
   a.src_val_d = (double)(T)val;
   a.probe = g->probe;
   const int64_t nb = a.t.blocks();
-  if ((energy || probe) && ensure_part(g, nb)) return FIT_E_OOM;
+  if (energy && ensure_part(g, nb)) return FIT_E_OOM;
+  if (probe) {
+    if (int rc = ensure_pacc(g, nb)) return rc;
+  }
   a.part = g->part;
+  a.pacc = g->pacc;
+  a.pscale = dt;
   hipError_t e;
   {
     ProfScope ps(g, FIT_PROF_STEP);
     e = launch_step<T>(a, g->lossy, energy, probe, g->s);
   }
   if (e != hipSuccess) return hip_fail(e, "fused step launch");
-  if (have_row || probe) {
-    double* row = have_row ? g->trace + g->trace_rows * FIT_TRACE_COLS : nullptr;
+  if (have_row) {
+    double* row = g->trace + g->trace_rows * FIT_TRACE_COLS;
     const int cols[kPartTerms] = {1, 2, 3, 8, 9, -1, 5, 6, 7, -1};
     const bool prev_ok = g->pend_m == m;
     ProfScope ps(g, FIT_PROF_REDUCE);
-    e = launch_reduce(g->part, nb, row, cols, probe ? PE_PROBE : -1, dt,
-                      probe ? g->jacc : nullptr, have_row && !prev_ok ? 4 : -1,
-                      have_row ? m : -1, have_row && prev_ok ? g->pend : nullptr, 4, g->s);
+    e = launch_reduce(g->part, nb, row, cols, -1, 0.0, nullptr, !prev_ok ? 4 : -1, m,
+                      prev_ok ? g->pend : nullptr, 4, g->s);
     if (e != hipSuccess) return hip_fail(e, "reduce launch");
   }
   if (tr_next) {
@@ -516,6 +554,7 @@ int fit_grid_destroy(fit_grid* g) {
   dev_free(reinterpret_cast<void*&>(g->trace));
   dev_free(reinterpret_cast<void*&>(g->jacc));
   dev_free(reinterpret_cast<void*&>(g->pend));
+  dev_free(reinterpret_cast<void*&>(g->pacc));
   dev_free(reinterpret_cast<void*&>(g->gram_part));
   dev_free(reinterpret_cast<void*&>(g->gram_G));
   dev_free(reinterpret_cast<void*&>(g->gram_w[0]));
@@ -783,7 +822,10 @@ int fit_set_probe(fit_grid* g, const int32_t lo[3], const int32_t hi[3]) {
 int fit_probe_value(fit_grid* g, double* J) {
   if (!g || !J) return fail(FIT_E_INVALID, "null argument");
   double v[2];
-  hipError_t e = hipMemcpyAsync(v, g->jacc, 2 * sizeof(double), hipMemcpyDeviceToHost, g->s);
+  hipError_t e = hipSuccess;
+  if (g->pacc) e = launch_pacc_flush(g->pacc, g->pacc_rows, g->jacc, g->s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(v, g->jacc, 2 * sizeof(double), hipMemcpyDeviceToHost, g->s);
   if (e == hipSuccess) e = hipStreamSynchronize(g->s);
   if (e != hipSuccess) return hip_fail(e, "probe readback");
   *J = v[0] + v[1];
@@ -793,6 +835,8 @@ int fit_probe_value(fit_grid* g, double* J) {
 int fit_probe_reset(fit_grid* g) {
   if (!g) return fail(FIT_E_INVALID, "null handle");
   hipError_t e = hipMemsetAsync(g->jacc, 0, 2 * sizeof(double), g->s);
+  if (e == hipSuccess && g->pacc)
+    e = hipMemsetAsync(g->pacc, 0, (size_t)g->pacc_rows * 2 * sizeof(double), g->s);
   if (e != hipSuccess) return hip_fail(e, "probe reset");
   return FIT_OK;
 }

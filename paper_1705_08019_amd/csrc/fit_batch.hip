@@ -49,6 +49,8 @@ __device__ __forceinline__ void batch_args(const BatchGrid<T>& G, int p, T src, 
   a.src_val_d = 0.0;
   a.probe.on = 0;
   a.part = nullptr;
+  a.pacc = nullptr;
+  a.pscale = 0.0;
 }
 
 // One step of every grid: one workgroup per item of the step's item table.
@@ -69,9 +71,9 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs<T> B) {
   const int tyi = rr % G.t.nty;
   const int kz = rr / G.t.nty;
   if (G.lossy)
-    step_tile<T, true, false, false>(a, tx, tyi, kz, sm, nullptr);
+    step_tile<T, true, false, false>(a, tx, tyi, kz, sm, nullptr, nullptr);
   else
-    step_tile<T, false, false, false>(a, tx, tyi, kz, sm, nullptr);
+    step_tile<T, false, false, false>(a, tx, tyi, kz, sm, nullptr, nullptr);
 }
 
 template <typename T>

@@ -11,14 +11,52 @@ namespace fit {
 void grid_release_extras(fit_grid* g) {
   if (!g->adj) return;
   fit_adjoint_ws* w = g->adj;
-  dev_free(w->lam);
-  dev_free(w->mu);
-  dev_free(w->tau);
-  dev_free(reinterpret_cast<void*&>(w->gMe));
-  dev_free(reinterpret_cast<void*&>(w->gMs));
+  for (int q = 0; q < 2; ++q) {
+    dev_free(w->lam[q]);
+    dev_free(w->mu[q]);
+  }
   dev_free(reinterpret_cast<void*&>(w->gcell));
   delete w;
   g->adj = nullptr;
+}
+
+// Tile of the reverse-step kernel: the width (32, 64 or 128) that wastes the
+// fewest lanes on the x extent (ties: the wider), as many rows as fit 512
+// threads (FP32; 256 for FP64) together with the tw + ty + 1 halo threads,
+// and z-chunks sized so that one round of resident workgroups covers the grid.
+static Tiling adjoint_tiling(const fit_grid* g) {
+  const Dims& d = g->d;
+  const int nt = g->f64 ? 256 : 512;
+  int tw = 32, best = 1 << 30;
+  for (int w : {128, 64, 32}) {
+    if ((nt - w - 1) / (w + 1) < 2) continue;
+    const int waste = ((d.nx + w - 1) / w) * w - d.nx;
+    if (waste < best) {
+      best = waste;
+      tw = w;
+    }
+  }
+  int ty = (nt - tw - 1) / (tw + 1);
+  ty = std::max(1, std::min(ty, d.ny));
+  if (g->atw > 0) {
+    tw = g->atw;
+    ty = g->aty;
+  }
+  if (g->akc > 0) return make_tiling(d, ty, std::min(g->akc, d.nz), tw);
+  int per_cu = adjoint_blocks_per_cu(tw, ty, g->esz, g->lossy);
+  if (per_cu < 1) per_cu = 1;
+  int cus = 256, dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  (void)hipGetLastError();
+  const int64_t tiles = (int64_t)((d.nx + tw - 1) / tw) * ((d.ny + ty - 1) / ty);
+  const int64_t nkc = std::max<int64_t>(1, (int64_t)cus * per_cu / tiles);
+  int kc = (int)((d.nz + nkc - 1) / nkc);
+  kc = std::min(d.nz, std::max(kc, std::min(8, d.nz)));
+  return make_tiling(d, ty, kc, tw);
 }
 
 template <typename T>
@@ -28,24 +66,31 @@ static int adjoint_step_t(fit_grid* g, int64_t m, const void* e_m, const void* e
   const Dims& d = g->d;
   AdjArgs<T> a;
   const T* h = static_cast<const T*>(h_mh);
-  T* mu = static_cast<T*>(w->mu);
+  const T* em = static_cast<const T*>(e_m);
+  const T* em1 = static_cast<const T*>(e_m1);
+  const T* l0 = static_cast<const T*>(w->lam[w->cur]);
+  const T* u0 = static_cast<const T*>(w->mu[w->cur]);
+  T* l1 = static_cast<T*>(w->lam[w->cur ^ 1]);
+  T* u1 = static_cast<T*>(w->mu[w->cur ^ 1]);
+  a.h = h;
+  a.em = em;
+  a.em1 = em1;
+  a.lam0 = l0;
+  a.mu0 = u0;
+  a.lam1 = l1;
+  a.mu1 = u1;
   for (int c = 0; c < 3; ++c) {
-    a.h[c] = h + c * d.n;
-    a.mu[c] = mu + c * d.n;
     a.kb[c] = (T)(4.0 * w->dt / g->gedge[c]);
     a.dmu[c] = (T)(w->dt * g->gf2[c]) * ((T)g->imu_u + (T)g->imu_u);
     a.ge[c] = g->gedge[c] / 4.0;
   }
-  a.lam = static_cast<T*>(w->lam);
-  a.tau = static_cast<T*>(w->tau);
-  a.em = static_cast<const T*>(e_m);
-  a.em1 = static_cast<const T*>(e_m1);
+  a.eps0 = g->desc.eps0;
   a.eps = static_cast<const T*>(g->eps);
   a.sig = static_cast<const T*>(g->sig);
-  a.gMe = w->gMe;
-  a.gMs = w->gMs;
+  a.geps = w->gcell;
+  a.gsig = w->gcell + d.n;
   a.d = d;
-  a.t = make_tiling(d, g->ty, g->kc);
+  a.t = w->t;
   a.hs = (T)(0.5 * w->dt);
   a.dt = w->dt;
   a.hdt = 0.5 * w->dt;
@@ -59,6 +104,7 @@ static int adjoint_step_t(fit_grid* g, int64_t m, const void* e_m, const void* e
     e = launch_adjoint_step<T>(a, g->lossy, g->s);
   }
   if (e != hipSuccess) return hip_fail(e, "adjoint step launch");
+  w->cur ^= 1;
   g->smvp += 2;
   return FIT_OK;
 }
@@ -109,6 +155,23 @@ int fit_step_record(fit_grid* g, int64_t nsteps, double dt, void* e_rec, void* h
                 : record_t<float>(g, nsteps, dt, e_rec, h_rec);
 }
 
+int fit_adjoint_set_tuning(fit_grid* g, int tw, int ty, int kc) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  if ((tw == 0) != (ty == 0)) return fail(FIT_E_INVALID, "give both tw and ty, or neither");
+  if (tw < 0 || ty < 0 || kc < 0) return fail(FIT_E_INVALID, "negative tile size");
+  if (tw > 0) {
+    if (tw > 256) return fail(FIT_E_INVALID, "tw must be <= 256");
+    const int nt = adjoint_threads(tw, ty);
+    if (nt > 512 || (int64_t)(tw + 2) * (ty + 2) > 3 * (int64_t)nt ||
+        adjoint_lds_bytes(tw, ty, g->esz) > 160 * 1024)
+      return fail(FIT_E_INVALID, "adjoint tile does not fit a workgroup (tw ty + tw + ty + 1 <= 512)");
+  }
+  g->atw = tw;
+  g->aty = ty;
+  g->akc = kc;
+  return FIT_OK;
+}
+
 int fit_adjoint_begin(fit_grid* g, int64_t nsteps, double dt) {
   if (!g) return fail(FIT_E_INVALID, "null handle");
   if (nsteps < 1) return fail(FIT_E_INVALID, "nsteps must be >= 1");
@@ -119,12 +182,12 @@ int fit_adjoint_begin(fit_grid* g, int64_t nsteps, double dt) {
     g->adj = new (std::nothrow) fit_adjoint_ws();
     if (!g->adj) return fail(FIT_E_OOM, "host allocation failed");
     fit_adjoint_ws* w = g->adj;
-    const size_t fb = 3 * (size_t)g->d.n * g->esz, db = 3 * (size_t)g->d.n * sizeof(double);
-    int rc = dev_alloc(&w->lam, fb, "adjoint lambda");
-    if (!rc) rc = dev_alloc(&w->mu, fb, "adjoint mu");
-    if (!rc) rc = dev_alloc(&w->tau, fb, "adjoint tau");
-    if (!rc) rc = dev_alloc(reinterpret_cast<void**>(&w->gMe), db, "dJ/dM_eps");
-    if (!rc) rc = dev_alloc(reinterpret_cast<void**>(&w->gMs), db, "dJ/dM_sigma");
+    const size_t fb = 3 * (size_t)g->d.n * g->esz;
+    int rc = FIT_OK;
+    for (int q = 0; q < 2 && !rc; ++q) {
+      rc = dev_alloc(&w->lam[q], fb, "adjoint lambda");
+      if (!rc) rc = dev_alloc(&w->mu[q], fb, "adjoint mu");
+    }
     if (!rc)
       rc = dev_alloc(reinterpret_cast<void**>(&w->gcell), 2 * (size_t)g->d.n * sizeof(double),
                      "cell gradients");
@@ -134,12 +197,19 @@ int fit_adjoint_begin(fit_grid* g, int64_t nsteps, double dt) {
     }
   }
   fit_adjoint_ws* w = g->adj;
-  const size_t fb = 3 * (size_t)g->d.n * g->esz, db = 3 * (size_t)g->d.n * sizeof(double);
-  hipError_t e = hipMemsetAsync(w->lam, 0, fb, g->s);
-  if (e == hipSuccess) e = hipMemsetAsync(w->mu, 0, fb, g->s);
-  if (e == hipSuccess) e = hipMemsetAsync(w->tau, 0, fb, g->s);
-  if (e == hipSuccess) e = hipMemsetAsync(w->gMe, 0, db, g->s);
-  if (e == hipSuccess) e = hipMemsetAsync(w->gMs, 0, db, g->s);
+  w->t = adjoint_tiling(g);
+  {
+    const int nt = adjoint_threads(w->t.tw, w->t.ty);
+    if ((int64_t)(w->t.tw + 2) * (w->t.ty + 2) > 3 * (int64_t)nt || nt > 512 ||
+        adjoint_lds_bytes(w->t.tw, w->t.ty, g->esz) > 160 * 1024)
+      return fail(FIT_E_INVALID, "adjoint tile does not fit a workgroup");
+  }
+  const size_t fb = 3 * (size_t)g->d.n * g->esz;
+  w->cur = 0;
+  hipError_t e = hipMemsetAsync(w->lam[0], 0, fb, g->s);
+  if (e == hipSuccess) e = hipMemsetAsync(w->mu[0], 0, fb, g->s);
+  if (e == hipSuccess)
+    e = hipMemsetAsync(w->gcell, 0, 2 * (size_t)g->d.n * sizeof(double), g->s);
   if (e != hipSuccess) return hip_fail(e, "adjoint clear");
   w->N = nsteps;
   w->dt = dt;
@@ -178,14 +248,9 @@ int fit_adjoint_grad(fit_grid* g, double* deps, double* dsigma, int on_device) {
   if (!g || !deps || !dsigma) return fail(FIT_E_INVALID, "null argument");
   if (!g->adj) return fail(FIT_E_STATE, "no adjoint sweep");
   fit_adjoint_ws* w = g->adj;
-  double gq[3];
-  for (int a = 0; a < 3; ++a) gq[a] = g->gedge[a] / 4.0;
-  hipError_t e = launch_adjoint_gather(w->gMe, w->gMs, g->d, gq, g->desc.eps0, w->gcell,
-                                       w->gcell + g->d.n, g->s);
-  if (e != hipSuccess) return hip_fail(e, "gradient gather");
   const size_t b = (size_t)g->d.n * sizeof(double);
   const hipMemcpyKind k = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
-  e = hipMemcpyAsync(deps, w->gcell, b, k, g->s);
+  hipError_t e = hipMemcpyAsync(deps, w->gcell, b, k, g->s);
   if (e == hipSuccess) e = hipMemcpyAsync(dsigma, w->gcell + g->d.n, b, k, g->s);
   if (e == hipSuccess && !on_device) e = hipStreamSynchronize(g->s);
   if (e != hipSuccess) return hip_fail(e, "gradient copy");

@@ -12,12 +12,11 @@ struct fit_adjoint_ws {
   int64_t N = 0;          // forward horizon (steps)
   double dt = 0.0;
   int64_t next_m = -1;    // reverse step expected next (N-1 down to 0)
-  void* lam = nullptr;    // 3n, grid dtype
-  void* mu = nullptr;
-  void* tau = nullptr;
-  double* gMe = nullptr;  // 3n
-  double* gMs = nullptr;
-  double* gcell = nullptr;  // 2n: per-cell gradients
+  void* lam[2] = {nullptr, nullptr};   // 3n each, grid dtype; ping-pong
+  void* mu[2] = {nullptr, nullptr};
+  int cur = 0;            // buffer set holding lambda^(m+2), mu^(m+3/2)
+  double* gcell = nullptr;  // 2n: per-cell dJ/deps_r, dJ/dsigma accumulators
+  fit::Tiling t{};        // tile of the reverse-step kernel
 };
 
 struct fit_grid {
@@ -60,6 +59,9 @@ struct fit_grid {
   void* e_alt = nullptr;        // second buffer set of the fused (ping-pong) step
   void* h_alt = nullptr;
   fit_adjoint_ws* adj = nullptr;
+  int atw = 0, aty = 0, akc = 0;   // reverse-step tile (0: default)
+  double* pacc = nullptr;       // probe objective: per-workgroup (sum, compensation) rows
+  int64_t pacc_rows = 0;
   double* gram_part = nullptr;  // per-workgroup Gram blocks
   double* gram_G = nullptr;     // device K x K result
   int64_t gram_G_cap = 0;
@@ -80,6 +82,7 @@ int hip_fail(hipError_t e, const char* what);
 int dev_alloc(void** p, size_t bytes, const char* what);
 void dev_free(void*& p);
 int ensure_part(fit_grid* g, int64_t rows);
+int ensure_pacc(fit_grid* g, int64_t rows);
 double source_value(const fit_grid* g, double dt, int64_t m);
 int check_dt(const fit_grid* g, double dt);
 template <typename T>

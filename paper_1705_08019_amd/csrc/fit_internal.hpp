@@ -71,6 +71,8 @@ struct EArgs {
   double src_val_d;
   Probe probe;
   double* part;      // [blocks][kPartTerms] or null
+  double* pacc;      // probe objective: per-workgroup (sum, compensation) rows
+  double pscale;     // dt: weight of this step's probe term
 };
 
 template <typename T>
@@ -110,7 +112,9 @@ struct SArgs {
   T src_val;
   double src_val_d;
   Probe probe;
-  double* part;
+  double* part;      // [blocks][kPartTerms] (energy steps) or null
+  double* pacc;      // probe objective: per-workgroup (sum, compensation) rows
+  double pscale;     // dt: weight of this step's probe term
 };
 
 // Dynamic LDS bytes of the fused kernel for a tw x ty tile, and the number
@@ -133,27 +137,31 @@ template <typename T>
 hipError_t launch_gram(const T* X, int64_t ld, int K, const double* W, const Dims& d, double* part,
                        int64_t part_cap_blocks, double* G, hipStream_t s, int64_t* nwg_used);
 
-// Reverse-time adjoint step (fit_adjoint.hip).  lam, tau, em, em1 are
-// 3-component slot-layout arrays (component a at a * n); gMe, gMs per-edge
-// FP64 sensitivities dJ/dM_eps, dJ/dM_sigma.
+// Reverse-time adjoint step (fit_adjoint.hip): one fused pass per reverse
+// step.  All field arrays are slot-layout components; lambda and mu
+// ping-pong (read *0, write *1).  geps / gsig: per-cell FP64 accumulators of
+// dJ/deps_r and dJ/dsigma.
 template <typename T>
 struct AdjArgs {
-  const T* h[3];      // h^(m+1/2)
-  T* mu[3];           // mu^(m+3/2) -> mu^(m+1/2)
-  T* lam;             // lambda^(m+2) -> lambda^(m+1)
-  T* tau;             // b lambda^(m+1)
+  // 3-component slot-layout fields (component c at offset c n)
+  const T* h;         // h^(m+1/2)
   const T* em;        // e^m
   const T* em1;       // e^(m+1)
+  const T* lam0;      // lambda^(m+2)
+  const T* mu0;       // mu^(m+3/2)
+  T* lam1;            // lambda^(m+1)
+  T* mu1;             // mu^(m+1/2)
   const T* eps;
   const T* sig;
-  double* gMe;
-  double* gMs;
+  double* geps;
+  double* gsig;
   Dims d;
   Tiling t;
   T kb[3];
   T hs;
   T dmu[3];           // dt M_mu^{-1} per facet direction (uniform mu)
-  double ge[3];
+  double ge[3];       // M_eps = ge E4 = (g_a / 4) E4; dM_sigma / d sigma(cell) = ge
+  double eps0;        // dM_eps / d eps_r(cell) = eps0 ge
   double dt, hdt;
   int src_comp;
   int64_t src_idx;
@@ -161,11 +169,11 @@ struct AdjArgs {
   Probe probe;
 };
 
+size_t adjoint_lds_bytes(int tw, int ty, size_t esz);
+int adjoint_threads(int tw, int ty);   // tw ty column threads + tw + ty + 1 halo threads
+int adjoint_blocks_per_cu(int tw, int ty, size_t esz, bool lossy);
 template <typename T>
 hipError_t launch_adjoint_step(const AdjArgs<T>& a, bool lossy, hipStream_t s);
-hipError_t launch_adjoint_gather(const double* gMe, const double* gMs, const Dims& d,
-                                 const double gq[3], double eps0, double* deps, double* dsig,
-                                 hipStream_t s);
 
 // Batched leapfrog, one launch per step of all grids (fit_batch.hip).
 struct BatchCtl {
@@ -228,6 +236,10 @@ hipError_t launch_hpass(const HArgs<T>& a, bool mu_uniform, bool energy, hipStre
 hipError_t launch_reduce(const double* part, int64_t nblk, double* dst, const int* cols,
                          int probe_term, double jscale, double* jacc, int nan_col,
                          int64_t row_m, const double* pend, int pend_col, hipStream_t s);
+
+// Add the per-workgroup probe rows (sum, compensation) pacc[0 .. nrows) into
+// the compensated pair jacc[0..1] in a fixed order, then clear the rows.
+hipError_t launch_pacc_flush(double* pacc, int64_t nrows, double* jacc, hipStream_t s);
 
 // Zero the slots of PEC-wall edges (which = 0) or facets (which = 1).
 template <typename T>

@@ -43,8 +43,9 @@ __device__ __forceinline__ void nadd(double& s, double& c, double x) {
 
 // Sum NT per-thread values over the (64 x blockDim.y) workgroup and write the
 // NT totals to out (fixed order: deterministic).
+// Returns the total of term threadIdx.x to the threads that store it (0 elsewhere).
 template <int NT>
-__device__ __forceinline__ void block_sum_store(double (&v)[NT], double* out) {
+__device__ __forceinline__ double block_sum_store(double (&v)[NT], double* out) {
   __shared__ double sh[8][NT];
 #pragma unroll
   for (int t = 0; t < NT; ++t) {
@@ -58,11 +59,12 @@ __device__ __forceinline__ void block_sum_store(double (&v)[NT], double* out) {
     for (int t = 0; t < NT; ++t) sh[threadIdx.y][t] = v[t];
   }
   __syncthreads();
+  double s = 0.0;
   if (threadIdx.y == 0 && threadIdx.x < NT) {
-    double s = 0.0;
     for (int w = 0; w < (int)blockDim.y; ++w) s += sh[w][threadIdx.x];
     out[threadIdx.x] = s;
   }
+  return s;
 }
 
 // --------------------------------------------------------------------------- e-update
@@ -200,7 +202,14 @@ __global__ __launch_bounds__(512) void k_epass(EArgs<T> A) {
     double v[6];
 #pragma unroll
     for (int t = 0; t < 6; ++t) v[t] = acc[t] + cmp[t];
-    block_sum_store<6>(v, A.part + (int64_t)blockIdx.x * kPartTerms);
+    const double tot = block_sum_store<6>(v, A.part + (int64_t)blockIdx.x * kPartTerms);
+    if (PROBE && threadIdx.y == 0 && threadIdx.x == PE_PROBE) {
+      double* prow = A.pacc + 2 * (int64_t)blockIdx.x;
+      double ps = prow[0], pc = prow[1];
+      nadd(ps, pc, A.pscale * tot);
+      prow[0] = ps;
+      prow[1] = pc;
+    }
   }
 }
 
@@ -282,8 +291,40 @@ __global__ __launch_bounds__(512) void k_hpass(HArgs<T> A) {
     double v[3];
 #pragma unroll
     for (int t = 0; t < 3; ++t) v[t] = acc[t] + cmp[t];
-    block_sum_store<3>(v, A.part + (int64_t)blockIdx.x * kPartTerms);
+    (void)block_sum_store<3>(v, A.part + (int64_t)blockIdx.x * kPartTerms);
   }
+}
+
+// --------------------------------------------------------------------------- probe rows
+// One workgroup: thread t sums rows t, t + 256, ... (Neumaier over sum and
+// compensation), the partial totals are combined in thread order, and the
+// total is added to jacc.  Rows are cleared.
+__global__ __launch_bounds__(256) void k_pacc_flush(double* pacc, int64_t nrows, double* jacc) {
+  __shared__ double sh[2][256];
+  double s = 0.0, c = 0.0;
+  for (int64_t r = threadIdx.x; r < nrows; r += 256) {
+    nadd(s, c, pacc[2 * r]);
+    nadd(s, c, pacc[2 * r + 1]);
+    pacc[2 * r] = 0.0;
+    pacc[2 * r + 1] = 0.0;
+  }
+  sh[0][threadIdx.x] = s;
+  sh[1][threadIdx.x] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double js = jacc[0], jc = jacc[1];
+    for (int t = 0; t < 256; ++t) {
+      nadd(js, jc, sh[0][t]);
+      nadd(js, jc, sh[1][t]);
+    }
+    jacc[0] = js;
+    jacc[1] = jc;
+  }
+}
+
+hipError_t launch_pacc_flush(double* pacc, int64_t nrows, double* jacc, hipStream_t s) {
+  hipLaunchKernelGGL(k_pacc_flush, dim3(1), dim3(256), 0, s, pacc, nrows, jacc);
+  return hipGetLastError();
 }
 
 // --------------------------------------------------------------------------- reduction

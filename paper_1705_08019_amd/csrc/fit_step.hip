@@ -32,8 +32,8 @@ __global__ __launch_bounds__(1024) void k_step(SArgs<T> A) {
   const int tyi = (int)(rr % A.t.nty);
   const int kz = (int)(rr / A.t.nty);
   step_tile<T, LOSSY, ENERGY, PROBE>(A, tx, tyi, kz, reinterpret_cast<T*>(smem_raw),
-                                     (ENERGY || PROBE) ? A.part + (int64_t)blockIdx.x * kPartTerms
-                                                       : nullptr);
+                                     ENERGY ? A.part + (int64_t)blockIdx.x * kPartTerms : nullptr,
+                                     PROBE ? A.pacc + 2 * (int64_t)blockIdx.x : nullptr);
 }
 
 template <typename T, bool LOSSY>

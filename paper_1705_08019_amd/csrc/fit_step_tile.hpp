@@ -33,14 +33,15 @@ constexpr int kRingPerThread = 3;
 
 // One tw x ty column tile of one z-chunk: tile coordinates (tx, tyi, kz);
 // sm = dynamic LDS of step_lds_bytes(); part = this tile's partial-sum row
-// (ENERGY or PROBE only).  The workgroup's threads (any 2-D shape, a multiple
+// (ENERGY only); prow = this workgroup's probe accumulator row (PROBE only),
+// to which the step adds pscale times its probe term.  The workgroup's threads (any 2-D shape, a multiple
 // of 64 and at least tw ty of them, also at least tw + ty + 1) are numbered
 // linearly; thread t < tw ty owns column (t mod tw, t div tw) of the tile, the
 // rest only help to stage planes (row-packed tiles of the batched kernel,
 // whose tile width is a grid's whole x extent, leave such threads over).
 template <typename T, bool LOSSY, bool ENERGY, bool PROBE>
 __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, int kz, T* sm,
-                                          double* part) {
+                                          double* part, double* prow) {
   const Dims d = A.d;
   const int TY = A.t.ty;
   const int TW = A.t.tw;                 // tile width (x) = blockDim.x
@@ -297,7 +298,13 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
     if (tid < 9) {
       double s = 0.0;
       for (int w = 0; w < nw; ++w) s += red[w][tid];
-      part[tid] = s;
+      if (ENERGY) part[tid] = s;
+      if (PROBE && tid == PE_PROBE) {
+        double ps = prow[0], pc = prow[1];
+        nadd_s(ps, pc, A.pscale * s);
+        prow[0] = ps;
+        prow[1] = pc;
+      }
     }
   }
 }

@@ -255,6 +255,11 @@ class FitGrid:
         call("fit_step_record", self._h, int(nsteps), float(dt), C.c_void_p(e_rec.data_ptr()),
              C.c_void_p(h_rec.data_ptr()))
 
+    def adjoint_set_tuning(self, tw: int = 0, ty: int = 0, kc: int = 0):
+        """Reverse-step tile (tw x ty columns, kc planes) from the next
+        adjoint_begin; zeros select the defaults."""
+        call("fit_adjoint_set_tuning", self._h, int(tw), int(ty), int(kc))
+
     def adjoint_begin(self, nsteps: int, dt: float):
         call("fit_adjoint_begin", self._h, int(nsteps), float(dt))
 

@@ -294,3 +294,40 @@ def test_autotune_keeps_state_and_results():
         g.step(30, dt)
         grids.append(g.get_fields())
     assert torch.equal(grids[0][0], grids[1][0]) and torch.equal(grids[0][1], grids[1][1])
+
+
+def test_probe_objective_across_tilings_and_paths():
+    """The probe objective accumulates per workgroup across steps; changing the
+    tile (more workgroups) or the kernel path mid-run, or reading it midway,
+    must not change the total (FP64, against one uninterrupted run)."""
+    from paper_1705_08019_amd import FitGrid
+    nx, ny, nz = 40, 28, 22
+    eps = dielectric_blocks(nx, ny, nz, 6, 12)
+    sig = lossy_slab(nx, ny, nz, 2)
+    box = ([8, 6, 5], [30, 20, 15])
+
+    def grid():
+        g = FitGrid(nx, ny, nz, "f64")
+        g.set_materials(eps, None, sig)
+        dt = 0.9 * g.cfl_dt()
+        g.set_source(2, 20, 14, 11, 1.0, 8 * dt)
+        g.set_probe(*box)
+        return g, dt
+
+    g, dt = grid()
+    g.step(80, dt)
+    J_ref = g.probe_value()
+    g.close()
+    g, dt = grid()
+    g.step(30, dt)
+    J_mid = g.probe_value()
+    g.set_tuning("fused", 2, 3, 32)        # many more workgroups than the default
+    g.step(25, dt)
+    g.set_tuning("split", 2, 5)
+    g.step(25, dt)
+    J = g.probe_value()
+    assert 0 < J_mid < J
+    assert abs(J - J_ref) <= 1e-13 * J_ref
+    g.probe_reset()
+    assert g.probe_value() == 0.0
+    g.close()
