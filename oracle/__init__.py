@@ -22,10 +22,14 @@ Discretization of Maxwell's equations"):
   snapshots.
 * ``adjoint``   -- the discrete reverse-time adjoint of the leapfrog
   recurrence and the per-cell gradient of a probe-energy objective.
+* ``expm``      -- the action of exp(tA) by scaling and a truncated Taylor
+  recurrence (Sec. III-A), with the parameter choice of its docstring.
+* ``paraexp``   -- ParaExp (Sec. III, Alg. 1) with leapfrog particular
+  solutions and the staggered reconstruction of Sec. III-B.
 
 Every function is FP64 and unblocked.  Pins (tests that tie the oracle to
 the paper and to the mathematics) live in ``tests/test_oracle_*.py``.
 Functions without such a pin say "parity unpinned" in their docstring;
 at present none does.
 """
-from . import topology, materials, leapfrog, stability, gram, adjoint, layout  # noqa: F401
+from . import topology, materials, leapfrog, stability, gram, adjoint, layout, expm, paraexp  # noqa: F401
