@@ -321,6 +321,68 @@ def form_adjoint():
                                  "note": "96^3 state (21 MB per field set) is largely resident in the 256 MB Infinity Cache"}}
 
 
+def form_paraexp(p: int = 8, nsteps: int = 1024, tol: float = 3e-3):
+    """ParaExp (Alg. 1) on the 128^3 dielectric-block grid without the lossy
+    slab (the exponential needs a lossless grid), FP32, p sub-intervals, the
+    particular solutions as one batch, Taylor exponentials; against one plain
+    leapfrog run of the same N steps.  Also the device time of one
+    application of B (k_opb, accumulating mode) and its bytes per cell."""
+    import torch
+    from fit_workloads import c2
+    from paper_1705_08019_amd import FitGrid
+    from paper_1705_08019_amd.paraexp import paraexp
+    sp = c2()
+    g = FitGrid(sp.nx, sp.ny, sp.nz, "f32")
+    g.set_materials(sp.eps_r)
+    dt = 0.9 * g.cfl_dt()
+    s = sp.source
+    src = dict(axis=s["axis"], i=s["i"], j=s["j"], k=s["k"], i_max=s["i_max"],
+               sigma_t=s["sigma_t_steps"] * dt)
+    g.set_source(src["axis"], src["i"], src["j"], src["k"], src["i_max"], src["sigma_t"])
+    rho = g.op_norm(60) * 1.02
+    g.autotune(dt, reps=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g.step(nsteps, dt)
+    torch.cuda.synchronize()
+    t_lf = time.perf_counter() - t0
+    e_lf, _ = g.get_fields()
+    # one application of B in the accumulating mode, timed with events
+    e, h = g.get_fields()
+    oe, oh = g.new_field(), g.new_field()
+    ae, ah = g.new_field(), g.new_field()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 20
+    g.expm(1e-3, e, h, rho, 1e-6, out=(ae, ah))   # warm-up
+    torch.cuda.synchronize()
+    g.profile_begin(4 * reps)
+    for _ in range(reps):
+        g.op_apply(e, h)
+    prof = g.profile_end()
+    us_apply = prof["other"][0] / max(prof["other"][1], 1) * 1e3
+    g.close()
+    paraexp(sp.nx, sp.ny, sp.nz, sp.eps_r, dt, 64, 2, src, tol=tol, rho=rho)   # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = paraexp(sp.nx, sp.ny, sp.nz, sp.eps_r, dt, nsteps, p, src, tol=tol, rho=rho)
+    torch.cuda.synchronize()
+    t_px = time.perf_counter() - t0
+    diff = float(torch.linalg.vector_norm((res.e - e_lf).double()) /
+                 torch.linalg.vector_norm(e_lf.double()))
+    b_apply = 4 * (6 + 1 + 6)      # read e, h, eps; write the image (mode 0)
+    return {"workload": f"128^3 dielectric blocks (seed 2), lossless, FP32, {nsteps} steps, p = {p}, "
+                        f"tol {tol:g}",
+            "paraexp_s": round(t_px, 4), "leapfrog_s": round(t_lf, 4),
+            "paraexp_over_leapfrog_time": round(t_px / t_lf, 2),
+            "rel_l2_e_vs_leapfrog": diff, "rho": round(res.rho, 5),
+            "expm_params": res.expm_params, "A_applications": res.A_applications,
+            "C_proc_parallel_form": res.C_proc, "C_LF": 2 * nsteps,
+            "apply_B_us": round(us_apply, 2),
+            "apply_B_alg_GBs": round(b_apply * sp.cells / (us_apply * 1e-6) / 1e9, 1),
+            "note": "one GPU: the p particular solutions run as one batch, the homogeneous "
+                    "propagations as a chain of exponentials; 128^3 is LLC-resident"}
+
+
 def gram_mfma_tiles(K: int) -> int:
     """16x16 output tiles the Gram kernel multiplies for K snapshots: per 64x64
     block pair (a0 <= b0) the tiles holding output, upper tile triangle only in
@@ -563,7 +625,7 @@ def main(argv=None):
     line["config"]["copy_GBs_read_plus_write"] = measure_copy()
     if not args.no_forms:
         line["forms"] = {"batched": form_batched(), "adjoint": form_adjoint(),
-                         "gram": form_gram()}
+                         "gram": form_gram(), "paraexp": form_paraexp()}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

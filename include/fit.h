@@ -244,6 +244,50 @@ int fit_adjoint_segment(fit_grid* g, int64_t m0, int64_t nsteps, const void* e_r
  * destinations.  Host destinations synchronise. */
 int fit_adjoint_grad(fit_grid* g, double* deps, double* dsigma, int on_device);
 
+/* ---- Matrix exponential and ParaExp building blocks (Sec. III) ----------
+ * On the voltages x = (e, h) of a lossless grid with uniform mu the
+ * semi-discrete system (eq. FIT_ode_1 without source) is dx/dt = B x,
+ *   B (e, h) = ( M_eps^{-1} C~ h ,  -M_mu^{-1} C e ),
+ * the similarity transform of the skew matrix A of eq. FIT_ode_2, so
+ * exp(tB) x = T^{-1} exp(tA) T x and ||A||_2 is the M-norm of B.  All field
+ * arguments are device pointers to 3-component slot-layout arrays of the
+ * grid's dtype.  Asynchronous on the grid's stream unless stated. */
+
+/* Taylor parameters (m terms, s sub-steps) for theta = |t| ||A||_2, a
+ * relative tolerance tol in (0, 1) and the unit roundoff u of the
+ * arithmetic: the fewest applications m s with
+ *   s delta (1 + delta)^(s-1) + s (m + 2) u e^(theta / s) <= tol,
+ *   delta = (theta / s)^(m+1) / (m+1)!
+ * (the Taylor remainder on an imaginary spectrum plus a rounding estimate).
+ * FIT_E_INVALID if tol is below what u allows.  Host only. */
+int fit_expm_params(double theta, double tol, double unit_roundoff, int* m, int64_t* s);
+
+/* out = alpha B in (two curl applications).  Needs a uniform mu; inputs
+ * and outputs must be distinct buffers.  Errors: FIT_E_INVALID. */
+int fit_op_apply(fit_grid* g, double alpha, const void* e_in, const void* h_in, void* e_out,
+                 void* h_out);
+
+/* ||A||_2 estimated by `iters` power iterations on -B^2 in the M inner
+ * product from a seeded pseudo-random start (Rayleigh quotients approach the
+ * norm from below).  Lossless grids with uniform mu.  Synchronises. */
+int fit_op_norm(fit_grid* g, int iters, uint64_t seed, double* rho);
+
+/* (e_out, h_out) = exp(t B) (e_in, h_in) by (T_m(tB/s))^s with (m, s) from
+ * fit_expm_params(|t| rho, tol, u) and u the unit roundoff of the grid's
+ * dtype (2^-53, 2^-24); rho = ||A||_2 or a bound on it.  m and s (may be
+ * null) receive the parameters used (m s applications of B).  In-place
+ * (out == in) is allowed.  Lossless grids with uniform mu. */
+int fit_expm(fit_grid* g, double t, double tol, double rho, const void* e_in, const void* h_in,
+             void* e_out, void* h_out, int* m, int64_t* s);
+
+/* h_out = h_in - c M_mu^{-1} C e (the h-update with step c; c = -dt/2 turns
+ * h^(m+1/2) into the collocated h(t_m) = (h^(m-1/2) + h^(m+1/2))/2 given e^m,
+ * c = +dt/2 turns it back).  h_out may equal h_in. */
+int fit_shift_h(fit_grid* g, double c, const void* e, const void* h_in, void* h_out);
+
+/* y += a x for two-field vectors (e, h). */
+int fit_axpy(fit_grid* g, double a, const void* x_e, const void* x_h, void* y_e, void* y_h);
+
 /* ---- Batched grids: many independent grids advanced together ------------
  * A batch advances nb grids (same dtype, uniform mu each; sizes, materials,
  * sources and dt may all differ) together.  Each launch covers one step of

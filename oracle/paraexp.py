@@ -52,7 +52,8 @@ def collocate_h(ops, e_m, h_half, dt):
 
 
 def paraexp(ops, dt: float, nsteps: int, p: int, source=None, e0=None, h0=None,
-            homogeneous: str = "expm", tol: float = 1e-12, rho=None):
+            homogeneous: str = "expm", tol: float = 1e-12, rho=None,
+            unit_roundoff: float = 2.0 ** -53):
     """(e^(N), h^(N+1/2), cost) of Alg. 1 for N = ``nsteps`` (divisible by p).
 
     ``homogeneous``: "expm" (the paper: Taylor action of exp(tA), see
@@ -60,7 +61,8 @@ def paraexp(ops, dt: float, nsteps: int, p: int, source=None, e0=None, h0=None,
     leapfrog on the staggered grid, which by linearity reproduces one
     leapfrog run over (0, T]).  ``cost``: leapfrog steps per sub-interval,
     applications of A per homogeneous solution, and C_proc of eq. tot_cost
-    (2 L + the largest count of A applications + 2).
+    (2 L + the largest count of A applications + 2).  ``unit_roundoff``
+    enters the Taylor parameter choice (see ``expm``).
     """
     if nsteps % p:
         raise ValueError("nsteps must be divisible by p")
@@ -95,16 +97,16 @@ def paraexp(ops, dt: float, nsteps: int, p: int, source=None, e0=None, h0=None,
     wsum = np.zeros(ops.n_h + ops.n_e)
     u0 = to_u(ops, e0, collocate_h(ops, e0, h0, dt))
     if np.any(u0):
-        w, ms = expm_action(A, u0, T, rho, tol)
+        w, ms = expm_action(A, u0, T, rho, tol, unit_roundoff=unit_roundoff)
         cost["A_applications"].append(ms[0] * ms[1])
         wsum += w
     for j in range(p - 1):
         e, h = parts[j]
         vj = to_u(ops, e, collocate_h(ops, e, h, dt))              # v_j(T_j)
-        w, ms = expm_action(A, vj, T - (j + 1) * L * dt, rho, tol)
+        w, ms = expm_action(A, vj, T - (j + 1) * L * dt, rho, tol, unit_roundoff=unit_roundoff)
         cost["A_applications"].append(ms[0] * ms[1])
         wsum += w
-    w_half, ms = expm_action(A, wsum, 0.5 * dt, rho, tol)
+    w_half, ms = expm_action(A, wsum, 0.5 * dt, rho, tol, unit_roundoff=unit_roundoff)
     cost["A_applications_half_step"] = ms[0] * ms[1]
     ew, _ = from_u(ops, wsum)
     _, hw = from_u(ops, w_half)

@@ -52,6 +52,7 @@ int ensure_pacc(fit_grid* g, int64_t rows) {
     if (e == hipSuccess) e = hipStreamSynchronize(g->s);
     if (e != hipSuccess) return hip_fail(e, "probe rows flush");
     dev_free(reinterpret_cast<void*&>(g->pacc));
+  dev_free(g->xw);
   }
   g->pacc_rows = 0;
   int rc = dev_alloc(reinterpret_cast<void**>(&g->pacc), (size_t)rows * 2 * sizeof(double),
@@ -555,6 +556,7 @@ int fit_grid_destroy(fit_grid* g) {
   dev_free(reinterpret_cast<void*&>(g->jacc));
   dev_free(reinterpret_cast<void*&>(g->pend));
   dev_free(reinterpret_cast<void*&>(g->pacc));
+  dev_free(g->xw);
   dev_free(reinterpret_cast<void*&>(g->gram_part));
   dev_free(reinterpret_cast<void*&>(g->gram_G));
   dev_free(reinterpret_cast<void*&>(g->gram_w[0]));

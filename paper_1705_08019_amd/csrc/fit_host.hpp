@@ -62,6 +62,7 @@ struct fit_grid {
   int atw = 0, aty = 0, akc = 0;   // reverse-step tile (0: default)
   double* pacc = nullptr;       // probe objective: per-workgroup (sum, compensation) rows
   int64_t pacc_rows = 0;
+  void* xw = nullptr;            // operator / exponential workspace: 3 (e, h) vectors
   double* gram_part = nullptr;  // per-workgroup Gram blocks
   double* gram_G = nullptr;     // device K x K result
   int64_t gram_G_cap = 0;

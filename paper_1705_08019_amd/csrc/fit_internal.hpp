@@ -241,6 +241,25 @@ hipError_t launch_reduce(const double* part, int64_t nblk, double* dst, const in
 // the compensated pair jacc[0..1] in a fixed order, then clear the rows.
 hipError_t launch_pacc_flush(double* pacc, int64_t nrows, double* jacc, hipStream_t s);
 
+// Semi-discrete operator B (e, h) = (M_eps^{-1} C~ h, -M_mu^{-1} C e) of a
+// lossless grid with uniform mu (fit_expm.hip): out = c B in with per-axis
+// coefficients ce = c / (g_a / 4), ch = -c gf2_a (imu + imu); mode 1 also
+// adds out to acc, mode 2 sets acc = in + out.  in, out, acc distinct.
+template <typename T>
+hipError_t launch_opb(const T* ein, const T* hin, T* eout, T* hout, T* eacc, T* hacc, int mode,
+                      const T* eps, const Dims& d, const Tiling& t, const double ce[3],
+                      const double ch[3], hipStream_t s);
+// Per-workgroup rows (terms 0, 1) of <a, b>_M: sum M_eps a_e b_e and
+// sum M_mu a_h b_h (mm = M_mu per facet direction); nblk rows of part.
+template <typename T>
+hipError_t launch_mdot(const T* ae, const T* ah, const T* be, const T* bh, const T* eps,
+                       const Dims& d, const double ge[3], const double mm[3], double* part,
+                       int64_t nblk, hipStream_t s);
+template <typename T>
+hipError_t launch_axpy(T a, const T* xe, const T* xh, T* ye, T* yh, int64_t n3, hipStream_t s);
+template <typename T>
+hipError_t launch_seed(T* xe, T* xh, const Dims& d, uint64_t seed, hipStream_t s);
+
 // Zero the slots of PEC-wall edges (which = 0) or facets (which = 1).
 template <typename T>
 hipError_t launch_mask(T* f, const Dims& d, int which, hipStream_t s);

@@ -151,6 +151,57 @@ class FitGrid:
              C.c_void_p(out.data_ptr()))
         return out
 
+    def _dev(self, *xs):
+        for x in xs:
+            if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == self.tdtype
+                    and x.is_contiguous() and x.numel() == 3 * self.cells):
+                raise ValueError("fields must be contiguous device tensors of the grid dtype "
+                                 f"with {3 * self.cells} values")
+        return [C.c_void_p(x.data_ptr()) for x in xs]
+
+    def new_field(self) -> torch.Tensor:
+        return torch.zeros(self.shape, dtype=self.tdtype, device=self.device)
+
+    def op_apply(self, e: torch.Tensor, h: torch.Tensor, alpha: float = 1.0):
+        """alpha B (e, h) = alpha (M_eps^{-1} C~ h, -M_mu^{-1} C e) as new tensors."""
+        eo, ho = self.new_field(), self.new_field()
+        call("fit_op_apply", self._h, float(alpha), *self._dev(e, h, eo, ho))
+        return eo, ho
+
+    def op_norm(self, iters: int = 100, seed: int = 1) -> float:
+        """||A||_2 of eq. FIT_ode_2 by power iteration (approaches from below)."""
+        v = C.c_double()
+        call("fit_op_norm", self._h, int(iters), C.c_uint64(seed), C.byref(v))
+        return v.value
+
+    def expm(self, t: float, e: torch.Tensor, h: torch.Tensor, rho: float, tol: float = 1e-12,
+             out=None):
+        """exp(t B) (e, h); returns (e_out, h_out, (m, s))."""
+        eo, ho = (self.new_field(), self.new_field()) if out is None else out
+        m, s_ = C.c_int(), C.c_int64()
+        call("fit_expm", self._h, float(t), float(tol), float(rho), *self._dev(e, h, eo, ho),
+             C.byref(m), C.byref(s_))
+        return eo, ho, (m.value, s_.value)
+
+    def shift_h(self, c: float, e: torch.Tensor, h_in: torch.Tensor, h_out=None):
+        """h_in - c M_mu^{-1} C e (c = -dt/2: collocate h^(m+1/2) at t_m)."""
+        ho = self.new_field() if h_out is None else h_out
+        call("fit_shift_h", self._h, float(c), *self._dev(e, h_in, ho))
+        return ho
+
+    def axpy(self, a: float, xe, xh, ye, yh):
+        """(ye, yh) += a (xe, xh) in place."""
+        call("fit_axpy", self._h, float(a), *self._dev(xe, xh, ye, yh))
+
+    UNIT_ROUNDOFF = {"f32": 2.0 ** -24, "f64": 2.0 ** -53}
+
+    @staticmethod
+    def expm_params(theta: float, tol: float, unit_roundoff: float = 2.0 ** -53):
+        m, s_ = C.c_int(), C.c_int64()
+        call("fit_expm_params", float(theta), float(tol), float(unit_roundoff), C.byref(m),
+             C.byref(s_))
+        return m.value, s_.value
+
     def step(self, nsteps: int, dt: float):
         call("fit_step", self._h, int(nsteps), float(dt))
 

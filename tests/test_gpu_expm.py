@@ -1,0 +1,160 @@
+"""GPU parity of the operator B, the ||A||_2 estimate, the Taylor action of
+exp(tB) and ParaExp (Sec. III, Alg. 1) against the oracle."""
+import math
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from fit_workloads import dielectric_blocks
+from oracle import expm as oexpm, paraexp as opx
+from oracle.stability import skew_matrix, spectral_norm, cfl_dt
+from oracle.leapfrog import run
+from _glue import oracle_ops, edges_from_slots, facets_from_slots, edges_to_slots, \
+    facets_to_slots, rel_l2, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _setup(n, dtype, seed=5):
+    from paper_1705_08019_amd import FitGrid
+    nx, ny, nz = n
+    eps = dielectric_blocks(nx, ny, nz, 5, seed)
+    g = FitGrid(nx, ny, nz, dtype)
+    g.set_materials(eps)
+    return g, oracle_ops(n, eps=eps), eps
+
+
+def _fields(g, ops, rng):
+    xe = ops.Ct @ rng.uniform(-1, 1, ops.n_h)
+    xh = rng.standard_normal(ops.n_h)
+    te = torch.tensor(edges_to_slots(ops, xe), dtype=g.tdtype, device="cuda").contiguous()
+    th = torch.tensor(facets_to_slots(ops, xh), dtype=g.tdtype, device="cuda").contiguous()
+    return xe, xh, te, th
+
+
+def _o_apply(ops, e, h, alpha=1.0):
+    return alpha * (ops.Ct @ h) / ops.M_eps, -alpha * ops.M_mu_inv * (ops.C @ e)
+
+
+@pytest.mark.parametrize("dtype,n", [("f64", (13, 9, 7)), ("f32", (70, 33, 21))])
+def test_operator_matches_oracle(dtype, n):
+    g, ops, _ = _setup(n, dtype)
+    rng = np.random.default_rng(1)
+    xe, xh, te, th = _fields(g, ops, rng)
+    oe, oh = g.op_apply(te, th, alpha=0.37)
+    re, rh = _o_apply(ops, xe, xh, 0.37)
+    tol = 1e-13 if dtype == "f64" else 1e-6
+    assert rel_l2(edges_from_slots(ops, to_np(oe)), re) <= tol
+    assert rel_l2(facets_from_slots(ops, to_np(oh)), rh) <= tol
+    # dead (PEC) slots stay zero
+    oe_np, oh_np = to_np(oe), to_np(oh)
+    assert np.array_equal(edges_to_slots(ops, edges_from_slots(ops, oe_np)).reshape(oe_np.shape),
+                          oe_np)
+    assert np.array_equal(facets_to_slots(ops, facets_from_slots(ops, oh_np)).reshape(oh_np.shape),
+                          oh_np)
+    g.close()
+
+
+def test_norm_estimate_matches_oracle():
+    g, ops, _ = _setup((12, 10, 8), "f64")
+    rho_o = spectral_norm(ops)
+    rho = g.op_norm(400)
+    assert rho <= rho_o * (1 + 1e-12)
+    assert rho >= rho_o * (1 - 2e-3)
+    g.close()
+
+
+def test_expm_params_match_oracle():
+    from paper_1705_08019_amd import FitGrid, FitError
+    for theta, tol, u in ((0.0, 1e-9, 2.0 ** -53), (0.2, 1e-12, 2.0 ** -53), (7.5, 1e-8, 2.0 ** -53),
+                          (300.0, 1e-6, 2.0 ** -53), (4000.0, 1e-10, 2.0 ** -53),
+                          (30.0, 1e-4, 2.0 ** -24), (230.0, 1e-3, 2.0 ** -24)):
+        assert FitGrid.expm_params(theta, tol, u) == oexpm.taylor_parameters(theta, tol, u), theta
+    with pytest.raises(FitError, match="INVALID"):
+        FitGrid.expm_params(500.0, 1e-9, 2.0 ** -24)
+
+
+@pytest.mark.parametrize("dtype,t", [("f64", 0.3), ("f64", 17.0), ("f32", 9.0)])
+def test_expm_matches_oracle_same_parameters(dtype, t):
+    """Same (m, s) on both sides: they evaluate the same polynomial, so they
+    differ by rounding only, each side within its bound (<= tol) in the
+    M-norm (the transformed unknowns of eq. FIT_ode_2)."""
+    from paper_1705_08019_amd import FitGrid
+    g, ops, _ = _setup((11, 8, 7), dtype)
+    rho = spectral_norm(ops)
+    rng = np.random.default_rng(2)
+    xe, xh, te, th = _fields(g, ops, rng)
+    tol = 1e-11 if dtype == "f64" else 1e-4
+    u_dt = FitGrid.UNIT_ROUNDOFF[dtype]
+    oe, oh, ms = g.expm(t, te, th, rho, tol)
+    A = skew_matrix(ops)
+    u0 = opx.to_u(ops, xe, xh)
+    u, ms_o = oexpm.expm_action(A, u0, t, rho, tol, unit_roundoff=u_dt)
+    assert ms == ms_o
+    ug = opx.to_u(ops, edges_from_slots(ops, to_np(oe)), facets_from_slots(ops, to_np(oh)))
+    assert np.linalg.norm(ug - u) <= 2 * tol * np.linalg.norm(u0)
+    # in place gives the same
+    ie, ih = te.clone(), th.clone()
+    g.expm(t, ie, ih, rho, tol, out=(ie, ih))
+    assert torch.equal(ie, oe) and torch.equal(ih, oh)
+    g.close()
+
+
+def test_shift_h_is_the_collocation_transform():
+    g, ops, _ = _setup((10, 9, 6), "f64")
+    rng = np.random.default_rng(3)
+    xe, xh, te, th = _fields(g, ops, rng)
+    dt = 0.4
+    hc = g.shift_h(-0.5 * dt, te, th)
+    ref = opx.collocate_h(ops, xe, xh, dt)
+    assert rel_l2(facets_from_slots(ops, to_np(hc)), ref) <= 1e-14
+    back = g.shift_h(0.5 * dt, te, hc)
+    assert rel_l2(facets_from_slots(ops, to_np(back)), xh) <= 1e-14
+    g.close()
+
+
+@pytest.mark.parametrize("dtype,p", [("f64", 4), ("f64", 1), ("f32", 3)])
+def test_paraexp_matches_oracle(dtype, p):
+    from paper_1705_08019_amd.paraexp import paraexp
+    n = (12, 9, 8)
+    nx, ny, nz = n
+    eps = dielectric_blocks(nx, ny, nz, 4, 17)
+    ops = oracle_ops(n, eps=eps)
+    dt = 0.9 * cfl_dt(eps)
+    N = 48
+    src = dict(axis=2, i=6, j=4, k=4, i_max=1.0, sigma_t=8 * dt)
+    rho = spectral_norm(ops)
+    tol = 1e-11 if dtype == "f64" else 1e-3
+    from paper_1705_08019_amd import FitGrid
+    res = paraexp(nx, ny, nz, eps, dt, N, p, src, dtype=dtype, tol=tol, rho=rho)
+    e_o, h_o, cost = opx.paraexp(ops, dt, N, p, src, tol=tol, rho=rho,
+                                 unit_roundoff=FitGrid.UNIT_ROUNDOFF[dtype])
+    # the exponentials differ by rounding only (same parameters); the FP32
+    # particular runs add the leapfrog FP32 error (<= 1e-4)
+    lim = 4 * tol if dtype == "f64" else 4 * tol + 1e-4
+    assert rel_l2(edges_from_slots(ops, to_np(res.e)), e_o) <= lim
+    assert rel_l2(facets_from_slots(ops, to_np(res.h)), h_o) <= lim
+    if p == 1:   # a single interval with zero initial values is one leapfrog run
+        e_lf, _, _ = run(ops, np.zeros(ops.n_e), np.zeros(ops.n_h), dt, N, src)
+        assert rel_l2(edges_from_slots(ops, to_np(res.e)), e_lf) <= lim
+    assert res.C_proc == cost["C_proc"]
+
+
+def test_operator_rejects_lossy_and_aliasing():
+    from paper_1705_08019_amd import FitGrid, FitError
+    from fit_workloads import lossy_slab
+    g = FitGrid(8, 8, 8, "f32")
+    g.set_materials(np.ones(512), None, lossy_slab(8, 8, 8, 2))
+    e, h = g.new_field(), g.new_field()
+    with pytest.raises(FitError, match="INVALID"):
+        g.expm(1.0, e, h, 3.0)
+    with pytest.raises(FitError, match="INVALID"):
+        g.op_norm(5)
+    import ctypes as C
+    from paper_1705_08019_amd._lib import call
+    with pytest.raises(FitError, match="INVALID"):
+        call("fit_op_apply", g.handle, 1.0, C.c_void_p(e.data_ptr()), C.c_void_p(h.data_ptr()),
+             C.c_void_p(e.data_ptr()), C.c_void_p(h.data_ptr()))
+    g.close()

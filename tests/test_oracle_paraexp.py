@@ -32,15 +32,46 @@ def _te101(ops, nx, nz):
 
 
 def test_taylor_parameters_meet_their_bound_and_are_cheapest():
-    for theta, tol in ((0.3, 1e-12), (5.0, 1e-8), (80.0, 1e-12), (1234.5, 1e-6)):
-        m, s = expm.taylor_parameters(theta, tol)
-        assert expm.taylor_error_bound(theta, m, s) <= tol
-        # no cheaper pair meets the bound (brute force over a window)
+    for theta, tol, u in ((0.3, 1e-12, 2.0 ** -53), (5.0, 1e-8, 2.0 ** -53),
+                          (80.0, 1e-12, 2.0 ** -53), (1234.5, 1e-6, 2.0 ** -53),
+                          (60.0, 1e-3, 2.0 ** -24)):
+        m, s = expm.taylor_parameters(theta, tol, u)
+        assert expm.taylor_error_bound(theta, m, s, u) <= tol
+        # no cheaper pair meets the bound (brute force)
         for mm in range(1, 61):
             for ss in range(1, m * s // mm + 1):
                 if mm * ss < m * s:
-                    assert expm.taylor_error_bound(theta, mm, ss) > tol
+                    assert expm.taylor_error_bound(theta, mm, ss, u) > tol, (theta, mm, ss)
     assert expm.taylor_parameters(0.0, 1e-12) == (0, 1)
+    with pytest.raises(ValueError):
+        expm.taylor_parameters(500.0, 1e-9, 2.0 ** -24)   # below the FP32 rounding floor
+
+
+def test_rounding_term_tracks_a_float32_evaluation():
+    """The rounding part of the bound covers a float32 evaluation of the
+    same polynomial on the skew matrix (against the float64 one)."""
+    nx, ny, nz = 6, 5, 4
+    ops = _ops(nx, ny, nz, dielectric_blocks(nx, ny, nz, 3, 9))
+    A = skew_matrix(ops)
+    rho = spectral_norm(ops)
+    rng = np.random.default_rng(8)
+    b = rng.standard_normal(A.shape[0])
+    A32 = A.astype(np.float32)
+    for t, tol in ((10.0, 1e-3), (4.0, 1e-4), (15.0, 2e-3)):
+        m, s = expm.taylor_parameters(t * rho, tol, 2.0 ** -24)
+        x64, _ = expm.expm_action(A, b, t, rho, params=(m, s))
+        x = b.astype(np.float32)
+        h = np.float32(t / s)
+        for _ in range(s):
+            term = x.copy()
+            acc = x.copy()
+            for k in range(1, m + 1):
+                term = (h / np.float32(k)) * (A32 @ term)
+                acc += term
+            x = acc
+        err = np.linalg.norm(x.astype(np.float64) - x64) / np.linalg.norm(b)
+        rnd = s * (m + 2) * 2.0 ** -24 * math.exp(t * rho / s)
+        assert err <= rnd, (m, s, err, rnd)
 
 
 def test_taylor_bound_is_a_true_bound_on_the_imaginary_axis():
@@ -78,7 +109,7 @@ def test_expm_action_rotates_the_te101_mode_at_the_discrete_frequency():
     u0 = paraexp.to_u(ops, phi, np.zeros(ops.n_h))
     ch = ops.M_mu_inv * (ops.C @ phi)
     for t in (0.7, 10.0, 31.3):
-        x, _ = expm.expm_action(A, u0, t, rho, tol=1e-13)
+        x, _ = expm.expm_action(A, u0, t, rho, tol=2e-12)
         e, h = paraexp.from_u(ops, x)
         np.testing.assert_allclose(e, math.cos(w * t) * phi, atol=1e-11)
         np.testing.assert_allclose(h, -math.sin(w * t) / w * ch, atol=1e-11)
@@ -112,7 +143,7 @@ def test_paraexp_single_interval_propagates_the_mode_exactly():
     ch = ops.M_mu_inv * (ops.C @ phi)
     h_half = -0.5 * dt * ch
     N = 40
-    e, h, cost = paraexp.paraexp(ops, dt, N, 1, None, phi, h_half, tol=1e-13)
+    e, h, cost = paraexp.paraexp(ops, dt, N, 1, None, phi, h_half, tol=2e-12)
     T = N * dt
     np.testing.assert_allclose(e, math.cos(w * T) * phi, atol=1e-11)
     np.testing.assert_allclose(h, -math.sin(w * (T + 0.5 * dt)) / w * ch, atol=1e-11)
@@ -144,6 +175,6 @@ def test_paraexp_and_leapfrog_differ_at_second_order():
         N = 48 * r
         src = dict(axis=2, i=4, j=3, k=3, i_max=1.0, sigma_t=T / 4)
         e_lf, _, _ = run(ops, np.zeros(ops.n_e), np.zeros(ops.n_h), dt, N, src)
-        e_px, _, _ = paraexp.paraexp(ops, dt, N, 4, src, tol=1e-13)
+        e_px, _, _ = paraexp.paraexp(ops, dt, N, 4, src, tol=2e-12)
         gaps.append(np.linalg.norm(e_px - e_lf) / np.linalg.norm(e_lf))
     assert 3.5 < gaps[0] / gaps[1] < 4.5 and 3.5 < gaps[1] / gaps[2] < 4.5, gaps
