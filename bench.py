@@ -624,8 +624,13 @@ def main(argv=None):
     r["grid"].close()
     line["config"]["copy_GBs_read_plus_write"] = measure_copy()
     if not args.no_forms:
-        line["forms"] = {"batched": form_batched(), "adjoint": form_adjoint(),
-                         "gram": form_gram(), "paraexp": form_paraexp()}
+        line["forms"] = {}
+        for name, fn in (("batched", form_batched), ("adjoint", form_adjoint),
+                         ("gram", form_gram), ("paraexp", form_paraexp)):
+            try:
+                line["forms"][name] = fn()
+            except Exception as ex:      # a failing form is reported, not hidden
+                line["forms"][name] = {"error": f"{type(ex).__name__}: {ex}"}
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)

@@ -12,6 +12,10 @@ Everything here is input data.  The five named workloads are:
   each, lossless, random interior source node each, 4000 steps.
 * ``c5``  96^3 FP32 adjoint workload: materials as c2, 4096 steps,
   checkpoints every 64 steps, probe box [64, 80]^3.
+* ``x1``  the paper's two-dimensional cylindrical wave (Sec. IV-A): a
+  20 m x 20 m x 1 m PEC box of vacuum, 41 (or 121) grid points per side in x
+  and y and 2 in z, SI constants, the Gaussian line current of eq.
+  line_current (1 A, 2e-8 s) on the z edge at the centre, T = 2e-7 s.
 
 Reduced copies (``*_small``) regenerate the same recipe at a smaller size for
 parity runs against the oracle.
@@ -28,7 +32,11 @@ __all__ = [
     "WorkloadSpec", "dielectric_blocks", "lossy_slab", "facet_potential",
     "centre_source", "random_source", "batch_sizes", "probe_box",
     "c1", "c2", "c3", "c4", "c5", "c2_small", "c4_small", "c5_small", "scaled",
+    "EPS0_SI", "MU0_SI", "x1", "steps_for",
 ]
+
+EPS0_SI = 8.8541878128e-12      # vacuum permittivity [F/m] (CODATA 2018)
+MU0_SI = 1.25663706212e-6       # vacuum permeability [H/m] (CODATA 2018)
 
 
 @dataclasses.dataclass
@@ -50,6 +58,9 @@ class WorkloadSpec:
     probe: Optional[tuple] = None   # ((lo_x, hi_x), (lo_y, hi_y), (lo_z, hi_z)) node coords
     checkpoint_every: int = 0
     spacing: tuple = (1.0, 1.0, 1.0)
+    eps0: float = 1.0               # eps = eps0 eps_r, mu = mu0 mu_r
+    mu0: float = 1.0
+    t_end: Optional[float] = None   # end time; then dt = t_end / ceil(t_end / dt_CFL)
 
     @property
     def cells(self) -> int:
@@ -183,3 +194,22 @@ def c5_small(n: int = 24, nsteps: int = 4096, dtype: str = "f32") -> WorkloadSpe
     box = probe_box(n, scaled(96, n, 16))
     return _block_grid(f"c5_small_{n}cube_{dtype}", n, n, n, dtype, nsteps, 32, 5,
                        scaled(96, n, 8), probe=(box, box, box), checkpoint_every=64)
+
+
+def x1(points: int = 41, dtype: str = "f64") -> WorkloadSpec:
+    """Cylindrical wave: ``points`` grid points per side in x, y (so points - 1
+    cells of 20 / (points - 1) m), 2 in z (one 1 m cell).  The source is the
+    +z edge at the centre node, sigma_t given in seconds (``sigma_t``)."""
+    n = points - 1
+    d = 20.0 / n
+    return WorkloadSpec(name=f"x1_cylindrical_wave_{points}pt_{dtype}", nx=n, ny=n, nz=1,
+                        dtype=dtype, nsteps=0, eps_r=np.ones((1, n, n)), sigma=None,
+                        cfl_frac=1.0, source=dict(axis=2, i=n // 2, j=n // 2, k=0, i_max=1.0,
+                                                  sigma_t=2e-8),
+                        spacing=(d, d, 1.0), eps0=EPS0_SI, mu0=MU0_SI, t_end=2e-7)
+
+
+def steps_for(t_end: float, dt_cfl: float) -> tuple:
+    """(n_t, dt): the fewest equal steps of at most dt_cfl that reach t_end."""
+    nt = int(math.ceil(t_end / dt_cfl))
+    return nt, t_end / nt

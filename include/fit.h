@@ -262,6 +262,14 @@ int fit_adjoint_grad(fit_grid* g, double* deps, double* dsigma, int on_device);
  * FIT_E_INVALID if tol is below what u allows.  Host only. */
 int fit_expm_params(double theta, double tol, double unit_roundoff, int* m, int64_t* s);
 
+/* Tolerance of the exponential that balances its backward error against the
+ * O(dt^2) leapfrog error of the particular solutions (Sec. III-D, eq.
+ * tolerance_leja_2): tol = beta dt^2 / kappa_exp(A), with kappa_exp(A) =
+ * ||A||_2 = rho for the normal A of eq. FIT_ode_2.  beta > 0 is the
+ * caller's constant of the leapfrog error (the paper leaves it open).
+ * FIT_E_INVALID unless beta, dt, rho are positive and finite.  Host only. */
+int fit_expm_tolerance(double beta, double dt, double rho, double* tol);
+
 /* out = alpha B in (two curl applications).  Needs a uniform mu; inputs
  * and outputs must be distinct buffers.  Errors: FIT_E_INVALID. */
 int fit_op_apply(fit_grid* g, double alpha, const void* e_in, const void* h_in, void* e_out,

@@ -27,7 +27,7 @@ import math
 
 import numpy as np
 
-__all__ = ["taylor_error_bound", "taylor_parameters", "expm_action"]
+__all__ = ["taylor_error_bound", "taylor_parameters", "expm_action", "optimal_tolerance"]
 
 
 def taylor_error_bound(theta: float, m: int, s: int, unit_roundoff: float = 2.0 ** -53) -> float:
@@ -112,3 +112,14 @@ def expm_action(A, b, t: float, rho: float, tol: float = 1e-12, params=None,
             acc += term
         x = acc
     return x, (m, s)
+
+
+def optimal_tolerance(beta: float, dt: float, rho: float) -> float:
+    """Sec. III-D, eq. tolerance_leja_2: with the leapfrog error of the
+    particular solutions eps_B = beta dt^2, the exponential's backward-error
+    tolerance that makes eps_B / eps_A equal to kappa_exp(A), and
+    kappa_exp(A) = ||A||_2 = rho for the normal A of eq. FIT_ode_2."""
+    if not (beta > 0 and dt > 0 and rho > 0):
+        raise ValueError("beta, dt and rho must be positive")
+    eps_b = beta * dt * dt
+    return eps_b / rho

@@ -64,6 +64,7 @@ SIGNATURES = {
                        C.POINTER(C.c_int)],
     "fit_gram": [_vp, _vp, _i64, _i, _i, _dp],
     "fit_expm_params": [_d, _d, _d, C.POINTER(C.c_int), _i64p],
+    "fit_expm_tolerance": [_d, _d, _d, C.POINTER(C.c_double)],
     "fit_op_apply": [_vp, _d, _vp, _vp, _vp, _vp],
     "fit_op_norm": [_vp, _i, C.c_uint64, _dp],
     "fit_expm": [_vp, _d, _d, _d, _vp, _vp, _vp, _vp, C.POINTER(C.c_int), _i64p],

@@ -269,6 +269,15 @@ int fit_expm_params(double theta, double tol, double unit_roundoff, int* m, int6
   return FIT_OK;
 }
 
+int fit_expm_tolerance(double beta, double dt, double rho, double* tol) {
+  if (!tol) return fail(FIT_E_INVALID, "null argument");
+  if (!(beta > 0.0) || !std::isfinite(beta) || !(dt > 0.0) || !std::isfinite(dt) ||
+      !(rho > 0.0) || !std::isfinite(rho))
+    return fail(FIT_E_INVALID, "beta, dt and rho must be positive and finite");
+  *tol = beta * dt * dt / rho;
+  return FIT_OK;
+}
+
 int fit_op_apply(fit_grid* g, double alpha, const void* e_in, const void* h_in, void* e_out,
                  void* h_out) {
   if (!g || !e_in || !h_in || !e_out || !h_out) return fail(FIT_E_INVALID, "null argument");

@@ -202,6 +202,13 @@ class FitGrid:
              C.byref(s_))
         return m.value, s_.value
 
+    @staticmethod
+    def expm_tolerance(beta: float, dt: float, rho: float) -> float:
+        """beta dt^2 / ||A||_2 (eq. tolerance_leja_2)."""
+        v = C.c_double()
+        call("fit_expm_tolerance", float(beta), float(dt), float(rho), C.byref(v))
+        return v.value
+
     def step(self, nsteps: int, dt: float):
         call("fit_step", self._h, int(nsteps), float(dt))
 

@@ -24,6 +24,7 @@ import numpy as np
 import torch
 
 from .batch import FitBatch
+from ._lib import FitError
 from .grid import FitGrid
 
 __all__ = ["ParaExpResult", "paraexp"]
@@ -34,22 +35,24 @@ class ParaExpResult:
     e: torch.Tensor                 # e^(N)
     h: torch.Tensor                 # h^(N+1/2)
     rho: float                      # ||A||_2 used for the Taylor parameters
+    tol: float                      # tolerance of every exponential
     expm_params: list               # (m, s) of every exponential, in order
     A_applications: int             # applications of B (2 curl products each)
     smvp_leapfrog: int              # curl products of the p particular runs
-    C_proc: int                     # eq. tot_cost with the longest propagation
+    C_proc: Optional[int]           # eq. tot_cost with the longest propagation
 
 
 def paraexp(nx: int, ny: int, nz: int, eps_r, dt: float, nsteps: int, p: int,
             source: Optional[dict] = None, dtype: str = "f32", tol: float = 1e-8,
             rho: Optional[float] = None, norm_iters: int = 60, norm_margin: float = 1.02,
             spacing=(1.0, 1.0, 1.0), e0=None, h0=None, use_graph: bool = True,
-            batch_tuning=None) -> ParaExpResult:
+            batch_tuning=None, beta: Optional[float] = None) -> ParaExpResult:
     """Alg. 1 for a lossless grid with uniform mu.  ``source``: dict(axis, i, j,
     k, i_max, sigma_t) in time units (or sigma_t_steps).  ``rho``: ||A||_2 or a
     bound; by default the power-iteration estimate times ``norm_margin``
     (the Rayleigh quotients approach the norm from below).  ``e0``, ``h0``:
-    initial e^(0), h^(1/2) (default zero)."""
+    initial e^(0), h^(1/2) (default zero).  ``beta``: if given, ``tol`` is
+    replaced by beta dt^2 / rho (eq. tolerance_leja_2)."""
     if nsteps % p:
         raise ValueError("nsteps must be divisible by p")
     L = nsteps // p
@@ -71,6 +74,8 @@ def paraexp(nx: int, ny: int, nz: int, eps_r, dt: float, nsteps: int, p: int,
     g0 = grids[0]
     if rho is None:
         rho = g0.op_norm(norm_iters) * norm_margin
+    if beta is not None:
+        tol = FitGrid.expm_tolerance(beta, dt, rho)
     params = []
     ye, yh = g0.new_field(), g0.new_field()
     started = False
@@ -96,11 +101,17 @@ def paraexp(nx: int, ny: int, nz: int, eps_r, dt: float, nsteps: int, p: int,
         params.append(ms)
         g0.axpy(1.0, ye, hh, ep, hp)       # e^(N) += y_e(T), h^(N+1/2) += y_h(T + dt/2)
     n_a = sum(m * s for m, s in params)
-    # eq. tot_cost: the longest propagation of the parallel form is (T - T_1)
-    m1, s1 = (FitGrid.expm_params(rho * (nsteps - L) * dt, tol, FitGrid.UNIT_ROUNDOFF[dtype])
-              if p > 1 else (0, 1))
-    res = ParaExpResult(e=ep, h=hp, rho=rho, expm_params=params, A_applications=n_a,
-                        smvp_leapfrog=2 * nsteps, C_proc=2 * L + m1 * s1 + 2)
+    # eq. tot_cost: the longest propagation of the parallel form is (T - T_1);
+    # None when that exponential cannot meet ``tol`` in this dtype (its
+    # rounding floor grows with the length of the propagation)
+    try:
+        m1, s1 = (FitGrid.expm_params(rho * (nsteps - L) * dt, tol, FitGrid.UNIT_ROUNDOFF[dtype])
+                  if p > 1 else (0, 1))
+        c_proc = 2 * L + m1 * s1 + 2
+    except FitError:
+        c_proc = None
+    res = ParaExpResult(e=ep, h=hp, rho=rho, tol=tol, expm_params=params, A_applications=n_a,
+                        smvp_leapfrog=2 * nsteps, C_proc=c_proc)
     for g in grids:
         g.close()
     return res

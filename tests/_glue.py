@@ -20,7 +20,7 @@ def oracle_ops(spec_or_dims, eps=None, sigma=None, mu=None, spacing=(1.0, 1.0, 1
         s = spec_or_dims
         t = Topology(s.nx, s.ny, s.nz)
         return Operators(t, Materials(t, s.eps_r, sigma=s.sigma, mu_r=s.mu_r,
-                                      spacing=s.spacing))
+                                      spacing=s.spacing, eps0=s.eps0, mu0=s.mu0))
     nx, ny, nz = spec_or_dims
     t = Topology(nx, ny, nz)
     eps = np.ones((nz, ny, nx)) if eps is None else eps
@@ -28,14 +28,15 @@ def oracle_ops(spec_or_dims, eps=None, sigma=None, mu=None, spacing=(1.0, 1.0, 1
 
 
 def spec_dt(spec) -> float:
-    return spec.cfl_frac * cfl_dt(spec.eps_r, spec.mu_r, spec.spacing)
+    return spec.cfl_frac * cfl_dt(spec.eps_r, spec.mu_r, spec.spacing, spec.eps0, spec.mu0)
 
 
 def oracle_source(spec, dt):
     if spec.source is None:
         return None
     s = dict(spec.source)
-    s["sigma_t"] = s.pop("sigma_t_steps") * dt
+    if "sigma_t_steps" in s:
+        s["sigma_t"] = s.pop("sigma_t_steps") * dt
     return s
 
 

@@ -74,6 +74,11 @@ def test_expm_params_match_oracle():
         assert FitGrid.expm_params(theta, tol, u) == oexpm.taylor_parameters(theta, tol, u), theta
     with pytest.raises(FitError, match="INVALID"):
         FitGrid.expm_params(500.0, 1e-9, 2.0 ** -24)
+    for beta, dt, rho in ((0.3, 0.05, 3.4), (2.0, 1e-11, 7e10)):
+        assert FitGrid.expm_tolerance(beta, dt, rho) == oexpm.optimal_tolerance(beta, dt, rho)
+    for bad in ((0.0, 0.1, 1.0), (1.0, -0.1, 1.0), (1.0, 0.1, float("inf"))):
+        with pytest.raises(FitError, match="INVALID"):
+            FitGrid.expm_tolerance(*bad)
 
 
 @pytest.mark.parametrize("dtype,t", [("f64", 0.3), ("f64", 17.0), ("f32", 9.0)])
@@ -115,8 +120,9 @@ def test_shift_h_is_the_collocation_transform():
     g.close()
 
 
-@pytest.mark.parametrize("dtype,p", [("f64", 4), ("f64", 1), ("f32", 3)])
-def test_paraexp_matches_oracle(dtype, p):
+@pytest.mark.parametrize("dtype,p,beta", [("f64", 4, None), ("f64", 1, None), ("f32", 3, None),
+                                          ("f64", 2, 1e-9)])
+def test_paraexp_matches_oracle(dtype, p, beta):
     from paper_1705_08019_amd.paraexp import paraexp
     n = (12, 9, 8)
     nx, ny, nz = n
@@ -127,8 +133,12 @@ def test_paraexp_matches_oracle(dtype, p):
     src = dict(axis=2, i=6, j=4, k=4, i_max=1.0, sigma_t=8 * dt)
     rho = spectral_norm(ops)
     tol = 1e-11 if dtype == "f64" else 1e-3
+    if beta is not None:            # eq. tolerance_leja_2
+        tol = oexpm.optimal_tolerance(beta, dt, rho)
     from paper_1705_08019_amd import FitGrid
-    res = paraexp(nx, ny, nz, eps, dt, N, p, src, dtype=dtype, tol=tol, rho=rho)
+    res = paraexp(nx, ny, nz, eps, dt, N, p, src, dtype=dtype, tol=None if beta else tol, rho=rho,
+                  beta=beta)
+    assert res.tol == tol
     e_o, h_o, cost = opx.paraexp(ops, dt, N, p, src, tol=tol, rho=rho,
                                  unit_roundoff=FitGrid.UNIT_ROUNDOFF[dtype])
     # the exponentials differ by rounding only (same parameters); the FP32

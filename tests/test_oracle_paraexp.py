@@ -178,3 +178,35 @@ def test_paraexp_and_leapfrog_differ_at_second_order():
         e_px, _, _ = paraexp.paraexp(ops, dt, N, 4, src, tol=2e-12)
         gaps.append(np.linalg.norm(e_px - e_lf) / np.linalg.norm(e_lf))
     assert 3.5 < gaps[0] / gaps[1] < 4.5 and 3.5 < gaps[1] / gaps[2] < 4.5, gaps
+
+
+def test_condition_number_of_the_fit_exponential_is_the_spectral_norm():
+    """Sec. III-D uses kappa_exp(A) = ||A||_2 for normal A.  For the FIT skew
+    matrix the 2-norm relative condition number of exp at tA,
+    max_E ||L(tA, E)||_2 / ||E||_2 * ||tA||_2 / ||exp(tA)||_2 (L the Frechet
+    derivative), is t ||A||_2: exp(tA) is orthogonal, ||L(tA, E)||_2 <=
+    ||E||_2 for random E, with equality at E = I.  The optimal tolerance
+    then balances eps_B / eps_A against that condition number."""
+    import scipy.linalg as sla
+    ops = _ops(4, 3, 3, dielectric_blocks(4, 3, 3, 2, 7))
+    A = skew_matrix(ops).toarray()
+    rho = spectral_norm(ops)
+    t = 0.7
+    X = t * A
+    E_X = sla.expm(X)
+    assert np.linalg.norm(E_X.T @ E_X - np.eye(len(A)), 2) <= 1e-12
+    rng = np.random.default_rng(0)
+    ratios = []
+    for q in range(6):
+        E = np.eye(len(A)) if q == 0 else rng.standard_normal(A.shape)
+        _, L = sla.expm_frechet(X, E)
+        ratios.append(np.linalg.norm(L, 2) / np.linalg.norm(E, 2))
+    assert abs(ratios[0] - 1.0) <= 1e-10
+    assert max(ratios) <= 1.0 + 1e-10
+    kappa = max(ratios) * np.linalg.norm(X, 2) / np.linalg.norm(E_X, 2)
+    assert abs(kappa - t * rho) <= 1e-10 * t * rho
+    beta, dt = 0.3, 0.05
+    tol = expm.optimal_tolerance(beta, dt, kappa / t)
+    assert abs(beta * dt ** 2 / tol - kappa / t) <= 1e-12 * rho
+    with pytest.raises(ValueError):
+        expm.optimal_tolerance(0.0, dt, rho)
