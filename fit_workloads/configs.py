@@ -16,6 +16,10 @@ Everything here is input data.  The five named workloads are:
   20 m x 20 m x 1 m PEC box of vacuum, 41 (or 121) grid points per side in x
   and y and 2 in z, SI constants, the Gaussian line current of eq.
   line_current (1 A, 2e-8 s) on the z edge at the centre, T = 2e-7 s.
+  ``x1_graded(points, k)`` is the same box with one element shrunk so that
+  the largest over the smallest cell width is k (Sec. IV-A, eq.
+  ration-costs): on a tensor grid that element's column in x and row in y
+  get width s and all others k s, s = 20 / ((n - 1) k + 1).
 
 Reduced copies (``*_small``) regenerate the same recipe at a smaller size for
 parity runs against the oracle.
@@ -32,7 +36,7 @@ __all__ = [
     "WorkloadSpec", "dielectric_blocks", "lossy_slab", "facet_potential",
     "centre_source", "random_source", "batch_sizes", "probe_box",
     "c1", "c2", "c3", "c4", "c5", "c2_small", "c4_small", "c5_small", "scaled",
-    "EPS0_SI", "MU0_SI", "x1", "steps_for",
+    "EPS0_SI", "MU0_SI", "x1", "x1_graded", "steps_for",
 ]
 
 EPS0_SI = 8.8541878128e-12      # vacuum permittivity [F/m] (CODATA 2018)
@@ -207,6 +211,20 @@ def x1(points: int = 41, dtype: str = "f64") -> WorkloadSpec:
                         cfl_frac=1.0, source=dict(axis=2, i=n // 2, j=n // 2, k=0, i_max=1.0,
                                                   sigma_t=2e-8),
                         spacing=(d, d, 1.0), eps0=EPS0_SI, mu0=MU0_SI, t_end=2e-7)
+
+
+def x1_graded(points: int = 41, k: float = 1.0, dtype: str = "f64") -> WorkloadSpec:
+    """x1 with per-axis cell widths: the cells with x index (points - 1) // 4
+    and y index (points - 1) // 4 are k times narrower than all others, the
+    box stays 20 m wide."""
+    spec = x1(points, dtype)
+    n = spec.nx
+    small = 20.0 / ((n - 1) * k + 1.0)
+    w = np.full(n, k * small)
+    w[n // 4] = small
+    spec.name = f"x1_graded_k{k:g}_{points}pt_{dtype}"
+    spec.spacing = (w.copy(), w.copy(), np.array([1.0]))
+    return spec
 
 
 def steps_for(t_end: float, dt_cfl: float) -> tuple:

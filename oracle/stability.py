@@ -21,11 +21,16 @@ __all__ = ["cfl_dt", "skew_matrix", "spectral_norm"]
 
 def cfl_dt(eps_r, mu_r=None, spacing=(1.0, 1.0, 1.0), eps0: float = 1.0,
            mu0: float = 1.0) -> float:
-    """dt_CFL = min over cells of sqrt(eps mu / (dx^-2 + dy^-2 + dz^-2))."""
+    """dt_CFL = min over cells of sqrt(eps mu / (dx^-2 + dy^-2 + dz^-2)), the
+    widths taken per cell (``spacing``: three scalars or three per-axis
+    arrays of cell widths; per-cell arrays have shape (nz, ny, nx))."""
     eps = eps0 * np.asarray(eps_r, dtype=np.float64)
     mu = mu0 * (np.ones_like(eps) if mu_r is None else np.asarray(mu_r, dtype=np.float64))
-    dx, dy, dz = spacing
-    inv = 1.0 / dx ** 2 + 1.0 / dy ** 2 + 1.0 / dz ** 2
+    nz, ny, nx = eps.shape
+    wx, wy, wz = (np.broadcast_to(np.asarray(s, dtype=np.float64), (n,))
+                  for s, n in zip(spacing, (nx, ny, nz)))
+    inv = (1.0 / wx[None, None, :] ** 2 + 1.0 / wy[None, :, None] ** 2 +
+           1.0 / wz[:, None, None] ** 2)
     return float(np.min(np.sqrt(eps * mu / inv)))
 
 
