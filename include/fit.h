@@ -104,6 +104,21 @@ int fit_grid_destroy(fit_grid* g);
 int fit_set_materials(fit_grid* g, const double* eps_r, const double* mu_r,
                       const double* sigma);
 
+/* Per-axis cell widths of a tensor grid (non-uniform spacing; Sec. II with
+ * the per-cell dimensions of eq. cfl): dx[nx], dy[ny], dz[nz] host FP64
+ * arrays of positive finite widths, replacing the descriptor's uniform
+ * spacing.  All three NULL returns to the descriptor's spacing.  The current
+ * materials are re-applied: an a-edge with index i along a gets M_eps =
+ * eps0 sum_c eps_r[c] (d_b[c] d_c[c] / 4) / d_a[i] over its <= 4 cells, an
+ * a-facet M_mu^{-1} = sum_c (d_a[c] / 2) / (mu0 mu_r[c]) / (d_b d_c) over its
+ * 2 cells, and dt_CFL takes each cell's own widths.  On such a grid the
+ * step uses the split kernels (the device arrays hold cell values times the
+ * cell volume); the fused path, batches, the adjoint and the exponential
+ * entry points reject it with FIT_E_INVALID.
+ * Errors: FIT_E_INVALID (a width <= 0 or non-finite, some but not all NULL),
+ * FIT_E_OOM. */
+int fit_set_spacing(fit_grid* g, const double* dx, const double* dy, const double* dz);
+
 /* Gaussian line-current source (Sec. IV-A, eq. line_current):
  * i(t) = i_max exp(-4 ((t - sigma_t) / sigma_t)^2) on the single primal edge
  * of direction `axis` (0, 1, 2) leaving node (i, j, k), flowing in +axis,

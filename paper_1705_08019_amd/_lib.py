@@ -43,6 +43,7 @@ SIGNATURES = {
     "fit_grid_create": [C.POINTER(GridDesc), _vp, C.POINTER(_vp)],
     "fit_grid_destroy": [_vp],
     "fit_set_materials": [_vp, _dp, _dp, _dp],
+    "fit_set_spacing": [_vp, _dp, _dp, _dp],
     "fit_set_source": [_vp, _i, _i, _i, _i, _d, _d],
     "fit_cfl_dt": [_vp, _dp],
     "fit_set_fields": [_vp, _vp, _vp, _i64, _i],

@@ -150,6 +150,12 @@ static bool valid_box(const int32_t lo[3], const int32_t hi[3]) {
   return true;
 }
 
+void set_metric(const fit_grid* g, const double* sq[3]) {
+  sq[0] = g->nu ? g->sq : nullptr;
+  sq[1] = g->nu ? g->sq + g->d.nx : nullptr;
+  sq[2] = g->nu ? g->sq + g->d.nx + g->d.ny : nullptr;
+}
+
 template <typename T>
 static void fill_eargs(fit_grid* g, EArgs<T>& a, const T* ein, T* eout, const T* h, double dt,
                        int64_t m) {
@@ -166,6 +172,8 @@ static void fill_eargs(fit_grid* g, EArgs<T>& a, const T* ein, T* eout, const T*
   a.d = d;
   a.t = make_tiling(d, g->ty, g->kc);
   a.hs = (T)(0.5 * dt);
+  set_metric(g, a.sq);
+  a.kbs = 4.0 * dt;
   a.src_comp = g->src_axis;
   a.src_idx = g->src_axis >= 0 ? g->src_idx : -1;
   const double val = g->src_axis >= 0 ? source_value(g, dt, m) : 0.0;
@@ -192,6 +200,8 @@ static void fill_hargs(fit_grid* g, HArgs<T>& a, const T* e, const T* hin, T* ho
   a.d = d;
   a.t = make_tiling(d, g->ty, g->kc);
   a.part = g->part;
+  set_metric(g, a.sq);
+  a.kds = dt;
 }
 
 ProfScope::ProfScope(fit_grid* g_, int kind) : g(g_), slot(-1) {
@@ -551,6 +561,7 @@ int fit_grid_destroy(fit_grid* g) {
   dev_free(g->eps);
   dev_free(g->sig);
   dev_free(g->imu);
+  dev_free(reinterpret_cast<void*&>(g->sq));
   dev_free(reinterpret_cast<void*&>(g->part));
   dev_free(reinterpret_cast<void*&>(g->trace));
   dev_free(reinterpret_cast<void*&>(g->jacc));
@@ -565,33 +576,38 @@ int fit_grid_destroy(fit_grid* g) {
   return FIT_OK;
 }
 
-int fit_set_materials(fit_grid* g, const double* eps_r, const double* mu_r, const double* sigma) {
-  if (!g || !eps_r) return fail(FIT_E_INVALID, "null argument");
+// Uploads the per-cell device arrays from the stored inputs (g->in_*) and
+// the current spacing.  On a tensor grid the arrays hold the cell values
+// times the cell volume and imu is always per cell.
+static int apply_materials(fit_grid* g) {
   g->gram_w_ok[0] = g->gram_w_ok[1] = false;
   const int64_t n = g->d.n;
+  const int nx = g->d.nx, ny = g->d.ny;
   std::vector<double> eps((size_t)n), imu((size_t)n), sig;
+  const bool has_mu = !g->in_mu.empty(), has_sig = !g->in_sig.empty();
   bool lossy = false;
   double cfl = INFINITY;
-  const double inv = 1.0 / (g->desc.dx * g->desc.dx) + 1.0 / (g->desc.dy * g->desc.dy) +
-                     1.0 / (g->desc.dz * g->desc.dz);
-  bool mu_uni = true;
+  const double inv_u = 1.0 / (g->desc.dx * g->desc.dx) + 1.0 / (g->desc.dy * g->desc.dy) +
+                       1.0 / (g->desc.dz * g->desc.dz);
+  bool mu_uni = !g->nu;
+  if (has_sig) sig.resize((size_t)n);
   for (int64_t c = 0; c < n; ++c) {
-    const double er = eps_r[c];
-    const double mr = mu_r ? mu_r[c] : 1.0;
-    if (!(er > 0.0) || !std::isfinite(er)) return fail(FIT_E_INVALID, "eps_r must be > 0 and finite");
-    if (!(mr > 0.0) || !std::isfinite(mr)) return fail(FIT_E_INVALID, "mu_r must be > 0 and finite");
-    eps[c] = g->desc.eps0 * er;
-    imu[c] = 1.0 / (g->desc.mu0 * mr);
+    const double er = g->in_eps[c];
+    const double mr = has_mu ? g->in_mu[c] : 1.0;
+    double vol = 1.0, inv = inv_u;
+    if (g->nu) {
+      const int i = (int)(c % nx), j = (int)((c / nx) % ny), k = (int)(c / ((int64_t)nx * ny));
+      const double wx = g->wd[0][i], wy = g->wd[1][j], wz = g->wd[2][k];
+      vol = wx * wy * wz;
+      inv = 1.0 / (wx * wx) + 1.0 / (wy * wy) + 1.0 / (wz * wz);
+    }
+    eps[c] = g->desc.eps0 * er * vol;
+    imu[c] = vol / (g->desc.mu0 * mr);
     if (imu[c] != imu[0]) mu_uni = false;
-    cfl = std::min(cfl, std::sqrt(eps[c] * (g->desc.mu0 * mr) / inv));
-  }
-  if (sigma) {
-    sig.resize((size_t)n);
-    for (int64_t c = 0; c < n; ++c) {
-      if (!(sigma[c] >= 0.0) || !std::isfinite(sigma[c]))
-        return fail(FIT_E_INVALID, "sigma must be >= 0 and finite");
-      sig[c] = sigma[c];
-      if (sigma[c] != 0.0) lossy = true;
+    cfl = std::min(cfl, std::sqrt(g->desc.eps0 * er * (g->desc.mu0 * mr) / inv));
+    if (has_sig) {
+      sig[c] = g->in_sig[c] * vol;
+      if (g->in_sig[c] != 0.0) lossy = true;
     }
   }
   int rc = g->f64 ? upload_cells<double>(g, &g->eps, eps, "eps") : upload_cells<float>(g, &g->eps, eps, "eps");
@@ -615,6 +631,58 @@ int fit_set_materials(fit_grid* g, const double* eps_r, const double* mu_r, cons
   g->sig_host = lossy ? sig : std::vector<double>();
   g->materials_version++;
   return FIT_OK;
+}
+
+int fit_set_materials(fit_grid* g, const double* eps_r, const double* mu_r, const double* sigma) {
+  if (!g || !eps_r) return fail(FIT_E_INVALID, "null argument");
+  const int64_t n = g->d.n;
+  for (int64_t c = 0; c < n; ++c) {
+    if (!(eps_r[c] > 0.0) || !std::isfinite(eps_r[c]))
+      return fail(FIT_E_INVALID, "eps_r must be > 0 and finite");
+    if (mu_r && (!(mu_r[c] > 0.0) || !std::isfinite(mu_r[c])))
+      return fail(FIT_E_INVALID, "mu_r must be > 0 and finite");
+    if (sigma && (!(sigma[c] >= 0.0) || !std::isfinite(sigma[c])))
+      return fail(FIT_E_INVALID, "sigma must be >= 0 and finite");
+  }
+  g->in_eps.assign(eps_r, eps_r + n);
+  if (mu_r) g->in_mu.assign(mu_r, mu_r + n);
+  else g->in_mu.clear();
+  if (sigma) g->in_sig.assign(sigma, sigma + n);
+  else g->in_sig.clear();
+  return apply_materials(g);
+}
+
+int fit_set_spacing(fit_grid* g, const double* dx, const double* dy, const double* dz) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  const double* w[3] = {dx, dy, dz};
+  const int nn[3] = {g->d.nx, g->d.ny, g->d.nz};
+  const int nnull = (dx == nullptr) + (dy == nullptr) + (dz == nullptr);
+  if (nnull == 3) {
+    g->nu = false;
+    for (auto& v : g->wd) v.clear();
+    return apply_materials(g);
+  }
+  if (nnull != 0) return fail(FIT_E_INVALID, "give all three width arrays or none");
+  for (int a = 0; a < 3; ++a)
+    for (int i = 0; i < nn[a]; ++i)
+      if (!(w[a][i] > 0.0) || !std::isfinite(w[a][i]))
+        return fail(FIT_E_INVALID, "cell widths must be > 0 and finite");
+  if (!g->sq) {
+    int rc = dev_alloc(reinterpret_cast<void**>(&g->sq),
+                       (size_t)(nn[0] + nn[1] + nn[2]) * sizeof(double), "cell widths");
+    if (rc) return rc;
+  }
+  std::vector<double> q;
+  for (int a = 0; a < 3; ++a) {
+    g->wd[a].assign(w[a], w[a] + nn[a]);
+    for (int i = 0; i < nn[a]; ++i) q.push_back(w[a][i] * w[a][i]);
+  }
+  hipError_t e = hipMemcpyAsync(g->sq, q.data(), q.size() * sizeof(double),
+                                hipMemcpyHostToDevice, g->s);
+  if (e == hipSuccess) e = hipStreamSynchronize(g->s);
+  if (e != hipSuccess) return hip_fail(e, "cell widths upload");
+  g->nu = true;
+  return apply_materials(g);
 }
 
 int fit_set_source(fit_grid* g, int axis, int i, int j, int k, double i_max, double sigma_t) {
@@ -747,12 +815,14 @@ int fit_energy(fit_grid* g, double out[2]) {
     e = launch_energy<double>(static_cast<const double*>(g->e), static_cast<const double*>(g->h),
                               static_cast<const double*>(g->eps),
                               g->mu_uniform ? nullptr : static_cast<const double*>(g->imu),
-                              g->imu_u, g->d, ge, gf2, g->part, &nblk, g->s);
+                              g->imu_u, g->d, ge, gf2, g->nu ? g->sq : nullptr, g->part, &nblk,
+                              g->s);
   else
     e = launch_energy<float>(static_cast<const float*>(g->e), static_cast<const float*>(g->h),
                              static_cast<const float*>(g->eps),
                              g->mu_uniform ? nullptr : static_cast<const float*>(g->imu),
-                             (float)g->imu_u, g->d, ge, gf2, g->part, &nblk, g->s);
+                             (float)g->imu_u, g->d, ge, gf2, g->nu ? g->sq : nullptr, g->part,
+                             &nblk, g->s);
   if (e != hipSuccess) return hip_fail(e, "energy launch");
   // reduce into the tail of the partial buffer's first row is unsafe; use the pending slot pair
   const int cols[kPartTerms] = {0, 1, -1, -1, -1, -1, -1, -1, -1, -1};
@@ -911,11 +981,11 @@ int fit_gram(fit_grid* g, const void* X, int64_t ld, int K, int which, double* G
     if (g->f64)
       e = launch_gram_weights<double>(g->gram_w[which], which, static_cast<const double*>(g->eps),
                                       g->mu_uniform ? nullptr : static_cast<const double*>(g->imu),
-                                      g->imu_u, g->d, gw, g->s);
+                                      g->imu_u, g->d, gw, g->nu ? g->sq : nullptr, g->s);
     else
       e = launch_gram_weights<float>(g->gram_w[which], which, static_cast<const float*>(g->eps),
                                      g->mu_uniform ? nullptr : static_cast<const float*>(g->imu),
-                                     (float)g->imu_u, g->d, gw, g->s);
+                                     (float)g->imu_u, g->d, gw, g->nu ? g->sq : nullptr, g->s);
     if (e != hipSuccess) return hip_fail(e, "Gram weights");
     g->gram_w_ok[which] = true;
   }
@@ -939,6 +1009,7 @@ int fit_gram(fit_grid* g, const void* X, int64_t ld, int K, int which, double* G
 int fit_set_tuning(fit_grid* g, int path, int tw, int ty, int kc) {
   if (!g) return fail(FIT_E_INVALID, "null handle");
   if (path < 0 || path > 2) return fail(FIT_E_INVALID, "path must be 0 (auto), 1 (split), 2 (fused)");
+  if (path == 2 && g->nu) return fail(FIT_E_INVALID, "the fused step needs a uniform spacing");
   if (path == 2 && !g->mu_uniform) return fail(FIT_E_INVALID, "the fused step needs a uniform mu");
   const bool fused = path == 2 || (path == 0 && g->mu_uniform);
   const bool expl = tw != 0 || ty != 0 || kc != 0;

@@ -306,6 +306,10 @@ int fit_batch_create(fit_grid* const* grids, int nb, void* stream, fit_batch** o
       delete b;
       return fail(FIT_E_INVALID, "all grids of a batch need the same dtype");
     }
+    if (gr->nu) {
+      delete b;
+      return fail(FIT_E_INVALID, "batched grids need a uniform spacing");
+    }
     if (!gr->mu_uniform) {
       delete b;
       return fail(FIT_E_INVALID, "batched grids need a uniform mu");

@@ -140,6 +140,7 @@ static int mdot_t(fit_grid* g, const T* ae, const T* ah, const T* be, const T* b
 }
 
 static int need_op(const fit_grid* g) {
+  if (g->nu) return fail(FIT_E_INVALID, "the operator needs a uniform spacing");
   if (!g->mu_uniform) return fail(FIT_E_INVALID, "the operator needs a uniform mu");
   if (g->lossy) return fail(FIT_E_INVALID, "the exponential needs a lossless grid (sigma = 0)");
   return FIT_OK;
@@ -242,6 +243,8 @@ static int shift_h_t(fit_grid* g, double c, const T* e, const T* hin, T* hout) {
   a.d = d;
   a.t = make_tiling(d, g->ty, g->kc);
   a.part = nullptr;
+  set_metric(g, a.sq);
+  a.kds = c;
   hipError_t err;
   {
     ProfScope ps(g, FIT_PROF_HPASS);
@@ -281,6 +284,7 @@ int fit_expm_tolerance(double beta, double dt, double rho, double* tol) {
 int fit_op_apply(fit_grid* g, double alpha, const void* e_in, const void* h_in, void* e_out,
                  void* h_out) {
   if (!g || !e_in || !h_in || !e_out || !h_out) return fail(FIT_E_INVALID, "null argument");
+  if (g->nu) return fail(FIT_E_INVALID, "the operator needs a uniform spacing");
   if (!g->mu_uniform) return fail(FIT_E_INVALID, "the operator needs a uniform mu");
   if (e_in == e_out || h_in == h_out || e_in == h_out || h_in == e_out)
     return fail(FIT_E_INVALID, "input and output must be distinct buffers");

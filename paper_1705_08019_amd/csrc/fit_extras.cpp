@@ -176,6 +176,7 @@ int fit_adjoint_begin(fit_grid* g, int64_t nsteps, double dt) {
   if (!g) return fail(FIT_E_INVALID, "null handle");
   if (nsteps < 1) return fail(FIT_E_INVALID, "nsteps must be >= 1");
   if (!g->probe.on) return fail(FIT_E_STATE, "the adjoint needs a probe (fit_set_probe)");
+  if (g->nu) return fail(FIT_E_INVALID, "the adjoint needs a uniform spacing");
   if (!g->mu_uniform) return fail(FIT_E_INVALID, "the adjoint needs a uniform mu");
   if (int rc = check_dt(g, dt)) return rc;
   if (!g->adj) {

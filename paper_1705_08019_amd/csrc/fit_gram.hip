@@ -46,6 +46,7 @@ struct WeightArgs {
   T imu_u;
   Dims d;
   double gw[3];        // g_a / 4 (which 0) or gf2_a (which 1)
+  const double* sq;    // tensor grid: squared widths [x | y | z], or null
 };
 
 // M_eps of an edge is (g_a / 4) times the sum of its 4 cells' eps0 eps_r;
@@ -63,6 +64,13 @@ __global__ __launch_bounds__(256) void k_gram_weights(WeightArgs<T> A) {
   const int j = (int)(t % A.d.ny);
   const int k = (int)(t / A.d.ny);
   const int64_t st[3] = {1, A.d.sx, A.d.sxy};
+  // tensor grid: the squared widths of this slot's cell indices per axis
+  double q[3] = {0.0, 0.0, 0.0};
+  if (A.sq) {
+    q[0] = A.sq[i];
+    q[1] = A.sq[A.d.nx + j];
+    q[2] = A.sq[A.d.nx + A.d.ny + k];
+  }
   double w = 0.0;
   if (A.which == 0) {
     if (g_edge_live(a, i, j, k)) {
@@ -70,19 +78,21 @@ __global__ __launch_bounds__(256) void k_gram_weights(WeightArgs<T> A) {
       const T* e = A.eps;
       const double s = (double)e[idx] + (double)e[idx - st[b]] + (double)e[idx - st[c]] +
                        (double)e[idx - st[b] - st[c]];
-      w = A.gw[a] * s;
+      w = (A.sq ? 0.25 / q[a] : A.gw[a]) * s;
     }
   } else if (g_facet_live(a, i, j, k)) {
     const double m = A.imu ? (double)A.imu[idx] + (double)A.imu[idx - st[a]]
                            : 2.0 * (double)A.imu_u;
-    w = 1.0 / (A.gw[a] * m);
+    const int b = (a + 1) % 3, c = (a + 2) % 3;
+    w = 1.0 / ((A.sq ? 0.5 / (q[b] * q[c]) : A.gw[a]) * m);
   }
   A.W[r] = w;
 }
 
 template <typename T>
 hipError_t launch_gram_weights(double* W, int which, const T* eps, const T* imu, T imu_u,
-                               const Dims& d, const double gw[3], hipStream_t s) {
+                               const Dims& d, const double gw[3], const double* sq,
+                               hipStream_t s) {
   WeightArgs<T> A;
   A.W = W;
   A.which = which;
@@ -90,6 +100,7 @@ hipError_t launch_gram_weights(double* W, int which, const T* eps, const T* imu,
   A.imu = imu;
   A.imu_u = imu_u;
   A.d = d;
+  A.sq = sq;
   for (int c = 0; c < 3; ++c) A.gw[c] = gw[c];
   const int64_t rows = 3 * d.n;
   hipLaunchKernelGGL(k_gram_weights<T>, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, s, A);
@@ -392,9 +403,11 @@ hipError_t launch_gram(const T* X, int64_t ld, int K, const double* W, const Dim
 }
 
 template hipError_t launch_gram_weights<float>(double*, int, const float*, const float*, float,
-                                               const Dims&, const double*, hipStream_t);
+                                               const Dims&, const double*, const double*,
+                                               hipStream_t);
 template hipError_t launch_gram_weights<double>(double*, int, const double*, const double*, double,
-                                                const Dims&, const double*, hipStream_t);
+                                                const Dims&, const double*, const double*,
+                                                hipStream_t);
 template hipError_t launch_gram<float>(const float*, int64_t, int, const double*, const Dims&,
                                        double*, int64_t, double*, hipStream_t, int64_t*);
 template hipError_t launch_gram<double>(const double*, int64_t, int, const double*, const Dims&,

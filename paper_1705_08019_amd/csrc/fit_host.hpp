@@ -35,6 +35,12 @@ struct fit_grid {
   double imu_u = 1.0;
   double cfl = 0.0;
   std::vector<double> eps_host, sig_host;   // FP64 copies (adjoint chain rule, checks)
+  // the caller's per-cell inputs (re-applied when the cell widths change)
+  std::vector<double> in_eps, in_mu, in_sig;
+  // tensor grid with per-axis cell widths (fit_set_spacing)
+  bool nu = false;
+  std::vector<double> wd[3];
+  double* sq = nullptr;          // device: squared widths [x (nx) | y (ny) | z (nz)]
   int64_t materials_version = 0;
   double gedge[3] = {1, 1, 1};   // d_b d_c / d_a
   double gf2[3] = {0.5, 0.5, 0.5};
@@ -84,6 +90,8 @@ int dev_alloc(void** p, size_t bytes, const char* what);
 void dev_free(void*& p);
 int ensure_part(fit_grid* g, int64_t rows);
 int ensure_pacc(fit_grid* g, int64_t rows);
+// The per-axis squared-width pointers of a tensor grid, or nulls.
+void set_metric(const fit_grid* g, const double* sq[3]);
 double source_value(const fit_grid* g, double dt, int64_t m);
 int check_dt(const fit_grid* g, double dt);
 template <typename T>

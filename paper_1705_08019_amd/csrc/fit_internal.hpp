@@ -65,6 +65,13 @@ struct EArgs {
   T kb[3];           // 4 dt / g_a with g_a = d_b d_c / d_a  (cb = kb / (S4eps + hs S4sig))
   T hs;              // dt / 2
   double ge[3];      // g_a / 4: M_eps = ge * S4eps,  M_sigma = ge * S4sig
+  // Tensor grid with per-axis cell widths (null on a uniform grid): sq[a][i]
+  // is the square of the a-width of cell index i, and eps, sig hold the cell
+  // values times the cell volume V.  An a-edge with index i along a then has
+  // M_eps = S4eps / (4 sq[a][i]) (its 4 cells share that width), so
+  // kb = kbs sq[a][i] with kbs = 4 dt and ge = 1 / (4 sq[a][i]).
+  const double* sq[3] = {nullptr, nullptr, nullptr};
+  double kbs = 0.0;
   int src_comp;      // -1: no source
   int64_t src_idx;
   T src_val;         // i(t_{m+1/2})
@@ -87,6 +94,13 @@ struct HArgs {
   T kd[3];           // dt * d_a / (d_b d_c) / 2  (cd = kd * (imu_1 + imu_2))
   double gf2[3];     // d_a / (d_b d_c) / 2: M_mu^{-1} = gf2 * (imu_1 + imu_2)
   double* part;
+  // Tensor grid (null on a uniform grid; needs the per-cell imu array, which
+  // then holds imu times the cell volume): an a-facet with indices j, k
+  // along the two other axes b, c has M_mu^{-1} = (imu_1 + imu_2) gf with
+  // gf = 1 / (2 sq[b][j] sq[c][k]) (its 2 cells share those widths), and
+  // kd = kds gf.
+  const double* sq[3] = {nullptr, nullptr, nullptr};
+  double kds = 0.0;
 };
 
 // Fused single-pass leapfrog step: reads state m from (e0, h0), writes state
@@ -127,9 +141,12 @@ hipError_t launch_step(const SArgs<T>& a, bool lossy, bool energy, bool probe, h
 
 // Row weights W (3 n doubles) of the Gram form: M_eps of the edges (which 0,
 // gw = g_a / 4) or M_mu of the facets (which 1, gw = gf2_a) (fit_gram.hip).
+// sq: null, or the squared cell widths [x (nx) | y (ny) | z (nz)] of a tensor
+// grid (then eps and imu hold cell values times the cell volume, gw unused).
 template <typename T>
 hipError_t launch_gram_weights(double* W, int which, const T* eps, const T* imu, T imu_u,
-                               const Dims& d, const double gw[3], hipStream_t s);
+                               const Dims& d, const double gw[3], const double* sq,
+                               hipStream_t s);
 
 // Gram matrix G = X^T diag(W) X over K snapshots (fit_gram.hip); part must
 // hold part_cap_blocks * 64 * 64 doubles, G (device) K * K doubles.
@@ -269,9 +286,10 @@ template <typename T>
 hipError_t launch_curl(const T* in, T* out, const Dims& d, int which, hipStream_t s);
 
 // Standalone energies <e,e>_eps and <h,h>_mu of a state -> part rows 0, 1.
+// sq as for launch_gram_weights.
 template <typename T>
 hipError_t launch_energy(const T* e, const T* h, const T* eps, const T* imu, T imu_u,
                          const Dims& d, const double ge[3], const double gf2[3],
-                         double* part, int64_t* nblk, hipStream_t s);
+                         const double* sq, double* part, int64_t* nblk, hipStream_t s);
 
 }  // namespace fit

@@ -91,6 +91,17 @@ __global__ __launch_bounds__(512) void k_epass(EArgs<T> A) {
 
   if (act) {
     const bool ip = i > 0, jp = j > 0;
+    // metric of this column (tensor grid) or the uniform constants
+    const bool nu = A.sq[0] != nullptr;
+    T kbx = A.kb[0], kby = A.kb[1], kbz = A.kb[2];
+    double gex = A.ge[0], gey = A.ge[1], gez = A.ge[2];
+    if (nu) {
+      const double qx = A.sq[0][i], qy = A.sq[1][j];
+      kbx = (T)(A.kbs * qx);
+      kby = (T)(A.kbs * qy);
+      gex = 0.25 / qx;
+      gey = 0.25 / qy;
+    }
     const T* __restrict__ hx = A.h[0];
     const T* __restrict__ hy = A.h[1];
     const T* __restrict__ hz = A.h[2];
@@ -121,6 +132,11 @@ __global__ __launch_bounds__(512) void k_epass(EArgs<T> A) {
       pj_xz = j >= A.probe.lo[1] && j <= A.probe.hi[1];
     }
     for (int k = k0; k < k1; ++k, idx += sxy) {
+      if (nu) {
+        const double qz = A.sq[2][k];
+        kbz = (T)(A.kbs * qz);
+        gez = 0.25 / qz;
+      }
       const T hxc = hx[idx], hyc = hy[idx], hzc = hz[idx];
       const T hz_jm = jp ? hz[idx - sx] : T(0);
       const T hx_jm = jp ? hx[idx - sx] : T(0);
@@ -154,14 +170,13 @@ __global__ __launch_bounds__(512) void k_epass(EArgs<T> A) {
       const T exo = A.ein[0][idx], eyo = A.ein[1][idx], ezo = A.ein[2][idx];
       T exn, eyn, ezn;
       e_point<T, LOSSY>(hxc, hyc, hzc, hxp, hyp, hx_jm, hy_im, hz_jm, hz_im, E4x, E4y, E4z, S4x,
-                        S4y, S4z, exo, eyo, ezo, jx, jy, jz, lx, ly, lz, A.kb[0], A.kb[1],
-                        A.kb[2], A.hs, exn, eyn, ezn);
+                        S4y, S4z, exo, eyo, ezo, jx, jy, jz, lx, ly, lz, kbx, kby, kbz, A.hs,
+                        exn, eyn, ezn);
       A.eout[0][idx] = exn;
       A.eout[1][idx] = eyn;
       A.eout[2][idx] = ezn;
       if (ENERGY) {
-        const double mx = A.ge[0] * (double)E4x, my = A.ge[1] * (double)E4y,
-                     mz = A.ge[2] * (double)E4z;
+        const double mx = gex * (double)E4x, my = gey * (double)E4y, mz = gez * (double)E4z;
         const double ox = exo, oy = eyo, oz = ezo, nx_ = exn, ny_ = eyn, nz_ = ezn;
         nadd(acc[PE_EE_MM], cmp[PE_EE_MM], mx * ox * ox + my * oy * oy + mz * oz * oz);
         nadd(acc[PE_EE_MM1], cmp[PE_EE_MM1], mx * ox * nx_ + my * oy * ny_ + mz * oz * nz_);
@@ -169,8 +184,8 @@ __global__ __launch_bounds__(512) void k_epass(EArgs<T> A) {
         if (LOSSY) {
           const double bx = 0.5 * (ox + nx_), by = 0.5 * (oy + ny_), bz = 0.5 * (oz + nz_);
           nadd(acc[PE_LOSS], cmp[PE_LOSS],
-               A.ge[0] * (double)S4x * bx * bx + A.ge[1] * (double)S4y * by * by +
-                   A.ge[2] * (double)S4z * bz * bz);
+               gex * (double)S4x * bx * bx + gey * (double)S4y * by * by +
+                   gez * (double)S4z * bz * bz);
         }
         if (idx == A.src_idx) {
           const double bs = A.src_comp == 0 ? 0.5 * (ox + nx_)
@@ -183,9 +198,9 @@ __global__ __launch_bounds__(512) void k_epass(EArgs<T> A) {
         const bool kz_ = k >= A.probe.lo[2] && k + 1 <= A.probe.hi[2];
         double p = 0.0;
         const double nx_ = exn, ny_ = eyn, nz_ = ezn;
-        if (pi_x && pj_xz && kx) p += A.ge[0] * (double)E4x * nx_ * nx_;
-        if (pi_yz && pj_y && kx) p += A.ge[1] * (double)E4y * ny_ * ny_;
-        if (pi_yz && pj_xz && kz_) p += A.ge[2] * (double)E4z * nz_ * nz_;
+        if (pi_x && pj_xz && kx) p += gex * (double)E4x * nx_ * nx_;
+        if (pi_yz && pj_y && kx) p += gey * (double)E4y * ny_ * ny_;
+        if (pi_yz && pj_xz && kz_) p += gez * (double)E4z * nz_ * nz_;
         nadd(acc[PE_PROBE], cmp[PE_PROBE], p);
       }
       hyp = hyc;
@@ -246,7 +261,25 @@ __global__ __launch_bounds__(512) void k_hpass(HArgs<T> A) {
     T exc = ex[idx], eyc = ey[idx];
     T imp = 0;
     if (!MU_UNIFORM && k0 > 0) imp = imu[idx - sxy];
+    // metric (tensor grid: per-cell imu times volume, see HArgs) or constants
+    const bool nu = !MU_UNIFORM && A.sq[0] != nullptr;
+    T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
+    double gfx = A.gf2[0], gfy = A.gf2[1], gfz = A.gf2[2];
+    double rqx = 0.0, rqy = 0.0;
+    if (nu) {
+      rqx = 1.0 / A.sq[0][i];
+      rqy = 1.0 / A.sq[1][j];
+      gfz = 0.5 * rqx * rqy;
+      kdz = (T)(A.kds * gfz);
+    }
     for (int k = k0; k < k1; ++k, idx += sxy) {
+      if (nu) {
+        const double rqz = 1.0 / A.sq[2][k];
+        gfx = 0.5 * rqy * rqz;
+        gfy = 0.5 * rqx * rqz;
+        kdx = (T)(A.kds * gfx);
+        kdy = (T)(A.kds * gfy);
+      }
       const bool kn = k + 1 < d.nz;
       const T exn = kn ? ex[idx + sxy] : T(0);
       const T eyn = kn ? ey[idx + sxy] : T(0);
@@ -268,15 +301,15 @@ __global__ __launch_bounds__(512) void k_hpass(HArgs<T> A) {
       const T hxo = A.hin[0][idx], hyo = A.hin[1][idx], hzo = A.hin[2][idx];
       T hxn, hyn, hzn;
       h_point<T>(exc, eyc, ezc, exn, eyn, ez_jn, ez_in, ey_in, ex_jn, hxo, hyo, hzo, mx, my, mz,
-                 ip, jp, k > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
+                 ip, jp, k > 0, kdx, kdy, kdz, hxn, hyn, hzn);
       A.hout[0][idx] = hxn;
       A.hout[1][idx] = hyn;
       A.hout[2][idx] = hzn;
       if (ENERGY) {
         // M_mu = 1 / (gf2 * (imu_1 + imu_2)); dead facets contribute 0.
-        const double wx = ip ? 1.0 / (A.gf2[0] * (double)mx) : 0.0;
-        const double wy = jp ? 1.0 / (A.gf2[1] * (double)my) : 0.0;
-        const double wz = k > 0 ? 1.0 / (A.gf2[2] * (double)mz) : 0.0;
+        const double wx = ip ? 1.0 / (gfx * (double)mx) : 0.0;
+        const double wy = jp ? 1.0 / (gfy * (double)my) : 0.0;
+        const double wz = k > 0 ? 1.0 / (gfz * (double)mz) : 0.0;
         const double ox = hxo, oy = hyo, oz = hzo, nx_ = hxn, ny_ = hyn, nz_ = hzn;
         nadd(acc[PH_HH_CC], cmp[PH_HH_CC], wx * ox * ox + wy * oy * oy + wz * oz * oz);
         nadd(acc[PH_HH_CN], cmp[PH_HH_CN], wx * ox * nx_ + wy * oy * ny_ + wz * oz * nz_);
@@ -533,7 +566,8 @@ __global__ __launch_bounds__(256) void k_energy(const T* __restrict__ e, const T
                                                 const T* __restrict__ eps,
                                                 const T* __restrict__ imu, T imu_u, Dims d,
                                                 double gex, double gey, double gez, double gfx,
-                                                double gfy, double gfz, double* part) {
+                                                double gfy, double gfz, const double* sq,
+                                                double* part) {
   const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.y * 64 + threadIdx.x;
   double v[2] = {0.0, 0.0};
   if (idx < d.n) {
@@ -549,6 +583,15 @@ __global__ __launch_bounds__(256) void k_energy(const T* __restrict__ e, const T
     };
     const double ex = e[idx], ey = e[idx + d.n], ez = e[idx + 2 * d.n];
     const double hx = h[idx], hy = h[idx + d.n], hz = h[idx + 2 * d.n];
+    if (sq) {   // tensor grid: eps, imu hold cell values times the cell volume
+      const double qx = sq[i], qy = sq[d.nx + j], qz = sq[d.nx + d.ny + k];
+      gex = 0.25 / qx;
+      gey = 0.25 / qy;
+      gez = 0.25 / qz;
+      gfx = 0.5 / (qy * qz);
+      gfy = 0.5 / (qx * qz);
+      gfz = 0.5 / (qx * qy);
+    }
     if (edge_live(0, i, j, k))
       v[0] += gex * (ce(i, j, k) + ce(i, j - 1, k) + ce(i, j, k - 1) + ce(i, j - 1, k - 1)) * ex * ex;
     if (edge_live(1, i, j, k))
@@ -565,19 +608,20 @@ __global__ __launch_bounds__(256) void k_energy(const T* __restrict__ e, const T
 
 template <typename T>
 hipError_t launch_energy(const T* e, const T* h, const T* eps, const T* imu, T imu_u,
-                         const Dims& d, const double ge[3], const double gf2[3], double* part,
-                         int64_t* nblk, hipStream_t s) {
+                         const Dims& d, const double ge[3], const double gf2[3], const double* sq,
+                         double* part, int64_t* nblk, hipStream_t s) {
   const int64_t nb = (d.n + 255) / 256;
   *nblk = nb;
   hipLaunchKernelGGL(k_energy<T>, dim3((unsigned)nb), dim3(64, 4), 0, s, e, h, eps, imu, imu_u, d,
-                     ge[0], ge[1], ge[2], gf2[0], gf2[1], gf2[2], part);
+                     ge[0], ge[1], ge[2], gf2[0], gf2[1], gf2[2], sq, part);
   return hipGetLastError();
 }
 template hipError_t launch_energy<float>(const float*, const float*, const float*, const float*,
-                                         float, const Dims&, const double*, const double*, double*,
-                                         int64_t*, hipStream_t);
+                                         float, const Dims&, const double*, const double*,
+                                         const double*, double*, int64_t*, hipStream_t);
 template hipError_t launch_energy<double>(const double*, const double*, const double*,
                                           const double*, double, const Dims&, const double*,
-                                          const double*, double*, int64_t*, hipStream_t);
+                                          const double*, const double*, double*, int64_t*,
+                                          hipStream_t);
 
 }  // namespace fit

@@ -36,13 +36,19 @@ class FitGrid:
         self.tdtype = _TORCH_DTYPE[dtype]
         self.device = torch.device("cuda", torch.cuda.current_device())
         self._stream = current_stream_handle() if stream is None else int(stream)
-        desc = _lib.GridDesc(self.nx, self.ny, self.nz, *map(float, spacing),
+        # three scalars: uniform spacing; any per-axis array: a tensor grid
+        widths = [np.asarray(s, dtype=np.float64) for s in spacing]
+        tensor = any(w.ndim > 0 for w in widths)
+        uni = (1.0, 1.0, 1.0) if tensor else tuple(float(w) for w in widths)
+        desc = _lib.GridDesc(self.nx, self.ny, self.nz, *uni,
                              float(eps0), float(mu0),
                              _lib.FIT_F64 if dtype == "f64" else _lib.FIT_F32,
                              _lib.FIT_ALLOW_UNSTABLE if allow_unstable else 0)
         h = C.c_void_p()
         call("fit_grid_create", C.byref(desc), C.c_void_p(self._stream), C.byref(h))
         self._h = h
+        if tensor:
+            self.set_spacing(*widths)
 
     # ------------------------------------------------------------------ lifecycle
     @property
@@ -79,6 +85,16 @@ class FitGrid:
             return a
         e, m, s = prep(eps_r), prep(mu_r), prep(sigma)
         call("fit_set_materials", self._h, dptr(e), dptr(m), dptr(s))
+
+    def set_spacing(self, dx=None, dy=None, dz=None):
+        """Per-axis cell widths (arrays of nx, ny, nz values; scalars are
+        broadcast); all None returns to the descriptor's uniform spacing."""
+        if dx is None and dy is None and dz is None:
+            call("fit_set_spacing", self._h, None, None, None)
+            return
+        ws = [np.ascontiguousarray(np.broadcast_to(np.asarray(w, dtype=np.float64), (n,)))
+              for w, n in zip((dx, dy, dz), (self.nx, self.ny, self.nz))]
+        call("fit_set_spacing", self._h, *(dptr(w) for w in ws))
 
     def set_source(self, axis: int, i: int, j: int, k: int, i_max: float, sigma_t: float):
         call("fit_set_source", self._h, axis, i, j, k, float(i_max), float(sigma_t))
