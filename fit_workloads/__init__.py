@@ -20,5 +20,5 @@ Conventions shared by both sides (they name data, they compute nothing):
 from .configs import (  # noqa: F401
     WorkloadSpec, dielectric_blocks, lossy_slab, facet_potential,
     centre_source, random_source, batch_sizes, probe_box, c1, c2, c3, c4, c5,
-    c2_small, c4_small, c5_small, scaled, EPS0_SI, MU0_SI, x1, x1_graded, steps_for,
+    c2_small, c4_small, c5_small, scaled, EPS0_SI, MU0_SI, x1, x1_graded, steps_for, c3_graded,
 )

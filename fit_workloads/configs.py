@@ -36,7 +36,7 @@ __all__ = [
     "WorkloadSpec", "dielectric_blocks", "lossy_slab", "facet_potential",
     "centre_source", "random_source", "batch_sizes", "probe_box",
     "c1", "c2", "c3", "c4", "c5", "c2_small", "c4_small", "c5_small", "scaled",
-    "EPS0_SI", "MU0_SI", "x1", "x1_graded", "steps_for",
+    "EPS0_SI", "MU0_SI", "x1", "x1_graded", "steps_for", "c3_graded",
 ]
 
 EPS0_SI = 8.8541878128e-12      # vacuum permittivity [F/m] (CODATA 2018)
@@ -168,6 +168,15 @@ def c2_small(n: int = 32, nsteps: int = 1000, dtype: str = "f32") -> WorkloadSpe
 def c3() -> WorkloadSpec:
     return _block_grid("c3_256x256x512_f32", 256, 256, 512, "f32", 2000, 64, 3, 8,
                        energy_every=50)
+
+
+def c3_graded() -> WorkloadSpec:
+    """c3 on a tensor grid: per-axis cell widths ~ U[0.5, 1.5] (seed 103)."""
+    spec = c3()
+    rng = np.random.default_rng(103)
+    spec.name = "c3_graded_256x256x512_f32"
+    spec.spacing = tuple(rng.uniform(0.5, 1.5, n) for n in (spec.nx, spec.ny, spec.nz))
+    return spec
 
 
 def c4(count: int = 64, nsteps: int = 4000, lo: int = 32, hi: int = 96,
