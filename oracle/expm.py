@@ -46,12 +46,11 @@ def taylor_error_bound(theta: float, m: int, s: int, unit_roundoff: float = 2.0 
     return math.exp(log_trunc) + math.exp(log_round)
 
 
-def _first_feasible(theta, m, tol, u):
-    """Smallest s with taylor_error_bound(theta, m, s) <= tol, or None.  On
-    s <= theta both parts of the bound fall with s (bisection is exact
-    there); beyond, the samples s* x (3/2)^q, q = 1..6, are tried and the
-    first feasible one is bisected down to the previous sample."""
-    bound = lambda q: taylor_error_bound(theta, m, q, u)
+def _first_feasible_generic(bound, theta, tol):
+    """Smallest s with bound(s) <= tol, or None, for a bound that falls with s
+    on s <= theta: bisection there; beyond, the samples s* x (3/2)^q,
+    q = 1..6 (s* = ceil(theta)), are tried and the first feasible one is
+    bisected down to the previous sample."""
     s_star = max(1, math.ceil(theta))
     lo = None
     if bound(s_star) <= tol:
@@ -73,6 +72,13 @@ def _first_feasible(theta, m, tol, u):
         else:
             lo = mid + 1
     return lo
+
+
+def _first_feasible(theta, m, tol, u):
+    """Smallest s with taylor_error_bound(theta, m, s) <= tol, or None.  On
+    s <= theta both parts of the bound fall with s (bisection is exact
+    there)."""
+    return _first_feasible_generic(lambda q: taylor_error_bound(theta, m, q, u), theta, tol)
 
 
 def taylor_parameters(theta: float, tol: float, unit_roundoff: float = 2.0 ** -53,
