@@ -303,6 +303,32 @@ int fit_op_norm(fit_grid* g, int iters, uint64_t seed, double* rho);
 int fit_expm(fit_grid* g, double t, double tol, double rho, const void* e_in, const void* h_in,
              void* e_out, void* h_out, int* m, int64_t* s);
 
+/* Leja interpolation of exp (Sec. III-A): the interpolant of exp at K
+ * conjugate pairs of points +-i c a_j on the imaginary interval i[-c, c],
+ * a_j^2 a Leja sequence of [0, 1] (x_0 = 1, then greedy on the grid
+ * (1 - cos(pi i / 4000)) / 2), degree 2K - 1.  One step of length h misses
+ * exp(hA) by at most delta = max_{tau in [0, c^2]} prod_j |tau - c^2 a_j^2|
+ * / (2K)! (remainder on the imaginary axis; c = rho h); (K, s) minimise the
+ * applications (2K - 1) s subject to s delta (1 + delta)^(s-1) plus the
+ * rounding estimate s (2K + 1) u S <= tol (S from the coefficients and the
+ * basis bounds).  K <= 30.  FIT_E_INVALID if tol is below what u allows.
+ * Host only. */
+int fit_leja_params(double theta, double tol, double unit_roundoff, int* K, int64_t* s);
+
+/* The evaluation coefficients of the K-pair interpolant on i[-c, c] in the
+ * basis q_0 = 1, q_(k+1) = (z^2 / g2 + a2[k]) q_k (g2 = max(c/2, 1)^2):
+ * p(z) = sum_k (alpha[k] + beta[k] z) q_k.  Arrays of K doubles.  Host only. */
+int fit_leja_coefficients(int K, double c, double* alpha, double* beta, double* a2, double* g2);
+
+/* (e_out, h_out) = exp(t B) (e_in, h_in) by s steps of the K-pair Leja
+ * interpolant with (K, s) from fit_leja_params(|t| rho, tol, u), u the unit
+ * roundoff of the grid's dtype (cached for repeated calls with the same
+ * arguments).  In place allowed.  Lossless grids with uniform mu and
+ * spacing.  K, s may be null.  Allocates a workspace of five field pairs on
+ * first use. */
+int fit_expm_leja(fit_grid* g, double t, double tol, double rho, const void* e_in,
+                  const void* h_in, void* e_out, void* h_out, int* K, int64_t* s);
+
 /* h_out = h_in - c M_mu^{-1} C e (the h-update with step c; c = -dt/2 turns
  * h^(m+1/2) into the collocated h(t_m) = (h^(m-1/2) + h^(m+1/2))/2 given e^m,
  * c = +dt/2 turns it back).  h_out may equal h_in. */

@@ -30,6 +30,7 @@ import numpy as np
 
 from . import leapfrog
 from .expm import expm_action
+from .leja import leja_action
 from .stability import skew_matrix, spectral_norm
 
 __all__ = ["to_u", "from_u", "collocate_h", "paraexp"]
@@ -57,7 +58,8 @@ def paraexp(ops, dt: float, nsteps: int, p: int, source=None, e0=None, h0=None,
     """(e^(N), h^(N+1/2), cost) of Alg. 1 for N = ``nsteps`` (divisible by p).
 
     ``homogeneous``: "expm" (the paper: Taylor action of exp(tA), see
-    ``expm``) or "leapfrog" (the homogeneous problems stepped by source-free
+    ``expm``), "leja" (Leja interpolation, see ``leja``) or "leapfrog" (the
+    homogeneous problems stepped by source-free
     leapfrog on the staggered grid, which by linearity reproduces one
     leapfrog run over (0, T]).  ``cost``: leapfrog steps per sub-interval,
     applications of A per homogeneous solution, and C_proc of eq. tot_cost
@@ -89,25 +91,28 @@ def paraexp(ops, dt: float, nsteps: int, p: int, source=None, e0=None, h0=None,
             e_tot += e
             h_tot += h
         return e_tot, h_tot, cost
-    if homogeneous != "expm":
-        raise ValueError("homogeneous must be 'expm' or 'leapfrog'")
+    if homogeneous not in ("expm", "leja"):
+        raise ValueError("homogeneous must be 'expm', 'leja' or 'leapfrog'")
+    action = expm_action if homogeneous == "expm" else leja_action
+    applications = (lambda ms: ms[0] * ms[1]) if homogeneous == "expm" else \
+        (lambda ms: (2 * ms[0] - 1) * ms[1] if ms[0] > 0 else 0)
     A = skew_matrix(ops)
     rho = spectral_norm(ops) if rho is None else rho
     T = nsteps * dt
     wsum = np.zeros(ops.n_h + ops.n_e)
     u0 = to_u(ops, e0, collocate_h(ops, e0, h0, dt))
     if np.any(u0):
-        w, ms = expm_action(A, u0, T, rho, tol, unit_roundoff=unit_roundoff)
-        cost["A_applications"].append(ms[0] * ms[1])
+        w, ms = action(A, u0, T, rho, tol, unit_roundoff=unit_roundoff)
+        cost["A_applications"].append(applications(ms))
         wsum += w
     for j in range(p - 1):
         e, h = parts[j]
         vj = to_u(ops, e, collocate_h(ops, e, h, dt))              # v_j(T_j)
-        w, ms = expm_action(A, vj, T - (j + 1) * L * dt, rho, tol, unit_roundoff=unit_roundoff)
-        cost["A_applications"].append(ms[0] * ms[1])
+        w, ms = action(A, vj, T - (j + 1) * L * dt, rho, tol, unit_roundoff=unit_roundoff)
+        cost["A_applications"].append(applications(ms))
         wsum += w
-    w_half, ms = expm_action(A, wsum, 0.5 * dt, rho, tol, unit_roundoff=unit_roundoff)
-    cost["A_applications_half_step"] = ms[0] * ms[1]
+    w_half, ms = action(A, wsum, 0.5 * dt, rho, tol, unit_roundoff=unit_roundoff)
+    cost["A_applications_half_step"] = applications(ms)
     ew, _ = from_u(ops, wsum)
     _, hw = from_u(ops, w_half)
     e_p, h_p = parts[-1]

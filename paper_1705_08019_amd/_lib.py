@@ -66,9 +66,12 @@ SIGNATURES = {
     "fit_gram": [_vp, _vp, _i64, _i, _i, _dp],
     "fit_expm_params": [_d, _d, _d, C.POINTER(C.c_int), _i64p],
     "fit_expm_tolerance": [_d, _d, _d, C.POINTER(C.c_double)],
+    "fit_leja_params": [_d, _d, _d, C.POINTER(C.c_int), _i64p],
+    "fit_leja_coefficients": [C.c_int, _d, _dp, _dp, _dp, _dp],
     "fit_op_apply": [_vp, _d, _vp, _vp, _vp, _vp],
     "fit_op_norm": [_vp, _i, C.c_uint64, _dp],
     "fit_expm": [_vp, _d, _d, _d, _vp, _vp, _vp, _vp, C.POINTER(C.c_int), _i64p],
+    "fit_expm_leja": [_vp, _d, _d, _d, _vp, _vp, _vp, _vp, C.POINTER(C.c_int), _i64p],
     "fit_shift_h": [_vp, _d, _vp, _vp, _vp],
     "fit_axpy": [_vp, _d, _vp, _vp, _vp, _vp],
     "fit_batch_create": [C.POINTER(_vp), _i, _vp, C.POINTER(_vp)],

@@ -53,6 +53,7 @@ int ensure_pacc(fit_grid* g, int64_t rows) {
     if (e != hipSuccess) return hip_fail(e, "probe rows flush");
     dev_free(reinterpret_cast<void*&>(g->pacc));
   dev_free(g->xw);
+  dev_free(g->lw);
   }
   g->pacc_rows = 0;
   int rc = dev_alloc(reinterpret_cast<void**>(&g->pacc), (size_t)rows * 2 * sizeof(double),

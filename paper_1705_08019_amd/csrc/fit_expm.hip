@@ -34,9 +34,15 @@ struct OpArgs {
   Tiling t;
   T ce[3];            // c / (g_a / 4): out_e = ce (C~ h) / E4
   T ch[3];            // -c gf2_a (imu + imu): out_h = ch (C e)
+  const T* ye;        // second input (modes 3, 4)
+  const T* yh;
+  T gam, al, be;      // modes 3, 4: out += gam y, acc (+)= al y + be in
 };
 
 // MODE 0: out = c B in.  MODE 1: also acc += out.  MODE 2: also acc = in + out.
+// MODE 3: out = c B in + gam y and acc += al y + be in (one pair step of the
+// Leja recurrence: in = r_k, y = q_k, out = q_(k+1)).  MODE 4: as 3 with
+// acc = al y + be in (the first pair).
 template <typename T, int MODE>
 __global__ __launch_bounds__(512) void k_opb(OpArgs<T> A) {
   const Dims d = A.d;
@@ -102,12 +108,43 @@ __global__ __launch_bounds__(512) void k_opb(OpArgs<T> A) {
     const T ohx = ip ? A.ch[0] * ((ez_jn - ezc) - (eyn - eyc)) : T(0);
     const T ohy = jp ? A.ch[1] * ((exn - exc) - (ez_in - ezc)) : T(0);
     const T ohz = k > 0 ? A.ch[2] * ((ey_in - eyc) - (ex_jn - exc)) : T(0);
-    A.eout[idx] = oex;
-    A.eout[n + idx] = oey;
-    A.eout[2 * n + idx] = oez;
-    A.hout[idx] = ohx;
-    A.hout[n + idx] = ohy;
-    A.hout[2 * n + idx] = ohz;
+    if (MODE == 3 || MODE == 4) {
+      // y and in are zero on dead slots, so out and acc stay zero there
+      const T yex = A.ye[idx], yey = A.ye[n + idx], yez = A.ye[2 * n + idx];
+      const T yhx = A.yh[idx], yhy = A.yh[n + idx], yhz = A.yh[2 * n + idx];
+      A.eout[idx] = oex + A.gam * yex;
+      A.eout[n + idx] = oey + A.gam * yey;
+      A.eout[2 * n + idx] = oez + A.gam * yez;
+      A.hout[idx] = ohx + A.gam * yhx;
+      A.hout[n + idx] = ohy + A.gam * yhy;
+      A.hout[2 * n + idx] = ohz + A.gam * yhz;
+      const T bex = A.al * yex + A.be * exc, bey = A.al * yey + A.be * eyc,
+              bez = A.al * yez + A.be * ezc;
+      const T bhx = A.al * yhx + A.be * hxc, bhy = A.al * yhy + A.be * hyc,
+              bhz = A.al * yhz + A.be * hzc;
+      if (MODE == 3) {
+        A.eacc[idx] += bex;
+        A.eacc[n + idx] += bey;
+        A.eacc[2 * n + idx] += bez;
+        A.hacc[idx] += bhx;
+        A.hacc[n + idx] += bhy;
+        A.hacc[2 * n + idx] += bhz;
+      } else {
+        A.eacc[idx] = bex;
+        A.eacc[n + idx] = bey;
+        A.eacc[2 * n + idx] = bez;
+        A.hacc[idx] = bhx;
+        A.hacc[n + idx] = bhy;
+        A.hacc[2 * n + idx] = bhz;
+      }
+    } else {
+      A.eout[idx] = oex;
+      A.eout[n + idx] = oey;
+      A.eout[2 * n + idx] = oez;
+      A.hout[idx] = ohx;
+      A.hout[n + idx] = ohy;
+      A.hout[2 * n + idx] = ohz;
+    }
     if (MODE == 1) {
       A.eacc[idx] += oex;
       A.eacc[n + idx] += oey;
@@ -240,8 +277,14 @@ __global__ __launch_bounds__(256) void k_seed(T* xe, T* xh, Dims d, uint64_t see
 template <typename T>
 hipError_t launch_opb(const T* ein, const T* hin, T* eout, T* hout, T* eacc, T* hacc, int mode,
                       const T* eps, const Dims& d, const Tiling& t, const double ce[3],
-                      const double ch[3], hipStream_t s) {
+                      const double ch[3], hipStream_t s, const T* ye, const T* yh, double gam,
+                      double al, double be) {
   OpArgs<T> A;
+  A.ye = ye;
+  A.yh = yh;
+  A.gam = (T)gam;
+  A.al = (T)al;
+  A.be = (T)be;
   A.ein = ein;
   A.hin = hin;
   A.eout = eout;
@@ -258,7 +301,9 @@ hipError_t launch_opb(const T* ein, const T* hin, T* eout, T* hout, T* eacc, T* 
   const dim3 blk(64, t.ty), grd((unsigned)t.blocks());
   if (mode == 0) hipLaunchKernelGGL((k_opb<T, 0>), grd, blk, 0, s, A);
   else if (mode == 1) hipLaunchKernelGGL((k_opb<T, 1>), grd, blk, 0, s, A);
-  else hipLaunchKernelGGL((k_opb<T, 2>), grd, blk, 0, s, A);
+  else if (mode == 2) hipLaunchKernelGGL((k_opb<T, 2>), grd, blk, 0, s, A);
+  else if (mode == 3) hipLaunchKernelGGL((k_opb<T, 3>), grd, blk, 0, s, A);
+  else hipLaunchKernelGGL((k_opb<T, 4>), grd, blk, 0, s, A);
   return hipGetLastError();
 }
 
@@ -288,7 +333,7 @@ hipError_t launch_seed(T* xe, T* xh, const Dims& d, uint64_t seed, hipStream_t s
 #define FIT_EXPM_INST(T)                                                                        \
   template hipError_t launch_opb<T>(const T*, const T*, T*, T*, T*, T*, int, const T*,          \
                                     const Dims&, const Tiling&, const double*, const double*,  \
-                                    hipStream_t);                                              \
+                                    hipStream_t, const T*, const T*, double, double, double);  \
   template hipError_t launch_mdot<T>(const T*, const T*, const T*, const T*, const T*,         \
                                      const Dims&, const double*, const double*, double*,       \
                                      int64_t, hipStream_t);                                    \

@@ -69,6 +69,11 @@ struct fit_grid {
   double* pacc = nullptr;       // probe objective: per-workgroup (sum, compensation) rows
   int64_t pacc_rows = 0;
   void* xw = nullptr;            // operator / exponential workspace: 3 (e, h) vectors
+  void* lw = nullptr;            // Leja workspace: 5 (e, h) vectors
+  // last Leja parameter choice (theta, tol, unit roundoff) -> (K, s)
+  double leja_theta = -1.0, leja_tol = -1.0, leja_u = -1.0;
+  int leja_K = 0;
+  int64_t leja_s = 1;
   double* gram_part = nullptr;  // per-workgroup Gram blocks
   double* gram_G = nullptr;     // device K x K result
   int64_t gram_G_cap = 0;

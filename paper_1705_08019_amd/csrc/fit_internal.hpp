@@ -261,11 +261,14 @@ hipError_t launch_pacc_flush(double* pacc, int64_t nrows, double* jacc, hipStrea
 // Semi-discrete operator B (e, h) = (M_eps^{-1} C~ h, -M_mu^{-1} C e) of a
 // lossless grid with uniform mu (fit_expm.hip): out = c B in with per-axis
 // coefficients ce = c / (g_a / 4), ch = -c gf2_a (imu + imu); mode 1 also
-// adds out to acc, mode 2 sets acc = in + out.  in, out, acc distinct.
+// adds out to acc, mode 2 sets acc = in + out; modes 3 and 4 (Leja pair
+// step) set out = c B in + gam y and acc += (3) or = (4) al y + be in.
+// in, out, acc, y distinct.
 template <typename T>
 hipError_t launch_opb(const T* ein, const T* hin, T* eout, T* hout, T* eacc, T* hacc, int mode,
                       const T* eps, const Dims& d, const Tiling& t, const double ce[3],
-                      const double ch[3], hipStream_t s);
+                      const double ch[3], hipStream_t s, const T* ye = nullptr,
+                      const T* yh = nullptr, double gam = 0.0, double al = 0.0, double be = 0.0);
 // Per-workgroup rows (terms 0, 1) of <a, b>_M: sum M_eps a_e b_e and
 // sum M_mu a_h b_h (mm = M_mu per facet direction); nblk rows of part.
 template <typename T>

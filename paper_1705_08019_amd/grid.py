@@ -191,12 +191,16 @@ class FitGrid:
         return v.value
 
     def expm(self, t: float, e: torch.Tensor, h: torch.Tensor, rho: float, tol: float = 1e-12,
-             out=None):
-        """exp(t B) (e, h); returns (e_out, h_out, (m, s))."""
+             out=None, method: str = "taylor"):
+        """exp(t B) (e, h); returns (e_out, h_out, params): params (m, s) of
+        the scaled Taylor recurrence, or (K, s) of the K-pair Leja
+        interpolant (method "leja")."""
+        if method not in ("taylor", "leja"):
+            raise ValueError("method must be 'taylor' or 'leja'")
         eo, ho = (self.new_field(), self.new_field()) if out is None else out
         m, s_ = C.c_int(), C.c_int64()
-        call("fit_expm", self._h, float(t), float(tol), float(rho), *self._dev(e, h, eo, ho),
-             C.byref(m), C.byref(s_))
+        call("fit_expm" if method == "taylor" else "fit_expm_leja", self._h, float(t), float(tol),
+             float(rho), *self._dev(e, h, eo, ho), C.byref(m), C.byref(s_))
         return eo, ho, (m.value, s_.value)
 
     def shift_h(self, c: float, e: torch.Tensor, h_in: torch.Tensor, h_out=None):
@@ -217,6 +221,21 @@ class FitGrid:
         call("fit_expm_params", float(theta), float(tol), float(unit_roundoff), C.byref(m),
              C.byref(s_))
         return m.value, s_.value
+
+    @staticmethod
+    def leja_params(theta: float, tol: float, unit_roundoff: float = 2.0 ** -53):
+        K, s_ = C.c_int(), C.c_int64()
+        call("fit_leja_params", float(theta), float(tol), float(unit_roundoff), C.byref(K),
+             C.byref(s_))
+        return K.value, s_.value
+
+    @staticmethod
+    def leja_coefficients(K: int, c: float):
+        """(alpha, beta, a2, g2) of the scaled K-pair basis on i[-c, c]."""
+        al, be, a2 = (np.empty(K) for _ in range(3))
+        g2 = C.c_double()
+        call("fit_leja_coefficients", int(K), float(c), dptr(al), dptr(be), dptr(a2), C.byref(g2))
+        return al, be, a2, g2.value
 
     @staticmethod
     def expm_tolerance(beta: float, dt: float, rho: float) -> float:

@@ -36,7 +36,7 @@ class ParaExpResult:
     h: torch.Tensor                 # h^(N+1/2)
     rho: float                      # ||A||_2 used for the Taylor parameters
     tol: float                      # tolerance of every exponential
-    expm_params: list               # (m, s) of every exponential, in order
+    expm_params: list               # (m, s) (Taylor) or (K, s) (Leja) of every exponential
     A_applications: int             # applications of B (2 curl products each)
     smvp_leapfrog: int              # curl products of the p particular runs
     C_proc: Optional[int]           # eq. tot_cost with the longest propagation
@@ -46,13 +46,16 @@ def paraexp(nx: int, ny: int, nz: int, eps_r, dt: float, nsteps: int, p: int,
             source: Optional[dict] = None, dtype: str = "f32", tol: float = 1e-8,
             rho: Optional[float] = None, norm_iters: int = 60, norm_margin: float = 1.02,
             spacing=(1.0, 1.0, 1.0), e0=None, h0=None, use_graph: bool = True,
-            batch_tuning=None, beta: Optional[float] = None) -> ParaExpResult:
+            batch_tuning=None, beta: Optional[float] = None,
+            method: str = "taylor") -> ParaExpResult:
     """Alg. 1 for a lossless grid with uniform mu.  ``source``: dict(axis, i, j,
     k, i_max, sigma_t) in time units (or sigma_t_steps).  ``rho``: ||A||_2 or a
     bound; by default the power-iteration estimate times ``norm_margin``
     (the Rayleigh quotients approach the norm from below).  ``e0``, ``h0``:
     initial e^(0), h^(1/2) (default zero).  ``beta``: if given, ``tol`` is
-    replaced by beta dt^2 / rho (eq. tolerance_leja_2)."""
+    replaced by beta dt^2 / rho (eq. tolerance_leja_2).  ``method``: the
+    exponential, "taylor" (scaled truncated Taylor) or "leja" (Leja
+    interpolation)."""
     if nsteps % p:
         raise ValueError("nsteps must be divisible by p")
     L = nsteps // p
@@ -88,26 +91,29 @@ def paraexp(nx: int, ny: int, nz: int, eps_r, dt: float, nsteps: int, p: int,
         started = True
     for j in range(p - 1):
         if started:
-            ye, yh, ms = g0.expm(L * dt, ye, yh, rho, tol)
+            ye, yh, ms = g0.expm(L * dt, ye, yh, rho, tol, method=method)
             params.append(ms)
         ve, vh = grids[j].get_fields()
         g0.axpy(1.0, ve, grids[j].shift_h(-0.5 * dt, ve, vh), ye, yh)   # + v_(j+1)(T_(j+1))
         started = True
     ep, hp = grids[-1].get_fields()
     if started:
-        ye, yh, ms = g0.expm(L * dt, ye, yh, rho, tol)
+        ye, yh, ms = g0.expm(L * dt, ye, yh, rho, tol, method=method)
         params.append(ms)
-        he, hh, ms = g0.expm(0.5 * dt, ye, yh, rho, tol)
+        he, hh, ms = g0.expm(0.5 * dt, ye, yh, rho, tol, method=method)
         params.append(ms)
         g0.axpy(1.0, ye, hh, ep, hp)       # e^(N) += y_e(T), h^(N+1/2) += y_h(T + dt/2)
-    n_a = sum(m * s for m, s in params)
+    apps = (lambda m, s: m * s) if method == "taylor" else \
+        (lambda K, s: (2 * K - 1) * s if K > 0 else 0)
+    n_a = sum(apps(m, s) for m, s in params)
     # eq. tot_cost: the longest propagation of the parallel form is (T - T_1);
     # None when that exponential cannot meet ``tol`` in this dtype (its
     # rounding floor grows with the length of the propagation)
     try:
-        m1, s1 = (FitGrid.expm_params(rho * (nsteps - L) * dt, tol, FitGrid.UNIT_ROUNDOFF[dtype])
+        pick = FitGrid.expm_params if method == "taylor" else FitGrid.leja_params
+        m1, s1 = (pick(rho * (nsteps - L) * dt, tol, FitGrid.UNIT_ROUNDOFF[dtype])
                   if p > 1 else (0, 1))
-        c_proc = 2 * L + m1 * s1 + 2
+        c_proc = 2 * L + apps(m1, s1) + 2
     except FitError:
         c_proc = None
     res = ParaExpResult(e=ep, h=hp, rho=rho, tol=tol, expm_params=params, A_applications=n_a,
