@@ -322,8 +322,8 @@ int fit_leja_coefficients(int K, double c, double* alpha, double* beta, double* 
 
 /* (e_out, h_out) = exp(t B) (e_in, h_in) by s steps of the K-pair Leja
  * interpolant with (K, s) from fit_leja_params(|t| rho, tol, u), u the unit
- * roundoff of the grid's dtype (cached for repeated calls with the same
- * arguments).  In place allowed.  Lossless grids with uniform mu and
+ * roundoff of the grid's dtype (the parameter search is memoised per
+ * process).  In place allowed.  Lossless grids with uniform mu and
  * spacing.  K, s may be null.  Allocates a workspace of five field pairs on
  * first use. */
 int fit_expm_leja(fit_grid* g, double t, double tol, double rho, const void* e_in,

@@ -584,13 +584,17 @@ static int apply_materials(fit_grid* g) {
   g->gram_w_ok[0] = g->gram_w_ok[1] = false;
   const int64_t n = g->d.n;
   const int nx = g->d.nx, ny = g->d.ny;
-  std::vector<double> eps((size_t)n), imu((size_t)n), sig;
   const bool has_mu = !g->in_mu.empty(), has_sig = !g->in_sig.empty();
+  // imu per cell only where it can vary (per-cell mu or a tensor grid)
+  const bool per_cell_mu = has_mu || g->nu;
+  std::vector<double> eps((size_t)n), imu(per_cell_mu ? (size_t)n : 1), sig;
   bool lossy = false;
-  double cfl = INFINITY;
+  double ratio = INFINITY;   // min over cells of eps mu / (dx^-2 + dy^-2 + dz^-2)
   const double inv_u = 1.0 / (g->desc.dx * g->desc.dx) + 1.0 / (g->desc.dy * g->desc.dy) +
                        1.0 / (g->desc.dz * g->desc.dz);
+  const double eps0 = g->desc.eps0, mu0 = g->desc.mu0;
   bool mu_uni = !g->nu;
+  if (!per_cell_mu) imu[0] = 1.0 / mu0;
   if (has_sig) sig.resize((size_t)n);
   for (int64_t c = 0; c < n; ++c) {
     const double er = g->in_eps[c];
@@ -602,15 +606,18 @@ static int apply_materials(fit_grid* g) {
       vol = wx * wy * wz;
       inv = 1.0 / (wx * wx) + 1.0 / (wy * wy) + 1.0 / (wz * wz);
     }
-    eps[c] = g->desc.eps0 * er * vol;
-    imu[c] = vol / (g->desc.mu0 * mr);
-    if (imu[c] != imu[0]) mu_uni = false;
-    cfl = std::min(cfl, std::sqrt(g->desc.eps0 * er * (g->desc.mu0 * mr) / inv));
+    eps[c] = eps0 * er * vol;
+    if (per_cell_mu) {
+      imu[c] = vol / (mu0 * mr);
+      if (imu[c] != imu[0]) mu_uni = false;
+    }
+    ratio = std::min(ratio, eps0 * er * (mu0 * mr) / inv);
     if (has_sig) {
       sig[c] = g->in_sig[c] * vol;
       if (g->in_sig[c] != 0.0) lossy = true;
     }
   }
+  const double cfl = std::sqrt(ratio);   // sqrt is monotone: the min of the roots
   int rc = g->f64 ? upload_cells<double>(g, &g->eps, eps, "eps") : upload_cells<float>(g, &g->eps, eps, "eps");
   if (rc) return rc;
   if (lossy) {
@@ -628,8 +635,6 @@ static int apply_materials(fit_grid* g) {
   if (!g->tile_explicit) default_step_tiling(g->d, g->esz, lossy, &g->sty, &g->skc, &g->stw);
   g->imu_u = imu[0];
   g->cfl = cfl;
-  g->eps_host = eps;
-  g->sig_host = lossy ? sig : std::vector<double>();
   g->materials_version++;
   return FIT_OK;
 }

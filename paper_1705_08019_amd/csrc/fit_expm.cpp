@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <complex>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -206,7 +207,40 @@ static double leja_bound(double theta, int K, int64_t s, double u) {
   return std::exp(log_trunc) + rnd;
 }
 
+static bool leja_search(double theta, double tol, double u, int* K_out, int64_t* s_out);
+
+// Process-wide memo of the parameter search (it takes ~0.1 s per call and
+// ParaExp asks for the same few (theta, tol, u) many times).
 static bool leja_params(double theta, double tol, double u, int* K_out, int64_t* s_out) {
+  struct Entry {
+    double theta, tol, u;
+    int K;
+    int64_t s;
+    bool ok;
+  };
+  static std::mutex mu;
+  static std::vector<Entry> memo;
+  {
+    std::lock_guard<std::mutex> lk(mu);
+    for (const Entry& e : memo)
+      if (e.theta == theta && e.tol == tol && e.u == u) {
+        *K_out = e.K;
+        *s_out = e.s;
+        return e.ok;
+      }
+  }
+  int K = 0;
+  int64_t s = 1;
+  const bool ok = leja_search(theta, tol, u, &K, &s);
+  std::lock_guard<std::mutex> lk(mu);
+  if (memo.size() >= 256) memo.erase(memo.begin());
+  memo.push_back({theta, tol, u, K, s, ok});
+  *K_out = K;
+  *s_out = s;
+  return ok;
+}
+
+static bool leja_search(double theta, double tol, double u, int* K_out, int64_t* s_out) {
   if (theta == 0.0) {
     *K_out = 0;
     *s_out = 1;
@@ -412,18 +446,8 @@ static int expm_leja_t(fit_grid* g, double t, double tol, double rho, const T* e
   int64_t s;
   const double u = std::ldexp(1.0, sizeof(T) == 8 ? -53 : -24);
   const double theta = std::fabs(t) * rho;
-  if (g->leja_theta == theta && g->leja_tol == tol && g->leja_u == u) {
-    K = g->leja_K;
-    s = g->leja_s;
-  } else {
-    if (!leja_params(theta, tol, u, &K, &s))
-      return fail(FIT_E_INVALID, "tolerance below the rounding floor of the field dtype");
-    g->leja_theta = theta;
-    g->leja_tol = tol;
-    g->leja_u = u;
-    g->leja_K = K;
-    g->leja_s = s;
-  }
+  if (!leja_params(theta, tol, u, &K, &s))
+    return fail(FIT_E_INVALID, "tolerance below the rounding floor of the field dtype");
   if (K_out) *K_out = K;
   if (s_out) *s_out = s;
   const size_t bytes = 3 * (size_t)g->d.n * sizeof(T);

@@ -34,7 +34,6 @@ struct fit_grid {
   bool mu_uniform = true;
   double imu_u = 1.0;
   double cfl = 0.0;
-  std::vector<double> eps_host, sig_host;   // FP64 copies (adjoint chain rule, checks)
   // the caller's per-cell inputs (re-applied when the cell widths change)
   std::vector<double> in_eps, in_mu, in_sig;
   // tensor grid with per-axis cell widths (fit_set_spacing)
@@ -70,10 +69,6 @@ struct fit_grid {
   int64_t pacc_rows = 0;
   void* xw = nullptr;            // operator / exponential workspace: 3 (e, h) vectors
   void* lw = nullptr;            // Leja workspace: 5 (e, h) vectors
-  // last Leja parameter choice (theta, tol, unit roundoff) -> (K, s)
-  double leja_theta = -1.0, leja_tol = -1.0, leja_u = -1.0;
-  int leja_K = 0;
-  int64_t leja_s = 1;
   double* gram_part = nullptr;  // per-workgroup Gram blocks
   double* gram_G = nullptr;     // device K x K result
   int64_t gram_G_cap = 0;
