@@ -323,23 +323,31 @@ def form_adjoint():
 
 def form_graded(steps: int = 300, warmup: int = 20):
     """The bandwidth workload on a tensor grid (per-axis widths ~U[0.5, 1.5]):
-    split kernels with per-column / per-plane metric, against the same grid
-    with uniform spacing on the same split path.  Algorithmic bytes: e-pass
-    44 B/cell (e, h, eps V, sigma V read, e written), h-pass 40 B/cell (e, h,
-    imu V read, h written; the uniform split h-pass reads no imu: 36 B)."""
+    the fused step with per-column / per-plane metric (autotuned tile; 80 B
+    algorithmic per cell-update) against the same grid with uniform spacing,
+    and both on the split kernels.  Split algorithmic bytes: e-pass 44 B/cell
+    (e, h, eps V, sigma V read, e written), h-pass 40 B/cell (e, h, imu V read,
+    h written; the uniform split h-pass reads no imu: 36 B)."""
     import torch
     from fit_workloads import c3_graded
     from paper_1705_08019_amd import FitGrid
     spec = c3_graded()
     out = {"workload": "256x256x512 FP32 c3 materials, per-axis cell widths ~U[0.5, 1.5] "
-                       f"(seed 103), {steps} steps, split path"}
-    for name, spacing in (("graded", spec.spacing), ("uniform_split", (1.0, 1.0, 1.0))):
+                       f"(seed 103), {steps} steps; fused (autotuned) and split paths"}
+    for name, spacing, path in (("graded_fused", spec.spacing, "fused"),
+                                ("uniform_fused", (1.0, 1.0, 1.0), "fused"),
+                                ("graded", spec.spacing, "split"),
+                                ("uniform_split", (1.0, 1.0, 1.0), "split")):
         g = FitGrid(spec.nx, spec.ny, spec.nz, "f32", spacing=spacing)
         g.set_materials(spec.eps_r, None, spec.sigma)
-        g.set_tuning("split")
         dt = 0.9 * g.cfl_dt()
         s = spec.source
         g.set_source(s["axis"], s["i"], s["j"], s["k"], s["i_max"], s["sigma_t_steps"] * dt)
+        if path == "fused":
+            p_, ty_, kc_, _, tw_ = g.autotune(dt, reps=5)
+            assert p_ == "fused"
+        else:
+            g.set_tuning("split")
         g.step(warmup, dt)
         torch.cuda.synchronize()
         g.profile_begin(4 * steps)
@@ -348,6 +356,14 @@ def form_graded(steps: int = 300, warmup: int = 20):
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
         prof = g.profile_end()
+        if path == "fused":
+            st = prof["step"][0] / max(prof["step"][1], 1)
+            out[name] = {"Gcell_updates_per_s": round(spec.cells * steps / wall / 1e9, 2),
+                         "step_ms": round(st, 4), "tile": [tw_, ty_, kc_],
+                         "alg_GBs": round(80 * spec.cells / (st * 1e-3) / 1e9, 1),
+                         "frac": round(80 * spec.cells / (st * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+            g.close()
+            continue
         ep = prof["epass"][0] / max(prof["epass"][1], 1)
         hp = prof["hpass"][0] / max(prof["hpass"][1], 1)
         hb = 40 if name == "graded" else 36

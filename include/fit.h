@@ -112,9 +112,9 @@ int fit_set_materials(fit_grid* g, const double* eps_r, const double* mu_r,
  * eps0 sum_c eps_r[c] (d_b[c] d_c[c] / 4) / d_a[i] over its <= 4 cells, an
  * a-facet M_mu^{-1} = sum_c (d_a[c] / 2) / (mu0 mu_r[c]) / (d_b d_c) over its
  * 2 cells, and dt_CFL takes each cell's own widths.  On such a grid the
- * step uses the split kernels (the device arrays hold cell values times the
- * cell volume); the fused path, batches, the adjoint and the exponential
- * entry points reject it with FIT_E_INVALID.
+ * device arrays hold cell values times the cell volume; the step runs fused
+ * when mu_r is uniform and on the split kernels otherwise; batches, the
+ * adjoint and the exponential entry points reject it with FIT_E_INVALID.
  * Errors: FIT_E_INVALID (a width <= 0 or non-finite, some but not all NULL),
  * FIT_E_OOM. */
 int fit_set_spacing(fit_grid* g, const double* dx, const double* dy, const double* dz);

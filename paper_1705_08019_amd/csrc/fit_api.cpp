@@ -138,9 +138,12 @@ void default_step_tiling(const Dims& d, size_t esz, bool lossy, int* ty, int* kc
 // Tile widths of the fused step: 32, 64, 128 or 256 lanes.
 static bool valid_tw(int tw) { return tw == 32 || tw == 64 || tw == 128 || tw == 256; }
 
+// The fused kernel takes a uniform mu (in value; on a tensor grid too).
+static bool fused_ok(const fit_grid* g) { return g->mu_uniform || (g->nu && g->mu_value_uniform); }
+
 bool use_fused(const fit_grid* g) {
   if (g->path == 1) return false;
-  return g->mu_uniform;   // the fused kernel takes a uniform mu
+  return fused_ok(g);
 }
 
 // Host-side mirror of the probe membership of a direction-a edge (used only
@@ -317,7 +320,21 @@ int step_fused_io(fit_grid* g, double dt, const T* e0, const T* h0, T* e1, T* h1
   a.d = d;
   a.t = make_tiling(d, g->sty, g->skc, g->stw);
   a.hs = (T)(0.5 * dt);
-  a.imu2 = (T)g->imu_u + (T)g->imu_u;
+  a.imu2 = (T)g->imu_value + (T)g->imu_value;
+  if (g->nu) {
+    const int nn[3] = {d.nx, d.ny, d.nz};
+    const int64_t tot = (int64_t)nn[0] + nn[1] + nn[2];
+    int64_t off = 0;
+    for (int c = 0; c < 3; ++c) {
+      a.nsq[c] = g->sq + off;
+      a.nw[c] = g->sq + tot + off;
+      a.ndl[c] = g->sq + 2 * tot + off;
+      a.nrw[c] = g->sq + 3 * tot + off;
+      off += nn[c];
+    }
+    a.kbs = 4.0 * dt;
+    a.kds = dt;
+  }
   a.src_comp = g->src_axis;
   a.src_idx = g->src_axis >= 0 ? g->src_idx : -1;
   const double val = g->src_axis >= 0 ? source_value(g, dt, m) : 0.0;
@@ -594,6 +611,7 @@ static int apply_materials(fit_grid* g) {
                        1.0 / (g->desc.dz * g->desc.dz);
   const double eps0 = g->desc.eps0, mu0 = g->desc.mu0;
   bool mu_uni = !g->nu;
+  bool mu_val_uni = true;
   if (!per_cell_mu) imu[0] = 1.0 / mu0;
   if (has_sig) sig.resize((size_t)n);
   for (int64_t c = 0; c < n; ++c) {
@@ -610,6 +628,7 @@ static int apply_materials(fit_grid* g) {
     if (per_cell_mu) {
       imu[c] = vol / (mu0 * mr);
       if (imu[c] != imu[0]) mu_uni = false;
+      if (has_mu && mr != g->in_mu[0]) mu_val_uni = false;
     }
     ratio = std::min(ratio, eps0 * er * (mu0 * mr) / inv);
     if (has_sig) {
@@ -634,6 +653,8 @@ static int apply_materials(fit_grid* g) {
   g->mu_uniform = mu_uni;
   if (!g->tile_explicit) default_step_tiling(g->d, g->esz, lossy, &g->sty, &g->skc, &g->stw);
   g->imu_u = imu[0];
+  g->mu_value_uniform = mu_val_uni;
+  g->imu_value = 1.0 / (mu0 * (has_mu ? g->in_mu[0] : 1.0));
   g->cfl = cfl;
   g->materials_version++;
   return FIT_OK;
@@ -675,14 +696,22 @@ int fit_set_spacing(fit_grid* g, const double* dx, const double* dy, const doubl
         return fail(FIT_E_INVALID, "cell widths must be > 0 and finite");
   if (!g->sq) {
     int rc = dev_alloc(reinterpret_cast<void**>(&g->sq),
-                       (size_t)(nn[0] + nn[1] + nn[2]) * sizeof(double), "cell widths");
+                       4 * (size_t)(nn[0] + nn[1] + nn[2]) * sizeof(double), "cell widths");
     if (rc) return rc;
   }
-  std::vector<double> q;
+  std::vector<double> q, wv, dl, rw;
   for (int a = 0; a < 3; ++a) {
     g->wd[a].assign(w[a], w[a] + nn[a]);
-    for (int i = 0; i < nn[a]; ++i) q.push_back(w[a][i] * w[a][i]);
+    for (int i = 0; i < nn[a]; ++i) {
+      q.push_back(w[a][i] * w[a][i]);
+      wv.push_back(w[a][i]);
+      dl.push_back(0.5 * ((i > 0 ? w[a][i - 1] : 0.0) + w[a][i]));
+      rw.push_back(1.0 / w[a][i]);
+    }
   }
+  q.insert(q.end(), wv.begin(), wv.end());
+  q.insert(q.end(), dl.begin(), dl.end());
+  q.insert(q.end(), rw.begin(), rw.end());
   hipError_t e = hipMemcpyAsync(g->sq, q.data(), q.size() * sizeof(double),
                                 hipMemcpyHostToDevice, g->s);
   if (e == hipSuccess) e = hipStreamSynchronize(g->s);
@@ -1015,9 +1044,8 @@ int fit_gram(fit_grid* g, const void* X, int64_t ld, int K, int which, double* G
 int fit_set_tuning(fit_grid* g, int path, int tw, int ty, int kc) {
   if (!g) return fail(FIT_E_INVALID, "null handle");
   if (path < 0 || path > 2) return fail(FIT_E_INVALID, "path must be 0 (auto), 1 (split), 2 (fused)");
-  if (path == 2 && g->nu) return fail(FIT_E_INVALID, "the fused step needs a uniform spacing");
-  if (path == 2 && !g->mu_uniform) return fail(FIT_E_INVALID, "the fused step needs a uniform mu");
-  const bool fused = path == 2 || (path == 0 && g->mu_uniform);
+  if (path == 2 && !fused_ok(g)) return fail(FIT_E_INVALID, "the fused step needs a uniform mu");
+  const bool fused = path == 2 || (path == 0 && fused_ok(g));
   const bool expl = tw != 0 || ty != 0 || kc != 0;
   if (expl && tw == 0) tw = 64;
   if (expl) {
@@ -1025,7 +1053,7 @@ int fit_set_tuning(fit_grid* g, int path, int tw, int ty, int kc) {
       if (!valid_tw(tw)) return fail(FIT_E_INVALID, "tw must be 32, 64, 128 or 256 for the fused step");
       if (ty < 2 || ty > 16 || (ty & (ty - 1)) != 0 || tw * ty > 1024)
         return fail(FIT_E_INVALID, "ty must be a power of two in [2, 16] with tw * ty <= 1024");
-      if (step_lds_bytes(ty, g->esz, g->lossy, tw) > 160 * 1024)
+      if (step_lds_bytes(ty, g->esz, g->lossy, tw, g->nu ? g->d.nz + 1 : 0) > 160 * 1024)
         return fail(FIT_E_INVALID, "tile needs more LDS than a CU has");
     } else {
       if (tw != 64) return fail(FIT_E_INVALID, "the split kernels use tw = 64");
@@ -1066,14 +1094,14 @@ int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* tw, int* ty, 
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
       cus = v;
   }
-  if (g->mu_uniform) {
+  if (fused_ok(g)) {
     const int widths[4] = {32, 64, 128, 256};
     const int heights[4] = {2, 4, 8, 16};
     for (int w : widths) {
       if (w > 2 * g->d.nx && w > 32) continue;        // mostly empty lanes
       for (int t : heights) {
         if (w * t > 1024 || w * t < 128) continue;
-        if (step_lds_bytes(t, g->esz, g->lossy, w) > 160 * 1024) continue;
+        if (step_lds_bytes(t, g->esz, g->lossy, w, g->nu ? g->d.nz + 1 : 0) > 160 * 1024) continue;
         const int per_cu = step_blocks_per_cu(t, g->esz, g->lossy, w);
         if (per_cu <= 0) continue;
         const int64_t tiles = (int64_t)((g->d.nx + w - 1) / w) * ((g->d.ny + t - 1) / t);

@@ -39,7 +39,12 @@ struct fit_grid {
   // tensor grid with per-axis cell widths (fit_set_spacing)
   bool nu = false;
   std::vector<double> wd[3];
-  double* sq = nullptr;          // device: squared widths [x (nx) | y (ny) | z (nz)]
+  // device, 4 (nx + ny + nz) doubles: squared widths [x | y | z], then the
+  // widths, the dual half-sums (d[i-1] + d[i]) / 2 (d[0] / 2 at i = 0) and the
+  // reciprocal widths
+  double* sq = nullptr;
+  bool mu_value_uniform = true;  // all mu_r equal (also on a tensor grid)
+  double imu_value = 1.0;        // 1 / (mu0 mu_r) of the first cell
   int64_t materials_version = 0;
   double gedge[3] = {1, 1, 1};   // d_b d_c / d_a
   double gf2[3] = {0.5, 0.5, 0.5};

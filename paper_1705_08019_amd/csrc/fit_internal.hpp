@@ -129,11 +129,24 @@ struct SArgs {
   double* part;      // [blocks][kPartTerms] (energy steps) or null
   double* pacc;      // probe objective: per-workgroup (sum, compensation) rows
   double pscale;     // dt: weight of this step's probe term
+  // Tensor grid (per-axis cell widths; null otherwise).  eps and sig hold the
+  // cell values times the cell volume; mu is uniform in value (imu2).
+  // nsq: squared widths, nw: widths, ndl: dual half-sums (d[i-1] + d[i]) / 2
+  // per axis.  An a-edge with index i along a: kb = kbs nsq[a][i], M_eps =
+  // S4eps / (4 nsq[a][i]).  An x-facet at (i, j, k): M_mu^{-1} = (imu + imu)
+  // ndl[0][i] / (2 nw[1][j] nw[2][k]), kd = kds times the factor of imu2
+  // (cyclic for y, z facets).
+  const double* nsq[3] = {nullptr, nullptr, nullptr};
+  const double* nw[3] = {nullptr, nullptr, nullptr};
+  const double* ndl[3] = {nullptr, nullptr, nullptr};
+  const double* nrw[3] = {nullptr, nullptr, nullptr};   // 1 / widths
+  double kbs = 0.0, kds = 0.0;
 };
 
 // Dynamic LDS bytes of the fused kernel for a tw x ty tile, and the number
 // of its workgroups a CU holds at once (0 if the runtime cannot tell).
-size_t step_lds_bytes(int ty, size_t esz, bool lossy, int tw = 64);
+// nu_planes: planes of per-plane metric staged on a tensor grid (0 otherwise).
+size_t step_lds_bytes(int ty, size_t esz, bool lossy, int tw = 64, int nu_planes = 0);
 int step_blocks_per_cu(int ty, size_t esz, bool lossy, int tw = 64);
 
 template <typename T>

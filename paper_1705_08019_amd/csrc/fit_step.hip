@@ -17,13 +17,13 @@
 
 namespace fit {
 
-size_t step_lds_bytes(int ty, size_t esz, bool lossy, int tw) {
+size_t step_lds_bytes(int ty, size_t esz, bool lossy, int tw, int nu_planes) {
   const size_t RP = (size_t)(tw + 2) * (size_t)(ty + 2);   // ring plane: x in [-1, tw], y in [-1, ty]
   const size_t EP = (size_t)(tw + 1) * (size_t)(ty + 1);   // ext plane: x in [0, tw], y in [0, ty]
-  return esz * (3 * 3 * RP + 3 * RP + (lossy ? 3 * RP : 0) + 2 * 3 * EP);
+  return esz * (3 * 3 * RP + 3 * RP + (lossy ? 3 * RP : 0) + 2 * 3 * EP + 3 * (size_t)nu_planes);
 }
 
-template <typename T, bool LOSSY, bool ENERGY, bool PROBE>
+template <typename T, bool LOSSY, bool ENERGY, bool PROBE, bool NU>
 __global__ __launch_bounds__(1024) void k_step(SArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t lt = xcd_remap(blockIdx.x, gridDim.x);
@@ -31,9 +31,10 @@ __global__ __launch_bounds__(1024) void k_step(SArgs<T> A) {
   const int64_t rr = lt / A.t.ntx;
   const int tyi = (int)(rr % A.t.nty);
   const int kz = (int)(rr / A.t.nty);
-  step_tile<T, LOSSY, ENERGY, PROBE>(A, tx, tyi, kz, reinterpret_cast<T*>(smem_raw),
-                                     ENERGY ? A.part + (int64_t)blockIdx.x * kPartTerms : nullptr,
-                                     PROBE ? A.pacc + 2 * (int64_t)blockIdx.x : nullptr);
+  step_tile<T, LOSSY, ENERGY, PROBE, NU>(A, tx, tyi, kz, reinterpret_cast<T*>(smem_raw),
+                                         ENERGY ? A.part + (int64_t)blockIdx.x * kPartTerms
+                                                : nullptr,
+                                         PROBE ? A.pacc + 2 * (int64_t)blockIdx.x : nullptr);
 }
 
 template <typename T, bool LOSSY>
@@ -41,10 +42,10 @@ static int occupancy_of(int ty, int tw) {
   int nb = 0;
   const size_t lds = step_lds_bytes(ty, sizeof(T), LOSSY, tw);
   if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step<T, LOSSY, false, false>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step<T, LOSSY, false, false, false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void*>(&k_step<T, LOSSY, false, false>), tw * ty, lds) !=
+          &nb, reinterpret_cast<const void*>(&k_step<T, LOSSY, false, false, false>), tw * ty, lds) !=
       hipSuccess) {
     (void)hipGetLastError();
     return 0;
@@ -61,24 +62,32 @@ int step_blocks_per_cu(int ty, size_t esz, bool lossy, int tw) {
 template <typename T>
 hipError_t launch_step(const SArgs<T>& a, bool lossy, bool energy, bool probe, hipStream_t s) {
   const dim3 blk(a.t.tw, a.t.ty), grd((unsigned)a.t.blocks());
-  const size_t lds = step_lds_bytes(a.t.ty, sizeof(T), lossy, a.t.tw);
-#define FIT_S(L, E, P)                                                                    \
+  const bool nu = a.nsq[0] != nullptr;
+  const size_t lds = step_lds_bytes(a.t.ty, sizeof(T), lossy, a.t.tw, nu ? a.t.kc + 1 : 0);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+#define FIT_S(L, E, P, N)                                                                 \
   do {                                                                                   \
     if (lds > 64 * 1024) {                                                               \
-      hipError_t ea = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step<T, L, E, P>), \
-                                          hipFuncAttributeMaxDynamicSharedMemorySize,    \
-                                          (int)lds);                                     \
+      hipError_t ea = hipFuncSetAttribute(                                               \
+          reinterpret_cast<const void*>(&k_step<T, L, E, P, N>),                         \
+          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);                         \
       if (ea != hipSuccess) return ea;                                                   \
     }                                                                                    \
-    hipLaunchKernelGGL((k_step<T, L, E, P>), grd, blk, lds, s, a);                        \
+    hipLaunchKernelGGL((k_step<T, L, E, P, N>), grd, blk, lds, s, a);                     \
+  } while (0)
+#define FIT_SN(L, E, P)              \
+  do {                               \
+    if (nu) FIT_S(L, E, P, true);    \
+    else FIT_S(L, E, P, false);      \
   } while (0)
   if (lossy) {
-    if (energy) { if (probe) FIT_S(true, true, true); else FIT_S(true, true, false); }
-    else { if (probe) FIT_S(true, false, true); else FIT_S(true, false, false); }
+    if (energy) { if (probe) FIT_SN(true, true, true); else FIT_SN(true, true, false); }
+    else { if (probe) FIT_SN(true, false, true); else FIT_SN(true, false, false); }
   } else {
-    if (energy) { if (probe) FIT_S(false, true, true); else FIT_S(false, true, false); }
-    else { if (probe) FIT_S(false, false, true); else FIT_S(false, false, false); }
+    if (energy) { if (probe) FIT_SN(false, true, true); else FIT_SN(false, true, false); }
+    else { if (probe) FIT_SN(false, false, true); else FIT_SN(false, false, false); }
   }
+#undef FIT_SN
 #undef FIT_S
   return hipGetLastError();
 }

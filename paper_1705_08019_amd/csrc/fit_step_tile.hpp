@@ -39,7 +39,7 @@ constexpr int kRingPerThread = 3;
 // linearly; thread t < tw ty owns column (t mod tw, t div tw) of the tile, the
 // rest only help to stage planes (row-packed tiles of the batched kernel,
 // whose tile width is a grid's whole x extent, leave such threads over).
-template <typename T, bool LOSSY, bool ENERGY, bool PROBE>
+template <typename T, bool LOSSY, bool ENERGY, bool PROBE, bool NU = false>
 __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, int kz, T* sm,
                                           double* part, double* prow) {
   const Dims d = A.d;
@@ -51,6 +51,7 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
   T* cL = hL + 9 * RP;                 // [3][RP]     eps0 eps_r
   T* sL = cL + 3 * RP;                 // [3][RP]     sigma (lossy only)
   T* nL = sL + (LOSSY ? 3 * RP : 0);   // [2][3][EP]  e^(m+1), planes k, k-1
+  T* zL = nL + 2 * 3 * EP;             // tensor grid: [3][kc + 1] per-plane factors
 
   const int i0 = tx * TW, j0 = tyi * TY;
   const int k0 = kz * A.t.kc;
@@ -73,6 +74,40 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
 
   auto ring = [&](int x, int y) { return (y + 1) * RW + (x + 1); };
   auto ext = [&](int x, int y) { return y * EW + x; };
+
+  // metric: uniform constants, or (tensor grid) the own and halo point's
+  // x / y factors, fixed over the z-march (indices clamped into the grid;
+  // out-of-grid points are discarded anyway)
+  // (the per-plane z factors below are products with precomputed per-axis
+  // arrays: no division in the march)
+  T kbox = A.kb[0], kboy = A.kb[1], kbhx = A.kb[0], kbhy = A.kb[1];
+  double gex = A.ge[0], gey = A.ge[1];
+  double hfx = 0.0, hfy = 0.0, hfz = 0.0;
+  T kdxb = 0, kdyb = 0, kdzb = 0;
+  if (NU) {
+    const int ci = min(i, d.nx - 1), cj = min(j, d.ny - 1);
+    const int chi = min(hi, d.nx - 1), chj = min(hj, d.ny - 1);
+    kbox = (T)(A.kbs * A.nsq[0][ci]);
+    kboy = (T)(A.kbs * A.nsq[1][cj]);
+    kbhx = (T)(A.kbs * A.nsq[0][chi]);
+    kbhy = (T)(A.kbs * A.nsq[1][chj]);
+    gex = 0.25 / A.nsq[0][ci];
+    gey = 0.25 / A.nsq[1][cj];
+    hfx = 0.5 * A.ndl[0][ci] * A.nrw[1][cj];
+    hfy = 0.5 * A.ndl[1][cj] * A.nrw[0][ci];
+    hfz = 0.5 * A.nrw[0][ci] * A.nrw[1][cj];
+    kdxb = (T)(A.kds * hfx);
+    kdyb = (T)(A.kds * hfy);
+    kdzb = (T)(A.kds * hfz);
+    // per-plane z factors of planes k0 .. k1 (read after the first barrier)
+    const int zp = A.t.kc + 1;
+    for (int q = tid; q <= k1 - k0 && k0 + q < d.nz; q += nthr) {
+      const int kk = k0 + q;
+      zL[q] = (T)(A.kbs * A.nsq[2][kk]);
+      zL[zp + q] = (T)A.nrw[2][kk];
+      zL[2 * zp + q] = (T)A.ndl[2][kk];
+    }
+  }
 
   // ---- register staging of one plane: ring entries q = tid + r * nthr
   T pre[kRingPerThread][5];
@@ -118,7 +153,8 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
 
   // e^(m+1) at ext point (x, y) of plane k; p = ring buffer of plane k, q of k-1.
   auto enew = [&](int x, int y, int k, int p, int q, T exo, T eyo, T ezo, bool valid, T& exn,
-                  T& eyn, T& ezn, T& E4x, T& E4y, T& E4z, T& S4x, T& S4y, T& S4z) {
+                  T& eyn, T& ezn, T& E4x, T& E4y, T& E4z, T& S4x, T& S4y, T& S4z, T kbx_,
+                  T kby_, T kbz_) {
     const int r = ring(x, y), rim = ring(x - 1, y), rjm = ring(x, y - 1), rijm = ring(x - 1, y - 1);
     const T* hp = hL + p * 3 * RP;
     const T* hq = hL + q * 3 * RP;
@@ -158,8 +194,8 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
     e_point<T, LOSSY>(hp[r], hp[RP + r], hp[2 * RP + r], hq[r], hq[RP + r], hp[rjm],
                       hp[RP + rim], hp[2 * RP + rjm], hp[2 * RP + rim], E4x, E4y, E4z, S4x, S4y,
                       S4z, exo, eyo, ezo, jx, jy, jz, valid && gj > 0 && k > 0,
-                      valid && gi > 0 && k > 0, valid && gi > 0 && gj > 0, A.kb[0], A.kb[1],
-                      A.kb[2], A.hs, exn, eyn, ezn);
+                      valid && gi > 0 && k > 0, valid && gi > 0 && gj > 0, kbx_, kby_, kbz_,
+                      A.hs, exn, eyn, ezn);
   };
 
   double acc[kPartTerms] = {0};
@@ -191,10 +227,16 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
     __syncthreads();
     T* np_ = nL + ep * 3 * EP;
     const int64_t g = i + sx * j + sxy * (int64_t)k;
+    T kbz = A.kb[2];
+    double gez = A.ge[2];
+    if (NU && plane) {
+      kbz = zL[k - k0];
+      if (ENERGY || PROBE) gez = 0.25 / A.nsq[2][k];
+    }
     if (act) {
       T exn = 0, eyn = 0, ezn = 0, E4x, E4y, E4z, S4x, S4y, S4z;
       if (plane) enew(lx, ly, k, bc, bp, eo0, eo1, eo2, own, exn, eyn, ezn, E4x, E4y, E4z, S4x,
-                      S4y, S4z);
+                      S4y, S4z, kbox, kboy, kbz);
       const int e = ext(lx, ly);
       np_[e] = exn;
       np_[EP + e] = eyn;
@@ -204,8 +246,7 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
         gst(A.e1[1], g, eyn);
         gst(A.e1[2], g, ezn);
         if (ENERGY) {
-          const double mx = A.ge[0] * (double)E4x, my = A.ge[1] * (double)E4y,
-                       mz = A.ge[2] * (double)E4z;
+          const double mx = gex * (double)E4x, my = gey * (double)E4y, mz = gez * (double)E4z;
           const double ox = eo0, oy = eo1, oz = eo2, nx_ = exn, ny_ = eyn, nz_ = ezn;
           nadd_s(acc[PE_EE_MM], cmp[PE_EE_MM], mx * ox * ox + my * oy * oy + mz * oz * oz);
           nadd_s(acc[PE_EE_MM1], cmp[PE_EE_MM1], mx * ox * nx_ + my * oy * ny_ + mz * oz * nz_);
@@ -214,8 +255,8 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
           if (LOSSY) {
             const double bx = 0.5 * (ox + nx_), by = 0.5 * (oy + ny_), bz = 0.5 * (oz + nz_);
             nadd_s(acc[PE_LOSS], cmp[PE_LOSS],
-                   A.ge[0] * (double)S4x * bx * bx + A.ge[1] * (double)S4y * by * by +
-                       A.ge[2] * (double)S4z * bz * bz);
+                   gex * (double)S4x * bx * bx + gey * (double)S4y * by * by +
+                       gez * (double)S4z * bz * bz);
           }
           if (g == A.src_idx) {
             const double bs = A.src_comp == 0 ? 0.5 * (ox + nx_)
@@ -228,9 +269,9 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
           const bool kz_ = k >= A.probe.lo[2] && k + 1 <= A.probe.hi[2];
           const double nx_ = exn, ny_ = eyn, nz_ = ezn;
           double pv = 0.0;
-          if (pi_x && pj_xz && kx) pv += A.ge[0] * (double)E4x * nx_ * nx_;
-          if (pi_yz && pj_y && kx) pv += A.ge[1] * (double)E4y * ny_ * ny_;
-          if (pi_yz && pj_xz && kz_) pv += A.ge[2] * (double)E4z * nz_ * nz_;
+          if (pi_x && pj_xz && kx) pv += gex * (double)E4x * nx_ * nx_;
+          if (pi_yz && pj_y && kx) pv += gey * (double)E4y * ny_ * ny_;
+          if (pi_yz && pj_xz && kz_) pv += gez * (double)E4z * nz_ * nz_;
           nadd_s(acc[PE_PROBE], cmp[PE_PROBE], pv);
         }
       }
@@ -238,7 +279,7 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
     if (has_h) {
       T exn = 0, eyn = 0, ezn = 0, E4x, E4y, E4z, S4x, S4y, S4z;
       if (plane) enew(hx_, hy_, k, bc, bp, ho0, ho1, ho2, hvalid, exn, eyn, ezn, E4x, E4y, E4z,
-                      S4x, S4y, S4z);
+                      S4x, S4y, S4z, kbhx, kbhy, kbz);
       const int e = ext(hx_, hy_);
       np_[e] = exn;
       np_[EP + e] = eyn;
@@ -253,18 +294,32 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
       const int r = ring(lx, ly);
       const T* hq = hL + bp * 3 * RP;
       const T hxo = hq[r], hyo = hq[RP + r], hzo = hq[2 * RP + r];
+      T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
+      double gfx = A.gf2[0], gfy = A.gf2[1], gfz = A.gf2[2];
+      if (NU) {
+        const int zp = A.t.kc + 1;
+        const T rz = zL[zp + km - k0];
+        kdx = kdxb * rz;
+        kdy = kdyb * rz;
+        kdz = kdzb * zL[2 * zp + km - k0];
+        if (ENERGY) {
+          gfx = hfx * A.nrw[2][km];
+          gfy = hfy * A.nrw[2][km];
+          gfz = hfz * A.ndl[2][km];
+        }
+      }
       T hxn, hyn, hzn;
       h_point<T>(nq[e], nq[EP + e], nq[2 * EP + e], np_[e], np_[EP + e], nq[2 * EP + e_jn],
                  nq[2 * EP + e_in], nq[EP + e_in], nq[e_jn], hxo, hyo, hzo, A.imu2, A.imu2,
-                 A.imu2, i > 0, j > 0, km > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
+                 A.imu2, i > 0, j > 0, km > 0, kdx, kdy, kdz, hxn, hyn, hzn);
       const int64_t gm = i + sx * j + sxy * (int64_t)km;
       gst(A.h1[0], gm, hxn);
       gst(A.h1[1], gm, hyn);
       gst(A.h1[2], gm, hzn);
       if (ENERGY) {
-        const double wx = i > 0 ? 1.0 / (A.gf2[0] * (double)A.imu2) : 0.0;
-        const double wy = j > 0 ? 1.0 / (A.gf2[1] * (double)A.imu2) : 0.0;
-        const double wz = km > 0 ? 1.0 / (A.gf2[2] * (double)A.imu2) : 0.0;
+        const double wx = i > 0 ? 1.0 / (gfx * (double)A.imu2) : 0.0;
+        const double wy = j > 0 ? 1.0 / (gfy * (double)A.imu2) : 0.0;
+        const double wz = km > 0 ? 1.0 / (gfz * (double)A.imu2) : 0.0;
         const double ox = hxo, oy = hyo, oz = hzo, nx_ = hxn, ny_ = hyn, nz_ = hzn;
         nadd_s(acc[PS_HH_CC], cmp[PS_HH_CC], wx * ox * ox + wy * oy * oy + wz * oz * oz);
         nadd_s(acc[PS_HH_CN], cmp[PS_HH_CN], wx * ox * nx_ + wy * oy * ny_ + wz * oz * nz_);

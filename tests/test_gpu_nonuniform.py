@@ -25,19 +25,24 @@ def _widths(rng, n, lo=0.3, hi=1.7):
     return [rng.uniform(lo, hi, k) for k in n]
 
 
-@pytest.mark.parametrize("dtype,n,lossy", [("f64", (70, 33, 21), True), ("f64", (13, 9, 7), False),
-                                           ("f32", (70, 33, 21), True), ("f32", (129, 5, 4), False)])
-def test_graded_grid_matches_oracle(dtype, n, lossy):
+@pytest.mark.parametrize("dtype,n,lossy,mu_cell,path", [
+    ("f64", (70, 33, 21), True, True, "split"), ("f64", (70, 33, 21), True, False, "fused"),
+    ("f64", (13, 9, 7), False, False, "split"), ("f64", (13, 9, 7), False, False, "fused"),
+    ("f32", (70, 33, 21), True, True, "split"), ("f32", (70, 33, 21), True, False, "fused"),
+    ("f32", (129, 5, 4), False, False, "fused")])
+def test_graded_grid_matches_oracle(dtype, n, lossy, mu_cell, path):
     from paper_1705_08019_amd import FitGrid
     nx, ny, nz = n
     rng = np.random.default_rng(nx + ny + nz)
     wd = _widths(rng, n)
     eps = dielectric_blocks(nx, ny, nz, 6, 5)
-    mu = rng.uniform(1.0, 2.0, (nz, ny, nx))
+    mu = rng.uniform(1.0, 2.0, (nz, ny, nx)) if mu_cell else np.full((nz, ny, nx), 1.7)
     sig = lossy_slab(nx, ny, nz, 2, 0.2) if lossy else None
     ops = oracle_ops(n, eps=eps, sigma=sig, mu=mu, spacing=wd)
     g = FitGrid(nx, ny, nz, dtype, spacing=wd)
     g.set_materials(eps, mu, sig)
+    g.set_tuning(path)
+    assert g.get_tuning()[0] == path
     dt_cfl = cfl_dt(eps, mu, wd)
     assert abs(g.cfl_dt() - dt_cfl) <= 1e-14 * dt_cfl
     dt = 0.95 * dt_cfl
@@ -50,7 +55,7 @@ def test_graded_grid_matches_oracle(dtype, n, lossy):
     g.set_probe([b[0] for b in box], [b[1] for b in box])
     steps = 60
     g.trace_config(5, steps)
-    print(f"graded {dtype} {n} lossy={lossy}", flush=True)
+    print(f"graded {dtype} {n} lossy={lossy} mu_cell={mu_cell} {path}", flush=True)
     g.step(steps, dt)
     e, h = g.get_fields()
     tr, _ = g.trace_read()
@@ -117,8 +122,9 @@ def test_equal_widths_match_the_uniform_grid_and_reset():
     assert rel_l2(out[1], out[0]) <= 1e-13
 
 
-@pytest.mark.parametrize("k,path_dtype", [(4.0, "f64"), (20.0, "f64"), (20.0, "f32")])
-def test_k_ratio_cylindrical_wave_matches_oracle(k, path_dtype):
+@pytest.mark.parametrize("k,path_dtype,path", [(4.0, "f64", "fused"), (20.0, "f64", "split"),
+                                               (20.0, "f64", "fused"), (20.0, "f32", "fused")])
+def test_k_ratio_cylindrical_wave_matches_oracle(k, path_dtype, path):
     """The cylindrical wave on the mesh with one element k times smaller
     (Sec. IV-A): the CFL step shrinks, n_t grows; parity over the whole
     T = 2e-7 s and the energy plateau on the GPU's own trace."""
@@ -130,6 +136,7 @@ def test_k_ratio_cylindrical_wave_matches_oracle(k, path_dtype):
     g = FitGrid(spec.nx, spec.ny, spec.nz, path_dtype, spacing=spec.spacing, eps0=spec.eps0,
                 mu0=spec.mu0)
     g.set_materials(spec.eps_r)
+    g.set_tuning(path)
     assert abs(g.cfl_dt() - dt_cfl) <= 1e-14 * dt_cfl
     s = spec.source
     g.set_source(s["axis"], s["i"], s["j"], s["k"], s["i_max"], s["sigma_t"])
@@ -152,8 +159,10 @@ def test_k_ratio_cylindrical_wave_matches_oracle(k, path_dtype):
 def test_graded_grid_rejections():
     from paper_1705_08019_amd import FitGrid, FitError, FitBatch
     g = FitGrid(8, 8, 8, "f32", spacing=(np.linspace(0.5, 1.5, 8), 1.0, 1.0))
+    g.set_tuning("fused")                     # uniform mu: the fused step takes tensor grids
+    g.set_materials(np.ones(512), np.linspace(1.0, 2.0, 512))
     with pytest.raises(FitError, match="INVALID"):
-        g.set_tuning("fused")
+        g.set_tuning("fused")                 # per-cell mu: split kernels only
     e, h = g.new_field(), g.new_field()
     with pytest.raises(FitError, match="INVALID"):
         g.op_apply(e, h)
@@ -167,3 +176,38 @@ def test_graded_grid_rejections():
     with pytest.raises(FitError, match="INVALID"):
         call("fit_set_spacing", g.handle, w.ctypes.data_as(C.POINTER(C.c_double)), None, None)
     g.close()
+
+
+def test_graded_fused_matches_split_across_tiles():
+    """On a tensor grid with uniform mu the fused step (every tile width) and
+    the split kernels agree to FP64 rounding, trace rows included."""
+    from paper_1705_08019_amd import FitGrid
+    n = (45, 26, 19)
+    nx, ny, nz = n
+    rng = np.random.default_rng(12)
+    wd = _widths(rng, n)
+    eps = dielectric_blocks(nx, ny, nz, 6, 8)
+    sig = lossy_slab(nx, ny, nz, 2, 0.1)
+    e0 = rng.standard_normal((3, nz, ny, nx))
+    out = {}
+    for cfg in (("split", 0, 0, None), ("fused", 4, 8, 32), ("fused", 8, 16, 64),
+                ("fused", 4, 5, 128), ("fused", 2, 19, 256)):
+        g = FitGrid(nx, ny, nz, "f64", spacing=wd)
+        g.set_materials(eps, None, sig)
+        g.set_tuning(*cfg)
+        g.set_fields(e0, None, 0)
+        g.set_source(2, nx // 2, ny // 2, nz // 2, 1.0, 5.0 * g.cfl_dt())
+        g.trace_config(3, 40)
+        g.step(30, 0.9 * g.cfl_dt())
+        e, h = g.get_fields()
+        tr, _ = g.trace_read()
+        out[cfg] = (to_np(e), to_np(h), tr)
+        g.close()
+    ref = out[("split", 0, 0, None)]
+    for cfg, (e, h, tr) in out.items():
+        assert rel_l2(e, ref[0]) <= 1e-13, cfg
+        assert rel_l2(h, ref[1]) <= 1e-13, cfg
+        scale = np.nanmax(np.abs(ref[2][:, 1:]))
+        np.testing.assert_allclose(tr[:, 1:], ref[2][:, 1:], rtol=0, atol=1e-12 * scale,
+                                   err_msg=str(cfg))
+
