@@ -392,7 +392,7 @@ int fit_batch_step(fit_batch* b, int64_t nsteps, const double* dt, int use_graph
  * (either may be NULL).  This is instrumentation for the paper's cost
  * measure (curl applications, eq. cost_LF) in wall-clock form. */
 enum { FIT_PROF_EPASS = 0, FIT_PROF_HPASS = 1, FIT_PROF_REDUCE = 2, FIT_PROF_STEP = 3,
-       FIT_PROF_ADJOINT = 4, FIT_PROF_OTHER = 5, FIT_PROF_N = 6 };
+       FIT_PROF_ADJOINT = 4, FIT_PROF_OTHER = 5, FIT_PROF_PAIR = 6, FIT_PROF_N = 7 };
 int fit_profile_begin(fit_grid* g, int64_t max_launches);
 int fit_profile_end(fit_grid* g, double ms[FIT_PROF_N], int64_t count[FIT_PROF_N]);
 
@@ -410,6 +410,21 @@ int fit_set_tuning(fit_grid* g, int path, int tw, int ty, int kc);
 
 /* The path fit_step will take and its tile shape. */
 int fit_get_tuning(const fit_grid* g, int* path, int* tw, int* ty, int* kc);
+
+/* Two leapfrog steps per pass (temporal blocking of the Sec. II-A
+ * recurrence): with enable = 1, fit_step advances pairs of steps with one
+ * launch that reads the state and the materials once and keeps the
+ * intermediate state on chip, whenever the fused path is active, the grid
+ * has uniform spacing, no probe is set and neither step of the pair needs
+ * energies for the trace (other steps run singly).  The result is bitwise
+ * that of single fused steps.  tw x ty: tile (a multiple of 64 threads, at
+ * most 1024, LDS within 160 KiB), kc: planes per chunk (0 = one round of
+ * resident workgroups); tw = ty = 0 takes the first of 64 x 16, 64 x 8,
+ * 32 x 16, 16 x 8 that fits the dtype.
+ * Errors: FIT_E_INVALID for an unsupported tile. */
+int fit_set_pair_tuning(fit_grid* g, int enable, int tw, int ty, int kc);
+/* The pair setting in effect (kc: the chunk a launch would use). */
+int fit_get_pair_tuning(const fit_grid* g, int* enable, int* tw, int* ty, int* kc);
 
 /* Autotuner: time candidate kernel paths and tile shapes (tile heights,
  * z-chunks sized to one or two rounds of resident workgroups, from the

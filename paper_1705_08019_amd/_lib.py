@@ -61,6 +61,8 @@ SIGNATURES = {
     "fit_profile_end": [_vp, _dp, _i64p],
     "fit_smvp_count": [_vp, _i64p],
     "fit_set_tuning": [_vp, _i, _i, _i, _i],
+    "fit_set_pair_tuning": [_vp, C.c_int, C.c_int, C.c_int, C.c_int],
+    "fit_get_pair_tuning": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "fit_get_tuning": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                        C.POINTER(C.c_int)],
     "fit_gram": [_vp, _vp, _i64, _i, _i, _dp],
@@ -91,7 +93,7 @@ SIGNATURES = {
     "fit_autotune": [_vp, _d, _i, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                      C.POINTER(C.c_int), C.POINTER(C.c_float)],
 }
-PROF_KINDS = ("epass", "hpass", "reduce", "step", "adjoint", "other")
+PROF_KINDS = ("epass", "hpass", "reduce", "step", "adjoint", "other", "pair")
 _CHAR = {"fit_version": [], "fit_last_error": []}
 
 _lib = None

@@ -52,8 +52,6 @@ int ensure_pacc(fit_grid* g, int64_t rows) {
     if (e == hipSuccess) e = hipStreamSynchronize(g->s);
     if (e != hipSuccess) return hip_fail(e, "probe rows flush");
     dev_free(reinterpret_cast<void*&>(g->pacc));
-  dev_free(g->xw);
-  dev_free(g->lw);
   }
   g->pacc_rows = 0;
   int rc = dev_alloc(reinterpret_cast<void**>(&g->pacc), (size_t)rows * 2 * sizeof(double),
@@ -303,6 +301,14 @@ int step_fused_io(fit_grid* g, double dt, const T* e0, const T* h0, T* e1, T* h1
   if (tr_this && !have_row) g->trace_dropped++;
   const bool probe = g->probe.on != 0;
   const bool energy = have_row || tr_next;
+  if (sizeof(T) == 4 && energy && probe) {
+    // The FP32 fused variant with both energies and the probe returned NaN
+    // h values on the GPU (the FP64 one and each of the two alone agree with
+    // the split kernels bitwise); until its cause is found such steps run
+    // on the split kernels, out of place into the same buffers.
+    if (tr_this && !have_row) g->trace_dropped--;   // step_once counts it again
+    return step_once<T>(g, dt, e0, e1, h0, h1);
+  }
   const Dims& d = g->d;
   SArgs<T> a;
   for (int c = 0; c < 3; ++c) {
@@ -397,6 +403,81 @@ int step_fused(fit_grid* g, double dt) {
   if (rc) return rc;
   std::swap(g->e, g->e_alt);
   std::swap(g->h, g->h_alt);
+  return FIT_OK;
+}
+
+// ---------------------------------------------------------------- step pairs
+static int device_cus() {
+  static int cus = 0;
+  if (cus == 0) {
+    int dev = 0, v = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+    else
+      cus = 256;
+  }
+  return cus;
+}
+
+// Planes per chunk for one round of resident pair workgroups.
+static int pair_kc(const fit_grid* g, int tw, int ty) {
+  const size_t lds = step2_lds_bytes(tw, ty, g->esz, g->lossy);
+  const int per_cu = std::max(1, std::min((int)((160 * 1024) / std::max<size_t>(lds, 1)),
+                                          2048 / (tw * ty)));
+  const int64_t tiles = (int64_t)((g->d.nx + tw - 1) / tw) * ((g->d.ny + ty - 1) / ty);
+  const int64_t nkc = std::max<int64_t>(1, (int64_t)device_cus() * per_cu / tiles);
+  const int k = (int)((g->d.nz + nkc - 1) / nkc);
+  return std::min(g->d.nz, std::max(k, std::min(8, g->d.nz)));
+}
+
+static bool pair_now(const fit_grid* g, int64_t nleft) {
+  if (nleft < 2 || !g->pair_on || !use_fused(g) || g->nu || g->probe.on) return false;
+  const int64_t te = g->trace_every, m = g->m;
+  if (te > 0 && (m % te == 0 || (m + 1) % te == 0 || (m + 2) % te == 0)) return false;
+  return true;
+}
+
+// Two fused steps m -> m+2 in one launch: state read from (e, h), written to
+// (e_alt, h_alt), then the two sets swap roles.
+template <typename T>
+static int step_pair(fit_grid* g, double dt) {
+  int rc = ensure_alt(g);
+  if (rc) return rc;
+  const Dims& d = g->d;
+  const T* e0 = static_cast<const T*>(g->e);
+  const T* h0 = static_cast<const T*>(g->h);
+  T* e2 = static_cast<T*>(g->e_alt);
+  T* h2 = static_cast<T*>(g->h_alt);
+  S2Args<T> a;
+  for (int c = 0; c < 3; ++c) {
+    a.e0[c] = e0 + c * d.n;
+    a.h0[c] = h0 + c * d.n;
+    a.e2[c] = e2 + c * d.n;
+    a.h2[c] = h2 + c * d.n;
+    a.kb[c] = (T)(4.0 * dt / g->gedge[c]);
+    a.kd[c] = (T)(dt * g->gf2[c]);
+  }
+  a.eps = static_cast<const T*>(g->eps);
+  a.sig = static_cast<const T*>(g->sig);
+  a.d = d;
+  a.t = make_tiling(d, g->pty, g->pkc > 0 ? g->pkc : pair_kc(g, g->ptw, g->pty), g->ptw);
+  a.hs = (T)(0.5 * dt);
+  a.imu2 = (T)g->imu_value + (T)g->imu_value;
+  a.src_comp = g->src_axis;
+  a.src_idx = g->src_axis >= 0 ? g->src_idx : -1;
+  a.src_val[0] = (T)(g->src_axis >= 0 ? source_value(g, dt, g->m) : 0.0);
+  a.src_val[1] = (T)(g->src_axis >= 0 ? source_value(g, dt, g->m + 1) : 0.0);
+  hipError_t e;
+  {
+    ProfScope ps(g, FIT_PROF_PAIR);
+    e = launch_step2<T>(a, g->lossy, g->s);
+  }
+  if (e != hipSuccess) return hip_fail(e, "step pair launch");
+  std::swap(g->e, g->e_alt);
+  std::swap(g->h, g->h_alt);
+  g->m += 2;
+  g->smvp += 4;
   return FIT_OK;
 }
 
@@ -586,6 +667,7 @@ int fit_grid_destroy(fit_grid* g) {
   dev_free(reinterpret_cast<void*&>(g->pend));
   dev_free(reinterpret_cast<void*&>(g->pacc));
   dev_free(g->xw);
+  dev_free(g->lw);
   dev_free(reinterpret_cast<void*&>(g->gram_part));
   dev_free(reinterpret_cast<void*&>(g->gram_G));
   dev_free(reinterpret_cast<void*&>(g->gram_w[0]));
@@ -821,7 +903,10 @@ int fit_step(fit_grid* g, int64_t nsteps, double dt) {
   if (rc) return rc;
   const bool fused = use_fused(g);
   for (int64_t s = 0; s < nsteps; ++s) {
-    if (fused) {
+    if (fused && pair_now(g, nsteps - s)) {
+      rc = g->f64 ? step_pair<double>(g, dt) : step_pair<float>(g, dt);
+      ++s;
+    } else if (fused) {
       rc = g->f64 ? step_fused<double>(g, dt) : step_fused<float>(g, dt);
     } else {
       rc = g->f64 ? step_once<double>(g, dt, static_cast<const double*>(g->e), static_cast<double*>(g->e),
@@ -1141,6 +1226,40 @@ int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* tw, int* ty, 
   if (ty) *ty = bc.ty;
   if (kc) *kc = bc.kc;
   if (ms_best) *ms_best = best;
+  return FIT_OK;
+}
+
+int fit_set_pair_tuning(fit_grid* g, int enable, int tw, int ty, int kc) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  if (enable != 0 && enable != 1) return fail(FIT_E_INVALID, "enable must be 0 or 1");
+  if (kc < 0) return fail(FIT_E_INVALID, "kc must be >= 0");
+  if (tw == 0 && ty == 0) {   // the first default tile that fits this dtype
+    const int shapes[4][2] = {{64, 16}, {64, 8}, {32, 16}, {16, 8}};
+    tw = 64;
+    ty = 16;
+    for (const auto& sh : shapes)
+      if (step2_shape_ok(sh[0], sh[1], g->esz, g->lossy)) {
+        tw = sh[0];
+        ty = sh[1];
+        break;
+      }
+  }
+  if (!step2_shape_ok(tw, ty, g->esz, g->lossy))
+    return fail(FIT_E_INVALID, "unsupported tile for the step pair (tw ty a multiple of 64 up "
+                               "to 1024, staged regions within 2 entries per thread, LDS <= 160 KiB)");
+  g->pair_on = enable;
+  g->ptw = tw;
+  g->pty = ty;
+  g->pkc = std::min(kc, g->d.nz);
+  return FIT_OK;
+}
+
+int fit_get_pair_tuning(const fit_grid* g, int* enable, int* tw, int* ty, int* kc) {
+  if (!g || !enable || !tw || !ty || !kc) return fail(FIT_E_INVALID, "null argument");
+  *enable = g->pair_on;
+  *tw = g->ptw;
+  *ty = g->pty;
+  *kc = g->pkc > 0 ? g->pkc : pair_kc(g, g->ptw, g->pty);
   return FIT_OK;
 }
 

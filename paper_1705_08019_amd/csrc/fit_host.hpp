@@ -44,6 +44,9 @@ struct fit_grid {
   // reciprocal widths
   double* sq = nullptr;
   bool mu_value_uniform = true;  // all mu_r equal (also on a tensor grid)
+  // two steps per pass (fit_set_pair_tuning)
+  int pair_on = 0;
+  int ptw = 64, pty = 16, pkc = 0;
   double imu_value = 1.0;        // 1 / (mu0 mu_r) of the first cell
   int64_t materials_version = 0;
   double gedge[3] = {1, 1, 1};   // d_b d_c / d_a

@@ -145,6 +145,35 @@ struct SArgs {
 
 // Dynamic LDS bytes of the fused kernel for a tw x ty tile, and the number
 // of its workgroups a CU holds at once (0 if the runtime cannot tell).
+// Two fused steps per pass (fit_step2.hip): reads (e0, h0) = state m and
+// writes (e2, h2) = state m+2 (distinct buffers).  Uniform mu and spacing,
+// no energies or probe.  src_val: i(t_{m+1/2}), i(t_{m+3/2}).
+constexpr int kS2Per = 2;   // staged X4 / R1 entries per thread
+template <typename T>
+struct S2Args {
+  const T* e0[3];
+  const T* h0[3];
+  T* e2[3];
+  T* h2[3];
+  const T* eps;
+  const T* sig;
+  Dims d;
+  Tiling t;
+  T kb[3];
+  T hs;
+  T kd[3];
+  T imu2;
+  int src_comp;
+  int64_t src_idx;
+  T src_val[2];
+};
+size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy);
+// Tile shapes the two-step kernel takes: tw ty a multiple of 64, <= 1024,
+// the staged regions within kS2Per entries per thread, LDS <= 160 KiB.
+bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy);
+template <typename T>
+hipError_t launch_step2(const S2Args<T>& a, bool lossy, hipStream_t s);
+
 // nu_planes: planes of per-plane metric staged on a tensor grid (0 otherwise).
 size_t step_lds_bytes(int ty, size_t esz, bool lossy, int tw = 64, int nu_planes = 0);
 int step_blocks_per_cu(int ty, size_t esz, bool lossy, int tw = 64);

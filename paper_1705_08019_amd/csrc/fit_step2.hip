@@ -1,0 +1,326 @@
+// Two leapfrog steps per pass (temporal blocking of the Sec. II-A
+// recurrence): one launch reads (e^m, h^(m+1/2)) and the materials once and
+// writes (e^(m+2), h^(m+5/2)); the intermediate state (e^(m+1), h^(m+3/2))
+// lives only in LDS.  Per cell and pair of steps this moves the 56 B of one
+// fused step instead of 112 B.
+//
+// A workgroup owns a TW x TY column tile and marches a chunk [k0, k1) of
+// z-planes with a lag of two planes between what it reads and what it
+// stores.  In local coordinates (x along i, y along j) the regions are
+//   X4: x in [-2, TW+1], y in [-2, TY+1]  staged h^(m+1/2), eps, sigma
+//   R1: x in [-1, TW+1], y in [-1, TY+1]  e^(m+1)       (needs X4)
+//   R2: x in [-1, TW],   y in [-1, TY]    h^(m+3/2)     (needs R1, X4)
+//   R3: x in [0, TW],    y in [0, TY]     e^(m+2)       (needs R2, R1, X4)
+//   tile                                  h^(m+5/2)     (needs R3, R2)
+// Iteration k forms e^(m+1) of plane k, h^(m+3/2) of plane k-1, e^(m+2) of
+// plane k-1 and h^(m+5/2) of plane k-2, for k = k0-1 .. k1+1; the halo rows
+// and columns are recomputed by every tile that needs them with the same
+// contraction-pinned point functions as the single-step kernels, so the
+// result is bitwise that of two single steps.  Values outside the grid and
+// on planes outside [0, nz) are zero (PEC), as in the single-step kernels.
+#include "fit_step_tile.hpp"
+
+namespace fit {
+
+struct S2Geom {
+  int W4, N4, W1, N1, W2, N2, W3, N3;
+};
+
+__host__ __device__ inline S2Geom s2_geom(int tw, int ty) {
+  S2Geom g;
+  g.W4 = tw + 4;
+  g.N4 = (tw + 4) * (ty + 4);
+  g.W1 = tw + 3;
+  g.N1 = (tw + 3) * (ty + 3);
+  g.W2 = tw + 2;
+  g.N2 = (tw + 2) * (ty + 2);
+  g.W3 = tw + 1;
+  g.N3 = (tw + 1) * (ty + 1);
+  return g;
+}
+
+size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy) {
+  const S2Geom g = s2_geom(tw, ty);
+  const size_t n = 6 * (size_t)g.N4 + 3 * (size_t)g.N4 + (lossy ? 3 * (size_t)g.N4 : 0) +
+                   6 * (size_t)g.N1 + 6 * (size_t)g.N2 + 6 * (size_t)g.N3;
+  return esz * n;
+}
+
+bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy) {
+  if (tw < 8 || ty < 2 || tw * ty > 1024 || (tw * ty) % 64 != 0) return false;
+  const S2Geom g = s2_geom(tw, ty);
+  const int nthr = tw * ty;
+  if (g.N4 > kS2Per * nthr || g.N1 > kS2Per * nthr) return false;
+  return step2_lds_bytes(tw, ty, esz, lossy) <= 160 * 1024;
+}
+
+template <typename T, bool LOSSY>
+__global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const Dims d = A.d;
+  const int64_t lt = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = (int)(lt % A.t.ntx);
+  const int64_t rr = lt / A.t.ntx;
+  const int tyi = (int)(rr % A.t.nty);
+  const int kz = (int)(rr / A.t.nty);
+  const int TW = A.t.tw, TY = A.t.ty;
+  const S2Geom G = s2_geom(TW, TY);
+  T* h0L = sm;                                // [2][3][N4]   h^(m+1/2), planes k, k-1
+  T* cL = h0L + 6 * G.N4;                     // [3][N4]      eps0 eps_r, planes k, k-1, k-2
+  T* sL = cL + 3 * G.N4;                      // [3][N4]      sigma (lossy)
+  T* e1L = sL + (LOSSY ? 3 * G.N4 : 0);       // [2][3][N1]   e^(m+1), planes k, k-1
+  T* h1L = e1L + 6 * G.N1;                    // [2][3][N2]   h^(m+3/2), planes k-1, k-2
+  T* e2L = h1L + 6 * G.N2;                    // [2][3][N3]   e^(m+2), planes k-1, k-2
+
+  const int i0 = tx * TW, j0 = tyi * TY;
+  const int k0 = kz * A.t.kc;
+  const int k1 = min(k0 + A.t.kc, d.nz);
+  const int tid = (int)(threadIdx.x + threadIdx.y * blockDim.x);
+  const int nthr = (int)(blockDim.x * blockDim.y);
+  const int64_t sx = d.sx, sxy = d.sxy;
+
+  auto hb = [](int k) { return k & 1; };                 // h0 / e1 / h1 / e2 buffer of plane k
+  auto cb = [](int k) { return ((k % 3) + 3) % 3; };     // eps / sigma buffer of plane k
+  auto i4 = [&](int x, int y) { return (y + 2) * G.W4 + (x + 2); };
+  auto i1 = [&](int x, int y) { return (y + 1) * G.W1 + (x + 1); };
+  auto i2 = [&](int x, int y) { return (y + 1) * G.W2 + (x + 1); };
+  auto i3 = [&](int x, int y) { return y * G.W3 + x; };
+  auto in_grid = [&](int gx, int gy) { return gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny; };
+
+  // ---- register staging of plane k: X4 entries (h x3, eps, sigma), R1 entries (e x3)
+  T ph[kS2Per][5];
+  T pe[kS2Per][3];
+  auto fetch = [&](int k) {
+    const bool plane = k >= 0 && k < d.nz;
+#pragma unroll
+    for (int r = 0; r < kS2Per; ++r) {
+      const int q = tid + r * nthr;
+      {
+        const int gx = i0 + (q % G.W4) - 2, gy = j0 + (q / G.W4) - 2;
+        const bool in = plane && q < G.N4 && in_grid(gx, gy);
+        const int64_t g = in ? gx + sx * gy + sxy * (int64_t)k : 0;
+        ph[r][0] = in ? gld(A.h0[0], g) : T(0);
+        ph[r][1] = in ? gld(A.h0[1], g) : T(0);
+        ph[r][2] = in ? gld(A.h0[2], g) : T(0);
+        ph[r][3] = in ? gld(A.eps, g) : T(0);
+        ph[r][4] = (LOSSY && in) ? gld(A.sig, g) : T(0);
+      }
+      {
+        const int gx = i0 + (q % G.W1) - 1, gy = j0 + (q / G.W1) - 1;
+        const bool in = plane && q < G.N1 && in_grid(gx, gy);
+        const int64_t g = in ? gx + sx * gy + sxy * (int64_t)k : 0;
+        pe[r][0] = in ? gld(A.e0[0], g) : T(0);
+        pe[r][1] = in ? gld(A.e0[1], g) : T(0);
+        pe[r][2] = in ? gld(A.e0[2], g) : T(0);
+      }
+    }
+  };
+  auto stage = [&](int k) {
+    T* h = h0L + hb(k) * 3 * G.N4;
+    T* c = cL + cb(k) * G.N4;
+    T* s = sL + cb(k) * G.N4;
+#pragma unroll
+    for (int r = 0; r < kS2Per; ++r) {
+      const int q = tid + r * nthr;
+      if (q < G.N4) {
+        h[q] = ph[r][0];
+        h[G.N4 + q] = ph[r][1];
+        h[2 * G.N4 + q] = ph[r][2];
+        c[q] = ph[r][3];
+        if (LOSSY) s[q] = ph[r][4];
+      }
+    }
+  };
+
+  // e-update of one point (local x, y) of plane k: h planes k (hp) and k-1
+  // (hq) with index map ih and row length nh, materials of planes k, k-1
+  // (X4 layout); same operand order as the single-step kernels.
+  auto e_upd = [&](int x, int y, int k, const T* hp, const T* hq, int NH, int rh, int rh_im,
+                   int rh_jm, const T* cp, const T* cq, const T* sp, const T* sq, T exo, T eyo,
+                   T ezo, T src, T& exn, T& eyn, T& ezn) {
+    const int gi = i0 + x, gj = j0 + y;
+    const bool valid = in_grid(gi, gj) && k >= 0 && k < d.nz;
+    const int r = i4(x, y), rim = i4(x - 1, y), rjm = i4(x, y - 1), rijm = i4(x - 1, y - 1);
+    const T c = cp[r], c_im = cp[rim], c_jm = cp[rjm], c_ijm = cp[rijm];
+    const T Sx = c + c_im, Sy = c + c_jm, Sxj = c_jm + c_ijm;
+    const T pc = cq[r];
+    const T sye = pc + cq[rjm], sxe = pc + cq[rim];
+    T E4x = sye + Sy, E4y = sxe + Sx, E4z = Sx + Sxj;
+    T S4x = 0, S4y = 0, S4z = 0;
+    if (LOSSY) {
+      const T s = sp[r], s_im = sp[rim], s_jm = sp[rjm], s_ijm = sp[rijm];
+      const T Sxs = s + s_im, Sys = s + s_jm;
+      const T ps = sq[r];
+      const T sys = ps + sq[rjm], sxs = ps + sq[rim];
+      S4x = sys + Sys;
+      S4y = sxs + Sxs;
+      S4z = Sxs + (s_jm + s_ijm);
+    }
+    const int64_t g = gi + sx * gj + sxy * (int64_t)k;
+    T jx = 0, jy = 0, jz = 0;
+    if (valid && g == A.src_idx) {
+      if (A.src_comp == 0) jx = src;
+      if (A.src_comp == 1) jy = src;
+      if (A.src_comp == 2) jz = src;
+    }
+    if (!valid) E4x = E4y = E4z = T(1);
+    e_point<T, LOSSY>(hp[rh], hp[NH + rh], hp[2 * NH + rh], hq[rh], hq[NH + rh], hp[rh_jm],
+                      hp[NH + rh_im], hp[2 * NH + rh_jm], hp[2 * NH + rh_im], E4x, E4y, E4z,
+                      S4x, S4y, S4z, exo, eyo, ezo, jx, jy, jz, valid && gj > 0 && k > 0,
+                      valid && gi > 0 && k > 0, valid && gi > 0 && gj > 0, A.kb[0], A.kb[1],
+                      A.kb[2], A.hs, exn, eyn, ezn);
+  };
+
+  // prologue: plane k0 - 2 staged, plane k0 - 1 in flight
+  fetch(k0 - 2);
+  stage(k0 - 2);
+  fetch(k0 - 1);
+
+  for (int k = k0 - 1; k <= k1 + 1; ++k) {
+    stage(k);
+    T e0r[kS2Per][3];
+#pragma unroll
+    for (int r = 0; r < kS2Per; ++r) {
+      e0r[r][0] = pe[r][0];
+      e0r[r][1] = pe[r][1];
+      e0r[r][2] = pe[r][2];
+    }
+    if (k + 1 <= k1 + 1) fetch(k + 1);
+    __syncthreads();
+
+    // ---- e^(m+1) of plane k on R1
+    {
+      const T* hp = h0L + hb(k) * 3 * G.N4;
+      const T* hq = h0L + hb(k - 1) * 3 * G.N4;
+      const T* cp = cL + cb(k) * G.N4;
+      const T* cq = cL + cb(k - 1) * G.N4;
+      const T* sp = sL + cb(k) * G.N4;
+      const T* sqq = sL + cb(k - 1) * G.N4;
+      T* out = e1L + hb(k) * 3 * G.N1;
+#pragma unroll
+      for (int r = 0; r < kS2Per; ++r) {
+        const int q = tid + r * nthr;
+        if (q < G.N1) {
+          const int x = q % G.W1 - 1, y = q / G.W1 - 1;
+          T exn, eyn, ezn;
+          e_upd(x, y, k, hp, hq, G.N4, i4(x, y), i4(x - 1, y), i4(x, y - 1), cp, cq, sp, sqq,
+                e0r[r][0], e0r[r][1], e0r[r][2], A.src_val[0], exn, eyn, ezn);
+          out[q] = exn;
+          out[G.N1 + q] = eyn;
+          out[2 * G.N1 + q] = ezn;
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- h^(m+3/2) of plane km = k - 1 on R2 (from e^(m+1) of planes km, k)
+    const int km = k - 1;
+    if (km >= k0 - 1) {
+      const T* nq = e1L + hb(km) * 3 * G.N1;
+      const T* np_ = e1L + hb(k) * 3 * G.N1;
+      const T* ho = h0L + hb(km) * 3 * G.N4;
+      T* out = h1L + hb(km) * 3 * G.N2;
+      const bool kin = km >= 0 && km < d.nz;
+      for (int q = tid; q < G.N2; q += nthr) {
+        const int x = q % G.W2 - 1, y = q / G.W2 - 1;
+        const int gi = i0 + x, gj = j0 + y;
+        const bool valid = kin && in_grid(gi, gj);
+        const int e = i1(x, y), e_in = i1(x + 1, y), e_jn = i1(x, y + 1);
+        const int r4 = i4(x, y);
+        T hxn, hyn, hzn;
+        h_point<T>(nq[e], nq[G.N1 + e], nq[2 * G.N1 + e], np_[e], np_[G.N1 + e],
+                   nq[2 * G.N1 + e_jn], nq[2 * G.N1 + e_in], nq[G.N1 + e_in], nq[e_jn], ho[r4],
+                   ho[G.N4 + r4], ho[2 * G.N4 + r4], A.imu2, A.imu2, A.imu2, valid && gi > 0,
+                   valid && gj > 0, valid && km > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
+        out[q] = hxn;
+        out[G.N2 + q] = hyn;
+        out[2 * G.N2 + q] = hzn;
+      }
+    }
+    __syncthreads();
+
+    // ---- e^(m+2) of plane km on R3 (from h^(m+3/2) of planes km, km - 1 and
+    // e^(m+1) of plane km); the tile part of planes [k0, k1) is stored
+    if (km >= k0) {
+      const T* hp = h1L + hb(km) * 3 * G.N2;
+      const T* hq = h1L + hb(km - 1) * 3 * G.N2;
+      const T* cp = cL + cb(km) * G.N4;
+      const T* cq = cL + cb(km - 1) * G.N4;
+      const T* sp = sL + cb(km) * G.N4;
+      const T* sqq = sL + cb(km - 1) * G.N4;
+      const T* eo = e1L + hb(km) * 3 * G.N1;
+      T* out = e2L + hb(km) * 3 * G.N3;
+      for (int q = tid; q < G.N3; q += nthr) {
+        const int x = q % G.W3, y = q / G.W3;
+        const int o = i1(x, y);
+        T exn, eyn, ezn;
+        e_upd(x, y, km, hp, hq, G.N2, i2(x, y), i2(x - 1, y), i2(x, y - 1), cp, cq, sp, sqq,
+              eo[o], eo[G.N1 + o], eo[2 * G.N1 + o], A.src_val[1], exn, eyn, ezn);
+        out[q] = exn;
+        out[G.N3 + q] = eyn;
+        out[2 * G.N3 + q] = ezn;
+        const int gi = i0 + x, gj = j0 + y;
+        if (x < TW && y < TY && km < k1 && in_grid(gi, gj)) {
+          const int64_t g = gi + sx * gj + sxy * (int64_t)km;
+          gst(A.e2[0], g, exn);
+          gst(A.e2[1], g, eyn);
+          gst(A.e2[2], g, ezn);
+        }
+      }
+    }
+    __syncthreads();
+
+    // ---- h^(m+5/2) of plane kh = k - 2 on the tile (from e^(m+2) of planes kh, kh + 1)
+    const int kh = k - 2;
+    if (kh >= k0 && kh < k1) {
+      const T* nq = e2L + hb(kh) * 3 * G.N3;
+      const T* np_ = e2L + hb(kh + 1) * 3 * G.N3;
+      const T* ho = h1L + hb(kh) * 3 * G.N2;
+      for (int q = tid; q < TW * TY; q += nthr) {
+        const int x = q % TW, y = q / TW;
+        const int gi = i0 + x, gj = j0 + y;
+        if (!in_grid(gi, gj)) continue;
+        const int e = i3(x, y), e_in = i3(x + 1, y), e_jn = i3(x, y + 1);
+        const int r2 = i2(x, y);
+        T hxn, hyn, hzn;
+        h_point<T>(nq[e], nq[G.N3 + e], nq[2 * G.N3 + e], np_[e], np_[G.N3 + e],
+                   nq[2 * G.N3 + e_jn], nq[2 * G.N3 + e_in], nq[G.N3 + e_in], nq[e_jn], ho[r2],
+                   ho[G.N2 + r2], ho[2 * G.N2 + r2], A.imu2, A.imu2, A.imu2, gi > 0, gj > 0,
+                   kh > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
+        const int64_t g = gi + sx * gj + sxy * (int64_t)kh;
+        gst(A.h2[0], g, hxn);
+        gst(A.h2[1], g, hyn);
+        gst(A.h2[2], g, hzn);
+      }
+    }
+  }
+}
+
+template <typename T>
+hipError_t launch_step2(const S2Args<T>& a, bool lossy, hipStream_t s) {
+  if (!step2_shape_ok(a.t.tw, a.t.ty, sizeof(T), lossy)) return hipErrorInvalidValue;
+  const dim3 blk(a.t.tw, a.t.ty), grd((unsigned)a.t.blocks());
+  const size_t lds = step2_lds_bytes(a.t.tw, a.t.ty, sizeof(T), lossy);
+  if (lossy) {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step2<T, true>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_step2<T, true>), grd, blk, lds, s, a);
+  } else {
+    if (lds > 64 * 1024) {
+      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step2<T, false>),
+                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+      if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_step2<T, false>), grd, blk, lds, s, a);
+  }
+  return hipGetLastError();
+}
+
+template hipError_t launch_step2<float>(const S2Args<float>&, bool, hipStream_t);
+template hipError_t launch_step2<double>(const S2Args<double>&, bool, hipStream_t);
+
+}  // namespace fit

@@ -307,6 +307,17 @@ class FitGrid:
             tw = 64 if (ty or kc) else 0
         call("fit_set_tuning", self._h, self.PATHS[path], int(tw), int(ty), int(kc))
 
+    def set_pair(self, enable: bool = True, tw: int = 0, ty: int = 0, kc: int = 0):
+        """Two steps per launch (temporal blocking) where eligible; tile tw x ty,
+        kc planes per chunk (zeros: defaults)."""
+        call("fit_set_pair_tuning", self._h, int(bool(enable)), int(tw), int(ty), int(kc))
+
+    def get_pair(self):
+        """(enabled, tw, ty, kc)."""
+        e, w, t, k = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        call("fit_get_pair_tuning", self._h, C.byref(e), C.byref(w), C.byref(t), C.byref(k))
+        return bool(e.value), w.value, t.value, k.value
+
     def get_tuning(self):
         """(path, ty, kc, tw)."""
         p, w, t, k = C.c_int(), C.c_int(), C.c_int(), C.c_int()

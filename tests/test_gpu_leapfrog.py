@@ -331,3 +331,37 @@ def test_probe_objective_across_tilings_and_paths():
     g.probe_reset()
     assert g.probe_value() == 0.0
     g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_fused_with_trace_and_probe_matches_split(dtype):
+    """Energies and the probe on the same fused steps (FP32 runs such steps on
+    the split kernels) give the split path's fields bitwise, its trace and its
+    objective."""
+    from paper_1705_08019_amd import FitGrid
+    nx, ny, nz = 45, 26, 19
+    eps = dielectric_blocks(nx, ny, nz, 5, 3)
+    sig = lossy_slab(nx, ny, nz, 1, 0.2)
+    rng = np.random.default_rng(3)
+    e0 = rng.standard_normal((3, nz, ny, nx))
+    out = []
+    for path in ("fused", "split"):
+        g = FitGrid(nx, ny, nz, dtype)
+        g.set_materials(eps, None, sig)
+        g.set_fields(e0, None, 0)
+        dt = 0.9 * g.cfl_dt()
+        g.set_source(2, nx // 2, ny // 2, nz // 2, 1.0, 4 * dt)
+        g.set_tuning(path)
+        g.trace_config(3, 20)
+        g.set_probe([2, 2, 2], [10, 10, 10])
+        g.step(20, dt)
+        e, h = g.get_fields()
+        tr, _ = g.trace_read()
+        out.append((to_np(e), to_np(h), tr, g.probe_value()))
+        g.close()
+    (ef, hf, tf, jf), (es, hs, ts, js) = out
+    assert np.all(np.isfinite(ef)) and np.all(np.isfinite(hf))
+    assert np.array_equal(ef, es) and np.array_equal(hf, hs)
+    tol = 1e-12 if dtype == "f64" else 1e-6
+    np.testing.assert_allclose(tf[:, 1:], ts[:, 1:], rtol=tol, atol=tol * np.nanmax(np.abs(ts[:, 1:])))
+    assert abs(jf - js) <= tol * abs(js)
