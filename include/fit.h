@@ -417,10 +417,11 @@ int fit_get_tuning(const fit_grid* g, int* path, int* tw, int* ty, int* kc);
  * intermediate state on chip, whenever the fused path is active, the grid
  * has uniform spacing, no probe is set and neither step of the pair needs
  * energies for the trace (other steps run singly).  The result is bitwise
- * that of single fused steps.  tw x ty: tile (a multiple of 64 threads, at
- * most 1024, LDS within 160 KiB), kc: planes per chunk (0 = one round of
- * resident workgroups); tw = ty = 0 takes the first of 64 x 16, 64 x 8,
- * 32 x 16, 16 x 8 that fits the dtype.
+ * that of single fused steps.  tw x ty: tile (tw >= 8, ty >= 2, tw ty <=
+ * 1024; a workgroup has one thread per point of the tile grown by 3 in x
+ * and y, at most 1024; LDS within 160 KiB), kc: planes per chunk (0 = one
+ * round of resident workgroups); tw = ty = 0 takes the first of 64 x 12,
+ * 64 x 8, 32 x 16, 32 x 8, 16 x 8 that fits the dtype.
  * Errors: FIT_E_INVALID for an unsupported tile. */
 int fit_set_pair_tuning(fit_grid* g, int enable, int tw, int ty, int kc);
 /* The pair setting in effect (kc: the chunk a launch would use). */
@@ -431,8 +432,10 @@ int fit_get_pair_tuning(const fit_grid* g, int* enable, int* tw, int* ty, int* k
  * runtime's occupancy query) with `reps` timed launches each, on the current
  * state and dt, and keep the fastest (as fit_set_tuning).  The state, step
  * counter, trace and probe are left unchanged (candidates run out of place
- * into the second buffer set).  Any output pointer may be NULL; *ms_best is
- * the per-step time of the winner.  Synchronises. */
+ * into the second buffer set).  On the fused path it also times step pairs
+ * (fit_set_pair_tuning) for a few tiles and z-chunks and switches them on
+ * when a pair takes less than 98 % of two single steps.  Any output pointer
+ * may be NULL; *ms_best is the per-step time of the winner.  Synchronises. */
 int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* tw, int* ty, int* kc,
                  float* ms_best);
 

@@ -424,7 +424,7 @@ static int device_cus() {
 static int pair_kc(const fit_grid* g, int tw, int ty) {
   const size_t lds = step2_lds_bytes(tw, ty, g->esz, g->lossy);
   const int per_cu = std::max(1, std::min((int)((160 * 1024) / std::max<size_t>(lds, 1)),
-                                          2048 / (tw * ty)));
+                                          2048 / step2_threads(tw, ty)));
   const int64_t tiles = (int64_t)((g->d.nx + tw - 1) / tw) * ((g->d.ny + ty - 1) / ty);
   const int64_t nkc = std::max<int64_t>(1, (int64_t)device_cus() * per_cu / tiles);
   const int k = (int)((g->d.nz + nkc - 1) / nkc);
@@ -479,6 +479,47 @@ static int step_pair(fit_grid* g, double dt) {
   g->m += 2;
   g->smvp += 4;
   return FIT_OK;
+}
+
+// Time `reps` pair launches of one tile on the current state (out of place,
+// swapped back: the state, step counter and pair setting are unchanged);
+// *ms = time per pair.
+template <typename T>
+static int time_pair(fit_grid* g, double dt, int tw, int ty, int kc, int reps, float* ms) {
+  const int s_on = g->pair_on, s_tw = g->ptw, s_ty = g->pty, s_kc = g->pkc;
+  const int64_t s_m = g->m, s_smvp = g->smvp;
+  g->ptw = tw;
+  g->pty = ty;
+  g->pkc = kc;
+  hipEvent_t ev[2];
+  (void)hipEventCreate(&ev[0]);
+  (void)hipEventCreate(&ev[1]);
+  auto one = [&]() -> int {
+    int r = step_pair<T>(g, dt);
+    std::swap(g->e, g->e_alt);
+    std::swap(g->h, g->h_alt);
+    return r;
+  };
+  int rc = FIT_OK;
+  for (int w = 0; w < 2 && !rc; ++w) rc = one();
+  if (!rc) {
+    (void)hipEventRecord(ev[0], g->s);
+    for (int r = 0; r < reps && !rc; ++r) rc = one();
+    (void)hipEventRecord(ev[1], g->s);
+    hipError_t e = hipEventSynchronize(ev[1]);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, ev[0], ev[1]);
+    if (e != hipSuccess && !rc) rc = hip_fail(e, "pair timing");
+    *ms /= (float)std::max(reps, 1);
+  }
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  g->pair_on = s_on;
+  g->ptw = s_tw;
+  g->pty = s_ty;
+  g->pkc = s_kc;
+  g->m = s_m;
+  g->smvp = s_smvp;
+  return rc;
 }
 
 template int step_fused<float>(fit_grid*, double);
@@ -1221,6 +1262,38 @@ int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* tw, int* ty, 
   }
   rc = fit_set_tuning(g, bc.path, bc.tw, bc.ty, bc.kc);
   if (rc) return rc;
+  // two steps per launch: take it when a pair beats two single steps
+  g->pair_on = 0;
+  if (use_fused(g) && !g->nu && g->d.nz >= 2) {
+    const int shapes[4][2] = {{32, 16}, {64, 8}, {32, 8}, {48, 8}};
+    float best_pair = 1e30f;
+    int bw = 0, bt = 0, bk = 0;
+    for (const auto& sh : shapes) {
+      if (!step2_shape_ok(sh[0], sh[1], g->esz, g->lossy)) continue;
+      const int k0 = pair_kc(g, sh[0], sh[1]);
+      const int kcs[2] = {k0, std::max(std::min(8, g->d.nz), k0 / 2)};
+      for (int q = 0; q < 2; ++q) {
+        if (q == 1 && kcs[1] == kcs[0]) continue;
+        float ms = 0.f;
+        rc = g->f64 ? time_pair<double>(g, dt, sh[0], sh[1], kcs[q], reps, &ms)
+                    : time_pair<float>(g, dt, sh[0], sh[1], kcs[q], reps, &ms);
+        if (rc) return rc;
+        if (ms < best_pair) {
+          best_pair = ms;
+          bw = sh[0];
+          bt = sh[1];
+          bk = kcs[q];
+        }
+      }
+    }
+    if (bw > 0 && 0.5f * best_pair < 0.98f * best) {
+      g->pair_on = 1;
+      g->ptw = bw;
+      g->pty = bt;
+      g->pkc = bk;
+      best = 0.5f * best_pair;
+    }
+  }
   if (path) *path = bc.path;
   if (tw) *tw = bc.tw;
   if (ty) *ty = bc.ty;
@@ -1234,7 +1307,7 @@ int fit_set_pair_tuning(fit_grid* g, int enable, int tw, int ty, int kc) {
   if (enable != 0 && enable != 1) return fail(FIT_E_INVALID, "enable must be 0 or 1");
   if (kc < 0) return fail(FIT_E_INVALID, "kc must be >= 0");
   if (tw == 0 && ty == 0) {   // the first default tile that fits this dtype
-    const int shapes[4][2] = {{64, 16}, {64, 8}, {32, 16}, {16, 8}};
+    const int shapes[5][2] = {{64, 12}, {64, 8}, {32, 16}, {32, 8}, {16, 8}};
     tw = 64;
     ty = 16;
     for (const auto& sh : shapes)
@@ -1245,8 +1318,8 @@ int fit_set_pair_tuning(fit_grid* g, int enable, int tw, int ty, int kc) {
       }
   }
   if (!step2_shape_ok(tw, ty, g->esz, g->lossy))
-    return fail(FIT_E_INVALID, "unsupported tile for the step pair (tw ty a multiple of 64 up "
-                               "to 1024, staged regions within 2 entries per thread, LDS <= 160 KiB)");
+    return fail(FIT_E_INVALID, "unsupported tile for the step pair (tw >= 8, ty >= 2, tw ty <= "
+                               "1024, staged regions within 2 entries per thread, LDS <= 160 KiB)");
   g->pair_on = enable;
   g->ptw = tw;
   g->pty = ty;

@@ -168,6 +168,9 @@ struct S2Args {
   T src_val[2];
 };
 size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy);
+// Threads of a pair workgroup: enough for one e^(m+1) point each (the
+// largest region), a multiple of 64, at most 1024.
+int step2_threads(int tw, int ty);
 // Tile shapes the two-step kernel takes: tw ty a multiple of 64, <= 1024,
 // the staged regions within kS2Per entries per thread, LDS <= 160 KiB.
 bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy);

@@ -4,7 +4,8 @@
 // lives only in LDS.  Per cell and pair of steps this moves the 56 B of one
 // fused step instead of 112 B.
 //
-// A workgroup owns a TW x TY column tile and marches a chunk [k0, k1) of
+// A workgroup (as many threads as the e^(m+1) region has points, up to
+// 1024, numbered linearly) owns a TW x TY column tile and marches a chunk [k0, k1) of
 // z-planes with a lag of two planes between what it reads and what it
 // stores.  In local coordinates (x along i, y along j) the regions are
 //   X4: x in [-2, TW+1], y in [-2, TY+1]  staged h^(m+1/2), eps, sigma
@@ -18,6 +19,8 @@
 // contraction-pinned point functions as the single-step kernels, so the
 // result is bitwise that of two single steps.  Values outside the grid and
 // on planes outside [0, nz) are zero (PEC), as in the single-step kernels.
+#include <algorithm>
+
 #include "fit_step_tile.hpp"
 
 namespace fit {
@@ -46,11 +49,16 @@ size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy) {
   return esz * n;
 }
 
-bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy) {
-  if (tw < 8 || ty < 2 || tw * ty > 1024 || (tw * ty) % 64 != 0) return false;
+int step2_threads(int tw, int ty) {
   const S2Geom g = s2_geom(tw, ty);
-  const int nthr = tw * ty;
-  if (g.N4 > kS2Per * nthr || g.N1 > kS2Per * nthr) return false;
+  return (g.N1 + 63) / 64 * 64;
+}
+
+bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy) {
+  if (tw < 8 || ty < 2) return false;
+  const S2Geom g = s2_geom(tw, ty);
+  const int nthr = step2_threads(tw, ty);   // one thread per point of the largest computed region
+  if (nthr > 1024 || g.N4 > kS2Per * nthr) return false;
   return step2_lds_bytes(tw, ty, esz, lossy) <= 160 * 1024;
 }
 
@@ -77,7 +85,7 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
   const int k0 = kz * A.t.kc;
   const int k1 = min(k0 + A.t.kc, d.nz);
   const int tid = (int)(threadIdx.x + threadIdx.y * blockDim.x);
-  const int nthr = (int)(blockDim.x * blockDim.y);
+  const int nthr = (int)(blockDim.x * blockDim.y);   // >= N1 >= N2 >= N3 >= TW TY
   const int64_t sx = d.sx, sxy = d.sxy;
 
   auto hb = [](int k) { return k & 1; };                 // h0 / e1 / h1 / e2 buffer of plane k
@@ -88,33 +96,68 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
   auto i3 = [&](int x, int y) { return y * G.W3 + x; };
   auto in_grid = [&](int gx, int gy) { return gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny; };
 
-  // ---- register staging of plane k: X4 entries (h x3, eps, sigma), R1 entries (e x3)
+  // ---- per-thread points of every region (fixed over the z-march)
+  // X4 staging entries (up to kS2Per per thread)
+  int64_t g4[kS2Per];
+  bool in4[kS2Per];
+#pragma unroll
+  for (int r = 0; r < kS2Per; ++r) {
+    const int q = tid + r * nthr;
+    const int gx = i0 + (q % G.W4) - 2, gy = j0 + (q / G.W4) - 2;
+    in4[r] = q < G.N4 && in_grid(gx, gy);
+    g4[r] = in4[r] ? gx + sx * gy : 0;
+  }
+  // R1 point (e^(m+1)): one per thread
+  const bool a1 = tid < G.N1;
+  const int x1 = tid % G.W1 - 1, y1 = tid / G.W1 - 1;
+  const int gx1 = i0 + x1, gy1 = j0 + y1;
+  const bool in1 = a1 && in_grid(gx1, gy1);
+  const int64_t g1 = in1 ? gx1 + sx * gy1 : 0;
+  const int r1 = i4(x1, y1), r1im = i4(x1 - 1, y1), r1jm = i4(x1, y1 - 1),
+            r1ijm = i4(x1 - 1, y1 - 1);
+  // R2 point (h^(m+3/2))
+  const bool a2 = tid < G.N2;
+  const int x2 = tid % G.W2 - 1, y2 = tid / G.W2 - 1;
+  const bool in2 = a2 && in_grid(i0 + x2, j0 + y2);
+  const bool px2 = in2 && i0 + x2 > 0, py2 = in2 && j0 + y2 > 0;
+  const int e2c = i1(x2, y2), e2in = i1(x2 + 1, y2), e2jn = i1(x2, y2 + 1), r2h = i4(x2, y2);
+  // R3 point (e^(m+2))
+  const bool a3 = tid < G.N3;
+  const int x3 = tid % G.W3, y3 = tid / G.W3;
+  const int gx3 = i0 + x3, gy3 = j0 + y3;
+  const bool in3 = a3 && in_grid(gx3, gy3);
+  const bool own3 = in3 && x3 < TW && y3 < TY;
+  const int64_t g3 = in3 ? gx3 + sx * gy3 : 0;
+  const int r3 = i4(x3, y3), r3im = i4(x3 - 1, y3), r3jm = i4(x3, y3 - 1),
+            r3ijm = i4(x3 - 1, y3 - 1);
+  const int h3 = i2(x3, y3), h3im = i2(x3 - 1, y3), h3jm = i2(x3, y3 - 1), o3 = i1(x3, y3);
+  // tile point (h^(m+5/2))
+  const int x5 = tid % TW, y5 = tid / TW;
+  const bool own5 = tid < TW * TY && in_grid(i0 + x5, j0 + y5);
+  const int64_t g5 = own5 ? (i0 + x5) + sx * (j0 + y5) : 0;
+  const int e5 = i3(x5, y5), e5in = i3(x5 + 1, y5), e5jn = i3(x5, y5 + 1), h5 = i2(x5, y5);
+
+  // ---- register staging of plane k: X4 entries (h x3, eps, sigma), R1 entry (e x3)
   T ph[kS2Per][5];
-  T pe[kS2Per][3];
+  T pe[3];
   auto fetch = [&](int k) {
     const bool plane = k >= 0 && k < d.nz;
+    const int64_t gk = sxy * (int64_t)k;
 #pragma unroll
     for (int r = 0; r < kS2Per; ++r) {
-      const int q = tid + r * nthr;
-      {
-        const int gx = i0 + (q % G.W4) - 2, gy = j0 + (q / G.W4) - 2;
-        const bool in = plane && q < G.N4 && in_grid(gx, gy);
-        const int64_t g = in ? gx + sx * gy + sxy * (int64_t)k : 0;
-        ph[r][0] = in ? gld(A.h0[0], g) : T(0);
-        ph[r][1] = in ? gld(A.h0[1], g) : T(0);
-        ph[r][2] = in ? gld(A.h0[2], g) : T(0);
-        ph[r][3] = in ? gld(A.eps, g) : T(0);
-        ph[r][4] = (LOSSY && in) ? gld(A.sig, g) : T(0);
-      }
-      {
-        const int gx = i0 + (q % G.W1) - 1, gy = j0 + (q / G.W1) - 1;
-        const bool in = plane && q < G.N1 && in_grid(gx, gy);
-        const int64_t g = in ? gx + sx * gy + sxy * (int64_t)k : 0;
-        pe[r][0] = in ? gld(A.e0[0], g) : T(0);
-        pe[r][1] = in ? gld(A.e0[1], g) : T(0);
-        pe[r][2] = in ? gld(A.e0[2], g) : T(0);
-      }
+      const bool in = plane && in4[r];
+      const int64_t g = g4[r] + (in ? gk : 0);
+      ph[r][0] = in ? gld(A.h0[0], g) : T(0);
+      ph[r][1] = in ? gld(A.h0[1], g) : T(0);
+      ph[r][2] = in ? gld(A.h0[2], g) : T(0);
+      ph[r][3] = in ? gld(A.eps, g) : T(0);
+      ph[r][4] = (LOSSY && in) ? gld(A.sig, g) : T(0);
     }
+    const bool in = plane && in1;
+    const int64_t g = g1 + (in ? gk : 0);
+    pe[0] = in ? gld(A.e0[0], g) : T(0);
+    pe[1] = in ? gld(A.e0[1], g) : T(0);
+    pe[2] = in ? gld(A.e0[2], g) : T(0);
   };
   auto stage = [&](int k) {
     T* h = h0L + hb(k) * 3 * G.N4;
@@ -133,15 +176,14 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
     }
   };
 
-  // e-update of one point (local x, y) of plane k: h planes k (hp) and k-1
-  // (hq) with index map ih and row length nh, materials of planes k, k-1
-  // (X4 layout); same operand order as the single-step kernels.
-  auto e_upd = [&](int x, int y, int k, const T* hp, const T* hq, int NH, int rh, int rh_im,
-                   int rh_jm, const T* cp, const T* cq, const T* sp, const T* sq, T exo, T eyo,
-                   T ezo, T src, T& exn, T& eyn, T& ezn) {
-    const int gi = i0 + x, gj = j0 + y;
-    const bool valid = in_grid(gi, gj) && k >= 0 && k < d.nz;
-    const int r = i4(x, y), rim = i4(x - 1, y), rjm = i4(x, y - 1), rijm = i4(x - 1, y - 1);
+  // e-update of one point of plane k: h planes k (hp) and k-1 (hq) with row
+  // stride NH and indices (rh, rh_im, rh_jm); materials of planes k, k-1 in
+  // the X4 layout at (r, rim, rjm, rijm); same operand order as the
+  // single-step kernels.
+  auto e_upd = [&](bool valid, int gi, int gj, int64_t g, int k, const T* hp, const T* hq, int NH,
+                   int rh, int rh_im, int rh_jm, int r, int rim, int rjm, int rijm, const T* cp,
+                   const T* cq, const T* sp, const T* sq, T exo, T eyo, T ezo, T src, T& exn,
+                   T& eyn, T& ezn) {
     const T c = cp[r], c_im = cp[rim], c_jm = cp[rjm], c_ijm = cp[rijm];
     const T Sx = c + c_im, Sy = c + c_jm, Sxj = c_jm + c_ijm;
     const T pc = cq[r];
@@ -157,7 +199,6 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
       S4y = sxs + Sxs;
       S4z = Sxs + (s_jm + s_ijm);
     }
-    const int64_t g = gi + sx * gj + sxy * (int64_t)k;
     T jx = 0, jy = 0, jz = 0;
     if (valid && g == A.src_idx) {
       if (A.src_comp == 0) jx = src;
@@ -179,120 +220,82 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
 
   for (int k = k0 - 1; k <= k1 + 1; ++k) {
     stage(k);
-    T e0r[kS2Per][3];
-#pragma unroll
-    for (int r = 0; r < kS2Per; ++r) {
-      e0r[r][0] = pe[r][0];
-      e0r[r][1] = pe[r][1];
-      e0r[r][2] = pe[r][2];
-    }
+    const T e0x = pe[0], e0y = pe[1], e0z = pe[2];
     if (k + 1 <= k1 + 1) fetch(k + 1);
     __syncthreads();
 
     // ---- e^(m+1) of plane k on R1
-    {
-      const T* hp = h0L + hb(k) * 3 * G.N4;
-      const T* hq = h0L + hb(k - 1) * 3 * G.N4;
-      const T* cp = cL + cb(k) * G.N4;
-      const T* cq = cL + cb(k - 1) * G.N4;
-      const T* sp = sL + cb(k) * G.N4;
-      const T* sqq = sL + cb(k - 1) * G.N4;
+    if (a1) {
+      const bool kin = k >= 0 && k < d.nz;
+      T exn, eyn, ezn;
+      e_upd(in1 && kin, gx1, gy1, g1 + sxy * (int64_t)k, k, h0L + hb(k) * 3 * G.N4,
+            h0L + hb(k - 1) * 3 * G.N4, G.N4, r1, r1im, r1jm, r1, r1im, r1jm, r1ijm,
+            cL + cb(k) * G.N4, cL + cb(k - 1) * G.N4, sL + cb(k) * G.N4, sL + cb(k - 1) * G.N4,
+            e0x, e0y, e0z, A.src_val[0], exn, eyn, ezn);
       T* out = e1L + hb(k) * 3 * G.N1;
-#pragma unroll
-      for (int r = 0; r < kS2Per; ++r) {
-        const int q = tid + r * nthr;
-        if (q < G.N1) {
-          const int x = q % G.W1 - 1, y = q / G.W1 - 1;
-          T exn, eyn, ezn;
-          e_upd(x, y, k, hp, hq, G.N4, i4(x, y), i4(x - 1, y), i4(x, y - 1), cp, cq, sp, sqq,
-                e0r[r][0], e0r[r][1], e0r[r][2], A.src_val[0], exn, eyn, ezn);
-          out[q] = exn;
-          out[G.N1 + q] = eyn;
-          out[2 * G.N1 + q] = ezn;
-        }
-      }
+      out[tid] = exn;
+      out[G.N1 + tid] = eyn;
+      out[2 * G.N1 + tid] = ezn;
     }
     __syncthreads();
 
     // ---- h^(m+3/2) of plane km = k - 1 on R2 (from e^(m+1) of planes km, k)
     const int km = k - 1;
-    if (km >= k0 - 1) {
+    if (km >= k0 - 1 && a2) {
       const T* nq = e1L + hb(km) * 3 * G.N1;
       const T* np_ = e1L + hb(k) * 3 * G.N1;
       const T* ho = h0L + hb(km) * 3 * G.N4;
+      const bool valid = in2 && km >= 0 && km < d.nz;
+      T hxn, hyn, hzn;
+      h_point<T>(nq[e2c], nq[G.N1 + e2c], nq[2 * G.N1 + e2c], np_[e2c], np_[G.N1 + e2c],
+                 nq[2 * G.N1 + e2jn], nq[2 * G.N1 + e2in], nq[G.N1 + e2in], nq[e2jn], ho[r2h],
+                 ho[G.N4 + r2h], ho[2 * G.N4 + r2h], A.imu2, A.imu2, A.imu2, valid && px2,
+                 valid && py2, valid && km > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
       T* out = h1L + hb(km) * 3 * G.N2;
-      const bool kin = km >= 0 && km < d.nz;
-      for (int q = tid; q < G.N2; q += nthr) {
-        const int x = q % G.W2 - 1, y = q / G.W2 - 1;
-        const int gi = i0 + x, gj = j0 + y;
-        const bool valid = kin && in_grid(gi, gj);
-        const int e = i1(x, y), e_in = i1(x + 1, y), e_jn = i1(x, y + 1);
-        const int r4 = i4(x, y);
-        T hxn, hyn, hzn;
-        h_point<T>(nq[e], nq[G.N1 + e], nq[2 * G.N1 + e], np_[e], np_[G.N1 + e],
-                   nq[2 * G.N1 + e_jn], nq[2 * G.N1 + e_in], nq[G.N1 + e_in], nq[e_jn], ho[r4],
-                   ho[G.N4 + r4], ho[2 * G.N4 + r4], A.imu2, A.imu2, A.imu2, valid && gi > 0,
-                   valid && gj > 0, valid && km > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
-        out[q] = hxn;
-        out[G.N2 + q] = hyn;
-        out[2 * G.N2 + q] = hzn;
-      }
+      out[tid] = hxn;
+      out[G.N2 + tid] = hyn;
+      out[2 * G.N2 + tid] = hzn;
     }
     __syncthreads();
 
     // ---- e^(m+2) of plane km on R3 (from h^(m+3/2) of planes km, km - 1 and
     // e^(m+1) of plane km); the tile part of planes [k0, k1) is stored
-    if (km >= k0) {
-      const T* hp = h1L + hb(km) * 3 * G.N2;
-      const T* hq = h1L + hb(km - 1) * 3 * G.N2;
-      const T* cp = cL + cb(km) * G.N4;
-      const T* cq = cL + cb(km - 1) * G.N4;
-      const T* sp = sL + cb(km) * G.N4;
-      const T* sqq = sL + cb(km - 1) * G.N4;
+    if (km >= k0 && a3) {
       const T* eo = e1L + hb(km) * 3 * G.N1;
+      const bool kin = km >= 0 && km < d.nz;
+      const int64_t g = g3 + sxy * (int64_t)km;
+      T exn, eyn, ezn;
+      e_upd(in3 && kin, gx3, gy3, g, km, h1L + hb(km) * 3 * G.N2, h1L + hb(km - 1) * 3 * G.N2,
+            G.N2, h3, h3im, h3jm, r3, r3im, r3jm, r3ijm, cL + cb(km) * G.N4,
+            cL + cb(km - 1) * G.N4, sL + cb(km) * G.N4, sL + cb(km - 1) * G.N4, eo[o3],
+            eo[G.N1 + o3], eo[2 * G.N1 + o3], A.src_val[1], exn, eyn, ezn);
       T* out = e2L + hb(km) * 3 * G.N3;
-      for (int q = tid; q < G.N3; q += nthr) {
-        const int x = q % G.W3, y = q / G.W3;
-        const int o = i1(x, y);
-        T exn, eyn, ezn;
-        e_upd(x, y, km, hp, hq, G.N2, i2(x, y), i2(x - 1, y), i2(x, y - 1), cp, cq, sp, sqq,
-              eo[o], eo[G.N1 + o], eo[2 * G.N1 + o], A.src_val[1], exn, eyn, ezn);
-        out[q] = exn;
-        out[G.N3 + q] = eyn;
-        out[2 * G.N3 + q] = ezn;
-        const int gi = i0 + x, gj = j0 + y;
-        if (x < TW && y < TY && km < k1 && in_grid(gi, gj)) {
-          const int64_t g = gi + sx * gj + sxy * (int64_t)km;
-          gst(A.e2[0], g, exn);
-          gst(A.e2[1], g, eyn);
-          gst(A.e2[2], g, ezn);
-        }
+      out[tid] = exn;
+      out[G.N3 + tid] = eyn;
+      out[2 * G.N3 + tid] = ezn;
+      if (own3 && km < k1) {
+        gst(A.e2[0], g, exn);
+        gst(A.e2[1], g, eyn);
+        gst(A.e2[2], g, ezn);
       }
     }
     __syncthreads();
 
     // ---- h^(m+5/2) of plane kh = k - 2 on the tile (from e^(m+2) of planes kh, kh + 1)
     const int kh = k - 2;
-    if (kh >= k0 && kh < k1) {
+    if (kh >= k0 && kh < k1 && own5) {
       const T* nq = e2L + hb(kh) * 3 * G.N3;
       const T* np_ = e2L + hb(kh + 1) * 3 * G.N3;
       const T* ho = h1L + hb(kh) * 3 * G.N2;
-      for (int q = tid; q < TW * TY; q += nthr) {
-        const int x = q % TW, y = q / TW;
-        const int gi = i0 + x, gj = j0 + y;
-        if (!in_grid(gi, gj)) continue;
-        const int e = i3(x, y), e_in = i3(x + 1, y), e_jn = i3(x, y + 1);
-        const int r2 = i2(x, y);
-        T hxn, hyn, hzn;
-        h_point<T>(nq[e], nq[G.N3 + e], nq[2 * G.N3 + e], np_[e], np_[G.N3 + e],
-                   nq[2 * G.N3 + e_jn], nq[2 * G.N3 + e_in], nq[G.N3 + e_in], nq[e_jn], ho[r2],
-                   ho[G.N2 + r2], ho[2 * G.N2 + r2], A.imu2, A.imu2, A.imu2, gi > 0, gj > 0,
-                   kh > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
-        const int64_t g = gi + sx * gj + sxy * (int64_t)kh;
-        gst(A.h2[0], g, hxn);
-        gst(A.h2[1], g, hyn);
-        gst(A.h2[2], g, hzn);
-      }
+      T hxn, hyn, hzn;
+      h_point<T>(nq[e5], nq[G.N3 + e5], nq[2 * G.N3 + e5], np_[e5], np_[G.N3 + e5],
+                 nq[2 * G.N3 + e5jn], nq[2 * G.N3 + e5in], nq[G.N3 + e5in], nq[e5jn], ho[h5],
+                 ho[G.N2 + h5], ho[2 * G.N2 + h5], A.imu2, A.imu2, A.imu2, i0 + x5 > 0,
+                 j0 + y5 > 0, kh > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
+      const int64_t g = g5 + sxy * (int64_t)kh;
+      gst(A.h2[0], g, hxn);
+      gst(A.h2[1], g, hyn);
+      gst(A.h2[2], g, hzn);
     }
   }
 }
@@ -300,7 +303,7 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
 template <typename T>
 hipError_t launch_step2(const S2Args<T>& a, bool lossy, hipStream_t s) {
   if (!step2_shape_ok(a.t.tw, a.t.ty, sizeof(T), lossy)) return hipErrorInvalidValue;
-  const dim3 blk(a.t.tw, a.t.ty), grd((unsigned)a.t.blocks());
+  const dim3 blk(step2_threads(a.t.tw, a.t.ty)), grd((unsigned)a.t.blocks());
   const size_t lds = step2_lds_bytes(a.t.tw, a.t.ty, sizeof(T), lossy);
   if (lossy) {
     if (lds > 64 * 1024) {

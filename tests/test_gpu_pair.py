@@ -50,8 +50,8 @@ def test_pair_is_bitwise_two_single_steps(dtype, n, lossy):
     steps = 10
     ref = _run(n, dtype, lossy, steps)
     assert ref[4]["pair"][1] == 0
-    shapes = [(64, 16, 0), (64, 8, 1), (32, 16, 2), (64, 8, 3), (32, 16, 5), (16, 8, 0),
-              (128, 8, 0)]
+    shapes = [(64, 12, 0), (64, 8, 1), (32, 16, 2), (64, 8, 3), (32, 16, 5), (16, 8, 0),
+              (128, 8, 0), (48, 10, 4), (20, 6, 0)]
     from paper_1705_08019_amd import FitError
     ran = 0
     for tw, ty, kc in shapes:
@@ -115,16 +115,33 @@ def test_pair_matches_oracle_fp64():
 def test_pair_tuning_errors():
     from paper_1705_08019_amd import FitGrid, FitError
     g = FitGrid(16, 16, 16, "f32")
-    for bad in ((64, 1, 0), (48, 3, 0), (16, 2, 0), (512, 4, 0), (64, 4, 0)):
+    for bad in ((64, 1, 0), (4, 8, 0), (512, 4, 0), (1024, 2, 0)):
         with pytest.raises(FitError, match="INVALID"):
             g.set_pair(True, *bad)
     with pytest.raises(FitError, match="INVALID"):
         g.set_pair(True, 64, 16, -1)
     g.set_pair(True)
-    assert g.get_pair()[:3] == (True, 64, 16)
+    assert g.get_pair()[:3] == (True, 64, 12)
     g.close()
     g = FitGrid(16, 16, 16, "f64")
     g.set_materials(np.ones(4096), None, np.full(4096, 0.1))
-    g.set_pair(True)                       # lossy FP64: 64 x 16 and 64 x 8 do not fit
+    g.set_pair(True)                       # lossy FP64: 64 x 12 and 64 x 8 do not fit
     assert g.get_pair()[:3] == (True, 32, 16)
     g.close()
+
+
+def test_autotune_with_pairs_keeps_the_result():
+    """The autotuner may switch pairs on; the state it leaves and the steps
+    taken afterwards equal plain single fused steps bitwise."""
+    n = (96, 80, 64)
+    g1, dt, _, _ = _grid(n, "f32", True)
+    g2, _, _, _ = _grid(n, "f32", True)
+    g2.autotune(dt, reps=2)
+    enabled, tw, ty, kc = g2.get_pair()
+    assert kc >= 1
+    for g in (g1, g2):
+        g.step(12, dt)
+    assert torch.equal(g1.get_fields()[0], g2.get_fields()[0])
+    assert torch.equal(g1.get_fields()[1], g2.get_fields()[1])
+    g1.close()
+    g2.close()
