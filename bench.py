@@ -8,10 +8,12 @@ z-current at the centre node (time width 20 steps), dt = 0.9 dt_CFL, FP64
 energies every 50 steps.  Inputs are synthetic and resident in HBM before
 the timed region starts.
 
-Prints ONE JSON line with the throughput (Gcell-updates/s), the roofline of
-the dominant kernel (algorithmic bytes / measured launch duration, HIP events
-on the library's stream), the oracle's CPU throughput on a bounded sample,
-and the batched / adjoint / Gram forms when available.
+The autotuner picks the kernel path and tile and, on the fused path, whether
+pairs of steps run as one launch (bitwise the same fields).  Prints ONE JSON
+line with the throughput (Gcell-updates/s), the roofline of the dominant
+kernel (algorithmic bytes / measured launch duration, HIP events on the
+library's stream), the oracle's CPU throughput on a bounded sample, and the
+batched / adjoint / Gram / ParaExp / graded-grid forms.
 
 Usage: python bench.py [--gpus 1] [--steps 2000] [--warmup 50]
 """
