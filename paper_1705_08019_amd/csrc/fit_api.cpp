@@ -433,6 +433,8 @@ static int pair_kc(const fit_grid* g, int tw, int ty) {
 
 static bool pair_now(const fit_grid* g, int64_t nleft) {
   if (nleft < 2 || !g->pair_on || !use_fused(g) || g->nu || g->probe.on) return false;
+  // the tile may no longer fit after the materials changed (lossless -> lossy)
+  if (!step2_shape_ok(g->ptw, g->pty, g->esz, g->lossy)) return false;
   const int64_t te = g->trace_every, m = g->m;
   if (te > 0 && (m % te == 0 || (m + 1) % te == 0 || (m + 2) % te == 0)) return false;
   return true;

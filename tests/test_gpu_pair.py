@@ -145,3 +145,20 @@ def test_autotune_with_pairs_keeps_the_result():
     assert torch.equal(g1.get_fields()[1], g2.get_fields()[1])
     g1.close()
     g2.close()
+
+
+def test_pair_tile_that_stops_fitting_falls_back_to_single_steps():
+    """A pair tile chosen for a lossless FP64 grid (64 x 8) does not fit once
+    the grid turns lossy; stepping then runs single fused steps."""
+    from paper_1705_08019_amd import FitGrid
+    n = (30, 20, 10)
+    g = FitGrid(*n, "f64")
+    g.set_materials(np.ones(6000))
+    g.set_pair(True, 64, 8, 0)
+    g.set_materials(np.ones(6000), None, np.full(6000, 0.1))
+    g.set_fields(np.random.default_rng(1).standard_normal((3, 10, 20, 30)), None, 0)
+    g.profile_begin(40)
+    g.step(6, 0.9 * g.cfl_dt())
+    prof = g.profile_end()
+    assert prof["pair"][1] == 0 and prof["step"][1] == 6
+    g.close()
