@@ -292,6 +292,24 @@ template int step_once<double>(fit_grid*, double, const double*, double*, const 
 
 // One fused leapfrog step m -> m+1: state read from (e, h), written to
 // (e_alt, h_alt), then the two sets swap roles.
+// Tensor-grid metric of the fused kernels: the per-axis arrays (squared
+// widths, widths, dual widths, reciprocal widths) and the dt scales.
+template <class Args>
+static void set_nu_args(const fit_grid* g, double dt, Args& a) {
+  const Dims& d = g->d;
+  const int nn[3] = {d.nx, d.ny, d.nz};
+  const int64_t tot = (int64_t)nn[0] + nn[1] + nn[2];
+  int64_t off = 0;
+  for (int c = 0; c < 3; ++c) {
+    a.nsq[c] = g->sq + off;
+    a.ndl[c] = g->sq + 2 * tot + off;
+    a.nrw[c] = g->sq + 3 * tot + off;
+    off += nn[c];
+  }
+  a.kbs = 4.0 * dt;
+  a.kds = dt;
+}
+
 template <typename T>
 int step_fused_io(fit_grid* g, double dt, const T* e0, const T* h0, T* e1, T* h1) {
   const int64_t m = g->m;
@@ -328,18 +346,11 @@ int step_fused_io(fit_grid* g, double dt, const T* e0, const T* h0, T* e1, T* h1
   a.hs = (T)(0.5 * dt);
   a.imu2 = (T)g->imu_value + (T)g->imu_value;
   if (g->nu) {
-    const int nn[3] = {d.nx, d.ny, d.nz};
-    const int64_t tot = (int64_t)nn[0] + nn[1] + nn[2];
-    int64_t off = 0;
-    for (int c = 0; c < 3; ++c) {
-      a.nsq[c] = g->sq + off;
-      a.nw[c] = g->sq + tot + off;
-      a.ndl[c] = g->sq + 2 * tot + off;
-      a.nrw[c] = g->sq + 3 * tot + off;
-      off += nn[c];
-    }
-    a.kbs = 4.0 * dt;
-    a.kds = dt;
+    set_nu_args(g, dt, a);
+    const int64_t tot = (int64_t)d.nx + d.ny + d.nz;
+    a.nw[0] = g->sq + tot;
+    a.nw[1] = a.nw[0] + d.nx;
+    a.nw[2] = a.nw[1] + d.ny;
   }
   a.src_comp = g->src_axis;
   a.src_idx = g->src_axis >= 0 ? g->src_idx : -1;
@@ -422,7 +433,7 @@ static int device_cus() {
 
 // Planes per chunk for one round of resident pair workgroups.
 static int pair_kc(const fit_grid* g, int tw, int ty) {
-  const size_t lds = step2_lds_bytes(tw, ty, g->esz, g->lossy);
+  const size_t lds = step2_lds_bytes(tw, ty, g->esz, g->lossy, 0);
   const int per_cu = std::max(1, std::min((int)((160 * 1024) / std::max<size_t>(lds, 1)),
                                           2048 / step2_threads(tw, ty)));
   const int64_t tiles = (int64_t)((g->d.nx + tw - 1) / tw) * ((g->d.ny + ty - 1) / ty);
@@ -431,10 +442,19 @@ static int pair_kc(const fit_grid* g, int tw, int ty) {
   return std::min(g->d.nz, std::max(k, std::min(8, g->d.nz)));
 }
 
+// Extra LDS planes of the tensor-grid pair kernel (z factors of the chunk
+// and its two halo planes), 0 on a uniform grid.
+static int pair_nu_planes(const fit_grid* g, int tw, int ty, int kc) {
+  return g->nu ? (kc > 0 ? kc : pair_kc(g, tw, ty)) + 3 : 0;
+}
+
 static bool pair_now(const fit_grid* g, int64_t nleft) {
-  if (nleft < 2 || !g->pair_on || !use_fused(g) || g->nu || g->probe.on) return false;
-  // the tile may no longer fit after the materials changed (lossless -> lossy)
-  if (!step2_shape_ok(g->ptw, g->pty, g->esz, g->lossy)) return false;
+  if (nleft < 2 || !g->pair_on || !use_fused(g) || g->probe.on) return false;
+  // the tile may no longer fit after the materials or spacing changed
+  // (lossless -> lossy, uniform -> tensor grid)
+  if (!step2_shape_ok(g->ptw, g->pty, g->esz, g->lossy,
+                      pair_nu_planes(g, g->ptw, g->pty, g->pkc)))
+    return false;
   const int64_t te = g->trace_every, m = g->m;
   if (te > 0 && (m % te == 0 || (m + 1) % te == 0 || (m + 2) % te == 0)) return false;
   return true;
@@ -470,6 +490,7 @@ static int step_pair(fit_grid* g, double dt) {
   a.src_idx = g->src_axis >= 0 ? g->src_idx : -1;
   a.src_val[0] = (T)(g->src_axis >= 0 ? source_value(g, dt, g->m) : 0.0);
   a.src_val[1] = (T)(g->src_axis >= 0 ? source_value(g, dt, g->m + 1) : 0.0);
+  if (g->nu) set_nu_args(g, dt, a);
   hipError_t e;
   {
     ProfScope ps(g, FIT_PROF_PAIR);
@@ -1266,13 +1287,14 @@ int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* tw, int* ty, 
   if (rc) return rc;
   // two steps per launch: take it when a pair beats two single steps
   g->pair_on = 0;
-  if (use_fused(g) && !g->nu && g->d.nz >= 2) {
+  if (use_fused(g) && g->d.nz >= 2) {
     const int shapes[4][2] = {{32, 16}, {64, 8}, {32, 8}, {48, 8}};
     float best_pair = 1e30f;
     int bw = 0, bt = 0, bk = 0;
     for (const auto& sh : shapes) {
-      if (!step2_shape_ok(sh[0], sh[1], g->esz, g->lossy)) continue;
       const int k0 = pair_kc(g, sh[0], sh[1]);
+      if (!step2_shape_ok(sh[0], sh[1], g->esz, g->lossy, pair_nu_planes(g, sh[0], sh[1], k0)))
+        continue;
       const int kcs[2] = {k0, std::max(std::min(8, g->d.nz), k0 / 2)};
       for (int q = 0; q < 2; ++q) {
         if (q == 1 && kcs[1] == kcs[0]) continue;

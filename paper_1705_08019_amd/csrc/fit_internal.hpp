@@ -166,14 +166,20 @@ struct S2Args {
   int src_comp;
   int64_t src_idx;
   T src_val[2];
+  // tensor grid (null otherwise): as in SArgs
+  const double* nsq[3] = {nullptr, nullptr, nullptr};
+  const double* ndl[3] = {nullptr, nullptr, nullptr};
+  const double* nrw[3] = {nullptr, nullptr, nullptr};
+  double kbs = 0.0, kds = 0.0;
 };
-size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy);
+// nu_planes: z-chunk planes + 3 on a tensor grid (per-plane metric in LDS), else 0.
+size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy, int nu_planes);
 // Threads of a pair workgroup: enough for one e^(m+1) point each (the
 // largest region), a multiple of 64, at most 1024.
 int step2_threads(int tw, int ty);
 // Tile shapes the two-step kernel takes: tw ty a multiple of 64, <= 1024,
 // the staged regions within kS2Per entries per thread, LDS <= 160 KiB.
-bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy);
+bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, int nu_planes = 0);
 template <typename T>
 hipError_t launch_step2(const S2Args<T>& a, bool lossy, hipStream_t s);
 

@@ -42,10 +42,11 @@ __host__ __device__ inline S2Geom s2_geom(int tw, int ty) {
   return g;
 }
 
-size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy) {
+size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy, int nu_planes) {
   const S2Geom g = s2_geom(tw, ty);
   const size_t n = 6 * (size_t)g.N4 + 3 * (size_t)g.N4 + (lossy ? 3 * (size_t)g.N4 : 0) +
-                   6 * (size_t)g.N1 + 6 * (size_t)g.N2 + 6 * (size_t)g.N3;
+                   6 * (size_t)g.N1 + 6 * (size_t)g.N2 + 6 * (size_t)g.N3 +
+                   3 * (size_t)nu_planes;
   return esz * n;
 }
 
@@ -54,16 +55,19 @@ int step2_threads(int tw, int ty) {
   return (g.N1 + 63) / 64 * 64;
 }
 
-bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy) {
+bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, int nu_planes) {
   if (tw < 8 || ty < 2) return false;
   const S2Geom g = s2_geom(tw, ty);
   const int nthr = step2_threads(tw, ty);   // one thread per point of the largest computed region
   if (nthr > 1024 || g.N4 > kS2Per * nthr) return false;
-  return step2_lds_bytes(tw, ty, esz, lossy) <= 160 * 1024;
+  return step2_lds_bytes(tw, ty, esz, lossy, nu_planes) <= 160 * 1024;
 }
 
-template <typename T, bool LOSSY>
-__global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
+// FP32: at most 80 VGPRs (6 waves per SIMD), so that two workgroups of the
+// 32 x 16 tile (11 waves each) are resident per CU.
+template <typename T, bool LOSSY, bool NU>
+__global__ __launch_bounds__(1024)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   const Dims d = A.d;
@@ -80,6 +84,7 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
   T* e1L = sL + (LOSSY ? 3 * G.N4 : 0);       // [2][3][N1]   e^(m+1), planes k, k-1
   T* h1L = e1L + 6 * G.N1;                    // [2][3][N2]   h^(m+3/2), planes k-1, k-2
   T* e2L = h1L + 6 * G.N2;                    // [2][3][N3]   e^(m+2), planes k-1, k-2
+  T* zL = e2L + 6 * G.N3;                     // tensor grid: [3][kc + 3] per-plane factors
 
   const int i0 = tx * TW, j0 = tyi * TY;
   const int k0 = kz * A.t.kc;
@@ -137,6 +142,35 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
   const int64_t g5 = own5 ? (i0 + x5) + sx * (j0 + y5) : 0;
   const int e5 = i3(x5, y5), e5in = i3(x5 + 1, y5), e5jn = i3(x5, y5 + 1), h5 = i2(x5, y5);
 
+  // ---- tensor-grid metric (as in the single fused step): x / y factors of
+  // each thread's points, z factors of planes k0 - 1 .. k1 + 1 staged in LDS
+  T kb1x = A.kb[0], kb1y = A.kb[1], kb3x = A.kb[0], kb3y = A.kb[1];
+  T kd2x = 0, kd2y = 0, kd2z = 0, kd5x = 0, kd5y = 0, kd5z = 0;
+  const int zp = A.t.kc + 3;
+  if (NU) {
+    auto cx = [&](int gx) { return min(max(gx, 0), d.nx - 1); };
+    auto cy = [&](int gy) { return min(max(gy, 0), d.ny - 1); };
+    kb1x = (T)(A.kbs * A.nsq[0][cx(gx1)]);
+    kb1y = (T)(A.kbs * A.nsq[1][cy(gy1)]);
+    kb3x = (T)(A.kbs * A.nsq[0][cx(gx3)]);
+    kb3y = (T)(A.kbs * A.nsq[1][cy(gy3)]);
+    const int ix2 = cx(i0 + x2), jy2 = cy(j0 + y2), ix5 = cx(i0 + x5), jy5 = cy(j0 + y5);
+    kd2x = (T)(A.kds * (0.5 * A.ndl[0][ix2] * A.nrw[1][jy2]));
+    kd2y = (T)(A.kds * (0.5 * A.ndl[1][jy2] * A.nrw[0][ix2]));
+    kd2z = (T)(A.kds * (0.5 * A.nrw[0][ix2] * A.nrw[1][jy2]));
+    kd5x = (T)(A.kds * (0.5 * A.ndl[0][ix5] * A.nrw[1][jy5]));
+    kd5y = (T)(A.kds * (0.5 * A.ndl[1][jy5] * A.nrw[0][ix5]));
+    kd5z = (T)(A.kds * (0.5 * A.nrw[0][ix5] * A.nrw[1][jy5]));
+    for (int q = tid; q < zp; q += nthr) {
+      const int kk = k0 - 1 + q;
+      const bool in = kk >= 0 && kk < d.nz;
+      zL[q] = in ? (T)(A.kbs * A.nsq[2][kk]) : T(0);
+      zL[zp + q] = in ? (T)A.nrw[2][kk] : T(0);
+      zL[2 * zp + q] = in ? (T)A.ndl[2][kk] : T(0);
+    }
+  }
+  auto zi = [&](int k) { return k - (k0 - 1); };   // z-factor slot of plane k
+
   // ---- register staging of plane k: X4 entries (h x3, eps, sigma), R1 entry (e x3)
   T ph[kS2Per][5];
   T pe[3];
@@ -182,8 +216,8 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
   // single-step kernels.
   auto e_upd = [&](bool valid, int gi, int gj, int64_t g, int k, const T* hp, const T* hq, int NH,
                    int rh, int rh_im, int rh_jm, int r, int rim, int rjm, int rijm, const T* cp,
-                   const T* cq, const T* sp, const T* sq, T exo, T eyo, T ezo, T src, T& exn,
-                   T& eyn, T& ezn) {
+                   const T* cq, const T* sp, const T* sq, T exo, T eyo, T ezo, T src, T kbx_,
+                   T kby_, T kbz_, T& exn, T& eyn, T& ezn) {
     const T c = cp[r], c_im = cp[rim], c_jm = cp[rjm], c_ijm = cp[rijm];
     const T Sx = c + c_im, Sy = c + c_jm, Sxj = c_jm + c_ijm;
     const T pc = cq[r];
@@ -209,8 +243,8 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
     e_point<T, LOSSY>(hp[rh], hp[NH + rh], hp[2 * NH + rh], hq[rh], hq[NH + rh], hp[rh_jm],
                       hp[NH + rh_im], hp[2 * NH + rh_jm], hp[2 * NH + rh_im], E4x, E4y, E4z,
                       S4x, S4y, S4z, exo, eyo, ezo, jx, jy, jz, valid && gj > 0 && k > 0,
-                      valid && gi > 0 && k > 0, valid && gi > 0 && gj > 0, A.kb[0], A.kb[1],
-                      A.kb[2], A.hs, exn, eyn, ezn);
+                      valid && gi > 0 && k > 0, valid && gi > 0 && gj > 0, kbx_, kby_, kbz_,
+                      A.hs, exn, eyn, ezn);
   };
 
   // prologue: plane k0 - 2 staged, plane k0 - 1 in flight
@@ -231,7 +265,7 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
       e_upd(in1 && kin, gx1, gy1, g1 + sxy * (int64_t)k, k, h0L + hb(k) * 3 * G.N4,
             h0L + hb(k - 1) * 3 * G.N4, G.N4, r1, r1im, r1jm, r1, r1im, r1jm, r1ijm,
             cL + cb(k) * G.N4, cL + cb(k - 1) * G.N4, sL + cb(k) * G.N4, sL + cb(k - 1) * G.N4,
-            e0x, e0y, e0z, A.src_val[0], exn, eyn, ezn);
+            e0x, e0y, e0z, A.src_val[0], kb1x, kb1y, NU ? zL[zi(k)] : A.kb[2], exn, eyn, ezn);
       T* out = e1L + hb(k) * 3 * G.N1;
       out[tid] = exn;
       out[G.N1 + tid] = eyn;
@@ -246,11 +280,18 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
       const T* np_ = e1L + hb(k) * 3 * G.N1;
       const T* ho = h0L + hb(km) * 3 * G.N4;
       const bool valid = in2 && km >= 0 && km < d.nz;
+      T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
+      if (NU) {
+        const T rz = zL[zp + zi(km)];
+        kdx = kd2x * rz;
+        kdy = kd2y * rz;
+        kdz = kd2z * zL[2 * zp + zi(km)];
+      }
       T hxn, hyn, hzn;
       h_point<T>(nq[e2c], nq[G.N1 + e2c], nq[2 * G.N1 + e2c], np_[e2c], np_[G.N1 + e2c],
                  nq[2 * G.N1 + e2jn], nq[2 * G.N1 + e2in], nq[G.N1 + e2in], nq[e2jn], ho[r2h],
                  ho[G.N4 + r2h], ho[2 * G.N4 + r2h], A.imu2, A.imu2, A.imu2, valid && px2,
-                 valid && py2, valid && km > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
+                 valid && py2, valid && km > 0, kdx, kdy, kdz, hxn, hyn, hzn);
       T* out = h1L + hb(km) * 3 * G.N2;
       out[tid] = hxn;
       out[G.N2 + tid] = hyn;
@@ -268,7 +309,8 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
       e_upd(in3 && kin, gx3, gy3, g, km, h1L + hb(km) * 3 * G.N2, h1L + hb(km - 1) * 3 * G.N2,
             G.N2, h3, h3im, h3jm, r3, r3im, r3jm, r3ijm, cL + cb(km) * G.N4,
             cL + cb(km - 1) * G.N4, sL + cb(km) * G.N4, sL + cb(km - 1) * G.N4, eo[o3],
-            eo[G.N1 + o3], eo[2 * G.N1 + o3], A.src_val[1], exn, eyn, ezn);
+            eo[G.N1 + o3], eo[2 * G.N1 + o3], A.src_val[1], kb3x, kb3y,
+            NU ? zL[zi(km)] : A.kb[2], exn, eyn, ezn);
       T* out = e2L + hb(km) * 3 * G.N3;
       out[tid] = exn;
       out[G.N3 + tid] = eyn;
@@ -287,11 +329,18 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
       const T* nq = e2L + hb(kh) * 3 * G.N3;
       const T* np_ = e2L + hb(kh + 1) * 3 * G.N3;
       const T* ho = h1L + hb(kh) * 3 * G.N2;
+      T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
+      if (NU) {
+        const T rz = zL[zp + zi(kh)];
+        kdx = kd5x * rz;
+        kdy = kd5y * rz;
+        kdz = kd5z * zL[2 * zp + zi(kh)];
+      }
       T hxn, hyn, hzn;
       h_point<T>(nq[e5], nq[G.N3 + e5], nq[2 * G.N3 + e5], np_[e5], np_[G.N3 + e5],
                  nq[2 * G.N3 + e5jn], nq[2 * G.N3 + e5in], nq[G.N3 + e5in], nq[e5jn], ho[h5],
                  ho[G.N2 + h5], ho[2 * G.N2 + h5], A.imu2, A.imu2, A.imu2, i0 + x5 > 0,
-                 j0 + y5 > 0, kh > 0, A.kd[0], A.kd[1], A.kd[2], hxn, hyn, hzn);
+                 j0 + y5 > 0, kh > 0, kdx, kdy, kdz, hxn, hyn, hzn);
       const int64_t g = g5 + sxy * (int64_t)kh;
       gst(A.h2[0], g, hxn);
       gst(A.h2[1], g, hyn);
@@ -300,27 +349,28 @@ __global__ __launch_bounds__(1024) void k_step2(S2Args<T> A) {
   }
 }
 
+template <typename T, bool L, bool N>
+static hipError_t go_step2(const S2Args<T>& a, dim3 grd, dim3 blk, size_t lds, hipStream_t s) {
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step2<T, L, N>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_step2<T, L, N>), grd, blk, lds, s, a);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_step2(const S2Args<T>& a, bool lossy, hipStream_t s) {
-  if (!step2_shape_ok(a.t.tw, a.t.ty, sizeof(T), lossy)) return hipErrorInvalidValue;
+  const bool nu = a.nsq[0] != nullptr;
+  const int nup = nu ? a.t.kc + 3 : 0;
+  if (!step2_shape_ok(a.t.tw, a.t.ty, sizeof(T), lossy, nup)) return hipErrorInvalidValue;
   const dim3 blk(step2_threads(a.t.tw, a.t.ty)), grd((unsigned)a.t.blocks());
-  const size_t lds = step2_lds_bytes(a.t.tw, a.t.ty, sizeof(T), lossy);
-  if (lossy) {
-    if (lds > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step2<T, true>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_step2<T, true>), grd, blk, lds, s, a);
-  } else {
-    if (lds > 64 * 1024) {
-      hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step2<T, false>),
-                                         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-      if (e != hipSuccess) return e;
-    }
-    hipLaunchKernelGGL((k_step2<T, false>), grd, blk, lds, s, a);
-  }
-  return hipGetLastError();
+  const size_t lds = step2_lds_bytes(a.t.tw, a.t.ty, sizeof(T), lossy, nup);
+  if (lossy) return nu ? go_step2<T, true, true>(a, grd, blk, lds, s)
+                       : go_step2<T, true, false>(a, grd, blk, lds, s);
+  return nu ? go_step2<T, false, true>(a, grd, blk, lds, s)
+            : go_step2<T, false, false>(a, grd, blk, lds, s);
 }
 
 template hipError_t launch_step2<float>(const S2Args<float>&, bool, hipStream_t);

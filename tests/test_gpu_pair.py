@@ -162,3 +162,73 @@ def test_pair_tile_that_stops_fitting_falls_back_to_single_steps():
     prof = g.profile_end()
     assert prof["pair"][1] == 0 and prof["step"][1] == 6
     g.close()
+
+
+def _graded(n, dtype, lossy, seed=11):
+    from paper_1705_08019_amd import FitGrid
+    nx, ny, nz = n
+    rng = np.random.default_rng(seed)
+    wd = [rng.uniform(0.3, 1.7, k) for k in n]
+    eps = dielectric_blocks(nx, ny, nz, 5, seed)
+    sig = lossy_slab(nx, ny, nz, 1, 0.2) if lossy else None
+    mu = np.full((nz, ny, nx), 1.3)
+    g = FitGrid(nx, ny, nz, dtype, spacing=wd)
+    g.set_materials(eps, mu, sig)
+    g.set_fields(rng.standard_normal((3, nz, ny, nx)), rng.standard_normal((3, nz, ny, nx)), 0)
+    dt = 0.9 * g.cfl_dt()
+    g.set_source(2, nx // 2, ny // 2, nz // 2, 1.0, 4 * dt)
+    g.set_tuning("fused")
+    return g, dt, (wd, eps, mu, sig)
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("n,lossy", [((70, 33, 21), True), ((13, 9, 7), False),
+                                     ((40, 40, 1), False), ((9, 70, 2), True)])
+def test_graded_pair_is_bitwise_two_single_steps(dtype, n, lossy):
+    """Tensor grids: the pair kernel uses the single fused step's per-axis
+    metric factors in the same arithmetic, chunk boundaries included."""
+    from paper_1705_08019_amd import FitError
+    steps = 10
+    g, dt, _ = _graded(n, dtype, lossy)
+    g.profile_begin(4 * steps + 8)
+    g.step(steps, dt)
+    assert g.profile_end()["pair"][1] == 0
+    ref = [x.clone() for x in g.get_fields()]
+    g.close()
+    ran = 0
+    for tw, ty, kc in [(32, 16, 0), (64, 8, 1), (32, 8, 2), (16, 8, 5), (48, 10, 3)]:
+        g, _, _ = _graded(n, dtype, lossy)
+        try:
+            g.set_pair(True, tw, ty, kc)
+        except FitError:
+            g.close()
+            continue
+        print(f"graded pair {dtype} {n} lossy={lossy} tile {tw}x{ty} kc={kc}", flush=True)
+        g.profile_begin(4 * steps + 8)
+        g.step(steps, dt)
+        prof = g.profile_end()
+        e, h = g.get_fields()
+        assert prof["pair"][1] == steps // 2, (tw, ty, kc)
+        assert torch.equal(e, ref[0]), (tw, ty, kc)
+        assert torch.equal(h, ref[1]), (tw, ty, kc)
+        g.close()
+        ran += 1
+    assert ran >= 3
+
+
+def test_graded_pair_matches_oracle_fp64():
+    n = (37, 22, 15)
+    g, dt, (wd, eps, mu, sig) = _graded(n, "f64", True)
+    g.set_pair(True, 32, 16, 4)
+    e0, h0 = (to_np(x) for x in g.get_fields())
+    ops = oracle_ops(n, eps=eps, sigma=sig, mu=mu, spacing=wd)
+    nx, ny, nz = n
+    src = dict(axis=2, i=nx // 2, j=ny // 2, k=nz // 2, i_max=1.0, sigma_t=4 * dt)
+    g.profile_begin(40)
+    g.step(20, dt)
+    assert g.profile_end()["pair"][1] == 10
+    e, h = g.get_fields()
+    eN, hN, _ = run(ops, edges_from_slots(ops, e0), facets_from_slots(ops, h0), dt, 20, src)
+    assert rel_l2(edges_from_slots(ops, to_np(e)), eN) <= 1e-12
+    assert rel_l2(facets_from_slots(ops, to_np(h)), hN) <= 1e-12
+    g.close()
