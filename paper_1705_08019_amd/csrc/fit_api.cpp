@@ -450,6 +450,7 @@ static int pair_nu_planes(const fit_grid* g, int tw, int ty, int kc) {
 
 static bool pair_now(const fit_grid* g, int64_t nleft) {
   if (nleft < 2 || !g->pair_on || !use_fused(g) || g->probe.on) return false;
+  if (!step2_plane_ok(g->d, g->esz)) return false;
   // the tile may no longer fit after the materials or spacing changed
   // (lossless -> lossy, uniform -> tensor grid)
   if (!step2_shape_ok(g->ptw, g->pty, g->esz, g->lossy,

@@ -180,6 +180,9 @@ int step2_threads(int tw, int ty);
 // Tile shapes the two-step kernel takes: tw ty a multiple of 64, <= 1024,
 // the staged regions within kS2Per entries per thread, LDS <= 160 KiB.
 bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, int nu_planes = 0);
+// In-plane byte offsets of the two-step kernel are 32-bit: a plane of the
+// slot layout must span at most 4 GiB.
+bool step2_plane_ok(const Dims& d, size_t esz);
 template <typename T>
 hipError_t launch_step2(const S2Args<T>& a, bool lossy, hipStream_t s);
 

@@ -9,6 +9,23 @@
 
 namespace fit {
 
+// Quotient a / b of the e-update coefficients (b > 0, a normal number).
+// FP32: the hardware reciprocal (1 ulp) and one Newton correction of the
+// quotient, q = a r, q + r (a - b q) (Markstein's refinement): within 1 ulp
+// of a / b in 4 instructions, against about 10 for the IEEE sequence with
+// its scaling and denormal-mode switches.  FP64: the IEEE division.
+template <typename T>
+__device__ __forceinline__ T qdiv(T a, T b) {
+  return a / b;
+}
+template <>
+__device__ __forceinline__ float qdiv<float>(float a, float b) {
+#pragma clang fp contract(off)
+  const float r = __builtin_amdgcn_rcpf(b);
+  const float q = a * r;
+  return fmaf(fmaf(-b, q, a), r, q);
+}
+
 // e-update of the three primal edges leaving one node (Sec. II-A):
 //   e^(m+1) = ca e^m + cb (C~ h^(m+1/2) - j_s)
 // with S4eps (E4*) and S4sig (S4*) the sums over the 4 cells around each edge,
@@ -31,13 +48,13 @@ __device__ __forceinline__ void e_point(T hxc, T hyc, T hzc, T hxp, T hyp, T hx_
     const T dpx = fma(hs, S4x, E4x), dmx = fma(-hs, S4x, E4x);
     const T dpy = fma(hs, S4y, E4y), dmy = fma(-hs, S4y, E4y);
     const T dpz = fma(hs, S4z, E4z), dmz = fma(-hs, S4z, E4z);
-    nx_ = fma(dmx, exo, kbx * cx) / dpx;
-    ny_ = fma(dmy, eyo, kby * cy) / dpy;
-    nz_ = fma(dmz, ezo, kbz * cz) / dpz;
+    nx_ = qdiv(fma(dmx, exo, kbx * cx), dpx);
+    ny_ = qdiv(fma(dmy, eyo, kby * cy), dpy);
+    nz_ = qdiv(fma(dmz, ezo, kbz * cz), dpz);
   } else {
-    nx_ = exo + (kbx * cx) / E4x;
-    ny_ = eyo + (kby * cy) / E4y;
-    nz_ = ezo + (kbz * cz) / E4z;
+    nx_ = exo + qdiv(kbx * cx, E4x);
+    ny_ = eyo + qdiv(kby * cy, E4y);
+    nz_ = ezo + qdiv(kbz * cz, E4z);
   }
   exn = lx ? nx_ : T(0);
   eyn = ly ? ny_ : T(0);

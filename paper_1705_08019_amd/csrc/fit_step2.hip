@@ -50,6 +50,10 @@ size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy, int nu_planes) {
   return esz * n;
 }
 
+bool step2_plane_ok(const Dims& d, size_t esz) {
+  return (uint64_t)d.sxy * esz <= (uint64_t)UINT32_MAX;
+}
+
 int step2_threads(int tw, int ty) {
   const S2Geom g = s2_geom(tw, ty);
   return (g.N1 + 63) / 64 * 64;
@@ -63,9 +67,35 @@ bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, int nu_planes) {
   return step2_lds_bytes(tw, ty, esz, lossy, nu_planes) <= 160 * 1024;
 }
 
+// Global access at a wave-uniform plane base plus a per-thread 32-bit byte
+// offset within the plane (the launchers check that a plane spans < 4 GiB):
+// the scalar-base + 32-bit-offset addressing of the global instructions, so
+// that no 64-bit vector address is formed per access.  `fresh` marks a
+// loop-invariant offset as redefined inside the z-march (an empty asm, once
+// per plane); otherwise its zero-extension is hoisted out of the loop and the
+// 64-bit form returns.
+__device__ __forceinline__ uint32_t fresh(uint32_t off) {
+  asm volatile("" : "+v"(off));
+  return off;
+}
+template <typename T>
+__device__ __forceinline__ T pld(const T* base, uint32_t off) {
+  using C1 = const __attribute__((address_space(1))) char;
+  using T1 = const __attribute__((address_space(1))) T;
+  return *(T1*)((C1*)base + off);
+}
+template <typename T>
+__device__ __forceinline__ void pst(T* base, uint32_t off, T v) {
+  using C1 = __attribute__((address_space(1))) char;
+  using T1 = __attribute__((address_space(1))) T;
+  *(T1*)((C1*)base + off) = v;
+}
+
 // FP32: at most 80 VGPRs (6 waves per SIMD), so that two workgroups of the
-// 32 x 16 tile (11 waves each) are resident per CU.
-template <typename T, bool LOSSY, bool NU>
+// 32 x 16 tile (11 waves each) are resident per CU.  CTW, CTY > 0 fix the
+// tile at compile time (every LDS offset an immediate), 0 takes it from the
+// tiling.
+template <typename T, bool LOSSY, bool NU, int CTW, int CTY>
 __global__ __launch_bounds__(1024)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
@@ -76,7 +106,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
   const int64_t rr = lt / A.t.ntx;
   const int tyi = (int)(rr % A.t.nty);
   const int kz = (int)(rr / A.t.nty);
-  const int TW = A.t.tw, TY = A.t.ty;
+  const int TW = CTW > 0 ? CTW : A.t.tw, TY = CTY > 0 ? CTY : A.t.ty;
   const S2Geom G = s2_geom(TW, TY);
   T* h0L = sm;                                // [2][3][N4]   h^(m+1/2), planes k, k-1
   T* cL = h0L + 6 * G.N4;                     // [3][N4]      eps0 eps_r, planes k, k-1, k-2
@@ -101,46 +131,52 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
   auto i3 = [&](int x, int y) { return y * G.W3 + x; };
   auto in_grid = [&](int gx, int gy) { return gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny; };
 
-  // ---- per-thread points of every region (fixed over the z-march)
+  // ---- per-thread points of every region (fixed over the z-march); grid
+  // points as in-plane element indices p (gx + sx gy); LDS neighbours as
+  // constant offsets from the point's own index (-1: x - 1, -W: y - 1)
+  // source point: plane sk, in-plane index sp (none: sk = -1)
+  const int64_t sk = A.src_idx >= 0 ? A.src_idx / sxy : -100;   // k >= -1 in the march
+  const uint32_t sp = (uint32_t)(A.src_idx - (sk >= 0 ? sk * sxy : A.src_idx));
+  constexpr uint32_t ES = sizeof(T);
   // X4 staging entries (up to kS2Per per thread)
-  int64_t g4[kS2Per];
+  uint32_t o4[kS2Per];
   bool in4[kS2Per];
 #pragma unroll
   for (int r = 0; r < kS2Per; ++r) {
     const int q = tid + r * nthr;
     const int gx = i0 + (q % G.W4) - 2, gy = j0 + (q / G.W4) - 2;
     in4[r] = q < G.N4 && in_grid(gx, gy);
-    g4[r] = in4[r] ? gx + sx * gy : 0;
+    o4[r] = in4[r] ? (uint32_t)(gx + sx * gy) * ES : 0u;
   }
   // R1 point (e^(m+1)): one per thread
   const bool a1 = tid < G.N1;
   const int x1 = tid % G.W1 - 1, y1 = tid / G.W1 - 1;
   const int gx1 = i0 + x1, gy1 = j0 + y1;
   const bool in1 = a1 && in_grid(gx1, gy1);
-  const int64_t g1 = in1 ? gx1 + sx * gy1 : 0;
-  const int r1 = i4(x1, y1), r1im = i4(x1 - 1, y1), r1jm = i4(x1, y1 - 1),
-            r1ijm = i4(x1 - 1, y1 - 1);
+  const uint32_t p1 = in1 ? (uint32_t)(gx1 + sx * gy1) : 0u;
+  const bool s1 = in1 && p1 == sp;
+  const int r1 = i4(x1, y1), r1im = r1 - 1, r1jm = r1 - G.W4, r1ijm = r1jm - 1;
   // R2 point (h^(m+3/2))
   const bool a2 = tid < G.N2;
   const int x2 = tid % G.W2 - 1, y2 = tid / G.W2 - 1;
   const bool in2 = a2 && in_grid(i0 + x2, j0 + y2);
   const bool px2 = in2 && i0 + x2 > 0, py2 = in2 && j0 + y2 > 0;
-  const int e2c = i1(x2, y2), e2in = i1(x2 + 1, y2), e2jn = i1(x2, y2 + 1), r2h = i4(x2, y2);
+  const int e2c = i1(x2, y2), e2in = e2c + 1, e2jn = e2c + G.W1, r2h = i4(x2, y2);
   // R3 point (e^(m+2))
   const bool a3 = tid < G.N3;
   const int x3 = tid % G.W3, y3 = tid / G.W3;
   const int gx3 = i0 + x3, gy3 = j0 + y3;
   const bool in3 = a3 && in_grid(gx3, gy3);
   const bool own3 = in3 && x3 < TW && y3 < TY;
-  const int64_t g3 = in3 ? gx3 + sx * gy3 : 0;
-  const int r3 = i4(x3, y3), r3im = i4(x3 - 1, y3), r3jm = i4(x3, y3 - 1),
-            r3ijm = i4(x3 - 1, y3 - 1);
-  const int h3 = i2(x3, y3), h3im = i2(x3 - 1, y3), h3jm = i2(x3, y3 - 1), o3 = i1(x3, y3);
+  const uint32_t p3 = in3 ? (uint32_t)(gx3 + sx * gy3) : 0u;
+  const bool s3 = in3 && p3 == sp;
+  const int r3 = i4(x3, y3), r3im = r3 - 1, r3jm = r3 - G.W4, r3ijm = r3jm - 1;
+  const int h3 = i2(x3, y3), h3im = h3 - 1, h3jm = h3 - G.W2, o3 = i1(x3, y3);
   // tile point (h^(m+5/2))
   const int x5 = tid % TW, y5 = tid / TW;
   const bool own5 = tid < TW * TY && in_grid(i0 + x5, j0 + y5);
-  const int64_t g5 = own5 ? (i0 + x5) + sx * (j0 + y5) : 0;
-  const int e5 = i3(x5, y5), e5in = i3(x5 + 1, y5), e5jn = i3(x5, y5 + 1), h5 = i2(x5, y5);
+  const uint32_t p5 = own5 ? (uint32_t)((i0 + x5) + sx * (j0 + y5)) : 0u;
+  const int e5 = i3(x5, y5), e5in = e5 + 1, e5jn = e5 + G.W3, h5 = i2(x5, y5);
 
   // ---- tensor-grid metric (as in the single fused step): x / y factors of
   // each thread's points, z factors of planes k0 - 1 .. k1 + 1 staged in LDS
@@ -176,22 +212,24 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
   T pe[3];
   auto fetch = [&](int k) {
     const bool plane = k >= 0 && k < d.nz;
-    const int64_t gk = sxy * (int64_t)k;
+    const int64_t gk = plane ? sxy * (int64_t)k : 0;
+    const T *bh0 = A.h0[0] + gk, *bh1 = A.h0[1] + gk, *bh2 = A.h0[2] + gk;
+    const T *bc = A.eps + gk, *bs = LOSSY ? A.sig + gk : nullptr;
 #pragma unroll
     for (int r = 0; r < kS2Per; ++r) {
       const bool in = plane && in4[r];
-      const int64_t g = g4[r] + (in ? gk : 0);
-      ph[r][0] = in ? gld(A.h0[0], g) : T(0);
-      ph[r][1] = in ? gld(A.h0[1], g) : T(0);
-      ph[r][2] = in ? gld(A.h0[2], g) : T(0);
-      ph[r][3] = in ? gld(A.eps, g) : T(0);
-      ph[r][4] = (LOSSY && in) ? gld(A.sig, g) : T(0);
+      const uint32_t o = fresh(o4[r]);
+      ph[r][0] = in ? pld(bh0, o) : T(0);
+      ph[r][1] = in ? pld(bh1, o) : T(0);
+      ph[r][2] = in ? pld(bh2, o) : T(0);
+      ph[r][3] = in ? pld(bc, o) : T(0);
+      ph[r][4] = (LOSSY && in) ? pld(bs, o) : T(0);
     }
     const bool in = plane && in1;
-    const int64_t g = g1 + (in ? gk : 0);
-    pe[0] = in ? gld(A.e0[0], g) : T(0);
-    pe[1] = in ? gld(A.e0[1], g) : T(0);
-    pe[2] = in ? gld(A.e0[2], g) : T(0);
+    const uint32_t o = fresh(p1 * ES);
+    pe[0] = in ? pld(A.e0[0] + gk, o) : T(0);
+    pe[1] = in ? pld(A.e0[1] + gk, o) : T(0);
+    pe[2] = in ? pld(A.e0[2] + gk, o) : T(0);
   };
   auto stage = [&](int k) {
     T* h = h0L + hb(k) * 3 * G.N4;
@@ -214,7 +252,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
   // stride NH and indices (rh, rh_im, rh_jm); materials of planes k, k-1 in
   // the X4 layout at (r, rim, rjm, rijm); same operand order as the
   // single-step kernels.
-  auto e_upd = [&](bool valid, int gi, int gj, int64_t g, int k, const T* hp, const T* hq, int NH,
+  auto e_upd = [&](bool valid, int gi, int gj, bool at_src, int k, const T* hp, const T* hq, int NH,
                    int rh, int rh_im, int rh_jm, int r, int rim, int rjm, int rijm, const T* cp,
                    const T* cq, const T* sp, const T* sq, T exo, T eyo, T ezo, T src, T kbx_,
                    T kby_, T kbz_, T& exn, T& eyn, T& ezn) {
@@ -234,7 +272,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
       S4z = Sxs + (s_jm + s_ijm);
     }
     T jx = 0, jy = 0, jz = 0;
-    if (valid && g == A.src_idx) {
+    if (valid && at_src) {
       if (A.src_comp == 0) jx = src;
       if (A.src_comp == 1) jy = src;
       if (A.src_comp == 2) jz = src;
@@ -262,7 +300,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
     if (a1) {
       const bool kin = k >= 0 && k < d.nz;
       T exn, eyn, ezn;
-      e_upd(in1 && kin, gx1, gy1, g1 + sxy * (int64_t)k, k, h0L + hb(k) * 3 * G.N4,
+      e_upd(in1 && kin, gx1, gy1, s1 && k == sk, k, h0L + hb(k) * 3 * G.N4,
             h0L + hb(k - 1) * 3 * G.N4, G.N4, r1, r1im, r1jm, r1, r1im, r1jm, r1ijm,
             cL + cb(k) * G.N4, cL + cb(k - 1) * G.N4, sL + cb(k) * G.N4, sL + cb(k - 1) * G.N4,
             e0x, e0y, e0z, A.src_val[0], kb1x, kb1y, NU ? zL[zi(k)] : A.kb[2], exn, eyn, ezn);
@@ -304,9 +342,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
     if (km >= k0 && a3) {
       const T* eo = e1L + hb(km) * 3 * G.N1;
       const bool kin = km >= 0 && km < d.nz;
-      const int64_t g = g3 + sxy * (int64_t)km;
       T exn, eyn, ezn;
-      e_upd(in3 && kin, gx3, gy3, g, km, h1L + hb(km) * 3 * G.N2, h1L + hb(km - 1) * 3 * G.N2,
+      e_upd(in3 && kin, gx3, gy3, s3 && km == sk, km, h1L + hb(km) * 3 * G.N2, h1L + hb(km - 1) * 3 * G.N2,
             G.N2, h3, h3im, h3jm, r3, r3im, r3jm, r3ijm, cL + cb(km) * G.N4,
             cL + cb(km - 1) * G.N4, sL + cb(km) * G.N4, sL + cb(km - 1) * G.N4, eo[o3],
             eo[G.N1 + o3], eo[2 * G.N1 + o3], A.src_val[1], kb3x, kb3y,
@@ -316,9 +353,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
       out[G.N3 + tid] = eyn;
       out[2 * G.N3 + tid] = ezn;
       if (own3 && km < k1) {
-        gst(A.e2[0], g, exn);
-        gst(A.e2[1], g, eyn);
-        gst(A.e2[2], g, ezn);
+        const int64_t gk = sxy * (int64_t)km;
+        const uint32_t o = fresh(p3 * ES);
+        pst(A.e2[0] + gk, o, exn);
+        pst(A.e2[1] + gk, o, eyn);
+        pst(A.e2[2] + gk, o, ezn);
       }
     }
     __syncthreads();
@@ -341,23 +380,32 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
                  nq[2 * G.N3 + e5jn], nq[2 * G.N3 + e5in], nq[G.N3 + e5in], nq[e5jn], ho[h5],
                  ho[G.N2 + h5], ho[2 * G.N2 + h5], A.imu2, A.imu2, A.imu2, i0 + x5 > 0,
                  j0 + y5 > 0, kh > 0, kdx, kdy, kdz, hxn, hyn, hzn);
-      const int64_t g = g5 + sxy * (int64_t)kh;
-      gst(A.h2[0], g, hxn);
-      gst(A.h2[1], g, hyn);
-      gst(A.h2[2], g, hzn);
+      const int64_t gk = sxy * (int64_t)kh;
+      const uint32_t o = fresh(p5 * ES);
+      pst(A.h2[0] + gk, o, hxn);
+      pst(A.h2[1] + gk, o, hyn);
+      pst(A.h2[2] + gk, o, hzn);
     }
   }
 }
 
-template <typename T, bool L, bool N>
-static hipError_t go_step2(const S2Args<T>& a, dim3 grd, dim3 blk, size_t lds, hipStream_t s) {
+template <typename T, bool L, bool N, int CW, int CY>
+static hipError_t go_step2_t(const S2Args<T>& a, dim3 grd, dim3 blk, size_t lds, hipStream_t s) {
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step2<T, L, N>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step2<T, L, N, CW, CY>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_step2<T, L, N>), grd, blk, lds, s, a);
+  hipLaunchKernelGGL((k_step2<T, L, N, CW, CY>), grd, blk, lds, s, a);
   return hipGetLastError();
+}
+
+// the 32 x 16 tile (the fastest on 256 x 256 x 512 grids) has its own
+// compile-time variant; other tiles take the generic one
+template <typename T, bool L, bool N>
+static hipError_t go_step2(const S2Args<T>& a, dim3 grd, dim3 blk, size_t lds, hipStream_t s) {
+  if (a.t.tw == 32 && a.t.ty == 16) return go_step2_t<T, L, N, 32, 16>(a, grd, blk, lds, s);
+  return go_step2_t<T, L, N, 0, 0>(a, grd, blk, lds, s);
 }
 
 template <typename T>
@@ -365,6 +413,7 @@ hipError_t launch_step2(const S2Args<T>& a, bool lossy, hipStream_t s) {
   const bool nu = a.nsq[0] != nullptr;
   const int nup = nu ? a.t.kc + 3 : 0;
   if (!step2_shape_ok(a.t.tw, a.t.ty, sizeof(T), lossy, nup)) return hipErrorInvalidValue;
+  if (!step2_plane_ok(a.d, sizeof(T))) return hipErrorInvalidValue;
   const dim3 blk(step2_threads(a.t.tw, a.t.ty)), grd((unsigned)a.t.blocks());
   const size_t lds = step2_lds_bytes(a.t.tw, a.t.ty, sizeof(T), lossy, nup);
   if (lossy) return nu ? go_step2<T, true, true>(a, grd, blk, lds, s)
