@@ -433,7 +433,7 @@ static int device_cus() {
 
 // Planes per chunk for one round of resident pair workgroups.
 static int pair_kc(const fit_grid* g, int tw, int ty) {
-  const size_t lds = step2_lds_bytes(tw, ty, g->esz, g->lossy, 0);
+  const size_t lds = step2_lds_bytes(tw, ty, g->esz, g->lossy, g->nu);
   const int per_cu = std::max(1, std::min((int)((160 * 1024) / std::max<size_t>(lds, 1)),
                                           2048 / step2_threads(tw, ty)));
   const int64_t tiles = (int64_t)((g->d.nx + tw - 1) / tw) * ((g->d.ny + ty - 1) / ty);
@@ -442,20 +442,12 @@ static int pair_kc(const fit_grid* g, int tw, int ty) {
   return std::min(g->d.nz, std::max(k, std::min(8, g->d.nz)));
 }
 
-// Extra LDS planes of the tensor-grid pair kernel (z factors of the chunk
-// and its two halo planes), 0 on a uniform grid.
-static int pair_nu_planes(const fit_grid* g, int tw, int ty, int kc) {
-  return g->nu ? (kc > 0 ? kc : pair_kc(g, tw, ty)) + 3 : 0;
-}
-
 static bool pair_now(const fit_grid* g, int64_t nleft) {
   if (nleft < 2 || !g->pair_on || !use_fused(g) || g->probe.on) return false;
   if (!step2_plane_ok(g->d, g->esz)) return false;
   // the tile may no longer fit after the materials or spacing changed
   // (lossless -> lossy, uniform -> tensor grid)
-  if (!step2_shape_ok(g->ptw, g->pty, g->esz, g->lossy,
-                      pair_nu_planes(g, g->ptw, g->pty, g->pkc)))
-    return false;
+  if (!step2_shape_ok(g->ptw, g->pty, g->esz, g->lossy, g->nu)) return false;
   const int64_t te = g->trace_every, m = g->m;
   if (te > 0 && (m % te == 0 || (m + 1) % te == 0 || (m + 2) % te == 0)) return false;
   return true;
@@ -1294,8 +1286,7 @@ int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* tw, int* ty, 
     int bw = 0, bt = 0, bk = 0;
     for (const auto& sh : shapes) {
       const int k0 = pair_kc(g, sh[0], sh[1]);
-      if (!step2_shape_ok(sh[0], sh[1], g->esz, g->lossy, pair_nu_planes(g, sh[0], sh[1], k0)))
-        continue;
+      if (!step2_shape_ok(sh[0], sh[1], g->esz, g->lossy, g->nu)) continue;
       const int kcs[2] = {k0, std::max(std::min(8, g->d.nz), k0 / 2)};
       for (int q = 0; q < 2; ++q) {
         if (q == 1 && kcs[1] == kcs[0]) continue;

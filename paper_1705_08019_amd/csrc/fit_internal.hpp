@@ -172,14 +172,17 @@ struct S2Args {
   const double* nrw[3] = {nullptr, nullptr, nullptr};
   double kbs = 0.0, kds = 0.0;
 };
-// nu_planes: z-chunk planes + 3 on a tensor grid (per-plane metric in LDS), else 0.
-size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy, int nu_planes);
+// Planes of per-plane metric factors held in LDS by the two-step kernel on a
+// tensor grid (a ring; a power of two).
+constexpr int kS2ZRing = 4;
+// nu: tensor grid (per-plane metric ring in LDS).
+size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy, bool nu);
 // Threads of a pair workgroup: enough for one e^(m+1) point each (the
 // largest region), a multiple of 64, at most 1024.
 int step2_threads(int tw, int ty);
 // Tile shapes the two-step kernel takes: tw ty a multiple of 64, <= 1024,
 // the staged regions within kS2Per entries per thread, LDS <= 160 KiB.
-bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, int nu_planes = 0);
+bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, bool nu = false);
 // In-plane byte offsets of the two-step kernel are 32-bit: a plane of the
 // slot layout must span at most 4 GiB.
 bool step2_plane_ok(const Dims& d, size_t esz);

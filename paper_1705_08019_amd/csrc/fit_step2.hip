@@ -13,6 +13,12 @@
 //   R2: x in [-1, TW],   y in [-1, TY]    h^(m+3/2)     (needs R1, X4)
 //   R3: x in [0, TW],    y in [0, TY]     e^(m+2)       (needs R2, R1, X4)
 //   tile                                  h^(m+5/2)     (needs R3, R2)
+// Every LDS array has the row stride W = TW + 4 of X4 (a region keeps only
+// its own rows), and in every phase thread t sits at column t % W (x = t % W
+// - 2) of row t / W of the region it computes, so that each LDS access is t
+// plus a constant: the lanes of a wave touch consecutive words (no bank
+// conflicts where a packed region row would wrap inside a wave) and no
+// per-point LDS index is held in registers.
 // Iteration k forms e^(m+1) of plane k, h^(m+3/2) of plane k-1, e^(m+2) of
 // plane k-1 and h^(m+5/2) of plane k-2, for k = k0-1 .. k1+1; the halo rows
 // and columns are recomputed by every tile that needs them with the same
@@ -25,28 +31,27 @@
 
 namespace fit {
 
+// Row stride W of every region; N4, N1, N2, N3: entries of X4 (ty + 4 rows),
+// R1 (ty + 3), R2 (ty + 2), R3 (ty + 1).
 struct S2Geom {
-  int W4, N4, W1, N1, W2, N2, W3, N3;
+  int W, N4, N1, N2, N3;
 };
 
 __host__ __device__ inline S2Geom s2_geom(int tw, int ty) {
   S2Geom g;
-  g.W4 = tw + 4;
-  g.N4 = (tw + 4) * (ty + 4);
-  g.W1 = tw + 3;
-  g.N1 = (tw + 3) * (ty + 3);
-  g.W2 = tw + 2;
-  g.N2 = (tw + 2) * (ty + 2);
-  g.W3 = tw + 1;
-  g.N3 = (tw + 1) * (ty + 1);
+  g.W = tw + 4;
+  g.N4 = g.W * (ty + 4);
+  g.N1 = g.W * (ty + 3);
+  g.N2 = g.W * (ty + 2);
+  g.N3 = g.W * (ty + 1);
   return g;
 }
 
-size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy, int nu_planes) {
+size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy, bool nu) {
   const S2Geom g = s2_geom(tw, ty);
   const size_t n = 6 * (size_t)g.N4 + 3 * (size_t)g.N4 + (lossy ? 3 * (size_t)g.N4 : 0) +
                    6 * (size_t)g.N1 + 6 * (size_t)g.N2 + 6 * (size_t)g.N3 +
-                   3 * (size_t)nu_planes;
+                   (nu ? 3 * (size_t)kS2ZRing : 0);
   return esz * n;
 }
 
@@ -59,12 +64,12 @@ int step2_threads(int tw, int ty) {
   return (g.N1 + 63) / 64 * 64;
 }
 
-bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, int nu_planes) {
+bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, bool nu) {
   if (tw < 8 || ty < 2) return false;
   const S2Geom g = s2_geom(tw, ty);
   const int nthr = step2_threads(tw, ty);   // one thread per point of the largest computed region
   if (nthr > 1024 || g.N4 > kS2Per * nthr) return false;
-  return step2_lds_bytes(tw, ty, esz, lossy, nu_planes) <= 160 * 1024;
+  return step2_lds_bytes(tw, ty, esz, lossy, nu) <= 160 * 1024;
 }
 
 // Global access at a wave-uniform plane base plus a per-thread 32-bit byte
@@ -114,7 +119,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
   T* e1L = sL + (LOSSY ? 3 * G.N4 : 0);       // [2][3][N1]   e^(m+1), planes k, k-1
   T* h1L = e1L + 6 * G.N1;                    // [2][3][N2]   h^(m+3/2), planes k-1, k-2
   T* e2L = h1L + 6 * G.N2;                    // [2][3][N3]   e^(m+2), planes k-1, k-2
-  T* zL = e2L + 6 * G.N3;                     // tensor grid: [3][kc + 3] per-plane factors
+  T* zL = e2L + 6 * G.N3;                     // tensor grid: [3][kS2ZRing] per-plane factors
 
   const int i0 = tx * TW, j0 = tyi * TY;
   const int k0 = kz * A.t.kc;
@@ -125,87 +130,72 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
 
   auto hb = [](int k) { return k & 1; };                 // h0 / e1 / h1 / e2 buffer of plane k
   auto cb = [](int k) { return ((k % 3) + 3) % 3; };     // eps / sigma buffer of plane k
-  auto i4 = [&](int x, int y) { return (y + 2) * G.W4 + (x + 2); };
-  auto i1 = [&](int x, int y) { return (y + 1) * G.W1 + (x + 1); };
-  auto i2 = [&](int x, int y) { return (y + 1) * G.W2 + (x + 1); };
-  auto i3 = [&](int x, int y) { return y * G.W3 + x; };
   auto in_grid = [&](int gx, int gy) { return gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny; };
 
-  // ---- per-thread points of every region (fixed over the z-march); grid
-  // points as in-plane element indices p (gx + sx gy); LDS neighbours as
-  // constant offsets from the point's own index (-1: x - 1, -W: y - 1)
-  // source point: plane sk, in-plane index sp (none: sk = -1)
+  // ---- per-thread points (fixed over the z-march); grid points as in-plane
+  // element indices p (gx + sx gy)
+  // source point: plane sk, in-plane index src_p (none: sk < -1)
   const int64_t sk = A.src_idx >= 0 ? A.src_idx / sxy : -100;   // k >= -1 in the march
-  const uint32_t sp = (uint32_t)(A.src_idx - (sk >= 0 ? sk * sxy : A.src_idx));
+  const uint32_t src_p = (uint32_t)(A.src_idx - (sk >= 0 ? sk * sxy : A.src_idx));
   constexpr uint32_t ES = sizeof(T);
+  const int W = G.W;
   // X4 staging entries (up to kS2Per per thread)
   uint32_t o4[kS2Per];
   bool in4[kS2Per];
 #pragma unroll
   for (int r = 0; r < kS2Per; ++r) {
     const int q = tid + r * nthr;
-    const int gx = i0 + (q % G.W4) - 2, gy = j0 + (q / G.W4) - 2;
+    const int gx = i0 + (q % W) - 2, gy = j0 + (q / W) - 2;
     in4[r] = q < G.N4 && in_grid(gx, gy);
     o4[r] = in4[r] ? (uint32_t)(gx + sx * gy) * ES : 0u;
   }
-  // R1 point (e^(m+1)): one per thread
-  const bool a1 = tid < G.N1;
-  const int x1 = tid % G.W1 - 1, y1 = tid / G.W1 - 1;
-  const int gx1 = i0 + x1, gy1 = j0 + y1;
-  const bool in1 = a1 && in_grid(gx1, gy1);
-  const uint32_t p1 = in1 ? (uint32_t)(gx1 + sx * gy1) : 0u;
-  const bool s1 = in1 && p1 == sp;
-  const int r1 = i4(x1, y1), r1im = r1 - 1, r1jm = r1 - G.W4, r1ijm = r1jm - 1;
-  // R2 point (h^(m+3/2))
-  const bool a2 = tid < G.N2;
-  const int x2 = tid % G.W2 - 1, y2 = tid / G.W2 - 1;
-  const bool in2 = a2 && in_grid(i0 + x2, j0 + y2);
-  const bool px2 = in2 && i0 + x2 > 0, py2 = in2 && j0 + y2 > 0;
-  const int e2c = i1(x2, y2), e2in = e2c + 1, e2jn = e2c + G.W1, r2h = i4(x2, y2);
-  // R3 point (e^(m+2))
-  const bool a3 = tid < G.N3;
-  const int x3 = tid % G.W3, y3 = tid / G.W3;
-  const int gx3 = i0 + x3, gy3 = j0 + y3;
-  const bool in3 = a3 && in_grid(gx3, gy3);
-  const bool own3 = in3 && x3 < TW && y3 < TY;
-  const uint32_t p3 = in3 ? (uint32_t)(gx3 + sx * gy3) : 0u;
-  const bool s3 = in3 && p3 == sp;
-  const int r3 = i4(x3, y3), r3im = r3 - 1, r3jm = r3 - G.W4, r3ijm = r3jm - 1;
-  const int h3 = i2(x3, y3), h3im = h3 - 1, h3jm = h3 - G.W2, o3 = i1(x3, y3);
-  // tile point (h^(m+5/2))
-  const int x5 = tid % TW, y5 = tid / TW;
-  const bool own5 = tid < TW * TY && in_grid(i0 + x5, j0 + y5);
-  const uint32_t p5 = own5 ? (uint32_t)((i0 + x5) + sx * (j0 + y5)) : 0u;
-  const int e5 = i3(x5, y5), e5in = e5 + 1, e5jn = e5 + G.W3, h5 = i2(x5, y5);
+  // the thread's column x (all phases) and rows: y = row - 1 in R1 / R2,
+  // y = row in R3 / the tile
+  const int row = tid / W, x = tid % W - 2;
+  const int gx = i0 + x, gyA = j0 + row - 1, gyB = j0 + row;
+  // R1 point (e^(m+1)); LDS: R1 index t, its X4 index t + W
+  const bool a1 = row < TY + 3 && x >= -1;
+  const bool in1 = a1 && in_grid(gx, gyA);
+  const uint32_t p1 = in1 ? (uint32_t)(gx + sx * gyA) : 0u;
+  const bool s1 = in1 && p1 == src_p;
+  // R2 point (h^(m+3/2)); LDS: R2 / R1 index t, X4 index t + W
+  const bool a2 = row < TY + 2 && x >= -1 && x <= TW;
+  const bool in2 = a2 && in_grid(gx, gyA);
+  const bool px2 = in2 && gx > 0, py2 = in2 && gyA > 0;
+  // R3 point (e^(m+2)); LDS: R3 index t, R2 / R1 index t + W, X4 index t + 2W
+  const bool a3 = row < TY + 1 && x >= 0 && x <= TW;
+  const bool in3 = a3 && in_grid(gx, gyB);
+  const uint32_t p3 = in3 ? (uint32_t)(gx + sx * gyB) : 0u;
+  const bool s3 = in3 && p3 == src_p;
+  // tile point (h^(m+5/2)) = the R3 point when it lies in the tile; LDS: R3
+  // index t, R2 index t + W
+  const bool own = in3 && x < TW && row < TY;
 
   // ---- tensor-grid metric (as in the single fused step): x / y factors of
   // each thread's points, z factors of planes k0 - 1 .. k1 + 1 staged in LDS
-  T kb1x = A.kb[0], kb1y = A.kb[1], kb3x = A.kb[0], kb3y = A.kb[1];
+  T kbx = A.kb[0], kb1y = A.kb[1], kb3y = A.kb[1];
   T kd2x = 0, kd2y = 0, kd2z = 0, kd5x = 0, kd5y = 0, kd5z = 0;
-  const int zp = A.t.kc + 3;
   if (NU) {
-    auto cx = [&](int gx) { return min(max(gx, 0), d.nx - 1); };
-    auto cy = [&](int gy) { return min(max(gy, 0), d.ny - 1); };
-    kb1x = (T)(A.kbs * A.nsq[0][cx(gx1)]);
-    kb1y = (T)(A.kbs * A.nsq[1][cy(gy1)]);
-    kb3x = (T)(A.kbs * A.nsq[0][cx(gx3)]);
-    kb3y = (T)(A.kbs * A.nsq[1][cy(gy3)]);
-    const int ix2 = cx(i0 + x2), jy2 = cy(j0 + y2), ix5 = cx(i0 + x5), jy5 = cy(j0 + y5);
-    kd2x = (T)(A.kds * (0.5 * A.ndl[0][ix2] * A.nrw[1][jy2]));
-    kd2y = (T)(A.kds * (0.5 * A.ndl[1][jy2] * A.nrw[0][ix2]));
-    kd2z = (T)(A.kds * (0.5 * A.nrw[0][ix2] * A.nrw[1][jy2]));
-    kd5x = (T)(A.kds * (0.5 * A.ndl[0][ix5] * A.nrw[1][jy5]));
-    kd5y = (T)(A.kds * (0.5 * A.ndl[1][jy5] * A.nrw[0][ix5]));
-    kd5z = (T)(A.kds * (0.5 * A.nrw[0][ix5] * A.nrw[1][jy5]));
-    for (int q = tid; q < zp; q += nthr) {
-      const int kk = k0 - 1 + q;
-      const bool in = kk >= 0 && kk < d.nz;
-      zL[q] = in ? (T)(A.kbs * A.nsq[2][kk]) : T(0);
-      zL[zp + q] = in ? (T)A.nrw[2][kk] : T(0);
-      zL[2 * zp + q] = in ? (T)A.ndl[2][kk] : T(0);
-    }
+    const int ix = min(max(gx, 0), d.nx - 1);
+    const int jA = min(max(gyA, 0), d.ny - 1), jB = min(max(gyB, 0), d.ny - 1);
+    kbx = (T)(A.kbs * A.nsq[0][ix]);
+    kb1y = (T)(A.kbs * A.nsq[1][jA]);
+    kb3y = (T)(A.kbs * A.nsq[1][jB]);
+    kd2x = (T)(A.kds * (0.5 * A.ndl[0][ix] * A.nrw[1][jA]));
+    kd2y = (T)(A.kds * (0.5 * A.ndl[1][jA] * A.nrw[0][ix]));
+    kd2z = (T)(A.kds * (0.5 * A.nrw[0][ix] * A.nrw[1][jA]));
+    kd5x = (T)(A.kds * (0.5 * A.ndl[0][ix] * A.nrw[1][jB]));
+    kd5y = (T)(A.kds * (0.5 * A.ndl[1][jB] * A.nrw[0][ix]));
+    kd5z = (T)(A.kds * (0.5 * A.nrw[0][ix] * A.nrw[1][jB]));
   }
-  auto zi = [&](int k) { return k - (k0 - 1); };   // z-factor slot of plane k
+  // the z factors of plane k sit in ring slot k mod kS2ZRing of zL (kb_z,
+  // 1 / w_z, dual width): thread 0 fetches them with the plane and stages
+  // them with it; a slot is rewritten three planes after its last reader
+  // (the tile h-update of plane k - 2 may still run while plane k + 1 is
+  // staged, so the ring holds four planes)
+  constexpr int ZR = kS2ZRing;
+  auto zs = [](int k) { return k & (ZR - 1); };
+  double zraw[3] = {0.0, 0.0, 0.0};
 
   // ---- register staging of plane k: X4 entries (h x3, eps, sigma), R1 entry (e x3)
   T ph[kS2Per][5];
@@ -224,6 +214,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
       ph[r][2] = in ? pld(bh2, o) : T(0);
       ph[r][3] = in ? pld(bc, o) : T(0);
       ph[r][4] = (LOSSY && in) ? pld(bs, o) : T(0);
+    }
+    if (NU && tid == 0) {
+      zraw[0] = plane ? A.nsq[2][k] : 0.0;
+      zraw[1] = plane ? A.nrw[2][k] : 0.0;
+      zraw[2] = plane ? A.ndl[2][k] : 0.0;
     }
     const bool in = plane && in1;
     const uint32_t o = fresh(p1 * ES);
@@ -245,6 +240,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
         c[q] = ph[r][3];
         if (LOSSY) s[q] = ph[r][4];
       }
+    }
+    if (NU && tid == 0) {
+      zL[zs(k)] = (T)(A.kbs * zraw[0]);
+      zL[ZR + zs(k)] = (T)zraw[1];
+      zL[2 * ZR + zs(k)] = (T)zraw[2];
     }
   };
 
@@ -300,10 +300,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
     if (a1) {
       const bool kin = k >= 0 && k < d.nz;
       T exn, eyn, ezn;
-      e_upd(in1 && kin, gx1, gy1, s1 && k == sk, k, h0L + hb(k) * 3 * G.N4,
-            h0L + hb(k - 1) * 3 * G.N4, G.N4, r1, r1im, r1jm, r1, r1im, r1jm, r1ijm,
-            cL + cb(k) * G.N4, cL + cb(k - 1) * G.N4, sL + cb(k) * G.N4, sL + cb(k - 1) * G.N4,
-            e0x, e0y, e0z, A.src_val[0], kb1x, kb1y, NU ? zL[zi(k)] : A.kb[2], exn, eyn, ezn);
+      e_upd(in1 && kin, gx, gyA, s1 && k == sk, k, h0L + hb(k) * 3 * G.N4,
+            h0L + hb(k - 1) * 3 * G.N4, G.N4, tid + W, tid + W - 1, tid, tid + W, tid + W - 1,
+            tid, tid - 1, cL + cb(k) * G.N4, cL + cb(k - 1) * G.N4, sL + cb(k) * G.N4,
+            sL + cb(k - 1) * G.N4, e0x, e0y, e0z, A.src_val[0], kbx, kb1y,
+            NU ? zL[zs(k)] : A.kb[2], exn, eyn, ezn);
       T* out = e1L + hb(k) * 3 * G.N1;
       out[tid] = exn;
       out[G.N1 + tid] = eyn;
@@ -320,15 +321,16 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
       const bool valid = in2 && km >= 0 && km < d.nz;
       T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
       if (NU) {
-        const T rz = zL[zp + zi(km)];
+        const T rz = zL[ZR + zs(km)];
         kdx = kd2x * rz;
         kdy = kd2y * rz;
-        kdz = kd2z * zL[2 * zp + zi(km)];
+        kdz = kd2z * zL[2 * ZR + zs(km)];
       }
       T hxn, hyn, hzn;
-      h_point<T>(nq[e2c], nq[G.N1 + e2c], nq[2 * G.N1 + e2c], np_[e2c], np_[G.N1 + e2c],
-                 nq[2 * G.N1 + e2jn], nq[2 * G.N1 + e2in], nq[G.N1 + e2in], nq[e2jn], ho[r2h],
-                 ho[G.N4 + r2h], ho[2 * G.N4 + r2h], A.imu2, A.imu2, A.imu2, valid && px2,
+      const int c = tid, cin = tid + 1, cjn = tid + W, rh = tid + W;
+      h_point<T>(nq[c], nq[G.N1 + c], nq[2 * G.N1 + c], np_[c], np_[G.N1 + c],
+                 nq[2 * G.N1 + cjn], nq[2 * G.N1 + cin], nq[G.N1 + cin], nq[cjn], ho[rh],
+                 ho[G.N4 + rh], ho[2 * G.N4 + rh], A.imu2, A.imu2, A.imu2, valid && px2,
                  valid && py2, valid && km > 0, kdx, kdy, kdz, hxn, hyn, hzn);
       T* out = h1L + hb(km) * 3 * G.N2;
       out[tid] = hxn;
@@ -343,16 +345,17 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
       const T* eo = e1L + hb(km) * 3 * G.N1;
       const bool kin = km >= 0 && km < d.nz;
       T exn, eyn, ezn;
-      e_upd(in3 && kin, gx3, gy3, s3 && km == sk, km, h1L + hb(km) * 3 * G.N2, h1L + hb(km - 1) * 3 * G.N2,
-            G.N2, h3, h3im, h3jm, r3, r3im, r3jm, r3ijm, cL + cb(km) * G.N4,
-            cL + cb(km - 1) * G.N4, sL + cb(km) * G.N4, sL + cb(km - 1) * G.N4, eo[o3],
-            eo[G.N1 + o3], eo[2 * G.N1 + o3], A.src_val[1], kb3x, kb3y,
-            NU ? zL[zi(km)] : A.kb[2], exn, eyn, ezn);
+      const int o = tid + W;
+      e_upd(in3 && kin, gx, gyB, s3 && km == sk, km, h1L + hb(km) * 3 * G.N2,
+            h1L + hb(km - 1) * 3 * G.N2, G.N2, tid + W, tid + W - 1, tid, tid + 2 * W,
+            tid + 2 * W - 1, tid + W, tid + W - 1, cL + cb(km) * G.N4, cL + cb(km - 1) * G.N4,
+            sL + cb(km) * G.N4, sL + cb(km - 1) * G.N4, eo[o], eo[G.N1 + o], eo[2 * G.N1 + o],
+            A.src_val[1], kbx, kb3y, NU ? zL[zs(km)] : A.kb[2], exn, eyn, ezn);
       T* out = e2L + hb(km) * 3 * G.N3;
       out[tid] = exn;
       out[G.N3 + tid] = eyn;
       out[2 * G.N3 + tid] = ezn;
-      if (own3 && km < k1) {
+      if (own && km < k1) {
         const int64_t gk = sxy * (int64_t)km;
         const uint32_t o = fresh(p3 * ES);
         pst(A.e2[0] + gk, o, exn);
@@ -364,24 +367,25 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
 
     // ---- h^(m+5/2) of plane kh = k - 2 on the tile (from e^(m+2) of planes kh, kh + 1)
     const int kh = k - 2;
-    if (kh >= k0 && kh < k1 && own5) {
+    if (kh >= k0 && kh < k1 && own) {
       const T* nq = e2L + hb(kh) * 3 * G.N3;
       const T* np_ = e2L + hb(kh + 1) * 3 * G.N3;
       const T* ho = h1L + hb(kh) * 3 * G.N2;
       T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
       if (NU) {
-        const T rz = zL[zp + zi(kh)];
+        const T rz = zL[ZR + zs(kh)];
         kdx = kd5x * rz;
         kdy = kd5y * rz;
-        kdz = kd5z * zL[2 * zp + zi(kh)];
+        kdz = kd5z * zL[2 * ZR + zs(kh)];
       }
       T hxn, hyn, hzn;
-      h_point<T>(nq[e5], nq[G.N3 + e5], nq[2 * G.N3 + e5], np_[e5], np_[G.N3 + e5],
-                 nq[2 * G.N3 + e5jn], nq[2 * G.N3 + e5in], nq[G.N3 + e5in], nq[e5jn], ho[h5],
-                 ho[G.N2 + h5], ho[2 * G.N2 + h5], A.imu2, A.imu2, A.imu2, i0 + x5 > 0,
-                 j0 + y5 > 0, kh > 0, kdx, kdy, kdz, hxn, hyn, hzn);
+      const int c = tid, cin = tid + 1, cjn = tid + W, rh = tid + W;
+      h_point<T>(nq[c], nq[G.N3 + c], nq[2 * G.N3 + c], np_[c], np_[G.N3 + c],
+                 nq[2 * G.N3 + cjn], nq[2 * G.N3 + cin], nq[G.N3 + cin], nq[cjn], ho[rh],
+                 ho[G.N2 + rh], ho[2 * G.N2 + rh], A.imu2, A.imu2, A.imu2, gx > 0, gyB > 0,
+                 kh > 0, kdx, kdy, kdz, hxn, hyn, hzn);
       const int64_t gk = sxy * (int64_t)kh;
-      const uint32_t o = fresh(p5 * ES);
+      const uint32_t o = fresh(p3 * ES);
       pst(A.h2[0] + gk, o, hxn);
       pst(A.h2[1] + gk, o, hyn);
       pst(A.h2[2] + gk, o, hzn);
@@ -411,11 +415,10 @@ static hipError_t go_step2(const S2Args<T>& a, dim3 grd, dim3 blk, size_t lds, h
 template <typename T>
 hipError_t launch_step2(const S2Args<T>& a, bool lossy, hipStream_t s) {
   const bool nu = a.nsq[0] != nullptr;
-  const int nup = nu ? a.t.kc + 3 : 0;
-  if (!step2_shape_ok(a.t.tw, a.t.ty, sizeof(T), lossy, nup)) return hipErrorInvalidValue;
+  if (!step2_shape_ok(a.t.tw, a.t.ty, sizeof(T), lossy, nu)) return hipErrorInvalidValue;
   if (!step2_plane_ok(a.d, sizeof(T))) return hipErrorInvalidValue;
   const dim3 blk(step2_threads(a.t.tw, a.t.ty)), grd((unsigned)a.t.blocks());
-  const size_t lds = step2_lds_bytes(a.t.tw, a.t.ty, sizeof(T), lossy, nup);
+  const size_t lds = step2_lds_bytes(a.t.tw, a.t.ty, sizeof(T), lossy, nu);
   if (lossy) return nu ? go_step2<T, true, true>(a, grd, blk, lds, s)
                        : go_step2<T, true, false>(a, grd, blk, lds, s);
   return nu ? go_step2<T, false, true>(a, grd, blk, lds, s)
