@@ -611,7 +611,7 @@ def summarize(kt, fetch, write, cfetch, cwrite, out_md, cells, cmd_note):
         name = key[0]
         lines.append(f"| `{name[:70]}` | {key[1]} | {key[2]} | {len(f)} | {fk:.0f} | {wk:.0f} | "
                      f"{gb:.4f} | {bpc:.2f} |")
-        tag = ("pair" if "k_step2<float, true>" in name
+        tag = ("pair" if "k_step2<float, true, false" in name
                else "step" if "k_step<float, true, false, false" in name
                else "epass" if "k_epass<float, true, false, false>" in name
                else "hpass" if "k_hpass<float, true, false>" in name else None)
