@@ -93,3 +93,83 @@ def test_c3_fullsize_sampled_windows_and_balance():
     de, dh, has_src = _window_check(spec, e_a, h_a, e_b, h_b, dt, src, origins[0], 15)
     assert has_src and de <= 1e-5 and dh <= 1e-5, (de, dh)
     g.close()
+
+
+def _window_check_steps(spec, e0, h0, e2, h2, dt, src, origin, step0, steps, w=10, margin=3):
+    """`steps` steps of a w^3 window by the oracle against the GPU's full-grid
+    result on the slots `margin` cells inside the window (the window's PEC
+    boundary reaches one cell further per step)."""
+    i0, j0, k0 = origin
+    sl = (slice(None), slice(k0, k0 + w), slice(j0, j0 + w), slice(i0, i0 + w))
+    t = Topology(w, w, w)
+    eps = spec.eps_r[sl[1:]]
+    sig = None if spec.sigma is None else spec.sigma[sl[1:]]
+    ops = Operators(t, Materials(t, eps, sigma=sig))
+    ew0 = layout.edges_from_slots(ops, e0[sl].astype(np.float64))
+    hw0 = layout.facets_from_slots(ops, h0[sl].astype(np.float64))
+    lsrc = None
+    si, sj, sk = src["i"] - i0, src["j"] - j0, src["k"] - k0
+    if 0 < si < w and 0 < sj < w and 0 <= sk < w:
+        lsrc = dict(src, i=si, j=sj, k=sk)
+    ewN, hwN, _ = run(ops, ew0, hw0, dt, steps, source=lsrc, step0=step0)
+    inner = (slice(None),) + (slice(margin, w - margin),) * 3
+    eo = layout.edges_to_slots(ops, ewN)[inner]
+    ho = layout.facets_to_slots(ops, hwN)[inner]
+    eg = e2[sl].astype(np.float64)[inner]
+    hg = h2[sl].astype(np.float64)[inner]
+    se = max(np.max(np.abs(eo)), np.max(np.abs(ew0)), 4 * dt * np.max(np.abs(hw0)), 1e-30)
+    sh = max(np.max(np.abs(ho)), np.max(np.abs(hw0)), 4 * dt * np.max(np.abs(ewN)), 1e-30)
+    return np.max(np.abs(eg - eo)) / se, np.max(np.abs(hg - ho)) / sh
+
+
+def test_c3_fullsize_step_pairs_in_the_benchmark_configuration():
+    """The benchmark's launch configuration: two steps per launch on 32 x 16
+    tiles with 64-plane chunks (single steps on 128 x 8 tiles around the
+    trace rows every 50 steps).  47 steps bitwise equal to single fused steps;
+    then one pair on sampled 10^3 windows against the oracle."""
+    from paper_1705_08019_amd import FitGrid
+    spec = c3()
+
+    def make(pair):
+        g = FitGrid(spec.nx, spec.ny, spec.nz, "f32")
+        g.set_materials(spec.eps_r, spec.mu_r, spec.sigma)
+        g.set_tuning("fused", 8, 128, 128)
+        if pair:
+            g.set_pair(True, 32, 16, 64)
+        g.trace_config(spec.energy_every, 64)
+        return g
+
+    g1, g2 = make(True), make(False)
+    dt = spec.cfl_frac * g1.cfl_dt()
+    s = spec.source
+    src = dict(axis=2, i=s["i"], j=s["j"], k=s["k"], i_max=s["i_max"],
+               sigma_t=s["sigma_t_steps"] * dt)
+    for g in (g1, g2):
+        g.set_source(2, s["i"], s["j"], s["k"], s["i_max"], src["sigma_t"])
+    print("c3 full size: 47 steps, pairs vs single", flush=True)
+    g1.profile_begin(200)
+    g1.step(47, dt)
+    assert g1.profile_end()["pair"][1] >= 22
+    g2.step(47, dt)
+    for a, b in zip(g1.get_fields(), g2.get_fields()):
+        assert torch.equal(a, b)
+    assert np.array_equal(g1.trace_read()[0], g2.trace_read()[0], equal_nan=True)
+    g2.close()
+    e0, h0 = (x.cpu().numpy() for x in g1.get_fields())
+    g1.profile_begin(8)
+    g1.step(2, dt)
+    assert g1.profile_end()["pair"][1] == 1
+    e2, h2 = (x.cpu().numpy() for x in g1.get_fields())
+    rng = np.random.default_rng(7)
+    origins = [(s["i"] - 5, s["j"] - 5, s["k"] - 5)]
+    origins += [(int(rng.integers(s["i"] - 40, s["i"] + 30)),
+                 int(rng.integers(s["j"] - 40, s["j"] + 30)),
+                 int(rng.integers(s["k"] - 40, s["k"] + 30))) for _ in range(16)]
+    # walls, and windows across the 32 x 16 tile and 64-plane chunk seams
+    origins += [(0, 0, 0), (spec.nx - 10, spec.ny - 10, spec.nz - 10), (27, 11, 59),
+                (123, 43, 187)]
+    print("c3 full size: pair windows vs oracle", flush=True)
+    for o in origins:
+        de, dh = _window_check_steps(spec, e0, h0, e2, h2, dt, src, o, 47, 2)
+        assert de <= 1e-5 and dh <= 1e-5, (o, de, dh)
+    g1.close()
