@@ -159,8 +159,19 @@ def cpu_baseline():
             "kind": "oracle",
             "sample": f"{nx}x{ny}x{nz} cells of the same recipe, {steps} steps, FP64 CSR "
                       f"leapfrog with per-step energies, {sec:.1f} s on 1 thread "
-                      f"({platform.processor() or platform.machine()}, "
-                      f"{os.cpu_count()} logical CPUs visible)"}
+                      f"({cpu_model()}, {os.cpu_count()} logical CPUs visible)"}
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (from /proc/cpuinfo where there is one)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def measure_copy(nbytes: int = 1 << 30, reps: int = 5) -> float:
@@ -709,6 +720,12 @@ def main(argv=None):
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
                 "traffic": (None if load_traffic(tkey) is None
                             else load_traffic(tkey)["bytes_per_launch"]),
+                # secondary roofline: measured HBM bytes over the launch time
+                "traffic_GBs": (None if load_traffic(tkey) is None else round(
+                    load_traffic(tkey)["bytes_per_launch"] / (avg / 1e3) / 1e9, 1)),
+                "traffic_frac": (None if load_traffic(tkey) is None else round(
+                    load_traffic(tkey)["bytes_per_launch"] / (avg / 1e3) / 1e9 / PEAK_HBM_GBS,
+                    4)),
                 "traffic_unit": "bytes per launch (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, "
                                 "scaled by a 1 GiB copy; profiles/traffic_c3.json)",
                 "alg_bytes_per_launch": kb * cells, "alg_bytes_per_cell": kb,
