@@ -238,6 +238,10 @@ int fit_step_record(fit_grid* g, int64_t nsteps, double dt, void* e_rec, void* h
  * resident workgroups).  Errors: FIT_E_INVALID. */
 int fit_adjoint_set_tuning(fit_grid* g, int tw, int ty, int kc);
 
+/* The reverse-step tile the next fit_adjoint_begin will use (the one set, or
+ * the defaults for this grid and device).  Errors: FIT_E_INVALID. */
+int fit_adjoint_get_tuning(const fit_grid* g, int* tw, int* ty, int* kc);
+
 /* Start a reverse sweep over a forward horizon of nsteps steps taken with dt:
  * clears lambda, mu and the accumulated sensitivities.  Errors: FIT_E_STATE
  * without a probe, FIT_E_INVALID for a non-uniform mu. */

@@ -86,6 +86,7 @@ SIGNATURES = {
     "fit_batch_step": [_vp, _i64, _dp, _i],
     "fit_step_record": [_vp, _i64, _d, _vp, _vp],
     "fit_adjoint_set_tuning": [_vp, _i, _i, _i],
+    "fit_adjoint_get_tuning": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "fit_adjoint_begin": [_vp, _i64, _d],
     "fit_adjoint_step": [_vp, _i64, _vp, _vp, _vp],
     "fit_adjoint_segment": [_vp, _i64, _i64, _vp, _vp],

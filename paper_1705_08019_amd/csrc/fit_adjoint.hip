@@ -27,7 +27,10 @@
 // sensitivities of the 12 edges of each cell of plane k-1 to the per-cell
 // accumulators.  lambda and mu ping-pong between two buffer sets.
 // mu (permeability) must be uniform here.
+#include <algorithm>
+
 #include "fit_internal.hpp"
+#include "fit_point.hpp"
 
 namespace fit {
 
@@ -49,9 +52,6 @@ __device__ __forceinline__ double rcp_d(double x) {
   return r;
 }
 
-// Ring entries per thread: (tw + 2)(ty + 2) <= 3 nthr (host-checked).
-constexpr int kAdjRing = 3;
-
 // z-neighbour (plane k-1) values of one point, carried between iterations.
 template <typename T>
 struct AdjPrev {
@@ -61,8 +61,11 @@ struct AdjPrev {
 // Threads: t < tw ty own tile column (t mod tw, t div tw); the next
 // tw + ty + 1 threads own one halo point each (the +y row, then the +x
 // column with the corner); the rest only stage planes.
+// FP32: at most 128 VGPRs (4 waves per SIMD), so that two 512-thread
+// workgroups are resident per CU.
 template <typename T, bool LOSSY>
-__global__ __launch_bounds__(512) void k_adj(AdjArgs<T> A) {
+__global__ __launch_bounds__(512)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj(AdjArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const Dims d = A.d;
   const int TW = A.t.tw, TY = A.t.ty;
@@ -217,8 +220,8 @@ __global__ __launch_bounds__(512) void k_adj(AdjArgs<T> A) {
       const double Me = A.ge[a] * (double)E;
       const double Ms = A.ge[a] * (double)S4[a];
       const T Dt = E + A.hs * S4[a];
-      const T ca = LOSSY ? (E - A.hs * S4[a]) / Dt : T(1);
-      const T cb = A.kb[a] / Dt;
+      const T ca = LOSSY ? qdiv(E - A.hs * S4[a], Dt) : T(1);
+      const T cb = qdiv(A.kb[a], Dt);
       const T em = v[3 + a], em1 = v[6 + a];
       T ln = ca * v[a] - gv[a];
       double probe_e2 = 0.0;
@@ -337,24 +340,17 @@ size_t adjoint_lds_bytes(int tw, int ty, size_t esz) {
 
 int adjoint_threads(int tw, int ty) { return ((tw * ty + tw + ty + 1 + 63) / 64) * 64; }
 
-template <typename T, bool LOSSY>
-static int adj_occupancy(int nthreads, size_t lds) {
-  const void* fn = reinterpret_cast<const void*>(&k_adj<T, LOSSY>);
-  (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  int nb = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, nthreads, lds) != hipSuccess) {
-    (void)hipGetLastError();
-    return 0;
-  }
-  return nb;
-}
-
+// Resident workgroups per CU: the waves per SIMD that the kernel's
+// waves-per-EU attribute guarantees (FP32 4, i.e. <= 128 VGPRs; FP64 2),
+// 4 SIMDs, and 160 KiB of LDS.
 int adjoint_blocks_per_cu(int tw, int ty, size_t esz, bool lossy) {
+  (void)lossy;
   const int nt = adjoint_threads(tw, ty);
   const size_t lds = adjoint_lds_bytes(tw, ty, esz);
-  if (esz == 8)
-    return lossy ? adj_occupancy<double, true>(nt, lds) : adj_occupancy<double, false>(nt, lds);
-  return lossy ? adj_occupancy<float, true>(nt, lds) : adj_occupancy<float, false>(nt, lds);
+  const int waves_simd = esz == 8 ? 2 : 4;
+  const int by_waves = 4 * waves_simd / ((nt + 63) / 64);
+  const int by_lds = (int)((160 * 1024) / std::max<size_t>(lds, 1));
+  return std::min(by_waves, by_lds);
 }
 
 template <typename T>

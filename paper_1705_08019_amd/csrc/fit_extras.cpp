@@ -55,7 +55,8 @@ static Tiling adjoint_tiling(const fit_grid* g) {
   const int64_t tiles = (int64_t)((d.nx + tw - 1) / tw) * ((d.ny + ty - 1) / ty);
   const int64_t nkc = std::max<int64_t>(1, (int64_t)cus * per_cu / tiles);
   int kc = (int)((d.nz + nkc - 1) / nkc);
-  kc = std::min(d.nz, std::max(kc, std::min(8, d.nz)));
+  // at least 4 planes per chunk (the march re-reads one plane below it)
+  kc = std::min(d.nz, std::max(kc, std::min(4, d.nz)));
   return make_tiling(d, ty, kc, tw);
 }
 
@@ -155,6 +156,15 @@ int fit_step_record(fit_grid* g, int64_t nsteps, double dt, void* e_rec, void* h
                 : record_t<float>(g, nsteps, dt, e_rec, h_rec);
 }
 
+int fit_adjoint_get_tuning(const fit_grid* g, int* tw, int* ty, int* kc) {
+  if (!g || !tw || !ty || !kc) return fail(FIT_E_INVALID, "null argument");
+  const Tiling t = adjoint_tiling(g);
+  *tw = t.tw;
+  *ty = t.ty;
+  *kc = t.kc;
+  return FIT_OK;
+}
+
 int fit_adjoint_set_tuning(fit_grid* g, int tw, int ty, int kc) {
   if (!g) return fail(FIT_E_INVALID, "null handle");
   if ((tw == 0) != (ty == 0)) return fail(FIT_E_INVALID, "give both tw and ty, or neither");
@@ -162,7 +172,7 @@ int fit_adjoint_set_tuning(fit_grid* g, int tw, int ty, int kc) {
   if (tw > 0) {
     if (tw > 256) return fail(FIT_E_INVALID, "tw must be <= 256");
     const int nt = adjoint_threads(tw, ty);
-    if (nt > 512 || (int64_t)(tw + 2) * (ty + 2) > 3 * (int64_t)nt ||
+    if (nt > 512 || (int64_t)(tw + 2) * (ty + 2) > kAdjRing * (int64_t)nt ||
         adjoint_lds_bytes(tw, ty, g->esz) > 160 * 1024)
       return fail(FIT_E_INVALID, "adjoint tile does not fit a workgroup (tw ty + tw + ty + 1 <= 512)");
   }
@@ -201,7 +211,7 @@ int fit_adjoint_begin(fit_grid* g, int64_t nsteps, double dt) {
   w->t = adjoint_tiling(g);
   {
     const int nt = adjoint_threads(w->t.tw, w->t.ty);
-    if ((int64_t)(w->t.tw + 2) * (w->t.ty + 2) > 3 * (int64_t)nt || nt > 512 ||
+    if ((int64_t)(w->t.tw + 2) * (w->t.ty + 2) > kAdjRing * (int64_t)nt || nt > 512 ||
         adjoint_lds_bytes(w->t.tw, w->t.ty, g->esz) > 160 * 1024)
       return fail(FIT_E_INVALID, "adjoint tile does not fit a workgroup");
   }

@@ -244,6 +244,9 @@ struct AdjArgs {
 };
 
 size_t adjoint_lds_bytes(int tw, int ty, size_t esz);
+// Ring entries of a plane staged per thread by the reverse-step kernel:
+// (tw + 2)(ty + 2) <= 2 (tw + 1)(ty + 1) <= 2 nthr whenever tw ty >= 2.
+constexpr int kAdjRing = 2;
 int adjoint_threads(int tw, int ty);   // tw ty column threads + tw + ty + 1 halo threads
 int adjoint_blocks_per_cu(int tw, int ty, size_t esz, bool lossy);
 template <typename T>

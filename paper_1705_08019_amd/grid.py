@@ -364,6 +364,12 @@ class FitGrid:
         adjoint_begin; zeros select the defaults."""
         call("fit_adjoint_set_tuning", self._h, int(tw), int(ty), int(kc))
 
+    def adjoint_get_tuning(self):
+        """(tw, ty, kc) of the reverse-step tile the next adjoint_begin uses."""
+        w, t, k = C.c_int(), C.c_int(), C.c_int()
+        call("fit_adjoint_get_tuning", self._h, C.byref(w), C.byref(t), C.byref(k))
+        return w.value, t.value, k.value
+
     def adjoint_begin(self, nsteps: int, dt: float):
         call("fit_adjoint_begin", self._h, int(nsteps), float(dt))
 

@@ -146,3 +146,45 @@ def test_adjoint_fp32_96cube_vs_fp64_central_differences():
         errs.append(abs(fd - gs[k, j, i]) / scale_s)
     print(f"96^3 FP32 adjoint vs FP64 central differences: max rel err {max(errs):.2e}")
     assert max(errs) <= 1e-4
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_adjoint_tiles_agree_bitwise(dtype):
+    """The reverse step recomputes its halo with the owner's arithmetic, so
+    every tile shape and z-chunk (ragged tiles, chunk seams at every plane)
+    gives the same gradients, bit for bit, as the default tiling."""
+    from paper_1705_08019_amd import FitGrid, FitError
+    spec = _small_spec((37, 29, 23))
+    nx, ny, nz = spec.nx, spec.ny, spec.nz
+    g = FitGrid(nx, ny, nz, dtype)
+    g.set_materials(spec.eps_r, None, spec.sigma)
+    dt = 0.9 * g.cfl_dt()
+    s = spec.source
+    g.set_source(s["axis"], s["i"], s["j"], s["k"], s["i_max"], s["sigma_t_steps"] * dt)
+    g.set_probe([b[0] for b in spec.probe], [b[1] for b in spec.probe])
+    K = 24
+    tdt = torch.float32 if dtype == "f32" else torch.float64
+    er = torch.empty((K + 1, 3, nz, ny, nx), dtype=tdt, device="cuda")
+    hr = torch.empty_like(er)
+    g.step(10, dt)
+    g.step_record(K, dt, er, hr)
+    m0 = g.step_index - K
+    ref = None
+    for tile in [(0, 0, 0), (32, 6, 5), (16, 12, 1), (64, 4, 3), (8, 20, 7), (32, 14, 23)]:
+        g.adjoint_set_tuning(*tile)
+        used = g.adjoint_get_tuning()
+        if tile[0]:
+            assert used == tile
+        print(f"adjoint {dtype} tile {used}", flush=True)
+        g.adjoint_begin(g.step_index, dt)
+        g.adjoint_segment(m0, K, er, hr)
+        de, ds = (x.clone() for x in g.adjoint_grad())
+        assert torch.isfinite(de).all() and torch.isfinite(ds).all()
+        if ref is None:
+            ref = (de, ds)
+            assert de.abs().max() > 0
+        else:
+            assert torch.equal(de, ref[0]) and torch.equal(ds, ref[1]), used
+    with pytest.raises(FitError):
+        g.adjoint_set_tuning(256, 4, 0)     # more than 512 threads with its halo
+    g.close()
