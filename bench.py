@@ -329,7 +329,7 @@ def form_adjoint():
     return {"workload": "c5: 96^3 FP32, 4096 steps, checkpoints every 64, probe 16^3",
             "forward_Gcell_steps_per_s": round(fwd, 3), "adjoint_Gcell_steps_per_s": round(bwd, 3),
             "adjoint_over_forward": round(bwd / fwd, 3), "forward_s": round(t1 - t0, 4),
-            "backward_s": round(t2 - t1, 4), "J": float(J),
+            "backward_s": round(t2 - t1, 4), "J": float(J.detach()),
             "note": "wall time incl. Python checkpoint bookkeeping; backward = recompute + reverse",
             "step_us": {"forward_with_probe": round(us_fwd, 2), "recompute_recording": round(us_rec, 2),
                         "reverse_k_adj": round(best, 2)},

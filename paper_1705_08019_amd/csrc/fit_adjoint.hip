@@ -254,11 +254,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj(AdjArgs<
   // prologue: plane k0 - 1 (zeros below the grid) gives the carried values
   AdjPrev<T> pvp{};
   fetch_ring(k0 - 1);
+  fetch_pt(k0);   // in flight together with the ring of plane k0 - 1
   stage(rL0 + 8 * RP);
   __syncthreads();
   if (act || hal) take_prev(rL0 + 8 * RP, px, py, pvp);
   fetch_ring(k0);
-  fetch_pt(k0);
   double Ae = 0.0, Ze = 0.0, As = 0.0, Zs = 0.0;   // own cell: partial sums of plane k-1
 
   for (int k = k0; k <= k1; ++k) {
