@@ -13,18 +13,26 @@
 //   R2: x in [-1, TW],   y in [-1, TY]    h^(m+3/2)     (needs R1, X4)
 //   R3: x in [0, TW],    y in [0, TY]     e^(m+2)       (needs R2, R1, X4)
 //   tile                                  h^(m+5/2)     (needs R3, R2)
-// Every LDS array has the row stride W = TW + 4 of X4 (a region keeps only
-// its own rows), and in every phase thread t sits at column t % W (x = t % W
-// - 2) of row t / W of the region it computes, so that each LDS access is t
-// plus a constant: the lanes of a wave touch consecutive words (no bank
-// conflicts where a packed region row would wrap inside a wave) and no
-// per-point LDS index is held in registers.
+// Thread t owns the point (x, y) = (t % W - 2, t / W - 1), W = TW + 4, in
+// every phase (each phase runs on the threads whose point lies in its
+// region), and every LDS array has the row stride W (a region keeps only its
+// own rows), so each LDS access is t plus a constant: the lanes of a wave
+// touch consecutive words, and no per-point LDS index is held in registers.
+// Because the point is the same in every phase, what a phase needs of the
+// point itself comes from registers: the thread carries its own h^(m+1/2),
+// e^(m+1), the 4-cell material sums, h^(m+3/2) and e^(m+2) of the latest
+// planes, and reads only the +-x / +-y neighbours from LDS.  The materials
+// are needed by the first e-update alone (the second reuses its sums), so
+// h^(m+1/2), eps and sigma are staged for one plane.
 // Iteration k forms e^(m+1) of plane k, h^(m+3/2) of plane k-1, e^(m+2) of
-// plane k-1 and h^(m+5/2) of plane k-2, for k = k0-1 .. k1+1; the halo rows
-// and columns are recomputed by every tile that needs them with the same
-// contraction-pinned point functions as the single-step kernels, so the
-// result is bitwise that of two single steps.  Values outside the grid and
-// on planes outside [0, nz) are zero (PEC), as in the single-step kernels.
+// plane k-1 and h^(m+5/2) of plane k-2, for k = k0-1 .. k1+1, with three
+// barriers (the last h-update reads the e^(m+2) plane written one iteration
+// earlier, double-buffered, so it follows the second e-update without one).
+// The halo rows and columns are recomputed by every tile that needs them
+// with the same contraction-pinned point functions and operand order as the
+// single-step kernels, so the result is bitwise that of two single steps.
+// Values outside the grid and on planes outside [0, nz) are zero (PEC), as
+// in the single-step kernels.
 #include <algorithm>
 
 #include "fit_step_tile.hpp"
@@ -49,8 +57,8 @@ __host__ __device__ inline S2Geom s2_geom(int tw, int ty) {
 
 size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy, bool nu) {
   const S2Geom g = s2_geom(tw, ty);
-  const size_t n = 6 * (size_t)g.N4 + 3 * (size_t)g.N4 + (lossy ? 3 * (size_t)g.N4 : 0) +
-                   6 * (size_t)g.N1 + 6 * (size_t)g.N2 + 6 * (size_t)g.N3 +
+  const size_t n = 3 * (size_t)g.N4 + (size_t)g.N4 + (lossy ? (size_t)g.N4 : 0) +
+                   6 * (size_t)g.N1 + 3 * (size_t)g.N2 + 6 * (size_t)g.N3 +
                    (nu ? 3 * (size_t)kS2ZRing : 0);
   return esz * n;
 }
@@ -96,13 +104,19 @@ __device__ __forceinline__ void pst(T* base, uint32_t off, T v) {
   *(T1*)((C1*)base + off) = v;
 }
 
-// FP32: at most 80 VGPRs (6 waves per SIMD), so that two workgroups of the
-// 32 x 16 tile (11 waves each) are resident per CU.  CTW, CTY > 0 fix the
-// tile at compile time (every LDS offset an immediate), 0 takes it from the
-// tiling.
+// CTW, CTY > 0 fix the tile at compile time (every LDS offset an
+// immediate), 0 takes it from the tiling.  Register budgets: the FP32 32 x 16
+// variant at most 80 VGPRs (6 waves per SIMD: two 11-wave workgroups per CU),
+// the FP64 one at most 168 (3 waves per SIMD: one workgroup, whose LDS is
+// 107 KB, and no spills); generic tiles 128 (up to 1024 threads).
+template <typename T>
+constexpr int s2_waves(bool fixed) { return !fixed ? 4 : sizeof(T) == 4 ? 6 : 3; }
+template <typename T>
+constexpr int s2_max_threads(bool fixed) { return fixed && sizeof(T) == 8 ? 768 : 1024; }
+
 template <typename T, bool LOSSY, bool NU, int CTW, int CTY>
-__global__ __launch_bounds__(1024)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args<T> A) {
+__global__ __launch_bounds__(s2_max_threads<T>(CTW > 0))
+__attribute__((amdgpu_waves_per_eu(s2_waves<T>(CTW > 0)))) void k_step2(S2Args<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   const Dims d = A.d;
@@ -113,27 +127,26 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
   const int kz = (int)(rr / A.t.nty);
   const int TW = CTW > 0 ? CTW : A.t.tw, TY = CTY > 0 ? CTY : A.t.ty;
   const S2Geom G = s2_geom(TW, TY);
-  T* h0L = sm;                                // [2][3][N4]   h^(m+1/2), planes k, k-1
-  T* cL = h0L + 6 * G.N4;                     // [3][N4]      eps0 eps_r, planes k, k-1, k-2
-  T* sL = cL + 3 * G.N4;                      // [3][N4]      sigma (lossy)
-  T* e1L = sL + (LOSSY ? 3 * G.N4 : 0);       // [2][3][N1]   e^(m+1), planes k, k-1
-  T* h1L = e1L + 6 * G.N1;                    // [2][3][N2]   h^(m+3/2), planes k-1, k-2
-  T* e2L = h1L + 6 * G.N2;                    // [2][3][N3]   e^(m+2), planes k-1, k-2
+  T* h0L = sm;                                // [3][N4]      h^(m+1/2) of plane k
+  T* cL = h0L + 3 * G.N4;                     // [N4]         eps0 eps_r V of plane k
+  T* sL = cL + G.N4;                          // [N4]         sigma V of plane k (lossy)
+  T* e1L = sL + (LOSSY ? G.N4 : 0);           // [2][3][N1]   e^(m+1), planes k, k-1
+  T* h1L = e1L + 6 * G.N1;                    // [3][N2]      h^(m+3/2) of plane k-1
+  T* e2L = h1L + 3 * G.N2;                    // [2][3][N3]   e^(m+2), planes k-1, k-2
   T* zL = e2L + 6 * G.N3;                     // tensor grid: [3][kS2ZRing] per-plane factors
 
   const int i0 = tx * TW, j0 = tyi * TY;
   const int k0 = kz * A.t.kc;
   const int k1 = min(k0 + A.t.kc, d.nz);
   const int tid = (int)(threadIdx.x + threadIdx.y * blockDim.x);
-  const int nthr = (int)(blockDim.x * blockDim.y);   // >= N1 >= N2 >= N3 >= TW TY
+  const int nthr = (int)(blockDim.x * blockDim.y);   // >= N1
   const int64_t sx = d.sx, sxy = d.sxy;
 
-  auto hb = [](int k) { return k & 1; };                 // h0 / e1 / h1 / e2 buffer of plane k
-  auto cb = [](int k) { return ((k % 3) + 3) % 3; };     // eps / sigma buffer of plane k
+  auto hb = [](int k) { return k & 1; };   // e1 / e2 buffer of plane k
   auto in_grid = [&](int gx, int gy) { return gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny; };
 
-  // ---- per-thread points (fixed over the z-march); grid points as in-plane
-  // element indices p (gx + sx gy)
+  // ---- the thread's point (x, y) = (t % W - 2, t / W - 1), the same in
+  // every phase; grid points as in-plane element indices p (gx + sx gy)
   // source point: plane sk, in-plane index src_p (none: sk < -1)
   const int64_t sk = A.src_idx >= 0 ? A.src_idx / sxy : -100;   // k >= -1 in the march
   const uint32_t src_p = (uint32_t)(A.src_idx - (sk >= 0 ? sk * sxy : A.src_idx));
@@ -149,44 +162,37 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
     in4[r] = q < G.N4 && in_grid(gx, gy);
     o4[r] = in4[r] ? (uint32_t)(gx + sx * gy) * ES : 0u;
   }
-  // the thread's column x (all phases) and rows: y = row - 1 in R1 / R2,
-  // y = row in R3 / the tile
-  const int row = tid / W, x = tid % W - 2;
-  const int gx = i0 + x, gyA = j0 + row - 1, gyB = j0 + row;
-  // R1 point (e^(m+1)); LDS: R1 index t, its X4 index t + W
+  const int row = tid / W, x = tid % W - 2, y = row - 1;
+  const int gx = i0 + x, gy = j0 + y;
+  const bool ing = in_grid(gx, gy);
+  const uint32_t pg = ing ? (uint32_t)(gx + sx * gy) : 0u;
+  const bool at_s = ing && pg == src_p;
+  // R1 (e^(m+1)): x in [-1, TW+1], y in [-1, TY+1]
   const bool a1 = row < TY + 3 && x >= -1;
-  const bool in1 = a1 && in_grid(gx, gyA);
-  const uint32_t p1 = in1 ? (uint32_t)(gx + sx * gyA) : 0u;
-  const bool s1 = in1 && p1 == src_p;
-  // R2 point (h^(m+3/2)); LDS: R2 / R1 index t, X4 index t + W
+  const bool in1 = a1 && ing;
+  // R2 (h^(m+3/2)): x in [-1, TW], y in [-1, TY]
   const bool a2 = row < TY + 2 && x >= -1 && x <= TW;
-  const bool in2 = a2 && in_grid(gx, gyA);
-  const bool px2 = in2 && gx > 0, py2 = in2 && gyA > 0;
-  // R3 point (e^(m+2)); LDS: R3 index t, R2 / R1 index t + W, X4 index t + 2W
-  const bool a3 = row < TY + 1 && x >= 0 && x <= TW;
-  const bool in3 = a3 && in_grid(gx, gyB);
-  const uint32_t p3 = in3 ? (uint32_t)(gx + sx * gyB) : 0u;
-  const bool s3 = in3 && p3 == src_p;
-  // tile point (h^(m+5/2)) = the R3 point when it lies in the tile; LDS: R3
-  // index t, R2 index t + W
-  const bool own = in3 && x < TW && row < TY;
+  const bool in2 = a2 && ing;
+  // R3 (e^(m+2)): x in [0, TW], y in [0, TY]
+  const bool a3 = row >= 1 && row < TY + 2 && x >= 0 && x <= TW;
+  const bool in3 = a3 && ing;
+  // the tile (h^(m+5/2), stored)
+  const bool own = in3 && x < TW && y < TY;
+  // LDS indices of the point: X4 t + W (neighbours -1: x - 1, -W: y - 1),
+  // R1 and R2 t (+1: x + 1, +W: y + 1), R3 t - W
+  const int i4 = tid + W, i1 = tid, i3 = tid - W;
 
   // ---- tensor-grid metric (as in the single fused step): x / y factors of
-  // each thread's points, z factors of planes k0 - 1 .. k1 + 1 staged in LDS
-  T kbx = A.kb[0], kb1y = A.kb[1], kb3y = A.kb[1];
-  T kd2x = 0, kd2y = 0, kd2z = 0, kd5x = 0, kd5y = 0, kd5z = 0;
+  // the point, z factors of planes k0 - 2 .. k1 + 1 in an LDS ring
+  T kbx = A.kb[0], kby = A.kb[1];
+  T kdxb = 0, kdyb = 0, kdzb = 0;
   if (NU) {
-    const int ix = min(max(gx, 0), d.nx - 1);
-    const int jA = min(max(gyA, 0), d.ny - 1), jB = min(max(gyB, 0), d.ny - 1);
+    const int ix = min(max(gx, 0), d.nx - 1), jy = min(max(gy, 0), d.ny - 1);
     kbx = (T)(A.kbs * A.nsq[0][ix]);
-    kb1y = (T)(A.kbs * A.nsq[1][jA]);
-    kb3y = (T)(A.kbs * A.nsq[1][jB]);
-    kd2x = (T)(A.kds * (0.5 * A.ndl[0][ix] * A.nrw[1][jA]));
-    kd2y = (T)(A.kds * (0.5 * A.ndl[1][jA] * A.nrw[0][ix]));
-    kd2z = (T)(A.kds * (0.5 * A.nrw[0][ix] * A.nrw[1][jA]));
-    kd5x = (T)(A.kds * (0.5 * A.ndl[0][ix] * A.nrw[1][jB]));
-    kd5y = (T)(A.kds * (0.5 * A.ndl[1][jB] * A.nrw[0][ix]));
-    kd5z = (T)(A.kds * (0.5 * A.nrw[0][ix] * A.nrw[1][jB]));
+    kby = (T)(A.kbs * A.nsq[1][jy]);
+    kdxb = (T)(A.kds * (0.5 * A.ndl[0][ix] * A.nrw[1][jy]));
+    kdyb = (T)(A.kds * (0.5 * A.ndl[1][jy] * A.nrw[0][ix]));
+    kdzb = (T)(A.kds * (0.5 * A.nrw[0][ix] * A.nrw[1][jy]));
   }
   // the z factors of plane k sit in ring slot k mod kS2ZRing of zL (kb_z,
   // 1 / w_z, dual width): thread 0 fetches them with the plane and stages
@@ -197,7 +203,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
   auto zs = [](int k) { return k & (ZR - 1); };
   double zraw[3] = {0.0, 0.0, 0.0};
 
-  // ---- register staging of plane k: X4 entries (h x3, eps, sigma), R1 entry (e x3)
+  // ---- register staging of plane k: X4 entries (h x3, eps, sigma), the
+  // point's e^m
   T ph[kS2Per][5];
   T pe[3];
   auto fetch = [&](int k) {
@@ -221,24 +228,21 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
       zraw[2] = plane ? A.ndl[2][k] : 0.0;
     }
     const bool in = plane && in1;
-    const uint32_t o = fresh(p1 * ES);
+    const uint32_t o = fresh(pg * ES);
     pe[0] = in ? pld(A.e0[0] + gk, o) : T(0);
     pe[1] = in ? pld(A.e0[1] + gk, o) : T(0);
     pe[2] = in ? pld(A.e0[2] + gk, o) : T(0);
   };
   auto stage = [&](int k) {
-    T* h = h0L + hb(k) * 3 * G.N4;
-    T* c = cL + cb(k) * G.N4;
-    T* s = sL + cb(k) * G.N4;
 #pragma unroll
     for (int r = 0; r < kS2Per; ++r) {
       const int q = tid + r * nthr;
       if (q < G.N4) {
-        h[q] = ph[r][0];
-        h[G.N4 + q] = ph[r][1];
-        h[2 * G.N4 + q] = ph[r][2];
-        c[q] = ph[r][3];
-        if (LOSSY) s[q] = ph[r][4];
+        h0L[q] = ph[r][0];
+        h0L[G.N4 + q] = ph[r][1];
+        h0L[2 * G.N4 + q] = ph[r][2];
+        cL[q] = ph[r][3];
+        if (LOSSY) sL[q] = ph[r][4];
       }
     }
     if (NU && tid == 0) {
@@ -248,47 +252,36 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
     }
   };
 
-  // e-update of one point of plane k: h planes k (hp) and k-1 (hq) with row
-  // stride NH and indices (rh, rh_im, rh_jm); materials of planes k, k-1 in
-  // the X4 layout at (r, rim, rjm, rijm); same operand order as the
-  // single-step kernels.
-  auto e_upd = [&](bool valid, int gi, int gj, bool at_src, int k, const T* hp, const T* hq, int NH,
-                   int rh, int rh_im, int rh_jm, int r, int rim, int rjm, int rijm, const T* cp,
-                   const T* cq, const T* sp, const T* sq, T exo, T eyo, T ezo, T src, T kbx_,
-                   T kby_, T kbz_, T& exn, T& eyn, T& ezn) {
-    const T c = cp[r], c_im = cp[rim], c_jm = cp[rjm], c_ijm = cp[rijm];
-    const T Sx = c + c_im, Sy = c + c_jm, Sxj = c_jm + c_ijm;
-    const T pc = cq[r];
-    const T sye = pc + cq[rjm], sxe = pc + cq[rim];
-    T E4x = sye + Sy, E4y = sxe + Sx, E4z = Sx + Sxj;
-    T S4x = 0, S4y = 0, S4z = 0;
-    if (LOSSY) {
-      const T s = sp[r], s_im = sp[rim], s_jm = sp[rjm], s_ijm = sp[rijm];
-      const T Sxs = s + s_im, Sys = s + s_jm;
-      const T ps = sq[r];
-      const T sys = ps + sq[rjm], sxs = ps + sq[rim];
-      S4x = sys + Sys;
-      S4y = sxs + Sxs;
-      S4z = Sxs + (s_jm + s_ijm);
-    }
-    T jx = 0, jy = 0, jz = 0;
-    if (valid && at_src) {
-      if (A.src_comp == 0) jx = src;
-      if (A.src_comp == 1) jy = src;
-      if (A.src_comp == 2) jz = src;
-    }
-    if (!valid) E4x = E4y = E4z = T(1);
-    e_point<T, LOSSY>(hp[rh], hp[NH + rh], hp[2 * NH + rh], hq[rh], hq[NH + rh], hp[rh_jm],
-                      hp[NH + rh_im], hp[2 * NH + rh_jm], hp[2 * NH + rh_im], E4x, E4y, E4z,
-                      S4x, S4y, S4z, exo, eyo, ezo, jx, jy, jz, valid && gj > 0 && k > 0,
-                      valid && gi > 0 && k > 0, valid && gi > 0 && gj > 0, kbx_, kby_, kbz_,
-                      A.hs, exn, eyn, ezn);
-  };
+  // ---- values of the point carried from plane to plane (zero below the
+  // chunk's first planes until they are formed):
+  // h^(m+1/2) of the previous plane; the 2-cell sums of eps (sigma) along
+  // x and y of the previous plane (the lower half of the next plane's x / y
+  // edge sums); e^(m+1), its 4-cell sums E4 (S4), h^(m+3/2) and e^(m+2) of
+  // the latest planes formed
+  T hq[3] = {T(0), T(0), T(0)};
+  T Sxq = 0, Syq = 0, Sxsq = 0, Sysq = 0;
+  T e1p[3] = {T(0), T(0), T(0)}, E4p[3] = {T(1), T(1), T(1)}, S4p[3] = {T(0), T(0), T(0)};
+  T h1p[3] = {T(0), T(0), T(0)}, e2p[3] = {T(0), T(0), T(0)};
 
-  // prologue: plane k0 - 2 staged, plane k0 - 1 in flight
+  // prologue: plane k0 - 2 staged for its carried values, plane k0 - 1 in flight
   fetch(k0 - 2);
   stage(k0 - 2);
+  __syncthreads();
+  if (a1) {
+    hq[0] = h0L[i4];
+    hq[1] = h0L[G.N4 + i4];
+    hq[2] = h0L[2 * G.N4 + i4];
+    const T c = cL[i4];
+    Sxq = c + cL[i4 - 1];
+    Syq = c + cL[i4 - W];
+    if (LOSSY) {
+      const T s = sL[i4];
+      Sxsq = s + sL[i4 - 1];
+      Sysq = s + sL[i4 - W];
+    }
+  }
   fetch(k0 - 1);
+  __syncthreads();   // the single staging buffer is read before it is reused
 
   for (int k = k0 - 1; k <= k1 + 1; ++k) {
     stage(k);
@@ -296,100 +289,144 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 4))) void k_step2(S2Args
     if (k + 1 <= k1 + 1) fetch(k + 1);
     __syncthreads();
 
-    // ---- e^(m+1) of plane k on R1
+    // ---- e^(m+1) of plane k on R1 (same operand order as the single step)
+    T e1c[3] = {T(0), T(0), T(0)}, E4c[3] = {T(1), T(1), T(1)}, S4c[3] = {T(0), T(0), T(0)};
+    T hc[3] = {T(0), T(0), T(0)};
+    T Sxc = 0, Syc = 0, Sxsc = 0, Sysc = 0;
     if (a1) {
-      const bool kin = k >= 0 && k < d.nz;
-      T exn, eyn, ezn;
-      e_upd(in1 && kin, gx, gyA, s1 && k == sk, k, h0L + hb(k) * 3 * G.N4,
-            h0L + hb(k - 1) * 3 * G.N4, G.N4, tid + W, tid + W - 1, tid, tid + W, tid + W - 1,
-            tid, tid - 1, cL + cb(k) * G.N4, cL + cb(k - 1) * G.N4, sL + cb(k) * G.N4,
-            sL + cb(k - 1) * G.N4, e0x, e0y, e0z, A.src_val[0], kbx, kb1y,
-            NU ? zL[zs(k)] : A.kb[2], exn, eyn, ezn);
+      const bool valid = in1 && k >= 0 && k < d.nz;
+      hc[0] = h0L[i4];
+      hc[1] = h0L[G.N4 + i4];
+      hc[2] = h0L[2 * G.N4 + i4];
+      const T c = cL[i4], c_im = cL[i4 - 1], c_jm = cL[i4 - W], c_ijm = cL[i4 - W - 1];
+      Sxc = c + c_im;
+      Syc = c + c_jm;
+      const T Sxj = c_jm + c_ijm;
+      E4c[0] = Syq + Syc;
+      E4c[1] = Sxq + Sxc;
+      E4c[2] = Sxc + Sxj;
+      if (LOSSY) {
+        const T s = sL[i4], s_im = sL[i4 - 1], s_jm = sL[i4 - W], s_ijm = sL[i4 - W - 1];
+        Sxsc = s + s_im;
+        Sysc = s + s_jm;
+        S4c[0] = Sysq + Sysc;
+        S4c[1] = Sxsq + Sxsc;
+        S4c[2] = Sxsc + (s_jm + s_ijm);
+      }
+      if (!valid) E4c[0] = E4c[1] = E4c[2] = T(1);
+      T jx = 0, jy = 0, jz = 0;
+      if (valid && at_s && k == sk) {
+        if (A.src_comp == 0) jx = A.src_val[0];
+        if (A.src_comp == 1) jy = A.src_val[0];
+        if (A.src_comp == 2) jz = A.src_val[0];
+      }
+      e_point<T, LOSSY>(hc[0], hc[1], hc[2], hq[0], hq[1], h0L[i4 - W], h0L[G.N4 + i4 - 1],
+                        h0L[2 * G.N4 + i4 - W], h0L[2 * G.N4 + i4 - 1], E4c[0], E4c[1],
+                        E4c[2], S4c[0], S4c[1], S4c[2], e0x, e0y, e0z, jx, jy, jz,
+                        valid && gy > 0 && k > 0, valid && gx > 0 && k > 0,
+                        valid && gx > 0 && gy > 0, kbx, kby, NU ? zL[zs(k)] : A.kb[2],
+                        A.hs, e1c[0], e1c[1], e1c[2]);
       T* out = e1L + hb(k) * 3 * G.N1;
-      out[tid] = exn;
-      out[G.N1 + tid] = eyn;
-      out[2 * G.N1 + tid] = ezn;
+      out[i1] = e1c[0];
+      out[G.N1 + i1] = e1c[1];
+      out[2 * G.N1 + i1] = e1c[2];
     }
     __syncthreads();
 
-    // ---- h^(m+3/2) of plane km = k - 1 on R2 (from e^(m+1) of planes km, k)
+    // ---- h^(m+3/2) of plane km = k - 1 on R2: e^(m+1) of planes km (the
+    // point from registers, its +x / +y neighbours from LDS) and k
     const int km = k - 1;
+    T h1c[3] = {T(0), T(0), T(0)};
     if (km >= k0 - 1 && a2) {
       const T* nq = e1L + hb(km) * 3 * G.N1;
-      const T* np_ = e1L + hb(k) * 3 * G.N1;
-      const T* ho = h0L + hb(km) * 3 * G.N4;
       const bool valid = in2 && km >= 0 && km < d.nz;
       T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
       if (NU) {
         const T rz = zL[ZR + zs(km)];
-        kdx = kd2x * rz;
-        kdy = kd2y * rz;
-        kdz = kd2z * zL[2 * ZR + zs(km)];
+        kdx = kdxb * rz;
+        kdy = kdyb * rz;
+        kdz = kdzb * zL[2 * ZR + zs(km)];
       }
-      T hxn, hyn, hzn;
-      const int c = tid, cin = tid + 1, cjn = tid + W, rh = tid + W;
-      h_point<T>(nq[c], nq[G.N1 + c], nq[2 * G.N1 + c], np_[c], np_[G.N1 + c],
-                 nq[2 * G.N1 + cjn], nq[2 * G.N1 + cin], nq[G.N1 + cin], nq[cjn], ho[rh],
-                 ho[G.N4 + rh], ho[2 * G.N4 + rh], A.imu2, A.imu2, A.imu2, valid && px2,
-                 valid && py2, valid && km > 0, kdx, kdy, kdz, hxn, hyn, hzn);
-      T* out = h1L + hb(km) * 3 * G.N2;
-      out[tid] = hxn;
-      out[G.N2 + tid] = hyn;
-      out[2 * G.N2 + tid] = hzn;
+      h_point<T>(e1p[0], e1p[1], e1p[2], e1c[0], e1c[1], nq[2 * G.N1 + i1 + W],
+                 nq[2 * G.N1 + i1 + 1], nq[G.N1 + i1 + 1], nq[i1 + W], hq[0], hq[1], hq[2],
+                 A.imu2, A.imu2, A.imu2, valid && gx > 0, valid && gy > 0, valid && km > 0,
+                 kdx, kdy, kdz, h1c[0], h1c[1], h1c[2]);
+      h1L[i1] = h1c[0];
+      h1L[G.N2 + i1] = h1c[1];
+      h1L[2 * G.N2 + i1] = h1c[2];
     }
     __syncthreads();
 
-    // ---- e^(m+2) of plane km on R3 (from h^(m+3/2) of planes km, km - 1 and
-    // e^(m+1) of plane km); the tile part of planes [k0, k1) is stored
+    // ---- e^(m+2) of plane km on R3: h^(m+3/2) of planes km (the point from
+    // registers, its -x / -y neighbours from LDS) and km - 1, e^(m+1) and
+    // the 4-cell sums of plane km from registers; the tile part of planes
+    // [k0, k1) is stored
+    T e2c[3] = {T(0), T(0), T(0)};
     if (km >= k0 && a3) {
-      const T* eo = e1L + hb(km) * 3 * G.N1;
-      const bool kin = km >= 0 && km < d.nz;
-      T exn, eyn, ezn;
-      const int o = tid + W;
-      e_upd(in3 && kin, gx, gyB, s3 && km == sk, km, h1L + hb(km) * 3 * G.N2,
-            h1L + hb(km - 1) * 3 * G.N2, G.N2, tid + W, tid + W - 1, tid, tid + 2 * W,
-            tid + 2 * W - 1, tid + W, tid + W - 1, cL + cb(km) * G.N4, cL + cb(km - 1) * G.N4,
-            sL + cb(km) * G.N4, sL + cb(km - 1) * G.N4, eo[o], eo[G.N1 + o], eo[2 * G.N1 + o],
-            A.src_val[1], kbx, kb3y, NU ? zL[zs(km)] : A.kb[2], exn, eyn, ezn);
+      const bool valid = in3 && km >= 0 && km < d.nz;
+      T jx = 0, jy = 0, jz = 0;
+      if (valid && at_s && km == sk) {
+        if (A.src_comp == 0) jx = A.src_val[1];
+        if (A.src_comp == 1) jy = A.src_val[1];
+        if (A.src_comp == 2) jz = A.src_val[1];
+      }
+      e_point<T, LOSSY>(h1c[0], h1c[1], h1c[2], h1p[0], h1p[1], h1L[i1 - W],
+                        h1L[G.N2 + i1 - 1], h1L[2 * G.N2 + i1 - W], h1L[2 * G.N2 + i1 - 1],
+                        E4p[0], E4p[1], E4p[2], S4p[0], S4p[1], S4p[2], e1p[0], e1p[1], e1p[2],
+                        jx, jy, jz, valid && gy > 0 && km > 0, valid && gx > 0 && km > 0,
+                        valid && gx > 0 && gy > 0, kbx, kby, NU ? zL[zs(km)] : A.kb[2], A.hs,
+                        e2c[0], e2c[1], e2c[2]);
       T* out = e2L + hb(km) * 3 * G.N3;
-      out[tid] = exn;
-      out[G.N3 + tid] = eyn;
-      out[2 * G.N3 + tid] = ezn;
+      out[i3] = e2c[0];
+      out[G.N3 + i3] = e2c[1];
+      out[2 * G.N3 + i3] = e2c[2];
       if (own && km < k1) {
         const int64_t gk = sxy * (int64_t)km;
-        const uint32_t o = fresh(p3 * ES);
-        pst(A.e2[0] + gk, o, exn);
-        pst(A.e2[1] + gk, o, eyn);
-        pst(A.e2[2] + gk, o, ezn);
+        const uint32_t o = fresh(pg * ES);
+        pst(A.e2[0] + gk, o, e2c[0]);
+        pst(A.e2[1] + gk, o, e2c[1]);
+        pst(A.e2[2] + gk, o, e2c[2]);
       }
     }
-    __syncthreads();
 
-    // ---- h^(m+5/2) of plane kh = k - 2 on the tile (from e^(m+2) of planes kh, kh + 1)
+    // ---- h^(m+5/2) of plane kh = k - 2 on the tile: e^(m+2) of planes kh
+    // (the point from registers, its +x / +y neighbours from LDS, written one
+    // iteration earlier) and kh + 1 (registers), h^(m+3/2) of plane kh
     const int kh = k - 2;
     if (kh >= k0 && kh < k1 && own) {
       const T* nq = e2L + hb(kh) * 3 * G.N3;
-      const T* np_ = e2L + hb(kh + 1) * 3 * G.N3;
-      const T* ho = h1L + hb(kh) * 3 * G.N2;
       T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
       if (NU) {
         const T rz = zL[ZR + zs(kh)];
-        kdx = kd5x * rz;
-        kdy = kd5y * rz;
-        kdz = kd5z * zL[2 * ZR + zs(kh)];
+        kdx = kdxb * rz;
+        kdy = kdyb * rz;
+        kdz = kdzb * zL[2 * ZR + zs(kh)];
       }
       T hxn, hyn, hzn;
-      const int c = tid, cin = tid + 1, cjn = tid + W, rh = tid + W;
-      h_point<T>(nq[c], nq[G.N3 + c], nq[2 * G.N3 + c], np_[c], np_[G.N3 + c],
-                 nq[2 * G.N3 + cjn], nq[2 * G.N3 + cin], nq[G.N3 + cin], nq[cjn], ho[rh],
-                 ho[G.N2 + rh], ho[2 * G.N2 + rh], A.imu2, A.imu2, A.imu2, gx > 0, gyB > 0,
-                 kh > 0, kdx, kdy, kdz, hxn, hyn, hzn);
+      h_point<T>(e2p[0], e2p[1], e2p[2], e2c[0], e2c[1], nq[2 * G.N3 + i3 + W],
+                 nq[2 * G.N3 + i3 + 1], nq[G.N3 + i3 + 1], nq[i3 + W], h1p[0], h1p[1], h1p[2],
+                 A.imu2, A.imu2, A.imu2, gx > 0, gy > 0, kh > 0, kdx, kdy, kdz, hxn, hyn, hzn);
       const int64_t gk = sxy * (int64_t)kh;
-      const uint32_t o = fresh(p3 * ES);
+      const uint32_t o = fresh(pg * ES);
       pst(A.h2[0] + gk, o, hxn);
       pst(A.h2[1] + gk, o, hyn);
       pst(A.h2[2] + gk, o, hzn);
     }
+
+    // ---- carry the point's values to the next plane
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      hq[c] = hc[c];
+      e1p[c] = e1c[c];
+      E4p[c] = E4c[c];
+      S4p[c] = S4c[c];
+      h1p[c] = h1c[c];
+      e2p[c] = e2c[c];
+    }
+    Sxq = Sxc;
+    Syq = Syc;
+    Sxsq = Sxsc;
+    Sysq = Sysc;
   }
 }
 

@@ -125,8 +125,8 @@ def test_pair_tuning_errors():
     g.close()
     g = FitGrid(16, 16, 16, "f64")
     g.set_materials(np.ones(4096), None, np.full(4096, 0.1))
-    g.set_pair(True)                       # lossy FP64: 64 x 12 and 64 x 8 do not fit
-    assert g.get_pair()[:3] == (True, 32, 16)
+    g.set_pair(True)                       # lossy FP64: 64 x 12 fits (157 KB of LDS)
+    assert g.get_pair()[:3] == (True, 64, 12)
     g.close()
 
 
@@ -147,20 +147,28 @@ def test_autotune_with_pairs_keeps_the_result():
     g2.close()
 
 
-def test_pair_tile_that_stops_fitting_falls_back_to_single_steps():
-    """A pair tile chosen for a lossless FP64 grid (64 x 8) does not fit once
-    the grid turns lossy; stepping then runs single fused steps."""
+def test_pairs_stay_off_where_the_fused_step_does_not_run():
+    """Pairs enabled on a grid whose permeability then varies per cell (the
+    fused kernels take a uniform mu): stepping runs the split kernels only,
+    and switching back to uniform mu runs pairs again."""
     from paper_1705_08019_amd import FitGrid
     n = (30, 20, 10)
     g = FitGrid(*n, "f64")
-    g.set_materials(np.ones(6000))
-    g.set_pair(True, 64, 8, 0)
     g.set_materials(np.ones(6000), None, np.full(6000, 0.1))
+    g.set_pair(True, 64, 8, 0)
+    g.set_materials(np.ones(6000), np.random.default_rng(2).uniform(1, 2, 6000),
+                    np.full(6000, 0.1))
     g.set_fields(np.random.default_rng(1).standard_normal((3, 10, 20, 30)), None, 0)
+    dt = 0.9 * g.cfl_dt()
     g.profile_begin(40)
-    g.step(6, 0.9 * g.cfl_dt())
+    g.step(6, dt)
     prof = g.profile_end()
-    assert prof["pair"][1] == 0 and prof["step"][1] == 6
+    assert prof["pair"][1] == 0 and prof["step"][1] == 0 and prof["epass"][1] == 6
+    g.set_materials(np.ones(6000), None, np.full(6000, 0.1))
+    g.set_tuning("fused")
+    g.profile_begin(40)
+    g.step(6, dt)
+    assert g.profile_end()["pair"][1] == 3
     g.close()
 
 
