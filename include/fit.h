@@ -418,12 +418,13 @@ int fit_get_tuning(const fit_grid* g, int* path, int* tw, int* ty, int* kc);
 /* Two leapfrog steps per pass (temporal blocking of the Sec. II-A
  * recurrence): with enable = 1, fit_step advances pairs of steps with one
  * launch that reads the state and the materials once and keeps the
- * intermediate state on chip, whenever the fused path is active, the grid
- * has uniform spacing, no probe is set and neither step of the pair needs
- * energies for the trace (other steps run singly).  The result is bitwise
- * that of single fused steps.  tw x ty: tile (tw >= 8, ty >= 2, tw ty <=
- * 1024; a workgroup has one thread per point of the tile grown by 3 in x
- * and y, at most 1024; LDS within 160 KiB), kc: planes per chunk (0 = one
+ * intermediate state on chip, whenever the fused path is active (uniform
+ * mu; uniform or tensor-product spacing), no probe is set, neither step of
+ * the pair needs energies for the trace, the tile fits the grid's materials
+ * and a z-plane of the grid spans at most 4 GiB (other steps run singly).
+ * The result is bitwise that of single fused steps.  tw x ty: tile (tw >= 8,
+ * ty >= 2; a workgroup has (tw + 4)(ty + 3) threads rounded up to a multiple
+ * of 64, at most 1024; LDS within 160 KiB), kc: planes per chunk (0 = one
  * round of resident workgroups); tw = ty = 0 takes the first of 64 x 12,
  * 64 x 8, 32 x 16, 32 x 8, 16 x 8 that fits the dtype.
  * Errors: FIT_E_INVALID for an unsupported tile. */

@@ -177,11 +177,12 @@ struct S2Args {
 constexpr int kS2ZRing = 4;
 // nu: tensor grid (per-plane metric ring in LDS).
 size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy, bool nu);
-// Threads of a pair workgroup: enough for one e^(m+1) point each (the
-// largest region), a multiple of 64, at most 1024.
+// Threads of a pair workgroup: one per point of the (tw + 4) x (ty + 3)
+// thread grid (the e^(m+1) region with its row stride), rounded up to a
+// multiple of 64.
 int step2_threads(int tw, int ty);
-// Tile shapes the two-step kernel takes: tw ty a multiple of 64, <= 1024,
-// the staged regions within kS2Per entries per thread, LDS <= 160 KiB.
+// Tile shapes the two-step kernel takes: tw >= 8, ty >= 2, at most 1024
+// threads, the staged plane within kS2Per entries per thread, LDS <= 160 KiB.
 bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, bool nu = false);
 // In-plane byte offsets of the two-step kernel are 32-bit: a plane of the
 // slot layout must span at most 4 GiB.
