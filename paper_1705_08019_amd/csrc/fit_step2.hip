@@ -101,7 +101,10 @@ template <typename T>
 __device__ __forceinline__ void pst(T* base, uint32_t off, T v) {
   using C1 = __attribute__((address_space(1))) char;
   using T1 = __attribute__((address_space(1))) T;
-  *(T1*)((C1*)base + off) = v;
+  // streaming store: the outputs are not read again by this launch, so they
+  // should not take L2 lines from the staged planes the neighbouring tiles
+  // still read (their halos)
+  __builtin_nontemporal_store(v, (T1*)((C1*)base + off));
 }
 
 // CTW, CTY > 0 fix the tile at compile time (every LDS offset an
