@@ -585,6 +585,23 @@ def _counter_by_launch(d, counter):
     return out
 
 
+def summarize_kernels(kt, out_md, cmd_note, title):
+    """Kernel durations of one rocprofv3 --kernel-trace --stats run as
+    profiles/<name>.md (every kernel, by total time)."""
+    stats = sorted(_csv_rows(kt, "_kernel_stats.csv"), key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# rocprofv3 summary: " + os.path.basename(out_md).replace(".md", ""), "", title, "",
+             "Commands (run from the repository root on the MI355X box):", "", "```"]
+    lines += cmd_note + ["```", "", "## Kernel durations (--kernel-trace --stats)", "",
+                         "| kernel | calls | total ms | avg us | min us | max us |",
+                         "|---|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['TotalDurationNs'])/1e6:.2f} | "
+                     f"{float(r['AverageNs'])/1e3:.2f} | {float(r['MinNs'])/1e3:.2f} | "
+                     f"{float(r['MaxNs'])/1e3:.2f} |")
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+
+
 def summarize(kt, fetch, write, cfetch, cwrite, out_md, cells, cmd_note):
     """Turn rocprofv3 outputs into profiles/<name>.md and profiles/traffic_c3.json."""
     stats = _csv_rows(kt, "_kernel_stats.csv")
@@ -649,6 +666,20 @@ def summarize(kt, fetch, write, cfetch, cwrite, out_md, cells, cmd_note):
     print(json.dumps(rec))
 
 
+def run_forms() -> dict:
+    """The batched, adjoint, Gram, ParaExp and graded-grid forms; a failing
+    form is reported, not hidden."""
+    out = {}
+    for name, fn in (("batched", form_batched), ("adjoint", form_adjoint),
+                     ("gram", form_gram), ("paraexp", form_paraexp), ("graded", form_graded)):
+        try:
+            out[name] = fn()
+        except Exception as ex:
+            out[name] = {"error": f"{type(ex).__name__}: {ex}"}
+        print(f"form {name} done", file=sys.stderr, flush=True)
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -663,11 +694,19 @@ def main(argv=None):
                     help="tw,ty,kc of the two-steps-per-launch kernel, or off (default: autotuner)")
     ap.add_argument("--tile", default=None,
                     help="path,ty,kc[,tw] (e.g. fused,16,128,64): skip the autotuner, use this tile")
+    ap.add_argument("--summarize-kernels", nargs=2, metavar=("DIR", "TITLE"), default=None,
+                    help="write --summary-out from one rocprofv3 --kernel-trace --stats run")
+    ap.add_argument("--forms-only", action="store_true",
+                    help="run only the batched / adjoint / Gram / ParaExp / graded forms")
     ap.add_argument("--summarize", nargs=5, metavar="DIR", default=None,
                     help="kt fetch write copyfetch copywrite rocprofv3 output dirs -> profiles/")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "fused_step_c3.md"))
     ap.add_argument("--summary-cmd", action="append", default=[])
     args = ap.parse_args(argv)
+    if args.summarize_kernels:
+        summarize_kernels(args.summarize_kernels[0], args.summary_out, args.summary_cmd,
+                          args.summarize_kernels[1])
+        return
     if args.summarize:
         summarize(*args.summarize, args.summary_out, 256 * 256 * 512, args.summary_cmd)
         return 0
@@ -683,6 +722,9 @@ def main(argv=None):
     torch.cuda.set_device(0)
     if args.calib_copy:
         calib_copy()
+        return 0
+    if args.forms_only:
+        print(json.dumps({"forms": run_forms()}), flush=True)
         return 0
     spec = c3_inputs()
     cells = spec.cells
@@ -753,14 +795,7 @@ def main(argv=None):
     r["grid"].close()
     line["config"]["copy_GBs_read_plus_write"] = measure_copy()
     if not args.no_forms:
-        line["forms"] = {}
-        for name, fn in (("batched", form_batched), ("adjoint", form_adjoint),
-                         ("gram", form_gram), ("paraexp", form_paraexp),
-                         ("graded", form_graded)):
-            try:
-                line["forms"][name] = fn()
-            except Exception as ex:      # a failing form is reported, not hidden
-                line["forms"][name] = {"error": f"{type(ex).__name__}: {ex}"}
+        line["forms"] = run_forms()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline()
     print(json.dumps(line), flush=True)
