@@ -49,7 +49,7 @@ B_ADJ = 4 * (6 + 6 + 9 + 2) + 8 * 2 * 3 * 2    # 188
 
 
 KERNEL_SOURCES = {"step": ("fit_step.hip", "fit_step_tile.hpp", "fit_point.hpp"),
-                  "pair": ("fit_step2.hip", "fit_step_tile.hpp", "fit_point.hpp"),
+                  "pair": ("fit_step2.hip", "fit_step2_tile.hpp", "fit_step_tile.hpp", "fit_point.hpp"),
                   "epass": ("fit_kernels.hip", "fit_point.hpp"),
                   "hpass": ("fit_kernels.hip", "fit_point.hpp")}
 
@@ -195,8 +195,9 @@ def measure_copy(nbytes: int = 1 << 30, reps: int = 5) -> float:
 def form_batched(plain_steps: int = 400):
     """64 FP32 grids, per-axis sizes ~ U{32..96}, 8 dielectric blocks each,
     lossless, random interior source each, 4000 steps: batched launches
-    (graph-captured, autotuned) against plain per-grid launches of the same
-    grids (plain timed over `plain_steps` steps)."""
+    (graph-captured, autotuned: single steps or step pairs) against plain
+    per-grid launches of the same grids (plain timed over `plain_steps`
+    steps)."""
     import torch
     from fit_workloads import c4
     from paper_1705_08019_amd import FitGrid, FitBatch
@@ -219,6 +220,7 @@ def form_batched(plain_steps: int = 400):
     grids, dts = make()
     b = FitBatch(grids)
     ty, kc, _, tw = b.autotune(dts, reps=5)
+    pair_on, pair_kc = b.get_pair()
     b.step(32, dts)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
@@ -250,7 +252,10 @@ def form_batched(plain_steps: int = 400):
             "alg_GBs": round(B_STEP * gb, 1), "frac": round(B_STEP * gb / PEAK_HBM_GBS, 4),
             "plain_per_grid_Gcell_updates_per_s": round(gp, 3),
             "plain_steps_timed": plain_steps, "batched_over_plain": round(gb / gp, 3),
-            "tile": [tw, ty, kc], "launch": "one launch per step of all grids, hipGraph chunks of 16"}
+            "tile": [tw, ty, kc], "pair_kc": pair_kc if pair_on else None,
+            "launch": ("one launch per pair of steps of all grids (32 x 16 tiles), hipGraph "
+                       "chunks of 8 pairs" if pair_on else
+                       "one launch per step of all grids, hipGraph chunks of 16")}
 
 
 def form_adjoint():

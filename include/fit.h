@@ -373,8 +373,20 @@ int fit_batch_set_tuning(fit_batch* b, int tw, int ty, int kc, int steps_per_gra
 int fit_batch_get_tuning(const fit_batch* b, int* tw, int* ty, int* kc, int* steps_per_graph,
                          int* nwg);
 
+/* Two steps of every grid per launch (temporal blocking of the Sec. II-A
+ * recurrence, as fit_set_pair_tuning for one grid): with enable = 1 the
+ * batch advances pairs of steps with one launch of 32 x 16 tiles of every
+ * grid (kc: z-planes per item, 0 = whole columns); an odd last step runs
+ * singly.  Each grid's result stays bitwise identical to fit_step on that
+ * grid alone.  FIT_E_INVALID if the pair tile does not fit the batch's dtype
+ * and materials, or a z-plane of a grid spans more than 4 GiB. */
+int fit_batch_set_pair(fit_batch* b, int enable, int kc);
+int fit_batch_get_pair(const fit_batch* b, int* enable, int* kc);
+
 /* Autotuner: time candidate (tw, ty, kc), row-packed ones included, with
- * `reps` single-step launches each (state unchanged) and keep the fastest.
+ * `reps` single-step launches each (state unchanged) and keep the fastest;
+ * then time step pairs (kc 16, 8, 6, 4) and switch them on when a pair takes
+ * less than 98 % of two single steps (ms_best is then half a pair).
  * dt: host array of nb step sizes. */
 int fit_batch_autotune(fit_batch* b, const double* dt, int reps, int* tw, int* ty, int* kc,
                        float* ms_best);

@@ -79,6 +79,8 @@ SIGNATURES = {
     "fit_batch_create": [C.POINTER(_vp), _i, _vp, C.POINTER(_vp)],
     "fit_batch_destroy": [_vp],
     "fit_batch_set_tuning": [_vp, _i, _i, _i, _i],
+    "fit_batch_set_pair": [_vp, _i, _i],
+    "fit_batch_get_pair": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "fit_batch_get_tuning": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                              C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "fit_batch_autotune": [_vp, _dp, _i, C.POINTER(C.c_int), C.POINTER(C.c_int),

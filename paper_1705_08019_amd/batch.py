@@ -52,6 +52,17 @@ class FitBatch:
         tw, ty, kc, spg, nwg = (x.value for x in v)
         return ty, kc, spg, nwg, tw
 
+    def set_pair(self, enable: bool = True, kc: int = 0):
+        """Two steps of every grid per launch (32 x 16 tiles, kc planes per
+        item, 0: whole columns)."""
+        call("fit_batch_set_pair", self._h, int(bool(enable)), int(kc))
+
+    def get_pair(self):
+        """(enabled, kc)."""
+        e, k = C.c_int(), C.c_int()
+        call("fit_batch_get_pair", self._h, C.byref(e), C.byref(k))
+        return bool(e.value), k.value
+
     def autotune(self, dt, reps: int = 5):
         """Returns (ty, kc, ms_per_step, tw)."""
         a = self._dt(dt)

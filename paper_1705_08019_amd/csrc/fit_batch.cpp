@@ -32,6 +32,14 @@ struct fit_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   int graph_S = 0;
+  bool graph_pairs = false;      // the captured chunk holds pair launches
+  // two steps per launch: 32 x 16 tiles of every grid, pkc planes per item
+  // (0: whole columns)
+  bool pair_on = false;
+  int pkc = 0;
+  int* item_grid2 = nullptr;     // device, P2 entries
+  int P2 = 0;
+  size_t lds2 = 0;
 };
 
 namespace fit {
@@ -42,6 +50,7 @@ static void batch_drop_graph(fit_batch* b) {
   b->exec = nullptr;
   b->graph = nullptr;
   b->graph_S = 0;
+  b->graph_pairs = false;
 }
 
 // Row-packed tile of one grid for `nt` threads: the tile width is the grid's
@@ -110,6 +119,41 @@ static int batch_layout(fit_batch* b) {
   return FIT_OK;
 }
 
+// Tiling of grid d for step pairs.
+static Tiling batch_tiling2(const fit_batch* b, const Dims& d) {
+  const int kc = b->pkc > 0 ? std::min(b->pkc, d.nz) : d.nz;
+  return make_tiling(d, kBatchPairTy, kc, kBatchPairTw);
+}
+
+// The pair item table and LDS size (FIT_E_INVALID if the pair tile does not
+// fit the dtype's LDS or a grid's plane is too large for the kernel).
+static int batch_layout2(fit_batch* b) {
+  const size_t esz = b->f64 ? 8 : 4;
+  const size_t lds = step2_lds_bytes(kBatchPairTw, kBatchPairTy, esz, b->lossy_any, false);
+  if (!step2_shape_ok(kBatchPairTw, kBatchPairTy, esz, b->lossy_any, false))
+    return fail(FIT_E_INVALID, "the pair tile does not fit a workgroup");
+  std::vector<int> items;
+  for (int g = 0; g < b->nb; ++g) {
+    if (!step2_plane_ok(b->grids[g]->d, esz))
+      return fail(FIT_E_INVALID, "a z-plane of a grid spans more than 4 GiB");
+    const Tiling t = batch_tiling2(b, b->grids[g]->d);
+    for (int64_t q = 0; q < t.blocks(); ++q) items.push_back(g);
+  }
+  if (items.size() > (size_t)0x7fffffff) return fail(FIT_E_INVALID, "too many work items");
+  dev_free(reinterpret_cast<void*&>(b->item_grid2));
+  b->P2 = 0;
+  int rc = dev_alloc(reinterpret_cast<void**>(&b->item_grid2), items.size() * sizeof(int),
+                     "pair item table");
+  if (rc) return rc;
+  hipError_t e = hipMemcpy(b->item_grid2, items.data(), items.size() * sizeof(int),
+                           hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(e, "pair item table upload");
+  b->P2 = (int)items.size();
+  b->lds2 = lds;
+  batch_drop_graph(b);
+  return FIT_OK;
+}
+
 // Set a tuning and lay the batch out for it; on failure the previous tuning
 // (and layout) is restored.
 static int batch_retune(fit_batch* b, int tw, int ty, int kc) {
@@ -142,7 +186,7 @@ static int batch_desc(fit_batch* b, const double* dt, int64_t nsteps, bool with_
   }
   std::vector<T> tab;
   if (with_src) tab.assign((size_t)b->nb * (size_t)b->src_cap, T(0));
-  int off = 0;
+  int off = 0, off2 = 0;
   for (int g = 0; g < b->nb; ++g) {
     fit_grid* gr = b->grids[g];
     BatchGrid<T>& D = desc[g];
@@ -173,6 +217,9 @@ static int batch_desc(fit_batch* b, const double* dt, int64_t nsteps, bool with_
     D.ntiles = (int)D.t.blocks();
     D.tile_off = off;
     off += D.ntiles;
+    D.t2 = batch_tiling2(b, gr->d);
+    D.tile_off2 = off2;
+    off2 += (int)D.t2.blocks();
   }
   hipError_t e = hipSuccess;
   if (with_src)
@@ -200,23 +247,41 @@ static BatchArgs<T> batch_args_host(fit_batch* b, int fixed) {
   return a;
 }
 
+// the same for pair launches
+template <typename T>
+static BatchArgs<T> batch_args_pair(fit_batch* b, int fixed) {
+  BatchArgs<T> a = batch_args_host<T>(b, fixed);
+  a.item_grid = b->item_grid2;
+  a.P = b->P2;
+  a.nthreads = step2_threads(kBatchPairTw, kBatchPairTy);
+  a.lds = (int)b->lds2;
+  return a;
+}
+
 template <typename T>
 static int batch_run(fit_batch* b, int64_t nsteps, const double* dt, int use_graph) {
   int rc = batch_desc<T>(b, dt, nsteps, true);
   if (rc) return rc;
-  const int S = std::max(1, b->steps_per_graph);
-  const int64_t chunks = use_graph ? nsteps / S : 0;
-  const int64_t rem = nsteps - chunks * S;
+  // launches: pairs of steps when enabled (an odd last step runs singly)
+  const bool pairs = b->pair_on && b->P2 > 0 && nsteps >= 2;
+  const int64_t npair = pairs ? nsteps / 2 : 0;
+  const int64_t nsingle = nsteps - 2 * npair;
+  const int64_t nlaunch = pairs ? npair : nsteps;   // launches of the graphed kind
+  const int S = std::max(1, pairs ? b->steps_per_graph / 2 : b->steps_per_graph);
+  const int64_t chunks = use_graph ? nlaunch / S : 0;
+  const int64_t rem = nlaunch - chunks * S;
   const BatchArgs<T> a = batch_args_host<T>(b, 0);
+  const BatchArgs<T> a2 = batch_args_pair<T>(b, 0);
+  auto one = [&]() { return pairs ? launch_batch2<T>(a2, b->s) : launch_batch<T>(a, b->s); };
   hipError_t e = launch_batch_set_base(b->ctl, 0, b->s);
   if (e != hipSuccess) return hip_fail(e, "batch step counter");
   if (chunks > 0) {
-    if (!b->exec || b->graph_S != S) {
+    if (!b->exec || b->graph_S != S || b->graph_pairs != pairs) {
       batch_drop_graph(b);
       e = hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "graph capture begin");
       hipError_t el = hipSuccess;
-      for (int q = 0; q < S && el == hipSuccess; ++q) el = launch_batch<T>(a, b->s);
+      for (int q = 0; q < S && el == hipSuccess; ++q) el = one();
       e = hipStreamEndCapture(b->s, &b->graph);
       if (el != hipSuccess) {
         batch_drop_graph(b);
@@ -232,6 +297,7 @@ static int batch_run(fit_batch* b, int64_t nsteps, const double* dt, int use_gra
         return hip_fail(e, "graph instantiate");
       }
       b->graph_S = S;
+      b->graph_pairs = pairs;
     }
     for (int64_t c = 0; c < chunks; ++c) {
       e = hipGraphLaunch(b->exec, b->s);
@@ -239,18 +305,46 @@ static int batch_run(fit_batch* b, int64_t nsteps, const double* dt, int use_gra
     }
   }
   for (int64_t q = 0; q < rem; ++q) {
+    e = one();
+    if (e != hipSuccess) return hip_fail(e, "batch launch");
+  }
+  if (pairs && nsingle > 0) {
     e = launch_batch<T>(a, b->s);
     if (e != hipSuccess) return hip_fail(e, "batch launch");
   }
+  // every launch writes the other buffer set
+  const int64_t launches = pairs ? npair + nsingle : nsteps;
   for (int g = 0; g < b->nb; ++g) {
     fit_grid* gr = b->grids[g];
-    if (nsteps & 1) {
+    if (launches & 1) {
       std::swap(gr->e, gr->e_alt);
       std::swap(gr->h, gr->h_alt);
     }
     gr->m += nsteps;
     gr->smvp += 2 * nsteps;
   }
+  return FIT_OK;
+}
+
+// Time `reps` pair launches (every launch reads the same state).
+template <typename T>
+static int batch_time2(fit_batch* b, const double* dt, int reps, float* ms) {
+  int rc = batch_desc<T>(b, dt, 2, true);
+  if (rc) return rc;
+  const BatchArgs<T> a = batch_args_pair<T>(b, 1);
+  hipEvent_t ev[2];
+  (void)hipEventCreate(&ev[0]);
+  (void)hipEventCreate(&ev[1]);
+  hipError_t e = launch_batch2<T>(a, b->s);
+  if (e == hipSuccess) e = hipEventRecord(ev[0], b->s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = launch_batch2<T>(a, b->s);
+  if (e == hipSuccess) e = hipEventRecord(ev[1], b->s);
+  if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+  if (e == hipSuccess) e = hipEventElapsedTime(ms, ev[0], ev[1]);
+  (void)hipEventDestroy(ev[0]);
+  (void)hipEventDestroy(ev[1]);
+  if (e != hipSuccess) return hip_fail(e, "batch pair timing");
+  *ms /= (float)reps;
   return FIT_OK;
 }
 
@@ -350,6 +444,7 @@ int fit_batch_destroy(fit_batch* b) {
   batch_drop_graph(b);
   dev_free(b->desc);
   dev_free(reinterpret_cast<void*&>(b->item_grid));
+  dev_free(reinterpret_cast<void*&>(b->item_grid2));
   dev_free(reinterpret_cast<void*&>(b->ctl));
   dev_free(b->src_tab);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
@@ -391,6 +486,31 @@ int fit_batch_get_tuning(const fit_batch* b, int* tw, int* ty, int* kc, int* ste
   if (kc) *kc = b->kc;
   if (steps_per_graph) *steps_per_graph = b->steps_per_graph;
   if (nwg) *nwg = b->P;
+  return FIT_OK;
+}
+
+int fit_batch_set_pair(fit_batch* b, int enable, int kc) {
+  if (!b) return fail(FIT_E_INVALID, "null batch");
+  if (enable != 0 && enable != 1) return fail(FIT_E_INVALID, "enable must be 0 or 1");
+  if (kc < 0) return fail(FIT_E_INVALID, "kc must be >= 0 (0: whole columns)");
+  const int okc = b->pkc;
+  b->pkc = kc;
+  if (enable) {
+    int rc = batch_layout2(b);
+    if (rc) {
+      b->pkc = okc;
+      return rc;
+    }
+  }
+  b->pair_on = enable != 0;
+  batch_drop_graph(b);
+  return FIT_OK;
+}
+
+int fit_batch_get_pair(const fit_batch* b, int* enable, int* kc) {
+  if (!b) return fail(FIT_E_INVALID, "null batch");
+  if (enable) *enable = b->pair_on ? 1 : 0;
+  if (kc) *kc = b->pkc;
   return FIT_OK;
 }
 
@@ -465,6 +585,35 @@ int fit_batch_autotune(fit_batch* b, const double* dt, int reps, int* tw, int* t
   b->ty = bty;
   b->kc = bkc;
   int rc2 = batch_layout(b);
+  // two steps per launch: taken when a pair beats two single steps by 2 %
+  // (short z-chunks: the grids are small, so many items are needed to fill
+  // the device)
+  b->pair_on = false;
+  const int pkc_prev = b->pkc;
+  if (!rc && !rc2) {
+    float best_pair = 1e30f;
+    int bpkc = -1;
+    for (int pk : {16, 8, 6, 4}) {
+      b->pkc = pk;
+      if (batch_layout2(b) != FIT_OK) break;   // the pair tile does not fit this batch
+      float ms = 0.f;
+      rc = b->f64 ? batch_time2<double>(b, dt, reps, &ms) : batch_time2<float>(b, dt, reps, &ms);
+      if (rc) break;
+      if (ms < best_pair) {
+        best_pair = ms;
+        bpkc = pk;
+      }
+    }
+    if (!rc && bpkc >= 0 && 0.5f * best_pair < 0.98f * best) {
+      b->pkc = bpkc;
+      rc2 = batch_layout2(b);
+      if (!rc2) {
+        b->pair_on = true;
+        best = 0.5f * best_pair;
+      }
+    }
+  }
+  if (!b->pair_on) b->pkc = pkc_prev;
   int rc3 = batch_leave(b);
   if (rc) return rc;
   if (rc2) return rc2;

@@ -9,6 +9,7 @@
 // are used.  The index of the step within a call lives in device memory and
 // is advanced by a one-thread kernel after every step, so a captured chain of
 // S (step, advance) launches can be replayed as a hipGraph.
+#include "fit_step2_tile.hpp"
 #include "fit_step_tile.hpp"
 
 namespace fit {
@@ -17,11 +18,16 @@ __global__ void k_batch_set_base(BatchCtl* ctl, int64_t base) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ctl->step_base = base;
     ctl->error = 0;
+    ctl->flip = 0;
   }
 }
 
-__global__ void k_batch_advance(BatchCtl* ctl) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) ctl->step_base += 1;
+// after a launch of `steps` steps: the step index and the buffer-set flips
+__global__ void k_batch_advance(BatchCtl* ctl, int steps) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->step_base += steps;
+    ctl->flip += 1;
+  }
 }
 
 template <typename T>
@@ -63,7 +69,7 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs<T> B) {
   const BatchGrid<T>& G = B.grids[g];
   const int t = r - G.tile_off;
   const int64_t sg = B.fixed_parity ? 0 : B.ctl->step_base;   // step index within the call
-  const int p = (int)((G.par0 + sg) & 1);
+  const int p = (int)((G.par0 + (B.fixed_parity ? 0 : B.ctl->flip)) & 1);
   SArgs<T> a;
   batch_args<T>(G, p, G.src_tab ? G.src_tab[sg] : T(0), a);
   const int tx = t % G.t.ntx;
@@ -74,6 +80,49 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs<T> B) {
     step_tile<T, true, false, false>(a, tx, tyi, kz, sm, nullptr, nullptr);
   else
     step_tile<T, false, false, false>(a, tx, tyi, kz, sm, nullptr, nullptr);
+}
+
+// Two steps of every grid: one workgroup per item of the pair item table,
+// i.e. one 32 x 16 tile (with its z-chunk) of one grid, run by the tile body
+// of the single-grid two-step kernel.  Budgets as that kernel's 32 x 16
+// variant.
+template <typename T>
+__global__ __launch_bounds__(sizeof(T) == 8 ? 768 : 1024)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 3))) void k_batch2(BatchArgs<T> B) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const int r = (int)xcd_remap(blockIdx.x, gridDim.x);
+  const int g = B.item_grid[r];
+  const BatchGrid<T>& G = B.grids[g];
+  const int t = r - G.tile_off2;
+  const int64_t sg = B.fixed_parity ? 0 : B.ctl->step_base;
+  const int p = (int)((G.par0 + (B.fixed_parity ? 0 : B.ctl->flip)) & 1);
+  S2Args<T> a;
+  const int64_t n = G.d.n;
+  for (int c = 0; c < 3; ++c) {
+    a.e0[c] = G.e[p] + c * n;
+    a.h0[c] = G.h[p] + c * n;
+    a.e2[c] = G.e[1 - p] + c * n;
+    a.h2[c] = G.h[1 - p] + c * n;
+    a.kb[c] = G.kb[c];
+    a.kd[c] = G.kd[c];
+  }
+  a.eps = G.eps;
+  a.sig = G.sig;
+  a.d = G.d;
+  a.t = G.t2;
+  a.hs = G.hs;
+  a.imu2 = G.imu2;
+  a.src_comp = G.src_comp;
+  a.src_idx = G.src_idx;
+  a.src_val[0] = G.src_tab ? G.src_tab[sg] : T(0);
+  a.src_val[1] = G.src_tab ? G.src_tab[sg + 1] : T(0);
+  const int tx = t % G.t2.ntx;
+  const int rr = t / G.t2.ntx;
+  if (G.lossy)
+    step2_tile<T, true, false, kBatchPairTw, kBatchPairTy>(a, tx, rr % G.t2.nty, rr / G.t2.nty, sm);
+  else
+    step2_tile<T, false, false, kBatchPairTw, kBatchPairTy>(a, tx, rr % G.t2.nty, rr / G.t2.nty, sm);
 }
 
 template <typename T>
@@ -99,7 +148,21 @@ hipError_t launch_batch(const BatchArgs<T>& b, hipStream_t s) {
   hipLaunchKernelGGL(k_batch<T>, dim3((unsigned)b.P), dim3(b.nthreads), (size_t)b.lds, s, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || b.fixed_parity) return e;
-  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, b.ctl);
+  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, b.ctl, 1);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_batch2(const BatchArgs<T>& b, hipStream_t s) {
+  if (b.lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch2<T>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, b.lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_batch2<T>, dim3((unsigned)b.P), dim3(b.nthreads), (size_t)b.lds, s, b);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || b.fixed_parity) return e;
+  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, b.ctl, 2);
   return hipGetLastError();
 }
 
@@ -110,5 +173,7 @@ hipError_t launch_batch_set_base(BatchCtl* ctl, int64_t base, hipStream_t s) {
 
 template hipError_t launch_batch<float>(const BatchArgs<float>&, hipStream_t);
 template hipError_t launch_batch<double>(const BatchArgs<double>&, hipStream_t);
+template hipError_t launch_batch2<float>(const BatchArgs<float>&, hipStream_t);
+template hipError_t launch_batch2<double>(const BatchArgs<double>&, hipStream_t);
 
 }  // namespace fit

@@ -257,7 +257,7 @@ hipError_t launch_adjoint_step(const AdjArgs<T>& a, bool lossy, hipStream_t s);
 struct BatchCtl {
   int64_t step_base;   // index of the next step within the current call
   int error;
-  int pad;
+  int flip;            // launches so far in the call (each swaps the buffer sets)
 };
 
 template <typename T>
@@ -279,7 +279,11 @@ struct BatchGrid {
   int par0;            // buffer set holding the state at the start of the call
   int ntiles;          // tiles per step
   int tile_off;        // offset of this grid's tiles within one step's items
+  Tiling t2;           // step pairs: 32 x 16 tiles (kBatchPairTw x kBatchPairTy)
+  int tile_off2;       // offset of this grid's tiles within one pair launch's items
 };
+// Tile of the batched two-steps-per-launch kernel.
+constexpr int kBatchPairTw = 32, kBatchPairTy = 16;
 
 template <typename T>
 struct BatchArgs {
@@ -298,6 +302,10 @@ struct BatchArgs {
 int batch_prepare(size_t esz, int nthreads, size_t lds);
 template <typename T>
 hipError_t launch_batch(const BatchArgs<T>& b, hipStream_t s);
+// Two steps of every grid per launch (b.item_grid: the pair item table,
+// b.P its length, b.lds the pair LDS); then the counters (+2 steps).
+template <typename T>
+hipError_t launch_batch2(const BatchArgs<T>& b, hipStream_t s);
 hipError_t launch_batch_set_base(BatchCtl* ctl, int64_t base, hipStream_t s);
 
 // Launch wrappers (fit_kernels.hip).  Return hipError_t of the launch.

@@ -1,59 +1,10 @@
-// Two leapfrog steps per pass (temporal blocking of the Sec. II-A
-// recurrence): one launch reads (e^m, h^(m+1/2)) and the materials once and
-// writes (e^(m+2), h^(m+5/2)); the intermediate state (e^(m+1), h^(m+3/2))
-// lives only in LDS.  Per cell and pair of steps this moves the 56 B of one
-// fused step instead of 112 B.
-//
-// A workgroup (as many threads as the e^(m+1) region has points, up to
-// 1024, numbered linearly) owns a TW x TY column tile and marches a chunk [k0, k1) of
-// z-planes with a lag of two planes between what it reads and what it
-// stores.  In local coordinates (x along i, y along j) the regions are
-//   X4: x in [-2, TW+1], y in [-2, TY+1]  staged h^(m+1/2), eps, sigma
-//   R1: x in [-1, TW+1], y in [-1, TY+1]  e^(m+1)       (needs X4)
-//   R2: x in [-1, TW],   y in [-1, TY]    h^(m+3/2)     (needs R1, X4)
-//   R3: x in [0, TW],    y in [0, TY]     e^(m+2)       (needs R2, R1, X4)
-//   tile                                  h^(m+5/2)     (needs R3, R2)
-// Thread t owns the point (x, y) = (t % W - 2, t / W - 1), W = TW + 4, in
-// every phase (each phase runs on the threads whose point lies in its
-// region), and every LDS array has the row stride W (a region keeps only its
-// own rows), so each LDS access is t plus a constant: the lanes of a wave
-// touch consecutive words, and no per-point LDS index is held in registers.
-// Because the point is the same in every phase, what a phase needs of the
-// point itself comes from registers: the thread carries its own h^(m+1/2),
-// e^(m+1), the 4-cell material sums, h^(m+3/2) and e^(m+2) of the latest
-// planes, and reads only the +-x / +-y neighbours from LDS.  The materials
-// are needed by the first e-update alone (the second reuses its sums), so
-// h^(m+1/2), eps and sigma are staged for one plane.
-// Iteration k forms e^(m+1) of plane k, h^(m+3/2) of plane k-1, e^(m+2) of
-// plane k-1 and h^(m+5/2) of plane k-2, for k = k0-1 .. k1+1, with three
-// barriers (the last h-update reads the e^(m+2) plane written one iteration
-// earlier, double-buffered, so it follows the second e-update without one).
-// The halo rows and columns are recomputed by every tile that needs them
-// with the same contraction-pinned point functions and operand order as the
-// single-step kernels, so the result is bitwise that of two single steps.
-// Values outside the grid and on planes outside [0, nz) are zero (PEC), as
-// in the single-step kernels.
+// Launchers and shape rules of the two-steps-per-pass kernel (the tile
+// body is in fit_step2_tile.hpp).
 #include <algorithm>
 
-#include "fit_step_tile.hpp"
+#include "fit_step2_tile.hpp"
 
 namespace fit {
-
-// Row stride W of every region; N4, N1, N2, N3: entries of X4 (ty + 4 rows),
-// R1 (ty + 3), R2 (ty + 2), R3 (ty + 1).
-struct S2Geom {
-  int W, N4, N1, N2, N3;
-};
-
-__host__ __device__ inline S2Geom s2_geom(int tw, int ty) {
-  S2Geom g;
-  g.W = tw + 4;
-  g.N4 = g.W * (ty + 4);
-  g.N1 = g.W * (ty + 3);
-  g.N2 = g.W * (ty + 2);
-  g.N3 = g.W * (ty + 1);
-  return g;
-}
 
 size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy, bool nu) {
   const S2Geom g = s2_geom(tw, ty);
@@ -80,38 +31,10 @@ bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, bool nu) {
   return step2_lds_bytes(tw, ty, esz, lossy, nu) <= 160 * 1024;
 }
 
-// Global access at a wave-uniform plane base plus a per-thread 32-bit byte
-// offset within the plane (the launchers check that a plane spans < 4 GiB):
-// the scalar-base + 32-bit-offset addressing of the global instructions, so
-// that no 64-bit vector address is formed per access.  `fresh` marks a
-// loop-invariant offset as redefined inside the z-march (an empty asm, once
-// per plane); otherwise its zero-extension is hoisted out of the loop and the
-// 64-bit form returns.
-__device__ __forceinline__ uint32_t fresh(uint32_t off) {
-  asm volatile("" : "+v"(off));
-  return off;
-}
-template <typename T>
-__device__ __forceinline__ T pld(const T* base, uint32_t off) {
-  using C1 = const __attribute__((address_space(1))) char;
-  using T1 = const __attribute__((address_space(1))) T;
-  return *(T1*)((C1*)base + off);
-}
-template <typename T>
-__device__ __forceinline__ void pst(T* base, uint32_t off, T v) {
-  using C1 = __attribute__((address_space(1))) char;
-  using T1 = __attribute__((address_space(1))) T;
-  // streaming store: the outputs are not read again by this launch, so they
-  // should not take L2 lines from the staged planes the neighbouring tiles
-  // still read (their halos)
-  __builtin_nontemporal_store(v, (T1*)((C1*)base + off));
-}
-
-// CTW, CTY > 0 fix the tile at compile time (every LDS offset an
-// immediate), 0 takes it from the tiling.  Register budgets: the FP32 32 x 16
-// variant at most 80 VGPRs (6 waves per SIMD: two 11-wave workgroups per CU),
-// the FP64 one at most 168 (3 waves per SIMD: one workgroup, whose LDS is
-// 107 KB, and no spills); generic tiles 128 (up to 1024 threads).
+// Register budgets: the FP32 32 x 16 variant at most 80 VGPRs (6 waves per
+// SIMD: two 11-wave workgroups per CU), the FP64 one at most 168 (3 waves per
+// SIMD: one workgroup, whose LDS is 107 KB, and no spills); generic tiles 128
+// (up to 1024 threads).
 template <typename T>
 constexpr int s2_waves(bool fixed) { return !fixed ? 4 : sizeof(T) == 4 ? 6 : 3; }
 template <typename T>
@@ -121,316 +44,11 @@ template <typename T, bool LOSSY, bool NU, int CTW, int CTY>
 __global__ __launch_bounds__(s2_max_threads<T>(CTW > 0))
 __attribute__((amdgpu_waves_per_eu(s2_waves<T>(CTW > 0)))) void k_step2(S2Args<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
-  const Dims d = A.d;
   const int64_t lt = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = (int)(lt % A.t.ntx);
   const int64_t rr = lt / A.t.ntx;
-  const int tyi = (int)(rr % A.t.nty);
-  const int kz = (int)(rr / A.t.nty);
-  const int TW = CTW > 0 ? CTW : A.t.tw, TY = CTY > 0 ? CTY : A.t.ty;
-  const S2Geom G = s2_geom(TW, TY);
-  T* h0L = sm;                                // [3][N4]      h^(m+1/2) of plane k
-  T* cL = h0L + 3 * G.N4;                     // [N4]         eps0 eps_r V of plane k
-  T* sL = cL + G.N4;                          // [N4]         sigma V of plane k (lossy)
-  T* e1L = sL + (LOSSY ? G.N4 : 0);           // [2][3][N1]   e^(m+1), planes k, k-1
-  T* h1L = e1L + 6 * G.N1;                    // [3][N2]      h^(m+3/2) of plane k-1
-  T* e2L = h1L + 3 * G.N2;                    // [2][3][N3]   e^(m+2), planes k-1, k-2
-  T* zL = e2L + 6 * G.N3;                     // tensor grid: [3][kS2ZRing] per-plane factors
-
-  const int i0 = tx * TW, j0 = tyi * TY;
-  const int k0 = kz * A.t.kc;
-  const int k1 = min(k0 + A.t.kc, d.nz);
-  const int tid = (int)(threadIdx.x + threadIdx.y * blockDim.x);
-  const int nthr = (int)(blockDim.x * blockDim.y);   // >= N1
-  const int64_t sx = d.sx, sxy = d.sxy;
-
-  auto hb = [](int k) { return k & 1; };   // e1 / e2 buffer of plane k
-  auto in_grid = [&](int gx, int gy) { return gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny; };
-
-  // ---- the thread's point (x, y) = (t % W - 2, t / W - 1), the same in
-  // every phase; grid points as in-plane element indices p (gx + sx gy)
-  // source point: plane sk, in-plane index src_p (none: sk < -1)
-  const int64_t sk = A.src_idx >= 0 ? A.src_idx / sxy : -100;   // k >= -1 in the march
-  const uint32_t src_p = (uint32_t)(A.src_idx - (sk >= 0 ? sk * sxy : A.src_idx));
-  constexpr uint32_t ES = sizeof(T);
-  const int W = G.W;
-  // X4 staging entries (up to kS2Per per thread)
-  uint32_t o4[kS2Per];
-  bool in4[kS2Per];
-#pragma unroll
-  for (int r = 0; r < kS2Per; ++r) {
-    const int q = tid + r * nthr;
-    const int gx = i0 + (q % W) - 2, gy = j0 + (q / W) - 2;
-    in4[r] = q < G.N4 && in_grid(gx, gy);
-    o4[r] = in4[r] ? (uint32_t)(gx + sx * gy) * ES : 0u;
-  }
-  const int row = tid / W, x = tid % W - 2, y = row - 1;
-  const int gx = i0 + x, gy = j0 + y;
-  const bool ing = in_grid(gx, gy);
-  const uint32_t pg = ing ? (uint32_t)(gx + sx * gy) : 0u;
-  const bool at_s = ing && pg == src_p;
-  // R1 (e^(m+1)): x in [-1, TW+1], y in [-1, TY+1]
-  const bool a1 = row < TY + 3 && x >= -1;
-  const bool in1 = a1 && ing;
-  // R2 (h^(m+3/2)): x in [-1, TW], y in [-1, TY]
-  const bool a2 = row < TY + 2 && x >= -1 && x <= TW;
-  const bool in2 = a2 && ing;
-  // R3 (e^(m+2)): x in [0, TW], y in [0, TY]
-  const bool a3 = row >= 1 && row < TY + 2 && x >= 0 && x <= TW;
-  const bool in3 = a3 && ing;
-  // the tile (h^(m+5/2), stored)
-  const bool own = in3 && x < TW && y < TY;
-  // LDS indices of the point: X4 t + W (neighbours -1: x - 1, -W: y - 1),
-  // R1 and R2 t (+1: x + 1, +W: y + 1), R3 t - W
-  const int i4 = tid + W, i1 = tid, i3 = tid - W;
-
-  // ---- tensor-grid metric (as in the single fused step): x / y factors of
-  // the point, z factors of planes k0 - 2 .. k1 + 1 in an LDS ring
-  T kbx = A.kb[0], kby = A.kb[1];
-  T kdxb = 0, kdyb = 0, kdzb = 0;
-  if (NU) {
-    const int ix = min(max(gx, 0), d.nx - 1), jy = min(max(gy, 0), d.ny - 1);
-    kbx = (T)(A.kbs * A.nsq[0][ix]);
-    kby = (T)(A.kbs * A.nsq[1][jy]);
-    kdxb = (T)(A.kds * (0.5 * A.ndl[0][ix] * A.nrw[1][jy]));
-    kdyb = (T)(A.kds * (0.5 * A.ndl[1][jy] * A.nrw[0][ix]));
-    kdzb = (T)(A.kds * (0.5 * A.nrw[0][ix] * A.nrw[1][jy]));
-  }
-  // the z factors of plane k sit in ring slot k mod kS2ZRing of zL (kb_z,
-  // 1 / w_z, dual width): thread 0 fetches them with the plane and stages
-  // them with it; a slot is rewritten three planes after its last reader
-  // (the tile h-update of plane k - 2 may still run while plane k + 1 is
-  // staged, so the ring holds four planes)
-  constexpr int ZR = kS2ZRing;
-  auto zs = [](int k) { return k & (ZR - 1); };
-  double zraw[3] = {0.0, 0.0, 0.0};
-
-  // ---- register staging of plane k: X4 entries (h x3, eps, sigma), the
-  // point's e^m
-  T ph[kS2Per][5];
-  T pe[3];
-  auto fetch = [&](int k) {
-    const bool plane = k >= 0 && k < d.nz;
-    const int64_t gk = plane ? sxy * (int64_t)k : 0;
-    const T *bh0 = A.h0[0] + gk, *bh1 = A.h0[1] + gk, *bh2 = A.h0[2] + gk;
-    const T *bc = A.eps + gk, *bs = LOSSY ? A.sig + gk : nullptr;
-#pragma unroll
-    for (int r = 0; r < kS2Per; ++r) {
-      const bool in = plane && in4[r];
-      const uint32_t o = fresh(o4[r]);
-      ph[r][0] = in ? pld(bh0, o) : T(0);
-      ph[r][1] = in ? pld(bh1, o) : T(0);
-      ph[r][2] = in ? pld(bh2, o) : T(0);
-      ph[r][3] = in ? pld(bc, o) : T(0);
-      ph[r][4] = (LOSSY && in) ? pld(bs, o) : T(0);
-    }
-    if (NU && tid == 0) {
-      zraw[0] = plane ? A.nsq[2][k] : 0.0;
-      zraw[1] = plane ? A.nrw[2][k] : 0.0;
-      zraw[2] = plane ? A.ndl[2][k] : 0.0;
-    }
-    const bool in = plane && in1;
-    const uint32_t o = fresh(pg * ES);
-    pe[0] = in ? pld(A.e0[0] + gk, o) : T(0);
-    pe[1] = in ? pld(A.e0[1] + gk, o) : T(0);
-    pe[2] = in ? pld(A.e0[2] + gk, o) : T(0);
-  };
-  auto stage = [&](int k) {
-#pragma unroll
-    for (int r = 0; r < kS2Per; ++r) {
-      const int q = tid + r * nthr;
-      if (q < G.N4) {
-        h0L[q] = ph[r][0];
-        h0L[G.N4 + q] = ph[r][1];
-        h0L[2 * G.N4 + q] = ph[r][2];
-        cL[q] = ph[r][3];
-        if (LOSSY) sL[q] = ph[r][4];
-      }
-    }
-    if (NU && tid == 0) {
-      zL[zs(k)] = (T)(A.kbs * zraw[0]);
-      zL[ZR + zs(k)] = (T)zraw[1];
-      zL[2 * ZR + zs(k)] = (T)zraw[2];
-    }
-  };
-
-  // ---- values of the point carried from plane to plane (zero below the
-  // chunk's first planes until they are formed):
-  // h^(m+1/2) of the previous plane; the 2-cell sums of eps (sigma) along
-  // x and y of the previous plane (the lower half of the next plane's x / y
-  // edge sums); e^(m+1), its 4-cell sums E4 (S4), h^(m+3/2) and e^(m+2) of
-  // the latest planes formed
-  T hq[3] = {T(0), T(0), T(0)};
-  T Sxq = 0, Syq = 0, Sxsq = 0, Sysq = 0;
-  T e1p[3] = {T(0), T(0), T(0)}, E4p[3] = {T(1), T(1), T(1)}, S4p[3] = {T(0), T(0), T(0)};
-  T h1p[3] = {T(0), T(0), T(0)}, e2p[3] = {T(0), T(0), T(0)};
-
-  // prologue: plane k0 - 2 staged for its carried values, plane k0 - 1 in flight
-  fetch(k0 - 2);
-  stage(k0 - 2);
-  __syncthreads();
-  if (a1) {
-    hq[0] = h0L[i4];
-    hq[1] = h0L[G.N4 + i4];
-    hq[2] = h0L[2 * G.N4 + i4];
-    const T c = cL[i4];
-    Sxq = c + cL[i4 - 1];
-    Syq = c + cL[i4 - W];
-    if (LOSSY) {
-      const T s = sL[i4];
-      Sxsq = s + sL[i4 - 1];
-      Sysq = s + sL[i4 - W];
-    }
-  }
-  fetch(k0 - 1);
-  __syncthreads();   // the single staging buffer is read before it is reused
-
-  for (int k = k0 - 1; k <= k1 + 1; ++k) {
-    stage(k);
-    const T e0x = pe[0], e0y = pe[1], e0z = pe[2];
-    if (k + 1 <= k1 + 1) fetch(k + 1);
-    __syncthreads();
-
-    // ---- e^(m+1) of plane k on R1 (same operand order as the single step)
-    T e1c[3] = {T(0), T(0), T(0)}, E4c[3] = {T(1), T(1), T(1)}, S4c[3] = {T(0), T(0), T(0)};
-    T hc[3] = {T(0), T(0), T(0)};
-    T Sxc = 0, Syc = 0, Sxsc = 0, Sysc = 0;
-    if (a1) {
-      const bool valid = in1 && k >= 0 && k < d.nz;
-      hc[0] = h0L[i4];
-      hc[1] = h0L[G.N4 + i4];
-      hc[2] = h0L[2 * G.N4 + i4];
-      const T c = cL[i4], c_im = cL[i4 - 1], c_jm = cL[i4 - W], c_ijm = cL[i4 - W - 1];
-      Sxc = c + c_im;
-      Syc = c + c_jm;
-      const T Sxj = c_jm + c_ijm;
-      E4c[0] = Syq + Syc;
-      E4c[1] = Sxq + Sxc;
-      E4c[2] = Sxc + Sxj;
-      if (LOSSY) {
-        const T s = sL[i4], s_im = sL[i4 - 1], s_jm = sL[i4 - W], s_ijm = sL[i4 - W - 1];
-        Sxsc = s + s_im;
-        Sysc = s + s_jm;
-        S4c[0] = Sysq + Sysc;
-        S4c[1] = Sxsq + Sxsc;
-        S4c[2] = Sxsc + (s_jm + s_ijm);
-      }
-      if (!valid) E4c[0] = E4c[1] = E4c[2] = T(1);
-      T jx = 0, jy = 0, jz = 0;
-      if (valid && at_s && k == sk) {
-        if (A.src_comp == 0) jx = A.src_val[0];
-        if (A.src_comp == 1) jy = A.src_val[0];
-        if (A.src_comp == 2) jz = A.src_val[0];
-      }
-      e_point<T, LOSSY>(hc[0], hc[1], hc[2], hq[0], hq[1], h0L[i4 - W], h0L[G.N4 + i4 - 1],
-                        h0L[2 * G.N4 + i4 - W], h0L[2 * G.N4 + i4 - 1], E4c[0], E4c[1],
-                        E4c[2], S4c[0], S4c[1], S4c[2], e0x, e0y, e0z, jx, jy, jz,
-                        valid && gy > 0 && k > 0, valid && gx > 0 && k > 0,
-                        valid && gx > 0 && gy > 0, kbx, kby, NU ? zL[zs(k)] : A.kb[2],
-                        A.hs, e1c[0], e1c[1], e1c[2]);
-      T* out = e1L + hb(k) * 3 * G.N1;
-      out[i1] = e1c[0];
-      out[G.N1 + i1] = e1c[1];
-      out[2 * G.N1 + i1] = e1c[2];
-    }
-    __syncthreads();
-
-    // ---- h^(m+3/2) of plane km = k - 1 on R2: e^(m+1) of planes km (the
-    // point from registers, its +x / +y neighbours from LDS) and k
-    const int km = k - 1;
-    T h1c[3] = {T(0), T(0), T(0)};
-    if (km >= k0 - 1 && a2) {
-      const T* nq = e1L + hb(km) * 3 * G.N1;
-      const bool valid = in2 && km >= 0 && km < d.nz;
-      T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
-      if (NU) {
-        const T rz = zL[ZR + zs(km)];
-        kdx = kdxb * rz;
-        kdy = kdyb * rz;
-        kdz = kdzb * zL[2 * ZR + zs(km)];
-      }
-      h_point<T>(e1p[0], e1p[1], e1p[2], e1c[0], e1c[1], nq[2 * G.N1 + i1 + W],
-                 nq[2 * G.N1 + i1 + 1], nq[G.N1 + i1 + 1], nq[i1 + W], hq[0], hq[1], hq[2],
-                 A.imu2, A.imu2, A.imu2, valid && gx > 0, valid && gy > 0, valid && km > 0,
-                 kdx, kdy, kdz, h1c[0], h1c[1], h1c[2]);
-      h1L[i1] = h1c[0];
-      h1L[G.N2 + i1] = h1c[1];
-      h1L[2 * G.N2 + i1] = h1c[2];
-    }
-    __syncthreads();
-
-    // ---- e^(m+2) of plane km on R3: h^(m+3/2) of planes km (the point from
-    // registers, its -x / -y neighbours from LDS) and km - 1, e^(m+1) and
-    // the 4-cell sums of plane km from registers; the tile part of planes
-    // [k0, k1) is stored
-    T e2c[3] = {T(0), T(0), T(0)};
-    if (km >= k0 && a3) {
-      const bool valid = in3 && km >= 0 && km < d.nz;
-      T jx = 0, jy = 0, jz = 0;
-      if (valid && at_s && km == sk) {
-        if (A.src_comp == 0) jx = A.src_val[1];
-        if (A.src_comp == 1) jy = A.src_val[1];
-        if (A.src_comp == 2) jz = A.src_val[1];
-      }
-      e_point<T, LOSSY>(h1c[0], h1c[1], h1c[2], h1p[0], h1p[1], h1L[i1 - W],
-                        h1L[G.N2 + i1 - 1], h1L[2 * G.N2 + i1 - W], h1L[2 * G.N2 + i1 - 1],
-                        E4p[0], E4p[1], E4p[2], S4p[0], S4p[1], S4p[2], e1p[0], e1p[1], e1p[2],
-                        jx, jy, jz, valid && gy > 0 && km > 0, valid && gx > 0 && km > 0,
-                        valid && gx > 0 && gy > 0, kbx, kby, NU ? zL[zs(km)] : A.kb[2], A.hs,
-                        e2c[0], e2c[1], e2c[2]);
-      T* out = e2L + hb(km) * 3 * G.N3;
-      out[i3] = e2c[0];
-      out[G.N3 + i3] = e2c[1];
-      out[2 * G.N3 + i3] = e2c[2];
-      if (own && km < k1) {
-        const int64_t gk = sxy * (int64_t)km;
-        const uint32_t o = fresh(pg * ES);
-        pst(A.e2[0] + gk, o, e2c[0]);
-        pst(A.e2[1] + gk, o, e2c[1]);
-        pst(A.e2[2] + gk, o, e2c[2]);
-      }
-    }
-
-    // ---- h^(m+5/2) of plane kh = k - 2 on the tile: e^(m+2) of planes kh
-    // (the point from registers, its +x / +y neighbours from LDS, written one
-    // iteration earlier) and kh + 1 (registers), h^(m+3/2) of plane kh
-    const int kh = k - 2;
-    if (kh >= k0 && kh < k1 && own) {
-      const T* nq = e2L + hb(kh) * 3 * G.N3;
-      T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
-      if (NU) {
-        const T rz = zL[ZR + zs(kh)];
-        kdx = kdxb * rz;
-        kdy = kdyb * rz;
-        kdz = kdzb * zL[2 * ZR + zs(kh)];
-      }
-      T hxn, hyn, hzn;
-      h_point<T>(e2p[0], e2p[1], e2p[2], e2c[0], e2c[1], nq[2 * G.N3 + i3 + W],
-                 nq[2 * G.N3 + i3 + 1], nq[G.N3 + i3 + 1], nq[i3 + W], h1p[0], h1p[1], h1p[2],
-                 A.imu2, A.imu2, A.imu2, gx > 0, gy > 0, kh > 0, kdx, kdy, kdz, hxn, hyn, hzn);
-      const int64_t gk = sxy * (int64_t)kh;
-      const uint32_t o = fresh(pg * ES);
-      pst(A.h2[0] + gk, o, hxn);
-      pst(A.h2[1] + gk, o, hyn);
-      pst(A.h2[2] + gk, o, hzn);
-    }
-
-    // ---- carry the point's values to the next plane
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      hq[c] = hc[c];
-      e1p[c] = e1c[c];
-      E4p[c] = E4c[c];
-      S4p[c] = S4c[c];
-      h1p[c] = h1c[c];
-      e2p[c] = e2c[c];
-    }
-    Sxq = Sxc;
-    Syq = Syc;
-    Sxsq = Sxsc;
-    Sysq = Sysc;
-  }
+  step2_tile<T, LOSSY, NU, CTW, CTY>(A, tx, (int)(rr % A.t.nty), (int)(rr / A.t.nty),
+                                      reinterpret_cast<T*>(smem_raw));
 }
 
 template <typename T, bool L, bool N, int CW, int CY>
