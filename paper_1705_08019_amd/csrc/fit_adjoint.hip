@@ -34,13 +34,27 @@
 
 namespace fit {
 
-template <typename T>
-__device__ __forceinline__ T ald(const T* p, int64_t i) {
-  return ((const __attribute__((address_space(1))) T*)p)[i];
+// Global access at a wave-uniform plane base (scalar registers) plus a
+// per-thread 32-bit byte offset within the plane (fit_adjoint_begin checks
+// that a plane of FP64 values spans < 4 GiB): no 64-bit vector address per
+// access.  `afresh` marks the loop-invariant offset as redefined at each
+// access (an empty asm) so that its zero-extension stays next to the access
+// instead of being hoisted and shared, which brings the 64-bit form back.
+__device__ __forceinline__ uint32_t afresh(uint32_t off) {
+  asm volatile("" : "+v"(off));
+  return off;
 }
 template <typename T>
-__device__ __forceinline__ void ast(T* p, int64_t i, T v) {
-  ((__attribute__((address_space(1))) T*)p)[i] = v;
+__device__ __forceinline__ T ald(const T* base, uint32_t off) {
+  using C1 = const __attribute__((address_space(1))) char;
+  using T1 = const __attribute__((address_space(1))) T;
+  return *(T1*)((C1*)base + afresh(off));
+}
+template <typename T>
+__device__ __forceinline__ void ast(T* base, uint32_t off, T v) {
+  using C1 = __attribute__((address_space(1))) char;
+  using T1 = __attribute__((address_space(1))) T;
+  *(T1*)((C1*)base + afresh(off)) = v;
 }
 
 // 1 / x for x > 0 in FP64: the hardware estimate refined by two Newton steps
@@ -96,6 +110,9 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj(AdjArgs<
   const bool pvalid = (act || hal) && pi < d.nx && pj < d.ny;
   const bool own = act && pvalid;
   const int64_t sx = d.sx, sxy = d.sxy, n = d.n;
+  constexpr uint32_t ES = sizeof(T);
+  // in-plane element index of the point (0 outside the grid)
+  const uint32_t pp = pvalid ? (uint32_t)(pi + sx * pj) : 0u;
 
   auto ring = [&](int x, int y) { return (y + 1) * RW + (x + 1); };
   auto ext = [&](int x, int y) { return y * EW + x; };
@@ -104,31 +121,41 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj(AdjArgs<
   // point values lambda^(m+2) xyz, e^m xyz, e^(m+1) xyz
   T pre[kAdjRing][8];
   T pv[9];
+  // ring entries of this thread: in-plane byte offsets (fixed over the march)
+  uint32_t oring[kAdjRing];
+  bool inring[kAdjRing];
+#pragma unroll
+  for (int r = 0; r < kAdjRing; ++r) {
+    const int q = tid + r * nthr;
+    const int gx = i0 + (q % RW) - 1, gy = j0 + (q / RW) - 1;
+    inring[r] = q < RP && gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny;
+    oring[r] = inring[r] ? (uint32_t)(gx + sx * gy) * ES : 0u;
+  }
   auto fetch_ring = [&](int k) {
+    const bool plane = k >= 0 && k < d.nz;
+    const int64_t gk = plane ? sxy * (int64_t)k : 0;
 #pragma unroll
     for (int r = 0; r < kAdjRing; ++r) {
-      const int q = tid + r * nthr;
-      const int gx = i0 + (q % RW) - 1, gy = j0 + (q / RW) - 1;
-      const bool in = q < RP && k >= 0 && k < d.nz && gx >= 0 && gx < d.nx && gy >= 0 &&
-                      gy < d.ny;
-      const int64_t g = gx + sx * gy + sxy * (int64_t)k;
+      const bool in = plane && inring[r];
+      const uint32_t o = afresh(oring[r]);
 #pragma unroll
       for (int c = 0; c < 3; ++c) {
-        pre[r][c] = in ? ald(A.h, g + c * n) : T(0);
-        pre[r][3 + c] = in ? ald(A.mu0, g + c * n) : T(0);
+        pre[r][c] = in ? ald(A.h + c * n + gk, o) : T(0);
+        pre[r][3 + c] = in ? ald(A.mu0 + c * n + gk, o) : T(0);
       }
-      pre[r][6] = in ? ald(A.eps, g) : T(0);
-      pre[r][7] = (LOSSY && in) ? ald(A.sig, g) : T(0);
+      pre[r][6] = in ? ald(A.eps + gk, o) : T(0);
+      pre[r][7] = (LOSSY && in) ? ald(A.sig + gk, o) : T(0);
     }
   };
   auto fetch_pt = [&](int k) {
     const bool lo = k >= 0 && k < d.nz && pvalid;
-    const int64_t g = pi + sx * pj + sxy * (int64_t)k;
+    const int64_t gk = lo ? sxy * (int64_t)k : 0;
+    const uint32_t o = afresh(pp * ES);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-      pv[c] = lo ? ald(A.lam0, g + c * n) : T(0);
-      pv[3 + c] = lo ? ald(A.em, g + c * n) : T(0);
-      pv[6 + c] = lo ? ald(A.em1, g + c * n) : T(0);
+      pv[c] = lo ? ald(A.lam0 + c * n + gk, o) : T(0);
+      pv[3 + c] = lo ? ald(A.em + c * n + gk, o) : T(0);
+      pv[6 + c] = lo ? ald(A.em1 + c * n + gk, o) : T(0);
     }
   };
   auto stage = [&](T* rL) {
@@ -265,9 +292,10 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj(AdjArgs<
     const bool plane = k < d.nz;
     // the accumulators of cell (i, j, k-1), updated at the end of this iteration
     const bool cell = own && k > k0;
-    const int64_t cidx = pi + sx * pj + sxy * (int64_t)(k - 1);
-    const double ge0 = cell ? ald(A.geps, cidx) : 0.0;
-    const double gs0 = cell ? ald(A.gsig, cidx) : 0.0;
+    const int64_t ck = cell ? sxy * (int64_t)(k - 1) : 0;   // plane of the cell
+    const uint32_t oc = afresh(pp * 8u);
+    const double ge0 = cell ? ald(A.geps + ck, oc) : 0.0;
+    const double gs0 = cell ? ald(A.gsig + ck, oc) : 0.0;
     // ring of plane k: buffer k & 1 (the other one may still be read for k-1)
     T* rL = rL0 + (k & 1) * 8 * RP;
     stage(rL);
@@ -290,9 +318,10 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj(AdjArgs<
         qL[(3 + a) * EP + e] = plane ? qs[a] : 0.0;
       }
       if (plane && own && k < k1) {
-        const int64_t g = pi + sx * pj + sxy * (int64_t)k;
+        const int64_t gk = sxy * (int64_t)k;
+        const uint32_t o = afresh(pp * ES);
 #pragma unroll
-        for (int a = 0; a < 3; ++a) ast(A.lam1, g + a * n, lam[a]);
+        for (int a = 0; a < 3; ++a) ast(A.lam1 + a * n + gk, o, lam[a]);
       }
     }
     if (k + 1 <= k1) fetch_pt(k + 1);   // in flight during the mu update and the cell sums
@@ -304,10 +333,11 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj(AdjArgs<
       const T cx = (tq[2 * EP + e_jn] - tzc) - (tau_o[1] - tyc);
       const T cy = (tau_o[0] - txc) - (tq[2 * EP + e_in] - tzc);
       const T cz = (tq[EP + e_in] - tyc) - (tq[e_jn] - txc);
-      const int64_t gm = pi + sx * pj + sxy * (int64_t)km;
-      ast(A.mu1, gm, pi > 0 ? mux + cx : T(0));
-      ast(A.mu1, gm + n, pj > 0 ? muy + cy : T(0));
-      ast(A.mu1, gm + 2 * n, km > 0 ? muz + cz : T(0));
+      const int64_t gk = sxy * (int64_t)km;
+      const uint32_t o = afresh(pp * ES);
+      ast(A.mu1 + gk, o, pi > 0 ? mux + cx : T(0));
+      ast(A.mu1 + n + gk, o, pj > 0 ? muy + cy : T(0));
+      ast(A.mu1 + 2 * n + gk, o, km > 0 ? muz + cz : T(0));
     }
     __syncthreads();
     // the 12 edges of cell (i, j, k-1): x-edges (i, j..j+1) and y-edges
@@ -322,8 +352,8 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj(AdjArgs<
       const double Zs_k =
           (qL[5 * EP + e] + qL[5 * EP + e_in]) + (qL[5 * EP + e_jn] + qL[5 * EP + e_ijn]);
       if (cell) {
-        ast(A.geps, cidx, ge0 + ((Ae + Ze) + Ae_k));
-        ast(A.gsig, cidx, gs0 + ((As + Zs) + As_k));
+        ast(A.geps + ck, oc, ge0 + ((Ae + Ze) + Ae_k));
+        ast(A.gsig + ck, oc, gs0 + ((As + Zs) + As_k));
       }
       Ae = Ae_k;
       Ze = Ze_k;

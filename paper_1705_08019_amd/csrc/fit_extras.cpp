@@ -209,6 +209,9 @@ int fit_adjoint_begin(fit_grid* g, int64_t nsteps, double dt) {
   }
   fit_adjoint_ws* w = g->adj;
   w->t = adjoint_tiling(g);
+  if ((uint64_t)g->d.sxy * sizeof(double) > (uint64_t)UINT32_MAX)
+    return fail(FIT_E_INVALID, "a z-plane of the grid spans more than 4 GiB of FP64 values "
+                               "(the reverse-step kernel addresses a plane with 32-bit offsets)");
   {
     const int nt = adjoint_threads(w->t.tw, w->t.ty);
     if ((int64_t)(w->t.tw + 2) * (w->t.ty + 2) > kAdjRing * (int64_t)nt || nt > 512 ||
