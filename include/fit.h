@@ -437,8 +437,8 @@ int fit_get_tuning(const fit_grid* g, int* path, int* tw, int* ty, int* kc);
  * The result is bitwise that of single fused steps.  tw x ty: tile (tw >= 8,
  * ty >= 2; a workgroup has (tw + 4)(ty + 3) threads rounded up to a multiple
  * of 64, at most 1024; LDS within 160 KiB), kc: planes per chunk (0 = one
- * round of resident workgroups); tw = ty = 0 takes the first of 64 x 12,
- * 64 x 8, 32 x 16, 32 x 8, 16 x 8 that fits the dtype.
+ * round of resident workgroups); tw = ty = 0 takes the first of 64 x 8,
+ * 32 x 16, 32 x 8, 16 x 8 that fits the dtype.
  * Errors: FIT_E_INVALID for an unsupported tile. */
 int fit_set_pair_tuning(fit_grid* g, int enable, int tw, int ty, int kc);
 /* The pair setting in effect (kc: the chunk a launch would use). */

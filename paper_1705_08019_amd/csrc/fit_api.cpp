@@ -1323,7 +1323,7 @@ int fit_set_pair_tuning(fit_grid* g, int enable, int tw, int ty, int kc) {
   if (enable != 0 && enable != 1) return fail(FIT_E_INVALID, "enable must be 0 or 1");
   if (kc < 0) return fail(FIT_E_INVALID, "kc must be >= 0");
   if (tw == 0 && ty == 0) {   // the first default tile that fits this dtype
-    const int shapes[5][2] = {{64, 12}, {64, 8}, {32, 16}, {32, 8}, {16, 8}};
+    const int shapes[4][2] = {{64, 8}, {32, 16}, {32, 8}, {16, 8}};
     tw = 64;
     ty = 16;
     for (const auto& sh : shapes)

@@ -31,18 +31,19 @@ bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, bool nu) {
   return step2_lds_bytes(tw, ty, esz, lossy, nu) <= 160 * 1024;
 }
 
-// Register budgets: the FP32 32 x 16 variant at most 80 VGPRs (6 waves per
-// SIMD: two 11-wave workgroups per CU), the FP64 one at most 168 (3 waves per
-// SIMD: one workgroup, whose LDS is 107 KB, and no spills); generic tiles 128
-// (up to 1024 threads).
-template <typename T>
-constexpr int s2_waves(bool fixed) { return !fixed ? 4 : sizeof(T) == 4 ? 6 : 3; }
-template <typename T>
-constexpr int s2_max_threads(bool fixed) { return fixed && sizeof(T) == 8 ? 768 : 1024; }
+// Register budgets: the FP32 compile-time tiles at most 80 VGPRs (6 waves
+// per SIMD: two 11- or 12-wave workgroups per CU); the FP64 ones at most 168
+// (3 waves per SIMD: one workgroup of up to 768 threads, no spills); generic
+// tiles 128 (up to 1024 threads).  (A 16-wave 64 x 12 tile would need 64
+// VGPRs for two workgroups per CU and spills there.)
+template <typename T, int CTW, int CTY>
+constexpr int s2_waves() { return CTW == 0 ? 4 : sizeof(T) == 8 ? 3 : 6; }
+template <typename T, int CTW>
+constexpr int s2_max_threads() { return CTW > 0 && sizeof(T) == 8 ? 768 : 1024; }
 
 template <typename T, bool LOSSY, bool NU, int CTW, int CTY>
-__global__ __launch_bounds__(s2_max_threads<T>(CTW > 0))
-__attribute__((amdgpu_waves_per_eu(s2_waves<T>(CTW > 0)))) void k_step2(S2Args<T> A) {
+__global__ __launch_bounds__((s2_max_threads<T, CTW>()))
+__attribute__((amdgpu_waves_per_eu((s2_waves<T, CTW, CTY>())))) void k_step2(S2Args<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t lt = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = (int)(lt % A.t.ntx);
@@ -62,11 +63,12 @@ static hipError_t go_step2_t(const S2Args<T>& a, dim3 grd, dim3 blk, size_t lds,
   return hipGetLastError();
 }
 
-// the 32 x 16 tile (the fastest on 256 x 256 x 512 grids) has its own
-// compile-time variant; other tiles take the generic one
+// the 64 x 8 and 32 x 16 tiles (the fastest on 256 x 256 x 512 grids) have
+// compile-time variants; other tiles take the generic one
 template <typename T, bool L, bool N>
 static hipError_t go_step2(const S2Args<T>& a, dim3 grd, dim3 blk, size_t lds, hipStream_t s) {
   if (a.t.tw == 32 && a.t.ty == 16) return go_step2_t<T, L, N, 32, 16>(a, grd, blk, lds, s);
+  if (a.t.tw == 64 && a.t.ty == 8) return go_step2_t<T, L, N, 64, 8>(a, grd, blk, lds, s);
   return go_step2_t<T, L, N, 0, 0>(a, grd, blk, lds, s);
 }
 

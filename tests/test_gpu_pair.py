@@ -121,12 +121,12 @@ def test_pair_tuning_errors():
     with pytest.raises(FitError, match="INVALID"):
         g.set_pair(True, 64, 16, -1)
     g.set_pair(True)
-    assert g.get_pair()[:3] == (True, 64, 12)
+    assert g.get_pair()[:3] == (True, 64, 8)
     g.close()
     g = FitGrid(16, 16, 16, "f64")
     g.set_materials(np.ones(4096), None, np.full(4096, 0.1))
-    g.set_pair(True)                       # lossy FP64: 64 x 12 fits (157 KB of LDS)
-    assert g.get_pair()[:3] == (True, 64, 12)
+    g.set_pair(True)                       # lossy FP64: 64 x 8 fits (114 KB of LDS)
+    assert g.get_pair()[:3] == (True, 64, 8)
     g.close()
 
 
