@@ -122,20 +122,22 @@ def _window_check_steps(spec, e0, h0, e2, h2, dt, src, origin, step0, steps, w=1
     return np.max(np.abs(eg - eo)) / se, np.max(np.abs(hg - ho)) / sh
 
 
-def test_c3_fullsize_step_pairs_in_the_benchmark_configuration():
-    """The benchmark's launch configuration: two steps per launch on 32 x 16
-    tiles with 64-plane chunks (single steps on 128 x 8 tiles around the
-    trace rows every 50 steps).  47 steps bitwise equal to single fused steps;
+@pytest.mark.parametrize("pair", [(64, 8, 128), (32, 16, 64)])
+def test_c3_fullsize_step_pairs_in_the_benchmark_configuration(pair):
+    """The benchmark's launch configuration: two steps per launch on 64 x 8
+    tiles with 128-plane chunks (the autotuner's choice on this grid; also
+    32 x 16 with 64-plane chunks), single steps on 128 x 8 tiles around the
+    trace rows every 50 steps.  47 steps bitwise equal to single fused steps;
     then one pair on sampled 10^3 windows against the oracle."""
     from paper_1705_08019_amd import FitGrid
     spec = c3()
 
-    def make(pair):
+    def make(on):
         g = FitGrid(spec.nx, spec.ny, spec.nz, "f32")
         g.set_materials(spec.eps_r, spec.mu_r, spec.sigma)
         g.set_tuning("fused", 8, 128, 128)
-        if pair:
-            g.set_pair(True, 32, 16, 64)
+        if on:
+            g.set_pair(True, *pair)
         g.trace_config(spec.energy_every, 64)
         return g
 
@@ -146,7 +148,7 @@ def test_c3_fullsize_step_pairs_in_the_benchmark_configuration():
                sigma_t=s["sigma_t_steps"] * dt)
     for g in (g1, g2):
         g.set_source(2, s["i"], s["j"], s["k"], s["i_max"], src["sigma_t"])
-    print("c3 full size: 47 steps, pairs vs single", flush=True)
+    print(f"c3 full size: 47 steps, pairs {pair} vs single", flush=True)
     g1.profile_begin(200)
     g1.step(47, dt)
     assert g1.profile_end()["pair"][1] >= 22
@@ -165,9 +167,10 @@ def test_c3_fullsize_step_pairs_in_the_benchmark_configuration():
     origins += [(int(rng.integers(s["i"] - 40, s["i"] + 30)),
                  int(rng.integers(s["j"] - 40, s["j"] + 30)),
                  int(rng.integers(s["k"] - 40, s["k"] + 30))) for _ in range(16)]
-    # walls, and windows across the 32 x 16 tile and 64-plane chunk seams
+    # walls, and windows across tile seams (x 32 / 64, y 8 / 16) and chunk
+    # seams (z 64 / 128)
     origins += [(0, 0, 0), (spec.nx - 10, spec.ny - 10, spec.nz - 10), (27, 11, 59),
-                (123, 43, 187)]
+                (123, 43, 187), (59, 5, 123)]
     print("c3 full size: pair windows vs oracle", flush=True)
     for o in origins:
         de, dh = _window_check_steps(spec, e0, h0, e2, h2, dt, src, o, 47, 2)
