@@ -21,6 +21,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import platform
@@ -55,13 +56,17 @@ KERNEL_SOURCES = {"step": ("fit_step.hip", "fit_step_tile.hpp", "fit_point.hpp")
 
 
 def kernel_source_hash(tag: str) -> str:
-    """Hash of the sources a kernel is compiled from (its counters go stale
-    when they change)."""
+    """Hash of the code a kernel is compiled from, comments and blank space
+    left out (its counters go stale when the code changes, not when a
+    comment does)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1705_08019_amd", "csrc")
     for f in KERNEL_SOURCES[tag]:
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(csrc, f)) as fh:
+            text = fh.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

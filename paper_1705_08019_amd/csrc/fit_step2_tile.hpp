@@ -4,10 +4,10 @@
 // lives only in LDS.  Per cell and pair of steps this moves the 56 B of one
 // fused step instead of 112 B.
 //
-// A workgroup (as many threads as the e^(m+1) region has points, up to
-// 1024, numbered linearly) owns a TW x TY column tile and marches a chunk [k0, k1) of
-// z-planes with a lag of two planes between what it reads and what it
-// stores.  In local coordinates (x along i, y along j) the regions are
+// A workgroup ((TW + 4)(TY + 3) threads rounded up to a multiple of 64, at
+// most 1024, numbered linearly) owns a TW x TY column tile and marches a
+// chunk [k0, k1) of z-planes with a lag of two planes between what it reads
+// and what it stores.  In local coordinates (x along i, y along j) the regions are
 //   X4: x in [-2, TW+1], y in [-2, TY+1]  staged h^(m+1/2), eps, sigma
 //   R1: x in [-1, TW+1], y in [-1, TY+1]  e^(m+1)       (needs X4)
 //   R2: x in [-1, TW],   y in [-1, TY]    h^(m+3/2)     (needs R1, X4)
