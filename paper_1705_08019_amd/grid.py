@@ -339,7 +339,7 @@ class FitGrid:
         if not (isinstance(X, torch.Tensor) and X.is_cuda):
             raise ValueError("X must be a device tensor")
         K = X.shape[0]
-        Xc = X.to(self.tdtype).reshape(K, -1).contiguous()
+        Xc = X.to(self.tdtype).reshape(K, int(np.prod(X.shape[1:]))).contiguous()
         if Xc.shape[1] != 3 * self.cells:
             raise ValueError("each snapshot must have 3 * nx * ny * nz values")
         G = np.empty((K, K), dtype=np.float64)

@@ -65,3 +65,35 @@ def test_batch_pair_errors_and_autotune():
     _assert_equal(_fields(gb), before)
     assert all(g.step_index == 10 for g in gb)
     b.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_zero_steps_change_nothing(dtype):
+    """A step count of 0 is a valid empty call (fields, step index and SMVP count
+    unchanged) for one grid and for a batch; a negative count is rejected and
+    leaves the state as it was."""
+    from paper_1705_08019_amd import FitBatch, FitError
+    specs = c4_small(count=3, nsteps=0)
+    gb, dts = _make(specs, dtype, lossy_every=2)
+    b = FitBatch(gb)
+    b.set_pair(True, 0)
+    b.step(3, dts)
+    before = _fields(gb)
+    idx = [g.step_index for g in gb]
+    smvp = [g.smvp_count() for g in gb]
+    for n in (0, -1):
+        if n < 0:
+            with pytest.raises(FitError, match="INVALID"):
+                b.step(n, dts)
+            with pytest.raises(FitError, match="INVALID"):
+                gb[0].step(n, dts[0])
+        else:
+            b.step(n, dts)
+            b.step(n, dts, use_graph=False)
+            gb[1].step(n, dts[1])
+        _assert_equal(_fields(gb), before)
+        assert [g.step_index for g in gb] == idx
+        assert [g.smvp_count() for g in gb] == smvp
+    b.step(2, dts)                                # still usable afterwards
+    assert [g.step_index for g in gb] == [i + 2 for i in idx]
+    b.close()

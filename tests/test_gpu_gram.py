@@ -51,3 +51,32 @@ def test_gram_cavity_modes_closed_form():
         X.append(arr)
     G = g.gram(torch.tensor(np.array(X), device="cuda"), 0)
     np.testing.assert_allclose(G, np.eye(5) * (nx / 2) * (nz / 2) * ny, rtol=0, atol=1e-10)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_gram_largest_K_sampled(dtype):
+    """K = 4096 snapshots (the largest accepted): entries on a sample of rows and
+    columns that includes the first and the last snapshot match the oracle's
+    exactly rounded sums (G restricted to a subset S of snapshots is the Gram
+    matrix of S); K = 0 and K = 4097 are rejected."""
+    from paper_1705_08019_amd import FitGrid, FitError
+    nx, ny, nz, K = 6, 5, 4, 4096
+    rng = np.random.default_rng(11)
+    eps = rng.uniform(1, 5, (nz, ny, nx))
+    ops = oracle_ops((nx, ny, nz), eps=eps)
+    g = FitGrid(nx, ny, nz, dtype)
+    g.set_materials(eps)
+    X = rng.standard_normal((K, 3, nz, ny, nx))
+    if dtype == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+    print(f"gram K={K} {dtype}", flush=True)
+    G = g.gram(torch.tensor(X, device="cuda"), 0)
+    assert np.array_equal(G, G.T)
+    S = np.unique(np.concatenate([[0, 1, K - 2, K - 1], rng.choice(K, 60, replace=False)]))
+    Xo = np.array([edges_from_slots(ops, X[s]) for s in S])
+    ref = gram(Xo, ops.M_eps)
+    tol = 1e-13 if dtype == "f64" else 1e-6
+    np.testing.assert_allclose(G[np.ix_(S, S)], ref, rtol=0, atol=tol * np.max(np.abs(ref)))
+    for bad in (0, K + 1):
+        with pytest.raises(FitError, match="INVALID"):
+            g.gram(torch.zeros((bad, 3, nz, ny, nx), device="cuda"), 0)
