@@ -772,13 +772,14 @@ def main(argv=None):
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
                 "traffic": (None if load_traffic(tkey) is None
                             else load_traffic(tkey)["bytes_per_launch"]),
-                # secondary roofline: measured HBM bytes over the launch time
+                # secondary figure: counted L2-miss bytes (to the Infinity Cache or
+                # HBM) over the launch time
                 "traffic_GBs": (None if load_traffic(tkey) is None else round(
                     load_traffic(tkey)["bytes_per_launch"] / (avg / 1e3) / 1e9, 1)),
                 "traffic_frac": (None if load_traffic(tkey) is None else round(
                     load_traffic(tkey)["bytes_per_launch"] / (avg / 1e3) / 1e9 / PEAK_HBM_GBS,
                     4)),
-                "traffic_unit": "bytes per launch (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, "
+                "traffic_unit": "L2-miss bytes per launch (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, "
                                 "scaled by a 1 GiB copy; profiles/traffic_c3.json)",
                 "alg_bytes_per_launch": kb * cells, "alg_bytes_per_cell": kb,
                 "avg_launch_ms": round(avg, 5), "launches_timed": st_n,
