@@ -126,3 +126,15 @@ def test_host_tolerance_equals_the_oracle(lib):
         assert math.isclose(t.value, expm.optimal_tolerance(beta, dt, rho), rel_tol=1e-15)
     assert lib.fit_expm_tolerance(-1.0, 0.5, 3.5, C.byref(t)) == -1
     assert lib.fit_expm_tolerance(1.0, 0.5, float("nan"), C.byref(t)) == -1
+
+
+def test_missing_library_fails_loudly(monkeypatch, tmp_path):
+    """Without libfit.so the binding raises at the first call: there is no
+    fallback path that would compute anything elsewhere."""
+    from paper_1705_08019_amd import _lib
+    monkeypatch.setattr(_lib, "LIB_PATH", str(tmp_path / "libfit.so"))
+    monkeypatch.setattr(_lib, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.lib()
+    with pytest.raises(RuntimeError, match="missing"):
+        _lib.call("fit_version")
