@@ -293,40 +293,61 @@ void k_gram(GramArgs<T> A) {
 
 // Sum the per-workgroup blocks entry by entry (Neumaier), write G rows
 // a0.. and columns b0.. of the K x K output (and the mirrored entries).
-// Entries of tiles the Gram kernel did not form (beyond na / nb, below the
-// tile diagonal of a diagonal block) are never read.
-__global__ __launch_bounds__(256) void k_gram_reduce(const double* part, int64_t nwg, double* G,
-                                                     int K, int a0, int na, int b0, int nb) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= kGramBlk * kGramBlk) return;
-  const int i = e / kGramBlk, j = e % kGramBlk;
-  if (i >= na || j >= nb) return;
-  if (a0 == b0 && (i / 16) > (j / 16)) return;
+// One workgroup per row i of the block; lane j of every wave holds entry
+// (i, j), and wave v sums the blocks v, v + 16, v + 32, ... (each load of a
+// wave reads 64 consecutive doubles of one block); the 16 wave sums are then
+// combined in wave order, so the result does not depend on timing.  Entries
+// of tiles the Gram kernel did not form (beyond na / nb, below the tile
+// diagonal of a diagonal block) are never read.
+constexpr int kGramRedWaves = 16;
+__global__ __launch_bounds__(64 * kGramRedWaves) void k_gram_reduce(const double* part,
+                                                                   int64_t nwg, double* G, int K,
+                                                                   int a0, int na, int b0,
+                                                                   int nb) {
+  __shared__ double rs[kGramRedWaves][kGramBlk], rc[kGramRedWaves][kGramBlk];
+  const int i = blockIdx.x;            // < na
+  const int j = threadIdx.x & 63;
+  const int v = threadIdx.x >> 6;
+  const bool live = j < nb && !(a0 == b0 && (i / 16) > (j / 16));
+  const int e = i * kGramBlk + j;
   double s = 0.0, c = 0.0;
-  int64_t w = 0;
-  for (; w + 8 <= nwg; w += 8) {
-    double x[8];
+  if (live) {
+    int64_t w = v;
+    for (; w + 7 * kGramRedWaves < nwg; w += 8 * kGramRedWaves) {
+      double x[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) x[q] = part[(w + q) * kGramBlk * kGramBlk + e];
+      for (int q = 0; q < 8; ++q) x[q] = part[(w + q * kGramRedWaves) * kGramBlk * kGramBlk + e];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const double t = s + x[q];
-      c += (fabs(s) >= fabs(x[q])) ? ((s - t) + x[q]) : ((x[q] - t) + s);
+      for (int q = 0; q < 8; ++q) {
+        const double t = s + x[q];
+        c += (fabs(s) >= fabs(x[q])) ? ((s - t) + x[q]) : ((x[q] - t) + s);
+        s = t;
+      }
+    }
+    for (; w < nwg; w += kGramRedWaves) {
+      const double x = part[w * kGramBlk * kGramBlk + e];
+      const double t = s + x;
+      c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
       s = t;
     }
   }
-  for (; w < nwg; ++w) {
-    const double x = part[w * kGramBlk * kGramBlk + e];
+  rs[v][j] = s;
+  rc[v][j] = c;
+  __syncthreads();
+  if (v != 0 || !live) return;
+  for (int u = 1; u < kGramRedWaves; ++u) {
+    const double x = rs[u][j];
     const double t = s + x;
     c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
     s = t;
+    c += rc[u][j];
   }
-  const double v = s + c;
+  const double val = s + c;
   // in a diagonal block only the upper triangle writes (and mirrors), so
   // every entry has exactly one writer
   if (a0 == b0 && i > j) return;
-  G[(int64_t)(a0 + i) * K + (b0 + j)] = v;
-  G[(int64_t)(b0 + j) * K + (a0 + i)] = v;
+  G[(int64_t)(a0 + i) * K + (b0 + j)] = val;
+  G[(int64_t)(b0 + j) * K + (a0 + i)] = val;
 }
 
 // One launch of a block pair: as many workgroups as are resident at once
@@ -393,8 +414,8 @@ hipError_t launch_gram(const T* X, int64_t ld, int K, const double* W, const Dim
       }
       if (e != hipSuccess) return e;
       *nwg_used = std::max(*nwg_used, nwg);
-      hipLaunchKernelGGL(k_gram_reduce, dim3(kGramBlk * kGramBlk / 256), dim3(256), 0, s, part,
-                         nwg, G, K, a0, A.na, b0, A.nb);
+      hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)A.na), dim3(64 * kGramRedWaves), 0, s,
+                         part, nwg, G, K, a0, A.na, b0, A.nb);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
