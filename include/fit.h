@@ -27,11 +27,18 @@
  * Dtype.  Fields and stencils run in FIT_F32 or FIT_F64; every reduction
  *         (energies, probe objective, Gram entries, adjoint gradients)
  *         accumulates in FP64 with compensated summation.
- * Memory. The library allocates (hipMalloc) and owns every device buffer it
- *         needs (fields, materials, partial sums, trace, adjoint state).
- *         Pointers passed in are borrowed for the duration of the call only.
- *         "device" pointers must be device memory of the current HIP device;
- *         "host" pointers ordinary host memory.
+ * Memory. The large device buffers -- both field buffer sets, the per-cell
+ *         material arrays and the adjoint state -- can be storage of the
+ *         caller's (e.g. PyTorch tensors) that the library borrows by pointer
+ *         (fit_bind_fields, fit_bind_materials, fit_adjoint_bind) and never
+ *         frees; the caller keeps them alive until they are unbound or the
+ *         handle is destroyed.  Unbound roles are allocated (hipMalloc) and
+ *         owned by the library, as are the small reduction scratch (partial
+ *         sums, trace rows, probe rows) and the optional workspaces of the
+ *         Gram and exponential entry points.  Other pointers passed in are
+ *         borrowed for the duration of the call only.  "device" pointers must
+ *         be device memory of the current HIP device; "host" pointers
+ *         ordinary host memory.
  * Streams. All work is enqueued on the stream given at creation (NULL =
  *         the default stream).  Calls that return host data synchronise that
  *         stream; the others return once the work is enqueued.
@@ -132,6 +139,37 @@ int fit_set_source(fit_grid* g, int axis, int i, int j, int k, double i_max,
  * sqrt(eps mu / (dx^-2 + dy^-2 + dz^-2)).  Writes *dt_cfl. */
 int fit_cfl_dt(const fit_grid* g, double* dt_cfl);
 
+/* Borrow caller-owned device storage for the fields (initial values and the
+ * leapfrog recurrence of Sec. II-A live there).  e, h: the buffers of the
+ * state (e^(m), h^(m+1/2)); e_alt, h_alt: the second buffer set the fused and
+ * two-step kernels write (both NULL: the library allocates its own on first
+ * use).  Each is 3*nx*ny*nz elements of the grid's dtype in the slot layout,
+ * 16-byte aligned, and no two overlap.  The current state is copied into
+ * (e, h), so binding does not change it.  The two sets swap roles as steps
+ * run: fit_get_state tells which buffers hold the state; the other set's
+ * contents are scratch between calls.  All four NULL returns the state to
+ * library-owned buffers (do this before freeing bound storage while the
+ * handle lives).  Synchronises.  Errors: FIT_E_INVALID (only one of e, h or
+ * of e_alt, h_alt given, misaligned or overlapping buffers, a buffer the
+ * library owns), FIT_E_OOM. */
+int fit_bind_fields(fit_grid* g, void* e, void* h, void* e_alt, void* h_alt);
+
+/* Borrow caller-owned device storage for the per-cell material arrays the
+ * kernels read (M_eps, M_sigma, M_mu^{-1} are formed from them, eq.
+ * maxwell_grid3): eps, sigma and imu, each nx*ny*nz elements of the grid's
+ * dtype, 16-byte aligned, disjoint.  The current materials are written into
+ * them now and by every later fit_set_materials / fit_set_spacing (eps0 eps_r,
+ * sigma and 1/(mu0 mu_r) per cell, times the cell volume on a tensor grid;
+ * sigma and imu are written only when some sigma != 0 or mu varies).  All
+ * three NULL returns to library-owned arrays.  Synchronises.
+ * Errors: FIT_E_INVALID, FIT_E_OOM. */
+int fit_bind_materials(fit_grid* g, void* eps, void* sigma, void* imu);
+
+/* Device pointers of the buffers holding the current state e^(m),
+ * h^(m+1/2) (bound or library-owned; valid until the next call that steps
+ * or rebinds). */
+int fit_get_state(const fit_grid* g, void** e, void** h);
+
 /* Set the state e^(m), h^(m+1/2) and the step counter m.  e, h: 3*nx*ny*nz
  * values each in the slot layout and the grid's dtype; on_device != 0 means
  * device pointers, else host pointers.  Either pointer may be NULL (that
@@ -163,10 +201,21 @@ int fit_apply_curl(fit_grid* g, int which, const void* in, void* out);
  * accumulated when a probe is set.  Asynchronous. */
 int fit_step(fit_grid* g, int64_t nsteps, double dt);
 
-/* Energies of the current state (eq. energy, m = n): out[0] = <e^m, e^m>_eps,
- * out[1] = <h^(m+1/2), h^(m+1/2)>_mu, FP64.  Synchronises.
- * Returns FIT_E_DIVERGED (with out filled) if either is not finite. */
-int fit_energy(fit_grid* g, double out[2]);
+/* Energies of the current state e^m, h^(m+1/2) (eq. energy), FP64:
+ *   out[0] = <e^m, e^m>_eps,   out[1] = <h^(m+1/2), h^(m+1/2)>_mu,
+ *   out[2] = W^m = <e^m, (e^m + e^(m+1))/2>_eps + <(h^(m-1/2) + h^(m+1/2))/2, h^(m+1/2)>_mu,
+ *            the energy the lossless, source-free recurrence conserves,
+ *   out[3] = Q^m = <e^m, e^m>_eps + <h^(m-1/2), h^(m+1/2)>_mu,
+ *   out[4] = Q^(m+1) - Q^m = -2 dt ebar . (M_sigma ebar + j_s(t_(m+1/2))),
+ *            ebar = (e^m + e^(m+1))/2: the exact discrete energy balance of
+ *            the step that starts at the current state (0 when lossless and
+ *            source-free).
+ * e^(m+1) is the e-update of the current state and h^(m-1/2) the h-update run
+ * backwards (h^(m+1/2) + dt M_mu^{-1} C e^m), both formed in the second field
+ * buffer set with dt of the handle's last fit_step or fit_step_record; before
+ * any step out[2..4] are NaN.  Synchronises.  Returns FIT_E_DIVERGED (with out
+ * filled) if out[0] or out[1] is not finite. */
+int fit_energy(fit_grid* g, double out[5]);
 
 /* Energy trace.  every > 0 records one row for each step m with
  * m % every == 0 (every = 0 disables); up to `capacity` rows are kept
@@ -241,6 +290,15 @@ int fit_adjoint_set_tuning(fit_grid* g, int tw, int ty, int kc);
 /* The reverse-step tile the next fit_adjoint_begin will use (the one set, or
  * the defaults for this grid and device).  Errors: FIT_E_INVALID. */
 int fit_adjoint_get_tuning(const fit_grid* g, int* tw, int* ty, int* kc);
+
+/* Borrow caller-owned device storage for the adjoint state: lam0, lam1,
+ * mu0, mu1 (3*nx*ny*nz elements of the grid's dtype each, the ping-pong
+ * buffers of lambda and mu) and gcell (2*nx*ny*nz doubles: the per-cell
+ * dJ/deps_r and dJ/dsigma accumulators), 16-byte aligned and disjoint.  Ends
+ * any reverse sweep in progress; all five NULL returns to library-owned
+ * storage at the next fit_adjoint_begin.  Synchronises.
+ * Errors: FIT_E_INVALID, FIT_E_OOM. */
+int fit_adjoint_bind(fit_grid* g, void* lam0, void* lam1, void* mu0, void* mu1, double* gcell);
 
 /* Start a reverse sweep over a forward horizon of nsteps steps taken with dt:
  * clears lambda, mu and the accumulated sensitivities.  Errors: FIT_E_STATE

@@ -46,6 +46,10 @@ SIGNATURES = {
     "fit_set_spacing": [_vp, _dp, _dp, _dp],
     "fit_set_source": [_vp, _i, _i, _i, _i, _d, _d],
     "fit_cfl_dt": [_vp, _dp],
+    "fit_bind_fields": [_vp, _vp, _vp, _vp, _vp],
+    "fit_bind_materials": [_vp, _vp, _vp, _vp],
+    "fit_get_state": [_vp, C.POINTER(_vp), C.POINTER(_vp)],
+    "fit_adjoint_bind": [_vp, _vp, _vp, _vp, _vp, _vp],
     "fit_set_fields": [_vp, _vp, _vp, _i64, _i],
     "fit_get_fields": [_vp, _vp, _vp, _i],
     "fit_get_step": [_vp, _i64p],

@@ -402,7 +402,16 @@ int ensure_alt(fit_grid* g) {
     dev_free(g->e_alt);
     dev_free(g->h_alt);
   }
+  g->bor_ealt = g->bor_halt = false;
+  g->storage_version++;
   return rc;
+}
+
+void swap_sets(fit_grid* g) {
+  std::swap(g->e, g->e_alt);
+  std::swap(g->h, g->h_alt);
+  std::swap(g->bor_e, g->bor_ealt);
+  std::swap(g->bor_h, g->bor_halt);
 }
 
 template <typename T>
@@ -412,8 +421,7 @@ int step_fused(fit_grid* g, double dt) {
   rc = step_fused_io<T>(g, dt, static_cast<const T*>(g->e), static_cast<const T*>(g->h),
                         static_cast<T*>(g->e_alt), static_cast<T*>(g->h_alt));
   if (rc) return rc;
-  std::swap(g->e, g->e_alt);
-  std::swap(g->h, g->h_alt);
+  swap_sets(g);
   return FIT_OK;
 }
 
@@ -490,8 +498,7 @@ static int step_pair(fit_grid* g, double dt) {
     e = launch_step2<T>(a, g->lossy, g->s);
   }
   if (e != hipSuccess) return hip_fail(e, "step pair launch");
-  std::swap(g->e, g->e_alt);
-  std::swap(g->h, g->h_alt);
+  swap_sets(g);
   g->m += 2;
   g->smvp += 4;
   return FIT_OK;
@@ -512,8 +519,7 @@ static int time_pair(fit_grid* g, double dt, int tw, int ty, int kc, int reps, f
   (void)hipEventCreate(&ev[1]);
   auto one = [&]() -> int {
     int r = step_pair<T>(g, dt);
-    std::swap(g->e, g->e_alt);
-    std::swap(g->h, g->h_alt);
+    swap_sets(g);
     return r;
   };
   int rc = FIT_OK;
@@ -570,7 +576,6 @@ int upload_cells(fit_grid* g, void** dst, const std::vector<double>& v, const ch
 // place into the second set.  The handle's state is left untouched.
 template <typename T>
 int time_candidate(fit_grid* g, double dt, int path, int tw, int ty, int kc, int reps, float* ms) {
-  const Dims& d = g->d;
   const int save_path = g->path, save_ty = g->ty, save_kc = g->kc, save_sty = g->sty,
             save_skc = g->skc, save_stw = g->stw;
   const int64_t save_m = g->m, save_smvp = g->smvp, save_tr = g->trace_every;
@@ -594,8 +599,7 @@ int time_candidate(fit_grid* g, double dt, int path, int tw, int ty, int kc, int
     if (path == 2) {
       // run the fused step, then swap back so the inputs stay the same
       int r = step_fused<T>(g, dt);
-      std::swap(g->e, g->e_alt);
-      std::swap(g->h, g->h_alt);
+      swap_sets(g);
       return r;
     }
     if (int r = ensure_alt(g)) return r;
@@ -626,6 +630,37 @@ int time_candidate(fit_grid* g, double dt, int path, int tw, int ty, int kc, int
   g->pend_m = save_pend;
   g->probe = save_probe;
   return rc;
+}
+
+// Inner products of the step that starts at the current state (e^m,
+// h^(m+1/2)), for fit_energy: the e-update runs out of place into the second
+// buffer set (e^(m+1), with the trace terms <e^m,e^m>, <e^m,e^(m+1)>, loss and
+// source), then the h-update with -dt turns h^(m+1/2) back into h^(m-1/2)
+// (<h^(m+1/2),h^(m+1/2)> and <h^(m+1/2),h^(m-1/2)>).  row: device, 10
+// doubles in the trace-row layout.
+template <typename T>
+static int state_terms(fit_grid* g, double dt, double* row) {
+  if (int rc = ensure_alt(g)) return rc;
+  const Tiling t = make_tiling(g->d, g->ty, g->kc);
+  const int64_t nb = t.blocks();
+  if (int rc = ensure_part(g, nb)) return rc;
+  const T* e = static_cast<const T*>(g->e);
+  const T* h = static_cast<const T*>(g->h);
+  EArgs<T> ea;
+  fill_eargs<T>(g, ea, e, static_cast<T*>(g->e_alt), h, dt, g->m);
+  hipError_t er = launch_epass<T>(ea, g->lossy, true, false, g->s);
+  if (er != hipSuccess) return hip_fail(er, "e-update launch");
+  const int ecols[kPartTerms] = {1, 2, 3, 8, 9, -1, -1, -1, -1, -1};
+  er = launch_reduce(g->part, nb, row, ecols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
+  if (er != hipSuccess) return hip_fail(er, "reduce launch");
+  HArgs<T> ha;
+  fill_hargs<T>(g, ha, e, h, static_cast<T*>(g->h_alt), -dt);
+  er = launch_hpass<T>(ha, g->mu_uniform, true, g->s);
+  if (er != hipSuccess) return hip_fail(er, "h-update launch");
+  const int hcols[kPartTerms] = {5, 4, -1, -1, -1, -1, -1, -1, -1, -1};
+  er = launch_reduce(g->part, nb, row, hcols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
+  if (er != hipSuccess) return hip_fail(er, "reduce launch");
+  return FIT_OK;
 }
 
 }  // namespace fit
@@ -680,7 +715,7 @@ int fit_grid_create(const fit_grid_desc* desc, void* stream, fit_grid** out) {
   int rc = dev_alloc(&g->e, 3 * n * g->esz, "e");
   if (!rc) rc = dev_alloc(&g->h, 3 * n * g->esz, "h");
   if (!rc) rc = dev_alloc(&g->eps, n * g->esz, "eps");
-  if (!rc) rc = dev_alloc(reinterpret_cast<void**>(&g->jacc), 4 * sizeof(double), "probe sum");
+  if (!rc) rc = dev_alloc(reinterpret_cast<void**>(&g->jacc), kJaccLen * sizeof(double), "probe sum");
   if (!rc) rc = dev_alloc(reinterpret_cast<void**>(&g->pend), sizeof(double), "pending term");
   if (rc) {
     fit_grid_destroy(g);
@@ -688,7 +723,7 @@ int fit_grid_create(const fit_grid_desc* desc, void* stream, fit_grid** out) {
   }
   hipError_t e = hipMemsetAsync(g->e, 0, 3 * n * g->esz, g->s);
   if (e == hipSuccess) e = hipMemsetAsync(g->h, 0, 3 * n * g->esz, g->s);
-  if (e == hipSuccess) e = hipMemsetAsync(g->jacc, 0, 4 * sizeof(double), g->s);
+  if (e == hipSuccess) e = hipMemsetAsync(g->jacc, 0, kJaccLen * sizeof(double), g->s);
   if (e != hipSuccess) {
     fit_grid_destroy(g);
     return hip_fail(e, "initial clear");
@@ -710,13 +745,15 @@ int fit_grid_destroy(fit_grid* g) {
   for (hipEvent_t ev : g->prof_ev) (void)hipEventDestroy(ev);
   g->prof_ev.clear();
   grid_release_extras(g);
-  dev_free(g->e);
-  dev_free(g->h);
-  dev_free(g->e_alt);
-  dev_free(g->h_alt);
-  dev_free(g->eps);
-  dev_free(g->sig);
-  dev_free(g->imu);
+  if (!g->bor_e) dev_free(g->e);
+  if (!g->bor_h) dev_free(g->h);
+  if (!g->bor_ealt) dev_free(g->e_alt);
+  if (!g->bor_halt) dev_free(g->h_alt);
+  if (!g->bor_mat) {
+    dev_free(g->eps);
+    dev_free(g->sig);
+    dev_free(g->imu);
+  }
   dev_free(reinterpret_cast<void*&>(g->sq));
   dev_free(reinterpret_cast<void*&>(g->part));
   dev_free(reinterpret_cast<void*&>(g->trace));
@@ -900,6 +937,117 @@ static int copy_field(fit_grid* g, void* dst, const void* src, int dir_in, int o
   return FIT_OK;
 }
 
+// Caller-provided device buffers: aligned to 16 bytes, pairwise disjoint
+// (each `bytes` long) and none of them a buffer the library owns.
+static int check_borrowed(const fit_grid* g, void* const* p, int np, size_t bytes) {
+  const void* owned[7] = {g->bor_e ? nullptr : g->e,        g->bor_h ? nullptr : g->h,
+                          g->bor_ealt ? nullptr : g->e_alt, g->bor_halt ? nullptr : g->h_alt,
+                          g->bor_mat ? nullptr : g->eps,    g->bor_mat ? nullptr : g->sig,
+                          g->bor_mat ? nullptr : g->imu};
+  for (int a = 0; a < np; ++a) {
+    if (!p[a]) continue;
+    if (reinterpret_cast<uintptr_t>(p[a]) % 16 != 0)
+      return fail(FIT_E_INVALID, "bound buffers must be aligned to 16 bytes");
+    for (const void* o : owned)
+      if (o && o == p[a]) return fail(FIT_E_INVALID, "a bound buffer is library-owned storage");
+    const char* x = static_cast<const char*>(p[a]);
+    for (int b = 0; b < a; ++b) {
+      const char* y = static_cast<const char*>(p[b]);
+      if (y && x < y + bytes && y < x + bytes)
+        return fail(FIT_E_INVALID, "bound buffers must not overlap");
+    }
+  }
+  return FIT_OK;
+}
+
+int fit_bind_fields(fit_grid* g, void* e, void* h, void* e_alt, void* h_alt) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  const size_t fb = 3 * (size_t)g->d.n * g->esz;
+  const bool unbind = !e && !h && !e_alt && !h_alt;
+  if (!unbind) {
+    if (!e || !h) return fail(FIT_E_INVALID, "e and h are both required");
+    if ((e_alt == nullptr) != (h_alt == nullptr))
+      return fail(FIT_E_INVALID, "give both second-set buffers or neither");
+    void* p[4] = {e, h, e_alt, h_alt};
+    if (int rc = check_borrowed(g, p, 4, fb)) return rc;
+  }
+  hipError_t er = hipStreamSynchronize(g->s);   // no launch may still use the old buffers
+  if (er != hipSuccess) return hip_fail(er, "bind sync");
+  void* ne = e;
+  void* nh = h;
+  if (unbind) {   // the state moves back into library-owned buffers
+    ne = g->bor_e ? nullptr : g->e;
+    nh = g->bor_h ? nullptr : g->h;
+    if (!ne) {
+      if (int rc = dev_alloc(&ne, fb, "e")) return rc;
+    }
+    if (!nh) {
+      if (int rc = dev_alloc(&nh, fb, "h")) {
+        if (g->bor_e) dev_free(ne);
+        return rc;
+      }
+    }
+  }
+  if (ne != g->e) er = hipMemcpyAsync(ne, g->e, fb, hipMemcpyDeviceToDevice, g->s);
+  if (er == hipSuccess && nh != g->h) er = hipMemcpyAsync(nh, g->h, fb, hipMemcpyDeviceToDevice, g->s);
+  if (er == hipSuccess) er = hipStreamSynchronize(g->s);
+  if (er != hipSuccess) return hip_fail(er, "state copy into the bound buffers");
+  if (!g->bor_e && g->e != ne) dev_free(g->e);
+  if (!g->bor_h && g->h != nh) dev_free(g->h);
+  g->e = ne;
+  g->h = nh;
+  g->bor_e = g->bor_h = !unbind;
+  if (e_alt) {
+    if (!g->bor_ealt) dev_free(g->e_alt);
+    if (!g->bor_halt) dev_free(g->h_alt);
+    g->e_alt = e_alt;
+    g->h_alt = h_alt;
+    g->bor_ealt = g->bor_halt = true;
+  } else if (g->bor_ealt || g->bor_halt) {   // allocated again on first use
+    if (!g->bor_ealt) dev_free(g->e_alt);
+    if (!g->bor_halt) dev_free(g->h_alt);
+    g->e_alt = g->h_alt = nullptr;
+    g->bor_ealt = g->bor_halt = false;
+  }
+  g->storage_version++;
+  return FIT_OK;
+}
+
+int fit_bind_materials(fit_grid* g, void* eps, void* sigma, void* imu) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  const size_t cb = (size_t)g->d.n * g->esz;
+  const bool unbind = !eps && !sigma && !imu;
+  if (!unbind) {
+    if (!eps || !sigma || !imu) return fail(FIT_E_INVALID, "give all three cell buffers or none");
+    void* p[3] = {eps, sigma, imu};
+    if (int rc = check_borrowed(g, p, 3, cb)) return rc;
+    const void* f[4] = {g->e, g->h, g->e_alt, g->h_alt};
+    for (void* q : p)
+      for (const void* o : f)
+        if (o && q == o) return fail(FIT_E_INVALID, "a cell buffer is a field buffer");
+  }
+  hipError_t er = hipStreamSynchronize(g->s);
+  if (er != hipSuccess) return hip_fail(er, "bind sync");
+  if (!g->bor_mat) {
+    dev_free(g->eps);
+    dev_free(g->sig);
+    dev_free(g->imu);
+  }
+  g->eps = eps;
+  g->sig = sigma;
+  g->imu = imu;
+  g->bor_mat = !unbind;
+  g->storage_version++;
+  return apply_materials(g);   // writes the current materials into the new buffers
+}
+
+int fit_get_state(const fit_grid* g, void** e, void** h) {
+  if (!g || !e || !h) return fail(FIT_E_INVALID, "null argument");
+  *e = g->e;
+  *h = g->h;
+  return FIT_OK;
+}
+
 int fit_set_fields(fit_grid* g, const void* e, const void* h, int64_t step, int on_device) {
   if (!g) return fail(FIT_E_INVALID, "null handle");
   if (step < 0) return fail(FIT_E_INVALID, "step must be >= 0");
@@ -958,6 +1106,7 @@ int fit_step(fit_grid* g, int64_t nsteps, double dt) {
   if (nsteps < 0) return fail(FIT_E_INVALID, "nsteps must be >= 0");
   int rc = check_dt(g, dt);
   if (rc) return rc;
+  if (nsteps > 0) g->last_dt = dt;
   const bool fused = use_fused(g);
   for (int64_t s = 0; s < nsteps; ++s) {
     if (fused && pair_now(g, nsteps - s)) {
@@ -976,7 +1125,7 @@ int fit_step(fit_grid* g, int64_t nsteps, double dt) {
   return FIT_OK;
 }
 
-int fit_energy(fit_grid* g, double out[2]) {
+int fit_energy(fit_grid* g, double out[5]) {
   if (!g || !out) return fail(FIT_E_INVALID, "null argument");
   const int64_t nb = (g->d.n + 255) / 256;
   int rc = ensure_part(g, nb);
@@ -1005,9 +1154,26 @@ int fit_energy(fit_grid* g, double out[2]) {
   const int cols[kPartTerms] = {0, 1, -1, -1, -1, -1, -1, -1, -1, -1};
   e = launch_reduce(g->part, nblk, g->jacc + 2, cols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
   if (e != hipSuccess) return hip_fail(e, "reduce launch");
-  e = hipMemcpyAsync(out, g->jacc + 2, 2 * sizeof(double), hipMemcpyDeviceToHost, g->s);
+  const double dt = g->last_dt;
+  if (dt > 0.0) {
+    rc = g->f64 ? state_terms<double>(g, dt, g->jacc + kJaccRow)
+                : state_terms<float>(g, dt, g->jacc + kJaccRow);
+    if (rc) return rc;
+  }
+  double v[2 + FIT_TRACE_COLS];
+  e = hipMemcpyAsync(v, g->jacc + 2, (dt > 0.0 ? 2 + FIT_TRACE_COLS : 2) * sizeof(double),
+                     hipMemcpyDeviceToHost, g->s);
   if (e == hipSuccess) e = hipStreamSynchronize(g->s);
   if (e != hipSuccess) return hip_fail(e, "energy readback");
+  out[0] = v[0];
+  out[1] = v[1];
+  out[2] = out[3] = out[4] = NAN;
+  if (dt > 0.0) {
+    const double* r = v + 2;   // trace-row layout of step m
+    out[2] = 0.5 * (r[1] + r[2] + r[4] + r[5]);   // W^m, eq. energy
+    out[3] = r[1] + r[4];                          // Q^m
+    out[4] = -2.0 * dt * (r[8] + r[9]);            // Q^(m+1) - Q^m
+  }
   if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
     return fail(FIT_E_DIVERGED, "energy is not finite");
   return FIT_OK;

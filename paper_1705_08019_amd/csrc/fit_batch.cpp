@@ -317,11 +317,11 @@ static int batch_run(fit_batch* b, int64_t nsteps, const double* dt, int use_gra
   for (int g = 0; g < b->nb; ++g) {
     fit_grid* gr = b->grids[g];
     if (launches & 1) {
-      std::swap(gr->e, gr->e_alt);
-      std::swap(gr->h, gr->h_alt);
+      swap_sets(gr);
     }
     gr->m += nsteps;
     gr->smvp += 2 * nsteps;
+    if (nsteps > 0) gr->last_dt = dt[g];
   }
   return FIT_OK;
 }
@@ -514,12 +514,37 @@ int fit_batch_get_pair(const fit_batch* b, int* enable, int* kc) {
   return FIT_OK;
 }
 
+// Checks made before every batched call: each grid's dt, and the grid
+// properties the batch was laid out for, which fit_set_materials,
+// fit_set_spacing, fit_set_probe or fit_bind_fields may have changed since.
+// A grid that became lossy re-lays the batch out for the lossy tile body
+// (its LDS holds the sigma planes); a non-uniform mu or spacing or a probe is
+// rejected; a second buffer set dropped by a rebind is allocated again.
 static int batch_check_dt(fit_batch* b, const double* dt) {
   if (!dt) return fail(FIT_E_INVALID, "dt array is null");
+  bool lossy = false;
   for (int g = 0; g < b->nb; ++g) {
-    if (int rc = check_dt(b->grids[g], dt[g])) return rc;
-    if (b->grids[g]->probe.on)
+    fit_grid* gr = b->grids[g];
+    if (int rc = check_dt(gr, dt[g])) return rc;
+    if (gr->probe.on)
       return fail(FIT_E_STATE, "batched steps do not accumulate a probe objective; clear the probe");
+    if (gr->nu) return fail(FIT_E_STATE, "a grid of the batch now has a non-uniform spacing");
+    if (!gr->mu_uniform) return fail(FIT_E_STATE, "a grid of the batch now has a non-uniform mu");
+    if (int rc = ensure_alt(gr)) return rc;
+    lossy |= gr->lossy;
+  }
+  if (lossy != b->lossy_any) {
+    const bool old = b->lossy_any;
+    b->lossy_any = lossy;
+    int rc = batch_layout(b);
+    if (!rc && b->pair_on) rc = batch_layout2(b);
+    if (rc) {
+      const std::string msg = fit_last_error();
+      b->lossy_any = old;
+      (void)batch_layout(b);
+      if (b->pair_on) (void)batch_layout2(b);
+      return fail(rc, msg);
+    }
   }
   return FIT_OK;
 }

@@ -11,11 +11,13 @@ namespace fit {
 void grid_release_extras(fit_grid* g) {
   if (!g->adj) return;
   fit_adjoint_ws* w = g->adj;
-  for (int q = 0; q < 2; ++q) {
-    dev_free(w->lam[q]);
-    dev_free(w->mu[q]);
+  if (!w->borrowed) {
+    for (int q = 0; q < 2; ++q) {
+      dev_free(w->lam[q]);
+      dev_free(w->mu[q]);
+    }
+    dev_free(reinterpret_cast<void*&>(w->gcell));
   }
-  dev_free(reinterpret_cast<void*&>(w->gcell));
   delete w;
   g->adj = nullptr;
 }
@@ -152,6 +154,7 @@ int fit_step_record(fit_grid* g, int64_t nsteps, double dt, void* e_rec, void* h
   if (!g || !e_rec || !h_rec) return fail(FIT_E_INVALID, "null argument");
   if (nsteps < 0) return fail(FIT_E_INVALID, "nsteps must be >= 0");
   if (int rc = check_dt(g, dt)) return rc;
+  if (nsteps > 0) g->last_dt = dt;
   return g->f64 ? record_t<double>(g, nsteps, dt, e_rec, h_rec)
                 : record_t<float>(g, nsteps, dt, e_rec, h_rec);
 }
@@ -179,6 +182,45 @@ int fit_adjoint_set_tuning(fit_grid* g, int tw, int ty, int kc) {
   g->atw = tw;
   g->aty = ty;
   g->akc = kc;
+  return FIT_OK;
+}
+
+int fit_adjoint_bind(fit_grid* g, void* lam0, void* lam1, void* mu0, void* mu1, double* gcell) {
+  if (!g) return fail(FIT_E_INVALID, "null handle");
+  void* p[5] = {lam0, lam1, mu0, mu1, gcell};
+  int nn = 0;
+  for (void* q : p) nn += q == nullptr;
+  if (nn != 0 && nn != 5) return fail(FIT_E_INVALID, "give all five adjoint buffers or none");
+  const size_t fb = 3 * (size_t)g->d.n * g->esz;
+  const size_t gb = 2 * (size_t)g->d.n * sizeof(double);
+  if (nn == 0) {
+    const void* f[7] = {g->e, g->h, g->e_alt, g->h_alt, g->eps, g->sig, g->imu};
+    for (int a = 0; a < 5; ++a) {
+      if (reinterpret_cast<uintptr_t>(p[a]) % 16 != 0)
+        return fail(FIT_E_INVALID, "bound buffers must be aligned to 16 bytes");
+      for (const void* o : f)
+        if (o && o == p[a]) return fail(FIT_E_INVALID, "an adjoint buffer is a field or cell buffer");
+      const char* x = static_cast<const char*>(p[a]);
+      const size_t xa = a == 4 ? gb : fb;
+      for (int b = 0; b < a; ++b) {
+        const char* y = static_cast<const char*>(p[b]);
+        if (x < y + fb && y < x + xa) return fail(FIT_E_INVALID, "adjoint buffers must not overlap");
+      }
+    }
+  }
+  hipError_t e = hipStreamSynchronize(g->s);
+  if (e != hipSuccess) return hip_fail(e, "bind sync");
+  grid_release_extras(g);   // any sweep in progress ends here
+  if (nn == 5) return FIT_OK;   // allocated by the library at the next fit_adjoint_begin
+  g->adj = new (std::nothrow) fit_adjoint_ws();
+  if (!g->adj) return fail(FIT_E_OOM, "host allocation failed");
+  fit_adjoint_ws* w = g->adj;
+  w->lam[0] = lam0;
+  w->lam[1] = lam1;
+  w->mu[0] = mu0;
+  w->mu[1] = mu1;
+  w->gcell = gcell;
+  w->borrowed = true;
   return FIT_OK;
 }
 

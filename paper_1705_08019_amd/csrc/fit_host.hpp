@@ -14,6 +14,7 @@ struct fit_adjoint_ws {
   int64_t next_m = -1;    // reverse step expected next (N-1 down to 0)
   void* lam[2] = {nullptr, nullptr};   // 3n each, grid dtype; ping-pong
   void* mu[2] = {nullptr, nullptr};
+  bool borrowed = false;  // lam, mu and gcell come from fit_adjoint_bind
   int cur = 0;            // buffer set holding lambda^(m+2), mu^(m+3/2)
   double* gcell = nullptr;  // 2n: per-cell dJ/deps_r, dJ/dsigma accumulators
   fit::Tiling t{};        // tile of the reverse-step kernel
@@ -30,6 +31,13 @@ struct fit_grid {
   void* eps = nullptr;   // eps0 * eps_r per cell (field dtype)
   void* sig = nullptr;   // sigma per cell, allocated when some sigma != 0
   void* imu = nullptr;   // 1/(mu0 mu_r) per cell, allocated when mu is not uniform
+  // storage borrowed from the caller (fit_bind_fields, fit_bind_materials):
+  // never freed by the library.  The flags travel with the pointers when the
+  // two field buffer sets swap roles.
+  bool bor_e = false, bor_h = false, bor_ealt = false, bor_halt = false;
+  bool bor_mat = false;          // eps, sig and imu all borrowed
+  int64_t storage_version = 0;   // bumped whenever a buffer pointer changes
+  double last_dt = 0.0;          // dt of the last fit_step / fit_step_record (0: none)
   bool lossy = false;
   bool mu_uniform = true;
   double imu_u = 1.0;
@@ -91,6 +99,11 @@ struct fit_grid {
 
 namespace fit {
 
+// Device scratch g->jacc: [0..1] probe objective (sum, compensation), [2..3]
+// state energies, [kJaccRow ..) the 10 inner products of fit_energy.
+constexpr int kJaccRow = 4;
+constexpr int kJaccLen = 16;
+
 extern thread_local std::string g_err;
 int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
@@ -113,6 +126,8 @@ int step_fused(fit_grid* g, double dt);
 template <typename T>
 int step_fused_io(fit_grid* g, double dt, const T* e0, const T* h0, T* e1, T* h1);
 int ensure_alt(fit_grid* g);
+// Swap the roles of the two field buffer sets (and their borrowed flags).
+void swap_sets(fit_grid* g);
 void default_tiling(const Dims& d, int* ty, int* kc);
 
 // Bracket one kernel launch with timing events when profiling is on.

@@ -1,8 +1,9 @@
 """Python handle for one FIT grid (thin wrapper over the C ABI in include/fit.h).
 
-PyTorch supplies device memory for the tensors handed in and out and the
-stream the library enqueues on; every step of the method runs in libfit's
-HIP kernels.
+PyTorch supplies the device memory -- both field buffer sets, the per-cell
+material arrays and the adjoint state are torch tensors the library borrows
+(fit_bind_fields, fit_bind_materials, fit_adjoint_bind) -- and the stream the
+library enqueues on; every step of the method runs in libfit's HIP kernels.
 """
 from __future__ import annotations
 
@@ -47,6 +48,13 @@ class FitGrid:
         h = C.c_void_p()
         call("fit_grid_create", C.byref(desc), C.c_void_p(self._stream), C.byref(h))
         self._h = h
+        # device storage owned by PyTorch and borrowed by the library
+        f = dict(dtype=self.tdtype, device=self.device)
+        self._fields = [torch.zeros(self.shape, **f) for _ in range(4)]
+        self._cells = [torch.zeros((self.nz, self.ny, self.nx), **f) for _ in range(3)]
+        self._adj_bufs = None
+        call("fit_bind_fields", self._h, *(C.c_void_p(t.data_ptr()) for t in self._fields))
+        call("fit_bind_materials", self._h, *(C.c_void_p(t.data_ptr()) for t in self._cells))
         if tensor:
             self.set_spacing(*widths)
 
@@ -59,6 +67,8 @@ class FitGrid:
         if getattr(self, "_h", None) is not None and self._h.value:
             _lib.lib().fit_grid_destroy(self._h)
             self._h = None
+        # the bound storage outlives the handle
+        self._fields = self._cells = self._adj_bufs = None
 
     def __del__(self):
         try:
@@ -143,6 +153,14 @@ class FitGrid:
         h = torch.empty(self.shape, dtype=self.tdtype, device=self.device)
         call("fit_get_fields", self._h, C.c_void_p(e.data_ptr()), C.c_void_p(h.data_ptr()), 1)
         return e, h
+
+    def state(self):
+        """The bound tensors holding the current state (e^m, h^(m+1/2)): views,
+        not copies; valid until the next call that steps the grid."""
+        pe, ph = C.c_void_p(), C.c_void_p()
+        call("fit_get_state", self._h, C.byref(pe), C.byref(ph))
+        by_ptr = {t.data_ptr(): t for t in self._fields}
+        return by_ptr[pe.value], by_ptr[ph.value]
 
     def get_fields_host(self):
         e = np.empty(self.shape, dtype=_NP_DTYPE[self.dtype])
@@ -248,9 +266,16 @@ class FitGrid:
         call("fit_step", self._h, int(nsteps), float(dt))
 
     def energy(self):
-        out = (C.c_double * 2)()
+        """(<e^m,e^m>_eps, <h^(m+1/2),h^(m+1/2)>_mu) of the current state."""
+        out = self.energies()
+        return out["ee"], out["hh"]
+
+    def energies(self) -> dict:
+        """eq. energy at the current state: ee = <e,e>_eps, hh = <h,h>_mu, the
+        conserved W, Q and dQ = Q^(m+1) - Q^m (NaN before the first step)."""
+        out = (C.c_double * 5)()
         call("fit_energy", self._h, out)
-        return out[0], out[1]
+        return dict(zip(("ee", "hh", "W", "Q", "dQ"), out))
 
     # ------------------------------------------------------------------ diagnostics
     def trace_config(self, every: int, capacity: int):
@@ -371,6 +396,13 @@ class FitGrid:
         return w.value, t.value, k.value
 
     def adjoint_begin(self, nsteps: int, dt: float):
+        if self._adj_bufs is None:   # lambda, mu ping-pong pairs and the cell gradients
+            f = dict(dtype=self.tdtype, device=self.device)
+            self._adj_bufs = [torch.zeros(self.shape, **f) for _ in range(4)] + [
+                torch.zeros((2, self.nz, self.ny, self.nx), dtype=torch.float64,
+                            device=self.device)]
+            call("fit_adjoint_bind", self._h,
+                 *(C.c_void_p(t.data_ptr()) for t in self._adj_bufs))
         call("fit_adjoint_begin", self._h, int(nsteps), float(dt))
 
     def adjoint_step(self, m: int, e_m: torch.Tensor, e_m1: torch.Tensor, h_mh: torch.Tensor):
