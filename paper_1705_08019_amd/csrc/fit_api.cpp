@@ -319,14 +319,6 @@ int step_fused_io(fit_grid* g, double dt, const T* e0, const T* h0, T* e1, T* h1
   if (tr_this && !have_row) g->trace_dropped++;
   const bool probe = g->probe.on != 0;
   const bool energy = have_row || tr_next;
-  if (sizeof(T) == 4 && energy && probe) {
-    // The FP32 fused variant with both energies and the probe returned NaN
-    // h values on the GPU (the FP64 one and each of the two alone agree with
-    // the split kernels bitwise); until its cause is found such steps run
-    // on the split kernels, out of place into the same buffers.
-    if (tr_this && !have_row) g->trace_dropped--;   // step_once counts it again
-    return step_once<T>(g, dt, e0, e1, h0, h1);
-  }
   const Dims& d = g->d;
   SArgs<T> a;
   for (int c = 0; c < 3; ++c) {

@@ -258,11 +258,16 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
                    gex * (double)S4x * bx * bx + gey * (double)S4y * by * by +
                        gez * (double)S4z * bz * bz);
           }
-          if (g == A.src_idx) {
-            const double bs = A.src_comp == 0 ? 0.5 * (ox + nx_)
-                            : A.src_comp == 1 ? 0.5 * (oy + ny_) : 0.5 * (oz + nz_);
-            nadd_s(acc[PE_SRC], cmp[PE_SRC], bs * A.src_val_d);
-          }
+          // The source term is selected, not branched to: every lane adds
+          // (exactly) 0 except the source edge's.  A branch here left the
+          // block divergent on one lane, and under the register pressure of
+          // the FP32 lossy energy+probe variant the gfx950 code generator
+          // placed register copies (of the h-update coefficient among
+          // others) inside that one-lane block, before the exec mask was
+          // restored, so every other lane later read stale registers.
+          const double bs = A.src_comp == 0 ? 0.5 * (ox + nx_)
+                          : A.src_comp == 1 ? 0.5 * (oy + ny_) : 0.5 * (oz + nz_);
+          nadd_s(acc[PE_SRC], cmp[PE_SRC], g == A.src_idx ? bs * A.src_val_d : 0.0);
         }
         if (PROBE) {
           const bool kx = k >= A.probe.lo[2] && k <= A.probe.hi[2];

@@ -334,14 +334,15 @@ def test_probe_objective_across_tilings_and_paths():
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_fused_with_trace_and_probe_matches_split(dtype):
-    """Energies and the probe on the same fused steps (FP32 runs such steps on
-    the split kernels) give the split path's fields bitwise, its trace and its
-    objective."""
+@pytest.mark.parametrize("lossy", [True, False])
+def test_fused_with_trace_and_probe_matches_split(dtype, lossy):
+    """Energies and the probe on the same fused steps give the split path's
+    fields bitwise, its trace and its objective; the fused kernel variant that
+    computes both (k_step with ENERGY and PROBE) is the one that ran."""
     from paper_1705_08019_amd import FitGrid
     nx, ny, nz = 45, 26, 19
     eps = dielectric_blocks(nx, ny, nz, 5, 3)
-    sig = lossy_slab(nx, ny, nz, 1, 0.2)
+    sig = lossy_slab(nx, ny, nz, 1, 0.2) if lossy else None
     rng = np.random.default_rng(3)
     e0 = rng.standard_normal((3, nz, ny, nx))
     out = []
@@ -352,9 +353,13 @@ def test_fused_with_trace_and_probe_matches_split(dtype):
         dt = 0.9 * g.cfl_dt()
         g.set_source(2, nx // 2, ny // 2, nz // 2, 1.0, 4 * dt)
         g.set_tuning(path)
-        g.trace_config(3, 20)
+        g.trace_config(1, 20)            # energies on every step
         g.set_probe([2, 2, 2], [10, 10, 10])
+        g.profile_begin(200)
         g.step(20, dt)
+        prof = g.profile_end()
+        if path == "fused":              # one fused launch per step, no split pass
+            assert prof["step"][1] == 20 and prof["epass"][1] == 0, prof
         e, h = g.get_fields()
         tr, _ = g.trace_read()
         out.append((to_np(e), to_np(h), tr, g.probe_value()))
