@@ -41,12 +41,17 @@ PEAK_HBM_GBS = 8000.0          # MI355X HBM3E spec
 # writes e; h-update reads h, e and writes h.
 B_EPASS = 4 * (3 + 3 + 3 + 2)   # 44
 B_HPASS = 4 * (3 + 3 + 3)       # 36
-B_STEP = B_EPASS + B_HPASS      # 80
-# reverse (adjoint) step, FP32 fields: lambda and mu read + write, e^m, e^(m+1)
-# and h^(m+1/2) read, eps and sigma read, and the two FP64 per-edge
-# sensitivity accumulators read + written (the per-edge form of the
-# recursion; the kernel folds them onto the cells and moves 124 B)
-B_ADJ = 4 * (6 + 6 + 9 + 2) + 8 * 2 * 3 * 2    # 188
+B_STEP = B_EPASS + B_HPASS      # 80: the per-cell-step figure with no fusion at all
+# Compulsory bytes of one launch of a fused kernel, per cell: read the state
+# (e, h) and the per-cell eps and sigma once, write the new state once.  The
+# same 56 B hold for a single fused step and for a two-step launch (whose
+# intermediate state never leaves the chip), so the roofline fraction of a
+# launch cannot exceed 1.
+B_LAUNCH = 4 * (6 + 2 + 6)      # 56
+# reverse (adjoint) step, FP32 fields: lambda and mu read + written, e^m,
+# e^(m+1) and h^(m+1/2) read, eps and sigma read, and the two per-cell FP64
+# gradient accumulators read + written
+B_ADJ = 4 * (6 + 6 + 9 + 2) + 8 * 2 * 2    # 124
 
 
 KERNEL_SOURCES = {"step": ("fit_step.hip", "fit_step_tile.hpp", "fit_point.hpp"),
@@ -110,8 +115,10 @@ def run_plain(spec, steps: int, warmup: int, profile: bool = True, tile=None, pa
             g.set_pair(False)
         else:
             g.set_pair(True, *map(int, pair))
-    g.trace_config(every, steps // every + warmup // every + 4)
     g.step(warmup, dt)
+    # the trace starts with the timed steps: the timed window holds a row at
+    # its first step and one every `every` steps (ceil(steps / every) rows)
+    g.trace_config(every, steps // every + 4)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     if profile:
@@ -131,6 +138,35 @@ def run_plain(spec, steps: int, warmup: int, profile: bool = True, tile=None, pa
     assert np.all(np.isfinite(e_tot)), "energy trace is not finite"
     out = dict(ms=ms, wall_s=wall, prof=prof, trace_rows=int(tr.shape[0]), tuned=tuned,
                energy_last=float(e_tot[-1]), smvp=g.smvp_count(), grid=g)
+    return out
+
+
+def measure_stream(nbytes: int = 1 << 30, reps: int = 5) -> dict:
+    """The measured HBM ceiling: the library's streaming copy / read / fill
+    kernels (fit_stream_probe) over 1 GiB buffers, best over grid sizes and
+    repetitions; GB/s counts the bytes read plus written."""
+    import ctypes as C
+    import torch
+    from paper_1705_08019_amd._lib import call
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    out = {}
+    for mode, name, moved in ((0, "copy", 2 * nbytes), (1, "read", nbytes), (2, "fill", nbytes)):
+        best = (1e30, 0)
+        for blocks in (1024, 2048, 4096, 8192):
+            for _ in range(reps):
+                ev[0].record()
+                call("fit_stream_probe", mode, C.c_void_p(b.data_ptr()), C.c_void_p(a.data_ptr()),
+                     nbytes, blocks, stream)
+                ev[1].record()
+                torch.cuda.synchronize()
+                best = min(best, (ev[0].elapsed_time(ev[1]), blocks))
+        out[name + "_GBs"] = round(moved / (best[0] / 1e3) / 1e9, 1)
+        out[name + "_blocks"] = best[1]
+    del a, b
+    out["kernel"] = "fit_stream_probe: 16-byte non-temporal accesses, 4 in flight per lane"
     return out
 
 
@@ -252,9 +288,12 @@ def form_batched(plain_steps: int = 400):
         g.close()
     gb = cells * nsteps / (ms_b / 1e3) / 1e9
     gp = cells * plain_steps / (ms_p / 1e3) / 1e9
+    # compulsory bytes per cell-update: 56 B per launch, one or two steps per launch
+    bcs = B_LAUNCH / 2 if pair_on else B_LAUNCH
     return {"workload": "c4: 64 FP32 grids, sizes ~U{32..96}^3, 8 blocks each, 4000 steps",
             "cells_total": cells, "steps": nsteps, "Gcell_updates_per_s": round(gb, 3),
-            "alg_GBs": round(B_STEP * gb, 1), "frac": round(B_STEP * gb / PEAK_HBM_GBS, 4),
+            "alg_bytes_per_cell_update": bcs,
+            "alg_GBs": round(bcs * gb, 1), "frac": round(bcs * gb / PEAK_HBM_GBS, 4),
             "plain_per_grid_Gcell_updates_per_s": round(gp, 3),
             "plain_steps_timed": plain_steps, "batched_over_plain": round(gb / gp, 3),
             "tile": [tw, ty, kc], "pair_kc": pair_kc if pair_on else None,
@@ -350,6 +389,48 @@ def form_adjoint():
                                  "note": "96^3 state (21 MB per field set) is largely resident in the 256 MB Infinity Cache"}}
 
 
+def form_c2(steps: int = 10_000, warmup: int = 100):
+    """The 128^3 workload (FP32, 32 blocks, sigma slabs, centre source) over
+    its full 10 000 steps, autotuned; its 2.1 M cells (51 MB of state) stay
+    resident in the 256 MB Infinity Cache, so its fraction is of the HBM
+    roofline but the data mostly come from the cache."""
+    import torch
+    from fit_workloads import c2
+    from paper_1705_08019_amd import FitGrid
+    sp = c2()
+    g = FitGrid(sp.nx, sp.ny, sp.nz, "f32")
+    g.set_materials(sp.eps_r, None, sp.sigma)
+    dt = 0.9 * g.cfl_dt()
+    s = sp.source
+    g.set_source(s["axis"], s["i"], s["j"], s["k"], s["i_max"], s["sigma_t_steps"] * dt)
+    p_, ty_, kc_, _, tw_ = g.autotune(dt, reps=10)
+    pon, ptw, pty, pkc = g.get_pair()
+    g.step(warmup, dt)
+    torch.cuda.synchronize()
+    g.profile_begin(2 * steps + 16)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    g.step(steps, dt)
+    ev[1].record()
+    torch.cuda.synchronize()
+    prof = g.profile_end()
+    ms = ev[0].elapsed_time(ev[1])
+    nlaunch = prof["step"][1] + prof["pair"][1]
+    kms = prof["step"][0] + prof["pair"][0]
+    gbs = B_LAUNCH * sp.cells * nlaunch / (kms * 1e-3) / 1e9
+    ee, hh = g.energy()
+    g.close()
+    return {"workload": "c2: 128^3 FP32, 32 blocks, sigma=0.05 z-slabs, centre source, "
+                        f"{steps} steps (after {warmup} warm-up steps)",
+            "Gcell_updates_per_s": round(sp.cells * steps / (ms / 1e3) / 1e9, 2),
+            "ms_per_step": round(ms / steps, 5), "tile": [p_, tw_, ty_, kc_],
+            "pair_tile": [ptw, pty, pkc] if pon else None,
+            "launches": nlaunch, "kernel_ms_per_step": round(kms / steps, 5),
+            "alg_GBs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4),
+            "residency": "LLC-resident (51 MB of state in the 256 MB Infinity Cache)",
+            "energy_end": [ee, hh]}
+
+
 def form_graded(steps: int = 300, warmup: int = 20):
     """The bandwidth workload on a tensor grid (per-axis widths ~U[0.5, 1.5]):
     the fused step with per-column / per-plane metric (autotuned tile, single
@@ -389,13 +470,16 @@ def form_graded(steps: int = 300, warmup: int = 20):
             # per-step kernel time over single fused steps and step pairs
             # (two steps per launch, when the autotuner enabled them)
             nstep = prof["step"][1] + 2 * prof["pair"][1]
-            st = (prof["step"][0] + prof["pair"][0]) / max(nstep, 1)
+            nlaunch = prof["step"][1] + prof["pair"][1]
+            kms = prof["step"][0] + prof["pair"][0]
+            st = kms / max(nstep, 1)
             pon, ptw, pty, pkc = g.get_pair()
+            # compulsory bytes (56 B per cell and launch) over the kernels' time
+            gbs = B_LAUNCH * spec.cells * nlaunch / (kms * 1e-3) / 1e9
             out[name] = {"Gcell_updates_per_s": round(spec.cells * steps / wall / 1e9, 2),
                          "step_ms": round(st, 4), "tile": [tw_, ty_, kc_],
                          "pair_tile": [ptw, pty, pkc] if pon else None,
-                         "alg_GBs": round(80 * spec.cells / (st * 1e-3) / 1e9, 1),
-                         "frac": round(80 * spec.cells / (st * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
+                         "alg_GBs": round(gbs, 1), "frac": round(gbs / PEAK_HBM_GBS, 4)}
             g.close()
             continue
         ep = prof["epass"][0] / max(prof["epass"][1], 1)
@@ -680,7 +764,7 @@ def run_forms() -> dict:
     """The batched, adjoint, Gram, ParaExp and graded-grid forms; a failing
     form is reported, not hidden."""
     out = {}
-    for name, fn in (("batched", form_batched), ("adjoint", form_adjoint),
+    for name, fn in (("c2", form_c2), ("batched", form_batched), ("adjoint", form_adjoint),
                      ("gram", form_gram), ("paraexp", form_paraexp), ("graded", form_graded)):
         try:
             out[name] = fn()
@@ -746,51 +830,58 @@ def main(argv=None):
     roof = None
     path, ty, kc, tw = r["grid"].get_tuning()
     pon, ptw, pty, pkc = r["grid"].get_pair()
+    ceiling = measure_stream()
     if r["prof"] is not None:
         st_ms, st_n = r["prof"]["step"]
         pr_ms, pr_n = r["prof"]["pair"]
         if pr_n > 0:   # two fused steps per launch: the dominant kernel
             avg = pr_ms / pr_n
-            kname, kb, tkey = ("k_step2 (two fused leapfrog steps per launch, intermediate state "
-                               "in LDS)"), 2 * B_STEP, "pair"
+            kname, kb, tkey, steps_per_launch = (
+                "k_step2 (two fused leapfrog steps per launch, intermediate state in LDS)",
+                B_LAUNCH, "pair", 2)
             st_n = pr_n
         elif st_n > 0:   # fused single-pass step kernel: one launch = one full step
             avg = st_ms / st_n
-            kname, kb, tkey = ("k_step (fused leapfrog step: dual curl + M_eps/M_sigma + source, "
-                               "primal curl + M_mu, energies)"), B_STEP, "step"
+            kname, kb, tkey, steps_per_launch = (
+                "k_step (fused leapfrog step: dual curl + M_eps/M_sigma + source, primal curl "
+                "+ M_mu, energies)", B_LAUNCH, "step", 1)
         else:          # split half-step kernels: the e-update is the larger one
             pe_ms, pe_n = r["prof"]["epass"]
             avg = pe_ms / max(pe_n, 1)
             st_n = pe_n
-            kname, kb, tkey = "k_epass (e-update: dual curl + M_eps/M_sigma + source)", B_EPASS, "epass"
+            kname, kb, tkey, steps_per_launch = (
+                "k_epass (e-update: dual curl + M_eps/M_sigma + source)", B_EPASS, "epass", 1)
         ach = kb * cells / (avg / 1e3) / 1e9
+        tr = load_traffic(tkey)
+        eq = B_STEP * steps_per_launch * cells / (avg / 1e3) / 1e9
         roof = {"bound": "hbm", "kernel": kname, "achieved": round(ach, 1),
-                "note": (None if pr_n == 0 else
-                         "one launch advances two steps: algorithmic bytes are 80 B per "
-                         "cell-update as for single steps, while the launch moves about half "
-                         "(traffic), so achieved can exceed the HBM peak"),
                 "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
-                "traffic": (None if load_traffic(tkey) is None
-                            else load_traffic(tkey)["bytes_per_launch"]),
-                # secondary figure: counted L2-miss bytes (to the Infinity Cache or
-                # HBM) over the launch time
-                "traffic_GBs": (None if load_traffic(tkey) is None else round(
-                    load_traffic(tkey)["bytes_per_launch"] / (avg / 1e3) / 1e9, 1)),
-                "traffic_frac": (None if load_traffic(tkey) is None else round(
-                    load_traffic(tkey)["bytes_per_launch"] / (avg / 1e3) / 1e9 / PEAK_HBM_GBS,
-                    4)),
-                "traffic_unit": "L2-miss bytes per launch (FETCH_SIZE x2.000 + WRITE_SIZE x1.000, "
-                                "scaled by a 1 GiB copy; profiles/traffic_c3.json)",
-                "alg_bytes_per_launch": kb * cells, "alg_bytes_per_cell": kb,
+                "traffic": None if tr is None else tr["bytes_per_launch"],
+                "alg_bytes_per_cell": kb, "alg_bytes_per_launch": kb * cells,
+                "alg_bytes_note": ("compulsory bytes of one launch: the state (e, h) and the "
+                                   "per-cell eps, sigma read once, the new state written once"),
                 "avg_launch_ms": round(avg, 5), "launches_timed": st_n,
+                "steps_per_launch": steps_per_launch,
+                "frac_of_measured_copy": round(ach / ceiling["copy_GBs"], 4),
+                "measured_ceiling": ceiling,
+                "traffic_GBs": None if tr is None else round(
+                    tr["bytes_per_launch"] / (avg / 1e3) / 1e9, 1),
+                "traffic_frac": None if tr is None else round(
+                    tr["bytes_per_launch"] / (avg / 1e3) / 1e9 / PEAK_HBM_GBS, 4),
+                "traffic_bytes_per_cell": None if tr is None else tr["bytes_per_cell"],
+                "traffic_method": None if tr is None else tr.get("method"),
+                "unfused_equivalent": {
+                    "bytes_per_cell_step": B_STEP, "GBs": round(eq, 1),
+                    "note": "80 B per cell-update (e-update and h-update as separate passes, "
+                            "no temporal blocking) over this launch's steps; not a fraction "
+                            "of the roofline: the fused launch moves fewer bytes"},
                 "path": path, "tile": [ptw, pty, pkc] if pr_n > 0 else [tw, ty, kc],
                 "single_tile": [path, ty, kc, tw], "pair_tile": [ptw, pty, pkc] if pon else None,
                 "single_step_launches": r["prof"]["step"][1],
                 "single_step_avg_ms": (round(r["prof"]["step"][0] / r["prof"]["step"][1], 5)
                                        if r["prof"]["step"][1] else None),
                 "autotune_ms_per_step": (None if r["tuned"][3] != r["tuned"][3]
-                                         else round(r["tuned"][3], 5)),
-                "step_alg_GBs": round(B_STEP * cells / (ms_step / 1e3) / 1e9, 1)}
+                                         else round(r["tuned"][3], 5))}
     line = {
         "metric": METRIC, "value": round(value, 3), "unit": "Gcell-updates/s",
         "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -800,11 +891,11 @@ def main(argv=None):
                                "blocks, sigma=0.05 z-slabs, Gaussian centre source, FP64 energies "
                                "every 50 steps, dt=0.9 dt_CFL",
                    "cells": cells, "energy_every": spec.energy_every,
-                   "trace_rows": r["trace_rows"], "smvp": r["smvp"]},
+                   "trace_rows_timed": r["trace_rows"], "smvp": r["smvp"]},
         "roofline": roof,
     }
     r["grid"].close()
-    line["config"]["copy_GBs_read_plus_write"] = measure_copy()
+    line["config"]["torch_copy_GBs_read_plus_write"] = measure_copy()
     if not args.no_forms:
         line["forms"] = run_forms()
     if not args.no_cpu:

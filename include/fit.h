@@ -170,6 +170,10 @@ int fit_bind_materials(fit_grid* g, void* eps, void* sigma, void* imu);
  * or rebinds). */
 int fit_get_state(const fit_grid* g, void** e, void** h);
 
+/* The step the grid advances with when asked for dt (fit_step): dt itself
+ * for FP64 grids, the largest FP32 value <= dt for FP32 grids.  Host only. */
+int fit_step_dt(const fit_grid* g, double dt, double* dt_used);
+
 /* Set the state e^(m), h^(m+1/2) and the step counter m.  e, h: 3*nx*ny*nz
  * values each in the slot layout and the grid's dtype; on_device != 0 means
  * device pointers, else host pointers.  Either pointer may be NULL (that
@@ -196,9 +200,15 @@ int fit_apply_curl(fit_grid* g, int which, const void* in, void* out);
  * (the loss current is taken at the interpolated e^(m+1/2) = (e^m + e^(m+1))/2;
  * for sigma = 0 this is the paper's update).  Cost: 2 curl applications per
  * step (eq. cost_LF).  dt must be > 0 and <= fit_cfl_dt unless the grid was
- * created with FIT_ALLOW_UNSTABLE (else FIT_E_UNSTABLE).  Energies are
- * traced as configured by fit_trace_config; the probe objective is
- * accumulated when a probe is set.  Asynchronous. */
+ * created with FIT_ALLOW_UNSTABLE (else FIT_E_UNSTABLE).  An FP32 grid
+ * advances with dt rounded down to the nearest FP32 value: its stencil
+ * coefficients are FP32, and the source times t_(m+1/2) use the same step,
+ * so the run is the leapfrog recurrence of that step (an unrepresented
+ * remainder of dt would otherwise act as a systematic time-step error whose
+ * phase drift grows linearly with the step count).  The same holds for
+ * fit_step_record, fit_adjoint_begin, fit_autotune and batched steps.
+ * Energies are traced as configured by fit_trace_config; the probe objective
+ * is accumulated when a probe is set.  Asynchronous. */
 int fit_step(fit_grid* g, int64_t nsteps, double dt);
 
 /* Energies of the current state e^m, h^(m+1/2) (eq. energy), FP64:
@@ -218,7 +228,8 @@ int fit_step(fit_grid* g, int64_t nsteps, double dt);
 int fit_energy(fit_grid* g, double out[5]);
 
 /* Energy trace.  every > 0 records one row for each step m with
- * m % every == 0 (every = 0 disables); up to `capacity` rows are kept
+ * (m - m0) % every == 0, m0 the step counter at this call (every = 0
+ * disables); up to `capacity` rows are kept
  * (later rows are dropped and counted).  The row of step m holds the inner
  * products available around that step (FP64):
  *   [0] m
@@ -469,6 +480,17 @@ enum { FIT_PROF_EPASS = 0, FIT_PROF_HPASS = 1, FIT_PROF_REDUCE = 2, FIT_PROF_STE
        FIT_PROF_ADJOINT = 4, FIT_PROF_OTHER = 5, FIT_PROF_PAIR = 6, FIT_PROF_N = 7 };
 int fit_profile_begin(fit_grid* g, int64_t max_launches);
 int fit_profile_end(fit_grid* g, double ms[FIT_PROF_N], int64_t count[FIT_PROF_N]);
+
+/* Streaming probe for the measured HBM ceiling (instrumentation; no step of
+ * the method uses it).  mode 0: copy `bytes` from src to dst; mode 1: read
+ * src (dst receives blocks * 256 floats of per-lane sums, which keeps the
+ * loads alive); mode 2: fill dst.  16-byte accesses by consecutive lanes,
+ * four in flight per lane, `blocks` workgroups of 256 threads striding over
+ * the buffer, non-temporal loads and stores.  bytes: a positive multiple of
+ * 16; device pointers, 16-byte aligned, src and dst disjoint.  Enqueued on
+ * `stream` (a hipStream_t or NULL).  Errors: FIT_E_INVALID, FIT_E_HIP. */
+int fit_stream_probe(int mode, void* dst, const void* src, int64_t bytes, int blocks,
+                     void* stream);
 
 /* Kernel path and tile shape of fit_step.  path: FIT_PATH_AUTO (fused
  * single-pass kernel when mu is uniform, else the two half-step kernels),

@@ -46,6 +46,7 @@ SIGNATURES = {
     "fit_set_spacing": [_vp, _dp, _dp, _dp],
     "fit_set_source": [_vp, _i, _i, _i, _i, _d, _d],
     "fit_cfl_dt": [_vp, _dp],
+    "fit_step_dt": [_vp, _d, _dp],
     "fit_bind_fields": [_vp, _vp, _vp, _vp, _vp],
     "fit_bind_materials": [_vp, _vp, _vp, _vp],
     "fit_get_state": [_vp, C.POINTER(_vp), C.POINTER(_vp)],
@@ -61,6 +62,7 @@ SIGNATURES = {
     "fit_set_probe": [_vp, _i32p, _i32p],
     "fit_probe_value": [_vp, _dp],
     "fit_probe_reset": [_vp],
+    "fit_stream_probe": [_i, _vp, _vp, _i64, _i, _vp],
     "fit_profile_begin": [_vp, _i64],
     "fit_profile_end": [_vp, _dp, _i64p],
     "fit_smvp_count": [_vp, _i64p],

@@ -262,7 +262,10 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 4 : 2))) void k_adj(AdjArgs<
       // da/dM_eps = dt M_sig / D^2, db/dM_eps = -dt / D^2,
       // da/dM_sig = -dt M_eps / D^2, db/dM_sig = -dt^2 / (2 D^2)
       const double Dd = Me + A.hdt * Ms;
-      const double f = (double)ln * A.dt * rcp_d(Dd * Dd);
+      // FP64 grids: the IEEE quotient (the FP64 path is held to the oracle at
+      // rounding level); FP32 grids: the refined hardware reciprocal
+      const double f = sizeof(T) == 8 ? (double)ln * A.dt / (Dd * Dd)
+                                      : (double)ln * A.dt * rcp_d(Dd * Dd);
       qe[a] = A.eps0 * A.ge[a] * (f * (Ms * (double)em - (double)sv[a]) + A.dt * probe_e2);
       qs[a] = A.ge[a] * (-f * (Me * (double)em + A.hdt * (double)sv[a]));
       if (!live[a]) qe[a] = qs[a] = 0.0;

@@ -217,6 +217,13 @@ ProfScope::~ProfScope() {
   if (slot >= 0) (void)hipEventRecord(g->prof_ev[2 * slot + 1], g->s);
 }
 
+bool trace_at(const fit_grid* g, int64_t m) {
+  const int64_t te = g->trace_every;
+  if (te <= 0) return false;
+  const int64_t r = (m - g->trace_m0) % te;
+  return r == 0;
+}
+
 double source_value(const fit_grid* g, double dt, int64_t m) {
   const double t = ((double)m + 0.5) * dt;
   const double x = (t - g->sigma_t) / g->sigma_t;
@@ -229,8 +236,8 @@ double source_value(const fit_grid* g, double dt, int64_t m) {
 template <typename T>
 int step_once(fit_grid* g, double dt, const T* ein, T* eout, const T* hin, T* hout) {
   const int64_t m = g->m;
-  const bool tr_this = g->trace_every > 0 && m % g->trace_every == 0;
-  const bool tr_next = g->trace_every > 0 && (m + 1) % g->trace_every == 0;
+  const bool tr_this = trace_at(g, m);
+  const bool tr_next = trace_at(g, m + 1);
   const bool have_row = tr_this && g->trace_rows < g->trace_cap;
   if (tr_this && !have_row) g->trace_dropped++;
   const bool probe = g->probe.on != 0;
@@ -313,8 +320,8 @@ static void set_nu_args(const fit_grid* g, double dt, Args& a) {
 template <typename T>
 int step_fused_io(fit_grid* g, double dt, const T* e0, const T* h0, T* e1, T* h1) {
   const int64_t m = g->m;
-  const bool tr_this = g->trace_every > 0 && m % g->trace_every == 0;
-  const bool tr_next = g->trace_every > 0 && (m + 1) % g->trace_every == 0;
+  const bool tr_this = trace_at(g, m);
+  const bool tr_next = trace_at(g, m + 1);
   const bool have_row = tr_this && g->trace_rows < g->trace_cap;
   if (tr_this && !have_row) g->trace_dropped++;
   const bool probe = g->probe.on != 0;
@@ -448,8 +455,8 @@ static bool pair_now(const fit_grid* g, int64_t nleft) {
   // the tile may no longer fit after the materials or spacing changed
   // (lossless -> lossy, uniform -> tensor grid)
   if (!step2_shape_ok(g->ptw, g->pty, g->esz, g->lossy, g->nu)) return false;
-  const int64_t te = g->trace_every, m = g->m;
-  if (te > 0 && (m % te == 0 || (m + 1) % te == 0 || (m + 2) % te == 0)) return false;
+  const int64_t m = g->m;
+  if (trace_at(g, m) || trace_at(g, m + 1) || trace_at(g, m + 2)) return false;
   return true;
 }
 
@@ -542,6 +549,13 @@ template int step_fused_io<float>(fit_grid*, double, const float*, const float*,
 template int step_fused_io<double>(fit_grid*, double, const double*, const double*, double*,
                                    double*);
 
+double step_dt(const fit_grid* g, double dt) {
+  if (g->f64) return dt;
+  float f = (float)dt;
+  if ((double)f > dt) f = std::nextafter(f, 0.0f);
+  return (double)f;
+}
+
 int check_dt(const fit_grid* g, double dt) {
   if (!(dt > 0.0) || !std::isfinite(dt)) return fail(FIT_E_INVALID, "dt must be positive and finite");
   if (!(g->desc.flags & FIT_ALLOW_UNSTABLE) && dt > g->cfl * (1.0 + 1e-12))
@@ -629,29 +643,76 @@ int time_candidate(fit_grid* g, double dt, int path, int tw, int ty, int kc, int
 // buffer set (e^(m+1), with the trace terms <e^m,e^m>, <e^m,e^(m+1)>, loss and
 // source), then the h-update with -dt turns h^(m+1/2) back into h^(m-1/2)
 // (<h^(m+1/2),h^(m+1/2)> and <h^(m+1/2),h^(m-1/2)>).  row: device, 10
-// doubles in the trace-row layout.
+// doubles in the trace-row layout; part: partial rows of the split tiling.
 template <typename T>
-static int state_terms(fit_grid* g, double dt, double* row) {
-  if (int rc = ensure_alt(g)) return rc;
+static int state_terms(fit_grid* g, double dt, double* part, double* row) {
   const Tiling t = make_tiling(g->d, g->ty, g->kc);
   const int64_t nb = t.blocks();
-  if (int rc = ensure_part(g, nb)) return rc;
   const T* e = static_cast<const T*>(g->e);
   const T* h = static_cast<const T*>(g->h);
   EArgs<T> ea;
   fill_eargs<T>(g, ea, e, static_cast<T*>(g->e_alt), h, dt, g->m);
+  ea.part = part;
   hipError_t er = launch_epass<T>(ea, g->lossy, true, false, g->s);
   if (er != hipSuccess) return hip_fail(er, "e-update launch");
   const int ecols[kPartTerms] = {1, 2, 3, 8, 9, -1, -1, -1, -1, -1};
-  er = launch_reduce(g->part, nb, row, ecols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
+  er = launch_reduce(part, nb, row, ecols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
   if (er != hipSuccess) return hip_fail(er, "reduce launch");
   HArgs<T> ha;
   fill_hargs<T>(g, ha, e, h, static_cast<T*>(g->h_alt), -dt);
+  ha.part = part;
   er = launch_hpass<T>(ha, g->mu_uniform, true, g->s);
   if (er != hipSuccess) return hip_fail(er, "h-update launch");
   const int hcols[kPartTerms] = {5, 4, -1, -1, -1, -1, -1, -1, -1, -1};
-  er = launch_reduce(g->part, nb, row, hcols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
+  er = launch_reduce(part, nb, row, hcols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
   if (er != hipSuccess) return hip_fail(er, "reduce launch");
+  return FIT_OK;
+}
+
+// Partial-sum rows the energy entry points need (standalone energy kernel and
+// the split tiling of state_terms).
+int64_t energy_rows(const fit_grid* g) {
+  const Tiling t = make_tiling(g->d, g->ty, g->kc);
+  return std::max<int64_t>(std::min<int64_t>((g->d.n + 255) / 256, kEnergyBlocks), t.blocks());
+}
+
+// Enqueue the five energies of the current state into out (device, 5
+// doubles): the standalone <e,e>, <h,h> kernel, then (once a step has fixed
+// dt) the inner products of state_terms, combined on the device.  part: at
+// least energy_rows(g) rows; work: 12 doubles of device scratch.  The second
+// field buffer set must exist.  Allocates nothing.
+int energy_enqueue(fit_grid* g, double* part, double* work, double* out) {
+  double ge[3], gf2[3];
+  for (int a = 0; a < 3; ++a) {
+    ge[a] = g->gedge[a] / 4.0;
+    gf2[a] = g->gf2[a];
+  }
+  int64_t nblk = 0;
+  hipError_t e;
+  if (g->f64)
+    e = launch_energy<double>(static_cast<const double*>(g->e), static_cast<const double*>(g->h),
+                              static_cast<const double*>(g->eps),
+                              g->mu_uniform ? nullptr : static_cast<const double*>(g->imu),
+                              g->imu_u, g->d, ge, gf2, g->nu ? g->sq : nullptr, part, &nblk,
+                              g->s);
+  else
+    e = launch_energy<float>(static_cast<const float*>(g->e), static_cast<const float*>(g->h),
+                             static_cast<const float*>(g->eps),
+                             g->mu_uniform ? nullptr : static_cast<const float*>(g->imu),
+                             (float)g->imu_u, g->d, ge, gf2, g->nu ? g->sq : nullptr, part,
+                             &nblk, g->s);
+  if (e != hipSuccess) return hip_fail(e, "energy launch");
+  const int cols[kPartTerms] = {0, 1, -1, -1, -1, -1, -1, -1, -1, -1};
+  e = launch_reduce(part, nblk, work, cols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
+  if (e != hipSuccess) return hip_fail(e, "reduce launch");
+  const double dt = g->last_dt;
+  if (dt > 0.0) {
+    int rc = g->f64 ? state_terms<double>(g, dt, part, work + 2)
+                    : state_terms<float>(g, dt, part, work + 2);
+    if (rc) return rc;
+  }
+  e = launch_energy_combine(work, dt, out, g->s);
+  if (e != hipSuccess) return hip_fail(e, "energy combine launch");
   return FIT_OK;
 }
 
@@ -688,6 +749,10 @@ int fit_grid_create(const fit_grid_desc* desc, void* stream, fit_grid** out) {
   if (g->desc.eps0 == 0.0) g->desc.eps0 = 1.0;
   if (g->desc.mu0 == 0.0) g->desc.mu0 = 1.0;
   g->s = static_cast<hipStream_t>(stream);
+  if (hipGetDevice(&g->dev) != hipSuccess) {
+    (void)hipGetLastError();
+    g->dev = 0;
+  }
   g->f64 = desc->dtype == FIT_F64;
   g->esz = g->f64 ? 8 : 4;
   g->d.nx = desc->nx;
@@ -913,6 +978,12 @@ int fit_set_source(fit_grid* g, int axis, int i, int j, int k, double i_max, dou
   return FIT_OK;
 }
 
+int fit_step_dt(const fit_grid* g, double dt, double* dt_used) {
+  if (!g || !dt_used) return fail(FIT_E_INVALID, "null argument");
+  *dt_used = step_dt(g, dt);
+  return FIT_OK;
+}
+
 int fit_cfl_dt(const fit_grid* g, double* dt_cfl) {
   if (!g || !dt_cfl) return fail(FIT_E_INVALID, "null argument");
   *dt_cfl = g->cfl;
@@ -1098,6 +1169,7 @@ int fit_step(fit_grid* g, int64_t nsteps, double dt) {
   if (nsteps < 0) return fail(FIT_E_INVALID, "nsteps must be >= 0");
   int rc = check_dt(g, dt);
   if (rc) return rc;
+  dt = step_dt(g, dt);
   if (nsteps > 0) g->last_dt = dt;
   const bool fused = use_fused(g);
   for (int64_t s = 0; s < nsteps; ++s) {
@@ -1119,53 +1191,14 @@ int fit_step(fit_grid* g, int64_t nsteps, double dt) {
 
 int fit_energy(fit_grid* g, double out[5]) {
   if (!g || !out) return fail(FIT_E_INVALID, "null argument");
-  const int64_t nb = (g->d.n + 255) / 256;
-  int rc = ensure_part(g, nb);
+  int rc = ensure_alt(g);
+  if (!rc) rc = ensure_part(g, energy_rows(g));
+  if (!rc) rc = energy_enqueue(g, g->part, g->jacc + kJaccWork, g->jacc + kJaccOut);
   if (rc) return rc;
-  double ge[3], gf2[3];
-  for (int a = 0; a < 3; ++a) {
-    ge[a] = g->gedge[a] / 4.0;
-    gf2[a] = g->gf2[a];
-  }
-  int64_t nblk = 0;
-  hipError_t e;
-  if (g->f64)
-    e = launch_energy<double>(static_cast<const double*>(g->e), static_cast<const double*>(g->h),
-                              static_cast<const double*>(g->eps),
-                              g->mu_uniform ? nullptr : static_cast<const double*>(g->imu),
-                              g->imu_u, g->d, ge, gf2, g->nu ? g->sq : nullptr, g->part, &nblk,
-                              g->s);
-  else
-    e = launch_energy<float>(static_cast<const float*>(g->e), static_cast<const float*>(g->h),
-                             static_cast<const float*>(g->eps),
-                             g->mu_uniform ? nullptr : static_cast<const float*>(g->imu),
-                             (float)g->imu_u, g->d, ge, gf2, g->nu ? g->sq : nullptr, g->part,
-                             &nblk, g->s);
-  if (e != hipSuccess) return hip_fail(e, "energy launch");
-  // reduce into the tail of the partial buffer's first row is unsafe; use the pending slot pair
-  const int cols[kPartTerms] = {0, 1, -1, -1, -1, -1, -1, -1, -1, -1};
-  e = launch_reduce(g->part, nblk, g->jacc + 2, cols, -1, 0.0, nullptr, -1, -1, nullptr, -1, g->s);
-  if (e != hipSuccess) return hip_fail(e, "reduce launch");
-  const double dt = g->last_dt;
-  if (dt > 0.0) {
-    rc = g->f64 ? state_terms<double>(g, dt, g->jacc + kJaccRow)
-                : state_terms<float>(g, dt, g->jacc + kJaccRow);
-    if (rc) return rc;
-  }
-  double v[2 + FIT_TRACE_COLS];
-  e = hipMemcpyAsync(v, g->jacc + 2, (dt > 0.0 ? 2 + FIT_TRACE_COLS : 2) * sizeof(double),
-                     hipMemcpyDeviceToHost, g->s);
+  hipError_t e = hipMemcpyAsync(out, g->jacc + kJaccOut, 5 * sizeof(double),
+                                hipMemcpyDeviceToHost, g->s);
   if (e == hipSuccess) e = hipStreamSynchronize(g->s);
   if (e != hipSuccess) return hip_fail(e, "energy readback");
-  out[0] = v[0];
-  out[1] = v[1];
-  out[2] = out[3] = out[4] = NAN;
-  if (dt > 0.0) {
-    const double* r = v + 2;   // trace-row layout of step m
-    out[2] = 0.5 * (r[1] + r[2] + r[4] + r[5]);   // W^m, eq. energy
-    out[3] = r[1] + r[4];                          // Q^m
-    out[4] = -2.0 * dt * (r[8] + r[9]);            // Q^(m+1) - Q^m
-  }
   if (!std::isfinite(out[0]) || !std::isfinite(out[1]))
     return fail(FIT_E_DIVERGED, "energy is not finite");
   return FIT_OK;
@@ -1181,6 +1214,7 @@ int fit_trace_config(fit_grid* g, int64_t every, int64_t capacity) {
   g->trace_rows = 0;
   g->trace_dropped = 0;
   g->pend_m = -1;
+  g->trace_m0 = g->m;
   if (every > 0 && capacity > 0) {
     int rc = dev_alloc(reinterpret_cast<void**>(&g->trace),
                        (size_t)capacity * FIT_TRACE_COLS * sizeof(double), "trace");
@@ -1386,6 +1420,7 @@ int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* tw, int* ty, 
   if (reps < 1 || reps > 1000) return fail(FIT_E_INVALID, "reps must be in [1, 1000]");
   int rc = check_dt(g, dt);
   if (rc) return rc;
+  dt = step_dt(g, dt);
   struct Cand { int path, tw, ty, kc; };
   std::vector<Cand> cands;
   int cus = 256, dev = 0;

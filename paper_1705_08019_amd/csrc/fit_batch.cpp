@@ -563,22 +563,33 @@ static int batch_leave(fit_batch* b) {
   return FIT_OK;
 }
 
-int fit_batch_step(fit_batch* b, int64_t nsteps, const double* dt, int use_graph) {
+// The steps the grids advance with (FP32 grids: rounded down to FP32).
+static std::vector<double> batch_dts(const fit_batch* b, const double* dt) {
+  std::vector<double> v((size_t)b->nb);
+  for (int g = 0; g < b->nb; ++g) v[g] = step_dt(b->grids[g], dt[g]);
+  return v;
+}
+
+int fit_batch_step(fit_batch* b, int64_t nsteps, const double* dt_in, int use_graph) {
   if (!b) return fail(FIT_E_INVALID, "null batch");
   if (nsteps < 0) return fail(FIT_E_INVALID, "nsteps must be >= 0");
-  if (int rc = batch_check_dt(b, dt)) return rc;
+  if (int rc = batch_check_dt(b, dt_in)) return rc;
   if (nsteps == 0) return FIT_OK;
+  const std::vector<double> dtv = batch_dts(b, dt_in);
+  const double* dt = dtv.data();
   if (int rc = batch_enter(b)) return rc;
   int rc = b->f64 ? batch_run<double>(b, nsteps, dt, use_graph) : batch_run<float>(b, nsteps, dt, use_graph);
   int rc2 = batch_leave(b);
   return rc ? rc : rc2;
 }
 
-int fit_batch_autotune(fit_batch* b, const double* dt, int reps, int* tw, int* ty, int* kc,
+int fit_batch_autotune(fit_batch* b, const double* dt_in, int reps, int* tw, int* ty, int* kc,
                        float* ms_best) {
   if (!b) return fail(FIT_E_INVALID, "null batch");
   if (reps < 1 || reps > 1000) return fail(FIT_E_INVALID, "reps must be in [1, 1000]");
-  if (int rc = batch_check_dt(b, dt)) return rc;
+  if (int rc = batch_check_dt(b, dt_in)) return rc;
+  const std::vector<double> dtv = batch_dts(b, dt_in);
+  const double* dt = dtv.data();
   if (int rc = batch_enter(b)) return rc;
   struct Cand { int tw, ty; };
   std::vector<Cand> shapes;

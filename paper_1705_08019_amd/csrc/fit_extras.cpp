@@ -154,6 +154,7 @@ int fit_step_record(fit_grid* g, int64_t nsteps, double dt, void* e_rec, void* h
   if (!g || !e_rec || !h_rec) return fail(FIT_E_INVALID, "null argument");
   if (nsteps < 0) return fail(FIT_E_INVALID, "nsteps must be >= 0");
   if (int rc = check_dt(g, dt)) return rc;
+  dt = step_dt(g, dt);
   if (nsteps > 0) g->last_dt = dt;
   return g->f64 ? record_t<double>(g, nsteps, dt, e_rec, h_rec)
                 : record_t<float>(g, nsteps, dt, e_rec, h_rec);
@@ -231,6 +232,7 @@ int fit_adjoint_begin(fit_grid* g, int64_t nsteps, double dt) {
   if (g->nu) return fail(FIT_E_INVALID, "the adjoint needs a uniform spacing");
   if (!g->mu_uniform) return fail(FIT_E_INVALID, "the adjoint needs a uniform mu");
   if (int rc = check_dt(g, dt)) return rc;
+  dt = step_dt(g, dt);
   if (!g->adj) {
     g->adj = new (std::nothrow) fit_adjoint_ws();
     if (!g->adj) return fail(FIT_E_OOM, "host allocation failed");

@@ -24,6 +24,7 @@ struct fit_grid {
   fit_grid_desc desc{};
   fit::Dims d{};
   hipStream_t s = nullptr;
+  int dev = 0;                   // HIP device current at creation
   bool f64 = false;
   size_t esz = 4;
   void* e = nullptr;     // 3 * n field values, slot layout
@@ -68,6 +69,7 @@ struct fit_grid {
   int64_t part_rows = 0;
   double* trace = nullptr;
   int64_t trace_every = 0, trace_cap = 0, trace_rows = 0, trace_dropped = 0;
+  int64_t trace_m0 = 0;          // step counter when the trace was configured
   double* pend = nullptr;        // h cross term waiting for the next trace row
   int64_t pend_m = -1;
   double* jacc = nullptr;        // [0..1] probe (sum, comp), [2..3] energy scratch
@@ -99,10 +101,17 @@ struct fit_grid {
 
 namespace fit {
 
-// Device scratch g->jacc: [0..1] probe objective (sum, compensation), [2..3]
-// state energies, [kJaccRow ..) the 10 inner products of fit_energy.
-constexpr int kJaccRow = 4;
-constexpr int kJaccLen = 16;
+// Device scratch g->jacc: [0..1] probe objective (sum, compensation),
+// [kJaccWork, +12) the inner products fit_energy combines, [kJaccOut, +5) its
+// five results.
+constexpr int kJaccWork = 2;
+constexpr int kJaccOut = 14;
+constexpr int kJaccLen = 24;
+// Energy entry points (fit_api.cpp): partial rows needed, and the enqueue of
+// the five energies into device `out` (part: energy_rows rows; work: 12
+// doubles; the second field buffer set must exist; allocates nothing).
+int64_t energy_rows(const fit_grid* g);
+int energy_enqueue(fit_grid* g, double* part, double* work, double* out);
 
 extern thread_local std::string g_err;
 int fail(int code, const std::string& msg);
@@ -114,7 +123,15 @@ int ensure_pacc(fit_grid* g, int64_t rows);
 // The per-axis squared-width pointers of a tensor grid, or nulls.
 void set_metric(const fit_grid* g, const double* sq[3]);
 double source_value(const fit_grid* g, double dt, int64_t m);
+// Step m records a trace row: m - m0 is a multiple of the trace interval
+// (m0: the step counter when the trace was configured).
+bool trace_at(const fit_grid* g, int64_t m);
 int check_dt(const fit_grid* g, double dt);
+// The step a grid advances with: dt itself for FP64 grids; for FP32 grids
+// the largest FP32 value <= dt, so that the stencil coefficients (exact
+// multiples of it on a uniform unit grid) and the source times describe one
+// and the same leapfrog step.
+double step_dt(const fit_grid* g, double dt);
 template <typename T>
 int step_once(fit_grid* g, double dt, const T* ein, T* eout, const T* hin, T* hout);
 // Frees adjoint/other optional workspaces (defined with those features).

@@ -46,6 +46,8 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
 }
 
 constexpr int kPartTerms = 10;
+// Workgroups of the standalone energy kernel (grid-stride beyond that).
+constexpr int64_t kEnergyBlocks = 4096;
 // E-pass partial term slots
 enum { PE_EE_MM = 0, PE_EE_MM1 = 1, PE_EE_M1M1 = 2, PE_LOSS = 3, PE_SRC = 4, PE_PROBE = 5 };
 // H-pass partial term slots
@@ -322,6 +324,11 @@ hipError_t launch_hpass(const HArgs<T>& a, bool mu_uniform, bool energy, hipStre
 hipError_t launch_reduce(const double* part, int64_t nblk, double* dst, const int* cols,
                          int probe_term, double jscale, double* jacc, int nan_col,
                          int64_t row_m, const double* pend, int pend_col, hipStream_t s);
+
+// out[0..4] = <e,e>, <h,h>, W, Q, Q^(m+1) - Q^m from work[0..1] (<e,e>,
+// <h,h>) and work[2..11] (the trace-row terms of the step from the current
+// state); with dt <= 0 the last three are NaN.
+hipError_t launch_energy_combine(const double* work, double dt, double* out, hipStream_t s);
 
 // Add the per-workgroup probe rows (sum, compensation) pacc[0 .. nrows) into
 // the compensated pair jacc[0..1] in a fixed order, then clear the rows.

@@ -19,6 +19,7 @@
 #include "fit_internal.hpp"
 #include "fit_point.hpp"
 
+#include <algorithm>
 #include <cmath>
 
 namespace fit {
@@ -328,6 +329,29 @@ __global__ __launch_bounds__(512) void k_hpass(HArgs<T> A) {
   }
 }
 
+// --------------------------------------------------------------------------- energy combination
+// out[0..4] from work (see launch_energy_combine): eq. energy's W^m, Q^m and
+// the Poynting balance Q^(m+1) - Q^m = -2 dt ebar . (M_sigma ebar + j_s).
+__global__ void k_energy_combine(const double* __restrict__ work, double dt,
+                                 double* __restrict__ out) {
+  if (threadIdx.x != 0) return;
+  out[0] = work[0];
+  out[1] = work[1];
+  if (dt > 0.0) {
+    const double* r = work + 2;
+    out[2] = 0.5 * (r[1] + r[2] + r[4] + r[5]);
+    out[3] = r[1] + r[4];
+    out[4] = -2.0 * dt * (r[8] + r[9]);
+  } else {
+    out[2] = out[3] = out[4] = __builtin_nan("");
+  }
+}
+
+hipError_t launch_energy_combine(const double* work, double dt, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_energy_combine, dim3(1), dim3(64), 0, s, work, dt, out);
+  return hipGetLastError();
+}
+
 // --------------------------------------------------------------------------- probe rows
 // One workgroup: thread t sums rows t, t + 256, ... (Neumaier over sum and
 // compensation), the partial totals are combined in thread order, and the
@@ -568,9 +592,13 @@ __global__ __launch_bounds__(256) void k_energy(const T* __restrict__ e, const T
                                                 double gex, double gey, double gez, double gfx,
                                                 double gfy, double gfz, const double* sq,
                                                 double* part) {
-  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.y * 64 + threadIdx.x;
+  // grid-stride over the cell slots (at most kEnergyBlocks workgroups), FP64
+  // Neumaier accumulation per thread
   double v[2] = {0.0, 0.0};
-  if (idx < d.n) {
+  double cv[2] = {0.0, 0.0};
+  for (int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.y * 64 + threadIdx.x; idx < d.n;
+       idx += (int64_t)gridDim.x * 256) {
+    double ve = 0.0, vh = 0.0;
     int i, j, k;
     decode(idx, d, i, j, k);
     auto ce = [&](int ii, int jj, int kk) -> double {
@@ -583,25 +611,30 @@ __global__ __launch_bounds__(256) void k_energy(const T* __restrict__ e, const T
     };
     const double ex = e[idx], ey = e[idx + d.n], ez = e[idx + 2 * d.n];
     const double hx = h[idx], hy = h[idx + d.n], hz = h[idx + 2 * d.n];
+    double gx = gex, gy = gey, gz = gez, fx = gfx, fy = gfy, fz = gfz;
     if (sq) {   // tensor grid: eps, imu hold cell values times the cell volume
       const double qx = sq[i], qy = sq[d.nx + j], qz = sq[d.nx + d.ny + k];
-      gex = 0.25 / qx;
-      gey = 0.25 / qy;
-      gez = 0.25 / qz;
-      gfx = 0.5 / (qy * qz);
-      gfy = 0.5 / (qx * qz);
-      gfz = 0.5 / (qx * qy);
+      gx = 0.25 / qx;
+      gy = 0.25 / qy;
+      gz = 0.25 / qz;
+      fx = 0.5 / (qy * qz);
+      fy = 0.5 / (qx * qz);
+      fz = 0.5 / (qx * qy);
     }
     if (edge_live(0, i, j, k))
-      v[0] += gex * (ce(i, j, k) + ce(i, j - 1, k) + ce(i, j, k - 1) + ce(i, j - 1, k - 1)) * ex * ex;
+      ve += gx * (ce(i, j, k) + ce(i, j - 1, k) + ce(i, j, k - 1) + ce(i, j - 1, k - 1)) * ex * ex;
     if (edge_live(1, i, j, k))
-      v[0] += gey * (ce(i, j, k) + ce(i - 1, j, k) + ce(i, j, k - 1) + ce(i - 1, j, k - 1)) * ey * ey;
+      ve += gy * (ce(i, j, k) + ce(i - 1, j, k) + ce(i, j, k - 1) + ce(i - 1, j, k - 1)) * ey * ey;
     if (edge_live(2, i, j, k))
-      v[0] += gez * (ce(i, j, k) + ce(i - 1, j, k) + ce(i, j - 1, k) + ce(i - 1, j - 1, k)) * ez * ez;
-    if (facet_live(0, i, j, k)) v[1] += hx * hx / (gfx * (cm(i, j, k) + cm(i - 1, j, k)));
-    if (facet_live(1, i, j, k)) v[1] += hy * hy / (gfy * (cm(i, j, k) + cm(i, j - 1, k)));
-    if (facet_live(2, i, j, k)) v[1] += hz * hz / (gfz * (cm(i, j, k) + cm(i, j, k - 1)));
+      ve += gz * (ce(i, j, k) + ce(i - 1, j, k) + ce(i, j - 1, k) + ce(i - 1, j - 1, k)) * ez * ez;
+    if (facet_live(0, i, j, k)) vh += hx * hx / (fx * (cm(i, j, k) + cm(i - 1, j, k)));
+    if (facet_live(1, i, j, k)) vh += hy * hy / (fy * (cm(i, j, k) + cm(i, j - 1, k)));
+    if (facet_live(2, i, j, k)) vh += hz * hz / (fz * (cm(i, j, k) + cm(i, j, k - 1)));
+    nadd(v[0], cv[0], ve);
+    nadd(v[1], cv[1], vh);
   }
+  v[0] += cv[0];
+  v[1] += cv[1];
   // blockDim = (64, 4) viewed as 256 threads: reuse the 2-D block sum
   block_sum_store<2>(v, part + (int64_t)blockIdx.x * kPartTerms);
 }
@@ -610,7 +643,7 @@ template <typename T>
 hipError_t launch_energy(const T* e, const T* h, const T* eps, const T* imu, T imu_u,
                          const Dims& d, const double ge[3], const double gf2[3], const double* sq,
                          double* part, int64_t* nblk, hipStream_t s) {
-  const int64_t nb = (d.n + 255) / 256;
+  const int64_t nb = std::min<int64_t>((d.n + 255) / 256, kEnergyBlocks);
   *nblk = nb;
   hipLaunchKernelGGL(k_energy<T>, dim3((unsigned)nb), dim3(64, 4), 0, s, e, h, eps, imu, imu_u, d,
                      ge[0], ge[1], ge[2], gf2[0], gf2[1], gf2[2], sq, part);

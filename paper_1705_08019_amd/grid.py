@@ -112,6 +112,13 @@ class FitGrid:
     def clear_source(self):
         call("fit_set_source", self._h, -1, 0, 0, 0, 0.0, 1.0)
 
+    def step_dt(self, dt: float) -> float:
+        """The step the grid takes when asked for dt (FP32 grids: dt rounded
+        down to FP32)."""
+        v = C.c_double()
+        call("fit_step_dt", self._h, float(dt), C.byref(v))
+        return v.value
+
     def cfl_dt(self) -> float:
         v = C.c_double()
         call("fit_cfl_dt", self._h, C.byref(v))

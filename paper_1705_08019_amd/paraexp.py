@@ -69,6 +69,7 @@ def paraexp(nx: int, ny: int, nz: int, eps_r, dt: float, nsteps: int, p: int,
                          source.get("i_max", 1.0), st)
         g.set_fields(None, None, j * L)
         grids.append(g)
+    dt = grids[0].step_dt(dt)   # the step the leapfrog runs take (FP32: rounded down)
     b = FitBatch(grids)
     if batch_tuning is not None:
         b.set_tuning(*batch_tuning)

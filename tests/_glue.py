@@ -61,3 +61,14 @@ edges_from_slots = layout.edges_from_slots
 facets_from_slots = layout.facets_from_slots
 edges_to_slots = layout.edges_to_slots
 facets_to_slots = layout.facets_to_slots
+
+
+def state_errors(ops, e, h, e_ref, h_ref) -> dict:
+    """Errors of e and h (kept-entity vectors) against the reference: each
+    relative to its own L2 norm, and each in the energy norm relative to the
+    energy norm of the whole reference state, sqrt(<e,e>_eps + <h,h>_mu)."""
+    de, dh = np.asarray(e) - e_ref, np.asarray(h) - h_ref
+    scale = np.sqrt(e_ref @ (ops.M_eps * e_ref) + h_ref @ (ops.M_mu * h_ref))
+    return dict(e_own=rel_l2(e, e_ref), h_own=rel_l2(h, h_ref),
+                e_state=float(np.sqrt(de @ (ops.M_eps * de)) / scale),
+                h_state=float(np.sqrt(dh @ (ops.M_mu * dh)) / scale))

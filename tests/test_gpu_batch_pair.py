@@ -7,7 +7,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from fit_workloads import c4, c4_small
+from fit_workloads import c4, c4_small, lossy_slab
 from test_gpu_batch_step import _make, _fields, _assert_equal
 
 pytestmark = pytest.mark.gpu
@@ -96,4 +96,69 @@ def test_zero_steps_change_nothing(dtype):
         assert [g.smvp_count() for g in gb] == smvp
     b.step(2, dts)                                # still usable afterwards
     assert [g.step_index for g in gb] == [i + 2 for i in idx]
+    b.close()
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("which", ["small", "c4"])
+def test_batch_pairs_match_oracle(dtype, which):
+    """Each grid of a batch advanced by graph-captured pair launches (Sec. III,
+    Alg. 1: the p particular solutions are independent leapfrog runs) equals
+    the oracle's leapfrog run of that grid: FP64 relative L2 <= 1e-12, FP32
+    <= 1e-4, after >= 100 steps (odd count: a last single step)."""
+    from paper_1705_08019_amd import FitBatch
+    from oracle.leapfrog import run
+    from _glue import oracle_ops, to_np, edges_from_slots, facets_from_slots, state_errors
+    specs = c4_small(count=6, nsteps=0) if which == "small" else c4()[:3]
+    gb, dts = _make(specs, dtype, lossy_every=3)
+    b = FitBatch(gb)
+    b.set_pair(True, 8)
+    b.set_tuning(0, 0, 16)
+    n = 121 if which == "small" else 101
+    print(f"batch pairs vs oracle {dtype} {which}: {n} steps", flush=True)
+    b.step(n, dts)
+    tol = 1e-12 if dtype == "f64" else 1e-4
+    for k, (s, g, dt) in enumerate(zip(specs, gb, dts)):
+        sig = lossy_slab(s.nx, s.ny, s.nz, 2, 0.05) if k % 3 == 0 else None
+        ops = oracle_ops((s.nx, s.ny, s.nz), eps=s.eps_r, sigma=sig)
+        src = dict(s.source)
+        src["sigma_t"] = src.pop("sigma_t_steps") * dt      # as _make set it
+        step = g.step_dt(dt)                                # the step the grid took
+        e_r, h_r, _ = run(ops, np.zeros(ops.n_e), np.zeros(ops.n_h), step, n, source=src)
+        e, h = g.get_fields()
+        err = state_errors(ops, edges_from_slots(ops, to_np(e)), facets_from_slots(ops, to_np(h)),
+                           e_r, h_r)
+        print(f"  grid {k} {s.nx}x{s.ny}x{s.nz}: " +
+              " ".join(f"{a} {b:.2e}" for a, b in err.items()), flush=True)
+        if dtype == "f64":
+            assert err["e_own"] <= tol and err["h_own"] <= tol, (k, err)
+        else:   # FP32: each field in the energy norm of the state (see test_gpu_horizon)
+            assert err["e_state"] <= tol and err["h_state"] <= tol and err["e_own"] <= tol, (k, err)
+    b.close()
+
+
+def test_batch_follows_a_grid_that_becomes_lossy():
+    """A batch laid out for lossless grids, one of which is then given a
+    conductivity, re-lays itself out for the lossy tile body (its LDS holds
+    the sigma planes) and still equals the plain runs bitwise; a grid that
+    gets a non-uniform mu is rejected."""
+    from paper_1705_08019_amd import FitBatch, FitError
+    specs = c4_small(count=5, nsteps=0)
+    gb, dts = _make(specs, "f32")
+    gp, _ = _make(specs, "f32")
+    b = FitBatch(gb)
+    b.set_pair(True, 0)
+    b.step(10, dts)
+    _plain(gp, dts, 10)
+    s = specs[2]
+    sig = lossy_slab(s.nx, s.ny, s.nz, 2, 0.1)
+    for g in (gb[2], gp[2]):
+        g.set_materials(s.eps_r, None, sig)
+    b.step(31, dts)
+    _plain(gp, dts, 31)
+    _assert_equal(_fields(gb), _fields(gp))
+    gb[1].set_materials(specs[1].eps_r, np.full(specs[1].eps_r.shape, 2.0) +
+                        (np.arange(specs[1].eps_r.size) % 2).reshape(specs[1].eps_r.shape))
+    with pytest.raises(FitError, match="STATE"):
+        b.step(2, dts)
     b.close()

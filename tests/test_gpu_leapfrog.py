@@ -40,8 +40,11 @@ def _derived(row):
 
 
 def _compare_trace(tr_gpu, tr_ref, steps, tol):
+    """Trace rows against the oracle's; prints the achieved errors (relative to
+    the energy scale) of the individual inner products and of W, Q, R."""
     _, etol, ctol = tol
     scale = np.nanmax(np.abs(tr_ref[:, 1:8]))
+    worst_c = worst_d = 0.0
     for row in tr_gpu:
         m = int(row[0])
         assert m in steps
@@ -50,11 +53,15 @@ def _compare_trace(tr_gpu, tr_ref, steps, tol):
             if math.isnan(ref[c]):
                 assert math.isnan(row[c]), (m, c)
             else:
+                worst_c = max(worst_c, abs(row[c] - ref[c]) / scale)
                 assert abs(row[c] - ref[c]) <= ctol * scale, (m, c, row[c], ref[c])
         dg, dr = _derived(row), _derived(ref)
         for q in range(4):
             if not math.isnan(dr[q]):
+                worst_d = max(worst_d, abs(dg[q] - dr[q]) / scale)
                 assert abs(dg[q] - dr[q]) <= etol * scale, (m, q, dg[q], dr[q])
+    print(f"trace vs oracle: inner products {worst_c:.2e}, W/Q/R {worst_d:.2e} "
+          f"(of the energy scale)", flush=True)
 
 
 @pytest.mark.parametrize("path", ["split", "fused"])
