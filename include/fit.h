@@ -227,6 +227,21 @@ int fit_step(fit_grid* g, int64_t nsteps, double dt);
  * filled) if out[0] or out[1] is not finite. */
 int fit_energy(fit_grid* g, double out[5]);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the five
+ * values of fit_energy written to out (a DEVICE pointer to 5 doubles) on the
+ * handle's stream, with no allocation, no memset and no synchronisation.
+ * The partial sums go to a fixed array of the library on the handle's
+ * device (640 KiB, held until the process ends, shared by every call on that
+ * device: calls that overlap on one device race).  Limits: the grid's
+ * partial-sum rows (at most 4096 for the energy kernel, and the workgroups of
+ * the half-step kernels' tiling) must not exceed 8192 (else FIT_E_INVALID);
+ * the second field buffer set must already exist (bound with
+ * fit_bind_fields or allocated by an earlier step; else FIT_E_STATE).
+ * Values equal fit_energy's bitwise.  The first call on a device looks up the
+ * array's device address. */
+int fit_energy_noalloc(fit_grid* g, double* out);
+
 /* Energy trace.  every > 0 records one row for each step m with
  * (m - m0) % every == 0, m0 the step counter at this call (every = 0
  * disables); up to `capacity` rows are kept

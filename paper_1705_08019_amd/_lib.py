@@ -57,6 +57,7 @@ SIGNATURES = {
     "fit_apply_curl": [_vp, _i, _vp, _vp],
     "fit_step": [_vp, _i64, _d],
     "fit_energy": [_vp, _dp],
+    "fit_energy_noalloc": [_vp, _vp],
     "fit_trace_config": [_vp, _i64, _i64],
     "fit_trace_read": [_vp, _dp, _i64, _i64p, _i64p],
     "fit_set_probe": [_vp, _i32p, _i32p],
