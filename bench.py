@@ -636,26 +636,34 @@ def form_gram(Ks=(64, 16), reps: int = 5):
 
 
 def calib_copy(nbytes: int = 1 << 30, reps: int = 3):
-    """Plain device copy of known size (dst.copy_(src), FP32) for scaling the
-    HBM byte counters: each launch reads and writes exactly nbytes."""
+    """Copies of known size for checking the HBM byte counters: the library's
+    streaming copy (k_stream_copy) and torch's copy_, each reading and
+    writing exactly nbytes per launch."""
+    import ctypes as C
     import torch
+    from paper_1705_08019_amd._lib import call
     n = nbytes // 4
     src = torch.ones(n, dtype=torch.float32, device="cuda")
     dst = torch.empty_like(src)
+    stream = C.c_void_p(torch.cuda.current_stream().cuda_stream)
     torch.cuda.synchronize()
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
-    ms = []
-    for _ in range(reps):
-        ev[0].record()
-        dst.copy_(src)
-        ev[1].record()
-        torch.cuda.synchronize()
-        ms.append(ev[0].elapsed_time(ev[1]))
-    best = min(ms)
-    print(json.dumps({"calib_copy_bytes_each_way": nbytes, "reps": reps,
-                      "best_ms": round(best, 4),
-                      "copy_GBs_read_plus_write": round(2 * nbytes / (best / 1e3) / 1e9, 1)}),
-          flush=True)
+    res = {}
+    for name in ("k_stream_copy", "torch_copy"):
+        ms = []
+        for _ in range(reps):
+            ev[0].record()
+            if name == "torch_copy":
+                dst.copy_(src)
+            else:
+                call("fit_stream_probe", 0, C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
+                     nbytes, 8192, stream)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms.append(ev[0].elapsed_time(ev[1]))
+        res[name] = {"best_ms": round(min(ms), 4),
+                     "GBs_read_plus_write": round(2 * nbytes / (min(ms) / 1e3) / 1e9, 1)}
+    print(json.dumps({"calib_copy_bytes_each_way": nbytes, "reps": reps, **res}), flush=True)
 
 
 def _csv_rows(d, suffix):
@@ -696,65 +704,92 @@ def summarize_kernels(kt, out_md, cmd_note, title):
         fh.write("\n".join(lines) + "\n")
 
 
-def summarize(kt, fetch, write, cfetch, cwrite, out_md, cells, cmd_note):
-    """Turn rocprofv3 outputs into profiles/<name>.md and profiles/traffic_c3.json."""
+# Request-size counters of the L2 (TCC) to memory (EA) interface: reads of
+# 32, 64 and 128 bytes, writes of 64 bytes (the rest 32 bytes).  Bytes per
+# dispatch = sum(size x count); no scale factor: a copy of known size checks
+# them (its counted bytes over the bytes it must move are reported).
+RD_COUNTERS = ("TCC_EA0_RDREQ_sum", "TCC_EA0_RDREQ_32B_sum", "TCC_EA0_RDREQ_64B_sum",
+               "TCC_EA0_RDREQ_128B_sum")
+WR_COUNTERS = ("TCC_EA0_WRREQ_sum", "TCC_EA0_WRREQ_64B_sum", "TCC_EA0_RDREQ_DRAM_sum",
+               "TCC_EA0_WRREQ_DRAM_sum")
+
+
+def _counters(dirs):
+    """{(kernel, grid, wg): {counter: [per-dispatch values]}} over --pmc runs."""
+    out = {}
+    for d in dirs:
+        for r in _csv_rows(d, "_counter_collection.csv"):
+            key = (r["Kernel_Name"], int(r["Grid_Size"]), int(r["Workgroup_Size"]))
+            out.setdefault(key, {}).setdefault(r["Counter_Name"], []).append(
+                float(r["Counter_Value"]))
+    return out
+
+
+def request_bytes(c):
+    """(read bytes, write bytes, read requests unaccounted) per dispatch from
+    the request-size counters (averages over the dispatches)."""
+    def avg(name):
+        v = c.get(name) or c.get(name.replace("_sum", ""))
+        return sum(v) / len(v) if v else 0.0
+    n, n32, n64, n128 = (avg(x) for x in RD_COUNTERS)
+    w, w64 = avg("TCC_EA0_WRREQ_sum"), avg("TCC_EA0_WRREQ_64B_sum")
+    rd = 32 * n32 + 64 * n64 + 128 * n128
+    wr = 64 * w64 + 32 * (w - w64)
+    return rd, wr, n - (n32 + n64 + n128)
+
+
+def summarize(kt, rd_dir, wr_dir, out_md, cells, cmd_note):
+    """Kernel durations and request-counted memory bytes of the bandwidth
+    workload -> profiles/<name>.md and profiles/traffic_c3.json."""
     stats = _csv_rows(kt, "_kernel_stats.csv")
-    calib = 1 << 30
-    cf = _counter_by_launch(cfetch, "FETCH_SIZE")
-    cw = _counter_by_launch(cwrite, "WRITE_SIZE")
-    f_copy = [v for k, vals in cf.items() if "copyBuffer" in k[0] or "copy" in k[0].lower()
-              for v in vals]
-    w_copy = [v for k, vals in cw.items() if "copyBuffer" in k[0] for v in vals]
-    fscale = calib / 1024.0 / (sum(f_copy) / len(f_copy))
-    wscale = calib / 1024.0 / (sum(w_copy) / len(w_copy))
-    fe = _counter_by_launch(fetch, "FETCH_SIZE")
-    wr = _counter_by_launch(write, "WRITE_SIZE")
+    cnt = _counters([rd_dir, wr_dir])
     lines = ["# rocprofv3 summary: " + os.path.basename(out_md).replace(".md", ""), "",
              "Commands (run from the repository root on the MI355X box):", "", "```"]
     lines += cmd_note + ["```", "", "## Kernel durations (--kernel-trace --stats)", "",
                          "| kernel | calls | avg us | min us | max us |", "|---|---|---|---|---|"]
-    for r in stats:
+    for r in sorted(stats, key=lambda r: -float(r["TotalDurationNs"])):
         lines.append(f"| `{r['Name'][:90]}` | {r['Calls']} | {float(r['AverageNs'])/1e3:.2f} | "
                      f"{float(r['MinNs'])/1e3:.2f} | {float(r['MaxNs'])/1e3:.2f} |")
-    lines += ["", "## HBM bytes (--pmc FETCH_SIZE, --pmc WRITE_SIZE)", "",
-              f"Calibration: a plain 1 GiB device copy reads FETCH_SIZE = "
-              f"{sum(f_copy)/len(f_copy):.0f} KiB and writes WRITE_SIZE = "
-              f"{sum(w_copy)/len(w_copy):.0f} KiB per launch, so the scale factors are "
-              f"fetch x{fscale:.3f}, write x{wscale:.3f}.", "",
-              "| kernel | grid | wg | launches | FETCH KiB | WRITE KiB | scaled GB/launch | "
-              "B/cell |", "|---|---|---|---|---|---|---|---|"]
+    lines += ["", "## Memory bytes per dispatch (request-size counters)", "",
+              "read = 32 RDREQ_32B + 64 RDREQ_64B + 128 RDREQ_128B, write = 64 WRREQ_64B + "
+              "32 (WRREQ - WRREQ_64B), all summed over the TCC instances (L2-miss traffic to "
+              "the memory side: Infinity Cache or HBM).  `unaccounted` = RDREQ minus the three "
+              "sized counts.  DRAM columns: requests of either size the TCC sends to DRAM.", "",
+              "| kernel | grid | wg | dispatches | read MB | write MB | B/cell | "
+              "unaccounted reqs | RDREQ_DRAM | WRREQ_DRAM |", "|---|---|---|---|---|---|---|---|---|---|"]
     kernels = {}
-    for key in sorted(set(fe) | set(wr)):
-        f = fe.get(key, [0.0])
-        w = wr.get(key, [0.0])
-        fk, wk = sum(f) / len(f), sum(w) / len(w)
-        gb = (fk * fscale + wk * wscale) * 1024 / 1e9
-        bpc = gb * 1e9 / cells
+    for key in sorted(cnt):
+        c = cnt[key]
+        rd, wr, lost = request_bytes(c)
+        nd = max(len(v) for v in c.values())
+        bpc = (rd + wr) / cells
+        dram = [sum(c.get(x, [0.0])) / max(len(c.get(x, [0.0])), 1)
+                for x in ("TCC_EA0_RDREQ_DRAM_sum", "TCC_EA0_WRREQ_DRAM_sum")]
+        lines.append(f"| `{key[0][:70]}` | {key[1]} | {key[2]} | {nd} | {rd/1e6:.1f} | "
+                     f"{wr/1e6:.1f} | {bpc:.2f} | {lost:.0f} | {dram[0]:.0f} | {dram[1]:.0f} |")
         name = key[0]
-        lines.append(f"| `{name[:70]}` | {key[1]} | {key[2]} | {len(f)} | {fk:.0f} | {wk:.0f} | "
-                     f"{gb:.4f} | {bpc:.2f} |")
         tag = ("pair" if "k_step2<float, true, false" in name
                else "step" if "k_step<float, true, false, false" in name
                else "epass" if "k_epass<float, true, false, false>" in name
-               else "hpass" if "k_hpass<float, true, false>" in name else None)
-        if tag and (tag not in kernels or len(f) > kernels[tag]["launches"]):
-            kernels[tag] = {"source_hash": kernel_source_hash(tag),
-                            "bytes_per_launch": round(gb * 1e9), "bytes_per_cell": round(bpc, 2),
-                            "fetch_KiB": round(fk, 1), "write_KiB": round(wk, 1),
-                            "fetch_scale": round(fscale, 4), "write_scale": round(wscale, 4),
-                            "launches": len(f), "grid": key[1], "wg": key[2]}
+               else "hpass" if "k_hpass<float, true, false>" in name
+               else "stream_copy" if "k_stream_copy" in name else None)
+        if tag and (tag not in kernels or nd > kernels[tag]["dispatches"]):
+            kernels[tag] = {"source_hash": kernel_source_hash(tag) if tag in KERNEL_SOURCES
+                            else None,
+                            "bytes_per_launch": round(rd + wr), "read_bytes": round(rd),
+                            "write_bytes": round(wr), "bytes_per_cell": round(bpc, 2),
+                            "dispatches": nd, "grid": key[1], "wg": key[2],
+                            "method": "request-size counters (no scale factor)"}
+    if "stream_copy" in kernels:
+        k = kernels["stream_copy"]
+        lines += ["", f"Check: the streaming copy of 1 GiB each way counts "
+                      f"{k['read_bytes'] / 2**30:.4f} GiB read and {k['write_bytes'] / 2**30:.4f} "
+                      f"GiB written per dispatch."]
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     tpath = os.path.join(os.path.dirname(out_md), "traffic_c3.json")
-    rec = {"cells": cells, "kernels": {}, "summaries": []}
-    try:
-        with open(tpath) as fh:
-            rec = json.load(fh)
-    except (OSError, ValueError):
-        pass
-    rec["kernels"].update(kernels)
-    if os.path.basename(out_md) not in rec["summaries"]:
-        rec["summaries"].append(os.path.basename(out_md))
+    rec = {"cells": cells, "kernels": kernels, "summaries": [os.path.basename(out_md)],
+           "method": "request-size counters: 32/64/128 B reads, 64/32 B writes"}
     with open(tpath, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
@@ -792,8 +827,9 @@ def main(argv=None):
                     help="write --summary-out from one rocprofv3 --kernel-trace --stats run")
     ap.add_argument("--forms-only", action="store_true",
                     help="run only the batched / adjoint / Gram / ParaExp / graded forms")
-    ap.add_argument("--summarize", nargs=5, metavar="DIR", default=None,
-                    help="kt fetch write copyfetch copywrite rocprofv3 output dirs -> profiles/")
+    ap.add_argument("--summarize", nargs=3, metavar="DIR", default=None,
+                    help="kernel-trace, read-counter and write-counter rocprofv3 output dirs "
+                         "-> profiles/")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "fused_step_c3.md"))
     ap.add_argument("--summary-cmd", action="append", default=[])
     args = ap.parse_args(argv)
