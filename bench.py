@@ -270,6 +270,29 @@ def form_batched(plain_steps: int = 400):
     ev[1].record()
     torch.cuda.synchronize()
     ms_b = ev[0].elapsed_time(ev[1])
+    # the persistent form: 16 steps of every grid per cooperative launch with a
+    # grid-wide barrier between the steps, the launch replayed from a hipGraph
+    persist = None
+    try:
+        b.set_pair(False)
+        b.set_tuning(0, 0, 16)
+        b.set_persistent(True)
+        b.step(32, dts)
+        torch.cuda.synchronize()
+        ev[0].record()
+        b.step(nsteps, dts)
+        ev[1].record()
+        torch.cuda.synchronize()
+        ms_ps = ev[0].elapsed_time(ev[1])
+        on, nwg, cap, failed = b.get_persistent()
+        gps = cells * nsteps / (ms_ps / 1e3) / 1e9
+        persist = {"Gcell_updates_per_s": round(gps, 3), "workgroups": nwg,
+                   "items_per_step": b.get_tuning()[3], "steps_per_launch": 16,
+                   "captured_in_graph": cap, "barrier_gave_up": failed,
+                   "alg_GBs": round(B_LAUNCH * gps, 1),
+                   "frac": round(B_LAUNCH * gps / PEAK_HBM_GBS, 4)}
+    except Exception as ex:   # reported, not hidden
+        persist = {"error": f"{type(ex).__name__}: {ex}"}
     b.close()
     for g in grids:
         g.close()
@@ -297,6 +320,7 @@ def form_batched(plain_steps: int = 400):
             "plain_per_grid_Gcell_updates_per_s": round(gp, 3),
             "plain_steps_timed": plain_steps, "batched_over_plain": round(gb / gp, 3),
             "tile": [tw, ty, kc], "pair_kc": pair_kc if pair_on else None,
+            "persistent": persist,
             "launch": ("one launch per pair of steps of all grids (32 x 16 tiles), hipGraph "
                        "chunks of 8 pairs" if pair_on else
                        "one launch per step of all grids, hipGraph chunks of 16")}

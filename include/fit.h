@@ -467,6 +467,27 @@ int fit_batch_get_tuning(const fit_batch* b, int* tw, int* ty, int* kc, int* ste
 int fit_batch_set_pair(fit_batch* b, int enable, int kc);
 int fit_batch_get_pair(const fit_batch* b, int* enable, int* kc);
 
+/* Persistent form of the batch (Sec. III, Alg. 1: the p independent leapfrog
+ * runs): with enable = 1, S steps of every grid run in ONE cooperative launch
+ * (S = steps_per_graph of fit_batch_set_tuning) whose workgroups -- as many
+ * as the device holds at once, at most one per item -- each take items w,
+ * w + G, w + 2G, ... of a step's tile table and then meet the whole launch
+ * at a grid-wide barrier before the next step.  The S-step launch is
+ * captured in a hipGraph and replayed for whole chunks (use_graph != 0; if
+ * the runtime cannot capture a cooperative launch, chunks are launched
+ * directly), the remainder runs as one launch.  Single steps only (pairs
+ * are not used while it is on).  Each grid's result stays bitwise identical
+ * to fit_step on that grid alone.  The barrier polls a device counter; a
+ * poll that waits longer than about half a second gives up and flags the
+ * call (the launch then ends with wrong fields instead of hanging).  get:
+ * enable, the workgroups of the launch, whether the launch is captured, and
+ * (synchronising) whether a barrier of the last fit_batch_step gave up; any
+ * output may be NULL.  Errors: FIT_E_INVALID if the device cannot launch
+ * cooperatively or the tile does not fit. */
+int fit_batch_set_persistent(fit_batch* b, int enable);
+int fit_batch_get_persistent(const fit_batch* b, int* enable, int* workgroups, int* captured,
+                             int* barrier_failed);
+
 /* Autotuner: time candidate (tw, ty, kc), row-packed ones included, with
  * `reps` single-step launches each (state unchanged) and keep the fastest;
  * then time step pairs (kc 16, 8, 6, 4) and switch them on when a pair takes

@@ -87,6 +87,9 @@ SIGNATURES = {
     "fit_batch_destroy": [_vp],
     "fit_batch_set_tuning": [_vp, _i, _i, _i, _i],
     "fit_batch_set_pair": [_vp, _i, _i],
+    "fit_batch_set_persistent": [_vp, _i],
+    "fit_batch_get_persistent": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                                 C.POINTER(C.c_int)],
     "fit_batch_get_pair": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "fit_batch_get_tuning": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                              C.POINTER(C.c_int), C.POINTER(C.c_int)],

@@ -57,6 +57,18 @@ class FitBatch:
         item, 0: whole columns)."""
         call("fit_batch_set_pair", self._h, int(bool(enable)), int(kc))
 
+    def set_persistent(self, enable: bool = True):
+        """S steps of every grid per cooperative launch with a grid-wide barrier
+        between the steps (S = steps_per_graph), captured in a hipGraph."""
+        call("fit_batch_set_persistent", self._h, int(bool(enable)))
+
+    def get_persistent(self):
+        """(enabled, workgroups of the launch, captured in a graph, a barrier of
+        the last step call gave up); synchronises."""
+        e, w, c, f = C.c_int(), C.c_int(), C.c_int(), C.c_int()
+        call("fit_batch_get_persistent", self._h, C.byref(e), C.byref(w), C.byref(c), C.byref(f))
+        return bool(e.value), w.value, bool(c.value), bool(f.value)
+
     def get_pair(self):
         """(enabled, kc)."""
         e, k = C.c_int(), C.c_int()

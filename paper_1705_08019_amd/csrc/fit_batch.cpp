@@ -40,6 +40,12 @@ struct fit_batch {
   int* item_grid2 = nullptr;     // device, P2 entries
   int P2 = 0;
   size_t lds2 = 0;
+  // persistent form: S steps per cooperative launch of persist_nwg resident
+  // workgroups (fit_batch_set_persistent); persist_graph: the S-step launch
+  // could be captured (else chunks are launched directly)
+  bool persist = false;
+  int persist_nwg = 0;
+  bool persist_graph = true;
 };
 
 namespace fit {
@@ -87,6 +93,22 @@ static Tiling batch_tiling(const fit_batch* b, const Dims& d) {
   return make_tiling(d, ty, kc, tw);
 }
 
+// Resident workgroups of the persistent kernel for the current layout
+// (at most one per item), 0 if it cannot run.
+static int persist_workgroups(const fit_batch* b) {
+  const size_t esz = b->f64 ? 8 : 4;
+  const int per_cu = batch_persist_blocks_per_cu(esz, b->nthreads, b->lds);
+  if (per_cu <= 0) return 0;
+  int cus = 256, dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  (void)hipGetLastError();
+  return (int)std::min<int64_t>((int64_t)per_cu * cus, b->P);
+}
+
 // Build the item table, the workgroup shape and the LDS size for the current
 // tiling.  FIT_E_INVALID (nothing changed) if a grid's tile needs more LDS
 // than a workgroup can have.
@@ -116,6 +138,11 @@ static int batch_layout(fit_batch* b) {
   b->lds = lds;
   (void)batch_prepare(esz, nt, lds);
   batch_drop_graph(b);
+  if (b->persist) {   // the persistent launch's resident workgroups for this layout
+    b->persist_nwg = persist_workgroups(b);
+    if (b->persist_nwg <= 0)
+      return fail(FIT_E_INVALID, "the persistent kernel cannot hold a workgroup of this tile");
+  }
   return FIT_OK;
 }
 
@@ -258,10 +285,62 @@ static BatchArgs<T> batch_args_pair(fit_batch* b, int fixed) {
   return a;
 }
 
+// nsteps steps of every grid through the persistent kernel: S-step launches
+// (a captured one replayed per chunk when the graph is wanted and capture
+// works), then one launch of the remainder.
+template <typename T>
+static int batch_run_persist(fit_batch* b, int64_t nsteps, int use_graph) {
+  const BatchArgs<T> a = batch_args_host<T>(b, 0);
+  const int nwg = b->persist_nwg;
+  hipError_t e = launch_batch_set_base(b->ctl, 0, b->s);
+  if (e != hipSuccess) return hip_fail(e, "batch step counter");
+  const int S = std::max(1, b->steps_per_graph);
+  int64_t done = 0;
+  if (use_graph && b->persist_graph && nsteps >= S) {
+    if (!b->exec || b->graph_S != S || b->graph_pairs) {
+      batch_drop_graph(b);
+      e = hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+      const hipError_t el = launch_batch_persist<T>(a, nwg, S, b->s);
+      e = hipStreamEndCapture(b->s, &b->graph);
+      if (el == hipSuccess && e == hipSuccess)
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+      if (el != hipSuccess || e != hipSuccess) {   // capture of the cooperative launch failed
+        (void)hipGetLastError();
+        batch_drop_graph(b);
+        b->persist_graph = false;
+      } else {
+        b->graph_S = S;
+        b->graph_pairs = false;
+      }
+    }
+    if (b->exec) {
+      for (; done + S <= nsteps; done += S) {
+        e = hipGraphLaunch(b->exec, b->s);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+      }
+    }
+  }
+  while (done < nsteps) {
+    const int n = (int)std::min<int64_t>(nsteps - done, use_graph ? S : (int64_t)1 << 30);
+    e = launch_batch_persist<T>(a, nwg, n, b->s);
+    if (e != hipSuccess) return hip_fail(e, "persistent batch launch");
+    done += n;
+  }
+  for (int g = 0; g < b->nb; ++g) {
+    fit_grid* gr = b->grids[g];
+    if (nsteps & 1) swap_sets(gr);
+    gr->m += nsteps;
+    gr->smvp += 2 * nsteps;
+  }
+  return FIT_OK;
+}
+
 template <typename T>
 static int batch_run(fit_batch* b, int64_t nsteps, const double* dt, int use_graph) {
   int rc = batch_desc<T>(b, dt, nsteps, true);
   if (rc) return rc;
+  if (b->persist) return batch_run_persist<T>(b, nsteps, use_graph);
   // launches: pairs of steps when enabled (an odd last step runs singly)
   const bool pairs = b->pair_on && b->P2 > 0 && nsteps >= 2;
   const int64_t npair = pairs ? nsteps / 2 : 0;
@@ -321,7 +400,6 @@ static int batch_run(fit_batch* b, int64_t nsteps, const double* dt, int use_gra
     }
     gr->m += nsteps;
     gr->smvp += 2 * nsteps;
-    if (nsteps > 0) gr->last_dt = dt[g];
   }
   return FIT_OK;
 }
@@ -507,6 +585,44 @@ int fit_batch_set_pair(fit_batch* b, int enable, int kc) {
   return FIT_OK;
 }
 
+int fit_batch_set_persistent(fit_batch* b, int enable) {
+  if (!b) return fail(FIT_E_INVALID, "null batch");
+  if (enable != 0 && enable != 1) return fail(FIT_E_INVALID, "enable must be 0 or 1");
+  if (enable) {
+    int dev = 0, coop = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess ||
+        !coop) {
+      (void)hipGetLastError();
+      return fail(FIT_E_INVALID, "the device does not support cooperative launches");
+    }
+    const int nwg = persist_workgroups(b);
+    if (nwg <= 0)
+      return fail(FIT_E_INVALID, "the persistent kernel cannot hold a workgroup of this tile on a CU");
+    b->persist_nwg = nwg;
+    b->persist_graph = true;
+  }
+  b->persist = enable != 0;
+  batch_drop_graph(b);
+  return FIT_OK;
+}
+
+int fit_batch_get_persistent(const fit_batch* b, int* enable, int* workgroups, int* captured,
+                             int* barrier_failed) {
+  if (!b) return fail(FIT_E_INVALID, "null batch");
+  if (enable) *enable = b->persist ? 1 : 0;
+  if (workgroups) *workgroups = b->persist ? b->persist_nwg : 0;
+  if (captured) *captured = (b->persist && b->persist_graph) ? 1 : 0;
+  if (barrier_failed) {
+    BatchCtl c{};
+    hipError_t e = hipMemcpyAsync(&c, b->ctl, sizeof(BatchCtl), hipMemcpyDeviceToHost, b->s);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->s);
+    if (e != hipSuccess) return hip_fail(e, "batch control readback");
+    *barrier_failed = c.error;
+  }
+  return FIT_OK;
+}
+
 int fit_batch_get_pair(const fit_batch* b, int* enable, int* kc) {
   if (!b) return fail(FIT_E_INVALID, "null batch");
   if (enable) *enable = b->pair_on ? 1 : 0;
@@ -580,6 +696,8 @@ int fit_batch_step(fit_batch* b, int64_t nsteps, const double* dt_in, int use_gr
   if (int rc = batch_enter(b)) return rc;
   int rc = b->f64 ? batch_run<double>(b, nsteps, dt, use_graph) : batch_run<float>(b, nsteps, dt, use_graph);
   int rc2 = batch_leave(b);
+  if (!rc)
+    for (int g = 0; g < b->nb; ++g) b->grids[g]->last_dt = dt[g];
   return rc ? rc : rc2;
 }
 
@@ -626,7 +744,7 @@ int fit_batch_autotune(fit_batch* b, const double* dt_in, int reps, int* tw, int
   // the device)
   b->pair_on = false;
   const int pkc_prev = b->pkc;
-  if (!rc && !rc2) {
+  if (!rc && !rc2 && !b->persist) {   // the persistent form runs single steps
     float best_pair = 1e30f;
     int bpkc = -1;
     for (int pk : {16, 8, 6, 4}) {

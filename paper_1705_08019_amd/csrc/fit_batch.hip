@@ -8,7 +8,9 @@
 // kernel boundary alone: no workgroup ever waits on another, and no atomics
 // are used.  The index of the step within a call lives in device memory and
 // is advanced by a one-thread kernel after every step, so a captured chain of
-// S (step, advance) launches can be replayed as a hipGraph.
+// S (step, advance) launches can be replayed as a hipGraph.  The persistent
+// form (k_batch_persist) runs S steps in one cooperative launch instead, with
+// a grid-wide barrier between the steps.
 #include "fit_step2_tile.hpp"
 #include "fit_step_tile.hpp"
 
@@ -124,6 +126,131 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 3))) void k_batch2(Batch
   else
     step2_tile<T, false, false, kBatchPairTw, kBatchPairTy>(a, tx, rr % G.t2.nty, rr / G.t2.nty, sm);
 }
+
+// Persistent form: S steps of every grid in ONE launch.  Workgroup w runs
+// items w, w + G, w + 2G, ... of each step's item table (G = gridDim.x; the
+// loop bounds are the same for every thread of a workgroup, so every thread
+// reaches every barrier), then the whole launch meets at a grid-wide barrier
+// before the next step.  The launch is cooperative when launched directly
+// (the runtime starts it only if every workgroup can be resident at once)
+// and G never exceeds the resident capacity.
+//
+// The barrier lives in the control block (bar_count, bar_gen), cleared by
+// k_batch_bar_reset before every launch: barrier s of the launch waits for
+// bar_gen >= s + 1.  Each workgroup's first thread, after the workgroup has
+// finished the step (every wave has released its writes at agent scope: its
+// stores completed and the L2 written back, so the other XCDs see them),
+// adds the workgroup to bar_count (agent-scope atomic),
+// and either -- as the last to arrive -- clears the count and publishes the
+// new generation with a release store, or polls bar_gen with agent-scope
+// loads (which go to the device's coherence point, not the XCD's L2),
+// sleeping between polls.  Then every thread acquires at agent scope (the
+// XCD's L2 and L1 drop lines another XCD may have rewritten).  A poll gives
+// up after kBarSpins tries and sets ctl->error, so a launch whose workgroups
+// could not all be resident ends (with wrong fields and the error flag)
+// instead of hanging.
+constexpr uint64_t kBarSpins = 1ull << 23;   // x >= 128 cycles: about 0.5 s
+
+__global__ void k_batch_bar_reset(BatchCtl* ctl) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    ctl->bar_count = 0u;
+    ctl->bar_gen = 0u;
+  }
+}
+
+__device__ __forceinline__ void grid_barrier(BatchCtl* ctl, unsigned target, unsigned nwg) {
+  // every wave: its stores complete and the XCD's L2 written back
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    const unsigned arrived =
+        __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
+    if (arrived == nwg) {
+      __hip_atomic_store(&ctl->bar_count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_store(&ctl->bar_gen, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      uint64_t spins = 0;
+      while (__hip_atomic_load(&ctl->bar_gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++spins >= kBarSpins) {
+          __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+      }
+    }
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <typename T>
+__global__ __launch_bounds__(1024) void k_batch_persist(BatchArgs<T> B, int S) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const int w = (int)xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t base = B.ctl->step_base;
+  const int flip = B.ctl->flip;
+  for (int s = 0; s < S; ++s) {
+    for (int r = w; r < B.P; r += (int)gridDim.x) {
+      const int g = B.item_grid[r];
+      const BatchGrid<T>& G = B.grids[g];
+      const int t = r - G.tile_off;
+      const int p = (G.par0 + flip + s) & 1;
+      SArgs<T> a;
+      batch_args<T>(G, p, G.src_tab ? G.src_tab[base + s] : T(0), a);
+      const int tx = t % G.t.ntx;
+      const int rr = t / G.t.ntx;
+      if (G.lossy)
+        step_tile<T, true, false, false>(a, tx, rr % G.t.nty, rr / G.t.nty, sm, nullptr, nullptr);
+      else
+        step_tile<T, false, false, false>(a, tx, rr % G.t.nty, rr / G.t.nty, sm, nullptr, nullptr);
+      __syncthreads();   // the next item restages the LDS
+    }
+    grid_barrier(B.ctl, (unsigned)s + 1u, gridDim.x);
+  }
+  // every workgroup has read step_base and flip before the last barrier
+  if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+    B.ctl->step_base = base + S;
+    B.ctl->flip = flip + S;
+  }
+}
+
+template <typename T>
+static int persist_occupancy(int nthreads, size_t lds) {
+  int nb = 0;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_persist<T>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void*>(&k_batch_persist<T>), nthreads, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
+int batch_persist_blocks_per_cu(size_t esz, int nthreads, size_t lds) {
+  return esz == 8 ? persist_occupancy<double>(nthreads, lds)
+                  : persist_occupancy<float>(nthreads, lds);
+}
+
+template <typename T>
+hipError_t launch_batch_persist(const BatchArgs<T>& b, int nwg, int S, hipStream_t s) {
+  BatchArgs<T> a = b;
+  int steps = S;
+  void* args[2] = {&a, &steps};
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch_persist<T>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, b.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_bar_reset, dim3(1), dim3(64), 0, s, b.ctl);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch_persist<T>),
+                                    dim3((unsigned)nwg), dim3((unsigned)b.nthreads), args,
+                                    (unsigned)b.lds, s);
+}
+
+template hipError_t launch_batch_persist<float>(const BatchArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_batch_persist<double>(const BatchArgs<double>&, int, int, hipStream_t);
 
 template <typename T>
 static int batch_occupancy(int nthreads, size_t lds) {

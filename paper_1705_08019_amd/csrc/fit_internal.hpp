@@ -258,8 +258,10 @@ hipError_t launch_adjoint_step(const AdjArgs<T>& a, bool lossy, hipStream_t s);
 // Batched leapfrog, one launch per step of all grids (fit_batch.hip).
 struct BatchCtl {
   int64_t step_base;   // index of the next step within the current call
-  int error;
-  int flip;            // launches so far in the call (each swaps the buffer sets)
+  int error;           // set by the persistent kernel when a barrier gave up
+  int flip;            // buffer-set swaps so far in the call
+  unsigned bar_count;  // persistent kernel: workgroups arrived at the barrier
+  unsigned bar_gen;    // persistent kernel: barriers completed in this launch
 };
 
 template <typename T>
@@ -309,6 +311,13 @@ hipError_t launch_batch(const BatchArgs<T>& b, hipStream_t s);
 template <typename T>
 hipError_t launch_batch2(const BatchArgs<T>& b, hipStream_t s);
 hipError_t launch_batch_set_base(BatchCtl* ctl, int64_t base, hipStream_t s);
+// S steps of every grid in one cooperative launch of nwg resident workgroups
+// (single-step items of b.item_grid; grid-wide barrier between steps); the
+// step index and parity come from and go back to b.ctl.
+template <typename T>
+hipError_t launch_batch_persist(const BatchArgs<T>& b, int nwg, int S, hipStream_t s);
+// Resident workgroups per CU of the persistent kernel (0 if unknown).
+int batch_persist_blocks_per_cu(size_t esz, int nthreads, size_t lds);
 
 // Launch wrappers (fit_kernels.hip).  Return hipError_t of the launch.
 template <typename T>

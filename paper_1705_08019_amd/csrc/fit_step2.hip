@@ -37,7 +37,11 @@ bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, bool nu) {
 // tiles 128 (up to 1024 threads).  (A 16-wave 64 x 12 tile would need 64
 // VGPRs for two workgroups per CU and spills there.)
 template <typename T, int CTW, int CTY>
-constexpr int s2_waves() { return CTW == 0 ? 4 : sizeof(T) == 8 ? 3 : 6; }
+constexpr int s2_waves() {
+  // one 16-wave workgroup per CU (4 waves per SIMD) for tiles of more than
+  // 12 waves, else two workgroups per CU
+  return CTW == 0 ? 4 : ((CTW + 4) * (CTY + 3) + 63) / 64 > 12 ? 4 : sizeof(T) == 8 ? 3 : 6;
+}
 template <typename T, int CTW>
 constexpr int s2_max_threads() { return CTW > 0 && sizeof(T) == 8 ? 768 : 1024; }
 
@@ -69,6 +73,8 @@ template <typename T, bool L, bool N>
 static hipError_t go_step2(const S2Args<T>& a, dim3 grd, dim3 blk, size_t lds, hipStream_t s) {
   if (a.t.tw == 32 && a.t.ty == 16) return go_step2_t<T, L, N, 32, 16>(a, grd, blk, lds, s);
   if (a.t.tw == 64 && a.t.ty == 8) return go_step2_t<T, L, N, 64, 8>(a, grd, blk, lds, s);
+  if (sizeof(T) == 4 && a.t.tw == 64 && a.t.ty == 12)   // 1024 threads: FP32 only
+    return go_step2_t<T, L, N, 64, 12>(a, grd, blk, lds, s);
   return go_step2_t<T, L, N, 0, 0>(a, grd, blk, lds, s);
 }
 

@@ -51,7 +51,7 @@ def test_pair_is_bitwise_two_single_steps(dtype, n, lossy):
     ref = _run(n, dtype, lossy, steps)
     assert ref[4]["pair"][1] == 0
     shapes = [(64, 12, 0), (64, 8, 1), (32, 16, 2), (64, 8, 3), (32, 16, 5), (16, 8, 0),
-              (128, 8, 0), (48, 10, 4), (20, 6, 0)]
+              (128, 8, 0), (48, 10, 4), (20, 6, 0), (48, 12, 2), (32, 24, 3)]
     from paper_1705_08019_amd import FitError
     ran = 0
     for tw, ty, kc in shapes:
