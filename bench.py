@@ -275,7 +275,8 @@ def form_batched(plain_steps: int = 400):
     persist = None
     try:
         b.set_pair(False)
-        b.set_tuning(0, 0, 16)
+        ty_, kc_, _, _, tw_ = b.get_tuning()
+        b.set_tuning(ty_, kc_, 16, tw_)           # the autotuned tile, 16 steps per launch
         b.set_persistent(True)
         b.step(32, dts)
         torch.cuda.synchronize()
@@ -288,6 +289,7 @@ def form_batched(plain_steps: int = 400):
         gps = cells * nsteps / (ms_ps / 1e3) / 1e9
         persist = {"Gcell_updates_per_s": round(gps, 3), "workgroups": nwg,
                    "items_per_step": b.get_tuning()[3], "steps_per_launch": 16,
+                   "tile": [tw_, ty_, kc_],
                    "captured_in_graph": cap, "barrier_gave_up": failed,
                    "alg_GBs": round(B_LAUNCH * gps, 1),
                    "frac": round(B_LAUNCH * gps / PEAK_HBM_GBS, 4)}

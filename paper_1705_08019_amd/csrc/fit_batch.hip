@@ -138,14 +138,17 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 3))) void k_batch2(Batch
 // The barrier lives in the control block (bar_count, bar_gen), cleared by
 // k_batch_bar_reset before every launch: barrier s of the launch waits for
 // bar_gen >= s + 1.  Each workgroup's first thread, after the workgroup has
-// finished the step (every wave has released its writes at agent scope: its
-// stores completed and the L2 written back, so the other XCDs see them),
-// adds the workgroup to bar_count (agent-scope atomic),
+// finished the step (every wave has waited for its stores to complete) and
+// released the workgroup's writes at agent scope (the XCD's L2 written back,
+// so the other XCDs see them), adds the workgroup to bar_count
+// (agent-scope atomic),
 // and either -- as the last to arrive -- clears the count and publishes the
 // new generation with a release store, or polls bar_gen with agent-scope
 // loads (which go to the device's coherence point, not the XCD's L2),
-// sleeping between polls.  Then every thread acquires at agent scope (the
-// XCD's L2 and L1 drop lines another XCD may have rewritten).  A poll gives
+// sleeping between polls, and acquires at agent scope (the CU's L1 and the
+// XCD's L2 drop lines another XCD may have rewritten) before the workgroup
+// goes on.  One release and one acquire per workgroup and step: making every
+// wave fence cost 1.6x the step time on the 64-grid workload.  A poll gives
 // up after kBarSpins tries and sets ctl->error, so a launch whose workgroups
 // could not all be resident ends (with wrong fields and the error flag)
 // instead of hanging.
@@ -159,10 +162,13 @@ __global__ void k_batch_bar_reset(BatchCtl* ctl) {
 }
 
 __device__ __forceinline__ void grid_barrier(BatchCtl* ctl, unsigned target, unsigned nwg) {
-  // every wave: its stores complete and the XCD's L2 written back
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  // every wave: its stores complete (acknowledged by the L2); then one
+  // thread writes the XCD's L2 back at agent scope (the workgroup's stores
+  // are all in it by now)
+  asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
   __syncthreads();
   if (threadIdx.x == 0 && threadIdx.y == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned arrived =
         __hip_atomic_fetch_add(&ctl->bar_count, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) + 1u;
     if (arrived == nwg) {
@@ -178,9 +184,11 @@ __device__ __forceinline__ void grid_barrier(BatchCtl* ctl, unsigned target, uns
         }
       }
     }
+    // acquire: the CU's L1 and the XCD's L2 drop their lines; the other
+    // waves of the workgroup (same CU) read only after the barrier below
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 }
 
 template <typename T>
