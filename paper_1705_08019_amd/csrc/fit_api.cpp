@@ -1474,7 +1474,7 @@ int fit_autotune(fit_grid* g, double dt, int reps, int* path, int* tw, int* ty, 
   // two steps per launch: take it when a pair beats two single steps
   g->pair_on = 0;
   if (use_fused(g) && g->d.nz >= 2) {
-    const int shapes[4][2] = {{32, 16}, {64, 8}, {32, 8}, {48, 8}};
+    const int shapes[5][2] = {{32, 16}, {64, 8}, {32, 8}, {48, 8}, {64, 16}};
     float best_pair = 1e30f;
     int bw = 0, bt = 0, bk = 0;
     for (const auto& sh : shapes) {
@@ -1527,8 +1527,8 @@ int fit_set_pair_tuning(fit_grid* g, int enable, int tw, int ty, int kc) {
       }
   }
   if (!step2_shape_ok(tw, ty, g->esz, g->lossy))
-    return fail(FIT_E_INVALID, "unsupported tile for the step pair (tw >= 8, ty >= 2, tw ty <= "
-                               "1024, staged regions within 2 entries per thread, LDS <= 160 KiB)");
+    return fail(FIT_E_INVALID, "unsupported tile for the step pair (tw >= 8, ty >= 2, at most 1024 "
+                               "threads with one point each or 768 with two, LDS <= 160 KiB)");
   g->pair_on = enable;
   g->ptw = tw;
   g->pty = ty;

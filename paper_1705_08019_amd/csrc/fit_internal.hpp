@@ -179,12 +179,16 @@ struct S2Args {
 constexpr int kS2ZRing = 4;
 // nu: tensor grid (per-plane metric ring in LDS).
 size_t step2_lds_bytes(int tw, int ty, size_t esz, bool lossy, bool nu);
-// Threads of a pair workgroup: one per point of the (tw + 4) x (ty + 3)
-// thread grid (the e^(m+1) region with its row stride), rounded up to a
+// Points of the (tw + 4) x (ty + 3) thread grid (the e^(m+1) region with its
+// row stride) per thread of a pair workgroup: 1, or 2 where the grid has more
+// than 1024 points.
+int step2_points(int tw, int ty);
+// Threads of a pair workgroup: the thread grid's points over step2_points,
+// at least the staged (tw + 4) x (ty + 4) plane over kS2Per, rounded up to a
 // multiple of 64.
 int step2_threads(int tw, int ty);
 // Tile shapes the two-step kernel takes: tw >= 8, ty >= 2, at most 1024
-// threads, the staged plane within kS2Per entries per thread, LDS <= 160 KiB.
+// threads with one point per thread (768 with two, FP32 only), LDS <= 160 KiB.
 bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, bool nu = false);
 // In-plane byte offsets of the two-step kernel are 32-bit: a plane of the
 // slot layout must span at most 4 GiB.

@@ -18,64 +18,85 @@ bool step2_plane_ok(const Dims& d, size_t esz) {
   return (uint64_t)d.sxy * esz <= (uint64_t)UINT32_MAX;
 }
 
+int step2_points(int tw, int ty) { return s2_geom(tw, ty).N1 > 1024 ? 2 : 1; }
+
 int step2_threads(int tw, int ty) {
   const S2Geom g = s2_geom(tw, ty);
-  return (g.N1 + 63) / 64 * 64;
+  const int np = step2_points(tw, ty);
+  // every point of R1 owned (np per thread), the staged X4 plane within
+  // kS2Per entries per thread
+  const int n = std::max((g.N1 + np - 1) / np, (g.N4 + kS2Per - 1) / kS2Per);
+  return (n + 63) / 64 * 64;
 }
 
 bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, bool nu) {
   if (tw < 8 || ty < 2) return false;
-  const S2Geom g = s2_geom(tw, ty);
-  const int nthr = step2_threads(tw, ty);   // one thread per point of the largest computed region
-  if (nthr > 1024 || g.N4 > kS2Per * nthr) return false;
+  const int nthr = step2_threads(tw, ty);
+  // one point per thread up to 1024 threads; two points per thread up to 768,
+  // FP32 only (FP64 two-point tiles spill registers, and the useful ones
+  // exceed the LDS)
+  if (step2_points(tw, ty) > 1 && esz != 4) return false;
+  if (nthr > (step2_points(tw, ty) == 1 ? 1024 : 768)) return false;
   return step2_lds_bytes(tw, ty, esz, lossy, nu) <= 160 * 1024;
 }
 
-// Register budgets: the FP32 compile-time tiles at most 80 VGPRs (6 waves
-// per SIMD: two 11- or 12-wave workgroups per CU); the FP64 ones at most 168
-// (3 waves per SIMD: one workgroup of up to 768 threads, no spills); generic
-// tiles 128 (up to 1024 threads).  (A 16-wave 64 x 12 tile would need 64
-// VGPRs for two workgroups per CU and spills there.)
-template <typename T, int CTW, int CTY>
+// Register budgets: the FP32 compile-time one-point tiles at most 80 VGPRs
+// (6 waves per SIMD: two 11- or 12-wave workgroups per CU); the FP64 ones at
+// most 168 (3 waves per SIMD: one workgroup of up to 768 threads, no
+// spills); two-point tiles 168 (one workgroup of up to 12 waves per CU: their
+// LDS leaves room for no second); generic one-point tiles 128 (up to 1024
+// threads).  (A 16-wave 64 x 12 tile would need 64 VGPRs for two workgroups
+// per CU and spills there.)
+template <typename T, int CTW, int CTY, int NP>
 constexpr int s2_waves() {
+  if (NP > 1) return 3;
   // one 16-wave workgroup per CU (4 waves per SIMD) for tiles of more than
   // 12 waves, else two workgroups per CU
   return CTW == 0 ? 4 : ((CTW + 4) * (CTY + 3) + 63) / 64 > 12 ? 4 : sizeof(T) == 8 ? 3 : 6;
 }
-template <typename T, int CTW>
-constexpr int s2_max_threads() { return CTW > 0 && sizeof(T) == 8 ? 768 : 1024; }
+template <typename T, int CTW, int NP>
+constexpr int s2_max_threads() { return NP > 1 || (CTW > 0 && sizeof(T) == 8) ? 768 : 1024; }
 
-template <typename T, bool LOSSY, bool NU, int CTW, int CTY>
-__global__ __launch_bounds__((s2_max_threads<T, CTW>()))
-__attribute__((amdgpu_waves_per_eu((s2_waves<T, CTW, CTY>())))) void k_step2(S2Args<T> A) {
+template <typename T, bool LOSSY, bool NU, int CTW, int CTY, int NP>
+__global__ __launch_bounds__((s2_max_threads<T, CTW, NP>()))
+__attribute__((amdgpu_waves_per_eu((s2_waves<T, CTW, CTY, NP>())))) void k_step2(S2Args<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t lt = xcd_remap(blockIdx.x, gridDim.x);
   const int tx = (int)(lt % A.t.ntx);
   const int64_t rr = lt / A.t.ntx;
-  step2_tile<T, LOSSY, NU, CTW, CTY>(A, tx, (int)(rr % A.t.nty), (int)(rr / A.t.nty),
-                                      reinterpret_cast<T*>(smem_raw));
+  step2_tile<T, LOSSY, NU, CTW, CTY, NP>(A, tx, (int)(rr % A.t.nty), (int)(rr / A.t.nty),
+                                          reinterpret_cast<T*>(smem_raw));
 }
 
-template <typename T, bool L, bool N, int CW, int CY>
+template <typename T, bool L, bool N, int CW, int CY, int NP>
 static hipError_t go_step2_t(const S2Args<T>& a, dim3 grd, dim3 blk, size_t lds, hipStream_t s) {
   if (lds > 64 * 1024) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step2<T, L, N, CW, CY>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step2<T, L, N, CW, CY, NP>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_step2<T, L, N, CW, CY>), grd, blk, lds, s, a);
+  hipLaunchKernelGGL((k_step2<T, L, N, CW, CY, NP>), grd, blk, lds, s, a);
   return hipGetLastError();
 }
 
-// the 64 x 8 and 32 x 16 tiles (the fastest on 256 x 256 x 512 grids) have
-// compile-time variants; other tiles take the generic one
+// the 64 x 8 and 32 x 16 tiles (the fastest one-point tiles on 256 x 256 x
+// 512 grids) and, in FP32, the two-point 64 x 16 tile have compile-time
+// variants; other tiles take the generic ones
 template <typename T, bool L, bool N>
 static hipError_t go_step2(const S2Args<T>& a, dim3 grd, dim3 blk, size_t lds, hipStream_t s) {
-  if (a.t.tw == 32 && a.t.ty == 16) return go_step2_t<T, L, N, 32, 16>(a, grd, blk, lds, s);
-  if (a.t.tw == 64 && a.t.ty == 8) return go_step2_t<T, L, N, 64, 8>(a, grd, blk, lds, s);
-  if (sizeof(T) == 4 && a.t.tw == 64 && a.t.ty == 12)   // 1024 threads: FP32 only
-    return go_step2_t<T, L, N, 64, 12>(a, grd, blk, lds, s);
-  return go_step2_t<T, L, N, 0, 0>(a, grd, blk, lds, s);
+  const int tw = a.t.tw, ty = a.t.ty;
+  if (step2_points(tw, ty) > 1) {
+    if constexpr (sizeof(T) == 4) {
+      if (tw == 64 && ty == 16) return go_step2_t<T, L, N, 64, 16, 2>(a, grd, blk, lds, s);
+      return go_step2_t<T, L, N, 0, 0, 2>(a, grd, blk, lds, s);
+    }
+    return hipErrorInvalidValue;   // not reached: step2_shape_ok rejects FP64 two-point tiles
+  }
+  if (tw == 32 && ty == 16) return go_step2_t<T, L, N, 32, 16, 1>(a, grd, blk, lds, s);
+  if (tw == 64 && ty == 8) return go_step2_t<T, L, N, 64, 8, 1>(a, grd, blk, lds, s);
+  if constexpr (sizeof(T) == 4)   // 1024 threads: FP32 only
+    if (tw == 64 && ty == 12) return go_step2_t<T, L, N, 64, 12, 1>(a, grd, blk, lds, s);
+  return go_step2_t<T, L, N, 0, 0, 1>(a, grd, blk, lds, s);
 }
 
 template <typename T>

@@ -4,8 +4,9 @@
 // lives only in LDS.  Per cell and pair of steps this moves the 56 B of one
 // fused step instead of 112 B.
 //
-// A workgroup ((TW + 4)(TY + 3) threads rounded up to a multiple of 64, at
-// most 1024, numbered linearly) owns a TW x TY column tile and marches a
+// A workgroup (threads numbered linearly; one per point of the (TW + 4) x
+// (TY + 3) thread grid, or one per two points for larger tiles) owns a
+// TW x TY column tile and marches a
 // chunk [k0, k1) of z-planes with a lag of two planes between what it reads
 // and what it stores.  In local coordinates (x along i, y along j) the regions are
 //   X4: x in [-2, TW+1], y in [-2, TY+1]  staged h^(m+1/2), eps, sigma
@@ -13,12 +14,12 @@
 //   R2: x in [-1, TW],   y in [-1, TY]    h^(m+3/2)     (needs R1, X4)
 //   R3: x in [0, TW],    y in [0, TY]     e^(m+2)       (needs R2, R1, X4)
 //   tile                                  h^(m+5/2)     (needs R3, R2)
-// Thread t owns the point (x, y) = (t % W - 2, t / W - 1), W = TW + 4, in
-// every phase (each phase runs on the threads whose point lies in its
-// region), and every LDS array has the row stride W (a region keeps only its
-// own rows), so each LDS access is t plus a constant: the lanes of a wave
-// touch consecutive words, and no per-point LDS index is held in registers.
-// Because the point is the same in every phase, what a phase needs of the
+// Point q of the thread grid is (x, y) = (q % W - 2, q / W - 1), W = TW + 4;
+// a thread owns the same points in every phase (each phase runs on the
+// points that lie in its region), and every LDS array has the row stride W
+// (a region keeps only its own rows), so each LDS access is q plus a
+// constant: the lanes of a wave touch consecutive words.
+// Because the points are the same in every phase, what a phase needs of a
 // point itself comes from registers: the thread carries its own h^(m+1/2),
 // e^(m+1), the 4-cell material sums, h^(m+3/2) and e^(m+2) of the latest
 // planes, and reads only the +-x / +-y neighbours from LDS.  The materials
@@ -85,8 +86,11 @@ __device__ __forceinline__ void pst(T* base, uint32_t off, T v) {
 // Two fused steps of tile (tx, tyi) and z-chunk kz of the tiling A.t;
 // sm: the workgroup's dynamic LDS (step2_lds_bytes).  CTW, CTY > 0 fix the
 // tile at compile time (every LDS offset an immediate), 0 takes it from the
-// tiling.
-template <typename T, bool LOSSY, bool NU, int CTW, int CTY>
+// tiling.  NP: points per thread -- thread t owns the points q = t + p nthr,
+// p < NP, of the thread grid (tiles whose R1 region has more than 1024
+// points, e.g. 64 x 16, take NP = 2); each point keeps its own carried
+// values, and every phase runs over the thread's points in turn.
+template <typename T, bool LOSSY, bool NU, int CTW, int CTY, int NP = 1>
 __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, int kz, T* sm) {
   const Dims d = A.d;
   const int TW = CTW > 0 ? CTW : A.t.tw, TY = CTY > 0 ? CTY : A.t.ty;
@@ -103,13 +107,13 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
   const int k0 = kz * A.t.kc;
   const int k1 = min(k0 + A.t.kc, d.nz);
   const int tid = (int)(threadIdx.x + threadIdx.y * blockDim.x);
-  const int nthr = (int)(blockDim.x * blockDim.y);   // >= N1
+  const int nthr = (int)(blockDim.x * blockDim.y);   // NP nthr >= N1
   const int64_t sx = d.sx, sxy = d.sxy;
 
   auto hb = [](int k) { return k & 1; };   // e1 / e2 buffer of plane k
   auto in_grid = [&](int gx, int gy) { return gx >= 0 && gx < d.nx && gy >= 0 && gy < d.ny; };
 
-  // ---- the thread's point (x, y) = (t % W - 2, t / W - 1), the same in
+  // ---- the thread's points (x, y) = (q % W - 2, q / W - 1), the same in
   // every phase; grid points as in-plane element indices p (gx + sx gy)
   // source point: plane sk, in-plane index src_p (none: sk < -1)
   const int64_t sk = A.src_idx >= 0 ? A.src_idx / sxy : -100;   // k >= -1 in the march
@@ -126,37 +130,53 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
     in4[r] = q < G.N4 && in_grid(gx, gy);
     o4[r] = in4[r] ? (uint32_t)(gx + sx * gy) * ES : 0u;
   }
-  const int row = tid / W, x = tid % W - 2, y = row - 1;
-  const int gx = i0 + x, gy = j0 + y;
-  const bool ing = in_grid(gx, gy);
-  const uint32_t pg = ing ? (uint32_t)(gx + sx * gy) : 0u;
-  const bool at_s = ing && pg == src_p;
-  // R1 (e^(m+1)): x in [-1, TW+1], y in [-1, TY+1]
-  const bool a1 = row < TY + 3 && x >= -1;
-  const bool in1 = a1 && ing;
-  // R2 (h^(m+3/2)): x in [-1, TW], y in [-1, TY]
-  const bool a2 = row < TY + 2 && x >= -1 && x <= TW;
-  const bool in2 = a2 && ing;
-  // R3 (e^(m+2)): x in [0, TW], y in [0, TY]
-  const bool a3 = row >= 1 && row < TY + 2 && x >= 0 && x <= TW;
-  const bool in3 = a3 && ing;
-  // the tile (h^(m+5/2), stored)
-  const bool own = in3 && x < TW && y < TY;
-  // LDS indices of the point: X4 t + W (neighbours -1: x - 1, -W: y - 1),
-  // R1 and R2 t (+1: x + 1, +W: y + 1), R3 t - W
-  const int i4 = tid + W, i1 = tid, i3 = tid - W;
+  int gxp[NP], gyp[NP], i4[NP], i1[NP], i3[NP];
+  uint32_t pg[NP];
+  bool at_s[NP], a1[NP], in1[NP], a2[NP], in2[NP], a3[NP], in3[NP], own[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    const int q = tid + p * nthr;
+    const int row = q / W, x = q % W - 2, y = row - 1;
+    const int gx = i0 + x, gy = j0 + y;
+    gxp[p] = gx;
+    gyp[p] = gy;
+    const bool ing = in_grid(gx, gy);
+    pg[p] = ing ? (uint32_t)(gx + sx * gy) : 0u;
+    at_s[p] = ing && pg[p] == src_p;
+    // R1 (e^(m+1)): x in [-1, TW+1], y in [-1, TY+1]
+    a1[p] = row < TY + 3 && x >= -1;
+    in1[p] = a1[p] && ing;
+    // R2 (h^(m+3/2)): x in [-1, TW], y in [-1, TY]
+    a2[p] = row < TY + 2 && x >= -1 && x <= TW;
+    in2[p] = a2[p] && ing;
+    // R3 (e^(m+2)): x in [0, TW], y in [0, TY]
+    a3[p] = row >= 1 && row < TY + 2 && x >= 0 && x <= TW;
+    in3[p] = a3[p] && ing;
+    // the tile (h^(m+5/2), stored)
+    own[p] = in3[p] && x < TW && y < TY;
+    // LDS indices of the point: X4 q + W (neighbours -1: x - 1, -W: y - 1),
+    // R1 and R2 q (+1: x + 1, +W: y + 1), R3 q - W
+    i4[p] = q + W;
+    i1[p] = q;
+    i3[p] = q - W;
+  }
 
   // ---- tensor-grid metric (as in the single fused step): x / y factors of
-  // the point, z factors of planes k0 - 2 .. k1 + 1 in an LDS ring
-  T kbx = A.kb[0], kby = A.kb[1];
-  T kdxb = 0, kdyb = 0, kdzb = 0;
-  if (NU) {
-    const int ix = min(max(gx, 0), d.nx - 1), jy = min(max(gy, 0), d.ny - 1);
-    kbx = (T)(A.kbs * A.nsq[0][ix]);
-    kby = (T)(A.kbs * A.nsq[1][jy]);
-    kdxb = (T)(A.kds * (0.5 * A.ndl[0][ix] * A.nrw[1][jy]));
-    kdyb = (T)(A.kds * (0.5 * A.ndl[1][jy] * A.nrw[0][ix]));
-    kdzb = (T)(A.kds * (0.5 * A.nrw[0][ix] * A.nrw[1][jy]));
+  // the points, z factors of planes k0 - 2 .. k1 + 1 in an LDS ring
+  T kbx[NP], kby[NP], kdxb[NP], kdyb[NP], kdzb[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    kbx[p] = A.kb[0];
+    kby[p] = A.kb[1];
+    kdxb[p] = kdyb[p] = kdzb[p] = T(0);
+    if (NU) {
+      const int ix = min(max(gxp[p], 0), d.nx - 1), jy = min(max(gyp[p], 0), d.ny - 1);
+      kbx[p] = (T)(A.kbs * A.nsq[0][ix]);
+      kby[p] = (T)(A.kbs * A.nsq[1][jy]);
+      kdxb[p] = (T)(A.kds * (0.5 * A.ndl[0][ix] * A.nrw[1][jy]));
+      kdyb[p] = (T)(A.kds * (0.5 * A.ndl[1][jy] * A.nrw[0][ix]));
+      kdzb[p] = (T)(A.kds * (0.5 * A.nrw[0][ix] * A.nrw[1][jy]));
+    }
   }
   // the z factors of plane k sit in ring slot k mod kS2ZRing of zL (kb_z,
   // 1 / w_z, dual width): thread 0 fetches them with the plane and stages
@@ -168,9 +188,9 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
   double zraw[3] = {0.0, 0.0, 0.0};
 
   // ---- register staging of plane k: X4 entries (h x3, eps, sigma), the
-  // point's e^m
+  // points' e^m
   T ph[kS2Per][5];
-  T pe[3];
+  T pe[NP][3];
   auto fetch = [&](int k) {
     const bool plane = k >= 0 && k < d.nz;
     const int64_t gk = plane ? sxy * (int64_t)k : 0;
@@ -191,11 +211,14 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
       zraw[1] = plane ? A.nrw[2][k] : 0.0;
       zraw[2] = plane ? A.ndl[2][k] : 0.0;
     }
-    const bool in = plane && in1;
-    const uint32_t o = fresh(pg * ES);
-    pe[0] = in ? pld(A.e0[0] + gk, o) : T(0);
-    pe[1] = in ? pld(A.e0[1] + gk, o) : T(0);
-    pe[2] = in ? pld(A.e0[2] + gk, o) : T(0);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const bool in = plane && in1[p];
+      const uint32_t o = fresh(pg[p] * ES);
+      pe[p][0] = in ? pld(A.e0[0] + gk, o) : T(0);
+      pe[p][1] = in ? pld(A.e0[1] + gk, o) : T(0);
+      pe[p][2] = in ? pld(A.e0[2] + gk, o) : T(0);
+    }
   };
   auto stage = [&](int k) {
 #pragma unroll
@@ -216,32 +239,43 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
     }
   };
 
-  // ---- values of the point carried from plane to plane (zero below the
+  // ---- values of each point carried from plane to plane (zero below the
   // chunk's first planes until they are formed):
   // h^(m+1/2) of the previous plane; the 2-cell sums of eps (sigma) along
   // x and y of the previous plane (the lower half of the next plane's x / y
   // edge sums); e^(m+1), its 4-cell sums E4 (S4), h^(m+3/2) and e^(m+2) of
   // the latest planes formed
-  T hq[3] = {T(0), T(0), T(0)};
-  T Sxq = 0, Syq = 0, Sxsq = 0, Sysq = 0;
-  T e1p[3] = {T(0), T(0), T(0)}, E4p[3] = {T(1), T(1), T(1)}, S4p[3] = {T(0), T(0), T(0)};
-  T h1p[3] = {T(0), T(0), T(0)}, e2p[3] = {T(0), T(0), T(0)};
+  T hq[NP][3], Sxq[NP], Syq[NP], Sxsq[NP], Sysq[NP];
+  T e1p[NP][3], E4p[NP][3], S4p[NP][3], h1p[NP][3], e2p[NP][3];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    Sxq[p] = Syq[p] = Sxsq[p] = Sysq[p] = T(0);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      hq[p][c] = e1p[p][c] = S4p[p][c] = h1p[p][c] = e2p[p][c] = T(0);
+      E4p[p][c] = T(1);
+    }
+  }
 
   // prologue: plane k0 - 2 staged for its carried values, plane k0 - 1 in flight
   fetch(k0 - 2);
   stage(k0 - 2);
   __syncthreads();
-  if (a1) {
-    hq[0] = h0L[i4];
-    hq[1] = h0L[G.N4 + i4];
-    hq[2] = h0L[2 * G.N4 + i4];
-    const T c = cL[i4];
-    Sxq = c + cL[i4 - 1];
-    Syq = c + cL[i4 - W];
-    if (LOSSY) {
-      const T s = sL[i4];
-      Sxsq = s + sL[i4 - 1];
-      Sysq = s + sL[i4 - W];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) {
+    if (a1[p]) {
+      const int j4 = i4[p];
+      hq[p][0] = h0L[j4];
+      hq[p][1] = h0L[G.N4 + j4];
+      hq[p][2] = h0L[2 * G.N4 + j4];
+      const T c = cL[j4];
+      Sxq[p] = c + cL[j4 - 1];
+      Syq[p] = c + cL[j4 - W];
+      if (LOSSY) {
+        const T s = sL[j4];
+        Sxsq[p] = s + sL[j4 - 1];
+        Sysq[p] = s + sL[j4 - W];
+      }
     }
   }
   fetch(k0 - 1);
@@ -249,75 +283,96 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
 
   for (int k = k0 - 1; k <= k1 + 1; ++k) {
     stage(k);
-    const T e0x = pe[0], e0y = pe[1], e0z = pe[2];
+    T e0[NP][3];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      e0[p][0] = pe[p][0];
+      e0[p][1] = pe[p][1];
+      e0[p][2] = pe[p][2];
+    }
     if (k + 1 <= k1 + 1) fetch(k + 1);
     __syncthreads();
 
     // ---- e^(m+1) of plane k on R1 (same operand order as the single step)
-    T e1c[3] = {T(0), T(0), T(0)}, E4c[3] = {T(1), T(1), T(1)}, S4c[3] = {T(0), T(0), T(0)};
-    T hc[3] = {T(0), T(0), T(0)};
-    T Sxc = 0, Syc = 0, Sxsc = 0, Sysc = 0;
-    if (a1) {
-      const bool valid = in1 && k >= 0 && k < d.nz;
-      hc[0] = h0L[i4];
-      hc[1] = h0L[G.N4 + i4];
-      hc[2] = h0L[2 * G.N4 + i4];
-      const T c = cL[i4], c_im = cL[i4 - 1], c_jm = cL[i4 - W], c_ijm = cL[i4 - W - 1];
-      Sxc = c + c_im;
-      Syc = c + c_jm;
-      const T Sxj = c_jm + c_ijm;
-      E4c[0] = Syq + Syc;
-      E4c[1] = Sxq + Sxc;
-      E4c[2] = Sxc + Sxj;
-      if (LOSSY) {
-        const T s = sL[i4], s_im = sL[i4 - 1], s_jm = sL[i4 - W], s_ijm = sL[i4 - W - 1];
-        Sxsc = s + s_im;
-        Sysc = s + s_jm;
-        S4c[0] = Sysq + Sysc;
-        S4c[1] = Sxsq + Sxsc;
-        S4c[2] = Sxsc + (s_jm + s_ijm);
+    T e1c[NP][3], E4c[NP][3], S4c[NP][3], hc[NP][3];
+    T Sxc[NP], Syc[NP], Sxsc[NP], Sysc[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      Sxc[p] = Syc[p] = Sxsc[p] = Sysc[p] = T(0);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        e1c[p][c] = S4c[p][c] = hc[p][c] = T(0);
+        E4c[p][c] = T(1);
       }
-      if (!valid) E4c[0] = E4c[1] = E4c[2] = T(1);
-      T jx = 0, jy = 0, jz = 0;
-      if (valid && at_s && k == sk) {
-        if (A.src_comp == 0) jx = A.src_val[0];
-        if (A.src_comp == 1) jy = A.src_val[0];
-        if (A.src_comp == 2) jz = A.src_val[0];
+      if (a1[p]) {
+        const int j4 = i4[p];
+        const bool valid = in1[p] && k >= 0 && k < d.nz;
+        hc[p][0] = h0L[j4];
+        hc[p][1] = h0L[G.N4 + j4];
+        hc[p][2] = h0L[2 * G.N4 + j4];
+        const T c = cL[j4], c_im = cL[j4 - 1], c_jm = cL[j4 - W], c_ijm = cL[j4 - W - 1];
+        Sxc[p] = c + c_im;
+        Syc[p] = c + c_jm;
+        const T Sxj = c_jm + c_ijm;
+        E4c[p][0] = Syq[p] + Syc[p];
+        E4c[p][1] = Sxq[p] + Sxc[p];
+        E4c[p][2] = Sxc[p] + Sxj;
+        if (LOSSY) {
+          const T s = sL[j4], s_im = sL[j4 - 1], s_jm = sL[j4 - W], s_ijm = sL[j4 - W - 1];
+          Sxsc[p] = s + s_im;
+          Sysc[p] = s + s_jm;
+          S4c[p][0] = Sysq[p] + Sysc[p];
+          S4c[p][1] = Sxsq[p] + Sxsc[p];
+          S4c[p][2] = Sxsc[p] + (s_jm + s_ijm);
+        }
+        if (!valid) E4c[p][0] = E4c[p][1] = E4c[p][2] = T(1);
+        T jx = 0, jy = 0, jz = 0;
+        if (valid && at_s[p] && k == sk) {
+          if (A.src_comp == 0) jx = A.src_val[0];
+          if (A.src_comp == 1) jy = A.src_val[0];
+          if (A.src_comp == 2) jz = A.src_val[0];
+        }
+        e_point<T, LOSSY>(hc[p][0], hc[p][1], hc[p][2], hq[p][0], hq[p][1], h0L[j4 - W],
+                          h0L[G.N4 + j4 - 1], h0L[2 * G.N4 + j4 - W], h0L[2 * G.N4 + j4 - 1],
+                          E4c[p][0], E4c[p][1], E4c[p][2], S4c[p][0], S4c[p][1], S4c[p][2],
+                          e0[p][0], e0[p][1], e0[p][2], jx, jy, jz,
+                          valid && gyp[p] > 0 && k > 0, valid && gxp[p] > 0 && k > 0,
+                          valid && gxp[p] > 0 && gyp[p] > 0, kbx[p], kby[p],
+                          NU ? zL[zs(k)] : A.kb[2], A.hs, e1c[p][0], e1c[p][1], e1c[p][2]);
+        T* out = e1L + hb(k) * 3 * G.N1;
+        out[i1[p]] = e1c[p][0];
+        out[G.N1 + i1[p]] = e1c[p][1];
+        out[2 * G.N1 + i1[p]] = e1c[p][2];
       }
-      e_point<T, LOSSY>(hc[0], hc[1], hc[2], hq[0], hq[1], h0L[i4 - W], h0L[G.N4 + i4 - 1],
-                        h0L[2 * G.N4 + i4 - W], h0L[2 * G.N4 + i4 - 1], E4c[0], E4c[1],
-                        E4c[2], S4c[0], S4c[1], S4c[2], e0x, e0y, e0z, jx, jy, jz,
-                        valid && gy > 0 && k > 0, valid && gx > 0 && k > 0,
-                        valid && gx > 0 && gy > 0, kbx, kby, NU ? zL[zs(k)] : A.kb[2],
-                        A.hs, e1c[0], e1c[1], e1c[2]);
-      T* out = e1L + hb(k) * 3 * G.N1;
-      out[i1] = e1c[0];
-      out[G.N1 + i1] = e1c[1];
-      out[2 * G.N1 + i1] = e1c[2];
     }
     __syncthreads();
 
     // ---- h^(m+3/2) of plane km = k - 1 on R2: e^(m+1) of planes km (the
     // point from registers, its +x / +y neighbours from LDS) and k
     const int km = k - 1;
-    T h1c[3] = {T(0), T(0), T(0)};
-    if (km >= k0 - 1 && a2) {
-      const T* nq = e1L + hb(km) * 3 * G.N1;
-      const bool valid = in2 && km >= 0 && km < d.nz;
-      T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
-      if (NU) {
-        const T rz = zL[ZR + zs(km)];
-        kdx = kdxb * rz;
-        kdy = kdyb * rz;
-        kdz = kdzb * zL[2 * ZR + zs(km)];
+    T h1c[NP][3];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      h1c[p][0] = h1c[p][1] = h1c[p][2] = T(0);
+      if (km >= k0 - 1 && a2[p]) {
+        const T* nq = e1L + hb(km) * 3 * G.N1;
+        const int j1 = i1[p];
+        const bool valid = in2[p] && km >= 0 && km < d.nz;
+        T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
+        if (NU) {
+          const T rz = zL[ZR + zs(km)];
+          kdx = kdxb[p] * rz;
+          kdy = kdyb[p] * rz;
+          kdz = kdzb[p] * zL[2 * ZR + zs(km)];
+        }
+        h_point<T>(e1p[p][0], e1p[p][1], e1p[p][2], e1c[p][0], e1c[p][1], nq[2 * G.N1 + j1 + W],
+                   nq[2 * G.N1 + j1 + 1], nq[G.N1 + j1 + 1], nq[j1 + W], hq[p][0], hq[p][1],
+                   hq[p][2], A.imu2, A.imu2, A.imu2, valid && gxp[p] > 0, valid && gyp[p] > 0,
+                   valid && km > 0, kdx, kdy, kdz, h1c[p][0], h1c[p][1], h1c[p][2]);
+        h1L[j1] = h1c[p][0];
+        h1L[G.N2 + j1] = h1c[p][1];
+        h1L[2 * G.N2 + j1] = h1c[p][2];
       }
-      h_point<T>(e1p[0], e1p[1], e1p[2], e1c[0], e1c[1], nq[2 * G.N1 + i1 + W],
-                 nq[2 * G.N1 + i1 + 1], nq[G.N1 + i1 + 1], nq[i1 + W], hq[0], hq[1], hq[2],
-                 A.imu2, A.imu2, A.imu2, valid && gx > 0, valid && gy > 0, valid && km > 0,
-                 kdx, kdy, kdz, h1c[0], h1c[1], h1c[2]);
-      h1L[i1] = h1c[0];
-      h1L[G.N2 + i1] = h1c[1];
-      h1L[2 * G.N2 + i1] = h1c[2];
     }
     __syncthreads();
 
@@ -325,31 +380,37 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
     // registers, its -x / -y neighbours from LDS) and km - 1, e^(m+1) and
     // the 4-cell sums of plane km from registers; the tile part of planes
     // [k0, k1) is stored
-    T e2c[3] = {T(0), T(0), T(0)};
-    if (km >= k0 && a3) {
-      const bool valid = in3 && km >= 0 && km < d.nz;
-      T jx = 0, jy = 0, jz = 0;
-      if (valid && at_s && km == sk) {
-        if (A.src_comp == 0) jx = A.src_val[1];
-        if (A.src_comp == 1) jy = A.src_val[1];
-        if (A.src_comp == 2) jz = A.src_val[1];
-      }
-      e_point<T, LOSSY>(h1c[0], h1c[1], h1c[2], h1p[0], h1p[1], h1L[i1 - W],
-                        h1L[G.N2 + i1 - 1], h1L[2 * G.N2 + i1 - W], h1L[2 * G.N2 + i1 - 1],
-                        E4p[0], E4p[1], E4p[2], S4p[0], S4p[1], S4p[2], e1p[0], e1p[1], e1p[2],
-                        jx, jy, jz, valid && gy > 0 && km > 0, valid && gx > 0 && km > 0,
-                        valid && gx > 0 && gy > 0, kbx, kby, NU ? zL[zs(km)] : A.kb[2], A.hs,
-                        e2c[0], e2c[1], e2c[2]);
-      T* out = e2L + hb(km) * 3 * G.N3;
-      out[i3] = e2c[0];
-      out[G.N3 + i3] = e2c[1];
-      out[2 * G.N3 + i3] = e2c[2];
-      if (own && km < k1) {
-        const int64_t gk = sxy * (int64_t)km;
-        const uint32_t o = fresh(pg * ES);
-        pst(A.e2[0] + gk, o, e2c[0]);
-        pst(A.e2[1] + gk, o, e2c[1]);
-        pst(A.e2[2] + gk, o, e2c[2]);
+    T e2c[NP][3];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      e2c[p][0] = e2c[p][1] = e2c[p][2] = T(0);
+      if (km >= k0 && a3[p]) {
+        const int j1 = i1[p];
+        const bool valid = in3[p] && km >= 0 && km < d.nz;
+        T jx = 0, jy = 0, jz = 0;
+        if (valid && at_s[p] && km == sk) {
+          if (A.src_comp == 0) jx = A.src_val[1];
+          if (A.src_comp == 1) jy = A.src_val[1];
+          if (A.src_comp == 2) jz = A.src_val[1];
+        }
+        e_point<T, LOSSY>(h1c[p][0], h1c[p][1], h1c[p][2], h1p[p][0], h1p[p][1], h1L[j1 - W],
+                          h1L[G.N2 + j1 - 1], h1L[2 * G.N2 + j1 - W], h1L[2 * G.N2 + j1 - 1],
+                          E4p[p][0], E4p[p][1], E4p[p][2], S4p[p][0], S4p[p][1], S4p[p][2],
+                          e1p[p][0], e1p[p][1], e1p[p][2], jx, jy, jz,
+                          valid && gyp[p] > 0 && km > 0, valid && gxp[p] > 0 && km > 0,
+                          valid && gxp[p] > 0 && gyp[p] > 0, kbx[p], kby[p],
+                          NU ? zL[zs(km)] : A.kb[2], A.hs, e2c[p][0], e2c[p][1], e2c[p][2]);
+        T* out = e2L + hb(km) * 3 * G.N3;
+        out[i3[p]] = e2c[p][0];
+        out[G.N3 + i3[p]] = e2c[p][1];
+        out[2 * G.N3 + i3[p]] = e2c[p][2];
+        if (own[p] && km < k1) {
+          const int64_t gk = sxy * (int64_t)km;
+          const uint32_t o = fresh(pg[p] * ES);
+          pst(A.e2[0] + gk, o, e2c[p][0]);
+          pst(A.e2[1] + gk, o, e2c[p][1]);
+          pst(A.e2[2] + gk, o, e2c[p][2]);
+        }
       }
     }
 
@@ -357,40 +418,48 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
     // (the point from registers, its +x / +y neighbours from LDS, written one
     // iteration earlier) and kh + 1 (registers), h^(m+3/2) of plane kh
     const int kh = k - 2;
-    if (kh >= k0 && kh < k1 && own) {
-      const T* nq = e2L + hb(kh) * 3 * G.N3;
-      T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
-      if (NU) {
-        const T rz = zL[ZR + zs(kh)];
-        kdx = kdxb * rz;
-        kdy = kdyb * rz;
-        kdz = kdzb * zL[2 * ZR + zs(kh)];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      if (kh >= k0 && kh < k1 && own[p]) {
+        const T* nq = e2L + hb(kh) * 3 * G.N3;
+        const int j3 = i3[p];
+        T kdx = A.kd[0], kdy = A.kd[1], kdz = A.kd[2];
+        if (NU) {
+          const T rz = zL[ZR + zs(kh)];
+          kdx = kdxb[p] * rz;
+          kdy = kdyb[p] * rz;
+          kdz = kdzb[p] * zL[2 * ZR + zs(kh)];
+        }
+        T hxn, hyn, hzn;
+        h_point<T>(e2p[p][0], e2p[p][1], e2p[p][2], e2c[p][0], e2c[p][1], nq[2 * G.N3 + j3 + W],
+                   nq[2 * G.N3 + j3 + 1], nq[G.N3 + j3 + 1], nq[j3 + W], h1p[p][0], h1p[p][1],
+                   h1p[p][2], A.imu2, A.imu2, A.imu2, gxp[p] > 0, gyp[p] > 0, kh > 0, kdx, kdy,
+                   kdz, hxn, hyn, hzn);
+        const int64_t gk = sxy * (int64_t)kh;
+        const uint32_t o = fresh(pg[p] * ES);
+        pst(A.h2[0] + gk, o, hxn);
+        pst(A.h2[1] + gk, o, hyn);
+        pst(A.h2[2] + gk, o, hzn);
       }
-      T hxn, hyn, hzn;
-      h_point<T>(e2p[0], e2p[1], e2p[2], e2c[0], e2c[1], nq[2 * G.N3 + i3 + W],
-                 nq[2 * G.N3 + i3 + 1], nq[G.N3 + i3 + 1], nq[i3 + W], h1p[0], h1p[1], h1p[2],
-                 A.imu2, A.imu2, A.imu2, gx > 0, gy > 0, kh > 0, kdx, kdy, kdz, hxn, hyn, hzn);
-      const int64_t gk = sxy * (int64_t)kh;
-      const uint32_t o = fresh(pg * ES);
-      pst(A.h2[0] + gk, o, hxn);
-      pst(A.h2[1] + gk, o, hyn);
-      pst(A.h2[2] + gk, o, hzn);
     }
 
-    // ---- carry the point's values to the next plane
+    // ---- carry the points' values to the next plane
 #pragma unroll
-    for (int c = 0; c < 3; ++c) {
-      hq[c] = hc[c];
-      e1p[c] = e1c[c];
-      E4p[c] = E4c[c];
-      S4p[c] = S4c[c];
-      h1p[c] = h1c[c];
-      e2p[c] = e2c[c];
+    for (int p = 0; p < NP; ++p) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        hq[p][c] = hc[p][c];
+        e1p[p][c] = e1c[p][c];
+        E4p[p][c] = E4c[p][c];
+        S4p[p][c] = S4c[p][c];
+        h1p[p][c] = h1c[p][c];
+        e2p[p][c] = e2c[p][c];
+      }
+      Sxq[p] = Sxc[p];
+      Syq[p] = Syc[p];
+      Sxsq[p] = Sxsc[p];
+      Sysq[p] = Sysc[p];
     }
-    Sxq = Sxc;
-    Syq = Syc;
-    Sxsq = Sxsc;
-    Sysq = Sysc;
   }
 }
 

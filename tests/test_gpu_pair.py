@@ -51,7 +51,8 @@ def test_pair_is_bitwise_two_single_steps(dtype, n, lossy):
     ref = _run(n, dtype, lossy, steps)
     assert ref[4]["pair"][1] == 0
     shapes = [(64, 12, 0), (64, 8, 1), (32, 16, 2), (64, 8, 3), (32, 16, 5), (16, 8, 0),
-              (128, 8, 0), (48, 10, 4), (20, 6, 0), (48, 12, 2), (32, 24, 3)]
+              (128, 8, 0), (48, 10, 4), (20, 6, 0), (48, 12, 2), (32, 24, 3),
+              (64, 16, 0), (64, 16, 3), (40, 24, 2)]   # the last three: two points per thread (FP32)
     from paper_1705_08019_amd import FitError
     ran = 0
     for tw, ty, kc in shapes:
@@ -204,7 +205,8 @@ def test_graded_pair_is_bitwise_two_single_steps(dtype, n, lossy):
     ref = [x.clone() for x in g.get_fields()]
     g.close()
     ran = 0
-    for tw, ty, kc in [(32, 16, 0), (64, 8, 1), (32, 8, 2), (16, 8, 5), (48, 10, 3)]:
+    for tw, ty, kc in [(32, 16, 0), (64, 8, 1), (32, 8, 2), (16, 8, 5), (48, 10, 3), (64, 16, 2),
+                       (40, 24, 0)]:
         g, _, _ = _graded(n, dtype, lossy)
         try:
             g.set_pair(True, tw, ty, kc)
