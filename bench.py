@@ -622,10 +622,13 @@ def gram_mfma_tiles(K: int) -> int:
 
 def form_gram(Ks=(64, 16), reps: int = 5):
     """Gram matrix of K FP32 snapshots of the 128^3 e-field (6.29 M rows) on
-    the FP64 matrix cores.  Device time from HIP events around the launches.
-    `TFLOPs` is the dense-product rate 2 rows K^2 / t (the cost G has as a
-    plain product); `mfma_TFLOPs` counts the MFMA work actually issued (the
-    symmetric half is skipped) and `frac` is that against the FP64 MFMA peak."""
+    the FP64 matrix cores.  Device time from HIP events around the launches
+    (the Gram kernel and its cross-workgroup sum).  `TFLOPs` is the
+    dense-product rate 2 rows K^2 / t (the cost G has as a plain product);
+    `unique_TFLOPs` counts the K(K+1)/2 distinct entries; `mfma_TFLOPs` counts
+    the MFMA work actually issued (whole 16 x 16 tiles of the upper tile
+    triangle) and `frac` is that against the FP64 MFMA peak; `read_frac` is
+    the snapshots and row weights read once, against the 8 TB/s HBM peak."""
     import torch
     from fit_workloads import c2
     from paper_1705_08019_amd import FitGrid
@@ -646,14 +649,19 @@ def form_gram(Ks=(64, 16), reps: int = 5):
         ms_dev, n = g.profile_end()["other"]
         ms = ms_dev / reps
         dense = 2.0 * rows * K * K
+        unique = 1.0 * rows * K * (K + 1)      # the K(K+1)/2 distinct entries, 2 flop per row each
         mfma = 2.0 * 16 * 16 * rows * gram_mfma_tiles(K)
+        nbytes = K * rows * 4 + rows * 8       # the snapshots and the FP64 row weights, read once
         out.append({"workload": f"K={K} FP32 snapshots of the 128^3 e-field ({rows} rows)", "K": K,
                     "ms": round(ms, 4), "ms_wall_incl_readback": round(sec_wall * 1e3, 3),
                     "TFLOPs": round(dense / ms / 1e9, 2),
+                    "unique_TFLOPs": round(unique / ms / 1e9, 2),
+                    "unique_frac": round(unique / ms / 1e9 / PEAK_FP64_MFMA, 4),
                     "mfma_TFLOPs": round(mfma / ms / 1e9, 2),
                     "peak_fp64_mfma_TFLOPs": PEAK_FP64_MFMA,
                     "frac": round(mfma / ms / 1e9 / PEAK_FP64_MFMA, 4),
-                    "read_GBs": round(K * rows * 4 / ms / 1e6, 1)})
+                    "read_GBs": round(nbytes / ms / 1e6, 1),
+                    "read_frac": round(nbytes / ms / 1e6 / 8000.0, 4)})
         del X
     g.close()
     res = out[0]

@@ -22,6 +22,13 @@ HIP_FLAGS = [
     "-Wall", "-Wno-unused-function",
 ]
 
+# Per-source additions: the Gram kernel keeps its MFMA accumulators in the
+# VGPR form (the default heuristic moved them between AGPRs and VGPRs on every
+# row step of the streaming loop)
+FILE_FLAGS = {
+    "fit_gram.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"],
+}
+
 
 def sources():
     return sorted(os.path.join(CSRC, f) for f in os.listdir(CSRC)
@@ -37,7 +44,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     for src in sources():
         obj = os.path.join(objdir, os.path.basename(src) + ".o")
         objs.append(obj)
-        cmd = [hipcc, *HIP_FLAGS, "-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj]
+        cmd = [hipcc, *HIP_FLAGS, *FILE_FLAGS.get(os.path.basename(src), []), "-I", INCLUDE,
+               "-I", CSRC, "-c", src, "-o", obj]
         if src.endswith(".cpp"):
             cmd[1:1] = ["-x", "hip"]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT,

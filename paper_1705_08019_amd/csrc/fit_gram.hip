@@ -20,6 +20,8 @@
 // current one is multiplied.  Each workgroup writes its FP64 block; a second
 // kernel sums the blocks per entry with Neumaier compensation.  Larger K is
 // covered block pair by block pair.
+#include <type_traits>
+
 #include "fit_internal.hpp"
 
 namespace fit {
@@ -27,7 +29,7 @@ namespace fit {
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
 constexpr int kGramBlk = 64;         // snapshots per output block side
-constexpr int kGramChunkAlign = 256; // workgroup row chunks: a multiple of every slab height
+constexpr int kGramChunkAlign = 256; // workgroup row chunks: a multiple of every workgroup step
 
 __device__ __forceinline__ bool g_edge_live(int a, int i, int j, int k) {
   return a == 0 ? (j > 0 && k > 0) : a == 1 ? (i > 0 && k > 0) : (i > 0 && j > 0);
@@ -116,7 +118,7 @@ struct GramArgs {
   const double* W;     // row weights
   int64_t rows;        // 3 n
   int64_t chunk;       // rows per workgroup (multiple of kGramChunkAlign)
-  double* part;        // [nwg][64][64]
+  double* part;        // [nwg][16 NTA][16 NTB] packed blocks
 };
 
 // Tile q of a block with NTA x NTB tiles, row-major; upper triangle only if DIAG.
@@ -143,204 +145,268 @@ struct TileSet {
   }
 };
 
-// MFMAs of one wave over the staged slab: the row quads kk = phase, phase + P,
-// ... and the tiles q = GRP, GRP + G, ... of the block.
-template <int NTA, int NTB, bool DIAG, int P, int GRP, int R, int C>
-__device__ __forceinline__ void gram_slab(const double (*LA)[C + 1], const double (*LB)[C + 1],
-                                          const double* LW, int phase, int lane, d4_t* acc) {
-  using TS = TileSet<NTA, NTB, DIAG>;
-  constexpr int G = 4 / P;
-  const int col = lane & 15;
+// f(integral_constant<int, I>) for I = B .. E-1: the tile loops must see
+// their tile indices as constants (a runtime loop over the tile list leaves
+// index searches and operand selects in the MFMA stream).
+template <int B, int E, typename F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// Row layout of a wave step (base r0, lane group g = lane / 16): the lane's
+// row offset c < RL is row r0 + 16 (c / 4) + 4 g + c % 4, so the four lane
+// groups read 4 consecutive rows each and one 16-byte load of every lane
+// covers 16 consecutive rows of each snapshot; a wave step spans 4 RL rows.
+__device__ __forceinline__ int gram_row(int g, int c) { return 16 * (c / 4) + 4 * g + c % 4; }
+
+// The lane's RL rows of one snapshot (p = the snapshot at the step base plus
+// 4 g): 16-byte loads when VEC (p 16-byte aligned), else element by element.
+template <typename T, int RL, bool VEC>
+__device__ __forceinline__ void gram_rows(const T* p, T (&v)[RL]) {
+  typedef float f4 __attribute__((ext_vector_type(4)));
+  typedef double d2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-  for (int kk0 = 0; kk0 < R / 4; kk0 += P) {
-    const int rr = 4 * (kk0 + phase) + (lane >> 4);
-    const double w = LW[rr];
-    double av[NTA], bv[NTB];
+  for (int u = 0; u < RL / 4; ++u) {
+    const T* q = p + 16 * u;
+    if constexpr (VEC && sizeof(T) == 4) {
+      const f4 x = *reinterpret_cast<const f4*>(q);
+      v[4 * u] = x.x;
+      v[4 * u + 1] = x.y;
+      v[4 * u + 2] = x.z;
+      v[4 * u + 3] = x.w;
+    } else if constexpr (VEC) {
+      const d2 x0 = *reinterpret_cast<const d2*>(q);
+      const d2 x1 = *reinterpret_cast<const d2*>(q + 2);
+      v[4 * u] = x0.x;
+      v[4 * u + 1] = x0.y;
+      v[4 * u + 2] = x1.x;
+      v[4 * u + 3] = x1.y;
+    } else {
 #pragma unroll
-    for (int ta = 0; ta < NTA; ++ta) av[ta] = w * LA[rr][16 * ta + col];
-#pragma unroll
-    for (int tb = 0; tb < NTB; ++tb) bv[tb] = LB[rr][16 * tb + col];
-#pragma unroll
-    for (int u = 0; GRP + G * u < TS::count; ++u) {
-      const int q = GRP + G * u;
-      acc[u] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[TS::ta(q)], bv[TS::tb(q)], acc[u], 0, 0,
-                                                    0);
+      for (int c = 0; c < 4; ++c) v[4 * u + c] = q[c];
     }
   }
 }
 
-// Add this wave's tiles into the LDS block O ((16 NTA) x (16 NTB), row-major).
-template <int NTA, int NTB, bool DIAG, int P, int GRP>
-__device__ __forceinline__ void gram_store(double* O, int lane, const d4_t* acc, bool first) {
-  using TS = TileSet<NTA, NTB, DIAG>;
-  constexpr int G = 4 / P;
-#pragma unroll
-  for (int u = 0; GRP + G * u < TS::count; ++u) {
-    const int q = GRP + G * u;
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      // register v of a lane holds row lane / 16 + 4 v, column lane % 16
-      const int i = 16 * TS::ta(q) + (lane >> 4) + 4 * v;
-      const int j = 16 * TS::tb(q) + (lane & 15);
-      O[i * (16 * NTB) + j] = first ? acc[u][v] : O[i * (16 * NTB) + j] + acc[u][v];
-    }
-  }
+// Lane c of the lane's 16-lane row (DPP row broadcast, both halves of the
+// double): the row weight of row offset c, which lane c of each group holds.
+template <int C>
+__device__ __forceinline__ double gram_bcast(double x) {
+  const long long b = __builtin_bit_cast(long long, x);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, 0x150 + C, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), 0x150 + C, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned)lo);
 }
 
-// Waves per SIMD the register allocation must leave room for: 3 for the
-// diagonal FP32 blocks (their accumulators then live in VGPRs, no spills);
-// the FP64 and off-diagonal variants take what their registers allow.
-template <typename T, bool DIAG>
-constexpr int gram_min_waves() { return (DIAG && sizeof(T) == 4) ? 3 : 1; }
+// The operands of one wave step: RL rows per lane of the NTA (and, off the
+// diagonal, NB) snapshot tiles, and one row weight per lane (lane i of group
+// g holds the weight of its group's row offset i % RL).
+template <typename T, int NTA, int NB, int RL>
+struct GramStage {
+  T a[NTA][RL];
+  T b[NB][RL];
+  double w;
+};
 
-template <typename T, int NTA, int NTB, bool DIAG>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(gram_min_waves<T, DIAG>())))
-void k_gram(GramArgs<T> A) {
+// G block (a0.., b0..) over the workgroup's row chunk, streamed straight
+// from HBM into the MFMA operands (no LDS staging, no barriers in the row
+// loop).  Lane l of a wave holds snapshot a0 + 16 ta + l % 16 (and b0 + 16 tb
+// + l % 16) and its lane group g = l / 16 takes RL rows of the step: the
+// MFMA's 4-long inner dimension runs over the 4 lane groups, so one MFMA per
+// row offset c < RL and tile adds 4 rows of w x_a x_b, with the A operand
+// w x_a and the B operand x_b taken from the lane's own registers (the
+// weight broadcast within the group's 16-lane DPP row).  A wave step covers
+// 4 RL rows (whole 128-byte lines of every snapshot for RL >= 8 in FP32, 4 in FP64); the
+// 4 waves of the workgroup take consecutive steps, and each step's loads are
+// in flight while the previous step is multiplied (two register stages,
+// alternating).  Full rounds of the four waves load unconditionally; the
+// chunk's last, partial round reads element by element (rows past the chunk
+// as zero).  The waves' partial tiles are summed in LDS at the end and the
+// workgroup writes its FP64 block.
+template <typename T, int NTA, int NTB, bool DIAG, int RL, bool VEC>
+__global__ __launch_bounds__(256) void k_gram(GramArgs<T> A) {
+  static_assert(RL % 4 == 0 && RL <= 16, "RL: a multiple of 4, at most one 16-lane row");
   using TS = TileSet<NTA, NTB, DIAG>;
-  // row phases: every wave forms all tiles when their accumulators fit the
-  // registers, else two tile halves x two row phases
-  constexpr int P = TS::count <= 10 ? 4 : 2;
-  constexpr int G = 4 / P;
-  constexpr int NTW = (TS::count + G - 1) / G;
-  // slab: R rows x C snapshot columns (R C = 4096: narrow blocks stage more
-  // rows per round, so every round moves the same bytes)
-  constexpr int NT = NTA > NTB ? NTA : NTB;
-  constexpr int C = 16 * NT;
-  constexpr int R = NT == 1 ? 256 : NT == 2 ? 128 : 64;
-  constexpr int SS = 256 / R;                  // snapshot stride between a thread's loads
-  constexpr int NQ = (C + SS - 1) / SS;        // loads per thread per operand
-  __shared__ double LA[R][C + 1];
-  __shared__ double LB[DIAG ? 1 : R][C + 1];
-  __shared__ double LW[R];
+  constexpr int NB = DIAG ? 1 : NTB;   // B operands of their own (off the diagonal)
+  constexpr int NQ = TS::count;
+  constexpr int OR = 16 * NTA, OC = 16 * NTB;
+  using Stage = GramStage<T, NTA, NB, RL>;
+  __shared__ double O[OR * OC];
   const int tid = threadIdx.x;
-  const int lane = tid & 63;
+  const int lane = tid & 63, i = lane & 15, grp = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int phase = wave % P, grp = wave / P;
   const int64_t r_begin = (int64_t)blockIdx.x * A.chunk;
   const int64_t r_end = min(r_begin + A.chunk, A.rows);
 
-  d4_t acc[NTW];
+  // snapshot rows of the lane; a lane past na (nb) reads snapshot a0 (b0)
+  // instead: its operand values only reach the output rows (columns) past
+  // na (nb), which the reduction never reads (each MFMA output entry is
+  // formed from its own A row and B column alone)
+  const T* pa[NTA];
+  const T* pb[NB];
 #pragma unroll
-  for (int u = 0; u < NTW; ++u) acc[u] = d4_t{0.0, 0.0, 0.0, 0.0};
+  for (int ta = 0; ta < NTA; ++ta)
+    pa[ta] = A.X + (int64_t)(16 * ta + i < A.na ? A.a0 + 16 * ta + i : A.a0) * A.ld + 4 * grp;
+#pragma unroll
+  for (int tb = 0; tb < NB; ++tb)
+    pb[tb] = A.X + (int64_t)(!DIAG && 16 * tb + i < A.nb ? A.b0 + 16 * tb + i : A.b0) * A.ld +
+             4 * grp;
+  const int wrow = gram_row(grp, i % RL);   // the row whose weight the lane holds
 
-  // staging: thread -> row r0 + tid % R of the snapshots tid / R + SS q:
-  // every load instruction of a wave reads 64 consecutive rows of one snapshot
-  const int row = tid % R, s0 = tid / R;
-  constexpr int NB = DIAG ? 1 : NQ;
-  T pa[NQ], pb[NB];
+  d4_t acc[NQ];
 #pragma unroll
-  for (int q = 0; q < NQ; ++q) pa[q] = T(0);
+  for (int q = 0; q < NQ; ++q) acc[q] = d4_t{0.0, 0.0, 0.0, 0.0};
+
+  auto load_full = [&](int64_t r0, Stage& st) {
 #pragma unroll
-  for (int q = 0; q < NB; ++q) pb[q] = T(0);
-  double pw = 0.0;
-  // loads clamp the row to the chunk (in bounds); rows past it are zeroed on staging
-  auto fetch = [&](int64_t r0) {
-    const int64_t r = min(r0 + row, r_end - 1);
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-      if (s0 + SS * q < A.na) pa[q] = A.X[(int64_t)(A.a0 + s0 + SS * q) * A.ld + r];
+    for (int ta = 0; ta < NTA; ++ta) gram_rows<T, RL, VEC>(pa[ta] + r0, st.a[ta]);
     if (!DIAG) {
 #pragma unroll
-      for (int q = 0; q < NB; ++q)
-        if (s0 + SS * q < A.nb) pb[q] = A.X[(int64_t)(A.b0 + s0 + SS * q) * A.ld + r];
+      for (int tb = 0; tb < NB; ++tb) gram_rows<T, RL, VEC>(pb[tb] + r0, st.b[tb]);
     }
-    if (tid < R) pw = A.W[r];
+    st.w = A.W[r0 + wrow];
   };
-
-  fetch(r_begin);
-  for (int64_t r0 = r_begin; r0 < r_end; r0 += R) {
-    __syncthreads();   // the previous slab's reads of LA / LB / LW are done
-    const bool in = r0 + row < r_end;
+  auto load_tail = [&](int64_t r0, Stage& st) {
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int sq = s0 + SS * q;
-      if (sq < C) LA[row][sq] = (in && sq < A.na) ? (double)pa[q] : 0.0;
-    }
-    if (!DIAG) {
+    for (int c = 0; c < RL; ++c) {
+      const int64_t r = r0 + gram_row(grp, c);
+      const int o = 16 * (c / 4) + c % 4;   // from the lane's base (which includes 4 g)
+      const bool in = r < r_end;
 #pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int sq = s0 + SS * q;
-        if (sq < C) LB[DIAG ? 0 : row][sq] = (in && sq < A.nb) ? (double)pb[q] : 0.0;
+      for (int ta = 0; ta < NTA; ++ta) st.a[ta][c] = in ? pa[ta][r0 + o] : T(0);
+      if (!DIAG) {
+#pragma unroll
+        for (int tb = 0; tb < NB; ++tb) st.b[tb][c] = in ? pb[tb][r0 + o] : T(0);
       }
     }
-    if (tid < R) LW[tid] = in ? pw : 0.0;
-    __syncthreads();
-    if (r0 + R < r_end) fetch(r0 + R);   // in flight during the MFMAs
-    const double(*Bsrc)[C + 1] = DIAG ? LA : LB;
-    if (G == 1 || grp == 0)
-      gram_slab<NTA, NTB, DIAG, P, 0, R, C>(LA, Bsrc, LW, phase, lane, acc);
-    else
-      gram_slab<NTA, NTB, DIAG, P, (G > 1 ? 1 : 0), R, C>(LA, Bsrc, LW, phase, lane, acc);
+    st.w = r0 + wrow < r_end ? A.W[r0 + wrow] : 0.0;
+  };
+  auto multiply = [&](const Stage& st) {
+    static_for<0, RL>([&](auto cc) {
+      constexpr int c = decltype(cc)::value;
+      const double w = gram_bcast<c>(st.w);
+      double av[NTA], bv[NTB];
+#pragma unroll
+      for (int ta = 0; ta < NTA; ++ta) av[ta] = w * (double)st.a[ta][c];
+#pragma unroll
+      for (int tb = 0; tb < NTB; ++tb)
+        bv[tb] = (double)(DIAG ? st.a[tb][c] : st.b[tb < NB ? tb : 0][c]);
+      static_for<0, NQ>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int ta = TS::ta(q), tb = TS::tb(q);
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[ta], bv[tb], acc[q], 0, 0, 0);
+      });
+    });
+  };
+
+  constexpr int64_t kStep = 4 * RL;          // rows of one wave step
+  constexpr int64_t kRound = 4 * kStep;      // rows of one step of all four waves
+  const int64_t full = (r_end - r_begin) / kRound;
+  int64_t r0 = r_begin + wave * kStep;
+  Stage s0, s1;
+  int64_t k = 0;
+  if (full > 0) load_full(r0, s0);
+  // two rounds per pass, the stages alternate; every load in the loop is
+  // unconditional, so each multiply waits only for its own stage's loads.
+  // The scheduling barriers keep the compiler from hoisting the next
+  // stage's loads above the multiply (which would need a third stage of
+  // registers and wait for both stages at once).
+  for (; k + 2 < full; k += 2) {
+    load_full(r0 + kRound, s1);
+    __builtin_amdgcn_sched_barrier(0);
+    multiply(s0);
+    __builtin_amdgcn_sched_barrier(0);
+    load_full(r0 + 2 * kRound, s0);
+    __builtin_amdgcn_sched_barrier(0);
+    multiply(s1);
+    __builtin_amdgcn_sched_barrier(0);
+    r0 += 2 * kRound;
+  }
+  if (full - k == 2) {              // the last two full rounds (the first in s0)
+    load_full(r0 + kRound, s1);
+    multiply(s0);
+    multiply(s1);
+    r0 += 2 * kRound;
+  } else if (full - k == 1) {       // the last full round (in s0)
+    multiply(s0);
+    r0 += kRound;
+  }
+  if (r_begin + full * kRound < r_end) {   // the partial round
+    load_tail(r0, s1);
+    multiply(s1);
   }
 
-  // sum the row phases' partial tiles in LDS (LA reused as the output block)
-  double* O = &LA[0][0];
-  constexpr int OR = 16 * NTA, OC = 16 * NTB;
-  static_assert(R * (C + 1) >= OR * OC, "LDS block too small");
-  for (int ph = 0; ph < P; ++ph) {
-    __syncthreads();
-    if (phase == ph) {
-      if (G == 1 || grp == 0)
-        gram_store<NTA, NTB, DIAG, P, 0>(O, lane, acc, ph == 0);
-      else
-        gram_store<NTA, NTB, DIAG, P, (G > 1 ? 1 : 0)>(O, lane, acc, ph == 0);
+  // sum the four waves' tiles in LDS, in wave order
+  for (int w = 0; w < 4; ++w) {
+    if (wave == w) {
+      static_for<0, NQ>([&](auto qc) {
+        constexpr int q = decltype(qc)::value;
+        constexpr int ta = TS::ta(q), tb = TS::tb(q);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          // register v of a lane holds row lane / 16 + 4 v, column lane % 16
+          const int e = (16 * ta + grp + 4 * v) * OC + 16 * tb + i;
+          O[e] = w == 0 ? acc[q][v] : O[e] + acc[q][v];
+        }
+      });
     }
+    __syncthreads();
   }
-  __syncthreads();
-  double* out = A.part + (int64_t)blockIdx.x * kGramBlk * kGramBlk;
-  for (int e = tid; e < OR * OC; e += 256) out[(e / OC) * kGramBlk + e % OC] = O[e];
+  // the block, packed (OR x OC, row-major) at its workgroup's slot
+  double* out = A.part + (int64_t)blockIdx.x * (OR * OC);
+  for (int e = tid; e < OR * OC; e += 256) out[e] = O[e];
 }
 
 // Sum the per-workgroup blocks entry by entry (Neumaier), write G rows
 // a0.. and columns b0.. of the K x K output (and the mirrored entries).
-// One workgroup per row i of the block; lane j of every wave holds entry
-// (i, j), and wave v sums the blocks v, v + 16, v + 32, ... (each load of a
-// wave reads 64 consecutive doubles of one block); the 16 wave sums are then
-// combined in wave order, so the result does not depend on timing.  Entries
-// of tiles the Gram kernel did not form (beyond na / nb, below the tile
-// diagonal of a diagonal block) are never read.
-constexpr int kGramRedWaves = 16;
-__global__ __launch_bounds__(64 * kGramRedWaves) void k_gram_reduce(const double* part,
-                                                                   int64_t nwg, double* G, int K,
-                                                                   int a0, int na, int b0,
-                                                                   int nb) {
-  __shared__ double rs[kGramRedWaves][kGramBlk], rc[kGramRedWaves][kGramBlk];
+// One workgroup of 1024 threads per row i of the block: thread t holds
+// column j = t % NBP (NBP = nb rounded up to 16, 32 or 64) and sums the
+// blocks v, v + V, v + 2V, ... for its set v = t / NBP (V = 1024 / NBP sets,
+// so narrow blocks keep every lane busy; each load of a set reads NBP
+// consecutive doubles of one block); the V set sums are then combined in set
+// order, so the result does not depend on timing.  Entries of tiles the Gram
+// kernel did not form (beyond na / nb, below the tile diagonal of a diagonal
+// block) are never read.
+constexpr int kGramRedThreads = 1024;
+__global__ __launch_bounds__(kGramRedThreads) void k_gram_reduce(const double* part, int64_t nwg,
+                                                                 int64_t blk, int oc, double* G,
+                                                                 int K, int a0, int na, int b0,
+                                                                 int nb) {
+  __shared__ double rs[kGramRedThreads], rc[kGramRedThreads];
   const int i = blockIdx.x;            // < na
-  const int j = threadIdx.x & 63;
-  const int v = threadIdx.x >> 6;
+  const int NBP = nb <= 16 ? 16 : nb <= 32 ? 32 : 64;
+  const int V = kGramRedThreads / NBP;
+  const int j = threadIdx.x % NBP;
+  const int v = threadIdx.x / NBP;
   const bool live = j < nb && !(a0 == b0 && (i / 16) > (j / 16));
-  const int e = i * kGramBlk + j;
+  const int e = i * oc + j;   // entry (i, j) of a packed block (blk doubles, row stride oc)
   double s = 0.0, c = 0.0;
-  if (live) {
-    int64_t w = v;
-    for (; w + 7 * kGramRedWaves < nwg; w += 8 * kGramRedWaves) {
-      double x[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) x[q] = part[(w + q * kGramRedWaves) * kGramBlk * kGramBlk + e];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        const double t = s + x[q];
-        c += (fabs(s) >= fabs(x[q])) ? ((s - t) + x[q]) : ((x[q] - t) + s);
-        s = t;
-      }
-    }
-    for (; w < nwg; w += kGramRedWaves) {
-      const double x = part[w * kGramBlk * kGramBlk + e];
-      const double t = s + x;
-      c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
-      s = t;
-    }
-  }
-  rs[v][j] = s;
-  rc[v][j] = c;
-  __syncthreads();
-  if (v != 0 || !live) return;
-  for (int u = 1; u < kGramRedWaves; ++u) {
-    const double x = rs[u][j];
+  auto add = [&](double x) {
     const double t = s + x;
     c += (fabs(s) >= fabs(x)) ? ((s - t) + x) : ((x - t) + s);
     s = t;
-    c += rc[u][j];
+  };
+  if (live) {
+    int64_t w = v;
+    for (; w + 3 * V < nwg; w += 4 * V) {
+      double x[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) x[q] = part[(w + q * V) * blk + e];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) add(x[q]);
+    }
+    for (; w < nwg; w += V) add(part[w * blk + e]);
+  }
+  rs[threadIdx.x] = s;
+  rc[threadIdx.x] = c;
+  __syncthreads();
+  if (v != 0 || !live) return;
+  for (int u = 1; u < V; ++u) {
+    add(rs[u * NBP + j]);
+    c += rc[u * NBP + j];
   }
   const double val = s + c;
   // in a diagonal block only the upper triangle writes (and mirrors), so
@@ -351,10 +417,21 @@ __global__ __launch_bounds__(64 * kGramRedWaves) void k_gram_reduce(const double
 }
 
 // One launch of a block pair: as many workgroups as are resident at once
-// (one round, no tail), at most part_cap; returns the count used.
-template <typename T, int NTA, int NTB, bool DIAG>
+// (one round, no tail), at most part_cap; returns the count used.  Rows per
+// lane: 16 for single-tile blocks (K <= 16: more bytes in flight for the
+// memory-bound case), else the fewest for which a wave step reads whole
+// 128-byte lines (8 FP32, 4 FP64 rows), except 4 for off-diagonal FP32
+// blocks of more than 8 tiles (their two operand stages would not fit the
+// registers beside the accumulators).
+template <typename T, int NTA, int NTB, bool DIAG, bool VEC>
 static hipError_t gram_go(GramArgs<T> A, int64_t part_cap, hipStream_t s, int64_t* nwg_used) {
-  const void* fn = reinterpret_cast<const void*>(&k_gram<T, NTA, NTB, DIAG>);
+  // part_cap: the partials buffer in 64 x 64 blocks; a workgroup writes a
+  // packed (16 NTA) x (16 NTB) block
+  part_cap = part_cap * kGramBlk * kGramBlk / (256 * NTA * NTB);
+  constexpr int RL = NTA == 1 && NTB == 1                      ? 16
+                     : sizeof(T) == 8 || (!DIAG && NTA * NTB > 8) ? 4
+                                                                  : 8;
+  const void* fn = reinterpret_cast<const void*>(&k_gram<T, NTA, NTB, DIAG, RL, VEC>);
   int per_cu = 0, cus = 0, dev = 0;
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1)
     per_cu = 2;
@@ -368,19 +445,30 @@ static hipError_t gram_go(GramArgs<T> A, int64_t part_cap, hipStream_t s, int64_
   nwg = (A.rows + chunk - 1) / chunk;
   A.chunk = chunk;
   *nwg_used = nwg;
-  hipLaunchKernelGGL((k_gram<T, NTA, NTB, DIAG>), dim3((unsigned)nwg), dim3(256), 0, s, A);
+  hipLaunchKernelGGL((k_gram<T, NTA, NTB, DIAG, RL, VEC>), dim3((unsigned)nwg), dim3(256), 0, s, A);
   return hipGetLastError();
 }
 
-template <typename T, int NTA>
+template <typename T, int NTA, bool VEC>
 static hipError_t gram_go_b(const GramArgs<T>& A, int ntb, bool diag, int64_t cap, hipStream_t s,
                             int64_t* nwg) {
-  if (diag) return gram_go<T, NTA, NTA, true>(A, cap, s, nwg);
+  if (diag) return gram_go<T, NTA, NTA, true, VEC>(A, cap, s, nwg);
   switch (ntb) {
-    case 1: return gram_go<T, NTA, 1, false>(A, cap, s, nwg);
-    case 2: return gram_go<T, NTA, 2, false>(A, cap, s, nwg);
-    case 3: return gram_go<T, NTA, 3, false>(A, cap, s, nwg);
-    default: return gram_go<T, NTA, 4, false>(A, cap, s, nwg);
+    case 1: return gram_go<T, NTA, 1, false, VEC>(A, cap, s, nwg);
+    case 2: return gram_go<T, NTA, 2, false, VEC>(A, cap, s, nwg);
+    case 3: return gram_go<T, NTA, 3, false, VEC>(A, cap, s, nwg);
+    default: return gram_go<T, NTA, 4, false, VEC>(A, cap, s, nwg);
+  }
+}
+
+template <typename T, bool VEC>
+static hipError_t gram_go_a(const GramArgs<T>& A, int nta, int ntb, bool diag, int64_t cap,
+                            hipStream_t s, int64_t* nwg) {
+  switch (nta) {
+    case 1: return gram_go_b<T, 1, VEC>(A, ntb, diag, cap, s, nwg);
+    case 2: return gram_go_b<T, 2, VEC>(A, ntb, diag, cap, s, nwg);
+    case 3: return gram_go_b<T, 3, VEC>(A, ntb, diag, cap, s, nwg);
+    default: return gram_go_b<T, 4, VEC>(A, ntb, diag, cap, s, nwg);
   }
 }
 
@@ -405,17 +493,14 @@ hipError_t launch_gram(const T* X, int64_t ld, int K, const double* W, const Dim
       const int nta = (A.na + 15) / 16, ntb = (A.nb + 15) / 16;
       const bool diag = a0 == b0;
       int64_t nwg = 0;
-      hipError_t e;
-      switch (nta) {
-        case 1: e = gram_go_b<T, 1>(A, ntb, diag, part_cap_blocks, s, &nwg); break;
-        case 2: e = gram_go_b<T, 2>(A, ntb, diag, part_cap_blocks, s, &nwg); break;
-        case 3: e = gram_go_b<T, 3>(A, ntb, diag, part_cap_blocks, s, &nwg); break;
-        default: e = gram_go_b<T, 4>(A, ntb, diag, part_cap_blocks, s, &nwg); break;
-      }
+      // 16-byte loads need a 16-byte aligned base and snapshot stride
+      const bool vec = (reinterpret_cast<uintptr_t>(X) % 16) == 0 && (ld * sizeof(T)) % 16 == 0;
+      hipError_t e = vec ? gram_go_a<T, true>(A, nta, ntb, diag, part_cap_blocks, s, &nwg)
+                         : gram_go_a<T, false>(A, nta, ntb, diag, part_cap_blocks, s, &nwg);
       if (e != hipSuccess) return e;
       *nwg_used = std::max(*nwg_used, nwg);
-      hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)A.na), dim3(64 * kGramRedWaves), 0, s,
-                         part, nwg, G, K, a0, A.na, b0, A.nb);
+      hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)A.na), dim3(kGramRedThreads), 0, s,
+                         part, nwg, (int64_t)256 * nta * ntb, 16 * ntb, G, K, a0, A.na, b0, A.nb);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
