@@ -459,13 +459,21 @@ int fit_batch_get_tuning(const fit_batch* b, int* tw, int* ty, int* kc, int* ste
 
 /* Two steps of every grid per launch (temporal blocking of the Sec. II-A
  * recurrence, as fit_set_pair_tuning for one grid): with enable = 1 the
- * batch advances pairs of steps with one launch of 32 x 16 tiles of every
- * grid (kc: z-planes per item, 0 = whole columns); an odd last step runs
- * singly.  Each grid's result stays bitwise identical to fit_step on that
- * grid alone.  FIT_E_INVALID if the pair tile does not fit the batch's dtype
- * and materials, or a z-plane of a grid spans more than 4 GiB. */
+ * batch advances pairs of steps with one launch over tiles of every grid;
+ * an odd last step runs singly.  Each grid takes the tile shape of a fixed
+ * set (32 x 16, 32 x 18, 40 x 14, 24 x 24) that stages the fewest points
+ * for its x / y extent, and its columns are cut into ceil(nz / kc) z-chunks
+ * of even length (kc = 0: whole columns); the work items are launched
+ * largest first.  Each grid's result stays bitwise identical to fit_step on
+ * that grid alone.  FIT_E_INVALID if no pair tile fits the batch's dtype and
+ * materials, or a z-plane of a grid spans more than 4 GiB. */
 int fit_batch_set_pair(fit_batch* b, int enable, int kc);
 int fit_batch_get_pair(const fit_batch* b, int* enable, int* kc);
+
+/* The pair tile of grid g (0-based, in the order given to fit_batch_create)
+ * in the current layout: tw x ty columns, kc planes per z-chunk.
+ * FIT_E_INVALID for a bad index, FIT_E_STATE when pairs are off. */
+int fit_batch_get_pair_tile(const fit_batch* b, int g, int* tw, int* ty, int* kc);
 
 /* Persistent form of the batch (Sec. III, Alg. 1: the p independent leapfrog
  * runs): with enable = 1, S steps of every grid run in ONE cooperative launch

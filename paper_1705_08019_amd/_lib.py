@@ -91,6 +91,7 @@ SIGNATURES = {
     "fit_batch_get_persistent": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                                  C.POINTER(C.c_int)],
     "fit_batch_get_pair": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int)],
+    "fit_batch_get_pair_tile": [_vp, _i, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "fit_batch_get_tuning": [_vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                              C.POINTER(C.c_int), C.POINTER(C.c_int)],
     "fit_batch_autotune": [_vp, _dp, _i, C.POINTER(C.c_int), C.POINTER(C.c_int),

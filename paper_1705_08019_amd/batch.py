@@ -53,8 +53,9 @@ class FitBatch:
         return ty, kc, spg, nwg, tw
 
     def set_pair(self, enable: bool = True, kc: int = 0):
-        """Two steps of every grid per launch (32 x 16 tiles, kc planes per
-        item, 0: whole columns)."""
+        """Two steps of every grid per launch (each grid in the pair tile shape
+        that suits its extent, columns cut into even z-chunks of at most kc
+        planes, 0: whole columns)."""
         call("fit_batch_set_pair", self._h, int(bool(enable)), int(kc))
 
     def set_persistent(self, enable: bool = True):
@@ -74,6 +75,12 @@ class FitBatch:
         e, k = C.c_int(), C.c_int()
         call("fit_batch_get_pair", self._h, C.byref(e), C.byref(k))
         return bool(e.value), k.value
+
+    def get_pair_tile(self, g: int):
+        """(tw, ty, kc) of grid g's pair tiles in the current layout."""
+        w, t, k = C.c_int(), C.c_int(), C.c_int()
+        call("fit_batch_get_pair_tile", self._h, int(g), C.byref(w), C.byref(t), C.byref(k))
+        return w.value, t.value, k.value
 
     def autotune(self, dt, reps: int = 5):
         """Returns (ty, kc, ms_per_step, tw)."""

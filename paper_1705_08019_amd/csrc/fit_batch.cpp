@@ -33,13 +33,16 @@ struct fit_batch {
   hipGraphExec_t exec = nullptr;
   int graph_S = 0;
   bool graph_pairs = false;      // the captured chunk holds pair launches
-  // two steps per launch: 32 x 16 tiles of every grid, pkc planes per item
-  // (0: whole columns)
+  // two steps per launch: each grid in its own pair tile shape, its columns
+  // cut into even z-chunks of at most pkc planes (0: whole columns)
   bool pair_on = false;
   int pkc = 0;
-  int* item_grid2 = nullptr;     // device, P2 entries
+  fit::BatchItem* items2 = nullptr;   // device, P2 entries, largest first
   int P2 = 0;
   size_t lds2 = 0;
+  int nthreads2 = 0;
+  std::vector<int> pshape;            // per grid: index into kBatchPairShapes
+  std::vector<fit::Tiling> pt2;       // per grid: its pair tiling
   // persistent form: S steps per cooperative launch of persist_nwg resident
   // workgroups (fit_batch_set_persistent); persist_graph: the S-step launch
   // could be captured (else chunks are launched directly)
@@ -146,37 +149,85 @@ static int batch_layout(fit_batch* b) {
   return FIT_OK;
 }
 
-// Tiling of grid d for step pairs.
-static Tiling batch_tiling2(const fit_batch* b, const Dims& d) {
-  const int kc = b->pkc > 0 ? std::min(b->pkc, d.nz) : d.nz;
-  return make_tiling(d, kBatchPairTy, kc, kBatchPairTw);
+// Staged points per z-plane of grid d in pair tile shape q: the tiles'
+// staging regions ((tw + 4) x (ty + 4) points of h, eps and, lossy, sigma)
+// and e-update regions ((tw + 4) x (ty + 3) points of e).
+static double pair_plane_cost(const Dims& d, int q, bool lossy) {
+  const int tw = kBatchPairShapes[q][0], ty = kBatchPairShapes[q][1];
+  const double tiles = (double)((d.nx + tw - 1) / tw) * ((d.ny + ty - 1) / ty);
+  return tiles * ((tw + 4.0) * (ty + 4.0) * (lossy ? 5 : 4) + (tw + 4.0) * (ty + 3.0) * 3);
 }
 
-// The pair item table and LDS size (FIT_E_INVALID if the pair tile does not
-// fit the dtype's LDS or a grid's plane is too large for the kernel).
+// The pair layout: each grid's tile shape (the one of kBatchPairShapes that
+// fits the dtype and stages the fewest points for its x / y extent; ties go
+// to the earlier, wider shape) and its z-chunks (the column cut into
+// ceil(nz / pkc) chunks of even length, pkc = 0: whole columns); the item
+// table lists every tile of every grid, largest first (an item's work grows
+// with its chunk length plus the two planes of lag and one of halo, times its
+// tile's staged points), so the dispatcher hands out the long items first;
+// the kernel's threads and LDS are the largest any used shape needs.
+// FIT_E_INVALID if no shape fits the dtype or a grid's plane is too large.
 static int batch_layout2(fit_batch* b) {
   const size_t esz = b->f64 ? 8 : 4;
-  const size_t lds = step2_lds_bytes(kBatchPairTw, kBatchPairTy, esz, b->lossy_any, false);
-  if (!step2_shape_ok(kBatchPairTw, kBatchPairTy, esz, b->lossy_any, false))
-    return fail(FIT_E_INVALID, "the pair tile does not fit a workgroup");
-  std::vector<int> items;
+  std::vector<int> shape((size_t)b->nb);
+  std::vector<Tiling> til((size_t)b->nb);
+  struct Item {
+    double cost;
+    int grid, tile;
+  };
+  std::vector<Item> items;
+  size_t lds = 0;
+  int nthreads = 64;
   for (int g = 0; g < b->nb; ++g) {
-    if (!step2_plane_ok(b->grids[g]->d, esz))
+    const fit_grid* gr = b->grids[g];
+    const Dims& d = gr->d;
+    if (!step2_plane_ok(d, esz))
       return fail(FIT_E_INVALID, "a z-plane of a grid spans more than 4 GiB");
-    const Tiling t = batch_tiling2(b, b->grids[g]->d);
-    for (int64_t q = 0; q < t.blocks(); ++q) items.push_back(g);
+    int best = -1;
+    double best_cost = 0.0;
+    for (int q = 0; q < kBatchPairNShapes; ++q) {
+      const int tw = kBatchPairShapes[q][0], ty = kBatchPairShapes[q][1];
+      if (!step2_shape_ok(tw, ty, esz, b->lossy_any, false) || step2_threads(tw, ty) > 768)
+        continue;
+      const double c = pair_plane_cost(d, q, gr->lossy);
+      if (best < 0 || c < best_cost) {
+        best = q;
+        best_cost = c;
+      }
+    }
+    if (best < 0) return fail(FIT_E_INVALID, "no pair tile fits a workgroup for this dtype");
+    const int tw = kBatchPairShapes[best][0], ty = kBatchPairShapes[best][1];
+    const int nch = b->pkc > 0 ? (d.nz + b->pkc - 1) / b->pkc : 1;
+    const int kc = (d.nz + nch - 1) / nch;
+    shape[g] = best;
+    til[g] = make_tiling(d, ty, kc, tw);
+    lds = std::max(lds, step2_lds_bytes(tw, ty, esz, b->lossy_any, false));
+    nthreads = std::max(nthreads, step2_threads(tw, ty));
+    const double per_plane = best_cost / ((double)til[g].ntx * til[g].nty);
+    for (int64_t t = 0; t < til[g].blocks(); ++t) {
+      const int kz = (int)(t / ((int64_t)til[g].ntx * til[g].nty));
+      const int planes = std::min(kc, d.nz - kz * kc);
+      items.push_back({(planes + 3) * per_plane, g, (int)t});
+    }
   }
   if (items.size() > (size_t)0x7fffffff) return fail(FIT_E_INVALID, "too many work items");
-  dev_free(reinterpret_cast<void*&>(b->item_grid2));
+  std::stable_sort(items.begin(), items.end(),
+                   [](const Item& x, const Item& y) { return x.cost > y.cost; });
+  std::vector<BatchItem> table(items.size());
+  for (size_t r = 0; r < items.size(); ++r) table[r] = BatchItem{items[r].grid, items[r].tile};
+  dev_free(reinterpret_cast<void*&>(b->items2));
   b->P2 = 0;
-  int rc = dev_alloc(reinterpret_cast<void**>(&b->item_grid2), items.size() * sizeof(int),
+  int rc = dev_alloc(reinterpret_cast<void**>(&b->items2), table.size() * sizeof(BatchItem),
                      "pair item table");
   if (rc) return rc;
-  hipError_t e = hipMemcpy(b->item_grid2, items.data(), items.size() * sizeof(int),
+  hipError_t e = hipMemcpy(b->items2, table.data(), table.size() * sizeof(BatchItem),
                            hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(e, "pair item table upload");
-  b->P2 = (int)items.size();
+  b->P2 = (int)table.size();
   b->lds2 = lds;
+  b->nthreads2 = nthreads;
+  b->pshape = shape;
+  b->pt2 = til;
   batch_drop_graph(b);
   return FIT_OK;
 }
@@ -213,7 +264,7 @@ static int batch_desc(fit_batch* b, const double* dt, int64_t nsteps, bool with_
   }
   std::vector<T> tab;
   if (with_src) tab.assign((size_t)b->nb * (size_t)b->src_cap, T(0));
-  int off = 0, off2 = 0;
+  int off = 0;
   for (int g = 0; g < b->nb; ++g) {
     fit_grid* gr = b->grids[g];
     BatchGrid<T>& D = desc[g];
@@ -244,9 +295,13 @@ static int batch_desc(fit_batch* b, const double* dt, int64_t nsteps, bool with_
     D.ntiles = (int)D.t.blocks();
     D.tile_off = off;
     off += D.ntiles;
-    D.t2 = batch_tiling2(b, gr->d);
-    D.tile_off2 = off2;
-    off2 += (int)D.t2.blocks();
+    if (g < (int)b->pt2.size()) {   // the pair layout (empty until pairs are laid out)
+      D.t2 = b->pt2[g];
+      D.s2shape = b->pshape[g];
+    } else {
+      D.t2 = Tiling{};
+      D.s2shape = 0;
+    }
   }
   hipError_t e = hipSuccess;
   if (with_src)
@@ -265,6 +320,8 @@ static BatchArgs<T> batch_args_host(fit_batch* b, int fixed) {
   BatchArgs<T> a;
   a.grids = static_cast<const BatchGrid<T>*>(b->desc);
   a.item_grid = b->item_grid;
+  a.items2 = nullptr;
+  a.launch_off = 0;
   a.ctl = b->ctl;
   a.nb = b->nb;
   a.P = b->P;
@@ -278,9 +335,10 @@ static BatchArgs<T> batch_args_host(fit_batch* b, int fixed) {
 template <typename T>
 static BatchArgs<T> batch_args_pair(fit_batch* b, int fixed) {
   BatchArgs<T> a = batch_args_host<T>(b, fixed);
-  a.item_grid = b->item_grid2;
+  a.item_grid = nullptr;
+  a.items2 = b->items2;
   a.P = b->P2;
-  a.nthreads = step2_threads(kBatchPairTw, kBatchPairTy);
+  a.nthreads = b->nthreads2;
   a.lds = (int)b->lds2;
   return a;
 }
@@ -351,7 +409,22 @@ static int batch_run(fit_batch* b, int64_t nsteps, const double* dt, int use_gra
   const int64_t rem = nlaunch - chunks * S;
   const BatchArgs<T> a = batch_args_host<T>(b, 0);
   const BatchArgs<T> a2 = batch_args_pair<T>(b, 0);
-  auto one = [&]() { return pairs ? launch_batch2<T>(a2, b->s) : launch_batch<T>(a, b->s); };
+  // a single step advances the counters itself; a pair launch reads them
+  // plus its offset within the chunk, and the chunk advances them once
+  auto one = [&]() {
+    if (!pairs) return launch_batch<T>(a, b->s);
+    hipError_t el = launch_batch2<T>(a2, b->s);
+    return el == hipSuccess ? launch_batch_advance(b->ctl, 2, 1, b->s) : el;
+  };
+  auto chunk_of_pairs = [&]() {
+    hipError_t el = hipSuccess;
+    BatchArgs<T> ak = a2;
+    for (int q = 0; q < S && el == hipSuccess; ++q) {
+      ak.launch_off = q;
+      el = launch_batch2<T>(ak, b->s);
+    }
+    return el == hipSuccess ? launch_batch_advance(b->ctl, 2 * S, S, b->s) : el;
+  };
   hipError_t e = launch_batch_set_base(b->ctl, 0, b->s);
   if (e != hipSuccess) return hip_fail(e, "batch step counter");
   if (chunks > 0) {
@@ -360,7 +433,10 @@ static int batch_run(fit_batch* b, int64_t nsteps, const double* dt, int use_gra
       e = hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal);
       if (e != hipSuccess) return hip_fail(e, "graph capture begin");
       hipError_t el = hipSuccess;
-      for (int q = 0; q < S && el == hipSuccess; ++q) el = one();
+      if (pairs)
+        el = chunk_of_pairs();
+      else
+        for (int q = 0; q < S && el == hipSuccess; ++q) el = one();
       e = hipStreamEndCapture(b->s, &b->graph);
       if (el != hipSuccess) {
         batch_drop_graph(b);
@@ -522,7 +598,7 @@ int fit_batch_destroy(fit_batch* b) {
   batch_drop_graph(b);
   dev_free(b->desc);
   dev_free(reinterpret_cast<void*&>(b->item_grid));
-  dev_free(reinterpret_cast<void*&>(b->item_grid2));
+  dev_free(reinterpret_cast<void*&>(b->items2));
   dev_free(reinterpret_cast<void*&>(b->ctl));
   dev_free(b->src_tab);
   if (b->ev_in) (void)hipEventDestroy(b->ev_in);
@@ -627,6 +703,18 @@ int fit_batch_get_pair(const fit_batch* b, int* enable, int* kc) {
   if (!b) return fail(FIT_E_INVALID, "null batch");
   if (enable) *enable = b->pair_on ? 1 : 0;
   if (kc) *kc = b->pkc;
+  return FIT_OK;
+}
+
+int fit_batch_get_pair_tile(const fit_batch* b, int g, int* tw, int* ty, int* kc) {
+  if (!b) return fail(FIT_E_INVALID, "null batch");
+  if (g < 0 || g >= b->nb) return fail(FIT_E_INVALID, "grid index out of range");
+  if (!b->pair_on || g >= (int)b->pt2.size())
+    return fail(FIT_E_STATE, "step pairs are not enabled for this batch");
+  const fit::Tiling& t = b->pt2[(size_t)g];
+  if (tw) *tw = t.tw;
+  if (ty) *ty = t.ty;
+  if (kc) *kc = t.kc;
   return FIT_OK;
 }
 
@@ -747,7 +835,7 @@ int fit_batch_autotune(fit_batch* b, const double* dt_in, int reps, int* tw, int
   if (!rc && !rc2 && !b->persist) {   // the persistent form runs single steps
     float best_pair = 1e30f;
     int bpkc = -1;
-    for (int pk : {16, 8, 6, 4}) {
+    for (int pk : {8, 16, 24, 32, 48, 0}) {
       b->pkc = pk;
       if (batch_layout2(b) != FIT_OK) break;   // the pair tile does not fit this batch
       float ms = 0.f;

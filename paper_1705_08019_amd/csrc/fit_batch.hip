@@ -24,11 +24,12 @@ __global__ void k_batch_set_base(BatchCtl* ctl, int64_t base) {
   }
 }
 
-// after a launch of `steps` steps: the step index and the buffer-set flips
-__global__ void k_batch_advance(BatchCtl* ctl, int steps) {
+// after launches of `steps` steps in all: the step index and the buffer-set
+// flips (one per launch)
+__global__ void k_batch_advance(BatchCtl* ctl, int steps, int flips) {
   if (threadIdx.x == 0 && blockIdx.x == 0) {
     ctl->step_base += steps;
-    ctl->flip += 1;
+    ctl->flip += flips;
   }
 }
 
@@ -85,20 +86,45 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs<T> B) {
 }
 
 // Two steps of every grid: one workgroup per item of the pair item table,
-// i.e. one 32 x 16 tile (with its z-chunk) of one grid, run by the tile body
-// of the single-grid two-step kernel.  Budgets as that kernel's 32 x 16
-// variant.
+// i.e. one tile (with its z-chunk) of one grid, run by the tile body of the
+// single-grid two-step kernel in the grid's compile-time tile shape.  The
+// table lists the items largest first and is read in launch order (no XCD
+// remapping), so the dispatcher hands out the longest items first and the
+// short ones fill the tail.  The step index and buffer set of launch
+// launch_off of a captured chain come from the counters plus its offset, so
+// the counters are advanced once per chain.  Budgets as the single-grid
+// kernel's one-point compile-time variants (at most 768 threads).
+template <typename T, bool LOSSY>
+__device__ __forceinline__ void batch2_tile(const S2Args<T>& a, int shape, int t, T* sm) {
+  const int tx = t % a.t.ntx;
+  const int rr = t / a.t.ntx;
+  const int tyi = rr % a.t.nty, kz = rr / a.t.nty;
+  static_assert(kBatchPairNShapes == 4, "one case per shape");
+  switch (shape) {
+    case 0:
+      step2_tile<T, LOSSY, false, kBatchPairShapes[0][0], kBatchPairShapes[0][1]>(a, tx, tyi, kz, sm);
+      break;
+    case 1:
+      step2_tile<T, LOSSY, false, kBatchPairShapes[1][0], kBatchPairShapes[1][1]>(a, tx, tyi, kz, sm);
+      break;
+    case 2:
+      step2_tile<T, LOSSY, false, kBatchPairShapes[2][0], kBatchPairShapes[2][1]>(a, tx, tyi, kz, sm);
+      break;
+    default:
+      step2_tile<T, LOSSY, false, kBatchPairShapes[3][0], kBatchPairShapes[3][1]>(a, tx, tyi, kz, sm);
+      break;
+  }
+}
+
 template <typename T>
-__global__ __launch_bounds__(sizeof(T) == 8 ? 768 : 1024)
+__global__ __launch_bounds__(768)
 __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 3))) void k_batch2(BatchArgs<T> B) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
-  const int r = (int)xcd_remap(blockIdx.x, gridDim.x);
-  const int g = B.item_grid[r];
-  const BatchGrid<T>& G = B.grids[g];
-  const int t = r - G.tile_off2;
-  const int64_t sg = B.fixed_parity ? 0 : B.ctl->step_base;
-  const int p = (int)((G.par0 + (B.fixed_parity ? 0 : B.ctl->flip)) & 1);
+  const BatchItem it = B.items2[blockIdx.x];
+  const BatchGrid<T>& G = B.grids[it.grid];
+  const int64_t sg = B.fixed_parity ? 0 : B.ctl->step_base + 2 * (int64_t)B.launch_off;
+  const int p = (int)((G.par0 + (B.fixed_parity ? 0 : B.ctl->flip + B.launch_off)) & 1);
   S2Args<T> a;
   const int64_t n = G.d.n;
   for (int c = 0; c < 3; ++c) {
@@ -119,12 +145,10 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 3))) void k_batch2(Batch
   a.src_idx = G.src_idx;
   a.src_val[0] = G.src_tab ? G.src_tab[sg] : T(0);
   a.src_val[1] = G.src_tab ? G.src_tab[sg + 1] : T(0);
-  const int tx = t % G.t2.ntx;
-  const int rr = t / G.t2.ntx;
   if (G.lossy)
-    step2_tile<T, true, false, kBatchPairTw, kBatchPairTy>(a, tx, rr % G.t2.nty, rr / G.t2.nty, sm);
+    batch2_tile<T, true>(a, G.s2shape, it.tile, sm);
   else
-    step2_tile<T, false, false, kBatchPairTw, kBatchPairTy>(a, tx, rr % G.t2.nty, rr / G.t2.nty, sm);
+    batch2_tile<T, false>(a, G.s2shape, it.tile, sm);
 }
 
 // Persistent form: S steps of every grid in ONE launch.  Workgroup w runs
@@ -283,7 +307,7 @@ hipError_t launch_batch(const BatchArgs<T>& b, hipStream_t s) {
   hipLaunchKernelGGL(k_batch<T>, dim3((unsigned)b.P), dim3(b.nthreads), (size_t)b.lds, s, b);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess || b.fixed_parity) return e;
-  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, b.ctl, 1);
+  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, b.ctl, 1, 1);
   return hipGetLastError();
 }
 
@@ -295,9 +319,11 @@ hipError_t launch_batch2(const BatchArgs<T>& b, hipStream_t s) {
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_batch2<T>, dim3((unsigned)b.P), dim3(b.nthreads), (size_t)b.lds, s, b);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess || b.fixed_parity) return e;
-  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, b.ctl, 2);
+  return hipGetLastError();
+}
+
+hipError_t launch_batch_advance(BatchCtl* ctl, int steps, int flips, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_advance, dim3(1), dim3(64), 0, s, ctl, steps, flips);
   return hipGetLastError();
 }
 

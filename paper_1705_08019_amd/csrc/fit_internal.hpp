@@ -287,22 +287,33 @@ struct BatchGrid {
   int par0;            // buffer set holding the state at the start of the call
   int ntiles;          // tiles per step
   int tile_off;        // offset of this grid's tiles within one step's items
-  Tiling t2;           // step pairs: 32 x 16 tiles (kBatchPairTw x kBatchPairTy)
-  int tile_off2;       // offset of this grid's tiles within one pair launch's items
+  Tiling t2;           // step pairs: this grid's pair tiling (tw x ty, kc planes)
+  int s2shape;         // its tile: index into kBatchPairShapes
 };
-// Tile of the batched two-steps-per-launch kernel.
-constexpr int kBatchPairTw = 32, kBatchPairTy = 16;
+// Tiles of the batched two-steps-per-launch kernel (compile-time variants of
+// the pair tile body, at most 768 threads each); every grid takes the one
+// that stages the fewest points for its x / y extent.
+constexpr int kBatchPairShapes[4][2] = {{32, 16}, {32, 18}, {40, 14}, {24, 24}};
+constexpr int kBatchPairNShapes = 4;
+// One work item of a pair launch: tile `tile` (x fastest, then y, then
+// z-chunk) of grid `grid`.
+struct BatchItem {
+  int grid, tile;
+};
 
 template <typename T>
 struct BatchArgs {
   const BatchGrid<T>* grids;
   const int* item_grid;   // grid of each item of a step (P entries)
+  const BatchItem* items2; // pair launches: the items, largest first (P entries)
   BatchCtl* ctl;
   int nb;
   int P;                  // items (workgroups) per step
   int nthreads;           // threads per workgroup (1-D; >= tw ty of every grid's tile)
   int lds;                // dynamic LDS bytes (the largest grid tile's)
   int fixed_parity;       // autotuning: read par0, step index 0, no counter
+  int launch_off;         // pair launches: index of the launch since the counters
+                          // were last advanced (steps 2 launch_off, as many flips)
 };
 
 // Allow the batched kernel the largest dynamic LDS a workgroup can have and
@@ -310,11 +321,14 @@ struct BatchArgs {
 int batch_prepare(size_t esz, int nthreads, size_t lds);
 template <typename T>
 hipError_t launch_batch(const BatchArgs<T>& b, hipStream_t s);
-// Two steps of every grid per launch (b.item_grid: the pair item table,
-// b.P its length, b.lds the pair LDS); then the counters (+2 steps).
+// Two steps of every grid per launch (b.items2: the pair item table, b.P
+// its length, b.lds the pair LDS, b.launch_off the launch's place since the
+// last counter advance).  The counters are not advanced here.
 template <typename T>
 hipError_t launch_batch2(const BatchArgs<T>& b, hipStream_t s);
 hipError_t launch_batch_set_base(BatchCtl* ctl, int64_t base, hipStream_t s);
+// Advance the step index by `steps` and the buffer-set flips by `flips`.
+hipError_t launch_batch_advance(BatchCtl* ctl, int steps, int flips, hipStream_t s);
 // S steps of every grid in one cooperative launch of nwg resident workgroups
 // (single-step items of b.item_grid; grid-wide barrier between steps); the
 // step index and parity come from and go back to b.ctl.

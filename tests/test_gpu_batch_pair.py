@@ -1,4 +1,4 @@
-"""Batched step pairs (two steps of every grid per launch, 32 x 16 tiles):
+"""Batched step pairs (two steps of every grid per launch, per-grid tiles):
 every grid equals its plain single-grid run bitwise through direct launches,
 graph replays of pairs, odd step counts (a last single step), z-chunked
 items and mixed lossy / lossless grids, in FP32 and FP64."""
@@ -47,6 +47,45 @@ def test_batch_pairs_equal_plain(dtype, which):
     _plain(gp, dts, 3)
     _assert_equal(_fields(gb), _fields(gp))
     assert all(g.step_index == 113 for g in gb)
+    b.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_batch_pair_tiles_per_grid(dtype):
+    """Each grid takes its own pair tile shape (the one staging the fewest
+    points for its x / y extent) and z-chunks of even length; the batch of
+    mixed shapes, launched largest item first, stays bitwise equal to plain
+    per-grid steps through graph chunks (per-launch offsets, one counter
+    advance per chunk), direct launches and a last single step."""
+    import math
+    from paper_1705_08019_amd import FitBatch, FitError
+    specs = c4()[:12]
+    gb, dts = _make(specs, dtype, lossy_every=4)
+    gp, _ = _make(specs, dtype, lossy_every=4)
+    b = FitBatch(gb)
+    with pytest.raises(FitError, match="STATE"):
+        b.get_pair_tile(0)                      # pairs are off
+    b.set_pair(True, 24)
+    shapes = set()
+    for n, s in enumerate(specs):
+        tw, ty, kc = b.get_pair_tile(n)
+        shapes.add((tw, ty))
+        nch = math.ceil(s.nz / 24)
+        assert kc == math.ceil(s.nz / nch) and kc <= 24, (n, s.nz, kc)
+    with pytest.raises(FitError, match="INVALID"):
+        b.get_pair_tile(len(specs))
+    print(f"pair tiles {dtype}: {sorted(shapes)}", flush=True)
+    assert len(shapes) >= 2
+    assert shapes <= {(32, 16), (32, 18), (40, 14), (24, 24)}
+    b.set_tuning(0, 0, 8)                       # 4 pairs per captured chunk
+    b.step(21, dts)                             # 2 replays, 2 direct pairs, 1 single step
+    _plain(gp, dts, 21)
+    _assert_equal(_fields(gb), _fields(gp))
+    b.set_pair(True, 0)                         # whole columns
+    b.step(18, dts, use_graph=False)
+    _plain(gp, dts, 18)
+    _assert_equal(_fields(gb), _fields(gp))
+    assert all(g.step_index == 39 for g in gb)
     b.close()
 
 
