@@ -288,12 +288,15 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs<T> A) {
     static_for<0, RL>([&](auto cc) {
       constexpr int c = decltype(cc)::value;
       const double w = gram_bcast<c>(st.w);
+      // a dead row (weight 0: PEC-wall or phantom slot) contributes exactly
+      // 0 whatever the snapshots hold there: its values are selected away
+      const bool live = w != 0.0;
       double av[NTA], bv[NTB];
 #pragma unroll
-      for (int ta = 0; ta < NTA; ++ta) av[ta] = w * (double)st.a[ta][c];
+      for (int ta = 0; ta < NTA; ++ta) av[ta] = w * (double)(live ? st.a[ta][c] : T(0));
 #pragma unroll
       for (int tb = 0; tb < NTB; ++tb)
-        bv[tb] = (double)(DIAG ? st.a[tb][c] : st.b[tb < NB ? tb : 0][c]);
+        bv[tb] = (double)(live ? (DIAG ? st.a[tb][c] : st.b[tb < NB ? tb : 0][c]) : T(0));
       static_for<0, NQ>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
         constexpr int ta = TS::ta(q), tb = TS::tb(q);

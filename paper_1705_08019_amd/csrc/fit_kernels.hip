@@ -178,7 +178,9 @@ __global__ __launch_bounds__(512) void k_epass(EArgs<T> A) {
       A.eout[2][idx] = ezn;
       if (ENERGY) {
         const double mx = gex * (double)E4x, my = gey * (double)E4y, mz = gez * (double)E4z;
-        const double ox = exo, oy = eyo, oz = ezo, nx_ = exn, ny_ = eyn, nz_ = ezn;
+        // dead edges' e^m is selected away (not multiplied by a zero weight)
+        const double ox = lx ? (double)exo : 0.0, oy = ly ? (double)eyo : 0.0;
+        const double oz = lz ? (double)ezo : 0.0, nx_ = exn, ny_ = eyn, nz_ = ezn;
         nadd(acc[PE_EE_MM], cmp[PE_EE_MM], mx * ox * ox + my * oy * oy + mz * oz * oz);
         nadd(acc[PE_EE_MM1], cmp[PE_EE_MM1], mx * ox * nx_ + my * oy * ny_ + mz * oz * nz_);
         nadd(acc[PE_EE_M1M1], cmp[PE_EE_M1M1], mx * nx_ * nx_ + my * ny_ * ny_ + mz * nz_ * nz_);
@@ -311,7 +313,8 @@ __global__ __launch_bounds__(512) void k_hpass(HArgs<T> A) {
         const double wx = ip ? 1.0 / (gfx * (double)mx) : 0.0;
         const double wy = jp ? 1.0 / (gfy * (double)my) : 0.0;
         const double wz = k > 0 ? 1.0 / (gfz * (double)mz) : 0.0;
-        const double ox = hxo, oy = hyo, oz = hzo, nx_ = hxn, ny_ = hyn, nz_ = hzn;
+        const double ox = ip ? (double)hxo : 0.0, oy = jp ? (double)hyo : 0.0;
+        const double oz = k > 0 ? (double)hzo : 0.0, nx_ = hxn, ny_ = hyn, nz_ = hzn;
         nadd(acc[PH_HH_CC], cmp[PH_HH_CC], wx * ox * ox + wy * oy * oy + wz * oz * oz);
         nadd(acc[PH_HH_CN], cmp[PH_HH_CN], wx * ox * nx_ + wy * oy * ny_ + wz * oz * nz_);
         nadd(acc[PH_HH_NN], cmp[PH_HH_NN], wx * nx_ * nx_ + wy * ny_ * ny_ + wz * nz_ * nz_);

@@ -247,7 +247,12 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
         gst(A.e1[2], g, ezn);
         if (ENERGY) {
           const double mx = gex * (double)E4x, my = gey * (double)E4y, mz = gez * (double)E4z;
-          const double ox = eo0, oy = eo1, oz = eo2, nx_ = exn, ny_ = eyn, nz_ = ezn;
+          // e^m of dead edges (PEC walls, phantom slots) is selected away, not
+          // multiplied by a zero weight: whatever such a slot holds stays out
+          const double ox = j > 0 && k > 0 ? (double)eo0 : 0.0;
+          const double oy = i > 0 && k > 0 ? (double)eo1 : 0.0;
+          const double oz = i > 0 && j > 0 ? (double)eo2 : 0.0;
+          const double nx_ = exn, ny_ = eyn, nz_ = ezn;
           nadd_s(acc[PE_EE_MM], cmp[PE_EE_MM], mx * ox * ox + my * oy * oy + mz * oz * oz);
           nadd_s(acc[PE_EE_MM1], cmp[PE_EE_MM1], mx * ox * nx_ + my * oy * ny_ + mz * oz * nz_);
           nadd_s(acc[PE_EE_M1M1], cmp[PE_EE_M1M1],
@@ -325,7 +330,8 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
         const double wx = i > 0 ? 1.0 / (gfx * (double)A.imu2) : 0.0;
         const double wy = j > 0 ? 1.0 / (gfy * (double)A.imu2) : 0.0;
         const double wz = km > 0 ? 1.0 / (gfz * (double)A.imu2) : 0.0;
-        const double ox = hxo, oy = hyo, oz = hzo, nx_ = hxn, ny_ = hyn, nz_ = hzn;
+        const double ox = i > 0 ? (double)hxo : 0.0, oy = j > 0 ? (double)hyo : 0.0;
+        const double oz = km > 0 ? (double)hzo : 0.0, nx_ = hxn, ny_ = hyn, nz_ = hzn;
         nadd_s(acc[PS_HH_CC], cmp[PS_HH_CC], wx * ox * ox + wy * oy * oy + wz * oz * oz);
         nadd_s(acc[PS_HH_CN], cmp[PS_HH_CN], wx * ox * nx_ + wy * oy * ny_ + wz * oz * nz_);
         nadd_s(acc[PS_HH_NN], cmp[PS_HH_NN], wx * nx_ * nx_ + wy * ny_ * ny_ + wz * nz_ * nz_);
