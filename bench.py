@@ -233,7 +233,7 @@ def measure_copy(nbytes: int = 1 << 30, reps: int = 5) -> float:
     return round(2 * nbytes / (best / 1e3) / 1e9, 1)
 
 
-def form_batched(plain_steps: int = 400):
+def form_batched(plain_steps: int = 400, persistent: bool = True):
     """64 FP32 grids, per-axis sizes ~ U{32..96}, 8 dielectric blocks each,
     lossless, random interior source each, 4000 steps: batched launches
     (graph-captured, autotuned: single steps or step pairs) against plain
@@ -274,6 +274,8 @@ def form_batched(plain_steps: int = 400):
     # grid-wide barrier between the steps, the launch replayed from a hipGraph
     persist = None
     try:
+        if not persistent:
+            raise RuntimeError("skipped (--no-persistent)")
         b.set_pair(False)
         ty_, kc_, _, _, tw_ = b.get_tuning()
         b.set_tuning(ty_, kc_, 16, tw_)           # the autotuned tile, 16 steps per launch
@@ -724,7 +726,19 @@ def _counter_by_launch(d, counter):
 def summarize_kernels(kt, out_md, cmd_note, title):
     """Kernel durations of one rocprofv3 --kernel-trace --stats run as
     profiles/<name>.md (every kernel, by total time)."""
-    stats = sorted(_csv_rows(kt, "_kernel_stats.csv"), key=lambda r: -float(r["TotalDurationNs"]))
+    # one row per kernel, merged over the runs found below `kt` (one run per
+    # form when the forms are profiled separately)
+    merged = {}
+    for r in _csv_rows(kt, "_kernel_stats.csv"):
+        m = merged.setdefault(r["Name"], {"Name": r["Name"], "Calls": 0, "TotalDurationNs": 0.0,
+                                          "MinNs": float("inf"), "MaxNs": 0.0})
+        m["Calls"] += int(r["Calls"])
+        m["TotalDurationNs"] += float(r["TotalDurationNs"])
+        m["MinNs"] = min(m["MinNs"], float(r["MinNs"]))
+        m["MaxNs"] = max(m["MaxNs"], float(r["MaxNs"]))
+    for m in merged.values():
+        m["AverageNs"] = m["TotalDurationNs"] / max(m["Calls"], 1)
+    stats = sorted(merged.values(), key=lambda r: -float(r["TotalDurationNs"]))
     lines = ["# rocprofv3 summary: " + os.path.basename(out_md).replace(".md", ""), "", title, "",
              "Commands (run from the repository root on the MI355X box):", "", "```"]
     lines += cmd_note + ["```", "", "## Kernel durations (--kernel-trace --stats)", "",
@@ -829,12 +843,15 @@ def summarize(kt, rd_dir, wr_dir, out_md, cells, cmd_note):
     print(json.dumps(rec))
 
 
-def run_forms() -> dict:
-    """The batched, adjoint, Gram, ParaExp and graded-grid forms; a failing
-    form is reported, not hidden."""
+def run_forms(only=None, persistent=True) -> dict:
+    """The batched, adjoint, Gram, ParaExp and graded-grid forms (or those
+    named in `only`); a failing form is reported, not hidden."""
     out = {}
-    for name, fn in (("c2", form_c2), ("batched", form_batched), ("adjoint", form_adjoint),
+    batched = lambda: form_batched(persistent=persistent)
+    for name, fn in (("c2", form_c2), ("batched", batched), ("adjoint", form_adjoint),
                      ("gram", form_gram), ("paraexp", form_paraexp), ("graded", form_graded)):
+        if only and name not in only:
+            continue
         try:
             out[name] = fn()
         except Exception as ex:
@@ -861,6 +878,13 @@ def main(argv=None):
                     help="write --summary-out from one rocprofv3 --kernel-trace --stats run")
     ap.add_argument("--forms-only", action="store_true",
                     help="run only the batched / adjoint / Gram / ParaExp / graded forms")
+    ap.add_argument("--no-persistent", action="store_true",
+                    help="batched form without its persistent sub-form (rocprofv3's kernel "
+                         "trace of a process that ran the cooperative launch ends before "
+                         "writing its results)")
+    ap.add_argument("--form", action="append", default=[],
+                    choices=["c2", "batched", "adjoint", "gram", "paraexp", "graded"],
+                    help="with --forms-only: run only this form (repeatable)")
     ap.add_argument("--summarize", nargs=3, metavar="DIR", default=None,
                     help="kernel-trace, read-counter and write-counter rocprofv3 output dirs "
                          "-> profiles/")
@@ -888,7 +912,7 @@ def main(argv=None):
         calib_copy()
         return 0
     if args.forms_only:
-        print(json.dumps({"forms": run_forms()}), flush=True)
+        print(json.dumps({"forms": run_forms(args.form, not args.no_persistent)}), flush=True)
         return 0
     spec = c3_inputs()
     cells = spec.cells
