@@ -247,13 +247,24 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
   // the latest planes formed
   T hq[NP][3], Sxq[NP], Syq[NP], Sxsq[NP], Sysq[NP];
   T e1p[NP][3], E4p[NP][3], S4p[NP][3], h1p[NP][3], e2p[NP][3];
+  // the values formed in an iteration: assigned only where a point takes
+  // part in a phase (its region and the plane range), and read only there
+  // or, carried, by the same point's later phases, which run on a subset of
+  // the same condition -- so they are initialised once, not per plane (a
+  // per-plane reset cost a register move for every value and plane)
+  T e1c[NP][3], E4c[NP][3], S4c[NP][3], hc[NP][3];
+  T Sxc[NP], Syc[NP], Sxsc[NP], Sysc[NP];
+  T h1c[NP][3], e2c[NP][3];
 #pragma unroll
   for (int p = 0; p < NP; ++p) {
     Sxq[p] = Syq[p] = Sxsq[p] = Sysq[p] = T(0);
+    Sxc[p] = Syc[p] = Sxsc[p] = Sysc[p] = T(0);
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
       hq[p][c] = e1p[p][c] = S4p[p][c] = h1p[p][c] = e2p[p][c] = T(0);
       E4p[p][c] = T(1);
+      e1c[p][c] = S4c[p][c] = hc[p][c] = h1c[p][c] = e2c[p][c] = T(0);
+      E4c[p][c] = T(1);
     }
   }
 
@@ -294,16 +305,8 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
     __syncthreads();
 
     // ---- e^(m+1) of plane k on R1 (same operand order as the single step)
-    T e1c[NP][3], E4c[NP][3], S4c[NP][3], hc[NP][3];
-    T Sxc[NP], Syc[NP], Sxsc[NP], Sysc[NP];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      Sxc[p] = Syc[p] = Sxsc[p] = Sysc[p] = T(0);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        e1c[p][c] = S4c[p][c] = hc[p][c] = T(0);
-        E4c[p][c] = T(1);
-      }
       if (a1[p]) {
         const int j4 = i4[p];
         const bool valid = in1[p] && k >= 0 && k < d.nz;
@@ -350,10 +353,8 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
     // ---- h^(m+3/2) of plane km = k - 1 on R2: e^(m+1) of planes km (the
     // point from registers, its +x / +y neighbours from LDS) and k
     const int km = k - 1;
-    T h1c[NP][3];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      h1c[p][0] = h1c[p][1] = h1c[p][2] = T(0);
       if (km >= k0 - 1 && a2[p]) {
         const T* nq = e1L + hb(km) * 3 * G.N1;
         const int j1 = i1[p];
@@ -380,10 +381,8 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
     // registers, its -x / -y neighbours from LDS) and km - 1, e^(m+1) and
     // the 4-cell sums of plane km from registers; the tile part of planes
     // [k0, k1) is stored
-    T e2c[NP][3];
 #pragma unroll
     for (int p = 0; p < NP; ++p) {
-      e2c[p][0] = e2c[p][1] = e2c[p][2] = T(0);
       if (km >= k0 && a3[p]) {
         const int j1 = i1[p];
         const bool valid = in3[p] && km >= 0 && km < d.nz;
