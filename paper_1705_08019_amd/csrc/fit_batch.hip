@@ -7,10 +7,12 @@
 // fit_step_tile.hpp) of one grid.  Consecutive steps are ordered by the
 // kernel boundary alone: no workgroup ever waits on another, and no atomics
 // are used.  The index of the step within a call lives in device memory and
-// is advanced by a one-thread kernel after every step, so a captured chain of
-// S (step, advance) launches can be replayed as a hipGraph.  The persistent
-// form (k_batch_persist) runs S steps in one cooperative launch instead, with
-// a grid-wide barrier between the steps.
+// is advanced by a one-thread kernel after every single step, so a captured
+// chain of S (step, advance) launches can be replayed as a hipGraph; a chain
+// of pair launches (k_batch2) reads the counters plus each launch's offset in
+// the chain and advances them once per chain.  The persistent form
+// (k_batch_persist) runs S steps in one cooperative launch instead, with a
+// grid-wide barrier between the steps.
 #include "fit_step2_tile.hpp"
 #include "fit_step_tile.hpp"
 
