@@ -19,7 +19,9 @@
  *         (i fastest) holds the voltage of the direction-a primal edge (for e)
  *         or of the dual edge crossing the direction-a primal facet (for h)
  *         anchored at node (i, j, k).  Every edge and facet that is not in a
- *         PEC wall has a slot; all other slots are zero and stay zero.
+ *         PEC wall has a slot; the library writes every other slot as zero
+ *         and never reads one as data (values a caller leaves there, NaN
+ *         included, reach no field, energy or Gram result).
  *         e lives on edges with (for a = x) 1 <= j <= ny-1, 1 <= k <= nz-1
  *         (cyclically for y, z); h on facets with 1 <= i <= nx-1 (for a = x).
  * Boundary. Perfect electric conductor on all six faces (tangential e = 0,
@@ -281,7 +283,8 @@ int fit_probe_reset(fit_grid* g);
  * M = M_eps (which = 0, x are e-fields) or M = M_mu (which = 1, h-fields)
  * of this grid's materials.  X: device pointer, snapshot a at X + a * ld
  * elements, each in the slot layout and the grid's dtype (ld >= 3 nx ny nz);
- * PEC-wall slots carry weight 0.  Computed on the FP64 matrix cores with
+ * PEC-wall and phantom slots carry weight 0 and their values are ignored
+ * (non-finite values there do not reach G).  Computed on the FP64 matrix cores with
  * FP64 accumulation inside a workgroup and compensated summation across
  * workgroups.  G: host, K * K doubles row-major, exactly symmetric.
  * 1 <= K <= 4096.  Synchronises. */
