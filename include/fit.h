@@ -19,9 +19,10 @@
  *         (i fastest) holds the voltage of the direction-a primal edge (for e)
  *         or of the dual edge crossing the direction-a primal facet (for h)
  *         anchored at node (i, j, k).  Every edge and facet that is not in a
- *         PEC wall has a slot; the library writes every other slot as zero
- *         and never reads one as data (values a caller leaves there, NaN
- *         included, reach no field, energy or Gram result).
+ *         PEC wall has a slot; all other slots are zero.  The step kernels
+ *         (single, pair, split, batched) write them as zero and, like the
+ *         energies and the Gram matrix, never read them as data: values a
+ *         caller leaves there, NaN included, reach none of these results.
  *         e lives on edges with (for a = x) 1 <= j <= ny-1, 1 <= k <= nz-1
  *         (cyclically for y, z); h on facets with 1 <= i <= nx-1 (for a = x).
  * Boundary. Perfect electric conductor on all six faces (tangential e = 0,
