@@ -38,6 +38,36 @@ def test_gram_random_snapshots(dtype, K, which):
     np.testing.assert_allclose(G, ref, rtol=0, atol=tol * np.max(np.abs(ref)))
 
 
+@pytest.mark.parametrize("dtype,K,which", [("f32", 70, 0), ("f64", 33, 1), ("f32", 9, 1)])
+def test_gram_aligned_rows_with_a_partial_round(dtype, K, which):
+    """A grid whose snapshot stride is a multiple of 16 bytes takes the
+    16-byte-load path of the Gram kernel (the 37 x 21 x 13 grid above takes
+    the element-wise one); 3 x 28 x 12 x 10 = 10080 rows leave a last
+    workgroup chunk shorter than one round of its four waves, so the partial
+    round is exercised too.  Against the oracle's exactly rounded sums."""
+    from paper_1705_08019_amd import FitGrid
+    nx, ny, nz = 28, 12, 10
+    assert (3 * nx * ny * nz * (4 if dtype == "f32" else 8)) % 16 == 0
+    assert (3 * nx * ny * nz) % 128 != 0
+    rng = np.random.default_rng(100 + K)
+    eps = dielectric_blocks(nx, ny, nz, 4, 3)
+    mu = rng.uniform(1, 4, (nz, ny, nx)) if which == 1 else None
+    ops = oracle_ops((nx, ny, nz), eps=eps, mu=mu)
+    g = FitGrid(nx, ny, nz, dtype)
+    g.set_materials(eps, mu)
+    X = rng.standard_normal((K, 3, nz, ny, nx))
+    if dtype == "f32":
+        X = X.astype(np.float32).astype(np.float64)
+    G = g.gram(torch.tensor(X, device="cuda"), which)
+    conv = edges_from_slots if which == 0 else facets_from_slots
+    M = ops.M_eps if which == 0 else ops.M_mu
+    ref = gram(np.array([conv(ops, x) for x in X]), M)
+    tol = 1e-13 if dtype == "f64" else 1e-6
+    assert np.array_equal(G, G.T)
+    np.testing.assert_allclose(G, ref, rtol=0, atol=tol * np.max(np.abs(ref)))
+    g.close()
+
+
 def test_gram_cavity_modes_closed_form():
     from paper_1705_08019_amd import FitGrid
     nx, ny, nz = 40, 12, 20
