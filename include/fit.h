@@ -467,8 +467,9 @@ int fit_batch_get_tuning(const fit_batch* b, int* tw, int* ty, int* kc, int* ste
  * an odd last step runs singly.  Each grid takes the tile shape of a fixed
  * set (32 x 16, 32 x 18, 40 x 14, 24 x 24) that stages the fewest points
  * for its x / y extent, and its columns are cut into ceil(nz / kc) z-chunks
- * of even length (kc = 0: whole columns); the work items are launched
- * largest first.  Each grid's result stays bitwise identical to fit_step on
+ * of even length (kc = 0: whole columns); the tiles of one z-chunk of one
+ * grid are launched onto one XCD (their shared halo rows stay in its L2), the
+ * longest first, with the work balanced over the XCDs.  Each grid's result stays bitwise identical to fit_step on
  * that grid alone.  FIT_E_INVALID if no pair tile fits the batch's dtype and
  * materials, or a z-plane of a grid spans more than 4 GiB. */
 int fit_batch_set_pair(fit_batch* b, int enable, int kc);

@@ -37,7 +37,7 @@ struct fit_batch {
   // cut into even z-chunks of at most pkc planes (0: whole columns)
   bool pair_on = false;
   int pkc = 0;
-  fit::BatchItem* items2 = nullptr;   // device, P2 entries, largest first
+  fit::BatchItem* items2 = nullptr;   // device, P2 entries, XCD-interleaved
   int P2 = 0;
   size_t lds2 = 0;
   int nthreads2 = 0;
@@ -161,23 +161,31 @@ static double pair_plane_cost(const Dims& d, int q, bool lossy) {
 // The pair layout: each grid's tile shape (the one of kBatchPairShapes that
 // fits the dtype and stages the fewest points for its x / y extent; ties go
 // to the earlier, wider shape) and its z-chunks (the column cut into
-// ceil(nz / pkc) chunks of even length, pkc = 0: whole columns); the item
-// table lists every tile of every grid, largest first (an item's work grows
-// with its chunk length plus the two planes of lag and one of halo, times its
-// tile's staged points), so the dispatcher hands out the long items first;
-// the kernel's threads and LDS are the largest any used shape needs.
+// ceil(nz / pkc) chunks of even length, pkc = 0: whole columns).  An item's
+// work grows with its chunk length plus the two planes of lag and one of
+// halo, times its tile's staged points.
+// The item table is laid out for the dispatcher, which hands workgroup b to
+// XCD b mod 8: the tiles of one z-chunk of one grid (a group, cut into runs
+// of consecutive tiles when it would exceed a 32nd of the whole work) go to
+// one XCD, so the halo rows neighbouring tiles share are read once into that
+// XCD's L2; groups are dealt largest first to the least loaded XCD, and each
+// XCD takes its items largest first, so the short ones fill its tail.  The
+// XCD lists are interleaved into the table (entry 8 i + x = item i of XCD
+// x), the shorter ones padded with empty entries (grid -1).
+// The kernel's threads and LDS are the largest any used shape needs.
 // FIT_E_INVALID if no shape fits the dtype or a grid's plane is too large.
 static int batch_layout2(fit_batch* b) {
   const size_t esz = b->f64 ? 8 : 4;
   std::vector<int> shape((size_t)b->nb);
   std::vector<Tiling> til((size_t)b->nb);
-  struct Item {
-    double cost;
-    int grid, tile;
+  struct Run {
+    double cost, item_cost;
+    int grid, t0, n;
   };
-  std::vector<Item> items;
+  std::vector<Run> groups;
   size_t lds = 0;
   int nthreads = 64;
+  double total = 0.0;
   for (int g = 0; g < b->nb; ++g) {
     const fit_grid* gr = b->grids[g];
     const Dims& d = gr->d;
@@ -203,18 +211,44 @@ static int batch_layout2(fit_batch* b) {
     til[g] = make_tiling(d, ty, kc, tw);
     lds = std::max(lds, step2_lds_bytes(tw, ty, esz, b->lossy_any, false));
     nthreads = std::max(nthreads, step2_threads(tw, ty));
-    const double per_plane = best_cost / ((double)til[g].ntx * til[g].nty);
-    for (int64_t t = 0; t < til[g].blocks(); ++t) {
-      const int kz = (int)(t / ((int64_t)til[g].ntx * til[g].nty));
+    const int per = til[g].ntx * til[g].nty;
+    const double per_plane = best_cost / per;
+    for (int kz = 0; kz < til[g].nkc; ++kz) {
       const int planes = std::min(kc, d.nz - kz * kc);
-      items.push_back({(planes + 3) * per_plane, g, (int)t});
+      const double ic = (planes + 3) * per_plane;
+      groups.push_back({ic * per, ic, g, kz * per, per});
+      total += ic * per;
     }
   }
-  if (items.size() > (size_t)0x7fffffff) return fail(FIT_E_INVALID, "too many work items");
-  std::stable_sort(items.begin(), items.end(),
-                   [](const Item& x, const Item& y) { return x.cost > y.cost; });
-  std::vector<BatchItem> table(items.size());
-  for (size_t r = 0; r < items.size(); ++r) table[r] = BatchItem{items[r].grid, items[r].tile};
+  // cut the groups into runs of at most a 32nd of the work (at least one tile)
+  std::vector<Run> runs;
+  const double cap = total / (kXcds * 4);
+  for (const Run& r : groups) {
+    const int np = std::min(r.n, std::max(1, (int)std::ceil(r.cost / cap - 1e-9)));
+    for (int k = 0, t = r.t0; k < np; ++k) {
+      const int n = r.n / np + (k < r.n % np ? 1 : 0);
+      runs.push_back({n * r.item_cost, r.item_cost, r.grid, t, n});
+      t += n;
+    }
+  }
+  std::stable_sort(runs.begin(), runs.end(), [](const Run& x, const Run& y) {
+    return x.item_cost != y.item_cost ? x.item_cost > y.item_cost : x.cost > y.cost;
+  });
+  std::vector<std::vector<BatchItem>> xl(kXcds);
+  double load[kXcds] = {};
+  for (const Run& r : runs) {
+    int x = 0;
+    for (int k = 1; k < kXcds; ++k)
+      if (load[k] < load[x]) x = k;
+    load[x] += r.cost;
+    for (int t = r.t0; t < r.t0 + r.n; ++t) xl[x].push_back(BatchItem{r.grid, t});
+  }
+  size_t len = 0;
+  for (const auto& l : xl) len = std::max(len, l.size());
+  if (len * kXcds > (size_t)0x7fffffff) return fail(FIT_E_INVALID, "too many work items");
+  std::vector<BatchItem> table(len * kXcds, BatchItem{-1, 0});
+  for (int x = 0; x < kXcds; ++x)
+    for (size_t i = 0; i < xl[x].size(); ++i) table[i * kXcds + x] = xl[x][i];
   dev_free(reinterpret_cast<void*&>(b->items2));
   b->P2 = 0;
   int rc = dev_alloc(reinterpret_cast<void**>(&b->items2), table.size() * sizeof(BatchItem),

@@ -90,9 +90,9 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs<T> B) {
 // Two steps of every grid: one workgroup per item of the pair item table,
 // i.e. one tile (with its z-chunk) of one grid, run by the tile body of the
 // single-grid two-step kernel in the grid's compile-time tile shape.  The
-// table lists the items largest first and is read in launch order (no XCD
-// remapping), so the dispatcher hands out the longest items first and the
-// short ones fill the tail.  The step index and buffer set of launch
+// table is read in launch order: it is laid out so that the dispatcher's
+// round-robin over the XCDs gives each XCD whole groups of neighbouring
+// tiles, longest first (entries of grid -1 are padding).  The step index and buffer set of launch
 // launch_off of a captured chain come from the counters plus its offset, so
 // the counters are advanced once per chain.  Budgets as the single-grid
 // kernel's one-point compile-time variants (at most 768 threads).
@@ -124,6 +124,7 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 3))) void k_batch2(Batch
   extern __shared__ __align__(16) unsigned char smem_raw[];
   T* sm = reinterpret_cast<T*>(smem_raw);
   const BatchItem it = B.items2[blockIdx.x];
+  if (it.grid < 0) return;   // padding of a shorter XCD list
   const BatchGrid<T>& G = B.grids[it.grid];
   const int64_t sg = B.fixed_parity ? 0 : B.ctl->step_base + 2 * (int64_t)B.launch_off;
   const int p = (int)((G.par0 + (B.fixed_parity ? 0 : B.ctl->flip + B.launch_off)) & 1);

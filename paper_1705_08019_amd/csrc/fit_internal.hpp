@@ -39,9 +39,10 @@ struct Probe {
 // each XCD a contiguous range of logical work items (tiles in x-fastest, then
 // y, then z-chunk order) so that halo rows shared by neighbouring tiles stay
 // in one XCD's L2.  bid = hardware workgroup index, nb = grid size.
+constexpr int kXcds = 8;
 __device__ __forceinline__ int64_t xcd_remap(int64_t bid, int64_t nb) {
-  const int64_t q = nb / 8, r = nb % 8;
-  const int64_t x = bid % 8, l = bid / 8;
+  const int64_t q = nb / kXcds, r = nb % kXcds;
+  const int64_t x = bid % kXcds, l = bid / kXcds;
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
 }
 
@@ -305,7 +306,7 @@ template <typename T>
 struct BatchArgs {
   const BatchGrid<T>* grids;
   const int* item_grid;   // grid of each item of a step (P entries)
-  const BatchItem* items2; // pair launches: the items, largest first (P entries)
+  const BatchItem* items2; // pair launches: the items, XCD-interleaved (P entries)
   BatchCtl* ctl;
   int nb;
   int P;                  // items (workgroups) per step
