@@ -869,7 +869,7 @@ int fit_batch_autotune(fit_batch* b, const double* dt_in, int reps, int* tw, int
   if (!rc && !rc2 && !b->persist) {   // the persistent form runs single steps
     float best_pair = 1e30f;
     int bpkc = -1;
-    for (int pk : {8, 16, 24, 32, 48, 0}) {
+    for (int pk : {6, 8, 12, 16, 24, 32, 0}) {
       b->pkc = pk;
       if (batch_layout2(b) != FIT_OK) break;   // the pair tile does not fit this batch
       float ms = 0.f;

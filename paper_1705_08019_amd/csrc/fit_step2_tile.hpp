@@ -26,9 +26,11 @@
 // are needed by the first e-update alone (the second reuses its sums), so
 // h^(m+1/2), eps and sigma are staged for one plane.
 // Iteration k forms e^(m+1) of plane k, h^(m+3/2) of plane k-1, e^(m+2) of
-// plane k-1 and h^(m+5/2) of plane k-2, for k = k0-1 .. k1+1, with three
-// barriers (the last h-update reads the e^(m+2) plane written one iteration
-// earlier, double-buffered, so it follows the second e-update without one).
+// plane k-1 and h^(m+5/2) of plane k-2, for k = k0-1 .. k1+1, with two
+// barriers: one after staging, one before the second e-update.  Each
+// h-update reads from LDS only the e plane formed one iteration earlier
+// (double-buffered; the newer plane comes from the point's own registers),
+// so neither follows its e-update with a barrier.
 // The halo rows and columns are recomputed by every tile that needs them
 // with the same contraction-pinned point functions and operand order as the
 // single-step kernels, so the result is bitwise that of two single steps.
@@ -348,7 +350,9 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
         out[2 * G.N1 + i1[p]] = e1c[p][2];
       }
     }
-    __syncthreads();
+    // (no barrier: the h-update below reads e^(m+1) of plane k - 1 alone from
+    // LDS, the other buffer, written before the barriers of the previous
+    // iteration; plane k enters through the point's own registers)
 
     // ---- h^(m+3/2) of plane km = k - 1 on R2: e^(m+1) of planes km (the
     // point from registers, its +x / +y neighbours from LDS) and k
