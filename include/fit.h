@@ -503,7 +503,8 @@ int fit_batch_get_persistent(const fit_batch* b, int* enable, int* workgroups, i
 
 /* Autotuner: time candidate (tw, ty, kc), row-packed ones included, with
  * `reps` single-step launches each (state unchanged) and keep the fastest;
- * then time step pairs (kc 16, 8, 6, 4) and switch them on when a pair takes
+ * then time step pairs (kc 6, 8, 12, 16, 24, 32 and whole columns) and
+ * switch them on when a pair takes
  * less than 98 % of two single steps (ms_best is then half a pair).
  * dt: host array of nb step sizes. */
 int fit_batch_autotune(fit_batch* b, const double* dt, int reps, int* tw, int* ty, int* kc,
