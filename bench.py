@@ -325,7 +325,7 @@ def form_batched(plain_steps: int = 400, persistent: bool = True):
             "plain_steps_timed": plain_steps, "batched_over_plain": round(gb / gp, 3),
             "tile": [tw, ty, kc], "pair_kc": pair_kc if pair_on else None,
             "persistent": persist,
-            "launch": ("one launch per pair of steps of all grids (per-grid pair tiles, largest items first), hipGraph "
+            "launch": ("one launch per pair of steps of all grids (per-grid pair tiles, the tiles of one z-chunk of a grid on one XCD, longest first), hipGraph "
                        "chunks of 8 pairs" if pair_on else
                        "one launch per step of all grids, hipGraph chunks of 16")}
 
