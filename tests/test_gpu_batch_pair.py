@@ -54,7 +54,7 @@ def test_batch_pairs_equal_plain(dtype, which):
 def test_batch_pair_tiles_per_grid(dtype):
     """Each grid takes its own pair tile shape (the one staging the fewest
     points for its x / y extent) and z-chunks of even length; the batch of
-    mixed shapes, launched largest item first, stays bitwise equal to plain
+    mixed shapes, its items laid out over the XCDs, stays bitwise equal to plain
     per-grid steps through graph chunks (per-launch offsets, one counter
     advance per chunk), direct launches and a last single step."""
     import math
@@ -86,6 +86,41 @@ def test_batch_pair_tiles_per_grid(dtype):
     _plain(gp, dts, 18)
     _assert_equal(_fields(gb), _fields(gp))
     assert all(g.step_index == 39 for g in gb)
+    b.close()
+
+
+def _specs(sizes, seed):
+    from fit_workloads.configs import WorkloadSpec, dielectric_blocks, random_source
+    rng = np.random.default_rng(seed)
+    return [WorkloadSpec(name=f"xcd{n}", nx=nx, ny=ny, nz=nz, dtype="f32", nsteps=0,
+                         eps_r=dielectric_blocks(nx, ny, nz, 4, seed + n), sigma=None,
+                         source=random_source(nx, ny, nz, rng))
+            for n, (nx, ny, nz) in enumerate(sizes)]
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+@pytest.mark.parametrize("case", ["one-grid", "one-tile", "uneven"])
+def test_batch_pair_xcd_table_edge_cases(dtype, case):
+    """The pair item table is dealt over the 8 XCDs in groups (the tiles of
+    one z-chunk of one grid), cut into runs when a group exceeds a 32nd of
+    the work, and padded with empty entries: a single multi-tile grid (one
+    group per chunk, cut into runs), a single one-tile grid (one item, seven
+    empty entries) and a large grid beside a tiny one all stay bitwise equal
+    to plain per-grid steps, with whole columns and short chunks."""
+    from paper_1705_08019_amd import FitBatch
+    sizes = {"one-grid": [(70, 50, 30)], "one-tile": [(10, 9, 8)],
+             "uneven": [(96, 80, 40), (7, 6, 5)]}[case]
+    specs = _specs(sizes, 300)
+    gb, dts = _make(specs, dtype, lossy_every=2)
+    gp, _ = _make(specs, dtype, lossy_every=2)
+    b = FitBatch(gb)
+    for kc, n in ((0, 9), (7, 10), (3, 8)):
+        b.set_pair(True, kc)
+        print(f"xcd table {case} {dtype}: kc {kc}", flush=True)
+        b.step(n, dts, use_graph=(kc == 7))
+        _plain(gp, dts, n)
+        _assert_equal(_fields(gb), _fields(gp))
+    assert all(g.step_index == 27 for g in gb)
     b.close()
 
 
