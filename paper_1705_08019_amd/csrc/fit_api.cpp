@@ -325,7 +325,8 @@ int step_fused_io(fit_grid* g, double dt, const T* e0, const T* h0, T* e1, T* h1
   const bool have_row = tr_this && g->trace_rows < g->trace_cap;
   if (tr_this && !have_row) g->trace_dropped++;
   const bool probe = g->probe.on != 0;
-  const bool energy = have_row || tr_next;
+  // the step before a trace row forms only the h cross term of that row
+  const int energy = have_row ? kEnergyAll : tr_next ? kEnergyHCross : kEnergyNone;
   const Dims& d = g->d;
   SArgs<T> a;
   for (int c = 0; c < 3; ++c) {

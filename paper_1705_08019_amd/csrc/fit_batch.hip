@@ -82,9 +82,9 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs<T> B) {
   const int tyi = rr % G.t.nty;
   const int kz = rr / G.t.nty;
   if (G.lossy)
-    step_tile<T, true, false, false>(a, tx, tyi, kz, sm, nullptr, nullptr);
+    step_tile<T, true, kEnergyNone, false>(a, tx, tyi, kz, sm, nullptr, nullptr);
   else
-    step_tile<T, false, false, false>(a, tx, tyi, kz, sm, nullptr, nullptr);
+    step_tile<T, false, kEnergyNone, false>(a, tx, tyi, kz, sm, nullptr, nullptr);
 }
 
 // Two steps of every grid: one workgroup per item of the pair item table,
@@ -236,9 +236,9 @@ __global__ __launch_bounds__(1024) void k_batch_persist(BatchArgs<T> B, int S) {
       const int tx = t % G.t.ntx;
       const int rr = t / G.t.ntx;
       if (G.lossy)
-        step_tile<T, true, false, false>(a, tx, rr % G.t.nty, rr / G.t.nty, sm, nullptr, nullptr);
+        step_tile<T, true, kEnergyNone, false>(a, tx, rr % G.t.nty, rr / G.t.nty, sm, nullptr, nullptr);
       else
-        step_tile<T, false, false, false>(a, tx, rr % G.t.nty, rr / G.t.nty, sm, nullptr, nullptr);
+        step_tile<T, false, kEnergyNone, false>(a, tx, rr % G.t.nty, rr / G.t.nty, sm, nullptr, nullptr);
       __syncthreads();   // the next item restages the LDS
     }
     grid_barrier(B.ctl, (unsigned)s + 1u, gridDim.x);

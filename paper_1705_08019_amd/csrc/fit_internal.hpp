@@ -55,6 +55,9 @@ enum { PE_EE_MM = 0, PE_EE_MM1 = 1, PE_EE_M1M1 = 2, PE_LOSS = 3, PE_SRC = 4, PE_
 enum { PH_HH_CC = 0, PH_HH_CN = 1, PH_HH_NN = 2 };
 // Fused-step partial term slots: the E slots above, then the H terms.
 enum { PS_HH_CC = 6, PS_HH_CN = 7, PS_HH_NN = 8 };
+// Energy modes of the fused step: none, every term, or only the h cross
+// term <h^(m+1/2), h^(m+3/2)> (the step before a trace row needs no other).
+enum { kEnergyNone = 0, kEnergyAll = 1, kEnergyHCross = 2 };
 
 template <typename T>
 struct EArgs {
@@ -202,7 +205,7 @@ size_t step_lds_bytes(int ty, size_t esz, bool lossy, int tw = 64, int nu_planes
 int step_blocks_per_cu(int ty, size_t esz, bool lossy, int tw = 64);
 
 template <typename T>
-hipError_t launch_step(const SArgs<T>& a, bool lossy, bool energy, bool probe, hipStream_t s);
+hipError_t launch_step(const SArgs<T>& a, bool lossy, int energy, bool probe, hipStream_t s);
 
 // Row weights W (3 n doubles) of the Gram form: M_eps of the edges (which 0,
 // gw = g_a / 4) or M_mu of the facets (which 1, gw = gf2_a) (fit_gram.hip).

@@ -23,7 +23,7 @@ size_t step_lds_bytes(int ty, size_t esz, bool lossy, int tw, int nu_planes) {
   return esz * (3 * 3 * RP + 3 * RP + (lossy ? 3 * RP : 0) + 2 * 3 * EP + 3 * (size_t)nu_planes);
 }
 
-template <typename T, bool LOSSY, bool ENERGY, bool PROBE, bool NU>
+template <typename T, bool LOSSY, int ENERGY, bool PROBE, bool NU>
 __global__ __launch_bounds__(1024) void k_step(SArgs<T> A) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   const int64_t lt = xcd_remap(blockIdx.x, gridDim.x);
@@ -32,7 +32,8 @@ __global__ __launch_bounds__(1024) void k_step(SArgs<T> A) {
   const int tyi = (int)(rr % A.t.nty);
   const int kz = (int)(rr / A.t.nty);
   step_tile<T, LOSSY, ENERGY, PROBE, NU>(A, tx, tyi, kz, reinterpret_cast<T*>(smem_raw),
-                                         ENERGY ? A.part + (int64_t)blockIdx.x * kPartTerms
+                                         ENERGY != kEnergyNone
+                                             ? A.part + (int64_t)blockIdx.x * kPartTerms
                                                 : nullptr,
                                          PROBE ? A.pacc + 2 * (int64_t)blockIdx.x : nullptr);
 }
@@ -42,10 +43,10 @@ static int occupancy_of(int ty, int tw) {
   int nb = 0;
   const size_t lds = step_lds_bytes(ty, sizeof(T), LOSSY, tw);
   if (lds > 64 * 1024)
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step<T, LOSSY, false, false, false>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step<T, LOSSY, kEnergyNone, false, false>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
-          &nb, reinterpret_cast<const void*>(&k_step<T, LOSSY, false, false, false>), tw * ty, lds) !=
+          &nb, reinterpret_cast<const void*>(&k_step<T, LOSSY, kEnergyNone, false, false>), tw * ty, lds) !=
       hipSuccess) {
     (void)hipGetLastError();
     return 0;
@@ -60,7 +61,7 @@ int step_blocks_per_cu(int ty, size_t esz, bool lossy, int tw) {
 }
 
 template <typename T>
-hipError_t launch_step(const SArgs<T>& a, bool lossy, bool energy, bool probe, hipStream_t s) {
+hipError_t launch_step(const SArgs<T>& a, bool lossy, int energy, bool probe, hipStream_t s) {
   const dim3 blk(a.t.tw, a.t.ty), grd((unsigned)a.t.blocks());
   const bool nu = a.nsq[0] != nullptr;
   const size_t lds = step_lds_bytes(a.t.ty, sizeof(T), lossy, a.t.tw, nu ? a.t.kc + 1 : 0);
@@ -80,19 +81,29 @@ hipError_t launch_step(const SArgs<T>& a, bool lossy, bool energy, bool probe, h
     if (nu) FIT_S(L, E, P, true);    \
     else FIT_S(L, E, P, false);      \
   } while (0)
-  if (lossy) {
-    if (energy) { if (probe) FIT_SN(true, true, true); else FIT_SN(true, true, false); }
-    else { if (probe) FIT_SN(true, false, true); else FIT_SN(true, false, false); }
-  } else {
-    if (energy) { if (probe) FIT_SN(false, true, true); else FIT_SN(false, true, false); }
-    else { if (probe) FIT_SN(false, false, true); else FIT_SN(false, false, false); }
-  }
+#define FIT_SP(L, E)                  \
+  do {                                \
+    if (probe) FIT_SN(L, E, true);    \
+    else FIT_SN(L, E, false);         \
+  } while (0)
+#define FIT_SE(L)                                        \
+  do {                                                   \
+    if (energy == kEnergyAll) FIT_SP(L, kEnergyAll);     \
+    else if (energy == kEnergyHCross) FIT_SP(L, kEnergyHCross); \
+    else FIT_SP(L, kEnergyNone);                         \
+  } while (0)
+  if (energy != kEnergyNone && energy != kEnergyAll && energy != kEnergyHCross)
+    return hipErrorInvalidValue;
+  if (lossy) FIT_SE(true);
+  else FIT_SE(false);
+#undef FIT_SE
+#undef FIT_SP
 #undef FIT_SN
 #undef FIT_S
   return hipGetLastError();
 }
 
-template hipError_t launch_step<float>(const SArgs<float>&, bool, bool, bool, hipStream_t);
-template hipError_t launch_step<double>(const SArgs<double>&, bool, bool, bool, hipStream_t);
+template hipError_t launch_step<float>(const SArgs<float>&, bool, int, bool, hipStream_t);
+template hipError_t launch_step<double>(const SArgs<double>&, bool, int, bool, hipStream_t);
 
 }  // namespace fit

@@ -33,13 +33,13 @@ constexpr int kRingPerThread = 3;
 
 // One tw x ty column tile of one z-chunk: tile coordinates (tx, tyi, kz);
 // sm = dynamic LDS of step_lds_bytes(); part = this tile's partial-sum row
-// (ENERGY only); prow = this workgroup's probe accumulator row (PROBE only),
+// (ENERGY: kEnergyAll every term, kEnergyHCross only the h cross term); prow = this workgroup's probe accumulator row (PROBE only),
 // to which the step adds pscale times its probe term.  The workgroup's threads (any 2-D shape, a multiple
 // of 64 and at least tw ty of them, also at least tw + ty + 1) are numbered
 // linearly; thread t < tw ty owns column (t mod tw, t div tw) of the tile, the
 // rest only help to stage planes (row-packed tiles of the batched kernel,
 // whose tile width is a grid's whole x extent, leave such threads over).
-template <typename T, bool LOSSY, bool ENERGY, bool PROBE, bool NU = false>
+template <typename T, bool LOSSY, int ENERGY, bool PROBE, bool NU = false>
 __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, int kz, T* sm,
                                           double* part, double* prow) {
   const Dims d = A.d;
@@ -231,7 +231,7 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
     double gez = A.ge[2];
     if (NU && plane) {
       kbz = zL[k - k0];
-      if (ENERGY || PROBE) gez = 0.25 / A.nsq[2][k];
+      if (ENERGY == kEnergyAll || PROBE) gez = 0.25 / A.nsq[2][k];
     }
     if (act) {
       T exn = 0, eyn = 0, ezn = 0, E4x, E4y, E4z, S4x, S4y, S4z;
@@ -245,7 +245,7 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
         gst(A.e1[0], g, exn);
         gst(A.e1[1], g, eyn);
         gst(A.e1[2], g, ezn);
-        if (ENERGY) {
+        if (ENERGY == kEnergyAll) {
           const double mx = gex * (double)E4x, my = gey * (double)E4y, mz = gez * (double)E4z;
           // e^m of dead edges (PEC walls, phantom slots) is selected away, not
           // multiplied by a zero weight: whatever such a slot holds stays out
@@ -312,7 +312,7 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
         kdx = kdxb * rz;
         kdy = kdyb * rz;
         kdz = kdzb * zL[2 * zp + km - k0];
-        if (ENERGY) {
+        if (ENERGY != kEnergyNone) {
           gfx = hfx * A.nrw[2][km];
           gfy = hfy * A.nrw[2][km];
           gfz = hfz * A.ndl[2][km];
@@ -326,15 +326,17 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
       gst(A.h1[0], gm, hxn);
       gst(A.h1[1], gm, hyn);
       gst(A.h1[2], gm, hzn);
-      if (ENERGY) {
+      if (ENERGY != kEnergyNone) {
         const double wx = i > 0 ? 1.0 / (gfx * (double)A.imu2) : 0.0;
         const double wy = j > 0 ? 1.0 / (gfy * (double)A.imu2) : 0.0;
         const double wz = km > 0 ? 1.0 / (gfz * (double)A.imu2) : 0.0;
         const double ox = i > 0 ? (double)hxo : 0.0, oy = j > 0 ? (double)hyo : 0.0;
         const double oz = km > 0 ? (double)hzo : 0.0, nx_ = hxn, ny_ = hyn, nz_ = hzn;
-        nadd_s(acc[PS_HH_CC], cmp[PS_HH_CC], wx * ox * ox + wy * oy * oy + wz * oz * oz);
+        if (ENERGY == kEnergyAll)
+          nadd_s(acc[PS_HH_CC], cmp[PS_HH_CC], wx * ox * ox + wy * oy * oy + wz * oz * oz);
         nadd_s(acc[PS_HH_CN], cmp[PS_HH_CN], wx * ox * nx_ + wy * oy * ny_ + wz * oz * nz_);
-        nadd_s(acc[PS_HH_NN], cmp[PS_HH_NN], wx * nx_ * nx_ + wy * ny_ * ny_ + wz * nz_ * nz_);
+        if (ENERGY == kEnergyAll)
+          nadd_s(acc[PS_HH_NN], cmp[PS_HH_NN], wx * nx_ * nx_ + wy * ny_ * ny_ + wz * nz_ * nz_);
       }
     }
     // rotate ring buffers: plane k becomes k-1; the oldest buffer takes k+1
@@ -343,8 +345,9 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
     bc = nb_;
   }
 
-  if (ENERGY || PROBE) {
-    // block sum of the 9 terms, fixed order: per wave, then over waves
+  if (ENERGY != kEnergyNone || PROBE) {
+    // block sum of the 9 terms, fixed order: per wave, then over waves (the
+    // terms a mode does not form are zero)
     __shared__ double red[16][9];
     const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
     double v[9];
@@ -364,7 +367,7 @@ __device__ __forceinline__ void step_tile(const SArgs<T>& A, int tx, int tyi, in
     if (tid < 9) {
       double s = 0.0;
       for (int w = 0; w < nw; ++w) s += red[w][tid];
-      if (ENERGY) part[tid] = s;
+      if (ENERGY != kEnergyNone) part[tid] = s;
       if (PROBE && tid == PE_PROBE) {
         double ps = prow[0], pc = prow[1];
         nadd_s(ps, pc, A.pscale * s);
