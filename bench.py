@@ -271,32 +271,47 @@ def form_batched(plain_steps: int = 400, persistent: bool = True):
     torch.cuda.synchronize()
     ms_b = ev[0].elapsed_time(ev[1])
     # the persistent form: 16 steps of every grid per cooperative launch with a
-    # grid-wide barrier between the steps, the launch replayed from a hipGraph
-    persist = None
-    try:
-        if not persistent:
-            raise RuntimeError("skipped (--no-persistent)")
-        b.set_pair(False)
-        ty_, kc_, _, _, tw_ = b.get_tuning()
-        b.set_tuning(ty_, kc_, 16, tw_)           # the autotuned tile, 16 steps per launch
-        b.set_persistent(True)
-        b.step(32, dts)
-        torch.cuda.synchronize()
-        ev[0].record()
-        b.step(nsteps, dts)
-        ev[1].record()
-        torch.cuda.synchronize()
-        ms_ps = ev[0].elapsed_time(ev[1])
-        on, nwg, cap, failed = b.get_persistent()
-        gps = cells * nsteps / (ms_ps / 1e3) / 1e9
-        persist = {"Gcell_updates_per_s": round(gps, 3), "workgroups": nwg,
-                   "items_per_step": b.get_tuning()[3], "steps_per_launch": 16,
-                   "tile": [tw_, ty_, kc_],
-                   "captured_in_graph": cap, "barrier_gave_up": failed,
-                   "alg_GBs": round(B_LAUNCH * gps, 1),
-                   "frac": round(B_LAUNCH * gps / PEAK_HBM_GBS, 4)}
-    except Exception as ex:   # reported, not hidden
-        persist = {"error": f"{type(ex).__name__}: {ex}"}
+    # grid-wide barrier between the steps (single steps) or between the pairs
+    # of steps (8 pairs per launch), the launch replayed from a hipGraph
+    def persistent_form(pairs):
+        try:
+            if not persistent:
+                raise RuntimeError("skipped (--no-persistent)")
+            b.set_persistent(False)
+            if pairs:
+                b.set_pair(True, pair_kc if pair_on else 6)
+            else:
+                b.set_pair(False)
+            ty_, kc_, _, _, tw_ = b.get_tuning()
+            b.set_tuning(ty_, kc_, 16, tw_)           # the autotuned tile, 16 steps per launch
+            b.set_persistent(True)
+            b.step(32, dts)
+            torch.cuda.synchronize()
+            ev[0].record()
+            b.step(nsteps, dts)
+            ev[1].record()
+            torch.cuda.synchronize()
+            ms_ps = ev[0].elapsed_time(ev[1])
+            on, nwg, cap, failed = b.get_persistent()
+            gps = cells * nsteps / (ms_ps / 1e3) / 1e9
+            bcs = B_LAUNCH / 2 if pairs else B_LAUNCH
+            out = {"Gcell_updates_per_s": round(gps, 3), "workgroups": nwg,
+                   "steps_per_launch": 16, "captured_in_graph": cap, "barrier_gave_up": failed,
+                   "alg_bytes_per_cell_update": bcs,
+                   "alg_GBs": round(bcs * gps, 1), "frac": round(bcs * gps / PEAK_HBM_GBS, 4)}
+            if pairs:
+                out["pair_kc"] = b.get_pair()[1]
+                out["launch"] = ("8 pairs of steps of all grids per cooperative launch, grid "
+                                 "barrier after every pair, each XCD's workgroups walking its "
+                                 "own list of the pair item table")
+            else:
+                out.update({"items_per_step": b.get_tuning()[3], "tile": [tw_, ty_, kc_]})
+            return out
+        except Exception as ex:   # reported, not hidden
+            return {"error": f"{type(ex).__name__}: {ex}"}
+
+    persist = persistent_form(False)
+    persist_pairs = persistent_form(True)
     b.close()
     for g in grids:
         g.close()
@@ -324,7 +339,7 @@ def form_batched(plain_steps: int = 400, persistent: bool = True):
             "plain_per_grid_Gcell_updates_per_s": round(gp, 3),
             "plain_steps_timed": plain_steps, "batched_over_plain": round(gb / gp, 3),
             "tile": [tw, ty, kc], "pair_kc": pair_kc if pair_on else None,
-            "persistent": persist,
+            "persistent": persist, "persistent_pairs": persist_pairs,
             "launch": ("one launch per pair of steps of all grids (per-grid pair tiles, the tiles of one z-chunk of a grid on one XCD, longest first), hipGraph "
                        "chunks of 8 pairs" if pair_on else
                        "one launch per step of all grids, hipGraph chunks of 16")}

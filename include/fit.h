@@ -488,9 +488,13 @@ int fit_batch_get_pair_tile(const fit_batch* b, int g, int* tw, int* ty, int* kc
  * at a grid-wide barrier before the next step.  The S-step launch is
  * captured in a hipGraph and replayed for whole chunks (use_graph != 0; if
  * the runtime cannot capture a cooperative launch, chunks are launched
- * directly), the remainder runs as one launch.  Single steps only (pairs
- * are not used while it is on).  Each grid's result stays bitwise identical
- * to fit_step on that grid alone.  The barrier polls a device counter; a
+ * directly), the remainder runs as one launch.  With step pairs on
+ * (fit_batch_set_pair), a launch runs S / 2 pairs instead: its workgroups (a
+ * multiple of 8, as many as the device holds at once) take entries w,
+ * w + G, ... of the pair item table, whose entry r lies on the XCD of
+ * workgroup r, and meet at the barrier after every pair; an odd last step
+ * runs through the single-step launch.  Each grid's result stays bitwise
+ * identical to fit_step on that grid alone.  The barrier polls a device counter; a
  * poll that waits longer than about half a second gives up and flags the
  * call (the launch then ends with wrong fields instead of hanging).  get:
  * enable, the workgroups of the launch, whether the launch is captured, and

@@ -112,6 +112,25 @@ static int persist_workgroups(const fit_batch* b) {
   return (int)std::min<int64_t>((int64_t)per_cu * cus, b->P);
 }
 
+// Resident workgroups of the persistent pair kernel for the pair layout, a
+// multiple of 8 (entry r of the pair item table belongs to XCD r mod 8, and
+// so does workgroup r of a launch) and at most the table's length; 0 if it
+// cannot run.
+static int persist2_workgroups(const fit_batch* b) {
+  const size_t esz = b->f64 ? 8 : 4;
+  const int per_cu = batch2_persist_blocks_per_cu(esz, b->nthreads2, b->lds2);
+  if (per_cu <= 0 || b->P2 <= 0) return 0;
+  int cus = 256, dev = 0;
+  if (hipGetDevice(&dev) == hipSuccess) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0)
+      cus = v;
+  }
+  (void)hipGetLastError();
+  const int64_t n = std::min<int64_t>((int64_t)per_cu * cus, b->P2);
+  return (int)(n / kXcds * kXcds);
+}
+
 // Build the item table, the workgroup shape and the LDS size for the current
 // tiling.  FIT_E_INVALID (nothing changed) if a grid's tile needs more LDS
 // than a workgroup can have.
@@ -377,11 +396,69 @@ static BatchArgs<T> batch_args_pair(fit_batch* b, int fixed) {
   return a;
 }
 
-// nsteps steps of every grid through the persistent kernel: S-step launches
-// (a captured one replayed per chunk when the graph is wanted and capture
-// works), then one launch of the remainder.
+// nsteps steps of every grid through the persistent kernels: with step pairs
+// on, launches of S / 2 pairs (S = steps per graph) and an odd last step
+// through the single-step kernel; else S-step launches.  A captured launch
+// is replayed per chunk when the graph is wanted and capture works, then one
+// launch takes the remainder.
+template <typename T>
+static int batch_run_persist_pairs(fit_batch* b, int64_t nsteps, int use_graph) {
+  const BatchArgs<T> a2 = batch_args_pair<T>(b, 0);
+  const int nwg2 = persist2_workgroups(b);
+  if (nwg2 <= 0)
+    return fail(FIT_E_INVALID, "the persistent pair kernel cannot hold a workgroup of this tile");
+  hipError_t e = launch_batch_set_base(b->ctl, 0, b->s);
+  if (e != hipSuccess) return hip_fail(e, "batch step counter");
+  const int64_t npair = nsteps / 2, nsingle = nsteps & 1;
+  const int S2 = std::max(1, b->steps_per_graph / 2);
+  int64_t done = 0;
+  if (use_graph && b->persist_graph && npair >= S2) {
+    if (!b->exec || b->graph_S != S2 || !b->graph_pairs) {
+      batch_drop_graph(b);
+      e = hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) return hip_fail(e, "graph capture begin");
+      const hipError_t el = launch_batch2_persist<T>(a2, nwg2, S2, b->s);
+      e = hipStreamEndCapture(b->s, &b->graph);
+      if (el == hipSuccess && e == hipSuccess)
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+      if (el != hipSuccess || e != hipSuccess) {   // capture of the cooperative launch failed
+        (void)hipGetLastError();
+        batch_drop_graph(b);
+        b->persist_graph = false;
+      } else {
+        b->graph_S = S2;
+        b->graph_pairs = true;
+      }
+    }
+    if (b->exec) {
+      for (; done + S2 <= npair; done += S2) {
+        e = hipGraphLaunch(b->exec, b->s);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+      }
+    }
+  }
+  while (done < npair) {
+    const int n = (int)std::min<int64_t>(npair - done, use_graph ? S2 : (int64_t)1 << 30);
+    e = launch_batch2_persist<T>(a2, nwg2, n, b->s);
+    if (e != hipSuccess) return hip_fail(e, "persistent pair launch");
+    done += n;
+  }
+  if (nsingle) {
+    e = launch_batch_persist<T>(batch_args_host<T>(b, 0), b->persist_nwg, 1, b->s);
+    if (e != hipSuccess) return hip_fail(e, "persistent batch launch");
+  }
+  for (int g = 0; g < b->nb; ++g) {
+    fit_grid* gr = b->grids[g];
+    if ((npair + nsingle) & 1) swap_sets(gr);
+    gr->m += nsteps;
+    gr->smvp += 2 * nsteps;
+  }
+  return FIT_OK;
+}
+
 template <typename T>
 static int batch_run_persist(fit_batch* b, int64_t nsteps, int use_graph) {
+  if (b->pair_on && b->P2 > 0 && nsteps >= 2) return batch_run_persist_pairs<T>(b, nsteps, use_graph);
   const BatchArgs<T> a = batch_args_host<T>(b, 0);
   const int nwg = b->persist_nwg;
   hipError_t e = launch_batch_set_base(b->ctl, 0, b->s);
@@ -721,7 +798,8 @@ int fit_batch_get_persistent(const fit_batch* b, int* enable, int* workgroups, i
                              int* barrier_failed) {
   if (!b) return fail(FIT_E_INVALID, "null batch");
   if (enable) *enable = b->persist ? 1 : 0;
-  if (workgroups) *workgroups = b->persist ? b->persist_nwg : 0;
+  if (workgroups)
+    *workgroups = !b->persist ? 0 : (b->pair_on && b->P2 > 0) ? persist2_workgroups(b) : b->persist_nwg;
   if (captured) *captured = (b->persist && b->persist_graph) ? 1 : 0;
   if (barrier_failed) {
     BatchCtl c{};
@@ -866,7 +944,7 @@ int fit_batch_autotune(fit_batch* b, const double* dt_in, int reps, int* tw, int
   // the device)
   b->pair_on = false;
   const int pkc_prev = b->pkc;
-  if (!rc && !rc2 && !b->persist) {   // the persistent form runs single steps
+  if (!rc && !rc2) {   // (timed as dispatcher-fed launches; the persistent form follows)
     float best_pair = 1e30f;
     int bpkc = -1;
     for (int pk : {6, 8, 12, 16, 24, 32, 0}) {

@@ -118,16 +118,13 @@ __device__ __forceinline__ void batch2_tile(const S2Args<T>& a, int shape, int t
   }
 }
 
+// Two steps of item `it` (not padding) from step index sg with buffer-set
+// offset flip (the grid's own parity added).
 template <typename T>
-__global__ __launch_bounds__(768)
-__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 3))) void k_batch2(BatchArgs<T> B) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  T* sm = reinterpret_cast<T*>(smem_raw);
-  const BatchItem it = B.items2[blockIdx.x];
-  if (it.grid < 0) return;   // padding of a shorter XCD list
+__device__ __forceinline__ void batch2_item(const BatchArgs<T>& B, const BatchItem it, int64_t sg,
+                                            int flip, T* sm) {
   const BatchGrid<T>& G = B.grids[it.grid];
-  const int64_t sg = B.fixed_parity ? 0 : B.ctl->step_base + 2 * (int64_t)B.launch_off;
-  const int p = (int)((G.par0 + (B.fixed_parity ? 0 : B.ctl->flip + B.launch_off)) & 1);
+  const int p = (int)((G.par0 + flip) & 1);
   S2Args<T> a;
   const int64_t n = G.d.n;
   for (int c = 0; c < 3; ++c) {
@@ -152,6 +149,18 @@ __attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 3))) void k_batch2(Batch
     batch2_tile<T, true>(a, G.s2shape, it.tile, sm);
   else
     batch2_tile<T, false>(a, G.s2shape, it.tile, sm);
+}
+
+template <typename T>
+__global__ __launch_bounds__(768)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 3))) void k_batch2(BatchArgs<T> B) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const BatchItem it = B.items2[blockIdx.x];
+  if (it.grid < 0) return;   // padding of a shorter XCD list
+  const int64_t sg = B.fixed_parity ? 0 : B.ctl->step_base + 2 * (int64_t)B.launch_off;
+  const int flip = B.fixed_parity ? 0 : B.ctl->flip + B.launch_off;
+  batch2_item<T>(B, it, sg, flip, sm);
 }
 
 // Persistent form: S steps of every grid in ONE launch.  Workgroup w runs
@@ -249,6 +258,76 @@ __global__ __launch_bounds__(1024) void k_batch_persist(BatchArgs<T> B, int S) {
     B.ctl->flip = flip + S;
   }
 }
+
+// Persistent pairs: npairs pairs of steps of every grid in one cooperative
+// launch of G = gridDim.x resident workgroups (a multiple of 8).  Workgroup w
+// runs entries w, w + G, w + 2G, ... of the pair item table, whose entry r
+// belongs to XCD r mod 8 -- the XCD the dispatcher puts workgroup r on -- so
+// each XCD's workgroups walk its own list (the tiles of a z-chunk of a grid
+// together, longest first); empty entries are skipped.  The launch meets at
+// the grid barrier after every pair (same barrier, bounds and error flag as
+// the single-step form).
+template <typename T>
+__global__ __launch_bounds__(768)
+__attribute__((amdgpu_waves_per_eu(sizeof(T) == 4 ? 6 : 3))) void k_batch2_persist(BatchArgs<T> B,
+                                                                                   int npairs) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  T* sm = reinterpret_cast<T*>(smem_raw);
+  const int64_t base = B.ctl->step_base;
+  const int flip = B.ctl->flip;
+  for (int j = 0; j < npairs; ++j) {
+    for (int r = (int)blockIdx.x; r < B.P; r += (int)gridDim.x) {
+      const BatchItem it = B.items2[r];
+      if (it.grid < 0) continue;
+      batch2_item<T>(B, it, base + 2 * (int64_t)j, flip + j, sm);
+      __syncthreads();   // the next item restages the LDS
+    }
+    grid_barrier(B.ctl, (unsigned)j + 1u, gridDim.x);
+  }
+  // every workgroup has read step_base and flip before the last barrier
+  if (blockIdx.x == 0 && threadIdx.x == 0 && threadIdx.y == 0) {
+    B.ctl->step_base = base + 2 * (int64_t)npairs;
+    B.ctl->flip = flip + npairs;
+  }
+}
+
+template <typename T>
+static int persist2_occupancy(int nthreads, size_t lds) {
+  int nb = 0;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch2_persist<T>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &nb, reinterpret_cast<const void*>(&k_batch2_persist<T>), nthreads, lds) != hipSuccess) {
+    (void)hipGetLastError();
+    return 0;
+  }
+  return nb;
+}
+
+int batch2_persist_blocks_per_cu(size_t esz, int nthreads, size_t lds) {
+  return esz == 8 ? persist2_occupancy<double>(nthreads, lds)
+                  : persist2_occupancy<float>(nthreads, lds);
+}
+
+template <typename T>
+hipError_t launch_batch2_persist(const BatchArgs<T>& b, int nwg, int npairs, hipStream_t s) {
+  if (nwg <= 0 || nwg % kXcds != 0 || npairs <= 0) return hipErrorInvalidValue;
+  BatchArgs<T> a = b;
+  int n = npairs;
+  void* args[2] = {&a, &n};
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_batch2_persist<T>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, b.lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_batch_bar_reset, dim3(1), dim3(64), 0, s, b.ctl);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_batch2_persist<T>),
+                                    dim3((unsigned)nwg), dim3((unsigned)b.nthreads), args,
+                                    (unsigned)b.lds, s);
+}
+
+template hipError_t launch_batch2_persist<float>(const BatchArgs<float>&, int, int, hipStream_t);
+template hipError_t launch_batch2_persist<double>(const BatchArgs<double>&, int, int, hipStream_t);
 
 template <typename T>
 static int persist_occupancy(int nthreads, size_t lds) {

@@ -340,6 +340,13 @@ template <typename T>
 hipError_t launch_batch_persist(const BatchArgs<T>& b, int nwg, int S, hipStream_t s);
 // Resident workgroups per CU of the persistent kernel (0 if unknown).
 int batch_persist_blocks_per_cu(size_t esz, int nthreads, size_t lds);
+// Persistent pairs: npairs pairs of steps of every grid in one cooperative
+// launch of nwg resident workgroups (a multiple of 8; the pair item table of
+// b, its threads and LDS), then the counters advanced by 2 npairs steps and
+// npairs flips.
+template <typename T>
+hipError_t launch_batch2_persist(const BatchArgs<T>& b, int nwg, int npairs, hipStream_t s);
+int batch2_persist_blocks_per_cu(size_t esz, int nthreads, size_t lds);
 
 // Launch wrappers (fit_kernels.hip).  Return hipError_t of the launch.
 template <typename T>
