@@ -832,7 +832,7 @@ def summarize(kt, rd_dir, wr_dir, out_md, cells, cmd_note):
                      f"{wr/1e6:.1f} | {bpc:.2f} | {lost:.0f} | {dram[0]:.0f} | {dram[1]:.0f} |")
         name = key[0]
         tag = ("pair" if "k_step2<float, true, false" in name
-               else "step" if "k_step<float, true, false, false" in name
+               else "step" if "k_step<float, true, 0, false, false" in name
                else "epass" if "k_epass<float, true, false, false>" in name
                else "hpass" if "k_hpass<float, true, false>" in name
                else "stream_copy" if "k_stream_copy" in name else None)
