@@ -458,8 +458,8 @@ def form_c2(steps: int = 10_000, warmup: int = 100):
     torch.cuda.synchronize()
     prof = g.profile_end()
     ms = ev[0].elapsed_time(ev[1])
-    nlaunch = prof["step"][1] + prof["pair"][1]
-    kms = prof["step"][0] + prof["pair"][0]
+    nlaunch = prof["step"][1] + prof["pair"][1] + prof["pair_energy"][1]
+    kms = prof["step"][0] + prof["pair"][0] + prof["pair_energy"][0]
     gbs = B_LAUNCH * sp.cells * nlaunch / (kms * 1e-3) / 1e9
     ee, hh = g.energy()
     g.close()
@@ -512,9 +512,10 @@ def form_graded(steps: int = 300, warmup: int = 20):
         if path == "fused":
             # per-step kernel time over single fused steps and step pairs
             # (two steps per launch, when the autotuner enabled them)
-            nstep = prof["step"][1] + 2 * prof["pair"][1]
-            nlaunch = prof["step"][1] + prof["pair"][1]
-            kms = prof["step"][0] + prof["pair"][0]
+            npair = prof["pair"][1] + prof["pair_energy"][1]
+            nstep = prof["step"][1] + 2 * npair
+            nlaunch = prof["step"][1] + npair
+            kms = prof["step"][0] + prof["pair"][0] + prof["pair_energy"][0]
             st = kms / max(nstep, 1)
             pon, ptw, pty, pkc = g.get_pair()
             # compulsory bytes (56 B per cell and launch) over the kernels' time
@@ -986,6 +987,10 @@ def main(argv=None):
                             "of the roofline: the fused launch moves fewer bytes"},
                 "path": path, "tile": [ptw, pty, pkc] if pr_n > 0 else [tw, ty, kc],
                 "single_tile": [path, ty, kc, tw], "pair_tile": [ptw, pty, pkc] if pon else None,
+                "energy_pair_launches": r["prof"]["pair_energy"][1],
+                "energy_pair_avg_ms": (round(r["prof"]["pair_energy"][0] /
+                                             r["prof"]["pair_energy"][1], 5)
+                                       if r["prof"]["pair_energy"][1] else None),
                 "single_step_launches": r["prof"]["step"][1],
                 "single_step_avg_ms": (round(r["prof"]["step"][0] / r["prof"]["step"][1], 5)
                                        if r["prof"]["step"][1] else None),

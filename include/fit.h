@@ -528,10 +528,12 @@ int fit_batch_step(fit_batch* b, int64_t nsteps, const double* dt, int use_graph
  * run untimed).  fit_profile_end synchronises and writes, per kernel class
  * (FIT_PROF_* index), the summed launch duration in milliseconds to
  * ms[FIT_PROF_N] and the number of timed launches to count[FIT_PROF_N]
- * (either may be NULL).  This is instrumentation for the paper's cost
+ * (either may be NULL); FIT_PROF_PAIR counts step pairs, FIT_PROF_PAIR_ENERGY
+ * the pairs that also record a trace row.  This is instrumentation for the paper's cost
  * measure (curl applications, eq. cost_LF) in wall-clock form. */
 enum { FIT_PROF_EPASS = 0, FIT_PROF_HPASS = 1, FIT_PROF_REDUCE = 2, FIT_PROF_STEP = 3,
-       FIT_PROF_ADJOINT = 4, FIT_PROF_OTHER = 5, FIT_PROF_PAIR = 6, FIT_PROF_N = 7 };
+       FIT_PROF_ADJOINT = 4, FIT_PROF_OTHER = 5, FIT_PROF_PAIR = 6, FIT_PROF_PAIR_ENERGY = 7,
+       FIT_PROF_N = 8 };
 int fit_profile_begin(fit_grid* g, int64_t max_launches);
 int fit_profile_end(fit_grid* g, double ms[FIT_PROF_N], int64_t count[FIT_PROF_N]);
 

@@ -107,7 +107,7 @@ SIGNATURES = {
     "fit_autotune": [_vp, _d, _i, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
                      C.POINTER(C.c_int), C.POINTER(C.c_float)],
 }
-PROF_KINDS = ("epass", "hpass", "reduce", "step", "adjoint", "other", "pair")
+PROF_KINDS = ("epass", "hpass", "reduce", "step", "adjoint", "other", "pair", "pair_energy")
 _CHAR = {"fit_version": [], "fit_last_error": []}
 
 _lib = None

@@ -450,21 +450,29 @@ static int pair_kc(const fit_grid* g, int tw, int ty) {
   return std::min(g->d.nz, std::max(k, std::min(8, g->d.nz)));
 }
 
-static bool pair_now(const fit_grid* g, int64_t nleft) {
-  if (nleft < 2 || !g->pair_on || !use_fused(g) || g->probe.on) return false;
-  if (!step2_plane_ok(g->d, g->esz)) return false;
+// How steps m, m+1 run: kPairNone (singly), kPairPlain (a pair; no trace
+// row at m, m+1 or m+2 -- a row at m+2 needs step m+1's h cross term), or
+// kPairEnergy (a pair whose second step records the row at m+1, its first
+// step the row's pending h cross term; uniform grids, one-point tiles).
+enum { kPairNone = 0, kPairPlain = 1, kPairEnergy = 2 };
+static int pair_now(const fit_grid* g, int64_t nleft) {
+  if (nleft < 2 || !g->pair_on || !use_fused(g) || g->probe.on) return kPairNone;
+  if (!step2_plane_ok(g->d, g->esz)) return kPairNone;
   // the tile may no longer fit after the materials or spacing changed
   // (lossless -> lossy, uniform -> tensor grid)
-  if (!step2_shape_ok(g->ptw, g->pty, g->esz, g->lossy, g->nu)) return false;
+  if (!step2_shape_ok(g->ptw, g->pty, g->esz, g->lossy, g->nu)) return kPairNone;
   const int64_t m = g->m;
-  if (trace_at(g, m) || trace_at(g, m + 1) || trace_at(g, m + 2)) return false;
-  return true;
+  if (trace_at(g, m) || trace_at(g, m + 2)) return kPairNone;
+  if (!trace_at(g, m + 1)) return kPairPlain;
+  return step2_energy_ok(g->ptw, g->pty, g->nu) ? kPairEnergy : kPairNone;
 }
 
 // Two fused steps m -> m+2 in one launch: state read from (e, h), written to
-// (e_alt, h_alt), then the two sets swap roles.
+// (e_alt, h_alt), then the two sets swap roles.  energy: the trace row of
+// step m+1 is recorded from the launch's partial sums (dropped, and the pair
+// run plainly, when the trace is full).
 template <typename T>
-static int step_pair(fit_grid* g, double dt) {
+static int step_pair(fit_grid* g, double dt, bool energy = false) {
   int rc = ensure_alt(g);
   if (rc) return rc;
   const Dims& d = g->d;
@@ -492,12 +500,35 @@ static int step_pair(fit_grid* g, double dt) {
   a.src_val[0] = (T)(g->src_axis >= 0 ? source_value(g, dt, g->m) : 0.0);
   a.src_val[1] = (T)(g->src_axis >= 0 ? source_value(g, dt, g->m + 1) : 0.0);
   if (g->nu) set_nu_args(g, dt, a);
+  if (energy && g->trace_rows >= g->trace_cap) {
+    g->trace_dropped++;
+    energy = false;
+  }
+  const int64_t nb = a.t.blocks();
+  if (energy) {
+    if (ensure_part(g, nb)) return FIT_E_OOM;
+    for (int c = 0; c < 3; ++c) {
+      a.ge[c] = g->gedge[c] / 4.0;
+      a.gf2[c] = g->gf2[c];
+    }
+    a.part = g->part;
+  }
   hipError_t e;
   {
-    ProfScope ps(g, FIT_PROF_PAIR);
-    e = launch_step2<T>(a, g->lossy, g->s);
+    ProfScope ps(g, energy ? FIT_PROF_PAIR_ENERGY : FIT_PROF_PAIR);
+    e = energy ? launch_step2_energy<T>(a, g->lossy, g->s) : launch_step2<T>(a, g->lossy, g->s);
   }
   if (e != hipSuccess) return hip_fail(e, "step pair launch");
+  if (energy) {
+    // the row of step m+1: its terms, and the first step's h cross term in
+    // the pending column
+    double* row = g->trace + g->trace_rows * FIT_TRACE_COLS;
+    const int cols[kPartTerms] = {1, 2, 3, 8, 9, -1, 5, 6, 7, 4};
+    ProfScope ps(g, FIT_PROF_REDUCE);
+    e = launch_reduce(g->part, nb, row, cols, -1, 0.0, nullptr, -1, g->m + 1, nullptr, -1, g->s);
+    if (e != hipSuccess) return hip_fail(e, "reduce launch");
+    g->trace_rows++;
+  }
   swap_sets(g);
   g->m += 2;
   g->smvp += 4;
@@ -1174,8 +1205,10 @@ int fit_step(fit_grid* g, int64_t nsteps, double dt) {
   if (nsteps > 0) g->last_dt = dt;
   const bool fused = use_fused(g);
   for (int64_t s = 0; s < nsteps; ++s) {
-    if (fused && pair_now(g, nsteps - s)) {
-      rc = g->f64 ? step_pair<double>(g, dt) : step_pair<float>(g, dt);
+    const int pm = fused ? pair_now(g, nsteps - s) : kPairNone;
+    if (pm != kPairNone) {
+      const bool en = pm == kPairEnergy;
+      rc = g->f64 ? step_pair<double>(g, dt, en) : step_pair<float>(g, dt, en);
       ++s;
     } else if (fused) {
       rc = g->f64 ? step_fused<double>(g, dt) : step_fused<float>(g, dt);

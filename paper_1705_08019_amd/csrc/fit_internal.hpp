@@ -55,6 +55,9 @@ enum { PE_EE_MM = 0, PE_EE_MM1 = 1, PE_EE_M1M1 = 2, PE_LOSS = 3, PE_SRC = 4, PE_
 enum { PH_HH_CC = 0, PH_HH_CN = 1, PH_HH_NN = 2 };
 // Fused-step partial term slots: the E slots above, then the H terms.
 enum { PS_HH_CC = 6, PS_HH_CN = 7, PS_HH_NN = 8 };
+// Energy pairs: the first step's h cross term <h^(m+1/2), h^(m+3/2)> (the
+// pending term of the row the second step records).
+constexpr int kPairHCross = 9;
 // Energy modes of the fused step: none, every term, or only the h cross
 // term <h^(m+1/2), h^(m+3/2)> (the step before a trace row needs no other).
 enum { kEnergyNone = 0, kEnergyAll = 1, kEnergyHCross = 2 };
@@ -172,6 +175,11 @@ struct S2Args {
   int src_comp;
   int64_t src_idx;
   T src_val[2];
+  // energy pairs (uniform grids): edge and facet metrics as in SArgs, and
+  // the launch's partial-sum rows (kPartTerms per workgroup)
+  double ge[3] = {0.0, 0.0, 0.0};
+  double gf2[3] = {0.0, 0.0, 0.0};
+  double* part = nullptr;
   // tensor grid (null otherwise): as in SArgs
   const double* nsq[3] = {nullptr, nullptr, nullptr};
   const double* ndl[3] = {nullptr, nullptr, nullptr};
@@ -199,6 +207,14 @@ bool step2_shape_ok(int tw, int ty, size_t esz, bool lossy, bool nu = false);
 bool step2_plane_ok(const Dims& d, size_t esz);
 template <typename T>
 hipError_t launch_step2(const S2Args<T>& a, bool lossy, hipStream_t s);
+// A pair whose second step is a trace row (uniform grids, tiles of one point
+// per thread): as launch_step2, and every workgroup writes its kPartTerms
+// partial sums to a.part: the terms of the fused step with every energy term
+// for the second step (slots PE_* and PS_*), the h cross term of the first
+// step in slot kPairHCross.  hipErrorInvalidValue for other grids or tiles.
+template <typename T>
+hipError_t launch_step2_energy(const S2Args<T>& a, bool lossy, hipStream_t s);
+bool step2_energy_ok(int tw, int ty, bool nu);
 
 // nu_planes: planes of per-plane metric staged on a tensor grid (0 otherwise).
 size_t step_lds_bytes(int ty, size_t esz, bool lossy, int tw = 64, int nu_planes = 0);

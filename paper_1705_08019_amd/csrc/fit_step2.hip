@@ -115,4 +115,65 @@ hipError_t launch_step2(const S2Args<T>& a, bool lossy, hipStream_t s) {
 template hipError_t launch_step2<float>(const S2Args<float>&, bool, hipStream_t);
 template hipError_t launch_step2<double>(const S2Args<double>&, bool, hipStream_t);
 
+// Energy pairs: the same tile body with the FP64 energy sums; its nine
+// compensated accumulators do not fit the two-workgroups-per-CU budget, so
+// one workgroup per CU (3 or 4 waves per SIMD).
+bool step2_energy_ok(int tw, int ty, bool nu) { return !nu && step2_points(tw, ty) == 1; }
+
+// the compile-time tile's own thread count (step2_threads), 1024 for generic tiles
+template <int CTW, int CTY>
+constexpr int s2e_threads() {
+  if (CTW == 0) return 1024;
+  const int n1 = (CTW + 4) * (CTY + 3), n4 = ((CTW + 4) * (CTY + 4) + kS2Per - 1) / kS2Per;
+  return ((n1 > n4 ? n1 : n4) + 63) / 64 * 64;
+}
+
+template <typename T, bool LOSSY, int CTW, int CTY>
+__global__ __launch_bounds__((s2e_threads<CTW, CTY>()))
+__attribute__((amdgpu_waves_per_eu((s2e_threads<CTW, CTY>() > 768 ? 4 : 3)))) void k_step2e(
+    S2Args<T> A) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  const int64_t lt = xcd_remap(blockIdx.x, gridDim.x);
+  const int tx = (int)(lt % A.t.ntx);
+  const int64_t rr = lt / A.t.ntx;
+  step2_tile<T, LOSSY, false, CTW, CTY, 1, true>(A, tx, (int)(rr % A.t.nty), (int)(rr / A.t.nty),
+                                                 reinterpret_cast<T*>(smem_raw),
+                                                 A.part + (int64_t)blockIdx.x * kPartTerms);
+}
+
+template <typename T, bool L, int CW, int CY>
+static hipError_t go_step2e_t(const S2Args<T>& a, dim3 grd, dim3 blk, size_t lds, hipStream_t s) {
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_step2e<T, L, CW, CY>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_step2e<T, L, CW, CY>), grd, blk, lds, s, a);
+  return hipGetLastError();
+}
+
+template <typename T, bool L>
+static hipError_t go_step2e(const S2Args<T>& a, dim3 grd, dim3 blk, size_t lds, hipStream_t s) {
+  const int tw = a.t.tw, ty = a.t.ty;
+  if (tw == 32 && ty == 16) return go_step2e_t<T, L, 32, 16>(a, grd, blk, lds, s);
+  if (tw == 64 && ty == 8) return go_step2e_t<T, L, 64, 8>(a, grd, blk, lds, s);
+  if constexpr (sizeof(T) == 4)
+    if (tw == 64 && ty == 12) return go_step2e_t<T, L, 64, 12>(a, grd, blk, lds, s);
+  return go_step2e_t<T, L, 0, 0>(a, grd, blk, lds, s);
+}
+
+template <typename T>
+hipError_t launch_step2_energy(const S2Args<T>& a, bool lossy, hipStream_t s) {
+  const bool nu = a.nsq[0] != nullptr;
+  if (!step2_energy_ok(a.t.tw, a.t.ty, nu) || !a.part) return hipErrorInvalidValue;
+  if (!step2_shape_ok(a.t.tw, a.t.ty, sizeof(T), lossy, nu)) return hipErrorInvalidValue;
+  if (!step2_plane_ok(a.d, sizeof(T))) return hipErrorInvalidValue;
+  const dim3 blk(step2_threads(a.t.tw, a.t.ty)), grd((unsigned)a.t.blocks());
+  const size_t lds = step2_lds_bytes(a.t.tw, a.t.ty, sizeof(T), lossy, nu);
+  return lossy ? go_step2e<T, true>(a, grd, blk, lds, s) : go_step2e<T, false>(a, grd, blk, lds, s);
+}
+
+template hipError_t launch_step2_energy<float>(const S2Args<float>&, bool, hipStream_t);
+template hipError_t launch_step2_energy<double>(const S2Args<double>&, bool, hipStream_t);
+
 }  // namespace fit

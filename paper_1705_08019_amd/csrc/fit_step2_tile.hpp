@@ -92,8 +92,10 @@ __device__ __forceinline__ void pst(T* base, uint32_t off, T v) {
 // p < NP, of the thread grid (tiles whose R1 region has more than 1024
 // points, e.g. 64 x 16, take NP = 2); each point keeps its own carried
 // values, and every phase runs over the thread's points in turn.
-template <typename T, bool LOSSY, bool NU, int CTW, int CTY, int NP = 1>
-__device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, int kz, T* sm) {
+template <typename T, bool LOSSY, bool NU, int CTW, int CTY, int NP = 1, bool EN = false>
+__device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, int kz, T* sm,
+                                           double* part = nullptr) {
+  static_assert(!EN || (NP == 1 && !NU), "energy pairs: uniform grids, one point per thread");
   const Dims d = A.d;
   const int TW = CTW > 0 ? CTW : A.t.tw, TY = CTY > 0 ? CTY : A.t.ty;
   const S2Geom G = s2_geom(TW, TY);
@@ -270,6 +272,12 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
     }
   }
 
+  // energy pairs: FP64 compensated sums of the tile's own points on planes
+  // [k0, k1), the terms of the fused single step (same selects of dead
+  // slots and operand order)
+  double acc[kPartTerms] = {};
+  double cmp[kPartTerms] = {};
+
   // prologue: plane k0 - 2 staged for its carried values, plane k0 - 1 in flight
   fetch(k0 - 2);
   stage(k0 - 2);
@@ -377,6 +385,17 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
         h1L[j1] = h1c[p][0];
         h1L[G.N2 + j1] = h1c[p][1];
         h1L[2 * G.N2 + j1] = h1c[p][2];
+        if (EN && own[p] && km >= k0 && km < k1) {
+          // <h^(m+1/2), h^(m+3/2)> of the first step
+          const double wx = gxp[p] > 0 ? 1.0 / (A.gf2[0] * (double)A.imu2) : 0.0;
+          const double wy = gyp[p] > 0 ? 1.0 / (A.gf2[1] * (double)A.imu2) : 0.0;
+          const double wz = km > 0 ? 1.0 / (A.gf2[2] * (double)A.imu2) : 0.0;
+          const double ox = gxp[p] > 0 ? (double)hq[p][0] : 0.0;
+          const double oy = gyp[p] > 0 ? (double)hq[p][1] : 0.0;
+          const double oz = km > 0 ? (double)hq[p][2] : 0.0;
+          const double nx_ = h1c[p][0], ny_ = h1c[p][1], nz_ = h1c[p][2];
+          nadd_s(acc[kPairHCross], cmp[kPairHCross], wx * ox * nx_ + wy * oy * ny_ + wz * oz * nz_);
+        }
       }
     }
     __syncthreads();
@@ -413,6 +432,29 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
           pst(A.e2[0] + gk, o, e2c[p][0]);
           pst(A.e2[1] + gk, o, e2c[p][1]);
           pst(A.e2[2] + gk, o, e2c[p][2]);
+          if (EN) {
+            // the second step's e terms: e^(m+1) (old), e^(m+2) (new)
+            const double mx = A.ge[0] * (double)E4p[p][0], my = A.ge[1] * (double)E4p[p][1],
+                         mz = A.ge[2] * (double)E4p[p][2];
+            const double ox = gyp[p] > 0 && km > 0 ? (double)e1p[p][0] : 0.0;
+            const double oy = gxp[p] > 0 && km > 0 ? (double)e1p[p][1] : 0.0;
+            const double oz = gxp[p] > 0 && gyp[p] > 0 ? (double)e1p[p][2] : 0.0;
+            const double nx_ = e2c[p][0], ny_ = e2c[p][1], nz_ = e2c[p][2];
+            nadd_s(acc[PE_EE_MM], cmp[PE_EE_MM], mx * ox * ox + my * oy * oy + mz * oz * oz);
+            nadd_s(acc[PE_EE_MM1], cmp[PE_EE_MM1], mx * ox * nx_ + my * oy * ny_ + mz * oz * nz_);
+            nadd_s(acc[PE_EE_M1M1], cmp[PE_EE_M1M1],
+                   mx * nx_ * nx_ + my * ny_ * ny_ + mz * nz_ * nz_);
+            if (LOSSY) {
+              const double bx = 0.5 * (ox + nx_), by = 0.5 * (oy + ny_), bz = 0.5 * (oz + nz_);
+              nadd_s(acc[PE_LOSS], cmp[PE_LOSS],
+                     A.ge[0] * (double)S4p[p][0] * bx * bx + A.ge[1] * (double)S4p[p][1] * by * by +
+                         A.ge[2] * (double)S4p[p][2] * bz * bz);
+            }
+            const double bs = A.src_comp == 0 ? 0.5 * (ox + nx_)
+                            : A.src_comp == 1 ? 0.5 * (oy + ny_) : 0.5 * (oz + nz_);
+            nadd_s(acc[PE_SRC], cmp[PE_SRC],
+                   at_s[p] && km == sk ? bs * (double)A.src_val[1] : 0.0);
+          }
         }
       }
     }
@@ -443,6 +485,19 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
         pst(A.h2[0] + gk, o, hxn);
         pst(A.h2[1] + gk, o, hyn);
         pst(A.h2[2] + gk, o, hzn);
+        if (EN) {
+          // the second step's h terms: h^(m+3/2) (old), h^(m+5/2) (new)
+          const double wx = gxp[p] > 0 ? 1.0 / (A.gf2[0] * (double)A.imu2) : 0.0;
+          const double wy = gyp[p] > 0 ? 1.0 / (A.gf2[1] * (double)A.imu2) : 0.0;
+          const double wz = kh > 0 ? 1.0 / (A.gf2[2] * (double)A.imu2) : 0.0;
+          const double ox = gxp[p] > 0 ? (double)h1p[p][0] : 0.0;
+          const double oy = gyp[p] > 0 ? (double)h1p[p][1] : 0.0;
+          const double oz = kh > 0 ? (double)h1p[p][2] : 0.0;
+          const double nx_ = hxn, ny_ = hyn, nz_ = hzn;
+          nadd_s(acc[PS_HH_CC], cmp[PS_HH_CC], wx * ox * ox + wy * oy * oy + wz * oz * oz);
+          nadd_s(acc[PS_HH_CN], cmp[PS_HH_CN], wx * ox * nx_ + wy * oy * ny_ + wz * oz * nz_);
+          nadd_s(acc[PS_HH_NN], cmp[PS_HH_NN], wx * nx_ * nx_ + wy * ny_ * ny_ + wz * nz_ * nz_);
+        }
       }
     }
 
@@ -462,6 +517,31 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
       Syq[p] = Syc[p];
       Sxsq[p] = Sxsc[p];
       Sysq[p] = Sysc[p];
+    }
+  }
+
+  if constexpr (EN) {
+    // block sums of the terms in a fixed order: per wave, then over waves
+    __shared__ double red[16][kPartTerms];
+    const int wave = tid >> 6, lane = tid & 63, nw = nthr >> 6;
+    double v[kPartTerms];
+#pragma unroll
+    for (int t = 0; t < kPartTerms; ++t) {
+      double x = acc[t] + cmp[t];
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off, 64);
+      v[t] = x;
+    }
+    __syncthreads();
+    if (lane == 0) {
+#pragma unroll
+      for (int t = 0; t < kPartTerms; ++t) red[wave][t] = v[t];
+    }
+    __syncthreads();
+    if (tid < kPartTerms) {
+      double s = 0.0;
+      for (int w = 0; w < nw; ++w) s += red[w][tid];
+      part[tid] = s;
     }
   }
 }

@@ -120,12 +120,14 @@ def test_curl_parity_ragged(which, dims):
     np.testing.assert_allclose(got, ref, rtol=0, atol=1e-14)
 
 
-@pytest.mark.parametrize("path", ["split", "fused"])
+@pytest.mark.parametrize("path", ["split", "fused", "pairs"])
 @pytest.mark.parametrize("dtype,dims,nsteps", [("f32", (32, 32, 32), 1000),
                                                ("f64", (67, 35, 21), 300)])
 def test_lossy_blocks_source_parity(dtype, dims, nsteps, path):
     """Dielectric blocks, lossy z-slabs and the Gaussian source; ragged tiles
-    (x spans two 64-lane tiles, z spans several chunks with a short tail)."""
+    (x spans two 64-lane tiles, z spans several chunks with a short tail).
+    pairs: two steps per launch, the trace rows recorded by the energy pairs
+    (the row's step second in its pair)."""
     from paper_1705_08019_amd import FitGrid
     nx, ny, nz = dims
     spec = c2_small(32, nsteps, dtype)
@@ -138,10 +140,19 @@ def test_lossy_blocks_source_parity(dtype, dims, nsteps, path):
     dt = spec_dt(spec)
     src = oracle_source(spec, dt)
     g = _grid(spec, dtype)
-    g.set_tuning(path)
+    g.set_tuning("fused" if path == "pairs" else path)
+    if path == "pairs":
+        g.set_pair(True, 32, 16, 8)
     g.set_source(2, src["i"], src["j"], src["k"], src["i_max"], src["sigma_t"])
     g.trace_config(10, nsteps)
+    g.profile_begin(4 * nsteps)
     g.step(nsteps, dt)
+    prof = g.profile_end()
+    if path == "pairs":
+        # step 0 singly, then pairs; every row after the first recorded by
+        # an energy pair (steps 10 r - 1, 10 r)
+        assert prof["pair_energy"][1] == (nsteps - 1) // 10, prof
+        assert prof["pair"][1] + prof["pair_energy"][1] == (nsteps - 1) // 2, prof
     e, h = g.get_fields()
     tr, _ = g.trace_read()
     eN, hN, tr_ref = run(ops, np.zeros(ops.n_e), np.zeros(ops.n_h), dt, nsteps, source=src)

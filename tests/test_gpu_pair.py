@@ -84,7 +84,11 @@ def test_pairs_around_trace_rows_and_odd_step_counts():
         assert torch.equal(g1.get_fields()[1], g2.get_fields()[1])
         t1, _ = g1.trace_read()
         t2, _ = g2.trace_read()
-        assert np.array_equal(t1, t2, equal_nan=True)
+        # rows recorded by energy pairs: the same per-cell FP64 terms summed
+        # over the pair tiling instead of the single-step one
+        assert t1.shape == t2.shape and np.array_equal(np.isnan(t1), np.isnan(t2))
+        np.testing.assert_allclose(t2, t1, rtol=1e-12, atol=1e-13 * np.nanmax(np.abs(t1)),
+                                   equal_nan=True)
         # a probe switches pairs off (the objective needs every step)
         g2.set_probe([2, 2, 2], [10, 10, 10])
         g1.set_probe([2, 2, 2], [10, 10, 10])
@@ -242,3 +246,37 @@ def test_graded_pair_matches_oracle_fp64():
     assert rel_l2(edges_from_slots(ops, to_np(e)), eN) <= 1e-12
     assert rel_l2(facets_from_slots(ops, to_np(h)), hN) <= 1e-12
     g.close()
+
+
+@pytest.mark.parametrize("dtype", ["f32", "f64"])
+def test_energy_pairs_record_the_rows(dtype):
+    """A trace row whose step is the second of a pair is recorded by the pair
+    (its pending h cross term by the pair's first step): the rows equal those
+    of single fused steps to the summation order, the fields bitwise; rows
+    past the trace's capacity are counted as dropped as on the single path;
+    tensor grids keep single steps around the rows."""
+    n = (45, 26, 19)
+    g1, dt, _, _ = _grid(n, dtype, True)
+    g2, _, _, _ = _grid(n, dtype, True)
+    g2.set_pair(True, 32, 16, 6)
+    for g in (g1, g2):
+        g.trace_config(10, 4)                   # rows at 0, 10, 20, 30; 40 and 50 dropped
+    g2.profile_begin(200)
+    for g in (g1, g2):
+        g.step(55, dt)
+    prof = g2.profile_end()
+    # 0 single, then pairs (1, 2) .. (9, 10) with the row, ...: 27 pairs, 3 of
+    # them recording rows 10, 20, 30 (40 and 50 do not fit), 1 single step
+    assert prof["pair"][1] == 24 and prof["pair_energy"][1] == 3 and prof["step"][1] == 1, prof
+    for a, b in zip(g1.get_fields(), g2.get_fields()):
+        assert torch.equal(a, b)
+    t1, d1 = g1.trace_read()
+    t2, d2 = g2.trace_read()
+    assert t1.shape == t2.shape == (4, 10) and d1 == d2 == 2
+    assert np.array_equal(t1[:, 0], t2[:, 0]) and np.array_equal(np.isnan(t1), np.isnan(t2))
+    np.testing.assert_allclose(t2, t1, rtol=1e-12, atol=1e-13 * np.nanmax(np.abs(t1)),
+                               equal_nan=True)
+    print(f"energy pairs {dtype}: max rel row diff "
+          f"{np.nanmax(np.abs(t2 - t1) / np.maximum(np.abs(t1), 1e-300)):.1e}", flush=True)
+    g1.close()
+    g2.close()
