@@ -91,7 +91,13 @@ __device__ __forceinline__ void pst(T* base, uint32_t off, T v) {
 // tiling.  NP: points per thread -- thread t owns the points q = t + p nthr,
 // p < NP, of the thread grid (tiles whose R1 region has more than 1024
 // points, e.g. 64 x 16, take NP = 2); each point keeps its own carried
-// values, and every phase runs over the thread's points in turn.
+// values, and every phase runs over the thread's points in turn.  EN
+// (uniform grids, NP = 1): also form the energy terms of a trace row at the
+// second step -- the e terms where the second e-update stores its point,
+// the h terms where the second h-update does, and the row's pending h cross
+// term where the first h-update forms an own point of [k0, k1) -- in FP64
+// with the compensated sums of the single step, and write the workgroup's
+// block sums (kPartTerms) to part.
 template <typename T, bool LOSSY, bool NU, int CTW, int CTY, int NP = 1, bool EN = false>
 __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, int kz, T* sm,
                                            double* part = nullptr) {
