@@ -7,19 +7,16 @@
 // per-cell materials (k_gram_weights) and kept until the materials change.
 //
 // Decomposition: the rows are split into contiguous chunks, one per
-// workgroup; a workgroup stages slabs of R rows x C snapshots of its chunk in
-// LDS as FP64 (R C = 4096: 64 x 64 for full blocks, 256 x 16 for K <= 16;
-// FP32 snapshots are widened on load; each wave load instruction reads 64
-// consecutive rows of one snapshot) and accumulates the 16 x 16
-// MFMA tiles of a 64 x 64 output block that hold output: tiles past the
-// snapshot count are never formed and, in a diagonal block, only the upper
-// tile triangle is (G is symmetric).  The 4 waves split the rows of each
-// staged slab (and, for a full 4 x 4 off-diagonal block, the tiles in two
-// halves), so every wave has the same work for any K; their partial tiles are
-// summed in LDS at the end.  The next slab is loaded into registers while the
-// current one is multiplied.  Each workgroup writes its FP64 block; a second
-// kernel sums the blocks per entry with Neumaier compensation.  Larger K is
-// covered block pair by block pair.
+// workgroup.  A workgroup forms the 16 x 16 MFMA tiles of one output block
+// (up to 64 x 64: 4 x 4 tiles; tiles past the snapshot count are never
+// formed and, in a diagonal block, only the upper tile triangle is, G being
+// symmetric) over its chunk, streaming the snapshots from HBM straight into
+// the MFMA operands: no LDS staging and no barrier in the row loop (k_gram
+// below gives the lane layout).  Its waves take consecutive row steps, each
+// with the next step's loads in flight while the current one is multiplied;
+// their partial tiles are summed in LDS at the end and the workgroup writes
+// its FP64 block.  A second kernel sums the blocks per entry with Neumaier
+// compensation.  Larger K is covered block pair by block pair.
 #include <type_traits>
 
 #include "fit_internal.hpp"
@@ -220,14 +217,14 @@ struct GramStage {
 // w x_a and the B operand x_b taken from the lane's own registers (the
 // weight broadcast within the group's 16-lane DPP row).  A wave step covers
 // 4 RL rows (whole 128-byte lines of every snapshot for RL >= 8 in FP32, 4 in FP64); the
-// 4 waves of the workgroup take consecutive steps, and each step's loads are
-// in flight while the previous step is multiplied (two register stages,
-// alternating).  Full rounds of the four waves load unconditionally; the
+// NWV waves of the workgroup take consecutive steps, and each step's loads
+// are in flight while the previous step is multiplied (two register stages,
+// alternating).  Full rounds of the NWV waves load unconditionally; the
 // chunk's last, partial round reads element by element (rows past the chunk
 // as zero).  The waves' partial tiles are summed in LDS at the end and the
 // workgroup writes its FP64 block.
-template <typename T, int NTA, int NTB, bool DIAG, int RL, bool VEC>
-__global__ __launch_bounds__(256) void k_gram(GramArgs<T> A) {
+template <typename T, int NTA, int NTB, bool DIAG, int RL, bool VEC, int NWV>
+__global__ __launch_bounds__(64 * NWV) void k_gram(GramArgs<T> A) {
   static_assert(RL % 4 == 0 && RL <= 16, "RL: a multiple of 4, at most one 16-lane row");
   using TS = TileSet<NTA, NTB, DIAG>;
   constexpr int NB = DIAG ? 1 : NTB;   // B operands of their own (off the diagonal)
@@ -306,7 +303,7 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs<T> A) {
   };
 
   constexpr int64_t kStep = 4 * RL;          // rows of one wave step
-  constexpr int64_t kRound = 4 * kStep;      // rows of one step of all four waves
+  constexpr int64_t kRound = NWV * kStep;    // rows of one step of all the waves
   const int64_t full = (r_end - r_begin) / kRound;
   int64_t r0 = r_begin + wave * kStep;
   Stage s0, s1;
@@ -342,8 +339,8 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs<T> A) {
     multiply(s1);
   }
 
-  // sum the four waves' tiles in LDS, in wave order
-  for (int w = 0; w < 4; ++w) {
+  // sum the waves' tiles in LDS, in wave order
+  for (int w = 0; w < NWV; ++w) {
     if (wave == w) {
       static_for<0, NQ>([&](auto qc) {
         constexpr int q = decltype(qc)::value;
@@ -360,7 +357,7 @@ __global__ __launch_bounds__(256) void k_gram(GramArgs<T> A) {
   }
   // the block, packed (OR x OC, row-major) at its workgroup's slot
   double* out = A.part + (int64_t)blockIdx.x * (OR * OC);
-  for (int e = tid; e < OR * OC; e += 256) out[e] = O[e];
+  for (int e = tid; e < OR * OC; e += 64 * NWV) out[e] = O[e];
 }
 
 // Sum the per-workgroup blocks entry by entry (Neumaier), write G rows
@@ -434,25 +431,33 @@ static hipError_t gram_go(GramArgs<T> A, int64_t part_cap, hipStream_t s, int64_
   constexpr int RL = NTA == 1 && NTB == 1                      ? 16
                      : sizeof(T) == 8 || (!DIAG && NTA * NTB > 8) ? 4
                                                                   : 8;
-  const void* fn = reinterpret_cast<const void*>(&k_gram<T, NTA, NTB, DIAG, RL, VEC>);
+  // waves per workgroup: 8 for single-tile blocks (K <= 16, read-bound), at
+  // most two workgroups per CU -- the same waves per CU as four 4-wave
+  // workgroups, half the concurrent snapshot streams, each workgroup reading
+  // twice the rows of every snapshot per round (0.0983-0.0995 -> 0.0970 ms
+  // per K = 16 call); 4 otherwise
+  constexpr int NWV = NTA == 1 && NTB == 1 ? 8 : 4;
+  const void* fn = reinterpret_cast<const void*>(&k_gram<T, NTA, NTB, DIAG, RL, VEC, NWV>);
   int per_cu = 0, cus = 0, dev = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 256, 0) != hipSuccess || per_cu < 1)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * NWV, 0) != hipSuccess ||
+      per_cu < 1)
     per_cu = 2;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
     cus = 256;
   (void)hipGetLastError();
-  // single-tile blocks (K <= 16) are read-bound: more than 4 workgroups per
-  // CU only add concurrent snapshot streams and partial blocks (measured:
-  // 0.100 ms per call at 4, 0.106 at 8)
-  if (NTA == 1 && NTB == 1) per_cu = std::min(per_cu, 4);
+  // single-tile blocks: more workgroups per CU only add concurrent snapshot
+  // streams and partial blocks (4-wave workgroups: 0.100 ms per call at 4
+  // per CU, 0.106 at 8; 8-wave ones: 0.097 at 2, 0.099 at 4)
+  if (NTA == 1 && NTB == 1) per_cu = std::min(per_cu, 2);
   int64_t nwg = std::min<int64_t>(part_cap, (int64_t)per_cu * cus);
   int64_t chunk = (A.rows + nwg - 1) / nwg;
   chunk = ((chunk + kGramChunkAlign - 1) / kGramChunkAlign) * kGramChunkAlign;
   nwg = (A.rows + chunk - 1) / chunk;
   A.chunk = chunk;
   *nwg_used = nwg;
-  hipLaunchKernelGGL((k_gram<T, NTA, NTB, DIAG, RL, VEC>), dim3((unsigned)nwg), dim3(256), 0, s, A);
+  hipLaunchKernelGGL((k_gram<T, NTA, NTB, DIAG, RL, VEC, NWV>), dim3((unsigned)nwg),
+                     dim3(64 * NWV), 0, s, A);
   return hipGetLastError();
 }
 
