@@ -249,15 +249,16 @@ def test_graded_pair_matches_oracle_fp64():
 
 
 @pytest.mark.parametrize("dtype", ["f32", "f64"])
-def test_energy_pairs_record_the_rows(dtype):
+@pytest.mark.parametrize("n,lossy", [((45, 26, 19), True), ((40, 40, 1), False), ((9, 70, 2), True),
+                                     ((5, 4, 3), False)])
+def test_energy_pairs_record_the_rows(dtype, n, lossy):
     """A trace row whose step is the second of a pair is recorded by the pair
     (its pending h cross term by the pair's first step): the rows equal those
     of single fused steps to the summation order, the fields bitwise; rows
     past the trace's capacity are counted as dropped as on the single path;
-    tensor grids keep single steps around the rows."""
-    n = (45, 26, 19)
-    g1, dt, _, _ = _grid(n, dtype, True)
-    g2, _, _, _ = _grid(n, dtype, True)
+    also on one- and two-plane grids and a grid smaller than one tile."""
+    g1, dt, _, _ = _grid(n, dtype, lossy)
+    g2, _, _, _ = _grid(n, dtype, lossy)
     g2.set_pair(True, 32, 16, 6)
     for g in (g1, g2):
         g.trace_config(10, 4)                   # rows at 0, 10, 20, 30; 40 and 50 dropped
@@ -276,7 +277,7 @@ def test_energy_pairs_record_the_rows(dtype):
     assert np.array_equal(t1[:, 0], t2[:, 0]) and np.array_equal(np.isnan(t1), np.isnan(t2))
     np.testing.assert_allclose(t2, t1, rtol=1e-12, atol=1e-13 * np.nanmax(np.abs(t1)),
                                equal_nan=True)
-    print(f"energy pairs {dtype}: max rel row diff "
+    print(f"energy pairs {dtype} {n}: max rel row diff "
           f"{np.nanmax(np.abs(t2 - t1) / np.maximum(np.abs(t1), 1e-300)):.1e}", flush=True)
     g1.close()
     g2.close()
