@@ -567,10 +567,16 @@ int fit_get_tuning(const fit_grid* g, int* path, int* tw, int* ty, int* kc);
  * recurrence): with enable = 1, fit_step advances pairs of steps with one
  * launch that reads the state and the materials once and keeps the
  * intermediate state on chip, whenever the fused path is active (uniform
- * mu; uniform or tensor-product spacing), no probe is set, neither step of
- * the pair needs energies for the trace, the tile fits the grid's materials
- * and a z-plane of the grid spans at most 4 GiB (other steps run singly).
- * The result is bitwise that of single fused steps.  tw x ty: tile (tw >= 8,
+ * mu; uniform or tensor-product spacing), no probe is set, the first step
+ * of the pair is no trace row and the step after it needs no h cross term
+ * for one (a trace row m+2), the tile fits the grid's materials and a
+ * z-plane of the grid spans at most 4 GiB (other steps run singly).  A pair
+ * whose second step is a trace row records the row itself (uniform spacing,
+ * tiles of one point per thread: the FP64 compensated energy terms of eq.
+ * energy formed in the pair, the row's pending h cross term from its first
+ * step), equal to the single-step row up to the summation order; on a
+ * tensor grid or a two-point tile that step runs singly.
+ * The fields are bitwise those of single fused steps.  tw x ty: tile (tw >= 8,
  * ty >= 2; a workgroup has (tw + 4)(ty + 3) threads rounded up to a multiple
  * of 64, at most 1024; LDS within 160 KiB), kc: planes per chunk (0 = one
  * round of resident workgroups); tw = ty = 0 takes the first of 64 x 8,
