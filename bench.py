@@ -851,8 +851,18 @@ def summarize(kt, rd_dir, wr_dir, out_md, cells, cmd_note):
                       f"GiB written per dispatch."]
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    # merge into the traffic record: this summary's kernels replace their own
+    # entries, the other kernels' entries (other summaries) stay
     tpath = os.path.join(os.path.dirname(out_md), "traffic_c3.json")
-    rec = {"cells": cells, "kernels": kernels, "summaries": [os.path.basename(out_md)],
+    try:
+        with open(tpath) as fh:
+            old = json.load(fh)
+    except (OSError, ValueError):
+        old = {}
+    merged = dict(old.get("kernels", {}))
+    merged.update(kernels)
+    summaries = sorted(set(old.get("summaries", [])) | {os.path.basename(out_md)})
+    rec = {"cells": cells, "kernels": merged, "summaries": summaries,
            "method": "request-size counters: 32/64/128 B reads, 64/32 B writes"}
     with open(tpath, "w") as fh:
         json.dump(rec, fh, indent=1)
