@@ -851,6 +851,8 @@ def summarize(kt, rd_dir, wr_dir, out_md, cells, cmd_note):
                       f"GiB written per dispatch."]
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
+    if not kernels:       # no kernel of the bandwidth workload in this summary
+        return
     # merge into the traffic record: this summary's kernels replace their own
     # entries, the other kernels' entries (other summaries) stay
     tpath = os.path.join(os.path.dirname(out_md), "traffic_c3.json")
@@ -869,14 +871,54 @@ def summarize(kt, rd_dir, wr_dir, out_md, cells, cmd_note):
     print(json.dumps(rec))
 
 
+def form_batched_pairs(kc: int = 6, steps: int = 200):
+    """The batched form's pair launches alone, at a fixed z-chunk length and
+    no autotuner or per-grid comparison: a short run for counter passes
+    (not part of the default forms)."""
+    import torch
+    from fit_workloads import c4
+    from paper_1705_08019_amd import FitGrid, FitBatch
+    specs = c4()
+    grids, dts = [], []
+    for sp in specs:
+        g = FitGrid(sp.nx, sp.ny, sp.nz, "f32")
+        g.set_materials(sp.eps_r, None, None)
+        dt = 0.9 * g.cfl_dt()
+        s = sp.source
+        g.set_source(s["axis"], s["i"], s["j"], s["k"], s["i_max"], s["sigma_t_steps"] * dt)
+        grids.append(g)
+        dts.append(dt)
+    dts = np.array(dts)
+    cells = sum(sp.cells for sp in specs)
+    b = FitBatch(grids)
+    b.set_pair(True, kc)
+    b.step(32, dts)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    b.step(steps, dts)
+    ev[1].record()
+    torch.cuda.synchronize()
+    ms = ev[0].elapsed_time(ev[1])
+    b.close()
+    for g in grids:
+        g.close()
+    gps = cells * steps / (ms / 1e3) / 1e9
+    return {"workload": "c4 grids, step pairs only", "cells_total": cells, "pair_kc": kc,
+            "steps": steps, "ms_per_pair_launch": round(2 * ms / steps, 4),
+            "Gcell_updates_per_s": round(gps, 2),
+            "frac": round(B_LAUNCH / 2 * gps / PEAK_HBM_GBS, 4)}
+
+
 def run_forms(only=None, persistent=True) -> dict:
     """The batched, adjoint, Gram, ParaExp and graded-grid forms (or those
     named in `only`); a failing form is reported, not hidden."""
     out = {}
     batched = lambda: form_batched(persistent=persistent)
     for name, fn in (("c2", form_c2), ("batched", batched), ("adjoint", form_adjoint),
-                     ("gram", form_gram), ("paraexp", form_paraexp), ("graded", form_graded)):
-        if only and name not in only:
+                     ("gram", form_gram), ("paraexp", form_paraexp), ("graded", form_graded),
+                     ("batched_pairs", form_batched_pairs)):
+        if (only and name not in only) or (not only and name == "batched_pairs"):
             continue
         try:
             out[name] = fn()
@@ -909,20 +951,22 @@ def main(argv=None):
                          "trace of a process that ran the cooperative launch ends before "
                          "writing its results)")
     ap.add_argument("--form", action="append", default=[],
-                    choices=["c2", "batched", "adjoint", "gram", "paraexp", "graded"],
+                    choices=["c2", "batched", "adjoint", "gram", "paraexp", "graded", "batched_pairs"],
                     help="with --forms-only: run only this form (repeatable)")
     ap.add_argument("--summarize", nargs=3, metavar="DIR", default=None,
                     help="kernel-trace, read-counter and write-counter rocprofv3 output dirs "
                          "-> profiles/")
     ap.add_argument("--summary-out", default=os.path.join(ROOT, "profiles", "fused_step_c3.md"))
     ap.add_argument("--summary-cmd", action="append", default=[])
+    ap.add_argument("--cells", type=int, default=256 * 256 * 512,
+                    help="with --summarize: cells per launch for the B/cell column")
     args = ap.parse_args(argv)
     if args.summarize_kernels:
         summarize_kernels(args.summarize_kernels[0], args.summary_out, args.summary_cmd,
                           args.summarize_kernels[1])
         return
     if args.summarize:
-        summarize(*args.summarize, args.summary_out, 256 * 256 * 512, args.summary_cmd)
+        summarize(*args.summarize, args.summary_out, args.cells, args.summary_cmd)
         return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
