@@ -176,3 +176,47 @@ def test_c3_fullsize_step_pairs_in_the_benchmark_configuration(pair):
         de, dh = _window_check_steps(spec, e0, h0, e2, h2, dt, src, o, 47, 2)
         assert de <= 1e-5 and dh <= 1e-5, (o, de, dh)
     g1.close()
+
+
+def test_c3_fullsize_energy_pair_records_the_row():
+    """The benchmark's launch configuration across a trace row: the row at
+    step 50 is recorded by the pair (49, 50) -> 51 (its FP64 energy sums in
+    the pair kernel's energy variant), the other steps by plain pairs and
+    the single step of row 0.  Against single fused steps over the same 53
+    steps: fields bitwise, both rows equal to the summation order."""
+    from paper_1705_08019_amd import FitGrid
+    spec = c3()
+
+    def make(on):
+        g = FitGrid(spec.nx, spec.ny, spec.nz, "f32")
+        g.set_materials(spec.eps_r, spec.mu_r, spec.sigma)
+        g.set_tuning("fused", 8, 128, 128)
+        if on:
+            g.set_pair(True, 64, 8, 128)
+        g.trace_config(spec.energy_every, 64)
+        return g
+
+    g1, g2 = make(True), make(False)
+    dt = spec.cfl_frac * g1.cfl_dt()
+    s = spec.source
+    for g in (g1, g2):
+        g.set_source(2, s["i"], s["j"], s["k"], s["i_max"], s["sigma_t_steps"] * dt)
+    print("c3 full size: 53 steps across the row at 50, pairs vs single", flush=True)
+    g1.profile_begin(200)
+    g1.step(53, dt)
+    prof = g1.profile_end()
+    # 0 single (row 0), pairs from 1 .. 47, the energy pair at 49, a pair at 51
+    assert prof["step"][1] == 1 and prof["pair"][1] == 25 and prof["pair_energy"][1] == 1, prof
+    g2.step(53, dt)
+    for a, b in zip(g1.get_fields(), g2.get_fields()):
+        assert torch.equal(a, b)
+    t1, d1 = g1.trace_read()
+    t2, d2 = g2.trace_read()
+    assert t1.shape == t2.shape == (2, 10) and d1 == d2 == 0
+    assert np.array_equal(t1[:, 0], t2[:, 0]) and np.array_equal(np.isnan(t1), np.isnan(t2))
+    np.testing.assert_allclose(t1, t2, rtol=1e-12, atol=1e-13 * np.nanmax(np.abs(t2)),
+                               equal_nan=True)
+    print(f"c3 full size: row 50 max rel diff "
+          f"{np.nanmax(np.abs(t1 - t2) / np.maximum(np.abs(t2), 1e-300)):.1e}", flush=True)
+    g1.close()
+    g2.close()
