@@ -881,7 +881,7 @@ def summarize(kt, rd_dir, wr_dir, out_md, cells, cmd_note):
     print(json.dumps(rec))
 
 
-def form_batched_pairs(kc: int = 6, steps: int = 200):
+def form_batched_pairs(kc: int = 16, steps: int = 200):
     """The batched form's pair launches alone, at a fixed z-chunk length and
     no autotuner or per-grid comparison: a short run for counter passes
     (not part of the default forms)."""

@@ -95,7 +95,10 @@ __global__ __launch_bounds__(1024) void k_batch(BatchArgs<T> B) {
 // tiles, longest first (entries of grid -1 are padding).  The step index and buffer set of launch
 // launch_off of a captured chain come from the counters plus its offset, so
 // the counters are advanced once per chain.  Budgets as the single-grid
-// kernel's one-point compile-time variants (at most 768 threads).
+// kernel's one-point compile-time variants (at most 768 threads).  The
+// outputs go out by ordinary stores: most grids' row segments straddle L2
+// lines, and the neighbouring tiles of a group, running together on one
+// XCD, complete those lines in L2 before they are written back.
 template <typename T, bool LOSSY>
 __device__ __forceinline__ void batch2_tile(const S2Args<T>& a, int shape, int t, T* sm) {
   const int tx = t % a.t.ntx;
@@ -104,16 +107,20 @@ __device__ __forceinline__ void batch2_tile(const S2Args<T>& a, int shape, int t
   static_assert(kBatchPairNShapes == 4, "one case per shape");
   switch (shape) {
     case 0:
-      step2_tile<T, LOSSY, false, kBatchPairShapes[0][0], kBatchPairShapes[0][1]>(a, tx, tyi, kz, sm);
+      step2_tile<T, LOSSY, false, kBatchPairShapes[0][0], kBatchPairShapes[0][1], 1, false,
+                 false>(a, tx, tyi, kz, sm);
       break;
     case 1:
-      step2_tile<T, LOSSY, false, kBatchPairShapes[1][0], kBatchPairShapes[1][1]>(a, tx, tyi, kz, sm);
+      step2_tile<T, LOSSY, false, kBatchPairShapes[1][0], kBatchPairShapes[1][1], 1, false,
+                 false>(a, tx, tyi, kz, sm);
       break;
     case 2:
-      step2_tile<T, LOSSY, false, kBatchPairShapes[2][0], kBatchPairShapes[2][1]>(a, tx, tyi, kz, sm);
+      step2_tile<T, LOSSY, false, kBatchPairShapes[2][0], kBatchPairShapes[2][1], 1, false,
+                 false>(a, tx, tyi, kz, sm);
       break;
     default:
-      step2_tile<T, LOSSY, false, kBatchPairShapes[3][0], kBatchPairShapes[3][1]>(a, tx, tyi, kz, sm);
+      step2_tile<T, LOSSY, false, kBatchPairShapes[3][0], kBatchPairShapes[3][1], 1, false,
+                 false>(a, tx, tyi, kz, sm);
       break;
   }
 }

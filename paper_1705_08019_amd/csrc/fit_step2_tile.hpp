@@ -75,14 +75,20 @@ __device__ __forceinline__ T pld(const T* base, uint32_t off) {
   using T1 = const __attribute__((address_space(1))) T;
   return *(T1*)((C1*)base + off);
 }
-template <typename T>
+// NTS: streaming store.  The outputs are not read again by the launch, so
+// on large grids they should not take L2 lines from the staged planes the
+// neighbouring tiles still read (their halos).  Ordinary stores let L2
+// merge the parts of one line that neighbouring tiles write, which matters
+// where a tile's row segments straddle lines (grids whose x extent is not
+// a multiple of the line's cells: the batched grids).
+template <bool NTS, typename T>
 __device__ __forceinline__ void pst(T* base, uint32_t off, T v) {
   using C1 = __attribute__((address_space(1))) char;
   using T1 = __attribute__((address_space(1))) T;
-  // streaming store: the outputs are not read again by this launch, so they
-  // should not take L2 lines from the staged planes the neighbouring tiles
-  // still read (their halos)
-  __builtin_nontemporal_store(v, (T1*)((C1*)base + off));
+  if constexpr (NTS)
+    __builtin_nontemporal_store(v, (T1*)((C1*)base + off));
+  else
+    *(T1*)((C1*)base + off) = v;
 }
 
 // Two fused steps of tile (tx, tyi) and z-chunk kz of the tiling A.t;
@@ -97,8 +103,10 @@ __device__ __forceinline__ void pst(T* base, uint32_t off, T v) {
 // the h terms where the second h-update does, and the row's pending h cross
 // term where the first h-update forms an own point of [k0, k1) -- in FP64
 // with the compensated sums of the single step, and write the workgroup's
-// block sums (kPartTerms) to part.
-template <typename T, bool LOSSY, bool NU, int CTW, int CTY, int NP = 1, bool EN = false>
+// block sums (kPartTerms) to part.  NTS: the outputs by streaming stores
+// (see pst).
+template <typename T, bool LOSSY, bool NU, int CTW, int CTY, int NP = 1, bool EN = false,
+          bool NTS = true>
 __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, int kz, T* sm,
                                            double* part = nullptr) {
   static_assert(!EN || (NP == 1 && !NU), "energy pairs: uniform grids, one point per thread");
@@ -435,9 +443,9 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
         if (own[p] && km < k1) {
           const int64_t gk = sxy * (int64_t)km;
           const uint32_t o = fresh(pg[p] * ES);
-          pst(A.e2[0] + gk, o, e2c[p][0]);
-          pst(A.e2[1] + gk, o, e2c[p][1]);
-          pst(A.e2[2] + gk, o, e2c[p][2]);
+          pst<NTS>(A.e2[0] + gk, o, e2c[p][0]);
+          pst<NTS>(A.e2[1] + gk, o, e2c[p][1]);
+          pst<NTS>(A.e2[2] + gk, o, e2c[p][2]);
           if (EN) {
             // the second step's e terms: e^(m+1) (old), e^(m+2) (new)
             const double mx = A.ge[0] * (double)E4p[p][0], my = A.ge[1] * (double)E4p[p][1],
@@ -488,9 +496,9 @@ __device__ __forceinline__ void step2_tile(const S2Args<T>& A, int tx, int tyi, 
                    kdz, hxn, hyn, hzn);
         const int64_t gk = sxy * (int64_t)kh;
         const uint32_t o = fresh(pg[p] * ES);
-        pst(A.h2[0] + gk, o, hxn);
-        pst(A.h2[1] + gk, o, hyn);
-        pst(A.h2[2] + gk, o, hzn);
+        pst<NTS>(A.h2[0] + gk, o, hxn);
+        pst<NTS>(A.h2[1] + gk, o, hyn);
+        pst<NTS>(A.h2[2] + gk, o, hzn);
         if (EN) {
           // the second step's h terms: h^(m+3/2) (old), h^(m+5/2) (new)
           const double wx = gxp[p] > 0 ? 1.0 / (A.gf2[0] * (double)A.imu2) : 0.0;
