@@ -21,13 +21,20 @@ bool step2_plane_ok(const Dims& d, size_t esz) {
 int step2_points(int tw, int ty) { return s2_geom(tw, ty).N1 > 1024 ? 2 : 1; }
 
 // Streaming output stores only where every tile row segment starts and ends
-// on a 128-byte line (rows and tile width whole lines): there they keep the
-// outputs from evicting the halos neighbouring tiles still read.  Elsewhere
-// the segments straddle lines, and ordinary stores let L2 join the parts
-// neighbouring tiles write (a 250 x 256 x 512 FP32 grid: 0.47 against 0.59
-// ms per launch).
+// on a 128-byte line (rows and tile width whole lines) and the launch's
+// state does not fit the 256 MiB Infinity Cache: there they keep the outputs
+// from evicting the halos neighbouring tiles still read.  Where the segments
+// straddle lines, ordinary stores let L2 join the parts neighbouring tiles
+// write (a 250 x 256 x 512 FP32 grid: 0.47 against 0.59 ms per launch);
+// where the state fits the Infinity Cache, ordinary stores keep the outputs
+// there for the next launch, which streaming stores do not (128^3 FP32:
+// 15.9 against 18.6 us per step).
+constexpr uint64_t kInfinityCacheBytes = 256ull << 20;
 static bool step2_streaming(const Dims& d, int tw, size_t esz) {
-  return ((size_t)d.nx * esz) % 128 == 0 && ((size_t)tw * esz) % 128 == 0;
+  // e and h read and written, eps and sigma read: 14 values per cell
+  const uint64_t state = (uint64_t)d.n * esz * 14;
+  return ((size_t)d.nx * esz) % 128 == 0 && ((size_t)tw * esz) % 128 == 0 &&
+         state > kInfinityCacheBytes;
 }
 
 int step2_threads(int tw, int ty) {
