@@ -281,3 +281,18 @@ def test_energy_pairs_record_the_rows(dtype, n, lossy):
           f"{np.nanmax(np.abs(t2 - t1) / np.maximum(np.abs(t1), 1e-300)):.1e}", flush=True)
     g1.close()
     g2.close()
+
+
+@pytest.mark.parametrize("n", [(256, 256, 160), (252, 256, 160), (128, 128, 128)])
+def test_pairs_with_either_store_kind_equal_single_steps(n):
+    """The pair launches write their outputs with streaming stores where rows
+    and tiles are whole 128-byte lines and the state exceeds the 256 MiB
+    Infinity Cache (256 x 256 x 160 FP32: 587 MB), with ordinary stores
+    elsewhere (252-cell rows; the cache-resident 128^3): bitwise equal to
+    single fused steps either way, across a ragged last z-chunk."""
+    print(f"pairs vs single, store rule case {n}", flush=True)
+    e1, h1, m1, _, prof = _run(n, "f32", True, 10, pair=(64, 8, 128))
+    assert prof["pair"][1] == 5, prof
+    e2, h2, m2, _, _ = _run(n, "f32", True, 10)
+    assert m1 == m2 == 10
+    assert torch.equal(e1, e2) and torch.equal(h1, h2)
