@@ -57,7 +57,9 @@ B_ADJ = 4 * (6 + 6 + 9 + 2) + 8 * 2 * 2    # 124
 KERNEL_SOURCES = {"step": ("fit_step.hip", "fit_step_tile.hpp", "fit_point.hpp"),
                   "pair": ("fit_step2.hip", "fit_step2_tile.hpp", "fit_step_tile.hpp", "fit_point.hpp"),
                   "epass": ("fit_kernels.hip", "fit_point.hpp"),
-                  "hpass": ("fit_kernels.hip", "fit_point.hpp")}
+                  "hpass": ("fit_kernels.hip", "fit_point.hpp"),
+                  "batch_pair": ("fit_batch.hip", "fit_step2_tile.hpp", "fit_step_tile.hpp",
+                                 "fit_point.hpp")}
 
 
 def kernel_source_hash(tag: str) -> str:
@@ -332,6 +334,14 @@ def form_batched(plain_steps: int = 400, persistent: bool = True):
     gp = cells * plain_steps / (ms_p / 1e3) / 1e9
     # compulsory bytes per cell-update: 56 B per launch, one or two steps per launch
     bcs = B_LAUNCH / 2 if pair_on else B_LAUNCH
+    # counted memory bytes of the pair launch (committed request-size counters
+    # of the pairs alone, 16-plane chunks), while they match the kernel's code
+    tr = load_traffic("batch_pair") if pair_on else None
+    traffic = None
+    if tr and tr.get("cells") == cells:
+        traffic = {"bytes_per_launch": tr["bytes_per_launch"],
+                   "bytes_per_cell": tr["bytes_per_cell"], "pair_kc_counted": 16,
+                   "summary": "profiles/batch_pairs_c4.md"}
     return {"workload": "c4: 64 FP32 grids, sizes ~U{32..96}^3, 8 blocks each, 4000 steps",
             "cells_total": cells, "steps": nsteps, "Gcell_updates_per_s": round(gb, 3),
             "alg_bytes_per_cell_update": bcs,
@@ -339,6 +349,7 @@ def form_batched(plain_steps: int = 400, persistent: bool = True):
             "plain_per_grid_Gcell_updates_per_s": round(gp, 3),
             "plain_steps_timed": plain_steps, "batched_over_plain": round(gb / gp, 3),
             "tile": [tw, ty, kc], "pair_kc": pair_kc if pair_on else None,
+            "pair_traffic": traffic,
             "persistent": persist, "persistent_pairs": persist_pairs,
             "launch": ("one launch per pair of steps of all grids (per-grid pair tiles, the tiles of one z-chunk of a grid on one XCD, longest first), hipGraph "
                        "chunks of 8 pairs" if pair_on else
@@ -846,13 +857,14 @@ def summarize(kt, rd_dir, wr_dir, out_md, cells, cmd_note):
                else "step" if "k_step<float, true, 0, false, false" in name
                else "epass" if "k_epass<float, true, false, false>" in name
                else "hpass" if "k_hpass<float, true, false>" in name
+               else "batch_pair" if "k_batch2<float>" in name
                else "stream_copy" if "k_stream_copy" in name else None)
         if tag and (tag not in kernels or nd > kernels[tag]["dispatches"]):
             kernels[tag] = {"source_hash": kernel_source_hash(tag) if tag in KERNEL_SOURCES
                             else None,
                             "bytes_per_launch": round(rd + wr), "read_bytes": round(rd),
                             "write_bytes": round(wr), "bytes_per_cell": round(bpc, 2),
-                            "dispatches": nd, "grid": key[1], "wg": key[2],
+                            "dispatches": nd, "grid": key[1], "wg": key[2], "cells": cells,
                             "method": "request-size counters (no scale factor)"}
     if "stream_copy" in kernels:
         k = kernels["stream_copy"]
@@ -874,7 +886,7 @@ def summarize(kt, rd_dir, wr_dir, out_md, cells, cmd_note):
     merged = dict(old.get("kernels", {}))
     merged.update(kernels)
     summaries = sorted(set(old.get("summaries", [])) | {os.path.basename(out_md)})
-    rec = {"cells": cells, "kernels": merged, "summaries": summaries,
+    rec = {"kernels": merged, "summaries": summaries,
            "method": "request-size counters: 32/64/128 B reads, 64/32 B writes"}
     with open(tpath, "w") as fh:
         json.dump(rec, fh, indent=1)
